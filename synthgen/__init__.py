@@ -1,0 +1,117 @@
+"""Seeded synthetic inputs for the closed-shell EOM-CCSD sigma / Davidson path.
+
+This module only draws random numbers and lays them out; it holds none of the
+method's arithmetic (no integrals, no amplitudes, no Fock builds).  Both the
+FP64 oracle (tests) and the HIP path (bench, GPU tests) take their inputs from
+here, so the two sides see bit-identical data.
+
+Recipe (one seeded PCG64 stream, fixed draw order):
+  1. occupied orbital energies  eps_occ ~ U[-1.5, -0.3] Eh, sorted ascending
+  2. virtual orbital energies   eps_vir ~ U[ 0.1,  3.0] Eh, sorted ascending
+  3. density-fitting factors    B^Q_pq for p <= q ~ N(0, sigma_B^2), Q-major,
+                                each Q row in row-major upper-triangle order,
+                                then mirrored so B^Q_pq = B^Q_qp
+  4. optional T1 amplitudes     t_i^a ~ N(0, sigma_t1^2)
+The Fock matrix is diag(eps) by construction, so Brillouin's condition f_ia = 0
+holds exactly.  sigma_B defaults to 0.05*sqrt(60/naux), which equals 0.05 at
+naux = 60 and keeps sum_Q (B^Q_pq)^2 independent of naux.  An optional virtual
+envelope multiplies B^Q_pq by g_p g_q with g_i = 1 and
+g_a = exp(-kappa (eps_a - eps_LUMO)); it gives the per-pair densities the
+eigenvalue decay that real molecules show.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = ["System", "make_system", "CONFIGS", "config_system", "random_r"]
+
+
+@dataclasses.dataclass
+class System:
+    o: int
+    v: int
+    naux: int
+    eps: np.ndarray          # (o+v,)  occupied first, each block ascending
+    B: np.ndarray            # (naux, o+v, o+v) float64, symmetric in p,q
+    t1: np.ndarray           # (o, v) float64 (zeros when not drawn)
+    seed: int
+    sigma_b: float
+    kappa: float
+
+    @property
+    def nmo(self) -> int:
+        return self.o + self.v
+
+
+def make_system(o: int, v: int, naux: int, seed: int, *, sigma_b: float | None = None,
+                kappa: float = 0.0, t1_sigma: float = 0.0, chunk: int = 64) -> System:
+    if o < 1 or v < 1 or naux < 1:
+        raise ValueError("o, v and naux must be positive")
+    if sigma_b is None:
+        sigma_b = 0.05 * math.sqrt(60.0 / naux)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    eps_o = np.sort(rng.uniform(-1.5, -0.3, o))
+    eps_v = np.sort(rng.uniform(0.1, 3.0, v))
+    eps = np.concatenate([eps_o, eps_v])
+    nmo = o + v
+    iu, ju = np.triu_indices(nmo)
+    B = np.empty((naux, nmo, nmo), dtype=np.float64)
+    for q0 in range(0, naux, chunk):
+        q1 = min(naux, q0 + chunk)
+        vals = rng.standard_normal((q1 - q0, iu.size)) * sigma_b
+        blk = B[q0:q1]
+        blk[:, iu, ju] = vals
+        blk[:, ju, iu] = vals
+    if kappa != 0.0:
+        g = np.ones(nmo)
+        g[o:] = np.exp(-kappa * (eps_v - eps_v[0]))
+        B *= g[None, :, None]
+        B *= g[None, None, :]
+    if t1_sigma > 0.0:
+        t1 = rng.standard_normal((o, v)) * t1_sigma
+    else:
+        t1 = np.zeros((o, v))
+    return System(o=o, v=v, naux=naux, eps=eps, B=B, t1=t1, seed=seed,
+                  sigma_b=sigma_b, kappa=kappa)
+
+
+# The five workloads.  "kappa" is the virtual-envelope decay chosen so that the
+# state-averaged pair densities keep the stated number of PNOs at T_cut = 1e-7.
+CONFIGS = {
+    1: dict(o=4, v=20, naux=60, t1_sigma=0.0, kappa=0.0, nroots=3, tol_e=1e-8,
+            space="canonical"),
+    2: dict(o=20, v=150, naux=450, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-8,
+            max_sub=60, space="canonical"),
+    3: dict(o=40, v=400, naux=1200, t1_sigma=1e-3, kappa=2.0, nroots=6, tol_e=1e-6,
+            tcut=1e-7, space="pno"),
+    4: dict(o=40, v=400, naux=1200, t1_sigma=1e-3, kappa=2.0, nroots=6, tol_e=1e-6,
+            tcut=1e-7, space="pno"),
+    5: dict(o=60, v=900, naux=2700, t1_sigma=1e-3, kappa=2.0, nroots=12, tol_e=1e-6,
+            tcut=1e-7, space="pno"),
+    # reduced PNO workload (o=10, v=100) small enough for the oracle to converge
+    "pno_small": dict(o=10, v=100, naux=300, t1_sigma=1e-3, kappa=2.0, nroots=4,
+                      tol_e=1e-8, tcut=1e-7, space="pno"),
+}
+
+
+def config_system(cfg, seed: int | None = None) -> System:
+    c = CONFIGS[cfg]
+    if seed is None:
+        seed = 1802 + (cfg if isinstance(cfg, int) else 100)
+    return make_system(c["o"], c["v"], c["naux"], seed, kappa=c["kappa"],
+                       t1_sigma=c["t1_sigma"])
+
+
+def random_r(o: int, v: int, seed: int, nvec: int = 1):
+    """Random trial amplitudes (R1, R2) with R2[i,j,a,b] = R2[j,i,b,a].
+
+    Returns arrays of shape (nvec, o, v) and (nvec, o, o, v, v), float64.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r1 = rng.standard_normal((nvec, o, v))
+    x = rng.standard_normal((nvec, o, o, v, v))
+    r2 = 0.5 * (x + x.transpose(0, 2, 1, 4, 3))
+    return r1, r2

@@ -1,0 +1,108 @@
+"""Write the stored reference values under tests/golden/ (calls only oracle/ and synthgen).
+
+    python tests/golden/make_golden.py c1 c1_pno pno_small c2
+
+Each section writes <section>.json with the excitation energies of the FP64
+oracle (Davidson at tol_e = 1e-11, and for config 1 also the dense eigenvalues
+of H-bar on the singlet space), plus the setup numbers (E_ref, E_MP2, CIS
+energies, PNO counts) that the GPU tests compare against.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from synthgen import config_system, CONFIGS                       # noqa: E402
+from oracle.ham import bare, mp2_energy                           # noqa: E402
+from oracle.sigma import SigmaOracle                              # noqa: E402
+from oracle.sapno import cis_roots, sa_densities, PNOBasis, CanonicalBasis   # noqa: E402
+from oracle.davidson import davidson, dense_eom                   # noqa: E402
+
+
+def _setup(cfg):
+    s = config_system(cfg)
+    so = SigmaOracle(s.eps, s.B, s.o, s.t1)
+    out = dict(config=str(cfg), o=s.o, v=s.v, naux=s.naux, seed=s.seed, sigma_b=s.sigma_b,
+               kappa=s.kappa, e_ref=so.e_ref, e_mp2=mp2_energy(s.eps, s.B, s.o))
+    return s, so, out
+
+
+def _guess(b, o, v, k):
+    return [(b[i], np.zeros((o, o, v, v))) for i in range(k)]
+
+
+def sec_c1():
+    s, so, out = _setup(1)
+    o, v, k = s.o, s.v, CONFIGS[1]["nroots"]
+    w, b = cis_roots(s.eps, s.B, o, k)
+    out["cis"] = w.tolist()
+    t0 = time.time()
+    res = davidson(so.sigma, CanonicalBasis(s.eps, o), _guess(b, o, v, k), o, v, k,
+                   tol_e=1e-11, tol_r=1e-8)
+    out["davidson"] = res["omega"].tolist()
+    out["davidson_iters"] = res["iters"]
+    out["davidson_seconds"] = time.time() - t0
+    wd, _ = dense_eom(so.sigma, o, v)
+    out["dense_eig"] = wd.real[:12].tolist()
+    out["dense_eig_imag"] = wd.imag[:12].tolist()
+    return out
+
+
+def _pno_section(cfg, tcut, nstates):
+    s, so, out = _setup(cfg)
+    o, v = s.o, s.v
+    k = CONFIGS[cfg]["nroots"]
+    D, w, b = sa_densities(s.eps, s.B, o, nstates)
+    pb = PNOBasis(D, s.eps, o, tcut)
+    out.update(cis=w.tolist(), tcut_pno=tcut, tcut_osv=tcut / 10.0, nstates_avg=nstates,
+               npno=pb.npno().tolist(), nosv=pb.nosv().tolist())
+    t0 = time.time()
+    res = davidson(so.sigma, pb, _guess(b, o, v, k), o, v, k, tol_e=1e-11, tol_r=1e-8)
+    out["davidson_pno"] = res["omega"].tolist()
+    out["davidson_pno_iters"] = res["iters"]
+    out["davidson_pno_seconds"] = time.time() - t0
+    t0 = time.time()
+    rc = davidson(so.sigma, CanonicalBasis(s.eps, o), _guess(b, o, v, k), o, v, k,
+                  tol_e=1e-11, tol_r=1e-8)
+    out["davidson"] = rc["omega"].tolist()
+    out["davidson_iters"] = rc["iters"]
+    out["davidson_seconds"] = time.time() - t0
+    return out
+
+
+def sec_c1_pno():
+    return _pno_section(1, 1e-6, CONFIGS[1]["nroots"])
+
+
+def sec_pno_small():
+    return _pno_section("pno_small", CONFIGS["pno_small"]["tcut"], CONFIGS["pno_small"]["nroots"])
+
+
+def sec_c2():
+    s, so, out = _setup(2)
+    o, v, k = s.o, s.v, CONFIGS[2]["nroots"]
+    w, b = cis_roots(s.eps, s.B, o, k)
+    out["cis"] = w.tolist()
+    t0 = time.time()
+    res = davidson(so.sigma, CanonicalBasis(s.eps, o), _guess(b, o, v, k), o, v, k,
+                   tol_e=1e-11, tol_r=3e-8, max_sub=CONFIGS[2]["max_sub"], verbose=True)
+    out["davidson"] = res["omega"].tolist()
+    out["davidson_resnorm"] = res["resnorm"].tolist()
+    out["davidson_iters"] = res["iters"]
+    out["davidson_seconds"] = time.time() - t0
+    return out
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:]:
+        t0 = time.time()
+        res = globals()["sec_" + name]()
+        res["wall_seconds"] = time.time() - t0
+        with open(os.path.join(HERE, name + ".json"), "w") as fh:
+            json.dump(res, fh, indent=1)
+        print(name, "done in", round(time.time() - t0, 1), "s", flush=True)

@@ -1,0 +1,360 @@
+"""Pins of the FP64 oracle against things other than itself (CPU only).
+
+Each test ties one oracle function to a brute-force determinant calculation, a
+closed form, a library routine applied to the plain definition, or an exact
+invariant, so that a dropped term, a wrong sign or index, or a transposed
+operand in the oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from synthgen import make_system, random_r, config_system
+from oracle.ham import bare, dress, mp2_amplitudes, mp2_energy
+from oracle.fci import FCI, full_eri
+from oracle.residual import ccsd_residual
+from oracle.sigma import SigmaOracle
+from oracle.sapno import (cis_matrix, cis_roots, cisd_k, cisd_doubles, pair_density,
+                          sa_densities, PNOBasis, CanonicalBasis, symmetrize)
+from oracle.davidson import davidson, dense_eom
+
+
+def _sym(x):
+    return 0.5 * (x + x.transpose(1, 0, 3, 2))
+
+
+def _tiny(o, v, naux=10, seed=11, sb=0.12):
+    s = make_system(o, v, naux, seed, sigma_b=sb)
+    _, h, eref = bare(s.eps, s.B, o)
+    return s, h, eref, FCI(h, full_eri(s.B), o)
+
+
+# ---------------------------------------------------------------- generator
+def test_generator_deterministic_symmetric():
+    a = make_system(3, 5, 7, 99, t1_sigma=1e-3)
+    b = make_system(3, 5, 7, 99, t1_sigma=1e-3)
+    assert np.array_equal(a.B, b.B) and np.array_equal(a.eps, b.eps) and np.array_equal(a.t1, b.t1)
+    assert np.array_equal(a.B, a.B.transpose(0, 2, 1))
+    assert np.all(np.diff(a.eps[:3]) >= 0) and np.all(np.diff(a.eps[3:]) >= 0)
+    assert a.eps[2] < -0.3 + 1e-12 and a.eps[3] > 0.1 - 1e-12
+    # (pq|rs) as a (pq) x (rs) matrix is positive semidefinite (B B^T form)
+    n = a.nmo
+    M = full_eri(a.B).reshape(n * n, n * n)
+    assert np.linalg.eigvalsh(M).min() > -1e-12
+    # chunked drawing gives the same stream as one draw
+    c = make_system(3, 5, 7, 99, t1_sigma=1e-3, chunk=2)
+    assert np.array_equal(a.B, c.B)
+
+
+# ---------------------------------------------------------------- Hamiltonian
+@pytest.mark.parametrize("o,v", [(2, 3), (3, 4)])
+def test_reference_energy_closed_form(o, v):
+    s, h, eref, f = _tiny(o, v)
+    assert abs(f.energy_ref() - eref) < 1e-12
+
+
+def test_mp2_energy_equals_rayleigh_schroedinger():
+    """E2 = -sum_D |<D|H|0>|^2 / (E_D^0 - E_0^0) over doubles (Moller-Plesset H0)."""
+    o, v = 2, 4
+    s, h, eref, f = _tiny(o, v)
+    ref = f.space.ref()
+    col = f.H(ref)
+    lev = f.excitation_level()
+    e0 = f.orbital_energy_sum(s.eps)
+    mask = lev == 2
+    e2 = -np.sum(col[mask] ** 2 / (e0[mask] - e0[f.space.hf]))
+    assert abs(mp2_energy(s.eps, s.B, o) - e2) < 1e-13
+    # Brillouin: no singles coupling because f = diag(eps)
+    assert np.max(np.abs(col[lev == 1])) < 1e-13
+
+
+def test_dressing_is_similarity_transform():
+    """exp(-T1) H exp(T1) has the same spectrum as H: E_ref shift check at first order."""
+    o, v = 2, 3
+    s, h, eref, f = _tiny(o, v)
+    t1 = np.random.default_rng(5).standard_normal((o, v)) * 0.2
+    Hd, Bd = dress(h, s.B, t1)
+    # integrals with no virtual creation and no occupied annihilation are untouched
+    assert np.allclose(Bd[:, :o, o:], s.B[:, :o, o:], atol=0, rtol=0)
+
+
+# ---------------------------------------------------------------- residual / sigma
+@pytest.mark.parametrize("o,v,seed", [(2, 3, 1), (3, 4, 2), (3, 5, 3)])
+def test_ccsd_residual_vs_brute_force(o, v, seed):
+    s, h, eref, f = _tiny(o, v, seed=seed)
+    rng = np.random.default_rng(seed)
+    t1 = rng.standard_normal((o, v)) * 0.15
+    t2 = _sym(rng.standard_normal((o, o, v, v)) * 0.15)
+    w1, w2 = f.omega(t1, t2)
+    o1, o2 = ccsd_residual(s.eps, s.B, o, t1, t2)
+    assert np.max(np.abs(w1 - o1)) < 1e-12 * max(1.0, np.max(np.abs(w1)))
+    assert np.max(np.abs(w2 - o2)) < 1e-12 * max(1.0, np.max(np.abs(w2)))
+
+
+@pytest.mark.parametrize("o,v,seed", [(2, 3, 4), (3, 4, 5), (3, 5, 6)])
+def test_sigma_vs_brute_force_commutator(o, v, seed):
+    """sigma = <mu|[exp(-T) H exp(T), R]|0> with random T1, T2, R1, R2."""
+    s, h, eref, f = _tiny(o, v, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    t1 = rng.standard_normal((o, v)) * 0.15
+    t2 = _sym(rng.standard_normal((o, o, v, v)) * 0.15)
+    r1 = rng.standard_normal((o, v))
+    r2 = _sym(rng.standard_normal((o, o, v, v)))
+    b1, b2 = f.sigma(t1, t2, r1, r2)
+    so = SigmaOracle(s.eps, s.B, o, t1, t2)
+    s1, s2 = so.sigma(r1, r2)
+    assert np.max(np.abs(b1 - s1)) < 1e-12 * np.max(np.abs(b1))
+    assert np.max(np.abs(b2 - s2)) < 1e-12 * np.max(np.abs(b2))
+
+
+def test_sigma_T0_equals_cisd_hamiltonian():
+    """With T = 0, sigma is (H - E_ref) on the singles+doubles space (brute force H)."""
+    o, v = 3, 4
+    s, h, eref, f = _tiny(o, v, seed=8)
+    rng = np.random.default_rng(8)
+    r1 = rng.standard_normal((o, v))
+    r2 = _sym(rng.standard_normal((o, o, v, v)))
+    R = f.space.excitation_op(r1, r2)
+    x = R @ f.space.ref()
+    y = f.H(x) - eref * x
+    b1, b2 = f.space.readoff(y, v)
+    so = SigmaOracle(s.eps, s.B, o, np.zeros((o, v)), np.zeros((o, o, v, v)))
+    s1, s2 = so.sigma(r1, r2)
+    assert np.max(np.abs(b1 - s1)) < 1e-12 * np.max(np.abs(b1))
+    assert np.max(np.abs(b2 - s2)) < 1e-12 * np.max(np.abs(b2))
+
+
+def test_cis_matrix_and_k_from_sigma_at_T0():
+    """Singles block of sigma(T=0) is CIS A; its doubles from R1 is the K of CIS(D)."""
+    s = make_system(3, 7, 15, 21)
+    o, v = 3, 7
+    so = SigmaOracle(s.eps, s.B, o, np.zeros((o, v)), np.zeros((o, o, v, v)))
+    A = cis_matrix(s.eps, s.B, o)
+    b = np.random.default_rng(3).standard_normal((o, v))
+    s1, s2 = so.sigma(b, np.zeros((o, o, v, v)))
+    assert np.allclose(s1.ravel(), A @ b.ravel(), atol=1e-13, rtol=0)
+    assert np.allclose(s2, cisd_k(s.eps, s.B, o, b), atol=1e-13, rtol=0)
+    # A is the singles-singles block of (H - E_ref) by brute force (tiny case)
+    st, h, eref, f = _tiny(2, 3, seed=4)
+    A2 = cis_matrix(st.eps, st.B, 2)
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = 1.0
+        R = f.space.excitation_op(e.reshape(2, 3), np.zeros((2, 2, 3, 3)))
+        x = R @ f.space.ref()
+        y1, _ = f.space.readoff(f.H(x) - eref * x, 3)
+        assert np.allclose(y1.ravel(), A2[:, k], atol=1e-13)
+
+
+def test_sigma_linear_and_symmetric():
+    s = make_system(3, 6, 12, 5, t1_sigma=1e-2)
+    o, v = 3, 6
+    so = SigmaOracle(s.eps, s.B, o, s.t1)
+    r1a, r2a = random_r(o, v, 1)
+    r1b, r2b = random_r(o, v, 2)
+    sa = so.sigma(r1a[0], r2a[0])
+    sb = so.sigma(r1b[0], r2b[0])
+    sc = so.sigma(2.0 * r1a[0] - r1b[0], 2.0 * r2a[0] - r2b[0])
+    assert np.allclose(sc[0], 2 * sa[0] - sb[0], atol=1e-12)
+    assert np.allclose(sc[1], 2 * sa[1] - sb[1], atol=1e-12)
+    assert np.allclose(sa[1], sa[1].transpose(1, 0, 3, 2), atol=1e-13)
+
+
+def test_sigma_is_derivative_of_residual():
+    """sigma(R) = d/de Omega(T + eR) at e = 0 (five-point rule, exact for degree <= 4)."""
+    s = make_system(4, 8, 20, 9, t1_sigma=0.05)
+    o, v = 4, 8
+    t2 = mp2_amplitudes(s.eps, s.B, o)
+    rng = np.random.default_rng(4)
+    r1 = rng.standard_normal((o, v)) * 0.05
+    r2 = _sym(rng.standard_normal((o, o, v, v)) * 0.05)
+    om = {}
+    for k in (-2, -1, 1, 2):
+        om[k] = ccsd_residual(s.eps, s.B, o, s.t1 + k * r1, t2 + k * r2)
+    d1 = (om[-2][0] - 8 * om[-1][0] + 8 * om[1][0] - om[2][0]) / 12.0
+    d2 = (om[-2][1] - 8 * om[-1][1] + 8 * om[1][1] - om[2][1]) / 12.0
+    so = SigmaOracle(s.eps, s.B, o, s.t1, t2)
+    s1, s2 = so.sigma(r1, r2)
+    assert np.max(np.abs(d1 - s1)) < 1e-11 * np.max(np.abs(s1))
+    assert np.max(np.abs(d2 - s2)) < 1e-11 * np.max(np.abs(s2))
+
+
+def test_two_electron_eom_ccsd_equals_fci():
+    """o = 1: CCSD is exact, so EOM-CCSD singlet energies are FCI singlet excitations."""
+    o, v = 1, 4
+    s, h, eref, f = _tiny(o, v, naux=8, seed=31, sb=0.15)
+    t1 = np.zeros((o, v))
+    t2 = mp2_amplitudes(s.eps, s.B, o)
+    eo, ev = s.eps[:o], s.eps[o:]
+    d1 = eo[:, None] - ev[None, :]
+    d2 = eo[:, None, None, None] + eo[None, :, None, None] - ev[None, None, :, None] - ev[None, None, None, :]
+    for _ in range(30):
+        w1, w2 = ccsd_residual(s.eps, s.B, o, t1, t2)
+        t1 = t1 + w1 / d1
+        t2 = t2 + w2 / d2
+    # Newton steps: the CC Jacobian applied to a vector is exactly sigma
+    from oracle.davidson import singlet_basis, pack, unpack
+    cols = singlet_basis(o, v)
+    nfull = o * v + o * o * v * v
+    Q = np.zeros((nfull, len(cols)))
+    for k, (ix, wt) in enumerate(cols):
+        Q[ix, k] = wt
+    for _ in range(4):
+        so = SigmaOracle(s.eps, s.B, o, t1, t2)
+        J = np.column_stack([Q.T @ pack(*so.sigma(*unpack(Q[:, k], o, v))) for k in range(Q.shape[1])])
+        w1, w2 = ccsd_residual(s.eps, s.B, o, t1, t2)
+        dx = Q @ np.linalg.solve(J, -(Q.T @ pack(w1, w2)))
+        a1, a2 = unpack(dx, o, v)
+        t1 = t1 + a1
+        t2 = t2 + a2
+    w1, w2 = ccsd_residual(s.eps, s.B, o, t1, t2)
+    assert max(np.abs(w1).max(), np.abs(w2).max()) < 1e-12
+    so = SigmaOracle(s.eps, s.B, o, t1, t2)
+    wd, _ = dense_eom(so.sigma, o, v)
+    # FCI singlets of two electrons: coefficients C[p_alpha, q_beta] symmetric
+    n = f.nmo
+    Hm = f.h_matrix_dense()
+    cols = []
+    for p in range(n):
+        for q in range(p, n):
+            x = np.zeros(n * n)
+            ip = f.space.index[1 << p]
+            iq = f.space.index[1 << q]
+            x[ip * n + iq] += 1.0
+            x[iq * n + ip] += 1.0
+            cols.append(x / np.linalg.norm(x))
+    Q = np.array(cols).T
+    ef = np.sort(np.linalg.eigvalsh(Q.T @ Hm @ Q))
+    exc = ef[1:] - ef[0]
+    assert np.max(np.abs(np.sort(wd.real) - exc)) < 1e-10
+    assert np.max(np.abs(wd.imag)) < 1e-10
+
+
+# ---------------------------------------------------------------- SA-PNO
+def test_cis_roots_library_eigh():
+    s = make_system(3, 6, 12, 2)
+    w, b = cis_roots(s.eps, s.B, 3, 4)
+    A = cis_matrix(s.eps, s.B, 3)
+    assert np.allclose(A, A.T, atol=1e-14)
+    for k in range(4):
+        assert abs(np.sum(b[k] ** 2) - 1.0) < 1e-12
+        assert np.allclose(A @ b[k].ravel(), w[k] * b[k].ravel(), atol=1e-12)
+    assert np.allclose(w, np.linalg.eigvalsh(A)[:4], atol=1e-12)
+
+
+def test_cisd_doubles_denominator():
+    s = make_system(2, 5, 9, 12)
+    w, b = cis_roots(s.eps, s.B, 2, 1)
+    K = cisd_k(s.eps, s.B, 2, b[0])
+    D = cisd_doubles(s.eps, s.B, 2, w[0], b[0])
+    i, j, a, c = 1, 0, 3, 2
+    den = w[0] + s.eps[i] + s.eps[j] - s.eps[2 + a] - s.eps[2 + c]
+    assert abs(D[i, j, a, c] - K[i, j, a, c] / den) < 1e-15
+    # K has the pair symmetry K_ij^ab = K_ji^ba
+    assert np.allclose(K, K.transpose(1, 0, 3, 2), atol=1e-15)
+
+
+def test_pair_density_properties():
+    rng = np.random.default_rng(2)
+    bij = rng.standard_normal((6, 6))
+    Dij = pair_density(bij, False)
+    Dji = pair_density(bij.T, False)
+    assert np.allclose(Dij, Dij.T) and np.allclose(Dij, Dji)
+    # diagonal pair: a symmetric B^{ii} gives D = B B (2/(1+1) * 2 * B B)... closed form
+    bs = bij + bij.T
+    assert np.allclose(pair_density(bs, True), 2.0 * bs @ bs)
+
+
+def test_sa_density_rotation_invariance_and_single_state():
+    s = make_system(3, 6, 12, 17)
+    o = 3
+    w, b = cis_roots(s.eps, s.B, o, 2)
+    om = 0.5 * (w[0] + w[1])
+    c, sn = math.cos(0.7), math.sin(0.7)
+    b1 = c * b[0] + sn * b[1]
+    b2 = -sn * b[0] + c * b[1]
+
+    def dens(omega, vecs):
+        out = 0
+        for x in vecs:
+            bk = cisd_doubles(s.eps, s.B, o, omega, x)
+            out = out + np.array([[pair_density(bk[i, j], i == j) for j in range(o)] for i in range(o)])
+        return out / len(vecs)
+    assert np.allclose(dens(om, [b[0], b[1]]), dens(om, [b1, b2]), atol=1e-14)
+    D1, _, _ = sa_densities(s.eps, s.B, o, 1)
+    bk = cisd_doubles(s.eps, s.B, o, w[0], b[0])
+    assert np.allclose(D1[0, 1], pair_density(bk[0, 1], False), atol=1e-15)
+
+
+def test_truncation_monotone_and_tcut0_identity():
+    s = make_system(3, 8, 16, 23, kappa=2.0)
+    o = 3
+    D, _, _ = sa_densities(s.eps, s.B, o, 2)
+    counts = [PNOBasis(D, s.eps, o, t).npno().sum() for t in (1e-4, 1e-6, 1e-8, 0.0)]
+    assert all(counts[k] <= counts[k + 1] for k in range(3))
+    full = PNOBasis(D, s.eps, o, 0.0)
+    assert np.all(full.npno() == 8) and np.all(full.nosv() == 8)
+    r1, r2 = random_r(o, 8, 4)
+    p1, p2 = full.project(r1[0], r2[0])
+    assert np.allclose(p1, r1[0], atol=1e-13) and np.allclose(p2, r2[0], atol=1e-13)
+    # P is an orthogonal projector in the Frobenius inner product
+    part = PNOBasis(D, s.eps, o, 1e-5)
+    q1, q2 = part.project(r1[0], r2[0])
+    z1, z2 = part.project(q1, q2)
+    assert np.allclose(z1, q1, atol=1e-13) and np.allclose(z2, q2, atol=1e-13)
+    ra1, ra2 = random_r(o, 8, 5)
+    a1, a2 = part.project(ra1[0], ra2[0])
+    lhs = np.sum(q1 * ra1[0]) + np.sum(q2 * ra2[0])
+    rhs = np.sum(r1[0] * a1) + np.sum(r2[0] * a2)
+    assert abs(lhs - rhs) < 1e-12
+
+
+# ---------------------------------------------------------------- Davidson
+def _small_system():
+    s = make_system(2, 6, 14, 41, t1_sigma=1e-2)
+    so = SigmaOracle(s.eps, s.B, 2, s.t1)
+    return s, so
+
+
+def test_davidson_equals_dense_canonical():
+    s, so = _small_system()
+    o, v = 2, 6
+    wd, _ = dense_eom(so.sigma, o, v)
+    w, b = cis_roots(s.eps, s.B, o, 3)
+    guess = [(b[k], np.zeros((o, o, v, v))) for k in range(3)]
+    res = davidson(so.sigma, CanonicalBasis(s.eps, o), guess, o, v, 3, tol_e=1e-12, tol_r=1e-9)
+    assert np.max(np.abs(res["omega"] - wd[:3].real)) < 1e-10
+
+
+def test_pno_davidson_equals_dense_projected_and_tcut0_canonical():
+    s, so = _small_system()
+    o, v = 2, 6
+    D, w, b = sa_densities(s.eps, s.B, o, 3)
+    guess = [(b[k], np.zeros((o, o, v, v))) for k in range(3)]
+    pb = PNOBasis(D, s.eps, o, 1e-6)
+    assert pb.npno().sum() < 3 * v * v    # truncation is active
+    wd, _ = dense_eom(so.sigma, o, v, basis=pb)
+    res = davidson(so.sigma, pb, guess, o, v, 3, tol_e=1e-12, tol_r=1e-9)
+    assert np.max(np.abs(res["omega"] - wd[:3].real)) < 1e-10
+    p0 = PNOBasis(D, s.eps, o, 0.0)
+    r0 = davidson(so.sigma, p0, guess, o, v, 3, tol_e=1e-12, tol_r=1e-9)
+    rc = davidson(so.sigma, CanonicalBasis(s.eps, o), guess, o, v, 3, tol_e=1e-12, tol_r=1e-9)
+    assert np.max(np.abs(r0["omega"] - rc["omega"])) < 1e-12
+    # the truncation raises these energies here (a trend the paper reports, checked on this case)
+    assert np.all(res["omega"] >= rc["omega"] - 1e-9)
+
+
+def test_c1_davidson_matches_stored_dense_eig():
+    """Config 1: the oracle Davidson reproduces the dense eigenvalues stored by
+    tests/golden/make_golden.py (dense eig of H-bar on the 3320-dim singlet space)."""
+    import json, os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c1.json")))
+    s = config_system(1)
+    o, v = s.o, s.v
+    so = SigmaOracle(s.eps, s.B, o, s.t1)
+    w, b = cis_roots(s.eps, s.B, o, 3)
+    guess = [(b[k], np.zeros((o, o, v, v))) for k in range(3)]
+    res = davidson(so.sigma, CanonicalBasis(s.eps, o), guess, o, v, 3, tol_e=1e-11, tol_r=1e-8)
+    assert np.max(np.abs(res["omega"] - np.array(gold["dense_eig"][:3]))) < 1e-10
