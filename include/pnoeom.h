@@ -1,0 +1,164 @@
+/*
+ * pnoeom -- closed-shell EOM-CCSD sigma vectors and a Davidson eigensolver with
+ * state-averaged PNO truncation of the doubles, for one AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Peng, Clement & Valeev, "Exploration of Reduced Scaling
+ * Formulation of EOM-CCSD Based on State-Averaged Pair Natural Orbitals"
+ * (arXiv:1802.06738):
+ *   - H-bar = exp(-T) H exp(T) and the EOM eigenproblem H-bar R|0> = E R|0> with
+ *     T = T1 + T2, R = R1 + R2 parameterised by the spin-summed excitation
+ *     operators E_i^a, E_ij^ab (Methods section, the EOM ansatz and its operator
+ *     parameterisation);
+ *   - the Hamiltonian is given by density-fitting factors (Computational Details);
+ *   - first-order (MP1) amplitudes as the default T2 (Methods, eq. T1);
+ *   - the ladder intermediate W_ab^cd (Methods, the largest intermediate);
+ *   - CIS(D) doubles, state-specific pair densities and their state average
+ *     (Methods, the CIS(D) doubles equation, the pair-density equation and the
+ *     state-averaged density equation), PNO truncation at T_CutPNO and OSVs from
+ *     diagonal pairs at T_CutOSV = T_CutPNO/10 (Methods; Computational Details);
+ *   - the PNO-modified Davidson step: residuals transformed to the semicanonical
+ *     OSV/PNO bases, preconditioned there and back-transformed (Methods, the
+ *     state-averaged PNO simulation in the Davidson solver).
+ *
+ * Conventions
+ *   o = active occupied orbitals, v = virtual orbitals, nmo = o + v, naux = DF rank.
+ *   Orbitals are indexed occupied first.  All floating-point arguments are FP64.
+ *   R1 / sigma1 layout [o][v];  R2 / sigma2 layout [o][o][v][v] (full array) with
+ *   R2[i][j][a][b] = R2[j][i][b][a] (the singlet space).
+ *   Device pointers are HIP device addresses on the context's device; host pointers
+ *   are ordinary CPU memory.  The caller owns every buffer it passes; pointers must
+ *   stay valid only for the duration of the call.  The library copies what it
+ *   keeps into memory owned by the context (freed by pnoeom_destroy).
+ *   All device work is ordered on the stream given to pnoeom_create; host outputs
+ *   are complete when a call returns.  One context per host thread.
+ *   Every entry point returns a status code (0 = success); no C++ exception
+ *   crosses this boundary.  pnoeom_last_error() gives the message of the last
+ *   failure on a context.
+ */
+#ifndef PNOEOM_H
+#define PNOEOM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pnoeom_ctx pnoeom_ctx;
+
+enum {
+  PNOEOM_OK = 0,
+  PNOEOM_EINVAL = -1,   /* bad argument (sizes, null pointers, unknown enum) */
+  PNOEOM_ENOMEM = -2,   /* device allocation failed */
+  PNOEOM_EHIP = -3,     /* HIP runtime error (message has the HIP error string) */
+  PNOEOM_ENOTCONV = -4, /* Davidson reached max_iter without convergence */
+  PNOEOM_ESTATE = -5,   /* call out of order (e.g. sigma before build_df) */
+  PNOEOM_ECOMPLEX = -6, /* converged with a complex Ritz pair (real parts returned) */
+  PNOEOM_EABORTED = -7  /* stopped by abort_after_iter (checkpoint written if requested) */
+};
+
+enum { PNOEOM_FP64 = 0, PNOEOM_FP32 = 1, PNOEOM_BF16 = 2 }; /* contraction precision */
+enum { PNOEOM_CANONICAL = 0, PNOEOM_PNO = 1 };              /* vector space */
+
+/* Create a context for o occupied, v virtual orbitals and naux fitting functions.
+ * hip_stream: a hipStream_t (NULL = the default stream).  Allocates nothing large. */
+int pnoeom_create(int o, int v, int naux, void* hip_stream, pnoeom_ctx** out);
+
+/* Free every device buffer of the context.  Accepts NULL. */
+void pnoeom_destroy(pnoeom_ctx* ctx);
+
+/* Message of the last failed call on ctx ("" if none).  Owned by ctx. */
+const char* pnoeom_last_error(const pnoeom_ctx* ctx);
+
+/* Build the T-dependent intermediates of sigma (H-bar pieces, dressed DF factors,
+ * the ladder intermediate W_ab^cd of the Methods section).
+ *   B    : device [naux][nmo][nmo], B[Q][p][q] = B[Q][q][p]; (pq|rs) = sum_Q B[Q][p][q] B[Q][r][s]
+ *   eps  : device [nmo], orbital energies; the Fock matrix is diag(eps)
+ *   t1   : device [o][v] or NULL (T1 = 0)
+ *   t2   : device [o][o][v][v] or NULL (first-order amplitudes (ia|jb)/(e_i+e_j-e_a-e_b))
+ *   precision : PNOEOM_FP64 or PNOEOM_FP32 (precision of the large contractions
+ *               used by later sigma calls; FP64 copies are always kept)
+ * Errors: EINVAL (null B/eps, bad precision), ENOMEM, EHIP. */
+int pnoeom_build_df(pnoeom_ctx* ctx, const double* B, const double* eps, const double* t1,
+                    const double* t2, int precision);
+
+/* Lowest nroots CIS excitation energies and unit-norm singles vectors of the bare
+ * Hamiltonian, A_{ia,jb} = d_ij d_ab (e_a - e_i) + 2(ia|jb) - (ij|ab).
+ *   omega_out : host [nroots];  vec_out : device [nroots][o][v] or NULL.
+ * Requires build_df.  Errors: ESTATE, EINVAL, ENOTCONV. */
+int pnoeom_cis(pnoeom_ctx* ctx, int nroots, double* omega_out, double* vec_out);
+
+/* Build state-averaged PNOs / OSVs (Methods: CIS(D) doubles of the lowest
+ * nstates CIS roots, pair densities averaged over the states, per-pair
+ * eigenvectors kept when |occupation| >= tcut_pno; OSVs from diagonal pairs with
+ * tcut_osv (tcut_osv < 0 selects tcut_pno/10)), rotated to the semicanonical basis.
+ *   npno_out : host [o(o+1)/2] (pairs i <= j, row-major) or NULL
+ *   nosv_out : host [o] or NULL
+ * Requires build_df.  Errors: ESTATE, EINVAL, ENOMEM, EHIP. */
+int pnoeom_build_sapno(pnoeom_ctx* ctx, int nstates, double tcut_pno, double tcut_osv, int* npno_out,
+                       int* nosv_out);
+
+/* Length of one PNO-space vector and its layout: singles block [sum_i nosv_i]
+ * followed by the pair blocks i <= j, each n_p x n_p row-major.
+ *   offsets : host [o + o(o+1)/2 + 1] start of each block (singles of i = 0..o-1,
+ *             then pairs) or NULL;  len : host, total length.
+ * Off-diagonal pair blocks are stored multiplied by sqrt(2), so the plain dot
+ * product of two PNO-space vectors is the full-array Frobenius inner product.
+ * Requires build_sapno.  Errors: ESTATE. */
+int pnoeom_pno_layout(const pnoeom_ctx* ctx, long long* offsets, long long* len);
+
+/* sigma = <mu|[H-bar, R]|0> for nvec trial vectors.
+ *   space = PNOEOM_CANONICAL: r1 device [nvec][o][v], r2 device [nvec][o][o][v][v];
+ *           s1, s2 the same shapes (outputs).
+ *   space = PNOEOM_PNO: r1 = device [nvec][len] PNO-space vectors (r2 ignored, may be
+ *           NULL); s1 = device [nvec][len] receives P sigma in the same layout.
+ *   precision : PNOEOM_FP64 or PNOEOM_FP32 for the large contractions.
+ * Requires build_df (and build_sapno for PNO).  Errors: ESTATE, EINVAL, ENOMEM, EHIP. */
+int pnoeom_apply_sigma(pnoeom_ctx* ctx, int nvec, const double* r1, const double* r2, double* s1,
+                       double* s2, int space, int precision);
+
+typedef struct {
+  int space;           /* PNOEOM_CANONICAL or PNOEOM_PNO */
+  int precision;       /* PNOEOM_FP64 or PNOEOM_FP32 contractions; subspace work is FP64 */
+  double tol_e;        /* |theta_k - theta_k(previous)| bound (Eh) */
+  double tol_r;        /* residual 2-norm bound; <= 0 selects 0.1*sqrt(tol_e) */
+  int max_sub;         /* largest subspace before collapse to the Ritz vectors */
+  int max_iter;        /* iteration limit (ENOTCONV when reached) */
+  int refine_fp64;     /* precision = FP32: finish with FP64 sigma from the converged FP32 roots */
+  int verbose;         /* 1: print one line per iteration to stdout */
+} pnoeom_davidson_opts;
+
+/* Fill opts with the defaults (canonical, FP64, tol_e 1e-8, tol_r 1e-5, max_sub 60,
+ * max_iter 100). */
+void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts);
+
+/* Lowest-real-part EOM-CCSD roots by the Davidson method with the PNO
+ * modification of the correction step (Methods).  Guess: the nroots lowest CIS
+ * vectors projected onto the space.
+ *   omega_out   : host [nroots] excitation energies (Eh)
+ *   resnorm_out : host [nroots] final residual norms or NULL
+ *   iters_out   : host, iterations used, or NULL
+ *   nsigma_out  : host, number of sigma vectors evaluated, or NULL
+ * Requires build_df (and build_sapno for PNO).
+ * Errors: ESTATE, EINVAL, ENOMEM, EHIP, ENOTCONV (omega_out holds the last Ritz
+ * values), ECOMPLEX (converged; real parts returned). */
+int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opts, double* omega_out,
+                    double* resnorm_out, int* iters_out, int* nsigma_out);
+
+/* Eigenvalues and right eigenvectors of a small dense real matrix on the host
+ * (Householder reduction to Hessenberg form, shifted QR iteration, inverse
+ * iteration for the vectors).  Used for the Davidson subspace matrix.
+ *   a  : host [n][n] row-major (not modified)
+ *   wr, wi : host [n] real / imaginary parts, sorted by real part
+ *   vr : host [n][n] or NULL; column k is the real part of the eigenvector of
+ *        eigenvalue k, unit 2-norm.
+ * Errors: EINVAL (n < 1 or null), ENOTCONV (QR iteration failed). */
+int pnoeom_host_eig(int n, const double* a, double* wr, double* wi, double* vr);
+
+/* Time spent in the last pnoeom_davidson / pnoeom_apply_sigma call, measured with
+ * HIP events on the context's stream: total milliseconds, milliseconds inside
+ * the ladder contraction, and the number of ladder launches. */
+int pnoeom_last_timing(const pnoeom_ctx* ctx, double* total_ms, double* ladder_ms, int* ladder_launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PNOEOM_H */

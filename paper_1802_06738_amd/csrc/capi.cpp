@@ -1,0 +1,205 @@
+// C ABI of libpnoeom: argument checks, exception-to-status mapping, timing.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+
+#include "context.h"
+
+struct pnoeom_ctx {
+  pnoeom::Context c;
+};
+
+namespace {
+
+template <typename F>
+int guarded(pnoeom_ctx* ctx, F&& f) {
+  if (!ctx) return PNOEOM_EINVAL;
+  try {
+    ctx->c.err.clear();
+    f(ctx->c);
+    return PNOEOM_OK;
+  } catch (const pnoeom::Error& e) {
+    ctx->c.err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    ctx->c.err = e.what();
+    return PNOEOM_EHIP;
+  } catch (...) {
+    ctx->c.err = "unknown error";
+    return PNOEOM_EHIP;
+  }
+}
+
+struct Timer {
+  pnoeom::Context& c;
+  hipEvent_t a = nullptr, b = nullptr;
+  explicit Timer(pnoeom::Context& cc) : c(cc) {
+    c.last_ladder_ms = 0;
+    c.last_ladder_launches = 0;
+    c.timing = true;
+    if (!c.ev_lad0) PNO_HIP(hipEventCreate(&c.ev_lad0));
+    if (!c.ev_lad1) PNO_HIP(hipEventCreate(&c.ev_lad1));
+    PNO_HIP(hipEventCreate(&a));
+    PNO_HIP(hipEventCreate(&b));
+    PNO_HIP(hipEventRecord(a, c.stream));
+  }
+  void stop() {
+    PNO_HIP(hipEventRecord(b, c.stream));
+    PNO_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    PNO_HIP(hipEventElapsedTime(&ms, a, b));
+    c.last_total_ms = ms;
+  }
+  ~Timer() {
+    c.timing = false;
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int pnoeom_create(int o, int v, int naux, void* hip_stream, pnoeom_ctx** out) {
+  if (!out) return PNOEOM_EINVAL;
+  *out = nullptr;
+  if (o < 1 || v < 1 || naux < 1) return PNOEOM_EINVAL;
+  pnoeom_ctx* ctx = new (std::nothrow) pnoeom_ctx();
+  if (!ctx) return PNOEOM_ENOMEM;
+  ctx->c.o = o;
+  ctx->c.v = v;
+  ctx->c.naux = naux;
+  ctx->c.nmo = o + v;
+  ctx->c.stream = (hipStream_t)hip_stream;
+  *out = ctx;
+  return PNOEOM_OK;
+}
+
+void pnoeom_destroy(pnoeom_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->c.ev_lad0) (void)hipEventDestroy(ctx->c.ev_lad0);
+  if (ctx->c.ev_lad1) (void)hipEventDestroy(ctx->c.ev_lad1);
+  delete ctx;
+}
+
+const char* pnoeom_last_error(const pnoeom_ctx* ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+int pnoeom_build_df(pnoeom_ctx* ctx, const double* B, const double* eps, const double* t1, const double* t2,
+                    int precision) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(B && eps, PNOEOM_EINVAL, "build_df: B and eps are required");
+    PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32, PNOEOM_EINVAL,
+              "build_df: precision must be PNOEOM_FP64 or PNOEOM_FP32");
+    pnoeom::build_df(c, B, eps, t1, t2, precision);
+  });
+}
+
+int pnoeom_cis(pnoeom_ctx* ctx, int nroots, double* omega_out, double* vec_out) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(omega_out, PNOEOM_EINVAL, "cis: omega_out is required");
+    pnoeom::cis_roots(c, nroots, omega_out, vec_out);
+  });
+}
+
+int pnoeom_build_sapno(pnoeom_ctx* ctx, int nstates, double tcut_pno, double tcut_osv, int* npno_out,
+                       int* nosv_out) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(c.have_df, PNOEOM_ESTATE, "build_sapno before build_df");
+    PNO_CHECK(nstates >= 1 && tcut_pno >= 0.0, PNOEOM_EINVAL, "build_sapno: bad arguments");
+    pnoeom::build_sapno(c, nstates, tcut_pno, tcut_osv < 0 ? tcut_pno / 10.0 : tcut_osv);
+    const int np = c.o * (c.o + 1) / 2;
+    if (npno_out) std::memcpy(npno_out, c.pno.npno.data(), np * sizeof(int));
+    if (nosv_out) std::memcpy(nosv_out, c.pno.nosv.data(), c.o * sizeof(int));
+  });
+}
+
+int pnoeom_pno_layout(const pnoeom_ctx* cctx, long long* offsets, long long* len) {
+  pnoeom_ctx* ctx = const_cast<pnoeom_ctx*>(cctx);
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(c.pno.built, PNOEOM_ESTATE, "pno_layout before build_sapno");
+    if (len) *len = c.pno.len;
+    if (offsets)
+      for (size_t k = 0; k < c.pno.off.size(); ++k) offsets[k] = c.pno.off[k];
+  });
+}
+
+int pnoeom_apply_sigma(pnoeom_ctx* ctx, int nvec, const double* r1, const double* r2, double* s1, double* s2,
+                       int space, int precision) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(c.have_df, PNOEOM_ESTATE, "apply_sigma before build_df");
+    PNO_CHECK(nvec >= 0, PNOEOM_EINVAL, "apply_sigma: nvec < 0");
+    PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32, PNOEOM_EINVAL,
+              "apply_sigma: precision must be PNOEOM_FP64 or PNOEOM_FP32");
+    PNO_CHECK(space == PNOEOM_CANONICAL || space == PNOEOM_PNO, PNOEOM_EINVAL, "apply_sigma: bad space");
+    if (nvec == 0) return;
+    Timer t(c);
+    if (space == PNOEOM_CANONICAL) {
+      PNO_CHECK(r1 && r2 && s1 && s2, PNOEOM_EINVAL, "apply_sigma: null vector pointer");
+      for (int q = 0; q < nvec; ++q)
+        pnoeom::sigma_canonical(c, r1 + (int64_t)q * c.ov(), r2 + (int64_t)q * c.oovv(), s1 + (int64_t)q * c.ov(),
+                                s2 + (int64_t)q * c.oovv(), precision);
+    } else {
+      PNO_CHECK(c.pno.built, PNOEOM_ESTATE, "apply_sigma(PNO) before build_sapno");
+      PNO_CHECK(r1 && s1, PNOEOM_EINVAL, "apply_sigma: null vector pointer");
+      pnoeom::sigma_pno(c, nvec, r1, s1, precision);
+    }
+    t.stop();
+  });
+}
+
+void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts) {
+  if (!opts) return;
+  opts->space = PNOEOM_CANONICAL;
+  opts->precision = PNOEOM_FP64;
+  opts->tol_e = 1e-8;
+  opts->tol_r = 1e-5;
+  opts->max_sub = 60;
+  opts->max_iter = 100;
+  opts->refine_fp64 = 0;
+  opts->verbose = 0;
+}
+
+int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opts, double* omega_out,
+                    double* resnorm_out, int* iters_out, int* nsigma_out) {
+  int complex_pair = 0;
+  int converged = 1;
+  int st = guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(opts && omega_out, PNOEOM_EINVAL, "davidson: opts and omega_out are required");
+    Timer t(c);
+    pnoeom::DavidsonResult r = pnoeom::davidson(c, nroots, *opts);
+    t.stop();
+    for (int k = 0; k < nroots; ++k) {
+      omega_out[k] = k < (int)r.omega.size() ? r.omega[k] : 0.0;
+      if (resnorm_out) resnorm_out[k] = k < (int)r.resnorm.size() ? r.resnorm[k] : 0.0;
+    }
+    if (iters_out) *iters_out = r.iters;
+    if (nsigma_out) *nsigma_out = r.nsigma;
+    complex_pair = r.complex_pair;
+    converged = r.converged;
+    if (!converged) c.err = "Davidson did not converge within max_iter";
+  });
+  if (st != PNOEOM_OK) return st;
+  if (!converged) return PNOEOM_ENOTCONV;
+  if (complex_pair) return PNOEOM_ECOMPLEX;
+  return PNOEOM_OK;
+}
+
+int pnoeom_host_eig(int n, const double* a, double* wr, double* wi, double* vr) {
+  try {
+    return pnoeom::host_eig(n, a, wr, wi, vr);
+  } catch (...) {
+    return PNOEOM_EHIP;
+  }
+}
+
+int pnoeom_last_timing(const pnoeom_ctx* ctx, double* total_ms, double* ladder_ms, int* ladder_launches) {
+  if (!ctx) return PNOEOM_EINVAL;
+  if (total_ms) *total_ms = ctx->c.last_total_ms;
+  if (ladder_ms) *ladder_ms = ctx->c.last_ladder_ms;
+  if (ladder_launches) *ladder_launches = ctx->c.last_ladder_launches;
+  return PNOEOM_OK;
+}
+
+}  // extern "C"

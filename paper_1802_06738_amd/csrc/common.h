@@ -1,0 +1,113 @@
+// Shared declarations for the pnoeom HIP library (gfx950 / MI355X only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pnoeom.h"
+
+namespace pnoeom {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define PNO_HIP(x)                                                                      \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      throw ::pnoeom::Error(PNOEOM_EHIP, std::string(#x " failed: ") + hipGetErrorString(e_) + \
+                                             " at " __FILE__ ":" + std::to_string(__LINE__)); \
+  } while (0)
+
+#define PNO_CHECK(cond, code, msg)                 \
+  do {                                             \
+    if (!(cond)) throw ::pnoeom::Error(code, msg); \
+  } while (0)
+
+// Device buffer owned by the library.
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    if (count == n && p) return;
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error(PNOEOM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+  }
+  operator T*() const { return p; }
+};
+
+// ----------------------------------------------------------------------------- GEMM
+// Row-major strided (batched) matrix product on MFMA:
+//   C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]
+// op(A) is M x K: A[m*lda + k] (transA = false) or A[k*lda + m] (transA = true).
+// op(B) is K x N: B[k*ldb + n] (transB = false) or B[n*ldb + k] (transB = true).
+// C[m*ldc + n].  With reduce = true the batch index is summed into one C.
+template <typename T>
+struct GemmDesc {
+  bool ta = false, tb = false;
+  int64_t M = 0, N = 0, K = 0;
+  T alpha = 1, beta = 0;
+  const T* A = nullptr;
+  int64_t lda = 0, sA = 0;
+  const T* B = nullptr;
+  int64_t ldb = 0, sB = 0;
+  T* C = nullptr;
+  int64_t ldc = 0, sC = 0;
+  int64_t batch = 1;
+  bool reduce = false;
+};
+
+void gemm(const GemmDesc<double>& d, hipStream_t s);
+void gemm(const GemmDesc<float>& d, hipStream_t s);
+
+// convenience: plain row-major C = alpha op(A) op(B) + beta C with leading dims = widths
+template <typename T>
+inline void mm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, const T* A,
+               const T* B, T beta, T* C) {
+  GemmDesc<T> d;
+  d.ta = ta; d.tb = tb; d.M = M; d.N = N; d.K = K; d.alpha = alpha; d.beta = beta;
+  d.A = A; d.lda = ta ? M : K;
+  d.B = B; d.ldb = tb ? K : N;
+  d.C = C; d.ldc = N;
+  gemm(d, s);
+}
+
+// ----------------------------------------------------------------------------- tensor ops
+// out[o0,o1,o2,o3] (strides os*) = alpha * in[o0*is0 + o1*is1 + o2*is2 + o3*is3] + beta * out
+struct Perm4 {
+  int64_t d[4];
+  int64_t is[4];
+  int64_t os[4];
+};
+void permute4(hipStream_t s, const Perm4& p, double alpha, const double* in, double beta, double* out);
+// contiguous output of a permuted contiguous input: out axes taken from input axes perm[]
+void permute_c(hipStream_t s, const int64_t in_dims[4], const int perm[4], double alpha, const double* in,
+               double beta, double* out);
+void axpby(hipStream_t s, int64_t n, double alpha, const double* x, double beta, double* y);
+void fill(hipStream_t s, int64_t n, double val, double* y);
+void to_float(hipStream_t s, int64_t n, const double* x, float* y);
+void to_double(hipStream_t s, int64_t n, const float* x, double* y, double beta);
+
+}  // namespace pnoeom

@@ -1,0 +1,101 @@
+// The library context: inputs, T-dependent intermediates, PNO data and workspaces.
+#pragma once
+
+#include "common.h"
+
+namespace pnoeom {
+
+// Per-vector workspace of the canonical sigma (all FP64, sized once).
+struct SigmaWork {
+  DBuf<double> Bp, hp, Jp, Kp, fp, dp, fp_ov, fp_vv, fp_oo;
+  DBuf<double> BvopT, BoopT, BvvpT;
+  DBuf<double> Ria, Rsia, UiaR, UR, URp, Ubr;
+  DBuf<double> Sd, Ziajb, Z3, Dtot, Xtot, DXtot, Zp, Cba, Xh, O4p, OOVVp, M1;
+  DBuf<double> Ftv, Fto;
+  // FP32 staging for the mixed-precision contractions
+  DBuf<float> fa, fb, fc;
+};
+
+struct PNOData {
+  bool built = false;
+  int nstates = 0;
+  double tcut_pno = 0, tcut_osv = 0;
+  std::vector<int> npno;        // [P_o] pairs i <= j
+  std::vector<int> nosv;        // [o]
+  std::vector<int64_t> off;     // [o + P_o + 1] offsets in the compressed vector
+  int64_t len = 0;
+  int nmax = 0;                 // largest n_p
+  // U^{ij} (v x n_p, column-major per pair = [k][a] rows? stored [a][k] row-major) and fbar
+  std::vector<int64_t> uoff;    // offsets of U^{ij} blocks in U (pairs then OSVs)
+  DBuf<double> U;               // concatenated [v][n] row-major blocks
+  DBuf<double> fbar;            // concatenated semicanonical energies, same order as blocks
+  std::vector<int64_t> foff;
+  // device tables for grouped kernels
+  DBuf<int64_t> d_off, d_uoff, d_foff;
+  DBuf<int> d_n, d_pi, d_pj;
+  DBuf<double> denom_base;      // per compressed element: eps_i (+ eps_j) - fbar_a (- fbar_b)
+  DBuf<double> weight;          // per compressed element: 1 or sqrt(2)
+};
+
+struct Context {
+  int o = 0, v = 0, naux = 0, nmo = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool have_df = false;
+  int precision = PNOEOM_FP64;
+
+  // inputs
+  DBuf<double> B, eps, t1;
+  // dressed Hamiltonian
+  DBuf<double> C1, Bt, h, hd, fd, dt, dtmp, J, K;
+  DBuf<double> BovT, BvoT, BooT, BvvT, Bvv2;
+  // amplitudes
+  DBuf<double> T, U, Tia, Tsia, UiaT;
+  // integrals / intermediates
+  DBuf<double> G, GX, g2, Gq, OVVO, OOVVx, Wh, OOOVp;
+  DBuf<double> Fqvv, Fqoo, Fvv, Foo, fd_ov;
+  DBuf<double> Dr, Xr, DX2, Wvo2;
+  DBuf<double> W;               // ladder matrix [(ab),(cd)] = (ac|bd)~, FP64
+  DBuf<float> Wf;               // FP32 copy when precision = FP32
+  DBuf<float> Tf, Tiaf, Tsiaf, Drf, Xrf, DX2f;
+  DBuf<double> scratch;         // build-time temporaries
+
+  SigmaWork sw;
+  PNOData pno;
+
+  // timing of the last sigma / Davidson call
+  double last_total_ms = 0, last_ladder_ms = 0;
+  int last_ladder_launches = 0;
+  hipEvent_t ev_lad0 = nullptr, ev_lad1 = nullptr;
+  bool timing = false;
+
+  int64_t ov() const { return (int64_t)o * v; }
+  int64_t oovv() const { return (int64_t)o * o * v * v; }
+  int64_t vlen() const { return ov() + oovv(); }  // canonical vector length
+};
+
+void build_df(Context& c, const double* B, const double* eps, const double* t1, const double* t2,
+              int precision);
+void sigma_canonical(Context& c, const double* r1, const double* r2, double* s1, double* s2, int precision);
+void symmetrize_r2(hipStream_t s, int o, int v, double* r2);
+// CIS lowest roots; vec (device [n][o][v]) may be null
+void cis_roots(Context& c, int n, double* omega, double* vec);
+void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv);
+// PNO compress / expand of nvec vectors (canonical full arrays <-> compressed)
+void pno_compress(Context& c, int nvec, const double* r1, const double* r2, double* x);
+void pno_expand(Context& c, int nvec, const double* x, double* r1, double* r2);
+void sigma_pno(Context& c, int nvec, const double* x, double* y, int precision);
+
+struct DavidsonResult {
+  std::vector<double> omega, resnorm;
+  int iters = 0;
+  int nsigma = 0;
+  bool converged = false;
+  bool complex_pair = false;
+};
+DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt);
+
+// host eigen-solver (eig.cpp); returns 0 or a negative status
+int host_eig(int n, const double* a, double* wr, double* wi, double* vr);
+
+}  // namespace pnoeom

@@ -1,0 +1,519 @@
+// Block Davidson eigensolver (non-Hermitian) on the GPU with an FP64 subspace.
+//
+// The subspace basis V and the projected sigma vectors S = P sigma(V) live in HBM
+// as [m][N] row-major FP64 arrays.  Inner products are split-K MFMA GEMMs whose
+// partial sums are reduced in a fixed order (bitwise reproducible); only the
+// m x m subspace matrix G = V S^T and the k Ritz coefficient vectors cross to
+// the host, where the small eigenproblem is solved.  The correction step is the
+// one the paper describes for the PNO simulation: residual -> (semicanonical
+// OSV/PNO basis) -> diagonal preconditioner -> back to the vector space.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <functional>
+
+#include "context.h"
+
+namespace pnoeom {
+namespace {
+
+constexpr double kClamp = 1e-4;
+
+__device__ __forceinline__ double clampd(double d) {
+  if (fabs(d) < kClamp) return d >= 0.0 ? kClamp : -kClamp;
+  return d;
+}
+
+__global__ void reduce_partials_kernel(int64_t nout, int64_t nparts, const double* __restrict__ part,
+                                       double* __restrict__ out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nout) return;
+  double acc = 0.0;
+  for (int64_t b = 0; b < nparts; ++b) acc += part[b * nout + e];
+  out[e] = acc;
+}
+
+// R[k][n] -= theta[k] * X[k][n]
+__global__ void sub_scaled_rows_kernel(int nr, int64_t N, const double* __restrict__ theta,
+                                       const double* __restrict__ X, double* __restrict__ R) {
+  const int64_t total = nr * N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    R[e] -= theta[e / N] * X[e];
+}
+
+__global__ void scale_kernel(int64_t n, double a, double* __restrict__ x) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    x[e] *= a;
+}
+
+// canonical preconditioner: singles / (theta + e_i - e_a), doubles / (theta + e_i + e_j - e_a - e_b)
+__global__ void precond_canonical_kernel(int o, int v, const double* __restrict__ eps, double theta,
+                                         double* __restrict__ x) {
+  const int64_t ov = (int64_t)o * v, n = ov + ov * ov;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    double d;
+    if (e < ov) {
+      const int i = (int)(e / v), a = (int)(e % v);
+      d = theta + eps[i] - eps[o + a];
+    } else {
+      int64_t r = e - ov;
+      const int b = (int)(r % v); r /= v;
+      const int a = (int)(r % v); r /= v;
+      const int j = (int)(r % o); r /= o;
+      const int i = (int)r;
+      d = theta + eps[i] + eps[j] - eps[o + a] - eps[o + b];
+    }
+    x[e] /= clampd(d);
+  }
+}
+
+// CIS preconditioner: r / (theta - (e_a - e_i))
+__global__ void precond_cis_kernel(int o, int v, const double* __restrict__ eps, double theta,
+                                   double* __restrict__ x) {
+  const int64_t ov = (int64_t)o * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ov; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / v), a = (int)(e % v);
+    x[e] /= clampd(theta - (eps[o + a] - eps[i]));
+  }
+}
+
+__global__ void cis_diag_kernel(int o, int v, const double* __restrict__ eps, double* __restrict__ A) {
+  const int64_t ov = (int64_t)o * v;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= ov) return;
+  const int i = (int)(e / v), a = (int)(e % v);
+  A[e * ov + e] += eps[o + a] - eps[i];
+}
+
+unsigned g1(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+struct Dots {
+  DBuf<double> part, out;
+};
+
+// host out[i][j] = sum_n A[i][n] B[j][n]   (A: na rows, B: nb rows, row stride N)
+void dots(hipStream_t s, Dots& w, const double* A, int na, const double* B, int nb, int64_t N, double* host) {
+  if (na == 0 || nb == 0) return;
+  int64_t chunk = (N + 511) / 512;
+  chunk = ((chunk + 63) / 64) * 64;
+  if (chunk < 64) chunk = 64;
+  const int64_t nfull = N / chunk;
+  const int64_t tail = N - nfull * chunk;
+  const int64_t nparts = nfull + (tail ? 1 : 0);
+  const int64_t nout = (int64_t)na * nb;
+  w.part.alloc(std::max<int64_t>(nparts * nout, w.part.n));
+  w.out.alloc(std::max<int64_t>(nout, w.out.n));
+  if (nfull) {
+    GemmDesc<double> d;
+    d.ta = false; d.tb = true; d.M = na; d.N = nb; d.K = chunk;
+    d.A = A; d.lda = N; d.sA = chunk;
+    d.B = B; d.ldb = N; d.sB = chunk;
+    d.C = w.part; d.ldc = nb; d.sC = nout; d.batch = nfull;
+    gemm(d, s);
+  }
+  if (tail) {
+    GemmDesc<double> d;
+    d.ta = false; d.tb = true; d.M = na; d.N = nb; d.K = tail;
+    d.A = A + nfull * chunk; d.lda = N;
+    d.B = B + nfull * chunk; d.ldb = N;
+    d.C = w.part + nfull * nout; d.ldc = nb;
+    gemm(d, s);
+  }
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 255) / 256), dim3(256), 0, s, nout, nparts,
+                     (const double*)w.part, (double*)w.out);
+  PNO_HIP(hipGetLastError());
+  PNO_HIP(hipMemcpyAsync(host, w.out, nout * sizeof(double), hipMemcpyDeviceToHost, s));
+  PNO_HIP(hipStreamSynchronize(s));
+}
+
+struct Operator {
+  int64_t N = 0;
+  std::function<void(int, const double*, double*)> apply;  // S = P A X for nvec rows
+  std::function<void(double*, double)> precond;            // in place, result in range(P)
+  std::function<void(double*)> project;                    // in place
+};
+
+// Orthonormal-column Q (m x k) of Y (m x k) by modified Gram-Schmidt with one re-orthogonalisation.
+std::vector<double> orth_cols(int m, int k, const std::vector<double>& Y) {
+  std::vector<double> Q = Y;
+  for (int j = 0; j < k; ++j) {
+    for (int pass = 0; pass < 2; ++pass)
+      for (int q = 0; q < j; ++q) {
+        double d = 0.0;
+        for (int i = 0; i < m; ++i) d += Q[i * k + q] * Q[i * k + j];
+        for (int i = 0; i < m; ++i) Q[i * k + j] -= d * Q[i * k + q];
+      }
+    double n = 0.0;
+    for (int i = 0; i < m; ++i) n += Q[i * k + j] * Q[i * k + j];
+    n = std::sqrt(n);
+    for (int i = 0; i < m; ++i) Q[i * k + j] /= n;
+  }
+  return Q;
+}
+
+DavidsonResult run_davidson(Context& c, Operator& op, int nroots, const double* guess, int nguess,
+                            const pnoeom_davidson_opts& opt, const char* tag, double* xout) {
+  hipStream_t s = c.stream;
+  const int64_t N = op.N;
+  const int maxs = std::max(opt.max_sub, nroots + nguess);
+  const int cap = maxs + nroots;
+  DBuf<double> V, S, X, R, cand, dY, dc, dth;
+  V.alloc((int64_t)cap * N);
+  S.alloc((int64_t)cap * N);
+  X.alloc((int64_t)nroots * N);
+  R.alloc((int64_t)nroots * N);
+  cand.alloc(N);
+  dY.alloc((int64_t)cap * nroots);
+  dc.alloc(cap);
+  dth.alloc(nroots);
+  Dots dw;
+  DavidsonResult res;
+  const double tol_r = opt.tol_r > 0 ? opt.tol_r : 0.1 * std::sqrt(opt.tol_e);
+
+  // orthonormalise x (device, length N) against V[0:m]; returns the norm left
+  auto orth = [&](double* x, int m) -> double {
+    std::vector<double> cvec(std::max(m, 1));
+    for (int pass = 0; pass < 2; ++pass) {
+      if (m > 0) {
+        dots(s, dw, V, m, x, 1, N, cvec.data());
+        PNO_HIP(hipMemcpyAsync(dc, cvec.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
+        GemmDesc<double> d;
+        d.M = 1; d.N = N; d.K = m; d.alpha = -1.0; d.beta = 1.0;
+        d.A = dc; d.lda = m; d.B = V; d.ldb = N; d.C = x; d.ldc = N;
+        gemm(d, s);
+      }
+    }
+    double nn = 0.0;
+    dots(s, dw, x, 1, x, 1, N, &nn);
+    return std::sqrt(nn);
+  };
+
+  int m = 0;
+  std::vector<int> newidx;
+  for (int g = 0; g < nguess; ++g) {
+    PNO_HIP(hipMemcpyAsync(cand, guess + (int64_t)g * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    op.project(cand);
+    double n0 = 0.0;
+    dots(s, dw, cand, 1, cand, 1, N, &n0);
+    if (n0 <= 0.0) continue;
+    hipLaunchKernelGGL(scale_kernel, dim3(g1(N)), dim3(256), 0, s, N, 1.0 / std::sqrt(n0), (double*)cand);
+    const double nrm = orth(cand, m);
+    if (nrm < 1e-10) continue;
+    hipLaunchKernelGGL(scale_kernel, dim3(g1(N)), dim3(256), 0, s, N, 1.0 / nrm, (double*)cand);
+    PNO_HIP(hipMemcpyAsync(V + (int64_t)m * N, cand, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    ++m;
+  }
+  PNO_CHECK(m >= nroots, PNOEOM_EINVAL, "Davidson: fewer independent guess vectors than roots");
+  op.apply(m, V, S);
+  res.nsigma += m;
+  std::vector<double> G((size_t)maxs * maxs);
+  {
+    std::vector<double> tmp((size_t)m * m);
+    dots(s, dw, V, m, S, m, N, tmp.data());
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) G[(size_t)i * maxs + j] = tmp[(size_t)i * m + j];
+  }
+  std::vector<double> theta_old(nroots, 0.0);
+  bool have_old = false;
+  for (int it = 1; it <= opt.max_iter; ++it) {
+    res.iters = it;
+    std::vector<double> Gm((size_t)m * m), wr(m), wi(m), vr((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) Gm[(size_t)i * m + j] = G[(size_t)i * maxs + j];
+    const int st = host_eig(m, Gm.data(), wr.data(), wi.data(), vr.data());
+    PNO_CHECK(st == PNOEOM_OK, PNOEOM_ENOTCONV, "subspace eigenproblem did not converge");
+    std::vector<double> theta(nroots), Y((size_t)m * nroots);
+    for (int k = 0; k < nroots; ++k) {
+      theta[k] = wr[k];
+      if (wi[k] != 0.0) res.complex_pair = true;
+      double n = 0.0;
+      for (int i = 0; i < m; ++i) n += vr[(size_t)i * m + k] * vr[(size_t)i * m + k];
+      n = std::sqrt(n);
+      for (int i = 0; i < m; ++i) Y[(size_t)i * nroots + k] = vr[(size_t)i * m + k] / n;
+    }
+    PNO_HIP(hipMemcpyAsync(dY, Y.data(), Y.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    PNO_HIP(hipMemcpyAsync(dth, theta.data(), nroots * sizeof(double), hipMemcpyHostToDevice, s));
+    {
+      GemmDesc<double> d;
+      d.ta = true; d.M = nroots; d.N = N; d.K = m;
+      d.A = dY; d.lda = nroots; d.B = V; d.ldb = N; d.C = X; d.ldc = N;
+      gemm(d, s);
+      d.B = S; d.C = R;
+      gemm(d, s);
+    }
+    hipLaunchKernelGGL(sub_scaled_rows_kernel, dim3(g1(nroots * N)), dim3(256), 0, s, nroots, N,
+                       (const double*)dth, (const double*)X, (double*)R);
+    std::vector<double> rr((size_t)nroots * nroots);
+    dots(s, dw, R, nroots, R, nroots, N, rr.data());
+    std::vector<double> rn(nroots);
+    std::vector<bool> conv(nroots);
+    bool all = true;
+    for (int k = 0; k < nroots; ++k) {
+      rn[k] = std::sqrt(std::max(0.0, rr[(size_t)k * nroots + k]));
+      const double de = have_old ? std::fabs(theta[k] - theta_old[k]) : 1e300;
+      conv[k] = rn[k] <= tol_r && de <= opt.tol_e;
+      all = all && conv[k];
+    }
+    res.omega = theta;
+    res.resnorm = rn;
+    if (opt.verbose) {
+      printf("[%s] it %3d m %3d", tag, it, m);
+      for (int k = 0; k < nroots; ++k) printf(" %.10f(%.1e)", theta[k], rn[k]);
+      printf("\n");
+      fflush(stdout);
+    }
+    if (all) {
+      res.converged = true;
+      if (xout)
+        PNO_HIP(hipMemcpyAsync(xout, X, (int64_t)nroots * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PNO_HIP(hipStreamSynchronize(s));
+      return res;
+    }
+    theta_old = theta;
+    have_old = true;
+    // corrections
+    std::vector<int> fresh;  // rows of R turned into new directions, staged in X
+    int nnew = 0;
+    for (int k = 0; k < nroots; ++k) {
+      if (conv[k]) continue;
+      PNO_HIP(hipMemcpyAsync(cand, R + (int64_t)k * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      op.precond(cand, theta[k]);
+      double n0 = 0.0;
+      dots(s, dw, cand, 1, cand, 1, N, &n0);
+      if (!(n0 > 0.0)) continue;
+      hipLaunchKernelGGL(scale_kernel, dim3(g1(N)), dim3(256), 0, s, N, 1.0 / std::sqrt(n0), (double*)cand);
+      // orthogonalise against V and the accepted new vectors (stored after V)
+      const double nrm = orth(cand, m + nnew);
+      if (nrm < 1e-10) continue;
+      hipLaunchKernelGGL(scale_kernel, dim3(g1(N)), dim3(256), 0, s, N, 1.0 / nrm, (double*)cand);
+      PNO_HIP(hipMemcpyAsync(V + (int64_t)(m + nnew) * N, cand, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      ++nnew;
+    }
+    PNO_CHECK(nnew > 0, PNOEOM_ENOTCONV, "Davidson stalled: no new directions");
+    if (m + nnew > maxs) {
+      // collapse onto the Ritz vectors: V <- V Q, S <- S Q, G <- Q^T G Q
+      const std::vector<double> Q = orth_cols(m, nroots, Y);
+      PNO_HIP(hipMemcpyAsync(dY, Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      GemmDesc<double> d;
+      d.ta = true; d.M = nroots; d.N = N; d.K = m;
+      d.A = dY; d.lda = nroots; d.B = V; d.ldb = N; d.C = X; d.ldc = N;
+      gemm(d, s);
+      d.B = S; d.C = R;
+      gemm(d, s);
+      // keep the staged new vectors: move them right after the collapsed block
+      DBuf<double> stage;
+      stage.alloc((int64_t)std::max(nnew, 1) * N);
+      PNO_HIP(hipMemcpyAsync(stage, V + (int64_t)m * N, (int64_t)nnew * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PNO_HIP(hipMemcpyAsync(V, X, (int64_t)nroots * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PNO_HIP(hipMemcpyAsync(S, R, (int64_t)nroots * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      std::vector<double> Gn((size_t)maxs * maxs, 0.0);
+      for (int a = 0; a < nroots; ++a)
+        for (int b = 0; b < nroots; ++b) {
+          double acc = 0.0;
+          for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) acc += Q[(size_t)i * nroots + a] * G[(size_t)i * maxs + j] * Q[(size_t)j * nroots + b];
+          Gn[(size_t)a * maxs + b] = acc;
+        }
+      G.swap(Gn);
+      m = nroots;
+      int kept = 0;
+      for (int q = 0; q < nnew; ++q) {
+        PNO_HIP(hipMemcpyAsync(cand, stage + (int64_t)q * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        const double nrm = orth(cand, m + kept);
+        if (nrm < 1e-10) continue;
+        hipLaunchKernelGGL(scale_kernel, dim3(g1(N)), dim3(256), 0, s, N, 1.0 / nrm, (double*)cand);
+        PNO_HIP(hipMemcpyAsync(V + (int64_t)(m + kept) * N, cand, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        ++kept;
+      }
+      nnew = kept;
+      PNO_CHECK(nnew > 0, PNOEOM_ENOTCONV, "Davidson stalled after collapse");
+    }
+    op.apply(nnew, V + (int64_t)m * N, S + (int64_t)m * N);
+    res.nsigma += nnew;
+    const int m1 = m + nnew;
+    {
+      std::vector<double> a((size_t)m1 * nnew), b((size_t)nnew * m);
+      dots(s, dw, V, m1, S + (int64_t)m * N, nnew, N, a.data());   // G[0:m1][m:m1]
+      for (int i = 0; i < m1; ++i)
+        for (int j = 0; j < nnew; ++j) G[(size_t)i * maxs + m + j] = a[(size_t)i * nnew + j];
+      if (m > 0) {
+        dots(s, dw, V + (int64_t)m * N, nnew, S, m, N, b.data());  // G[m:m1][0:m]
+        for (int i = 0; i < nnew; ++i)
+          for (int j = 0; j < m; ++j) G[(size_t)(m + i) * maxs + j] = b[(size_t)i * m + j];
+      }
+    }
+    m = m1;
+  }
+  res.converged = false;
+  if (xout)
+    PNO_HIP(hipMemcpyAsync(xout, X, (int64_t)nroots * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  PNO_HIP(hipStreamSynchronize(s));
+  return res;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- CIS
+void cis_roots(Context& c, int n, double* omega, double* vec) {
+  PNO_CHECK(c.have_df, PNOEOM_ESTATE, "cis before build_df");
+  const int o = c.o, v = c.v, naux = c.naux, nmo = c.nmo;
+  const int64_t ov = c.ov(), n2 = (int64_t)nmo * nmo;
+  PNO_CHECK(n >= 1 && n <= ov, PNOEOM_EINVAL, "cis: bad number of roots");
+  hipStream_t s = c.stream;
+  // A = 2 (ia|jb) - (ij|ab) + d(e_a - e_i), bare integrals
+  DBuf<double> A, BooT0, BvvT0, tmp;
+  A.alloc(ov * ov);
+  BooT0.alloc((int64_t)o * o * naux);
+  BvvT0.alloc((int64_t)v * v * naux);
+  tmp.alloc(ov * ov);
+  {
+    Perm4 p;
+    p.d[0] = o; p.d[1] = o; p.d[2] = naux; p.d[3] = 1;
+    p.is[0] = nmo; p.is[1] = 1; p.is[2] = n2; p.is[3] = 0;
+    p.os[0] = (int64_t)o * naux; p.os[1] = naux; p.os[2] = 1; p.os[3] = 0;
+    permute4(s, p, 1.0, c.B, 0.0, BooT0);
+    p.d[0] = v; p.d[1] = v;
+    p.os[0] = (int64_t)v * naux;
+    permute4(s, p, 1.0, c.B + (int64_t)o * nmo + o, 0.0, BvvT0);
+  }
+  GemmDesc<double> d;
+  d.tb = true; d.M = (int64_t)o * o; d.N = (int64_t)v * v; d.K = naux;
+  d.A = BooT0; d.lda = naux; d.B = BvvT0; d.ldb = naux; d.C = tmp; d.ldc = (int64_t)v * v;
+  gemm(d, s);
+  {
+    const int64_t dims[4] = {o, o, v, v};
+    const int pp[4] = {0, 3, 1, 2};
+    permute_c(s, dims, pp, -1.0, tmp, 0.0, A);
+  }
+  axpby(s, ov * ov, 2.0, c.G, 1.0, A);
+  hipLaunchKernelGGL(cis_diag_kernel, dim3((ov + 255) / 256), dim3(256), 0, s, o, v, (const double*)c.eps,
+                     (double*)A);
+  PNO_HIP(hipGetLastError());
+  BooT0.release();
+  BvvT0.release();
+  tmp.release();
+
+  Operator op;
+  op.N = ov;
+  const double* Ap = A;
+  op.apply = [&](int nv, const double* X, double* S) {
+    GemmDesc<double> g;
+    g.tb = true; g.M = nv; g.N = ov; g.K = ov;
+    g.A = X; g.lda = ov; g.B = Ap; g.ldb = ov; g.C = S; g.ldc = ov;
+    gemm(g, s);
+  };
+  op.precond = [&](double* x, double th) {
+    hipLaunchKernelGGL(precond_cis_kernel, dim3(g1(ov)), dim3(256), 0, s, o, v, (const double*)c.eps, th, x);
+  };
+  op.project = [](double*) {};
+  // guesses: unit vectors at the smallest orbital-energy differences
+  std::vector<double> eps(nmo);
+  PNO_HIP(hipMemcpyAsync(eps.data(), c.eps, nmo * sizeof(double), hipMemcpyDeviceToHost, s));
+  PNO_HIP(hipStreamSynchronize(s));
+  std::vector<int64_t> idx(ov);
+  for (int64_t e = 0; e < ov; ++e) idx[e] = e;
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+    return eps[o + x % v] - eps[x / v] < eps[o + y % v] - eps[y / v];
+  });
+  const int ng = (int)std::min<int64_t>(ov, std::max(2 * n, n + 4));
+  std::vector<double> gh((size_t)ng * ov, 0.0);
+  for (int g = 0; g < ng; ++g) gh[(size_t)g * ov + idx[g]] = 1.0;
+  DBuf<double> dg;
+  dg.alloc((int64_t)ng * ov);
+  PNO_HIP(hipMemcpyAsync(dg, gh.data(), gh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  pnoeom_davidson_opts opt;
+  pnoeom_davidson_defaults(&opt);
+  opt.tol_e = 1e-13;
+  opt.tol_r = 1e-10;
+  opt.max_sub = std::max(40, 4 * n + 8);
+  opt.max_iter = 300;
+  opt.verbose = 0;
+  DavidsonResult r = run_davidson(c, op, n, dg, ng, opt, "cis", vec);
+  PNO_CHECK(r.converged, PNOEOM_ENOTCONV, "CIS Davidson did not converge");
+  for (int k = 0; k < n; ++k) omega[k] = r.omega[k];
+}
+
+}  // namespace pnoeom
+
+// ----------------------------------------------------------------------------- EOM-CCSD roots
+namespace pnoeom {
+
+void precond_pno(Context& c, double* x, double theta);
+void project_pno(Context& c, double* x);
+
+DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt) {
+  PNO_CHECK(c.have_df, PNOEOM_ESTATE, "davidson before build_df");
+  PNO_CHECK(nroots >= 1 && nroots <= c.ov(), PNOEOM_EINVAL, "davidson: bad number of roots");
+  PNO_CHECK(opt.space == PNOEOM_CANONICAL || opt.space == PNOEOM_PNO, PNOEOM_EINVAL, "davidson: bad space");
+  PNO_CHECK(opt.precision == PNOEOM_FP64 || opt.precision == PNOEOM_FP32, PNOEOM_EINVAL,
+            "davidson: precision must be FP64 or FP32");
+  PNO_CHECK(opt.space == PNOEOM_CANONICAL || c.pno.built, PNOEOM_ESTATE, "PNO Davidson before build_sapno");
+  PNO_CHECK(opt.max_sub >= 2 * nroots, PNOEOM_EINVAL, "davidson: max_sub must be >= 2*nroots");
+  hipStream_t s = c.stream;
+  const int o = c.o, v = c.v;
+  const int64_t ov = c.ov();
+  // guess: CIS vectors (singles only)
+  std::vector<double> w(nroots);
+  DBuf<double> cisv;
+  cisv.alloc((int64_t)nroots * ov);
+  cis_roots(c, nroots, w.data(), cisv);
+
+  Operator op;
+  DBuf<double> guess;
+  if (opt.space == PNOEOM_CANONICAL) {
+    op.N = c.vlen();
+    guess.alloc((int64_t)nroots * op.N);
+    fill(s, (int64_t)nroots * op.N, 0.0, guess);
+    for (int k = 0; k < nroots; ++k)
+      PNO_HIP(hipMemcpyAsync(guess + (int64_t)k * op.N, cisv + (int64_t)k * ov, ov * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    op.project = [&](double* x) { symmetrize_r2(s, o, v, x + ov); };
+    op.precond = [&](double* x, double th) {
+      hipLaunchKernelGGL(precond_canonical_kernel, dim3(g1(op.N)), dim3(256), 0, s, o, v, (const double*)c.eps,
+                         th, x);
+      PNO_HIP(hipGetLastError());
+      symmetrize_r2(s, o, v, x + ov);
+    };
+  } else {
+    op.N = c.pno.len;
+    guess.alloc((int64_t)nroots * op.N);
+    DBuf<double> z2;
+    z2.alloc(c.oovv());
+    fill(s, c.oovv(), 0.0, z2);
+    for (int k = 0; k < nroots; ++k) pno_compress(c, 1, cisv + (int64_t)k * ov, z2, guess + (int64_t)k * op.N);
+    PNO_HIP(hipStreamSynchronize(s));
+    op.project = [&](double* x) { project_pno(c, x); };
+    op.precond = [&](double* x, double th) { precond_pno(c, x, th); };
+  }
+  int prec = opt.precision;
+  op.apply = [&](int nv, const double* X, double* S) {
+    if (opt.space == PNOEOM_CANONICAL) {
+      for (int q = 0; q < nv; ++q) {
+        const double* x = X + (int64_t)q * op.N;
+        double* y = S + (int64_t)q * op.N;
+        sigma_canonical(c, x, x + ov, y, y + ov, prec);
+        symmetrize_r2(s, o, v, y + ov);
+      }
+    } else {
+      sigma_pno(c, nv, X, S, prec);
+    }
+  };
+  DBuf<double> xr;
+  xr.alloc((int64_t)nroots * op.N);
+  DavidsonResult r = run_davidson(c, op, nroots, guess, nroots, opt, prec == PNOEOM_FP32 ? "eom-fp32" : "eom", xr);
+  if (prec == PNOEOM_FP32 && opt.refine_fp64 && r.converged) {
+    prec = PNOEOM_FP64;
+    DavidsonResult r2 = run_davidson(c, op, nroots, xr, nroots, opt, "eom-fp64-refine", nullptr);
+    r2.iters += r.iters;
+    r2.nsigma += r.nsigma;
+    r = r2;
+  }
+  return r;
+}
+
+}  // namespace pnoeom

@@ -1,0 +1,219 @@
+// MFMA-tiled strided/batched GEMM for gfx950 (FP64 and FP32 operands).
+//
+// One 256-thread workgroup (4 wave64s in a 2 x 2 arrangement) computes a BM x BN
+// tile of C.  Operand tiles of BK columns are staged through LDS as As[k][m] and
+// Bs[k][n] (m / n contiguous), the next tile is prefetched into registers while
+// the current one feeds the matrix cores, and each wave accumulates a
+// (BM/2) x (BN/2) block with 16x16x4 MFMA instructions
+// (v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32).  Operand layout of both:
+// lane l supplies A[l%16][k0 + l/16] and B[k0 + l/16][l%16].  Accumulator r of
+// lane l holds column l%16 and row 4*(l/16) + r (FP32) or row l/16 + 4*r (FP64),
+// as measured on gfx950.
+#include "common.h"
+
+namespace pnoeom {
+namespace {
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+  static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+  static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename T>
+struct KArgs {
+  int64_t M, N, K;
+  T alpha, beta;
+  const T* A;
+  int64_t lda, sA;
+  const T* B;
+  int64_t ldb, sB;
+  T* C;
+  int64_t ldc, sC;
+  int64_t batch;
+  int reduce;
+  int tiles_m, tiles_n;
+};
+
+constexpr int NT = 256;
+
+template <typename T, int BM, int BN, int BK, bool TA, bool TB>
+__global__ __launch_bounds__(NT) void gemm_kernel(KArgs<T> g) {
+  constexpr int PADA = (sizeof(T) == 8) ? 1 : 2;
+  __shared__ T As[BK][BM + PADA];
+  __shared__ T Bs[BK][BN + PADA];
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
+  static_assert(LA * NT == BM * BK && LB * NT == BN * BK, "tile/thread mismatch");
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // tile index -> (tm, tn): column-of-tiles major so that consecutive workgroups
+  // share the same B panel
+  const int64_t tile = blockIdx.x;
+  const int64_t tmi = tile % g.tiles_m;
+  const int64_t tni = tile / g.tiles_m;
+  const int64_t m0 = tmi * BM, n0 = tni * BN;
+  const int64_t bz = blockIdx.y;
+
+  typedef typename Mfma<T>::v4 v4;
+  v4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = v4{0, 0, 0, 0};
+
+  const int64_t ktiles = (g.K + BK - 1) / BK;
+  const int64_t nb = g.reduce ? g.batch : 1;
+  const int64_t total = ktiles * nb;
+
+  T ra[LA], rb[LB];
+
+  auto load = [&](int64_t it) {
+    const int64_t b = g.reduce ? (it / ktiles) : bz;
+    const int64_t k0 = (it % ktiles) * BK;
+    const T* A = g.A + b * g.sA;
+    const T* B = g.B + b * g.sB;
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int e = tid + q * NT;
+      int mm, kk;
+      if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      T val = 0;
+      if (gm < g.M && gk < g.K) val = TA ? A[gk * g.lda + gm] : A[gm * g.lda + gk];
+      ra[q] = val;
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int e = tid + q * NT;
+      int nn, kk;
+      if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      T val = 0;
+      if (gn < g.N && gk < g.K) val = TB ? B[gn * g.ldb + gk] : B[gk * g.ldb + gn];
+      rb[q] = val;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int e = tid + q * NT;
+      int mm, kk;
+      if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }
+      As[kk][mm] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int e = tid + q * NT;
+      int nn, kk;
+      if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
+      Bs[kk][nn] = rb[q];
+    }
+  };
+
+  if (total > 0) load(0);
+  for (int64_t it = 0; it < total; ++it) {
+    store();
+    __syncthreads();
+    if (it + 1 < total) load(it + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      T av[TM], bv[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) av[i] = As[kk + lk][wm * WM + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bv[j] = Bs[kk + lk][wn * WN + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mac(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+
+  T* C = g.C + (g.reduce ? 0 : bz * g.sC);
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int64_t gn = n0 + wn * WN + j * 16 + lr;
+      if (gn >= g.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm * WM + i * 16 + Mfma<T>::row(lk, r);
+        if (gm >= g.M) continue;
+        T* c = C + gm * g.ldc + gn;
+        T val = g.alpha * acc[i][j][r];
+        if (g.beta != T(0)) val += g.beta * (*c);
+        *c = val;
+      }
+    }
+}
+
+template <typename T, int BM, int BN, int BK>
+void launch_tile(const GemmDesc<T>& d, hipStream_t s) {
+  KArgs<T> g;
+  g.M = d.M; g.N = d.N; g.K = d.K; g.alpha = d.alpha; g.beta = d.beta;
+  g.A = d.A; g.lda = d.lda; g.sA = d.sA;
+  g.B = d.B; g.ldb = d.ldb; g.sB = d.sB;
+  g.C = d.C; g.ldc = d.ldc; g.sC = d.sC;
+  g.batch = d.batch; g.reduce = d.reduce ? 1 : 0;
+  g.tiles_m = (int)((d.M + BM - 1) / BM);
+  g.tiles_n = (int)((d.N + BN - 1) / BN);
+  const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n;
+  PNO_CHECK(tiles < (1ll << 31), PNOEOM_EINVAL, "gemm: too many tiles");
+  const int64_t gy = d.reduce ? 1 : d.batch;
+  PNO_CHECK(gy <= 65535, PNOEOM_EINVAL, "gemm: batch too large for grid.y");
+  dim3 grid((unsigned)tiles, (unsigned)gy, 1);
+  if (!d.ta && !d.tb)
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, false>), grid, dim3(NT), 0, s, g);
+  else if (d.ta && !d.tb)
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, true, false>), grid, dim3(NT), 0, s, g);
+  else if (!d.ta && d.tb)
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, true>), grid, dim3(NT), 0, s, g);
+  else
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, true, true>), grid, dim3(NT), 0, s, g);
+  PNO_HIP(hipGetLastError());
+}
+
+template <typename T>
+void gemm_impl(const GemmDesc<T>& d, hipStream_t s) {
+  PNO_CHECK(d.M >= 0 && d.N >= 0 && d.K >= 0 && d.batch >= 0, PNOEOM_EINVAL, "gemm: negative size");
+  if (d.M == 0 || d.N == 0 || d.batch == 0) return;
+  PNO_CHECK(d.A && d.B && d.C, PNOEOM_EINVAL, "gemm: null operand");
+  // tile choice: large tiles when both output dimensions fill them
+  if (d.M >= 128 && d.N >= 128)
+    launch_tile<T, 128, 128, 16>(d, s);
+  else if (d.M <= 32 && d.N >= 128)
+    launch_tile<T, 32, 128, 16>(d, s);
+  else if (d.N <= 32 && d.M >= 128)
+    launch_tile<T, 128, 32, 16>(d, s);
+  else
+    launch_tile<T, 64, 64, 16>(d, s);
+}
+
+}  // namespace
+
+void gemm(const GemmDesc<double>& d, hipStream_t s) { gemm_impl<double>(d, s); }
+void gemm(const GemmDesc<float>& d, hipStream_t s) { gemm_impl<float>(d, s); }
+
+}  // namespace pnoeom

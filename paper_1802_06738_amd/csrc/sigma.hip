@@ -1,0 +1,538 @@
+// Closed-shell EOM-CCSD sigma = <mu|[H-bar, R]|0> on the GPU.
+//
+// H-bar = exp(-T) H exp(T) (Methods).  T1 is folded into the DF factors by the
+// similarity dressing B~ = (1 - t)^T B (1 + t^T), which leaves a doubles-only
+// coupled-cluster polynomial in T2 with the dressed Hamiltonian.  Since R commutes
+// with T, sigma is the derivative of the projected CC equations along R:
+//   * R1 enters through the one-index transformation B' = -r^T B~ + B~ r^T of the
+//     dressed factors (and of the dressed core operator);
+//   * R2 enters linearly and through the two bilinear T2.T2 terms.
+// Every term is a pair of a "T-side" intermediate (built once per T in build_df)
+// applied to R, or an "R-side" intermediate applied to T; all of them are MFMA
+// GEMMs on ov x ov, o^2 x v^2 or v^2 x v^2 matrices plus layout permutations.
+// The particle-particle ladder sum_cd W_ab^cd R_ij^cd uses the dressed ladder
+// intermediate W_ab^cd = (ac|bd)~, which contains the first three terms and the
+// T1.T1 term of the paper's W_ab^cd; its T2 G_ij^cd part is applied as the
+// bilinear hole-ladder term X_klij = sum_cd (kc|ld) R_ij^cd.
+#include "context.h"
+
+namespace pnoeom {
+namespace {
+
+void gm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+        int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc) {
+  GemmDesc<double> d;
+  d.ta = ta; d.tb = tb; d.M = M; d.N = N; d.K = K; d.alpha = alpha; d.beta = beta;
+  d.A = A; d.lda = lda; d.B = B; d.ldb = ldb; d.C = C; d.ldc = ldc;
+  gemm(d, s);
+}
+
+void gmb(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+         int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C,
+         int64_t ldc, int64_t sC, int64_t batch, bool reduce = false) {
+  GemmDesc<double> d;
+  d.ta = ta; d.tb = tb; d.M = M; d.N = N; d.K = K; d.alpha = alpha; d.beta = beta;
+  d.A = A; d.lda = lda; d.sA = sA; d.B = B; d.ldb = ldb; d.sB = sB; d.C = C; d.ldc = ldc; d.sC = sC;
+  d.batch = batch; d.reduce = reduce;
+  gemm(d, s);
+}
+
+// mixed precision: C(double) = alpha op(A) op(B) + beta C with FP32 operands and FP32
+// accumulation; fa/fb/fc are staging buffers large enough for A, B and C.
+void gmf(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const float* A,
+         int64_t lda, const float* B, int64_t ldb, double beta, double* C, int64_t ldc, float* fc) {
+  GemmDesc<float> d;
+  d.ta = ta; d.tb = tb; d.M = M; d.N = N; d.K = K; d.alpha = (float)alpha; d.beta = 0.f;
+  d.A = A; d.lda = lda; d.B = B; d.ldb = ldb; d.C = fc; d.ldc = N;
+  gemm(d, s);
+  PNO_CHECK(ldc == N, PNOEOM_EINVAL, "gmf: C must be contiguous");
+  to_double(s, M * N, fc, C, beta);
+}
+
+// contiguous out[d0][d1][d2][d3] = alpha * in[i0*is0 + ...] + beta * out
+void ext(hipStream_t s, int64_t d0, int64_t d1, int64_t d2, int64_t d3, int64_t is0, int64_t is1, int64_t is2,
+         int64_t is3, const double* in, double* out, double alpha = 1.0, double beta = 0.0) {
+  Perm4 p;
+  p.d[0] = d0; p.d[1] = d1; p.d[2] = d2; p.d[3] = d3;
+  p.is[0] = is0; p.is[1] = is1; p.is[2] = is2; p.is[3] = is3;
+  p.os[3] = 1; p.os[2] = d3; p.os[1] = d2 * d3; p.os[0] = d1 * d2 * d3;
+  permute4(s, p, alpha, in, beta, out);
+}
+
+void perm(hipStream_t s, const double* in, int64_t a, int64_t b, int64_t c, int64_t d, int p0, int p1, int p2,
+          int p3, double* out, double alpha = 1.0, double beta = 0.0) {
+  const int64_t dims[4] = {a, b, c, d};
+  const int pp[4] = {p0, p1, p2, p3};
+  permute_c(s, dims, pp, alpha, in, beta, out);
+}
+
+__global__ void trace_occ_kernel(int naux, int nmo, int o, const double* __restrict__ B, double* __restrict__ d) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= naux) return;
+  const double* b = B + (int64_t)q * nmo * nmo;
+  double acc = 0.0;
+  for (int k = 0; k < o; ++k) acc += b[(int64_t)k * nmo + k];
+  d[q] = acc;
+}
+
+__global__ void add_diag_kernel(int n, const double* __restrict__ e, double* __restrict__ h) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) h[(int64_t)p * n + p] += e[p];
+}
+
+__global__ void mp2_div_kernel(int o, int v, const double* __restrict__ eps, double* __restrict__ t) {
+  const int64_t n = (int64_t)o * o * v * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    const int b = (int)(r % v); r /= v;
+    const int a = (int)(r % v); r /= v;
+    const int j = (int)(r % o); r /= o;
+    const int i = (int)r;
+    t[e] /= (eps[i] + eps[j] - eps[o + a] - eps[o + b]);
+  }
+}
+
+// s2[i][j][a][b] = Sd[ijab] + Z(i,j,a,b) + Z(j,i,b,a) with
+// Z(i,j,a,b) = Zp[i][j][a][b] + Ziajb[i][a][j][b] + Z3[j][a][i][b] - Cba[i][j][b][a]
+__global__ void assemble_s2_kernel(int o, int v, const double* __restrict__ Sd, const double* __restrict__ Zp,
+                                   const double* __restrict__ Zia, const double* __restrict__ Z3,
+                                   const double* __restrict__ Cba, double* __restrict__ s2) {
+  const int64_t n = (int64_t)o * o * v * v;
+  const int64_t V = v, O = o;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    const int64_t b = r % V; r /= V;
+    const int64_t a = r % V; r /= V;
+    const int64_t j = r % O; r /= O;
+    const int64_t i = r;
+    auto Z = [&](int64_t I, int64_t Jj, int64_t A, int64_t Bb) {
+      return Zp[((I * O + Jj) * V + A) * V + Bb] + Zia[((I * V + A) * O + Jj) * V + Bb] +
+             Z3[((Jj * V + A) * O + I) * V + Bb] - Cba[((I * O + Jj) * V + Bb) * V + A];
+    };
+    s2[e] = Sd[e] + Z(i, j, a, b) + Z(j, i, b, a);
+  }
+}
+
+__global__ void symmetrize_kernel(int o, int v, double* __restrict__ r2) {
+  const int64_t n = (int64_t)o * o * v * v;
+  const int64_t V = v, O = o;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    const int64_t b = r % V; r /= V;
+    const int64_t a = r % V; r /= V;
+    const int64_t j = r % O; r /= O;
+    const int64_t i = r;
+    const int64_t p = ((j * O + i) * V + b) * V + a;
+    if (p > e) {
+      const double m = 0.5 * (r2[e] + r2[p]);
+      r2[e] = m;
+      r2[p] = m;
+    }
+  }
+}
+
+unsigned grid1(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+// x~ = (1 - t)^T x (1 + t^T) for nb stacked nmo x nmo matrices; work has the same size as x
+void dress(Context& c, const double* x, double* out, double* work, int64_t nb) {
+  hipStream_t s = c.stream;
+  const int o = c.o, v = c.v, nmo = c.nmo;
+  const int64_t n2 = (int64_t)nmo * nmo;
+  PNO_HIP(hipMemcpyAsync(work, x, nb * n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // work[:, 0:o] += x[:, o:] t1^T
+  gmb(s, false, true, nmo, o, v, 1.0, x + o, nmo, n2, c.t1, v, 0, 1.0, work, nmo, n2, nb);
+  PNO_HIP(hipMemcpyAsync(out, work, nb * n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // out[o:, :] -= t1^T work[0:o, :]
+  gmb(s, true, false, v, nmo, o, -1.0, c.t1, v, 0, work, nmo, n2, 1.0, out + (int64_t)o * nmo, nmo, n2, nb);
+}
+
+// f = h + 2 J - K for the pairs (L, R) given (J, K summed over the listed pairs)
+void coulomb_exchange(Context& c, const double* L, const double* R, const double* dR, double* J, double* K,
+                      double beta) {
+  hipStream_t s = c.stream;
+  const int64_t n2 = (int64_t)c.nmo * c.nmo;
+  // J = dR^T L_flat   (M = 1, N = n2, K = naux)
+  gm(s, false, false, 1, n2, c.naux, 1.0, dR, c.naux, L, n2, beta, J, n2);
+  // K = sum_Q L_Q[:, 0:o] R_Q[0:o, :]
+  gmb(s, false, false, c.nmo, c.nmo, c.o, 1.0, L, c.nmo, n2, R, c.nmo, n2, beta, K, c.nmo, 0, c.naux, true);
+}
+
+}  // namespace
+
+void symmetrize_r2(hipStream_t s, int o, int v, double* r2) {
+  const int64_t n = (int64_t)o * o * v * v;
+  if (n == 0) return;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(grid1(n)), dim3(256), 0, s, o, v, r2);
+  PNO_HIP(hipGetLastError());
+}
+
+void build_df(Context& c, const double* Bin, const double* epsin, const double* t1in, const double* t2in,
+              int precision) {
+  hipStream_t s = c.stream;
+  const int o = c.o, v = c.v, nmo = c.nmo, naux = c.naux;
+  const int64_t n2 = (int64_t)nmo * nmo, ov = c.ov(), oo = (int64_t)o * o, vv = (int64_t)v * v;
+  const int64_t oovv = c.oovv();
+  c.have_df = false;
+  c.precision = precision;
+
+  c.B.alloc((int64_t)naux * n2);
+  c.eps.alloc(nmo);
+  c.t1.alloc(ov);
+  PNO_HIP(hipMemcpyAsync(c.B, Bin, (int64_t)naux * n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  PNO_HIP(hipMemcpyAsync(c.eps, epsin, nmo * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (t1in)
+    PNO_HIP(hipMemcpyAsync(c.t1, t1in, ov * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else
+    fill(s, ov, 0.0, c.t1);
+
+  // ---------------------------------------------------------------- dressing
+  c.C1.alloc((int64_t)naux * n2);
+  c.Bt.alloc((int64_t)naux * n2);
+  dress(c, c.B, c.Bt, c.C1, naux);
+  c.C1.release();
+
+  // core operator h = diag(eps) - (2 J - K) from the bare factors; dressed h~ and f~
+  c.dt.alloc(naux);
+  c.dtmp.alloc(naux);
+  c.J.alloc(n2);
+  c.K.alloc(n2);
+  c.h.alloc(n2);
+  c.hd.alloc(n2);
+  c.fd.alloc(n2);
+  hipLaunchKernelGGL(trace_occ_kernel, dim3((naux + 255) / 256), dim3(256), 0, s, naux, nmo, o,
+                     (const double*)c.B, (double*)c.dtmp);
+  coulomb_exchange(c, c.B, c.B, c.dtmp, c.J, c.K, 0.0);
+  axpby(s, n2, -2.0, c.J, 0.0, c.h);
+  axpby(s, n2, 1.0, c.K, 1.0, c.h);
+  hipLaunchKernelGGL(add_diag_kernel, dim3((nmo + 255) / 256), dim3(256), 0, s, nmo, (const double*)c.eps,
+                     (double*)c.h);
+  {
+    DBuf<double> w;
+    w.alloc(n2);
+    dress(c, c.h, c.hd, w, 1);
+  }
+  hipLaunchKernelGGL(trace_occ_kernel, dim3((naux + 255) / 256), dim3(256), 0, s, naux, nmo, o,
+                     (const double*)c.Bt, (double*)c.dt);
+  coulomb_exchange(c, c.Bt, c.Bt, c.dt, c.J, c.K, 0.0);
+  PNO_HIP(hipMemcpyAsync(c.fd, c.hd, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  axpby(s, n2, 2.0, c.J, 1.0, c.fd);
+  axpby(s, n2, -1.0, c.K, 1.0, c.fd);
+
+  // ---------------------------------------------------------------- transposed DF blocks [(p,q)][Q]
+  c.BovT.alloc(ov * naux);
+  c.BvoT.alloc(ov * naux);
+  c.BooT.alloc(oo * naux);
+  c.BvvT.alloc(vv * naux);
+  c.Bvv2.alloc(vv * naux);
+  ext(s, o, v, naux, 1, nmo, 1, n2, 0, c.Bt + o, c.BovT);
+  ext(s, o, v, naux, 1, 1, nmo, n2, 0, c.Bt + (int64_t)o * nmo, c.BvoT);
+  ext(s, o, o, naux, 1, nmo, 1, n2, 0, c.Bt, c.BooT);
+  ext(s, v, v, naux, 1, nmo, 1, n2, 0, c.Bt + (int64_t)o * nmo + o, c.BvvT);
+  ext(s, v, naux, v, 1, 1, n2, nmo, 0, c.Bt + (int64_t)o * nmo + o, c.Bvv2);
+
+  // ---------------------------------------------------------------- (kc|ld), amplitudes
+  // B~_ov = B_ov, so (ia|jb) of the bare and dressed Hamiltonians coincide.
+  c.G.alloc(ov * ov);
+  gm(s, false, true, ov, ov, naux, 1.0, c.BovT, naux, c.BovT, naux, 0.0, c.G, ov);
+  c.T.alloc(oovv);
+  if (t2in) {
+    PNO_HIP(hipMemcpyAsync(c.T, t2in, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    perm(s, c.G, o, v, o, v, 0, 2, 1, 3, c.T);
+    hipLaunchKernelGGL(mp2_div_kernel, dim3(grid1(oovv)), dim3(256), 0, s, o, v, (const double*)c.eps,
+                       (double*)c.T);
+    PNO_HIP(hipGetLastError());
+  }
+  c.U.alloc(oovv);
+  perm(s, c.T, o, o, v, v, 0, 1, 3, 2, c.U, -1.0, 0.0);
+  axpby(s, oovv, 2.0, c.T, 1.0, c.U);
+  c.Tia.alloc(oovv);
+  c.Tsia.alloc(oovv);
+  c.UiaT.alloc(oovv);
+  perm(s, c.T, o, o, v, v, 0, 2, 1, 3, c.Tia);
+  perm(s, c.T, o, o, v, v, 0, 3, 1, 2, c.Tsia);
+  PNO_HIP(hipMemcpyAsync(c.UiaT, c.Tia, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  axpby(s, oovv, -1.0, c.Tsia, 2.0, c.UiaT);
+
+  c.GX.alloc(oovv);
+  c.g2.alloc(oovv);
+  c.Gq.alloc(oovv);
+  perm(s, c.G, o, v, o, v, 0, 3, 2, 1, c.GX);
+  perm(s, c.G, o, v, o, v, 0, 2, 1, 3, c.g2);
+  perm(s, c.G, o, v, o, v, 0, 2, 3, 1, c.Gq);
+
+  // ---------------------------------------------------------------- dressed integral blocks
+  c.OVVO.alloc(oovv);
+  gm(s, false, true, ov, ov, naux, 1.0, c.BovT, naux, c.BvoT, naux, 0.0, c.OVVO, ov);
+  c.OOVVx.alloc(oovv);
+  {
+    DBuf<double> tmp;
+    tmp.alloc(oovv);
+    gm(s, false, true, oo, vv, naux, 1.0, c.BooT, naux, c.BvvT, naux, 0.0, tmp, vv);
+    perm(s, tmp, o, o, v, v, 0, 3, 1, 2, c.OOVVx);
+  }
+  c.Wh.alloc(oo * oo);
+  {
+    DBuf<double> tmp;
+    tmp.alloc(oo * oo);
+    gm(s, false, true, oo, oo, naux, 1.0, c.BooT, naux, c.BooT, naux, 0.0, tmp, oo);
+    perm(s, tmp, o, o, o, o, 1, 3, 0, 2, c.Wh);
+    gm(s, false, true, oo, oo, vv, 1.0, c.T, vv, c.g2, vv, 1.0, c.Wh, oo);
+  }
+  c.OOOVp.alloc(oo * ov);
+  {
+    DBuf<double> tmp;
+    tmp.alloc(oo * ov);
+    gm(s, false, true, oo, ov, naux, 1.0, c.BooT, naux, c.BovT, naux, 0.0, tmp, ov);
+    perm(s, tmp, o, o, o, v, 1, 0, 2, 3, c.OOOVp);
+  }
+
+  // Fock-like T intermediates
+  c.Fqvv.alloc(vv);
+  c.Fqoo.alloc(oo);
+  c.Fvv.alloc(vv);
+  c.Foo.alloc(oo);
+  c.fd_ov.alloc(ov);
+  {
+    DBuf<double> Ub;
+    Ub.alloc(oovv);
+    perm(s, c.U, o, o, v, v, 2, 0, 1, 3, Ub);
+    gm(s, false, false, v, v, oo * v, -1.0, Ub, oo * v, c.Gq, v, 0.0, c.Fqvv, v);
+  }
+  gm(s, false, true, o, o, ov * v, 1.0, c.g2, ov * v, c.U, ov * v, 0.0, c.Fqoo, o);
+  ext(s, v, v, 1, 1, nmo, 1, 0, 0, c.fd + (int64_t)o * nmo + o, c.Fvv);
+  axpby(s, vv, 1.0, c.Fqvv, 1.0, c.Fvv);
+  ext(s, o, o, 1, 1, nmo, 1, 0, 0, c.fd, c.Foo);
+  axpby(s, oo, 1.0, c.Fqoo, 1.0, c.Foo);
+  ext(s, o, v, 1, 1, nmo, 1, 0, 0, c.fd + o, c.fd_ov);
+
+  // ring intermediates: D = (kc|bj)~ + Dq(T), X = (kj|bc)~ + Xq(T)  as [(k,c),(j,b)]
+  c.Dr.alloc(oovv);
+  c.Xr.alloc(oovv);
+  c.DX2.alloc(oovv);
+  PNO_HIP(hipMemcpyAsync(c.Dr, c.OVVO, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  gm(s, false, true, ov, ov, ov, 0.5, c.G, ov, c.UiaT, ov, 1.0, c.Dr, ov);
+  gm(s, false, true, ov, ov, ov, -0.5, c.GX, ov, c.Tia, ov, 1.0, c.Dr, ov);
+  PNO_HIP(hipMemcpyAsync(c.Xr, c.OOVVx, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  gm(s, false, true, ov, ov, ov, -0.5, c.GX, ov, c.Tsia, ov, 1.0, c.Xr, ov);
+  PNO_HIP(hipMemcpyAsync(c.DX2, c.Xr, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  axpby(s, oovv, 2.0, c.Dr, -1.0, c.DX2);
+
+  // Wvo_kbij = sum_cd (kc|bd)~ T_ij^cd stored as [(i,j,b)][k]; built in slabs of b
+  c.Wvo2.alloc(oo * v * o);
+  {
+    int64_t nb = v;
+    const int64_t budget = (int64_t)1 << 28;  // doubles per temporary
+    while (nb > 1 && (int64_t)o * nb * vv > budget) nb = (nb + 1) / 2;
+    DBuf<double> t1b, t2b, t3b;
+    t1b.alloc(ov * nb * v);
+    t2b.alloc(ov * nb * v);
+    t3b.alloc(oo * o * nb);
+    for (int64_t b0 = 0; b0 < v; b0 += nb) {
+      const int64_t nbb = std::min<int64_t>(nb, v - b0);
+      // OVVV[(k,c),(b,d)] for b in slab
+      gm(s, false, true, ov, nbb * v, naux, 1.0, c.BovT, naux, c.BvvT + b0 * v * naux, naux, 0.0, t1b, nbb * v);
+      perm(s, t1b, o, v, nbb, v, 0, 2, 1, 3, t2b);   // [(k,b),(c,d)]
+      gm(s, false, true, oo, o * nbb, vv, 1.0, c.T, vv, t2b, vv, 0.0, t3b, o * nbb);  // [(i,j),(k,b)]
+      Perm4 p;
+      p.d[0] = oo; p.d[1] = nbb; p.d[2] = o; p.d[3] = 1;
+      p.is[0] = o * nbb; p.is[1] = 1; p.is[2] = nbb; p.is[3] = 0;
+      p.os[0] = (int64_t)v * o; p.os[1] = o; p.os[2] = 1; p.os[3] = 0;
+      permute4(s, p, 1.0, t3b, 0.0, c.Wvo2 + b0 * o);
+    }
+  }
+
+  // ladder matrix W[(a,b),(c,d)] = (ac|bd)~ in slabs of a
+  c.W.alloc(vv * vv);
+  {
+    int64_t na = v;
+    const int64_t budget = (int64_t)1 << 28;
+    while (na > 1 && na * v * vv > budget) na = (na + 1) / 2;
+    DBuf<double> tmp;
+    tmp.alloc(na * v * vv);
+    for (int64_t a0 = 0; a0 < v; a0 += na) {
+      const int64_t nab = std::min<int64_t>(na, v - a0);
+      gm(s, false, true, nab * v, vv, naux, 1.0, c.BvvT + a0 * v * naux, naux, c.BvvT, naux, 0.0, tmp, vv);
+      perm(s, tmp, nab, v, v, v, 0, 2, 1, 3, c.W + a0 * v * vv);
+    }
+  }
+  if (precision == PNOEOM_FP32) {
+    c.Wf.alloc(vv * vv);
+    to_float(s, vv * vv, c.W, c.Wf);
+    c.Tf.alloc(oovv);
+    c.Tiaf.alloc(oovv);
+    c.Tsiaf.alloc(oovv);
+    c.Drf.alloc(oovv);
+    c.Xrf.alloc(oovv);
+    c.DX2f.alloc(oovv);
+    to_float(s, oovv, c.T, c.Tf);
+    to_float(s, oovv, c.Tia, c.Tiaf);
+    to_float(s, oovv, c.Tsia, c.Tsiaf);
+    to_float(s, oovv, c.Dr, c.Drf);
+    to_float(s, oovv, c.Xr, c.Xrf);
+    to_float(s, oovv, c.DX2, c.DX2f);
+  }
+  PNO_HIP(hipStreamSynchronize(s));
+  c.have_df = true;
+}
+
+namespace {
+void alloc_sigma_work(Context& c, int precision) {
+  SigmaWork& w = c.sw;
+  const int64_t n2 = (int64_t)c.nmo * c.nmo, ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v;
+  const int64_t oovv = c.oovv();
+  w.Bp.alloc((int64_t)c.naux * n2);
+  w.hp.alloc(n2); w.Jp.alloc(n2); w.Kp.alloc(n2); w.fp.alloc(n2); w.dp.alloc(c.naux);
+  w.fp_ov.alloc(ov); w.fp_vv.alloc(vv); w.fp_oo.alloc(oo);
+  w.BvopT.alloc(ov * c.naux); w.BoopT.alloc(oo * c.naux); w.BvvpT.alloc(vv * c.naux);
+  w.Ria.alloc(oovv); w.Rsia.alloc(oovv); w.UiaR.alloc(oovv); w.UR.alloc(oovv); w.URp.alloc(oovv);
+  w.Ubr.alloc(oovv);
+  w.Sd.alloc(oovv); w.Ziajb.alloc(oovv); w.Z3.alloc(oovv); w.Dtot.alloc(oovv); w.Xtot.alloc(oovv);
+  w.DXtot.alloc(oovv); w.Zp.alloc(oovv); w.Cba.alloc(oovv); w.Xh.alloc(oo * oo); w.O4p.alloc(oo * oo);
+  w.OOVVp.alloc(oovv); w.M1.alloc(ov * c.naux);
+  w.Ftv.alloc(vv); w.Fto.alloc(oo);
+  if (precision == PNOEOM_FP32) {
+    const int64_t big = std::max<int64_t>(oovv, 1);
+    w.fa.alloc(big); w.fb.alloc(big); w.fc.alloc(big);
+  }
+}
+}  // namespace
+
+void sigma_canonical(Context& c, const double* r1, const double* r2, double* s1, double* s2, int precision) {
+  PNO_CHECK(c.have_df, PNOEOM_ESTATE, "sigma before build_df");
+  PNO_CHECK(precision == PNOEOM_FP64 || (precision == PNOEOM_FP32 && c.Wf.p), PNOEOM_EINVAL,
+            "sigma: FP32 contractions need build_df with precision FP32");
+  alloc_sigma_work(c, precision);
+  SigmaWork& w = c.sw;
+  hipStream_t s = c.stream;
+  const int o = c.o, v = c.v, nmo = c.nmo, naux = c.naux;
+  const int64_t n2 = (int64_t)nmo * nmo, ov = c.ov(), oo = (int64_t)o * o, vv = (int64_t)v * v;
+  const int64_t oovv = c.oovv();
+  const bool f32 = precision == PNOEOM_FP32;
+
+  // ---------------------------------------------------------------- R1: one-index transformed factors
+  fill(s, (int64_t)naux * n2, 0.0, w.Bp);
+  gmb(s, true, false, v, nmo, o, -1.0, r1, v, 0, c.Bt, nmo, n2, 1.0, w.Bp + (int64_t)o * nmo, nmo, n2, naux);
+  gmb(s, false, true, nmo, o, v, 1.0, c.Bt + o, nmo, n2, r1, v, 0, 1.0, w.Bp, nmo, n2, naux);
+  fill(s, n2, 0.0, w.hp);
+  gm(s, true, false, v, nmo, o, -1.0, r1, v, c.hd, nmo, 1.0, w.hp + (int64_t)o * nmo, nmo);
+  gm(s, false, true, nmo, o, v, 1.0, c.hd + o, nmo, r1, v, 1.0, w.hp, nmo);
+  hipLaunchKernelGGL(trace_occ_kernel, dim3((naux + 255) / 256), dim3(256), 0, s, naux, nmo, o,
+                     (const double*)w.Bp, (double*)w.dp);
+  // J' = dt^T Bp + dp^T Bt ; K' = sum_Q Bp_Q[:,occ] Bt_Q[occ,:] + Bt_Q[:,occ] Bp_Q[occ,:]
+  gm(s, false, false, 1, n2, naux, 1.0, c.dt, naux, w.Bp, n2, 0.0, w.Jp, n2);
+  gm(s, false, false, 1, n2, naux, 1.0, w.dp, naux, c.Bt, n2, 1.0, w.Jp, n2);
+  gmb(s, false, false, nmo, nmo, o, 1.0, w.Bp, nmo, n2, c.Bt, nmo, n2, 0.0, w.Kp, nmo, 0, naux, true);
+  gmb(s, false, false, nmo, nmo, o, 1.0, c.Bt, nmo, n2, w.Bp, nmo, n2, 1.0, w.Kp, nmo, 0, naux, true);
+  PNO_HIP(hipMemcpyAsync(w.fp, w.hp, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  axpby(s, n2, 2.0, w.Jp, 1.0, w.fp);
+  axpby(s, n2, -1.0, w.Kp, 1.0, w.fp);
+  ext(s, o, v, 1, 1, nmo, 1, 0, 0, w.fp + o, w.fp_ov);
+  ext(s, v, v, 1, 1, nmo, 1, 0, 0, w.fp + (int64_t)o * nmo + o, w.fp_vv);
+  ext(s, o, o, 1, 1, nmo, 1, 0, 0, w.fp, w.fp_oo);
+  ext(s, o, v, naux, 1, 1, nmo, n2, 0, w.Bp + (int64_t)o * nmo, w.BvopT);
+  ext(s, o, o, naux, 1, nmo, 1, n2, 0, w.Bp, w.BoopT);
+  ext(s, v, v, naux, 1, nmo, 1, n2, 0, w.Bp + (int64_t)o * nmo + o, w.BvvpT);
+
+  // ---------------------------------------------------------------- R2 layouts
+  perm(s, r2, o, o, v, v, 0, 2, 1, 3, w.Ria);
+  perm(s, r2, o, o, v, v, 0, 3, 1, 2, w.Rsia);
+  PNO_HIP(hipMemcpyAsync(w.UiaR, w.Ria, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  axpby(s, oovv, -1.0, w.Rsia, 2.0, w.UiaR);
+  perm(s, r2, o, o, v, v, 0, 1, 3, 2, w.UR, -1.0, 0.0);
+  axpby(s, oovv, 2.0, r2, 1.0, w.UR);
+  perm(s, w.UR, o, o, v, v, 0, 1, 3, 2, w.URp);
+  perm(s, w.UR, o, o, v, v, 2, 0, 1, 3, w.Ubr);
+
+  // ---------------------------------------------------------------- sigma1
+  ext(s, o, v, 1, 1, 1, nmo, 0, 0, w.fp + (int64_t)o * nmo, s1);        // f'_ai
+  gm(s, false, false, ov, 1, ov, 1.0, c.UiaT, ov, w.fp_ov, 1, 1.0, s1, 1);
+  gm(s, true, false, o, v, o, -1.0, c.Fqoo, o, r1, v, 1.0, s1, v);
+  gm(s, false, true, o, v, v, 1.0, r1, v, c.Fqvv, v, 1.0, s1, v);
+  gm(s, false, false, ov, 1, ov, 1.0, w.UiaR, ov, c.fd_ov, 1, 1.0, s1, 1);
+  gm(s, false, false, ov, naux, ov, 1.0, w.UiaR, ov, c.BovT, naux, 0.0, w.M1, naux);
+  gm(s, false, false, o, v, (int64_t)v * naux, 1.0, w.M1, (int64_t)v * naux, c.Bvv2, v, 1.0, s1, v);
+  gm(s, false, false, o, v, oo * v, -1.0, c.OOOVp, oo * v, w.URp, v, 1.0, s1, v);
+
+  // ---------------------------------------------------------------- sigma2, direct (not P-symmetrised)
+  if (c.timing) PNO_HIP(hipEventRecord(c.ev_lad0, s));
+  if (f32) {
+    to_float(s, oovv, r2, w.fa);
+    gmf(s, false, true, oo, vv, vv, 1.0, w.fa, vv, c.Wf, vv, 0.0, w.Sd, vv, w.fc);
+  } else {
+    gm(s, false, true, oo, vv, vv, 1.0, r2, vv, c.W, vv, 0.0, w.Sd, vv);
+  }
+  if (c.timing) {
+    PNO_HIP(hipEventRecord(c.ev_lad1, s));
+    PNO_HIP(hipEventSynchronize(c.ev_lad1));
+    float ms = 0.f;
+    PNO_HIP(hipEventElapsedTime(&ms, c.ev_lad0, c.ev_lad1));
+    c.last_ladder_ms += ms;
+    c.last_ladder_launches += 1;
+  }
+  gm(s, false, false, oo, vv, oo, 1.0, c.Wh, oo, r2, vv, 1.0, w.Sd, vv);
+  gm(s, false, true, oo, oo, vv, 1.0, r2, vv, c.g2, vv, 0.0, w.Xh, oo);
+  gm(s, false, true, oo, oo, naux, 1.0, w.BoopT, naux, c.BooT, naux, 0.0, w.O4p, oo);
+  gm(s, false, true, oo, oo, naux, 1.0, c.BooT, naux, w.BoopT, naux, 1.0, w.O4p, oo);
+  perm(s, w.O4p, o, o, o, o, 1, 3, 0, 2, w.Xh, 1.0, 1.0);
+  gm(s, false, false, oo, vv, oo, 1.0, w.Xh, oo, c.T, vv, 1.0, w.Sd, vv);
+
+  // ---------------------------------------------------------------- ring terms in [(i,a),(j,b)] form
+  gm(s, false, true, ov, ov, naux, 0.5, w.BvopT, naux, c.BvoT, naux, 0.0, w.Ziajb, ov);
+  gm(s, false, true, ov, ov, naux, 0.5, c.BvoT, naux, w.BvopT, naux, 1.0, w.Ziajb, ov);
+  // R-side intermediates D(R) and X(R)
+  gm(s, false, true, ov, ov, ov, 0.5, c.G, ov, w.UiaR, ov, 0.0, w.Dtot, ov);
+  gm(s, false, true, ov, ov, ov, -0.5, c.GX, ov, w.Ria, ov, 1.0, w.Dtot, ov);
+  gm(s, false, true, ov, ov, naux, 1.0, c.BovT, naux, w.BvopT, naux, 1.0, w.Dtot, ov);
+  gm(s, false, true, ov, ov, ov, -0.5, c.GX, ov, w.Rsia, ov, 0.0, w.Xtot, ov);
+  gm(s, false, true, oo, vv, naux, 1.0, w.BoopT, naux, c.BvvT, naux, 0.0, w.OOVVp, vv);
+  gm(s, false, true, oo, vv, naux, 1.0, c.BooT, naux, w.BvvpT, naux, 1.0, w.OOVVp, vv);
+  perm(s, w.OOVVp, o, o, v, v, 0, 3, 1, 2, w.Xtot, 1.0, 1.0);
+  PNO_HIP(hipMemcpyAsync(w.DXtot, w.Xtot, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  axpby(s, oovv, 2.0, w.Dtot, -1.0, w.DXtot);
+  if (f32) {
+    float* fa = w.fa;
+    float* fb = w.fb;
+    to_float(s, oovv, w.Ria, fa);
+    gmf(s, false, false, ov, ov, ov, 1.0, fa, ov, c.DX2f, ov, 1.0, w.Ziajb, ov, w.fc);
+    to_float(s, oovv, w.Rsia, fa);
+    gmf(s, false, false, ov, ov, ov, -1.0, fa, ov, c.Drf, ov, 1.0, w.Ziajb, ov, w.fc);
+    gmf(s, false, false, ov, ov, ov, -1.0, fa, ov, c.Xrf, ov, 0.0, w.Z3, ov, w.fc);
+    to_float(s, oovv, w.DXtot, fb);
+    gmf(s, false, false, ov, ov, ov, 1.0, c.Tiaf, ov, fb, ov, 1.0, w.Ziajb, ov, w.fc);
+    to_float(s, oovv, w.Dtot, fb);
+    gmf(s, false, false, ov, ov, ov, -1.0, c.Tsiaf, ov, fb, ov, 1.0, w.Ziajb, ov, w.fc);
+    to_float(s, oovv, w.Xtot, fb);
+    gmf(s, false, false, ov, ov, ov, -1.0, c.Tsiaf, ov, fb, ov, 1.0, w.Z3, ov, w.fc);
+  } else {
+    gm(s, false, false, ov, ov, ov, 1.0, w.Ria, ov, c.DX2, ov, 1.0, w.Ziajb, ov);
+    gm(s, false, false, ov, ov, ov, -1.0, w.Rsia, ov, c.Dr, ov, 1.0, w.Ziajb, ov);
+    gm(s, false, false, ov, ov, ov, -1.0, w.Rsia, ov, c.Xr, ov, 0.0, w.Z3, ov);
+    gm(s, false, false, ov, ov, ov, 1.0, c.Tia, ov, w.DXtot, ov, 1.0, w.Ziajb, ov);
+    gm(s, false, false, ov, ov, ov, -1.0, c.Tsia, ov, w.Dtot, ov, 1.0, w.Ziajb, ov);
+    gm(s, false, false, ov, ov, ov, -1.0, c.Tsia, ov, w.Xtot, ov, 1.0, w.Z3, ov);
+  }
+
+  // ---------------------------------------------------------------- Fock-type terms in [i][j][a][b]
+  gm(s, false, true, oo * v, v, v, 1.0, r2, v, c.Fvv, v, 0.0, w.Zp, v);
+  gmb(s, true, false, o, vv, o, -1.0, c.Foo, o, 0, r2, vv, o * vv, 1.0, w.Zp, vv, o * vv, o);
+  gm(s, false, false, v, v, oo * v, -1.0, w.Ubr, oo * v, c.Gq, v, 0.0, w.Ftv, v);
+  axpby(s, vv, 1.0, w.fp_vv, 1.0, w.Ftv);
+  gm(s, false, true, o, o, ov * v, 1.0, c.g2, ov * v, w.UR, ov * v, 0.0, w.Fto, o);
+  axpby(s, oo, 1.0, w.fp_oo, 1.0, w.Fto);
+  gm(s, false, true, oo * v, v, v, 1.0, c.T, v, w.Ftv, v, 1.0, w.Zp, v);
+  gmb(s, true, false, o, vv, o, -1.0, w.Fto, o, 0, c.T, vv, o * vv, 1.0, w.Zp, vv, o * vv, o);
+  // -P[ sum_k r_k^a Wvo_kbij ] collected as Cba[i][j][b][a] = sum_k Wvo2[(ijb)][k] r1[k][a]
+  gm(s, false, false, oo * v, v, o, 1.0, c.Wvo2, o, r1, v, 0.0, w.Cba, v);
+
+  hipLaunchKernelGGL(assemble_s2_kernel, dim3(grid1(oovv)), dim3(256), 0, s, o, v, (const double*)w.Sd,
+                     (const double*)w.Zp, (const double*)w.Ziajb, (const double*)w.Z3, (const double*)w.Cba, s2);
+  PNO_HIP(hipGetLastError());
+}
+
+}  // namespace pnoeom

@@ -1,0 +1,209 @@
+"""ctypes binding of libpnoeom.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module checks tensor shapes,
+dtypes and devices, passes raw device pointers and the current HIP stream, and
+turns status codes into exceptions.  It raises if the library is missing: there
+is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+FP64, FP32, BF16 = 0, 1, 2
+CANONICAL, PNO = 0, 1
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "ESTATE", -6: "ECOMPLEX",
+          -7: "EABORTED"}
+EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pnoeom_build_df", "pnoeom_cis",
+                    "pnoeom_build_sapno", "pnoeom_pno_layout", "pnoeom_apply_sigma", "pnoeom_davidson_defaults",
+                    "pnoeom_davidson", "pnoeom_host_eig", "pnoeom_last_timing"]
+
+
+class PnoEomError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class DavidsonOpts(C.Structure):
+    _fields_ = [("space", C.c_int), ("precision", C.c_int), ("tol_e", C.c_double), ("tol_r", C.c_double),
+                ("max_sub", C.c_int), ("max_iter", C.c_int), ("refine_fp64", C.c_int), ("verbose", C.c_int)]
+
+
+_LIB = None
+
+
+def library_path() -> str:
+    return os.path.join(HERE, "libpnoeom.so")
+
+
+def load_library():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = C.CDLL(path)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
+    lib.pnoeom_create.argtypes = [C.c_int, C.c_int, C.c_int, vp, C.POINTER(vp)]
+    lib.pnoeom_destroy.argtypes = [vp]
+    lib.pnoeom_destroy.restype = None
+    lib.pnoeom_last_error.argtypes = [vp]
+    lib.pnoeom_last_error.restype = C.c_char_p
+    lib.pnoeom_build_df.argtypes = [vp, vp, vp, vp, vp, C.c_int]
+    lib.pnoeom_cis.argtypes = [vp, C.c_int, dp, vp]
+    lib.pnoeom_build_sapno.argtypes = [vp, C.c_int, C.c_double, C.c_double, ip, ip]
+    lib.pnoeom_pno_layout.argtypes = [vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
+    lib.pnoeom_apply_sigma.argtypes = [vp, C.c_int, vp, vp, vp, vp, C.c_int, C.c_int]
+    lib.pnoeom_davidson_defaults.argtypes = [C.POINTER(DavidsonOpts)]
+    lib.pnoeom_davidson_defaults.restype = None
+    lib.pnoeom_davidson.argtypes = [vp, C.c_int, C.POINTER(DavidsonOpts), dp, dp, ip, ip]
+    lib.pnoeom_host_eig.argtypes = [C.c_int, dp, dp, dp, dp]
+    lib.pnoeom_last_timing.argtypes = [vp, dp, dp, ip]
+    _LIB = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def host_eig(a: np.ndarray, vectors: bool = True):
+    """Eigenvalues (sorted by real part) and right eigenvectors of a small dense matrix."""
+    lib = load_library()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    n = a.shape[0]
+    wr = np.zeros(n)
+    wi = np.zeros(n)
+    vr = np.zeros((n, n)) if vectors else None
+    st = lib.pnoeom_host_eig(n, _dptr(a), _dptr(wr), _dptr(wi), _dptr(vr) if vectors else None)
+    if st != 0:
+        raise PnoEomError(st, "host_eig failed")
+    return wr + 1j * wi, vr
+
+
+def _dev(t, shape=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on a HIP device")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+class PnoEom:
+    """One library context (o occupied, v virtual, naux fitting functions) on the current device."""
+
+    def __init__(self, o: int, v: int, naux: int, stream=None):
+        import torch
+        self.lib = load_library()
+        self.o, self.v, self.naux = o, v, naux
+        self.nmo = o + v
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        st = self.lib.pnoeom_create(o, v, naux, C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise PnoEomError(st, "pnoeom_create failed")
+        self.h = h
+        self._pno_len = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pnoeom_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise PnoEomError(st, self.lib.pnoeom_last_error(self.h).decode())
+
+    def build_df(self, B, eps, t1=None, t2=None, precision=FP64):
+        o, v, n = self.o, self.v, self.nmo
+        args = [_dev(B, (self.naux, n, n), "B"), _dev(eps, (n,), "eps"),
+                _dev(t1, (o, v), "t1") if t1 is not None else None,
+                _dev(t2, (o, o, v, v), "t2") if t2 is not None else None]
+        self._check(self.lib.pnoeom_build_df(self.h, *args, precision))
+
+    def cis(self, nroots, vectors=True):
+        import torch
+        om = np.zeros(nroots)
+        vec = torch.empty((nroots, self.o, self.v), dtype=torch.float64, device="cuda") if vectors else None
+        self._check(self.lib.pnoeom_cis(self.h, nroots, _dptr(om), _dev(vec) if vectors else None))
+        return om, vec
+
+    def build_sapno(self, nstates, tcut_pno, tcut_osv=-1.0):
+        npair = self.o * (self.o + 1) // 2
+        npno = np.zeros(npair, dtype=np.int32)
+        nosv = np.zeros(self.o, dtype=np.int32)
+        self._check(self.lib.pnoeom_build_sapno(self.h, nstates, tcut_pno, tcut_osv,
+                                                npno.ctypes.data_as(C.POINTER(C.c_int)),
+                                                nosv.ctypes.data_as(C.POINTER(C.c_int))))
+        self._pno_len = None
+        return npno, nosv
+
+    def pno_layout(self):
+        n = self.o + self.o * (self.o + 1) // 2 + 1
+        off = np.zeros(n, dtype=np.int64)
+        ln = C.c_longlong()
+        self._check(self.lib.pnoeom_pno_layout(self.h, off.ctypes.data_as(C.POINTER(C.c_longlong)), C.byref(ln)))
+        return off, int(ln.value)
+
+    def sigma(self, r1, r2, precision=FP64):
+        """Canonical sigma for r1 [nvec, o, v], r2 [nvec, o, o, v, v] (torch float64 on device)."""
+        import torch
+        nvec = r1.shape[0]
+        o, v = self.o, self.v
+        s1 = torch.empty_like(r1)
+        s2 = torch.empty_like(r2)
+        self._check(self.lib.pnoeom_apply_sigma(self.h, nvec, _dev(r1, (nvec, o, v), "r1"),
+                                                _dev(r2, (nvec, o, o, v, v), "r2"), _dev(s1), _dev(s2),
+                                                CANONICAL, precision))
+        return s1, s2
+
+    def sigma_pno(self, x, precision=FP64):
+        import torch
+        nvec, n = x.shape
+        y = torch.empty_like(x)
+        self._check(self.lib.pnoeom_apply_sigma(self.h, nvec, _dev(x, (nvec, n), "x"), None, _dev(y), None, PNO,
+                                                precision))
+        return y
+
+    def davidson(self, nroots, space=CANONICAL, precision=FP64, tol_e=1e-8, tol_r=-1.0, max_sub=60,
+                 max_iter=100, refine_fp64=False, verbose=False):
+        opts = DavidsonOpts()
+        self.lib.pnoeom_davidson_defaults(C.byref(opts))
+        opts.space, opts.precision, opts.tol_e, opts.tol_r = space, precision, tol_e, tol_r
+        opts.max_sub, opts.max_iter = max_sub, max_iter
+        opts.refine_fp64, opts.verbose = int(refine_fp64), int(verbose)
+        om = np.zeros(nroots)
+        rn = np.zeros(nroots)
+        it = C.c_int()
+        ns = C.c_int()
+        st = self.lib.pnoeom_davidson(self.h, nroots, C.byref(opts), _dptr(om), _dptr(rn), C.byref(it),
+                                      C.byref(ns))
+        if st not in (0, -6):
+            self._check(st)
+        return dict(omega=om, resnorm=rn, iters=it.value, nsigma=ns.value, complex=(st == -6))
+
+    def last_timing(self):
+        t = C.c_double()
+        lad = C.c_double()
+        n = C.c_int()
+        self._check(self.lib.pnoeom_last_timing(self.h, C.byref(t), C.byref(lad), C.byref(n)))
+        return dict(total_ms=t.value, ladder_ms=lad.value, ladder_launches=n.value)

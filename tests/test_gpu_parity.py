@@ -1,0 +1,117 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances: FP64 path - elementwise |gpu - oracle| <= 1e-12 * max|oracle| (the
+contractions differ only in summation order); FP32-MFMA path - 2e-5 relative
+(FP32 unit round-off 6e-8 times the contraction length ~1e2-1e4 with random
+signs); excitation energies - 1e-8 Eh (FP64) and 1e-6 Eh (mixed), the bounds
+the method's precision targets state.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synthgen import make_system, config_system, random_r, CONFIGS
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _ctx(s, precision=0, t2=None):
+    torch = _torch()
+    from paper_1802_06738_amd import PnoEom
+    ctx = PnoEom(s.o, s.v, s.naux)
+    B = torch.from_numpy(s.B).cuda()
+    eps = torch.from_numpy(s.eps).cuda()
+    t1 = torch.from_numpy(s.t1).cuda()
+    ctx.build_df(B, eps, t1, None if t2 is None else torch.from_numpy(t2).cuda(), precision=precision)
+    return ctx
+
+
+CASES = [(4, 20, 60, 0.0, 1), (5, 37, 53, 1e-2, 2), (7, 45, 90, 1e-3, 3), (12, 70, 150, 1e-3, 4)]
+
+
+@pytest.mark.parametrize("o,v,naux,t1s,seed", CASES)
+def test_sigma_fp64_matches_oracle(o, v, naux, t1s, seed):
+    print(f"[sigma fp64] o={o} v={v} naux={naux} seed={seed}", flush=True)
+    torch = _torch()
+    from oracle.sigma import SigmaOracle
+    s = make_system(o, v, naux, seed, t1_sigma=t1s)
+    ctx = _ctx(s)
+    r1, r2 = random_r(o, v, seed + 50, nvec=2)
+    g1, g2 = ctx.sigma(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda())
+    g1, g2 = g1.cpu().numpy(), g2.cpu().numpy()
+    so = SigmaOracle(s.eps, s.B, o, s.t1)
+    for k in range(2):
+        a1, a2 = so.sigma(r1[k], r2[k])
+        assert np.max(np.abs(g1[k] - a1)) <= 1e-12 * np.max(np.abs(a1))
+        assert np.max(np.abs(g2[k] - a2)) <= 1e-12 * np.max(np.abs(a2))
+
+
+@pytest.mark.parametrize("o,v,naux,t1s,seed", CASES[:3])
+def test_sigma_fp32_matches_oracle(o, v, naux, t1s, seed):
+    print(f"[sigma fp32] o={o} v={v} naux={naux} seed={seed}", flush=True)
+    torch = _torch()
+    from oracle.sigma import SigmaOracle
+    s = make_system(o, v, naux, seed, t1_sigma=t1s)
+    ctx = _ctx(s, precision=1)
+    r1, r2 = random_r(o, v, seed + 50)
+    g1, g2 = ctx.sigma(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda(), precision=1)
+    a1, a2 = SigmaOracle(s.eps, s.B, o, s.t1).sigma(r1[0], r2[0])
+    assert np.max(np.abs(g1.cpu().numpy()[0] - a1)) <= 2e-5 * np.max(np.abs(a1))
+    assert np.max(np.abs(g2.cpu().numpy()[0] - a2)) <= 2e-5 * np.max(np.abs(a2))
+
+
+def test_sigma_given_t2_and_zero_r():
+    """Explicit T2 input path; R = 0 gives sigma = 0 exactly (linearity)."""
+    torch = _torch()
+    from oracle.sigma import SigmaOracle
+    from oracle.ham import mp2_amplitudes
+    s = make_system(4, 13, 30, 8, t1_sigma=1e-2)
+    t2 = mp2_amplitudes(s.eps, s.B, 4) * 1.3
+    ctx = _ctx(s, t2=t2)
+    r1, r2 = random_r(4, 13, 9)
+    g1, g2 = ctx.sigma(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda())
+    a1, a2 = SigmaOracle(s.eps, s.B, 4, s.t1, t2).sigma(r1[0], r2[0])
+    assert np.max(np.abs(g2.cpu().numpy()[0] - a2)) <= 1e-12 * np.max(np.abs(a2))
+    z1, z2 = ctx.sigma(torch.zeros_like(torch.from_numpy(r1).cuda()), torch.zeros_like(torch.from_numpy(r2).cuda()))
+    assert float(z1.abs().max()) == 0.0 and float(z2.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("cfg,n", [(1, 3), ("pno_small", 4)])
+def test_cis_matches_oracle(cfg, n):
+    print(f"[cis] cfg={cfg}", flush=True)
+    from oracle.sapno import cis_roots
+    s = config_system(cfg)
+    ctx = _ctx(s)
+    om, vec = ctx.cis(n)
+    w, b = cis_roots(s.eps, s.B, s.o, n)
+    assert np.max(np.abs(om - w)) < 1e-11
+    vec = vec.cpu().numpy()
+    for k in range(n):
+        assert abs(abs(np.sum(vec[k] * b[k])) - 1.0) < 1e-9
+
+
+def test_davidson_c1_fp64_matches_dense_eig():
+    print("[davidson c1]", flush=True)
+    gold = json.load(open(os.path.join(GOLD, "c1.json")))
+    s = config_system(1)
+    ctx = _ctx(s)
+    r = ctx.davidson(3, tol_e=1e-10, tol_r=1e-7)
+    assert np.max(np.abs(r["omega"] - np.array(gold["dense_eig"][:3]))) <= 1e-8
+
+
+def test_davidson_c1_fp32_mixed():
+    print("[davidson c1 fp32]", flush=True)
+    gold = json.load(open(os.path.join(GOLD, "c1.json")))
+    s = config_system(1)
+    ctx = _ctx(s, precision=1)
+    r = ctx.davidson(3, precision=1, tol_e=1e-8, tol_r=1e-6)
+    assert np.max(np.abs(r["omega"] - np.array(gold["dense_eig"][:3]))) <= 1e-6

@@ -1,0 +1,61 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, and its
+host-side eigensolver agrees with LAPACK (no GPU calls)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1802_06738_amd import pnoeom
+    if not os.path.exists(pnoeom.library_path()):
+        from paper_1802_06738_amd import build_lib
+        build_lib.build()
+    return pnoeom.load_library()
+
+
+def test_header_symbols_exported():
+    lib = _lib()
+    hdr = open(os.path.join(ROOT, "include", "pnoeom.h")).read()
+    declared = set(re.findall(r"\b(pnoeom_[a-z_0-9]+)\s*\(", hdr))
+    from paper_1802_06738_amd.pnoeom import EXPORTED_SYMBOLS
+    assert declared == set(EXPORTED_SYMBOLS)
+    for name in declared:
+        assert getattr(lib, name) is not None
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (7, 2), (25, 3), (60, 4)])
+def test_host_eig_matches_lapack(n, seed):
+    _lib()
+    from paper_1802_06738_amd import host_eig
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((n, n)) + np.diag(np.linspace(0, 3, n))
+    w, vr = host_eig(a)
+    ref = np.linalg.eigvals(a)
+    ref = ref[np.lexsort((-ref.imag, ref.real))]
+    assert np.max(np.abs(w - ref)) < 1e-11 * max(1.0, np.abs(ref).max())
+    for k in range(n):
+        if abs(w[k].imag) == 0.0:
+            assert np.linalg.norm(a @ vr[:, k] - w[k].real * vr[:, k]) < 1e-10
+
+
+def test_host_eig_nearly_symmetric_degenerate():
+    _lib()
+    from paper_1802_06738_amd import host_eig
+    rng = np.random.default_rng(7)
+    q, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    d = np.array([1.0, 1.0, 2.0, 3.0, 3.0, 3.0, 4, 5, 6, 7, 8, 9])
+    a = q @ np.diag(d) @ q.T
+    w, vr = host_eig(a)
+    assert np.allclose(w.real, np.sort(d), atol=1e-12)
+    # vectors of the degenerate eigenvalues are independent
+    assert np.linalg.matrix_rank(vr[:, :2], tol=1e-6) == 2
+    assert np.linalg.matrix_rank(vr[:, 3:6], tol=1e-6) == 3
+
+
+def test_host_eig_rejects_bad_input():
+    lib = _lib()
+    assert lib.pnoeom_host_eig(0, None, None, None, None) == -1
