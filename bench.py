@@ -1,0 +1,177 @@
+"""Benchmark: closed-shell EOM-CCSD sigma evaluations and Davidson time-to-convergence
+on one MI355X, through the C-ABI library.
+
+One step = the whole hot path once for the config-2 workload (o=20 occupied,
+v=150 virtual, naux=450, T1 ~ N(0, 1e-3^2), T2 = first-order amplitudes, 6 roots,
+subspace <= 60): build the DF intermediates of H-bar, the CIS guess, and the
+Davidson iterations (sigma of every new trial vector, subspace algebra,
+preconditioner) until every root meets tol_e = 1e-8 Eh.  Inputs are uploaded to
+HBM before the timed region.
+
+Printed: one JSON line with sigma-evaluations/s (the headline value), time to
+convergence, the live roofline of the dominant kernel (the ladder contraction),
+the FP32-MFMA mixed variant with its per-root error, and the FP64 oracle timed
+on the host cores for a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "fp32": 157.3}    # MI355X dense matrix TFLOP/s
+HBM_PEAK = 8000.0                       # GB/s
+
+
+def ladder_flops_per_vector(o, v):
+    # irreducible ladder work with the +/- permutational packing: o^2 v^4 / 2
+    return 0.5 * (o * o) * (v ** 4)
+
+
+def run_steps(ctx, B, eps, t1, nroots, prec, steps, tol_e, tol_r, max_sub):
+    import torch
+    from paper_1802_06738_amd import FP64
+    res = []
+    for _ in range(steps):
+        ctx.build_df(B, eps, t1, None, precision=prec)
+        r = ctx.davidson(nroots, precision=prec, tol_e=tol_e, tol_r=tol_r, max_sub=max_sub,
+                         refine_fp64=(prec != FP64))
+        r["timing"] = ctx.last_timing()
+        res.append(r)
+    torch.cuda.synchronize()
+    return res
+
+
+def cpu_baseline(cfg_id, seconds_budget=30.0):
+    """The oracle (FP64, NumPy/OpenBLAS) timed on the host: sigma vectors per second."""
+    from synthgen import config_system, random_r
+    from oracle.sigma import SigmaOracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max(int(p.get("num_threads", 1)) for p in threadpool_info()) if threadpool_info() else 1
+    except Exception:
+        threads = os.cpu_count() or 1
+    s = config_system(cfg_id)
+    so = SigmaOracle(s.eps, s.B, s.o, s.t1)
+    r1, r2 = random_r(s.o, s.v, 7)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        so.sigma(r1[0], r2[0])
+        n += 1
+        if time.perf_counter() - t0 > seconds_budget or n >= 3:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "sigma-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} sigma vector(s) of the same workload (o={s.o}, v={s.v}, naux={s.naux}), "
+                      f"{dt:.1f} s wall, setup excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from synthgen import config_system, CONFIGS
+    from paper_1802_06738_amd import PnoEom, FP64, FP32
+
+    cfg = CONFIGS[args.config]
+    s = config_system(args.config)
+    o, v, naux, nroots = s.o, s.v, s.naux, cfg["nroots"]
+    tol_e = cfg["tol_e"]
+    tol_r = 1e-5
+    max_sub = cfg.get("max_sub", 60)
+    dev = torch.device("cuda:0")
+    B = torch.from_numpy(s.B).to(dev)
+    eps = torch.from_numpy(s.eps).to(dev)
+    t1 = torch.from_numpy(s.t1).to(dev)
+    torch.cuda.synchronize()
+    ctx = PnoEom(o, v, naux)
+
+    def measure(prec):
+        run_steps(ctx, B, eps, t1, nroots, prec, args.warmup, tol_e, tol_r, max_sub)
+        torch.cuda.synchronize()
+        print(f"[bench] precision {prec}: warmup done", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        res = run_steps(ctx, B, eps, t1, nroots, prec, args.steps, tol_e, tol_r, max_sub)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(f"[bench] precision {prec}: {args.steps} steps in {dt:.2f} s", file=sys.stderr, flush=True)
+        return res, dt
+
+    res64, dt64 = measure(FP64)
+    nsig = sum(r["nsigma"] for r in res64)
+    lad_ms = sum(r["timing"]["ladder_ms"] for r in res64)
+    lad_n = sum(r["timing"]["ladder_launches"] for r in res64)
+    omega64 = res64[-1]["omega"]
+    flops_launch = ladder_flops_per_vector(o, v)
+    avg_ms = lad_ms / max(lad_n, 1)
+    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+    out = {
+        "metric": "sigma evals/s & Davidson time-to-convergence (canonical FP64; FP32-MFMA mixed variant)",
+        "value": nsig / dt64,
+        "unit": "sigma-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt64 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"config {args.config}: canonical EOM-CCSD, o={o}, v={v}, naux={naux}, "
+                               f"{nroots} roots, tol_e={tol_e}, max_sub={max_sub}",
+                   "o": o, "v": v, "naux": naux, "nroots": nroots},
+        "time_to_convergence_s": dt64 / args.steps,
+        "sigma_per_step": nsig / args.steps,
+        "iters_per_step": res64[-1]["iters"],
+        "omega": [float(x) for x in omega64],
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK["fp64"], "traffic": None,
+                     "kernel": "ladder sum_cd W_ab^cd R_ij^cd (gemm_kernel tag 1, FP64 MFMA)",
+                     "algorithmic_flops_per_launch": flops_launch,
+                     "avg_launch_ms": avg_ms, "launches": lad_n},
+    }
+    gold = os.path.join(ROOT, "tests", "golden", f"c{args.config}.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold))
+        ref = np.array(g.get("davidson", g.get("dense_eig", []))[:nroots])
+        if ref.size == nroots:
+            out["max_abs_err_vs_oracle_eh"] = float(np.max(np.abs(omega64 - ref)))
+    if not args.no_mixed:
+        res32, dt32 = measure(FP32)
+        om32 = res32[-1]["omega"]
+        l32 = sum(r["timing"]["ladder_ms"] for r in res32)
+        n32 = sum(r["timing"]["ladder_launches"] for r in res32)
+        out["mixed_fp32"] = {
+            "time_to_convergence_s": dt32 / args.steps,
+            "sigma_evals_per_s": sum(r["nsigma"] for r in res32) / dt32,
+            "max_abs_diff_vs_fp64_eh": float(np.max(np.abs(om32 - omega64))),
+            "ladder_avg_launch_ms_fp32": l32 / max(n32, 1) if n32 else None,
+            "note": "FP32-MFMA sigma until convergence, then FP64 sigma refinement from the FP32 roots",
+        }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.config)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

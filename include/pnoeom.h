@@ -124,10 +124,11 @@ typedef struct {
   int max_iter;        /* iteration limit (ENOTCONV when reached) */
   int refine_fp64;     /* precision = FP32: finish with FP64 sigma from the converged FP32 roots */
   int verbose;         /* 1: print one line per iteration to stdout */
+  int nextra;          /* further Ritz pairs tracked and kept at collapse (need not converge) */
 } pnoeom_davidson_opts;
 
 /* Fill opts with the defaults (canonical, FP64, tol_e 1e-8, tol_r 1e-5, max_sub 60,
- * max_iter 100). */
+ * max_iter 200, nextra 0). */
 void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts);
 
 /* Lowest-real-part EOM-CCSD roots by the Davidson method with the PNO

@@ -15,8 +15,11 @@ steps are the standard non-Hermitian block Davidson method:
   7. correction for every unconverged root: the preconditioner of the basis
      (canonical, or the PNO/OSV one), normalised, orthogonalised, and dropped if
      the norm left after orthogonalisation is < 1e-10
-  8. collapse to the k Ritz vectors when the subspace would exceed max_sub
-A complex pair of Ritz values is handled with its real parts (reported).
+  8. collapse to the tracked Ritz vectors when the subspace would exceed max_sub
+nextra Ritz pairs beyond the k target roots are tracked (guessed from the next
+CIS vectors and kept at collapse) but need not converge; they speed up the
+highest target roots.  A complex pair of Ritz values is handled with its real
+parts (reported).
 """
 from __future__ import annotations
 
@@ -42,7 +45,7 @@ def _orth_against(V, x, passes=2):
 
 
 def davidson(sigma, basis, guess, o, v, nroots, tol_e=1e-8, tol_r=None, max_sub=60,
-             max_iter=200, verbose=False):
+             max_iter=200, verbose=False, nextra=0):
     """Lowest-real-part EOM roots of x -> P sigma(x) on range(P).
 
     sigma(r1, r2) -> (s1, s2); basis provides project() and precondition().
@@ -65,14 +68,16 @@ def davidson(sigma, basis, guess, o, v, nroots, tol_e=1e-8, tol_r=None, max_sub=
     S = [psig(x) for x in V]
     theta_old = None
     had_complex = False
+    ntarget = nroots
+    nk = nroots + nextra
     for it in range(1, max_iter + 1):
         Vm = np.array(V)
         Sm = np.array(S)
         G = Vm @ Sm.T
         w, Y = sla.eig(G)
         order = np.argsort(w.real, kind="stable")
-        w = w[order][:nroots]
-        Y = Y[:, order][:, :nroots]
+        w = w[order][:nk]
+        Y = Y[:, order][:, :nk]
         if np.any(np.abs(w.imag) > 0):
             had_complex = True
         theta = w.real
@@ -81,15 +86,17 @@ def davidson(sigma, basis, guess, o, v, nroots, tol_e=1e-8, tol_r=None, max_sub=
         X = Vm.T @ Y
         Rr = Sm.T @ Y - X * theta[None, :]
         rn = np.linalg.norm(Rr, axis=0)
-        de = np.abs(theta - theta_old) if theta_old is not None else np.full(nroots, np.inf)
+        de = np.abs(theta - theta_old) if theta_old is not None else np.full(nk, np.inf)
         conv = (rn <= tol_r) & (de <= tol_e)
+        conv[ntarget:] = True
         if verbose:
-            print(f"it {it:3d} m {len(V):3d} theta {theta} |r| {rn}")
+            print(f"it {it:3d} m {len(V):3d} theta {theta[:ntarget]} |r| {rn[:ntarget]}")
         if np.all(conv):
-            return dict(omega=theta, resnorm=rn, iters=it, vectors=X, complex=had_complex)
+            return dict(omega=theta[:ntarget], resnorm=rn[:ntarget], iters=it, vectors=X[:, :ntarget],
+                        complex=had_complex)
         theta_old = theta
         new = []
-        for k in range(nroots):
+        for k in range(ntarget):
             if conv[k]:
                 continue
             c1, c2 = basis.precondition(*unpack(Rr[:, k], o, v), theta[k])

@@ -192,19 +192,25 @@ class PNOBasis:
 
 
 class CanonicalBasis:
-    """P = identity; preconditioner with the canonical orbital energies."""
+    """P = identity (on the singlet space); diagonal preconditioner.
 
-    def __init__(self, eps, o):
+    The denominators use the occupied / virtual one-particle energies eo, ev
+    (default: the orbital energies; the Davidson drivers pass the diagonal of the
+    one-particle part of H-bar).
+    """
+
+    def __init__(self, eps, o, eo=None, ev=None):
         self.eps = eps
         self.o = o
+        self.eo = eps[:o] if eo is None else eo
+        self.ev = eps[o:] if ev is None else ev
 
     def project(self, r1, r2):
         return r1.copy(), symmetrize(r2)
 
     def precondition(self, r1, r2, omega):
-        o = self.o
-        eo = self.eps[:o]
-        ev = self.eps[o:]
+        eo = self.eo
+        ev = self.ev
         d1 = omega + eo[:, None] - ev[None, :]
         d2 = omega + eo[:, None, None, None] + eo[None, :, None, None] \
             - ev[None, None, :, None] - ev[None, None, None, :]

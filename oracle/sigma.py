@@ -51,6 +51,19 @@ class SigmaOracle:
         s2 += l2(self.Hd, r2) + q2(self.Hd, t2, r2) + q2(self.Hd, r2, t2)
         return s1, s2
 
+    def dressed_fock_diagonals(self):
+        """Diagonal of the one-particle part of H-bar at fixed T: f~ + the T2 terms.
+
+        F_kj = f~_kj + sum_lcd U_jl^cd (kc|ld),  F_bc = f~_bc - sum_kld U_kl^bd (kc|ld).
+        Used only by the Davidson preconditioner (convergence, not results).
+        """
+        from .residual import u_of
+        g = self.Hd.eri("ovov")
+        U = u_of(self.t2)
+        foo = self.Hd.fo("oo") + np.einsum("jlcd,kcld->kj", U, g, optimize=True)
+        fvv = self.Hd.fo("vv") - np.einsum("klbd,kcld->bc", U, g, optimize=True)
+        return np.diag(foo).copy(), np.diag(fvv).copy(), fvv
+
     def sigma_terms(self, r1, r2):
         """The R2-driven doubles pieces one by one (for per-term parity)."""
         Hd = self.Hd

@@ -38,8 +38,7 @@ struct Timer {
     c.last_ladder_ms = 0;
     c.last_ladder_launches = 0;
     c.timing = true;
-    if (!c.ev_lad0) PNO_HIP(hipEventCreate(&c.ev_lad0));
-    if (!c.ev_lad1) PNO_HIP(hipEventCreate(&c.ev_lad1));
+    c.ev_used = 0;
     PNO_HIP(hipEventCreate(&a));
     PNO_HIP(hipEventCreate(&b));
     PNO_HIP(hipEventRecord(a, c.stream));
@@ -50,6 +49,14 @@ struct Timer {
     float ms = 0.f;
     PNO_HIP(hipEventElapsedTime(&ms, a, b));
     c.last_total_ms = ms;
+    double lad = 0.0;
+    for (size_t k = 0; k + 1 < c.ev_used; k += 2) {
+      float t = 0.f;
+      PNO_HIP(hipEventElapsedTime(&t, c.ev_pool[k], c.ev_pool[k + 1]));
+      lad += t;
+    }
+    c.last_ladder_ms = lad;
+    c.last_ladder_launches = (int)(c.ev_used / 2);
   }
   ~Timer() {
     c.timing = false;
@@ -79,8 +86,7 @@ int pnoeom_create(int o, int v, int naux, void* hip_stream, pnoeom_ctx** out) {
 
 void pnoeom_destroy(pnoeom_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->c.ev_lad0) (void)hipEventDestroy(ctx->c.ev_lad0);
-  if (ctx->c.ev_lad1) (void)hipEventDestroy(ctx->c.ev_lad1);
+  for (hipEvent_t e : ctx->c.ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -156,9 +162,10 @@ void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts) {
   opts->tol_e = 1e-8;
   opts->tol_r = 1e-5;
   opts->max_sub = 60;
-  opts->max_iter = 100;
+  opts->max_iter = 200;
   opts->refine_fp64 = 0;
   opts->verbose = 0;
+  opts->nextra = 0;
 }
 
 int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opts, double* omega_out,

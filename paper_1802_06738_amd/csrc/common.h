@@ -77,6 +77,7 @@ struct GemmDesc {
   int64_t ldc = 0, sC = 0;
   int64_t batch = 1;
   bool reduce = false;
+  int tag = 0;  // 1: the particle-particle ladder (own kernel symbol, for profiling)
 };
 
 void gemm(const GemmDesc<double>& d, hipStream_t s);

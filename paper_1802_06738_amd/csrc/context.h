@@ -66,8 +66,17 @@ struct Context {
   // timing of the last sigma / Davidson call
   double last_total_ms = 0, last_ladder_ms = 0;
   int last_ladder_launches = 0;
-  hipEvent_t ev_lad0 = nullptr, ev_lad1 = nullptr;
   bool timing = false;
+  std::vector<hipEvent_t> ev_pool;  // start/stop pairs around ladder launches
+  size_t ev_used = 0;
+  hipEvent_t next_event() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      PNO_HIP(hipEventCreate(&e));
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
 
   int64_t ov() const { return (int64_t)o * v; }
   int64_t oovv() const { return (int64_t)o * o * v * v; }

@@ -46,22 +46,23 @@ __global__ void scale_kernel(int64_t n, double a, double* __restrict__ x) {
     x[e] *= a;
 }
 
-// canonical preconditioner: singles / (theta + e_i - e_a), doubles / (theta + e_i + e_j - e_a - e_b)
-__global__ void precond_canonical_kernel(int o, int v, const double* __restrict__ eps, double theta,
-                                         double* __restrict__ x) {
+// canonical preconditioner: singles / (theta + F_ii - F_aa), doubles / (theta + F_ii + F_jj - F_aa - F_bb)
+// with the diagonals of the one-particle part of H-bar (F_oo, F_vv, row-major o x o and v x v)
+__global__ void precond_canonical_kernel(int o, int v, const double* __restrict__ Foo, const double* __restrict__ Fvv,
+                                         double theta, double* __restrict__ x) {
   const int64_t ov = (int64_t)o * v, n = ov + ov * ov;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     double d;
     if (e < ov) {
       const int i = (int)(e / v), a = (int)(e % v);
-      d = theta + eps[i] - eps[o + a];
+      d = theta + Foo[(int64_t)i * o + i] - Fvv[(int64_t)a * v + a];
     } else {
       int64_t r = e - ov;
       const int b = (int)(r % v); r /= v;
       const int a = (int)(r % v); r /= v;
       const int j = (int)(r % o); r /= o;
       const int i = (int)r;
-      d = theta + eps[i] + eps[j] - eps[o + a] - eps[o + b];
+      d = theta + Foo[(int64_t)i * o + i] + Foo[(int64_t)j * o + j] - Fvv[(int64_t)a * v + a] - Fvv[(int64_t)b * v + b];
     }
     x[e] /= clampd(d);
   }
@@ -156,10 +157,13 @@ std::vector<double> orth_cols(int m, int k, const std::vector<double>& Y) {
   return Q;
 }
 
-DavidsonResult run_davidson(Context& c, Operator& op, int nroots, const double* guess, int nguess,
-                            const pnoeom_davidson_opts& opt, const char* tag, double* xout) {
+// nroots roots must converge; nextra further Ritz pairs are tracked (and kept at
+// collapse) to speed up convergence of the highest target root.
+DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double* guess, int nguess,
+                            const pnoeom_davidson_opts& opt, const char* tag, double* xout, int nextra = 0) {
   hipStream_t s = c.stream;
   const int64_t N = op.N;
+  const int nroots = ntarget + nextra;
   const int maxs = std::max(opt.max_sub, nroots + nguess);
   const int cap = maxs + nroots;
   DBuf<double> V, S, X, R, cand, dY, dc, dth;
@@ -209,6 +213,7 @@ DavidsonResult run_davidson(Context& c, Operator& op, int nroots, const double* 
     ++m;
   }
   PNO_CHECK(m >= nroots, PNOEOM_EINVAL, "Davidson: fewer independent guess vectors than roots");
+  PNO_CHECK(m <= maxs, PNOEOM_EINVAL, "Davidson: more guess vectors than the subspace holds");
   op.apply(m, V, S);
   res.nsigma += m;
   std::vector<double> G((size_t)maxs * maxs);
@@ -256,21 +261,21 @@ DavidsonResult run_davidson(Context& c, Operator& op, int nroots, const double* 
     for (int k = 0; k < nroots; ++k) {
       rn[k] = std::sqrt(std::max(0.0, rr[(size_t)k * nroots + k]));
       const double de = have_old ? std::fabs(theta[k] - theta_old[k]) : 1e300;
-      conv[k] = rn[k] <= tol_r && de <= opt.tol_e;
+      conv[k] = (k >= ntarget) || (rn[k] <= tol_r && de <= opt.tol_e);
       all = all && conv[k];
     }
-    res.omega = theta;
-    res.resnorm = rn;
+    res.omega.assign(theta.begin(), theta.begin() + ntarget);
+    res.resnorm.assign(rn.begin(), rn.begin() + ntarget);
     if (opt.verbose) {
       printf("[%s] it %3d m %3d", tag, it, m);
-      for (int k = 0; k < nroots; ++k) printf(" %.10f(%.1e)", theta[k], rn[k]);
+      for (int k = 0; k < ntarget; ++k) printf(" %.10f(%.1e)", theta[k], rn[k]);
       printf("\n");
       fflush(stdout);
     }
     if (all) {
       res.converged = true;
       if (xout)
-        PNO_HIP(hipMemcpyAsync(xout, X, (int64_t)nroots * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        PNO_HIP(hipMemcpyAsync(xout, X, (int64_t)ntarget * N * sizeof(double), hipMemcpyDeviceToDevice, s));
       PNO_HIP(hipStreamSynchronize(s));
       return res;
     }
@@ -351,7 +356,7 @@ DavidsonResult run_davidson(Context& c, Operator& op, int nroots, const double* 
   }
   res.converged = false;
   if (xout)
-    PNO_HIP(hipMemcpyAsync(xout, X, (int64_t)nroots * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PNO_HIP(hipMemcpyAsync(xout, X, (int64_t)ntarget * N * sizeof(double), hipMemcpyDeviceToDevice, s));
   PNO_HIP(hipStreamSynchronize(s));
   return res;
 }
@@ -428,12 +433,13 @@ void cis_roots(Context& c, int n, double* omega, double* vec) {
   PNO_HIP(hipMemcpyAsync(dg, gh.data(), gh.size() * sizeof(double), hipMemcpyHostToDevice, s));
   pnoeom_davidson_opts opt;
   pnoeom_davidson_defaults(&opt);
-  opt.tol_e = 1e-13;
-  opt.tol_r = 1e-10;
+  opt.tol_e = 1e-12;
+  opt.tol_r = 1e-9;
   opt.max_sub = std::max(40, 4 * n + 8);
   opt.max_iter = 300;
   opt.verbose = 0;
-  DavidsonResult r = run_davidson(c, op, n, dg, ng, opt, "cis", vec);
+  const int nextra = (int)std::min<int64_t>(ov - n, std::max(2, n / 2));
+  DavidsonResult r = run_davidson(c, op, n, dg, ng, opt, "cis", vec, nextra);
   PNO_CHECK(r.converged, PNOEOM_ENOTCONV, "CIS Davidson did not converge");
   for (int k = 0; k < n; ++k) omega[k] = r.omega[k];
 }
@@ -453,39 +459,41 @@ DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt)
   PNO_CHECK(opt.precision == PNOEOM_FP64 || opt.precision == PNOEOM_FP32, PNOEOM_EINVAL,
             "davidson: precision must be FP64 or FP32");
   PNO_CHECK(opt.space == PNOEOM_CANONICAL || c.pno.built, PNOEOM_ESTATE, "PNO Davidson before build_sapno");
-  PNO_CHECK(opt.max_sub >= 2 * nroots, PNOEOM_EINVAL, "davidson: max_sub must be >= 2*nroots");
+  PNO_CHECK(opt.nextra >= 0 && nroots + opt.nextra <= c.ov(), PNOEOM_EINVAL, "davidson: bad nextra");
+  const int nk = nroots + opt.nextra;
+  PNO_CHECK(opt.max_sub >= 2 * nk, PNOEOM_EINVAL, "davidson: max_sub must be >= 2*(nroots+nextra)");
   hipStream_t s = c.stream;
   const int o = c.o, v = c.v;
   const int64_t ov = c.ov();
-  // guess: CIS vectors (singles only)
-  std::vector<double> w(nroots);
+  // guess: CIS vectors (singles only), one per tracked root
+  std::vector<double> w(nk);
   DBuf<double> cisv;
-  cisv.alloc((int64_t)nroots * ov);
-  cis_roots(c, nroots, w.data(), cisv);
+  cisv.alloc((int64_t)nk * ov);
+  cis_roots(c, nk, w.data(), cisv);
 
   Operator op;
   DBuf<double> guess;
   if (opt.space == PNOEOM_CANONICAL) {
     op.N = c.vlen();
-    guess.alloc((int64_t)nroots * op.N);
-    fill(s, (int64_t)nroots * op.N, 0.0, guess);
-    for (int k = 0; k < nroots; ++k)
+    guess.alloc((int64_t)nk * op.N);
+    fill(s, (int64_t)nk * op.N, 0.0, guess);
+    for (int k = 0; k < nk; ++k)
       PNO_HIP(hipMemcpyAsync(guess + (int64_t)k * op.N, cisv + (int64_t)k * ov, ov * sizeof(double),
                              hipMemcpyDeviceToDevice, s));
     op.project = [&](double* x) { symmetrize_r2(s, o, v, x + ov); };
     op.precond = [&](double* x, double th) {
-      hipLaunchKernelGGL(precond_canonical_kernel, dim3(g1(op.N)), dim3(256), 0, s, o, v, (const double*)c.eps,
-                         th, x);
+      hipLaunchKernelGGL(precond_canonical_kernel, dim3(g1(op.N)), dim3(256), 0, s, o, v, (const double*)c.Foo,
+                         (const double*)c.Fvv, th, x);
       PNO_HIP(hipGetLastError());
       symmetrize_r2(s, o, v, x + ov);
     };
   } else {
     op.N = c.pno.len;
-    guess.alloc((int64_t)nroots * op.N);
+    guess.alloc((int64_t)nk * op.N);
     DBuf<double> z2;
     z2.alloc(c.oovv());
     fill(s, c.oovv(), 0.0, z2);
-    for (int k = 0; k < nroots; ++k) pno_compress(c, 1, cisv + (int64_t)k * ov, z2, guess + (int64_t)k * op.N);
+    for (int k = 0; k < nk; ++k) pno_compress(c, 1, cisv + (int64_t)k * ov, z2, guess + (int64_t)k * op.N);
     PNO_HIP(hipStreamSynchronize(s));
     op.project = [&](double* x) { project_pno(c, x); };
     op.precond = [&](double* x, double th) { precond_pno(c, x, th); };
@@ -505,10 +513,11 @@ DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt)
   };
   DBuf<double> xr;
   xr.alloc((int64_t)nroots * op.N);
-  DavidsonResult r = run_davidson(c, op, nroots, guess, nroots, opt, prec == PNOEOM_FP32 ? "eom-fp32" : "eom", xr);
+  DavidsonResult r = run_davidson(c, op, nroots, guess, nk, opt, prec == PNOEOM_FP32 ? "eom-fp32" : "eom", xr,
+                                  opt.nextra);
   if (prec == PNOEOM_FP32 && opt.refine_fp64 && r.converged) {
     prec = PNOEOM_FP64;
-    DavidsonResult r2 = run_davidson(c, op, nroots, xr, nroots, opt, "eom-fp64-refine", nullptr);
+    DavidsonResult r2 = run_davidson(c, op, nroots, xr, nroots, opt, "eom-fp64-refine", nullptr, 0);
     r2.iters += r.iters;
     r2.nsigma += r.nsigma;
     r = r2;

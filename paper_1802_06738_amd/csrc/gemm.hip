@@ -9,6 +9,8 @@
 // lane l supplies A[l%16][k0 + l/16] and B[k0 + l/16][l%16].  Accumulator r of
 // lane l holds column l%16 and row 4*(l/16) + r (FP32) or row l/16 + 4*r (FP64),
 // as measured on gfx950.
+#include <algorithm>
+
 #include "common.h"
 
 namespace pnoeom {
@@ -46,11 +48,13 @@ struct KArgs {
   int64_t batch;
   int reduce;
   int tiles_m, tiles_n;
+  int64_t it_split;   // K-loop iterations per split (split-K); 0: no split
+  T* ws;              // split-K partials [split][batch_out][M][N]
 };
 
 constexpr int NT = 256;
 
-template <typename T, int BM, int BN, int BK, bool TA, bool TB>
+template <typename T, int BM, int BN, int BK, bool TA, bool TB, int TAG>
 __global__ __launch_bounds__(NT) void gemm_kernel(KArgs<T> g) {
   constexpr int PADA = (sizeof(T) == 8) ? 1 : 2;
   __shared__ T As[BK][BM + PADA];
@@ -130,11 +134,16 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs<T> g) {
     }
   };
 
-  if (total > 0) load(0);
-  for (int64_t it = 0; it < total; ++it) {
+  int64_t it_begin = 0, it_end = total;
+  if (g.it_split > 0) {
+    it_begin = (int64_t)blockIdx.z * g.it_split;
+    it_end = it_begin + g.it_split < total ? it_begin + g.it_split : total;
+  }
+  if (it_begin < it_end) load(it_begin);
+  for (int64_t it = it_begin; it < it_end; ++it) {
     store();
     __syncthreads();
-    if (it + 1 < total) load(it + 1);
+    if (it + 1 < it_end) load(it + 1);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T av[TM], bv[TN];
@@ -150,7 +159,16 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs<T> g) {
     __syncthreads();
   }
 
-  T* C = g.C + (g.reduce ? 0 : bz * g.sC);
+  const bool split = g.it_split > 0;
+  T* C;
+  int64_t ldc;
+  if (split) {
+    C = g.ws + ((int64_t)blockIdx.z * gridDim.y + bz) * g.M * g.N;
+    ldc = g.N;
+  } else {
+    C = g.C + (g.reduce ? 0 : bz * g.sC);
+    ldc = g.ldc;
+  }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -161,12 +179,44 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs<T> g) {
       for (int r = 0; r < 4; ++r) {
         const int64_t gm = m0 + wm * WM + i * 16 + Mfma<T>::row(lk, r);
         if (gm >= g.M) continue;
-        T* c = C + gm * g.ldc + gn;
+        T* c = C + gm * ldc + gn;
         T val = g.alpha * acc[i][j][r];
-        if (g.beta != T(0)) val += g.beta * (*c);
+        if (!split && g.beta != T(0)) val += g.beta * (*c);
         *c = val;
       }
     }
+}
+
+// C[b][m][n] = beta * C[b][m][n] + sum_z ws[z][b][m][n], summed in split order
+template <typename T>
+__global__ void splitk_reduce_kernel(int64_t M, int64_t N, int64_t nb, int64_t nsplit, T beta, const T* __restrict__ ws,
+                                     T* __restrict__ C, int64_t ldc, int64_t sC) {
+  const int64_t per = M * N;
+  const int64_t total = per * nb;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / per, r = e % per;
+    const int64_t m = r / N, n = r % N;
+    T acc = 0;
+    for (int64_t z = 0; z < nsplit; ++z) acc += ws[(z * nb + b) * per + r];
+    T* c = C + b * sC + m * ldc + n;
+    if (beta != T(0)) acc += beta * (*c);
+    *c = acc;
+  }
+}
+
+// split-K workspace, grown on demand and kept for the life of the process
+template <typename T>
+T* splitk_ws(size_t count) {
+  static T* p = nullptr;
+  static size_t cap = 0;
+  if (count > cap) {
+    if (p) PNO_HIP(hipFree(p));
+    p = nullptr;
+    cap = 0;
+    PNO_HIP(hipMalloc(&p, count * sizeof(T)));
+    cap = count;
+  }
+  return p;
 }
 
 template <typename T, int BM, int BN, int BK>
@@ -183,16 +233,40 @@ void launch_tile(const GemmDesc<T>& d, hipStream_t s) {
   PNO_CHECK(tiles < (1ll << 31), PNOEOM_EINVAL, "gemm: too many tiles");
   const int64_t gy = d.reduce ? 1 : d.batch;
   PNO_CHECK(gy <= 65535, PNOEOM_EINVAL, "gemm: batch too large for grid.y");
-  dim3 grid((unsigned)tiles, (unsigned)gy, 1);
-  if (!d.ta && !d.tb)
-    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, false>), grid, dim3(NT), 0, s, g);
+  // split the K loop when the output has too few tiles to fill the 256 CUs
+  const int64_t loop = ((d.K + BK - 1) / BK) * (d.reduce ? d.batch : 1);
+  int64_t nsplit = 1;
+  if (tiles * gy < 256 && loop >= 32) {
+    nsplit = std::min<int64_t>(loop / 8, (512 + tiles * gy - 1) / (tiles * gy));
+    nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, 1024));
+  }
+  g.it_split = 0;
+  g.ws = nullptr;
+  if (nsplit > 1) {
+    g.it_split = (loop + nsplit - 1) / nsplit;
+    nsplit = (loop + g.it_split - 1) / g.it_split;
+    g.ws = splitk_ws<T>((size_t)nsplit * gy * d.M * d.N);
+  }
+  dim3 grid((unsigned)tiles, (unsigned)gy, (unsigned)nsplit);
+  if (d.tag == 1 && !d.ta && d.tb)
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, true, 1>), grid, dim3(NT), 0, s, g);
+  else if (!d.ta && !d.tb)
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, false, 0>), grid, dim3(NT), 0, s, g);
   else if (d.ta && !d.tb)
-    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, true, false>), grid, dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, true, false, 0>), grid, dim3(NT), 0, s, g);
   else if (!d.ta && d.tb)
-    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, true>), grid, dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, true, 0>), grid, dim3(NT), 0, s, g);
   else
-    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, true, true>), grid, dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, true, true, 0>), grid, dim3(NT), 0, s, g);
   PNO_HIP(hipGetLastError());
+  if (nsplit > 1) {
+    const int64_t total = gy * d.M * d.N;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, (int64_t)d.M,
+                       (int64_t)d.N, gy, nsplit, d.beta, (const T*)g.ws, d.C, d.ldc, d.reduce ? 0 : d.sC);
+    PNO_HIP(hipGetLastError());
+  }
 }
 
 template <typename T>

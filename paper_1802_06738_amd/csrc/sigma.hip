@@ -460,20 +460,26 @@ void sigma_canonical(Context& c, const double* r1, const double* r2, double* s1,
   gm(s, false, false, o, v, oo * v, -1.0, c.OOOVp, oo * v, w.URp, v, 1.0, s1, v);
 
   // ---------------------------------------------------------------- sigma2, direct (not P-symmetrised)
-  if (c.timing) PNO_HIP(hipEventRecord(c.ev_lad0, s));
+  hipEvent_t lad0 = nullptr, lad1 = nullptr;
+  if (c.timing) {
+    lad0 = c.next_event();
+    lad1 = c.next_event();
+    PNO_HIP(hipEventRecord(lad0, s));
+  }
   if (f32) {
     to_float(s, oovv, r2, w.fa);
-    gmf(s, false, true, oo, vv, vv, 1.0, w.fa, vv, c.Wf, vv, 0.0, w.Sd, vv, w.fc);
+    GemmDesc<float> d;
+    d.tb = true; d.M = oo; d.N = vv; d.K = vv; d.tag = 1;
+    d.A = w.fa; d.lda = vv; d.B = c.Wf; d.ldb = vv; d.C = w.fc; d.ldc = vv;
+    gemm(d, s);
+    if (c.timing) PNO_HIP(hipEventRecord(lad1, s));
+    to_double(s, oovv, w.fc, w.Sd, 0.0);
   } else {
-    gm(s, false, true, oo, vv, vv, 1.0, r2, vv, c.W, vv, 0.0, w.Sd, vv);
-  }
-  if (c.timing) {
-    PNO_HIP(hipEventRecord(c.ev_lad1, s));
-    PNO_HIP(hipEventSynchronize(c.ev_lad1));
-    float ms = 0.f;
-    PNO_HIP(hipEventElapsedTime(&ms, c.ev_lad0, c.ev_lad1));
-    c.last_ladder_ms += ms;
-    c.last_ladder_launches += 1;
+    GemmDesc<double> d;
+    d.tb = true; d.M = oo; d.N = vv; d.K = vv; d.tag = 1;
+    d.A = r2; d.lda = vv; d.B = c.W; d.ldb = vv; d.C = w.Sd; d.ldc = vv;
+    gemm(d, s);
+    if (c.timing) PNO_HIP(hipEventRecord(lad1, s));
   }
   gm(s, false, false, oo, vv, oo, 1.0, c.Wh, oo, r2, vv, 1.0, w.Sd, vv);
   gm(s, false, true, oo, oo, vv, 1.0, r2, vv, c.g2, vv, 0.0, w.Xh, oo);

@@ -31,7 +31,8 @@ class PnoEomError(RuntimeError):
 
 class DavidsonOpts(C.Structure):
     _fields_ = [("space", C.c_int), ("precision", C.c_int), ("tol_e", C.c_double), ("tol_r", C.c_double),
-                ("max_sub", C.c_int), ("max_iter", C.c_int), ("refine_fp64", C.c_int), ("verbose", C.c_int)]
+                ("max_sub", C.c_int), ("max_iter", C.c_int), ("refine_fp64", C.c_int), ("verbose", C.c_int),
+                ("nextra", C.c_int)]
 
 
 _LIB = None
@@ -185,12 +186,12 @@ class PnoEom:
         return y
 
     def davidson(self, nroots, space=CANONICAL, precision=FP64, tol_e=1e-8, tol_r=-1.0, max_sub=60,
-                 max_iter=100, refine_fp64=False, verbose=False):
+                 max_iter=200, refine_fp64=False, verbose=False, nextra=0):
         opts = DavidsonOpts()
         self.lib.pnoeom_davidson_defaults(C.byref(opts))
         opts.space, opts.precision, opts.tol_e, opts.tol_r = space, precision, tol_e, tol_r
         opts.max_sub, opts.max_iter = max_sub, max_iter
-        opts.refine_fp64, opts.verbose = int(refine_fp64), int(verbose)
+        opts.refine_fp64, opts.verbose, opts.nextra = int(refine_fp64), int(verbose), int(nextra)
         om = np.zeros(nroots)
         rn = np.zeros(nroots)
         it = C.c_int()

@@ -13,8 +13,13 @@ Recipe (one seeded PCG64 stream, fixed draw order):
                                 then mirrored so B^Q_pq = B^Q_qp
   4. optional T1 amplitudes     t_i^a ~ N(0, sigma_t1^2)
 The Fock matrix is diag(eps) by construction, so Brillouin's condition f_ia = 0
-holds exactly.  sigma_B defaults to 0.05*sqrt(60/naux), which equals 0.05 at
-naux = 60 and keeps sum_Q (B^Q_pq)^2 independent of naux.  An optional virtual
+holds exactly.  sigma_B defaults to 0.05 * (4*20^2*60 / (o*v^2*naux))^(1/4): the
+literal 0.05 at o=4, v=20, naux=60, scaled so that the second-order correlation
+energy per occupied orbital (proportional to o v^2 naux sigma_B^4) stays at that
+workload's level as o, v and naux grow.  Independent Gaussian factors couple every
+pair equally, so without this scaling the correlation grows like o^2 v^2 and the
+doubles dominate H-bar (second-order energy -207 Eh at o=20, v=150, naux=450,
+excitation energies near 10.7 Eh).  An optional virtual
 envelope multiplies B^Q_pq by g_p g_q with g_i = 1 and
 g_a = exp(-kappa (eps_a - eps_LUMO)); it gives the per-pair densities the
 eigenvalue decay that real molecules show.
@@ -26,7 +31,7 @@ import math
 
 import numpy as np
 
-__all__ = ["System", "make_system", "CONFIGS", "config_system", "random_r"]
+__all__ = ["System", "make_system", "default_sigma_b", "CONFIGS", "config_system", "random_r"]
 
 
 @dataclasses.dataclass
@@ -46,12 +51,16 @@ class System:
         return self.o + self.v
 
 
+def default_sigma_b(o: int, v: int, naux: int) -> float:
+    return 0.05 * (4.0 * 20.0 ** 2 * 60.0 / (o * v * v * naux)) ** 0.25
+
+
 def make_system(o: int, v: int, naux: int, seed: int, *, sigma_b: float | None = None,
                 kappa: float = 0.0, t1_sigma: float = 0.0, chunk: int = 64) -> System:
     if o < 1 or v < 1 or naux < 1:
         raise ValueError("o, v and naux must be positive")
     if sigma_b is None:
-        sigma_b = 0.05 * math.sqrt(60.0 / naux)
+        sigma_b = default_sigma_b(o, v, naux)
     rng = np.random.Generator(np.random.PCG64(seed))
     eps_o = np.sort(rng.uniform(-1.5, -0.3, o))
     eps_v = np.sort(rng.uniform(0.1, 3.0, v))
@@ -92,7 +101,7 @@ CONFIGS = {
     5: dict(o=60, v=900, naux=2700, t1_sigma=1e-3, kappa=2.0, nroots=12, tol_e=1e-6,
             tcut=1e-7, space="pno"),
     # reduced PNO workload (o=10, v=100) small enough for the oracle to converge
-    "pno_small": dict(o=10, v=100, naux=300, t1_sigma=1e-3, kappa=2.0, nroots=4,
+    "pno_small": dict(o=10, v=100, naux=300, t1_sigma=1e-3, kappa=1.0, nroots=4,
                       tol_e=1e-8, tcut=1e-7, space="pno"),
 }
 

@@ -42,7 +42,7 @@ def sec_c1():
     w, b = cis_roots(s.eps, s.B, o, k)
     out["cis"] = w.tolist()
     t0 = time.time()
-    res = davidson(so.sigma, CanonicalBasis(s.eps, o), _guess(b, o, v, k), o, v, k,
+    res = davidson(so.sigma, CanonicalBasis(s.eps, o, *so.dressed_fock_diagonals()[:2]), _guess(b, o, v, k), o, v, k,
                    tol_e=1e-11, tol_r=1e-8)
     out["davidson"] = res["omega"].tolist()
     out["davidson_iters"] = res["iters"]
@@ -67,7 +67,7 @@ def _pno_section(cfg, tcut, nstates):
     out["davidson_pno_iters"] = res["iters"]
     out["davidson_pno_seconds"] = time.time() - t0
     t0 = time.time()
-    rc = davidson(so.sigma, CanonicalBasis(s.eps, o), _guess(b, o, v, k), o, v, k,
+    rc = davidson(so.sigma, CanonicalBasis(s.eps, o, *so.dressed_fock_diagonals()[:2]), _guess(b, o, v, k), o, v, k,
                   tol_e=1e-11, tol_r=1e-8)
     out["davidson"] = rc["omega"].tolist()
     out["davidson_iters"] = rc["iters"]
@@ -89,7 +89,7 @@ def sec_c2():
     w, b = cis_roots(s.eps, s.B, o, k)
     out["cis"] = w.tolist()
     t0 = time.time()
-    res = davidson(so.sigma, CanonicalBasis(s.eps, o), _guess(b, o, v, k), o, v, k,
+    res = davidson(so.sigma, CanonicalBasis(s.eps, o, *so.dressed_fock_diagonals()[:2]), _guess(b, o, v, k), o, v, k,
                    tol_e=1e-11, tol_r=3e-8, max_sub=CONFIGS[2]["max_sub"], verbose=True)
     out["davidson"] = res["omega"].tolist()
     out["davidson_resnorm"] = res["resnorm"].tolist()
