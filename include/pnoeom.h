@@ -105,6 +105,18 @@ int pnoeom_build_sapno(pnoeom_ctx* ctx, int nstates, double tcut_pno, double tcu
  * Requires build_sapno.  Errors: ESTATE. */
 int pnoeom_pno_layout(const pnoeom_ctx* ctx, long long* offsets, long long* len);
 
+/* PNO projection and back-transformation of nvec vectors (Methods: the residual
+ * transformation into the OSV / PNO bases and the projection back to the canonical
+ * space of the PNO simulation), in the semicanonical bases built by build_sapno.
+ *   direction 0 (compress): x[q] = ( U^i^T r1[q]_i , w_p U^{ij}^T r2[q]^{ij} U^{ij} )
+ *                           reading r1 [nvec][o][v] and r2 [nvec][o][o][v][v] (device)
+ *   direction 1 (expand):   r1[q]_i = U^i x_i, r2[q]^{ij} = U^{ij} x_p U^{ij}^T / w_p and
+ *                           r2[q]^{ji} = (r2[q]^{ij})^T, writing r1, r2 (device)
+ * x is device [nvec][len] (pnoeom_pno_layout); w_p = sqrt(2) for i < j, 1 for i = j.
+ * expand(compress(r)) is the orthogonal projector P of the PNO space applied to r.
+ * Requires build_sapno.  Errors: ESTATE, EINVAL, EHIP. */
+int pnoeom_pno_transform(pnoeom_ctx* ctx, int nvec, int direction, double* r1, double* r2, double* x);
+
 /* sigma = <mu|[H-bar, R]|0> for nvec trial vectors.
  *   space = PNOEOM_CANONICAL: r1 device [nvec][o][v], r2 device [nvec][o][o][v][v];
  *           s1, s2 the same shapes (outputs).

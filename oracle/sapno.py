@@ -125,15 +125,21 @@ def truncated_basis(d, cut, fvv):
 
 
 class PNOBasis:
-    """Per-pair PNOs U^{ij} (i <= j) and per-occupied OSVs U^i, semicanonical."""
+    """Per-pair PNOs U^{ij} (i <= j) and per-occupied OSVs U^i, semicanonical.
 
-    def __init__(self, D, eps, o, tcut_pno, tcut_osv=None):
+    fvv (virtual one-particle matrix, default diag(eps_v)) defines the semicanonical
+    rotation through its symmetric part; eo (default eps_occ) the occupied energies
+    of the preconditioner.  Neither changes the projector P, only convergence.
+    """
+
+    def __init__(self, D, eps, o, tcut_pno, tcut_osv=None, fvv=None, eo=None):
         if tcut_osv is None or tcut_osv < 0:
             tcut_osv = tcut_pno / 10.0
         self.o = o
         self.v = D.shape[2]
         self.eps = eps
-        fvv = np.diag(eps[o:])
+        self.eo = eps[:o] if eo is None else eo
+        fvv = np.diag(eps[o:]) if fvv is None else 0.5 * (fvv + fvv.T)
         self.pno = {}
         self.fbar = {}
         for i in range(o):
@@ -174,7 +180,7 @@ class PNOBasis:
 
     def precondition(self, r1, r2, omega):
         """Residual -> OSV/PNO basis -> divide by semicanonical denominators -> back."""
-        eo = self.eps[:self.o]
+        eo = self.eo
         p1 = np.zeros_like(r1)
         p2 = np.zeros_like(r2)
         for i in range(self.o):

@@ -21,6 +21,7 @@ int guarded(pnoeom_ctx* ctx, F&& f) {
     return PNOEOM_OK;
   } catch (const pnoeom::Error& e) {
     ctx->c.err = e.what();
+    (void)hipGetLastError();  // do not let a reported failure resurface in the next call
     return e.code;
   } catch (const std::exception& e) {
     ctx->c.err = e.what();
@@ -128,6 +129,19 @@ int pnoeom_pno_layout(const pnoeom_ctx* cctx, long long* offsets, long long* len
     if (len) *len = c.pno.len;
     if (offsets)
       for (size_t k = 0; k < c.pno.off.size(); ++k) offsets[k] = c.pno.off[k];
+  });
+}
+
+int pnoeom_pno_transform(pnoeom_ctx* ctx, int nvec, int direction, double* r1, double* r2, double* x) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(c.pno.built, PNOEOM_ESTATE, "pno_transform before build_sapno");
+    PNO_CHECK(nvec >= 0 && (direction == 0 || direction == 1), PNOEOM_EINVAL, "pno_transform: bad arguments");
+    PNO_CHECK(r1 && r2 && x, PNOEOM_EINVAL, "pno_transform: null pointer");
+    if (direction == 0)
+      pnoeom::pno_compress(c, nvec, r1, r2, x);
+    else
+      pnoeom::pno_expand(c, nvec, x, r1, r2);
+    PNO_HIP(hipStreamSynchronize(c.stream));
   });
 }
 

@@ -83,6 +83,33 @@ struct GemmDesc {
 void gemm(const GemmDesc<double>& d, hipStream_t s);
 void gemm(const GemmDesc<float>& d, hipStream_t s);
 
+// Grouped GEMM: many independent products of different shapes in one launch.
+// Operand addresses are offsets from per-launch base pointers, so a descriptor
+// table built once can be reused for different vectors.
+struct GroupDesc {
+  int64_t M, N, K;
+  int64_t offA, lda, offB, ldb, offC, ldc;
+  int64_t tile_start;  // filled by gemm_grouped_prepare
+  int32_t tiles_m, pad;
+};
+struct GroupTable {
+  GroupDesc* d = nullptr;  // device copy
+  int n = 0;
+  int64_t total_tiles = 0;
+  bool ta = false, tb = false;
+  GroupTable() = default;
+  GroupTable(const GroupTable&) = delete;
+  GroupTable& operator=(const GroupTable&) = delete;
+  ~GroupTable() {
+    if (d) (void)hipFree(d);
+  }
+};
+// fill tile_start / tiles_m and upload (synchronous)
+void gemm_grouped_prepare(std::vector<GroupDesc>& g, bool ta, bool tb, GroupTable& t);
+// C_g = alpha op(A_g) op(B_g) + beta C_g for every group g
+void gemm_grouped(const GroupTable& t, double alpha, const double* A, const double* B, double beta, double* C,
+                  hipStream_t s);
+
 // convenience: plain row-major C = alpha op(A) op(B) + beta C with leading dims = widths
 template <typename T>
 inline void mm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, const T* A,

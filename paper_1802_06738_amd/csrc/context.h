@@ -20,21 +20,26 @@ struct PNOData {
   bool built = false;
   int nstates = 0;
   double tcut_pno = 0, tcut_osv = 0;
-  std::vector<int> npno;        // [P_o] pairs i <= j
+  std::vector<int> npno;        // [P_o] pairs i <= j, row-major
   std::vector<int> nosv;        // [o]
-  std::vector<int64_t> off;     // [o + P_o + 1] offsets in the compressed vector
+  std::vector<int64_t> off;     // [o + P_o + 1] block offsets in a compressed vector
   int64_t len = 0;
-  int nmax = 0;                 // largest n_p
-  // U^{ij} (v x n_p, column-major per pair = [k][a] rows? stored [a][k] row-major) and fbar
-  std::vector<int64_t> uoff;    // offsets of U^{ij} blocks in U (pairs then OSVs)
-  DBuf<double> U;               // concatenated [v][n] row-major blocks
-  DBuf<double> fbar;            // concatenated semicanonical energies, same order as blocks
-  std::vector<int64_t> foff;
-  // device tables for grouped kernels
-  DBuf<int64_t> d_off, d_uoff, d_foff;
-  DBuf<int> d_n, d_pi, d_pj;
-  DBuf<double> denom_base;      // per compressed element: eps_i (+ eps_j) - fbar_a (- fbar_b)
-  DBuf<double> weight;          // per compressed element: 1 or sqrt(2)
+  int nmax = 0;                 // largest block size
+  std::vector<int64_t> uoff;    // offsets of the v x n blocks in U (pairs, then OSVs)
+  std::vector<int64_t> toff;    // offsets of the per-pair v x n_p work blocks
+  DBuf<double> U;               // semicanonical PNO / OSV bases, [v][n] row-major blocks
+  DBuf<double> denom_base;      // per compressed element: F_ii (+ F_jj) - fbar_a (- fbar_b)
+  DBuf<int64_t> d_off;          // diagonal pair blocks: offsets
+  DBuf<int> d_n;                //                       sizes
+  GroupTable t_c1, t_c3, t_c2d, t_c2o, t_e1, t_e3, t_e2d, t_e2o;  // compress / expand
+  DBuf<double> Tw, r1, r2, s1, s2;
+  void reset() {
+    built = false;
+    npno.clear(); nosv.clear(); off.clear(); uoff.clear(); toff.clear();
+    len = 0; nmax = 0;
+    U.release(); denom_base.release(); d_off.release(); d_n.release();
+    Tw.release(); r1.release(); r2.release(); s1.release(); s2.release();
+  }
 };
 
 struct Context {

@@ -433,8 +433,8 @@ void cis_roots(Context& c, int n, double* omega, double* vec) {
   PNO_HIP(hipMemcpyAsync(dg, gh.data(), gh.size() * sizeof(double), hipMemcpyHostToDevice, s));
   pnoeom_davidson_opts opt;
   pnoeom_davidson_defaults(&opt);
-  opt.tol_e = 1e-12;
-  opt.tol_r = 1e-9;
+  opt.tol_e = 1e-13;
+  opt.tol_r = 1e-11;
   opt.max_sub = std::max(40, 4 * n + 8);
   opt.max_iter = 300;
   opt.verbose = 0;

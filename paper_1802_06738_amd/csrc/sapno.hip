@@ -1,21 +1,587 @@
-// State-averaged PNO machinery (placeholder until the grouped kernels land).
+// State-averaged PNOs and the PNO-projected Davidson space (Methods: CIS(D) doubles,
+// state-specific pair densities, their state average, PNO truncation, OSVs from the
+// diagonal pairs, semicanonical bases; the residual projection / back-transform of
+// the PNO simulation).
+//
+// Densities: for each averaged CIS root k the doubles B_(k) = K_(k) / (w_k + e_i + e_j
+// - e_a - e_b) come from the DF factors (K is the sigma-doubles of R1 = b_k at T = 0,
+// i.e. the (ai|bj) response to the one-index transformation by b_k); the pair
+// densities D^{ij} += 2/(1+d_ij)/N (B Bt^T + B^T Bt), Bt = 2B - B^T, are batched MFMA
+// GEMMs over all pairs.  Per-pair eigenproblems use a batched cyclic parallel Jacobi
+// method (one workgroup per matrix, Brent-Luk round-robin ordering), which keeps
+// small occupation numbers to high relative accuracy.  Compressed vectors hold the
+// singles blocks U^i^T r^i, then the pair blocks w_p U^p^T R^{ij} U^p for i <= j
+// (w_p = sqrt 2 for i < j, 1 for i = j), so plain dot products are the full-array
+// Frobenius inner product.
+#include <algorithm>
+#include <cmath>
+
 #include "context.h"
 
 namespace pnoeom {
+namespace {
 
-void build_sapno(Context&, int, double, double) {
-  throw Error(PNOEOM_EINVAL, "SA-PNO build is not available in this build");
+constexpr double kClamp = 1e-4;
+
+__device__ __forceinline__ double clampd(double d) {
+  if (fabs(d) < kClamp) return d >= 0.0 ? kClamp : -kClamp;
+  return d;
 }
-void pno_compress(Context&, int, const double*, const double*, double*) {
-  throw Error(PNOEOM_ESTATE, "PNO compress before build_sapno");
+
+unsigned gsz(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
 }
-void pno_expand(Context&, int, const double*, double*, double*) {
-  throw Error(PNOEOM_ESTATE, "PNO expand before build_sapno");
+
+void gm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+        int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc,
+        int64_t sC, int64_t batch) {
+  GemmDesc<double> d;
+  d.ta = ta; d.tb = tb; d.M = M; d.N = N; d.K = K; d.alpha = alpha; d.beta = beta;
+  d.A = A; d.lda = lda; d.sA = sA; d.B = B; d.ldb = ldb; d.sB = sB; d.C = C; d.ldc = ldc; d.sC = sC;
+  d.batch = batch;
+  gemm(d, s);
 }
-void sigma_pno(Context&, int, const double*, double*, int) {
-  throw Error(PNOEOM_ESTATE, "PNO sigma before build_sapno");
+
+void perm(hipStream_t s, const double* in, int64_t a, int64_t b, int64_t c, int64_t d, int p0, int p1, int p2,
+          int p3, double* out, double alpha = 1.0, double beta = 0.0) {
+  const int64_t dims[4] = {a, b, c, d};
+  const int pp[4] = {p0, p1, p2, p3};
+  permute_c(s, dims, pp, alpha, in, beta, out);
 }
-void precond_pno(Context&, double*, double) { throw Error(PNOEOM_ESTATE, "PNO preconditioner before build_sapno"); }
-void project_pno(Context&, double*) { throw Error(PNOEOM_ESTATE, "PNO projector before build_sapno"); }
+
+// t[i][j][a][b] = K / clamp(w + e_i + e_j - e_a - e_b)
+__global__ void cisd_div_kernel(int o, int v, const double* __restrict__ eps, double w, const double* __restrict__ K,
+                                double* __restrict__ t) {
+  const int64_t n = (int64_t)o * o * v * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    const int b = (int)(r % v); r /= v;
+    const int a = (int)(r % v); r /= v;
+    const int j = (int)(r % o); r /= o;
+    const int i = (int)r;
+    t[e] = K[e] / clampd(w + eps[i] + eps[j] - eps[o + a] - eps[o + b]);
+  }
+}
+
+// Dp[p] = scale_p * D[i_p][j_p] for the pairs i <= j
+__global__ void gather_pairs_kernel(int o, int v, int npair, const int* __restrict__ pi, const int* __restrict__ pj,
+                                    double inv_n, const double* __restrict__ D, double* __restrict__ Dp) {
+  const int64_t vv = (int64_t)v * v;
+  const int64_t n = (int64_t)npair * vv;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(e / vv);
+    const int64_t r = e % vv;
+    const int i = pi[p], j = pj[p];
+    const double sc = (i == j ? 1.0 : 2.0) * inv_n;
+    Dp[e] = sc * D[((int64_t)i * o + j) * vv + r];
+  }
+}
+
+// Batched symmetric eigensolver: cyclic parallel Jacobi, one 256-thread workgroup per
+// matrix.  A[m] (n_m x n_m, leading dimension ld, stride ld*ld) is overwritten; on exit
+// eval[m*ld + k] holds eigenvalue k and Vt[m] row k the unit eigenvector k.
+__global__ __launch_bounds__(256) void jacobi_kernel(int ld, const int* __restrict__ nsz, double* __restrict__ Aall,
+                                                     double* __restrict__ Vtall, double* __restrict__ evall,
+                                                     int max_sweeps) {
+  const int m = blockIdx.x;
+  const int n = nsz[m];
+  double* A = Aall + (int64_t)m * ld * ld;
+  double* Vt = Vtall + (int64_t)m * ld * ld;
+  double* ev = evall + (int64_t)m * ld;
+  const int tid = threadIdx.x;
+  __shared__ double cs[1024], sn[1024];
+  __shared__ int pp[1024], qq[1024];
+  __shared__ double red[256];
+  __shared__ int done;
+  if (n <= 0) return;
+  for (int64_t e = tid; e < (int64_t)n * n; e += 256) Vt[(e / n) * ld + (e % n)] = (e / n == e % n) ? 1.0 : 0.0;
+  const int np = (n + 1) & ~1;  // players, padded to even
+  const int half = np / 2;
+  __syncthreads();
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // convergence test: off-diagonal Frobenius norm vs the whole matrix
+    double off = 0.0, all = 0.0;
+    for (int64_t e = tid; e < (int64_t)n * n; e += 256) {
+      const int i = (int)(e / n), j = (int)(e % n);
+      const double x = A[(int64_t)i * ld + j];
+      all += x * x;
+      if (i != j) off += x * x;
+    }
+    red[tid] = off;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const double offs = red[0];
+    __syncthreads();
+    red[tid] = all;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) done = (offs <= 1e-30 * red[0] || offs == 0.0) ? 1 : 0;
+    __syncthreads();
+    if (done) break;
+    for (int round = 0; round < np - 1; ++round) {
+      for (int k = tid; k < half; k += 256) {
+        int p, q;
+        if (k == 0) { p = np - 1; q = round; }
+        else { p = (round + k) % (np - 1); q = (round - k + (np - 1)) % (np - 1); }
+        if (p > q) { const int t = p; p = q; q = t; }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[(int64_t)p * ld + q];
+          if (apq != 0.0) {
+            const double app = A[(int64_t)p * ld + p], aqq = A[(int64_t)q * ld + q];
+            const double th = (aqq - app) / (2.0 * apq);
+            const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+          }
+        }
+        pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s;
+      }
+      __syncthreads();
+      // rows: A <- J^T A ; Vt <- J^T Vt
+      for (int64_t e = tid; e < (int64_t)half * n; e += 256) {
+        const int k = (int)(e / n), j = (int)(e % n);
+        const int p = pp[k], q = qq[k];
+        if (q >= n || sn[k] == 0.0) continue;
+        const double c = cs[k], s = sn[k];
+        double* ap = A + (int64_t)p * ld;
+        double* aq = A + (int64_t)q * ld;
+        const double x = ap[j], y = aq[j];
+        ap[j] = c * x - s * y;
+        aq[j] = s * x + c * y;
+        double* vp = Vt + (int64_t)p * ld;
+        double* vq = Vt + (int64_t)q * ld;
+        const double vx = vp[j], vy = vq[j];
+        vp[j] = c * vx - s * vy;
+        vq[j] = s * vx + c * vy;
+      }
+      __syncthreads();
+      // columns: A <- A J
+      for (int64_t e = tid; e < (int64_t)half * n; e += 256) {
+        const int k = (int)(e % half), i = (int)(e / half);
+        const int p = pp[k], q = qq[k];
+        if (q >= n || sn[k] == 0.0) continue;
+        const double c = cs[k], s = sn[k];
+        double* ai = A + (int64_t)i * ld;
+        const double x = ai[p], y = ai[q];
+        ai[p] = c * x - s * y;
+        ai[q] = s * x + c * y;
+      }
+      __syncthreads();
+    }
+  }
+  for (int k = tid; k < n; k += 256) ev[k] = A[(int64_t)k * ld + k];
+}
+
+// U0[a][c] = Vt[m][idx[c]][a] for the kept columns of each matrix (rows of Vt)
+__global__ void gather_kept_kernel(int ld, int v, int nsel, const int* __restrict__ mat, const int* __restrict__ row,
+                                   const int64_t* __restrict__ off, const int* __restrict__ col, const int* __restrict__ ncol,
+                                   const double* __restrict__ Vt, double* __restrict__ U) {
+  const int64_t total = (int64_t)nsel * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(e / v), a = (int)(e % v);
+    U[off[t] + (int64_t)a * ncol[t] + col[t]] = Vt[((int64_t)mat[t] * ld + row[t]) * ld + a];
+  }
+}
+
+// r2[j][i][b][a] = r2[i][j][a][b] for i < j
+__global__ void mirror_pairs_kernel(int o, int v, double* __restrict__ r2) {
+  const int64_t vv = (int64_t)v * v, n = (int64_t)o * o * vv;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pr = e / vv, r = e % vv;
+    const int i = (int)(pr / o), j = (int)(pr % o);
+    if (i >= j) continue;
+    const int a = (int)(r / v), b = (int)(r % v);
+    r2[((int64_t)j * o + i) * vv + (int64_t)b * v + a] = r2[e];
+  }
+}
+
+// x[e] /= clamp(theta + base[e])
+__global__ void precond_pno_kernel(int64_t n, double theta, const double* __restrict__ base, double* __restrict__ x) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    x[e] /= clampd(theta + base[e]);
+}
+
+// symmetrise the diagonal pair blocks of a compressed vector
+__global__ void sym_diag_blocks_kernel(int ndiag, const int64_t* __restrict__ off, const int* __restrict__ nd,
+                                       double* __restrict__ x) {
+  const int b = blockIdx.x;
+  if (b >= ndiag) return;
+  const int n = nd[b];
+  double* X = x + off[b];
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (i < j) {
+      const double m = 0.5 * (X[(int64_t)i * n + j] + X[(int64_t)j * n + i]);
+      X[(int64_t)i * n + j] = m;
+      X[(int64_t)j * n + i] = m;
+    }
+  }
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- build
+void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
+  PNO_CHECK(c.have_df, PNOEOM_ESTATE, "build_sapno before build_df");
+  PNO_CHECK(nstates >= 1 && nstates <= c.ov(), PNOEOM_EINVAL, "build_sapno: bad nstates");
+  PNO_CHECK(c.v <= 2048, PNOEOM_EINVAL, "build_sapno: v > 2048 exceeds the Jacobi kernel's pair table");
+  hipStream_t s = c.stream;
+  PNOData& P = c.pno;
+  P.reset();
+  const int o = c.o, v = c.v, naux = c.naux, nmo = c.nmo;
+  const int64_t n2 = (int64_t)nmo * nmo, ov = c.ov(), oovv = c.oovv(), vv = (int64_t)v * v;
+  const int npair = o * (o + 1) / 2;
+  P.nstates = nstates;
+  P.tcut_pno = tcut_pno;
+  P.tcut_osv = tcut_osv;
+
+  // 1. CIS roots
+  std::vector<double> w(nstates);
+  DBuf<double> bvec;
+  bvec.alloc((int64_t)nstates * ov);
+  cis_roots(c, nstates, w.data(), bvec);
+
+  // 2. averaged pair densities D[i][j] (all pairs, unscaled sum over states)
+  DBuf<double> D, Bk, Bt2, Kt, Bp, XT, BvoT0;
+  D.alloc(oovv);
+  Bk.alloc(oovv);
+  Bt2.alloc(oovv);
+  Kt.alloc(oovv);
+  Bp.alloc((int64_t)naux * v * o);
+  XT.alloc(ov * naux);
+  BvoT0.alloc(ov * naux);
+  fill(s, oovv, 0.0, D);
+  {
+    Perm4 p;  // BvoT0[(j,b)][Q] = B[Q][o+b][j]
+    p.d[0] = o; p.d[1] = v; p.d[2] = naux; p.d[3] = 1;
+    p.is[0] = 1; p.is[1] = nmo; p.is[2] = n2; p.is[3] = 0;
+    p.os[0] = (int64_t)v * naux; p.os[1] = naux; p.os[2] = 1; p.os[3] = 0;
+    permute4(s, p, 1.0, c.B + (int64_t)o * nmo, 0.0, BvoT0);
+  }
+  for (int k = 0; k < nstates; ++k) {
+    const double* b = bvec + (int64_t)k * ov;
+    // B'_vo[Q][a][i] = -sum_l b_l^a B[Q][l][i] + sum_c B[Q][o+a][o+c] b_i^c
+    gm(s, true, false, v, o, o, -1.0, b, v, 0, c.B, nmo, n2, 0.0, Bp, o, (int64_t)v * o, naux);
+    gm(s, false, true, v, o, v, 1.0, c.B + (int64_t)o * nmo + o, nmo, n2, b, v, 0, 1.0, Bp, o, (int64_t)v * o, naux);
+    perm(s, Bp, naux, v, o, 1, 2, 1, 0, 3, XT);  // XT[(i,a)][Q]
+    // K[(i,a),(j,b)] = sum_Q B'_ai B_bj + B_ai B'_bj  ->  [i][j][a][b]
+    gm(s, false, true, ov, ov, naux, 1.0, XT, naux, 0, BvoT0, naux, 0, 0.0, Bt2, ov, 0, 1);
+    gm(s, false, true, ov, ov, naux, 1.0, BvoT0, naux, 0, XT, naux, 0, 1.0, Bt2, ov, 0, 1);
+    perm(s, Bt2, o, v, o, v, 0, 2, 1, 3, Kt);
+    hipLaunchKernelGGL(cisd_div_kernel, dim3(gsz(oovv)), dim3(256), 0, s, o, v, (const double*)c.eps, w[k],
+                       (const double*)Kt, (double*)Bk);
+    PNO_HIP(hipGetLastError());
+    // Bt = 2B - B^T per pair block
+    perm(s, Bk, o, o, v, v, 0, 1, 3, 2, Bt2, -1.0, 0.0);
+    axpby(s, oovv, 2.0, Bk, 1.0, Bt2);
+    // D += B Bt^T + B^T Bt   (all o^2 pairs, batched)
+    gm(s, false, true, v, v, v, 1.0, Bk, v, vv, Bt2, v, vv, 1.0, D, v, vv, (int64_t)o * o);
+    gm(s, true, false, v, v, v, 1.0, Bk, v, vv, Bt2, v, vv, 1.0, D, v, vv, (int64_t)o * o);
+  }
+  Bk.release(); Bt2.release(); Kt.release(); Bp.release(); XT.release(); BvoT0.release();
+
+  // 3. pair tables and per-pair eigenproblems
+  std::vector<int> pi(npair), pj(npair);
+  {
+    int p = 0;
+    for (int i = 0; i < o; ++i)
+      for (int j = i; j < o; ++j) { pi[p] = i; pj[p] = j; ++p; }
+  }
+  DBuf<int> dpi, dpj, dn;
+  dpi.alloc(npair); dpj.alloc(npair); dn.alloc(std::max(npair, o));
+  PNO_HIP(hipMemcpyAsync(dpi, pi.data(), npair * sizeof(int), hipMemcpyHostToDevice, s));
+  PNO_HIP(hipMemcpyAsync(dpj, pj.data(), npair * sizeof(int), hipMemcpyHostToDevice, s));
+  DBuf<double> Dp, Vt, ev;
+  Dp.alloc((int64_t)npair * vv);
+  Vt.alloc((int64_t)npair * vv);
+  ev.alloc((int64_t)npair * v);
+  hipLaunchKernelGGL(gather_pairs_kernel, dim3(gsz((int64_t)npair * vv)), dim3(256), 0, s, o, v, npair,
+                     (const int*)dpi, (const int*)dpj, 1.0 / nstates, (const double*)D, (double*)Dp);
+  PNO_HIP(hipGetLastError());
+  D.release();
+  {
+    std::vector<int> nv(npair, v);
+    PNO_HIP(hipMemcpyAsync(dn, nv.data(), npair * sizeof(int), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(256), 0, s, v, (const int*)dn, (double*)Dp, (double*)Vt,
+                       (double*)ev, 60);
+    PNO_HIP(hipGetLastError());
+  }
+  std::vector<double> evh((size_t)npair * v);
+  PNO_HIP(hipMemcpyAsync(evh.data(), ev, evh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  PNO_HIP(hipStreamSynchronize(s));
+  Dp.release();
+
+  // 4. kept vectors: pairs with |n| >= tcut_pno, OSVs (diagonal pairs) with |n| >= tcut_osv.
+  //    Blocks: 0..npair-1 pairs, npair..npair+o-1 OSVs.
+  const int nblk = npair + o;
+  std::vector<int> bn(nblk), bmat(nblk);
+  std::vector<int> smat, srow, scol, sncol;
+  std::vector<int64_t> soff;
+  std::vector<int64_t> uoff(nblk + 1, 0);
+  for (int b = 0; b < nblk; ++b) {
+    const int mtx = b < npair ? b : [&] {
+      const int i = b - npair;
+      return i * o - i * (i - 1) / 2;  // diagonal pair (i, i)
+    }();
+    const double cut = b < npair ? tcut_pno : tcut_osv;
+    std::vector<int> rows;
+    for (int k = 0; k < v; ++k)
+      if (std::fabs(evh[(size_t)mtx * v + k]) >= cut) rows.push_back(k);
+    bn[b] = (int)rows.size();
+    bmat[b] = mtx;
+    uoff[b + 1] = uoff[b] + (int64_t)v * bn[b];
+    for (int cidx = 0; cidx < bn[b]; ++cidx) {
+      smat.push_back(mtx);
+      srow.push_back(rows[cidx]);
+      soff.push_back(uoff[b]);
+      scol.push_back(cidx);
+      sncol.push_back(bn[b]);
+    }
+  }
+  const int64_t utot = uoff[nblk];
+  int nmax = 1;
+  for (int b = 0; b < nblk; ++b) nmax = std::max(nmax, bn[b]);
+  DBuf<double> U0;
+  U0.alloc(std::max<int64_t>(utot, 1));
+  if (!smat.empty()) {
+    const int nsel = (int)smat.size();
+    DBuf<int> dm, dr, dc, dnc;
+    DBuf<int64_t> dof;
+    dm.alloc(nsel); dr.alloc(nsel); dc.alloc(nsel); dnc.alloc(nsel); dof.alloc(nsel);
+    PNO_HIP(hipMemcpy(dm, smat.data(), nsel * sizeof(int), hipMemcpyHostToDevice));
+    PNO_HIP(hipMemcpy(dr, srow.data(), nsel * sizeof(int), hipMemcpyHostToDevice));
+    PNO_HIP(hipMemcpy(dc, scol.data(), nsel * sizeof(int), hipMemcpyHostToDevice));
+    PNO_HIP(hipMemcpy(dnc, sncol.data(), nsel * sizeof(int), hipMemcpyHostToDevice));
+    PNO_HIP(hipMemcpy(dof, soff.data(), nsel * sizeof(int64_t), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(gather_kept_kernel, dim3(gsz((int64_t)nsel * v)), dim3(256), 0, s, v, v, nsel,
+                       (const int*)dm, (const int*)dr, (const int64_t*)dof, (const int*)dc, (const int*)dnc,
+                       (const double*)Vt, (double*)U0);
+    PNO_HIP(hipGetLastError());
+    PNO_HIP(hipStreamSynchronize(s));
+  }
+  Vt.release();
+  ev.release();
+
+  // 5. semicanonical rotation: eigenvectors of U0^T Fs U0, Fs = symmetric part of the
+  //    one-particle virtual block of H-bar
+  DBuf<double> Fs, Tb, Fb, Wt, fev;
+  Fs.alloc(vv);
+  perm(s, c.Fvv, v, v, 1, 1, 1, 0, 2, 3, Fs, 0.5, 0.0);
+  axpby(s, vv, 0.5, c.Fvv, 1.0, Fs);
+  Tb.alloc(std::max<int64_t>(utot, 1));
+  Fb.alloc((int64_t)nblk * nmax * nmax);
+  Wt.alloc((int64_t)nblk * nmax * nmax);
+  fev.alloc((int64_t)nblk * nmax);
+  fill(s, (int64_t)nblk * nmax * nmax, 0.0, Fb);
+  {
+    std::vector<GroupDesc> g1, g2, g3;
+    for (int b = 0; b < nblk; ++b) {
+      const int n = bn[b];
+      if (n == 0) continue;
+      GroupDesc d{};
+      // Tb_b = Fs U0_b  (v x n)
+      d.M = v; d.N = n; d.K = v; d.offA = 0; d.lda = v; d.offB = uoff[b]; d.ldb = n; d.offC = uoff[b]; d.ldc = n;
+      g1.push_back(d);
+      // Fb_b = U0_b^T Tb_b  (n x n, padded ld nmax)
+      d.M = n; d.N = n; d.K = v; d.offA = uoff[b]; d.lda = n; d.offB = uoff[b]; d.ldb = n;
+      d.offC = (int64_t)b * nmax * nmax; d.ldc = nmax;
+      g2.push_back(d);
+      // U_b = U0_b Wt_b^T  (v x n)
+      d.M = v; d.N = n; d.K = n; d.offA = uoff[b]; d.lda = n; d.offB = (int64_t)b * nmax * nmax; d.ldb = nmax;
+      d.offC = uoff[b]; d.ldc = n;
+      g3.push_back(d);
+    }
+    GroupTable t1, t2, t3;
+    gemm_grouped_prepare(g1, false, false, t1);
+    gemm_grouped_prepare(g2, true, false, t2);
+    gemm_grouped_prepare(g3, false, true, t3);
+    gemm_grouped(t1, 1.0, Fs, U0, 0.0, Tb, s);
+    gemm_grouped(t2, 1.0, U0, Tb, 0.0, Fb, s);
+    DBuf<int> dnb;
+    dnb.alloc(nblk);
+    PNO_HIP(hipMemcpyAsync(dnb, bn.data(), nblk * sizeof(int), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(jacobi_kernel, dim3(nblk), dim3(256), 0, s, nmax, (const int*)dnb, (double*)Fb, (double*)Wt,
+                       (double*)fev, 60);
+    PNO_HIP(hipGetLastError());
+    P.U.alloc(std::max<int64_t>(utot, 1));
+    gemm_grouped(t3, 1.0, U0, Wt, 0.0, P.U, s);
+    PNO_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<double> fevh((size_t)nblk * nmax);
+  PNO_HIP(hipMemcpy(fevh.data(), fev, fevh.size() * sizeof(double), hipMemcpyDeviceToHost));
+
+  // 6. layout of compressed vectors: singles of i = 0..o-1, then pairs p
+  P.npno.assign(bn.begin(), bn.begin() + npair);
+  P.nosv.assign(bn.begin() + npair, bn.end());
+  P.off.assign(o + npair + 1, 0);
+  for (int i = 0; i < o; ++i) P.off[i + 1] = P.off[i] + P.nosv[i];
+  for (int p = 0; p < npair; ++p) P.off[o + p + 1] = P.off[o + p] + (int64_t)P.npno[p] * P.npno[p];
+  P.len = P.off[o + npair];
+  P.uoff = uoff;
+  P.nmax = nmax;
+  PNO_CHECK(P.len > 0, PNOEOM_EINVAL, "build_sapno: every PNO and OSV was truncated");
+  // preconditioner base: F_ii (+ F_jj) - fbar_a (- fbar_b); weights
+  std::vector<double> Fooh((size_t)o * o);
+  PNO_HIP(hipMemcpy(Fooh.data(), c.Foo, Fooh.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> base(P.len);
+  for (int i = 0; i < o; ++i) {
+    const int b = npair + i;
+    for (int a = 0; a < P.nosv[i]; ++a)
+      base[P.off[i] + a] = Fooh[(size_t)i * o + i] - fevh[(size_t)b * nmax + a];
+  }
+  for (int p = 0; p < npair; ++p) {
+    const int n = P.npno[p];
+    const double e = Fooh[(size_t)pi[p] * o + pi[p]] + Fooh[(size_t)pj[p] * o + pj[p]];
+    for (int a = 0; a < n; ++a)
+      for (int b2 = 0; b2 < n; ++b2)
+        base[P.off[o + p] + (int64_t)a * n + b2] = e - fevh[(size_t)p * nmax + a] - fevh[(size_t)p * nmax + b2];
+  }
+  P.denom_base.alloc(P.len);
+  PNO_HIP(hipMemcpy(P.denom_base, base.data(), P.len * sizeof(double), hipMemcpyHostToDevice));
+  // diagonal-pair block table for the singlet symmetrisation
+  {
+    std::vector<int64_t> doff;
+    std::vector<int> dsz;
+    for (int p = 0; p < npair; ++p)
+      if (pi[p] == pj[p]) { doff.push_back(P.off[o + p]); dsz.push_back(P.npno[p]); }
+    P.d_off.alloc(doff.size());
+    P.d_n.alloc(dsz.size());
+    PNO_HIP(hipMemcpy(P.d_off, doff.data(), doff.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    PNO_HIP(hipMemcpy(P.d_n, dsz.data(), dsz.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
+  // grouped-GEMM tables for compress / expand (one vector; bases shifted per vector)
+  {
+    std::vector<GroupDesc> cs1, cs2d, cs2o, cs3, ex1, ex2d, ex2o, ex3;
+    int64_t toff = 0;
+    P.toff.assign(npair + 1, 0);
+    for (int p = 0; p < npair; ++p) {
+      P.toff[p + 1] = P.toff[p] + (int64_t)v * P.npno[p];
+    }
+    (void)toff;
+    for (int i = 0; i < o; ++i) {
+      const int n = P.nosv[i];
+      if (n == 0) continue;
+      const int b = npair + i;
+      GroupDesc d{};
+      // x_i (1 x n) = r1_i (1 x v) U^i (v x n)
+      d.M = 1; d.N = n; d.K = v; d.offA = (int64_t)i * v; d.lda = v; d.offB = uoff[b]; d.ldb = n;
+      d.offC = P.off[i]; d.ldc = n;
+      cs1.push_back(d);
+      // r1_i (1 x v) = x_i (1 x n) U^i^T
+      d.M = 1; d.N = v; d.K = n; d.offA = P.off[i]; d.lda = n; d.offB = uoff[b]; d.ldb = n; d.offC = (int64_t)i * v;
+      d.ldc = v;
+      ex1.push_back(d);
+    }
+    for (int p = 0; p < npair; ++p) {
+      const int n = P.npno[p];
+      if (n == 0) continue;
+      const int64_t rof = ((int64_t)pi[p] * o + pj[p]) * vv;
+      GroupDesc d{};
+      // T_p = R^{ij} U_p   (v x n)
+      d.M = v; d.N = n; d.K = v; d.offA = rof; d.lda = v; d.offB = uoff[p]; d.ldb = n; d.offC = P.toff[p]; d.ldc = n;
+      cs3.push_back(d);
+      // x_p = w U_p^T T_p  (n x n)
+      d.M = n; d.N = n; d.K = v; d.offA = uoff[p]; d.lda = n; d.offB = P.toff[p]; d.ldb = n; d.offC = P.off[o + p];
+      d.ldc = n;
+      (pi[p] == pj[p] ? cs2d : cs2o).push_back(d);
+      // T_p = U_p X_p  (v x n)
+      d.M = v; d.N = n; d.K = n; d.offA = uoff[p]; d.lda = n; d.offB = P.off[o + p]; d.ldb = n; d.offC = P.toff[p];
+      d.ldc = n;
+      ex3.push_back(d);
+      // R^{ij} = T_p U_p^T / w  (v x v)
+      d.M = v; d.N = v; d.K = n; d.offA = P.toff[p]; d.lda = n; d.offB = uoff[p]; d.ldb = n; d.offC = rof; d.ldc = v;
+      (pi[p] == pj[p] ? ex2d : ex2o).push_back(d);
+    }
+    gemm_grouped_prepare(cs1, false, false, P.t_c1);
+    gemm_grouped_prepare(cs3, false, false, P.t_c3);
+    gemm_grouped_prepare(cs2d, true, false, P.t_c2d);
+    gemm_grouped_prepare(cs2o, true, false, P.t_c2o);
+    gemm_grouped_prepare(ex1, false, true, P.t_e1);
+    gemm_grouped_prepare(ex3, false, false, P.t_e3);
+    gemm_grouped_prepare(ex2d, false, true, P.t_e2d);
+    gemm_grouped_prepare(ex2o, false, true, P.t_e2o);
+    P.Tw.alloc(std::max<int64_t>(P.toff[npair], 1));
+  }
+  P.built = true;
+}
+
+// ----------------------------------------------------------------------------- transforms
+void pno_compress(Context& c, int nvec, const double* r1, const double* r2, double* x) {
+  PNOData& P = c.pno;
+  PNO_CHECK(P.built, PNOEOM_ESTATE, "PNO compress before build_sapno");
+  hipStream_t s = c.stream;
+  const double sq2 = std::sqrt(2.0);
+  for (int q = 0; q < nvec; ++q) {
+    const double* a1 = r1 + (int64_t)q * c.ov();
+    const double* a2 = r2 + (int64_t)q * c.oovv();
+    double* y = x + (int64_t)q * P.len;
+    gemm_grouped(P.t_c1, 1.0, a1, P.U, 0.0, y, s);
+    gemm_grouped(P.t_c3, 1.0, a2, P.U, 0.0, P.Tw, s);
+    gemm_grouped(P.t_c2d, 1.0, P.U, P.Tw, 0.0, y, s);
+    gemm_grouped(P.t_c2o, sq2, P.U, P.Tw, 0.0, y, s);
+  }
+}
+
+void pno_expand(Context& c, int nvec, const double* x, double* r1, double* r2) {
+  PNOData& P = c.pno;
+  PNO_CHECK(P.built, PNOEOM_ESTATE, "PNO expand before build_sapno");
+  hipStream_t s = c.stream;
+  const double isq2 = 1.0 / std::sqrt(2.0);
+  for (int q = 0; q < nvec; ++q) {
+    double* b1 = r1 + (int64_t)q * c.ov();
+    double* b2 = r2 + (int64_t)q * c.oovv();
+    const double* y = x + (int64_t)q * P.len;
+    fill(s, c.ov(), 0.0, b1);
+    fill(s, c.oovv(), 0.0, b2);
+    gemm_grouped(P.t_e1, 1.0, y, P.U, 0.0, b1, s);
+    gemm_grouped(P.t_e3, 1.0, P.U, y, 0.0, P.Tw, s);
+    gemm_grouped(P.t_e2d, 1.0, P.Tw, P.U, 0.0, b2, s);
+    gemm_grouped(P.t_e2o, isq2, P.Tw, P.U, 0.0, b2, s);
+    hipLaunchKernelGGL(mirror_pairs_kernel, dim3(gsz(c.oovv())), dim3(256), 0, s, c.o, c.v, b2);
+    PNO_HIP(hipGetLastError());
+  }
+}
+
+void project_pno(Context& c, double* x) {
+  PNOData& P = c.pno;
+  const int nd = (int)P.d_n.n;
+  if (nd == 0) return;
+  hipLaunchKernelGGL(sym_diag_blocks_kernel, dim3(nd), dim3(256), 0, c.stream, nd, (const int64_t*)P.d_off,
+                     (const int*)P.d_n, x);
+  PNO_HIP(hipGetLastError());
+}
+
+void precond_pno(Context& c, double* x, double theta) {
+  PNOData& P = c.pno;
+  hipLaunchKernelGGL(precond_pno_kernel, dim3(gsz(P.len)), dim3(256), 0, c.stream, P.len, theta,
+                     (const double*)P.denom_base, x);
+  PNO_HIP(hipGetLastError());
+  project_pno(c, x);
+}
+
+void sigma_pno(Context& c, int nvec, const double* x, double* y, int precision) {
+  PNOData& P = c.pno;
+  PNO_CHECK(P.built, PNOEOM_ESTATE, "PNO sigma before build_sapno");
+  P.r1.alloc(c.ov());
+  P.r2.alloc(c.oovv());
+  P.s1.alloc(c.ov());
+  P.s2.alloc(c.oovv());
+  for (int q = 0; q < nvec; ++q) {
+    pno_expand(c, 1, x + (int64_t)q * P.len, P.r1, P.r2);
+    sigma_canonical(c, P.r1, P.r2, P.s1, P.s2, precision);
+    pno_compress(c, 1, P.s1, P.s2, y + (int64_t)q * P.len);
+    project_pno(c, y + (int64_t)q * P.len);
+  }
+}
 
 }  // namespace pnoeom

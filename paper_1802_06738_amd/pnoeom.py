@@ -19,7 +19,7 @@ CANONICAL, PNO = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "ESTATE", -6: "ECOMPLEX",
           -7: "EABORTED"}
 EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pnoeom_build_df", "pnoeom_cis",
-                    "pnoeom_build_sapno", "pnoeom_pno_layout", "pnoeom_apply_sigma", "pnoeom_davidson_defaults",
+                    "pnoeom_build_sapno", "pnoeom_pno_layout", "pnoeom_pno_transform", "pnoeom_apply_sigma", "pnoeom_davidson_defaults",
                     "pnoeom_davidson", "pnoeom_host_eig", "pnoeom_last_timing"]
 
 
@@ -61,6 +61,7 @@ def load_library():
     lib.pnoeom_build_sapno.argtypes = [vp, C.c_int, C.c_double, C.c_double, ip, ip]
     lib.pnoeom_pno_layout.argtypes = [vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
     lib.pnoeom_apply_sigma.argtypes = [vp, C.c_int, vp, vp, vp, vp, C.c_int, C.c_int]
+    lib.pnoeom_pno_transform.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
     lib.pnoeom_davidson_defaults.argtypes = [C.POINTER(DavidsonOpts)]
     lib.pnoeom_davidson_defaults.restype = None
     lib.pnoeom_davidson.argtypes = [vp, C.c_int, C.POINTER(DavidsonOpts), dp, dp, ip, ip]
@@ -164,6 +165,23 @@ class PnoEom:
         ln = C.c_longlong()
         self._check(self.lib.pnoeom_pno_layout(self.h, off.ctypes.data_as(C.POINTER(C.c_longlong)), C.byref(ln)))
         return off, int(ln.value)
+
+    def pno_compress(self, r1, r2):
+        import torch
+        nvec = r1.shape[0]
+        _, ln = self.pno_layout()
+        x = torch.zeros((nvec, ln), dtype=torch.float64, device=r1.device)
+        self._check(self.lib.pnoeom_pno_transform(self.h, nvec, 0, _dev(r1, (nvec, self.o, self.v), "r1"),
+                                                  _dev(r2, (nvec, self.o, self.o, self.v, self.v), "r2"), _dev(x)))
+        return x
+
+    def pno_expand(self, x):
+        import torch
+        nvec = x.shape[0]
+        r1 = torch.empty((nvec, self.o, self.v), dtype=torch.float64, device=x.device)
+        r2 = torch.empty((nvec, self.o, self.o, self.v, self.v), dtype=torch.float64, device=x.device)
+        self._check(self.lib.pnoeom_pno_transform(self.h, nvec, 1, _dev(r1), _dev(r2), _dev(x, None, "x")))
+        return r1, r2
 
     def sigma(self, r1, r2, precision=FP64):
         """Canonical sigma for r1 [nvec, o, v], r2 [nvec, o, o, v, v] (torch float64 on device)."""

@@ -1,0 +1,115 @@
+"""GPU parity of the SA-PNO path (build, projection, PNO sigma, PNO Davidson) against
+the FP64 oracle, through the C ABI.
+
+PNO and OSV counts are integer decisions taken in FP64 on both sides and must
+agree exactly.  The bases themselves may differ by rotations inside each kept
+space (and by signs), so the comparisons use the projector P = expand(compress(.)),
+which is basis independent.  P depends on the CIS vectors through the densities;
+the GPU CIS Davidson stops at a residual of 1e-11, and an error dD moves the kept
+space by about |dD| / (eigenvalue gap at the cut), so P is compared at 1e-9
+relative.  Energies: 1e-8 Eh.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synthgen import make_system, config_system, random_r, CONFIGS
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _ctx(s):
+    import torch
+    from paper_1802_06738_amd import PnoEom
+    assert torch.cuda.is_available()
+    ctx = PnoEom(s.o, s.v, s.naux)
+    ctx.build_df(torch.from_numpy(s.B).cuda(), torch.from_numpy(s.eps).cuda(), torch.from_numpy(s.t1).cuda())
+    return ctx
+
+
+def _oracle_basis(s, nst, tcut):
+    from oracle.sapno import sa_densities, PNOBasis
+    from oracle.sigma import SigmaOracle
+    so = SigmaOracle(s.eps, s.B, s.o, s.t1)
+    eo, _, fvv = so.dressed_fock_diagonals()
+    D, w, b = sa_densities(s.eps, s.B, s.o, nst)
+    return so, PNOBasis(D, s.eps, s.o, tcut, fvv=fvv, eo=eo), b
+
+
+SMALL = [(4, 24, 50, 1.0, 3, 1e-5, 11), (5, 30, 70, 1.0, 3, 1e-6, 12)]
+
+
+@pytest.mark.parametrize("o,v,naux,kappa,nst,tcut,seed", SMALL)
+def test_sapno_counts_and_projector(o, v, naux, kappa, nst, tcut, seed):
+    print(f"[sapno] o={o} v={v} tcut={tcut}", flush=True)
+    import torch
+    s = make_system(o, v, naux, seed, kappa=kappa, t1_sigma=1e-3)
+    ctx = _ctx(s)
+    npno, nosv = ctx.build_sapno(nst, tcut)
+    so, pb, _ = _oracle_basis(s, nst, tcut)
+    assert np.array_equal(npno, pb.npno()) and np.array_equal(nosv, pb.nosv())
+    assert npno.sum() < v * v * len(npno)          # truncation active
+    r1, r2 = random_r(o, v, seed + 3, nvec=2)
+    x = ctx.pno_compress(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda())
+    e1, e2 = ctx.pno_expand(x)
+    e1, e2 = e1.cpu().numpy(), e2.cpu().numpy()
+    for k in range(2):
+        p1, p2 = pb.project(r1[k], r2[k])
+        assert np.max(np.abs(e1[k] - p1)) <= 1e-9 * np.max(np.abs(p1))
+        assert np.max(np.abs(e2[k] - p2)) <= 1e-9 * np.max(np.abs(p2))
+    # compressed inner product = full-array Frobenius product of the projections
+    xa = x.cpu().numpy()
+    p1a, p2a = pb.project(r1[0], r2[0])
+    p1b, p2b = pb.project(r1[1], r2[1])
+    assert abs(np.dot(xa[0], xa[1]) - (np.sum(p1a * p1b) + np.sum(p2a * p2b))) < 1e-10 * abs(np.dot(xa[0], xa[0]))
+    # P sigma in the PNO space
+    y = ctx.sigma_pno(x)
+    f1, f2 = ctx.pno_expand(y)
+    f1, f2 = f1.cpu().numpy(), f2.cpu().numpy()
+    q1, q2 = so.sigma(p1a, p2a)
+    q1, q2 = pb.project(q1, q2)
+    assert np.max(np.abs(f1[0] - q1)) <= 1e-9 * np.max(np.abs(q1))
+    assert np.max(np.abs(f2[0] - q2)) <= 1e-9 * np.max(np.abs(q2))
+
+
+def test_pno_davidson_matches_oracle_dense():
+    print("[pno davidson dense]", flush=True)
+    from oracle.davidson import dense_eom
+    o, v, naux, nst, tcut = 3, 14, 40, 3, 1e-5
+    s = make_system(o, v, naux, 21, kappa=1.0, t1_sigma=1e-3)
+    so, pb, _ = _oracle_basis(s, nst, tcut)
+    assert pb.npno().sum() < v * v * len(pb.npno())
+    wd, _ = dense_eom(so.sigma, o, v, basis=pb)
+    ctx = _ctx(s)
+    ctx.build_sapno(nst, tcut)
+    r = ctx.davidson(3, space=1, tol_e=1e-11, tol_r=1e-8, max_sub=40)
+    assert np.max(np.abs(r["omega"] - wd.real[:3])) <= 1e-8
+
+
+def test_pno_tcut0_equals_canonical():
+    print("[pno tcut0]", flush=True)
+    s = config_system(1)
+    ctx = _ctx(s)
+    npno, nosv = ctx.build_sapno(3, 0.0)
+    assert np.all(npno == s.v) and np.all(nosv == s.v)
+    rp = ctx.davidson(3, space=1, tol_e=1e-10, tol_r=1e-7)
+    rc = ctx.davidson(3, space=0, tol_e=1e-10, tol_r=1e-7)
+    assert np.max(np.abs(rp["omega"] - rc["omega"])) <= 1e-9
+
+
+def test_pno_small_workload_vs_golden():
+    path = os.path.join(GOLD, "pno_small.json")
+    if not os.path.exists(path):
+        pytest.skip("pno_small golden values not generated")
+    print("[pno_small]", flush=True)
+    g = json.load(open(path))
+    s = config_system("pno_small")
+    c = CONFIGS["pno_small"]
+    ctx = _ctx(s)
+    npno, nosv = ctx.build_sapno(g["nstates_avg"], g["tcut_pno"])
+    assert np.array_equal(npno, np.array(g["npno"])) and np.array_equal(nosv, np.array(g["nosv"]))
+    r = ctx.davidson(c["nroots"], space=1, tol_e=1e-10, tol_r=1e-6)
+    assert np.max(np.abs(r["omega"] - np.array(g["davidson_pno"]))) <= 1e-8
