@@ -167,9 +167,14 @@ int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opt
 int pnoeom_host_eig(int n, const double* a, double* wr, double* wi, double* vr);
 
 /* Time spent in the last pnoeom_davidson / pnoeom_apply_sigma call, measured with
- * HIP events on the context's stream: total milliseconds, milliseconds inside
- * the ladder contraction, and the number of ladder launches. */
-int pnoeom_last_timing(const pnoeom_ctx* ctx, double* total_ms, double* ladder_ms, int* ladder_launches);
+ * HIP events on the context's stream: total milliseconds; milliseconds inside the
+ * particle-ladder contractions and the number of ladder GEMM launches (two per
+ * sigma block: the + and - halves of the packed form); the algorithmic flop count
+ * of those contractions
+ * (2 * nvec * P_o * (v+^2 + v-^2), P_o = o(o+1)/2, v+- = v(v+-1)/2).  Any output
+ * pointer may be NULL. */
+int pnoeom_last_timing(const pnoeom_ctx* ctx, double* total_ms, double* ladder_ms, int* ladder_launches,
+                       double* ladder_flops);
 
 #ifdef __cplusplus
 }

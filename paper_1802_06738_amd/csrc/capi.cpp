@@ -38,6 +38,8 @@ struct Timer {
   explicit Timer(pnoeom::Context& cc) : c(cc) {
     c.last_ladder_ms = 0;
     c.last_ladder_launches = 0;
+    c.ladder_flops = 0;
+    c.ladder_kernel_launches = 0;
     c.timing = true;
     c.ev_used = 0;
     PNO_HIP(hipEventCreate(&a));
@@ -57,7 +59,8 @@ struct Timer {
       lad += t;
     }
     c.last_ladder_ms = lad;
-    c.last_ladder_launches = (int)(c.ev_used / 2);
+    c.last_ladder_launches = c.ladder_kernel_launches;
+    c.last_ladder_flops = c.ladder_flops;
   }
   ~Timer() {
     c.timing = false;
@@ -157,9 +160,7 @@ int pnoeom_apply_sigma(pnoeom_ctx* ctx, int nvec, const double* r1, const double
     Timer t(c);
     if (space == PNOEOM_CANONICAL) {
       PNO_CHECK(r1 && r2 && s1 && s2, PNOEOM_EINVAL, "apply_sigma: null vector pointer");
-      for (int q = 0; q < nvec; ++q)
-        pnoeom::sigma_canonical(c, r1 + (int64_t)q * c.ov(), r2 + (int64_t)q * c.oovv(), s1 + (int64_t)q * c.ov(),
-                                s2 + (int64_t)q * c.oovv(), precision);
+      pnoeom::sigma_block(c, nvec, r1, r2, s1, s2, c.ov(), c.oovv(), precision);
     } else {
       PNO_CHECK(c.pno.built, PNOEOM_ESTATE, "apply_sigma(PNO) before build_sapno");
       PNO_CHECK(r1 && s1, PNOEOM_EINVAL, "apply_sigma: null vector pointer");
@@ -215,8 +216,10 @@ int pnoeom_host_eig(int n, const double* a, double* wr, double* wi, double* vr) 
   }
 }
 
-int pnoeom_last_timing(const pnoeom_ctx* ctx, double* total_ms, double* ladder_ms, int* ladder_launches) {
+int pnoeom_last_timing(const pnoeom_ctx* ctx, double* total_ms, double* ladder_ms, int* ladder_launches,
+                       double* ladder_flops) {
   if (!ctx) return PNOEOM_EINVAL;
+  if (ladder_flops) *ladder_flops = ctx->c.last_ladder_flops;
   if (total_ms) *total_ms = ctx->c.last_total_ms;
   if (ladder_ms) *ladder_ms = ctx->c.last_ladder_ms;
   if (ladder_launches) *ladder_launches = ctx->c.last_ladder_launches;

@@ -12,6 +12,8 @@ struct SigmaWork {
   DBuf<double> Ria, Rsia, UiaR, UR, URp, Ubr;
   DBuf<double> Sd, Ziajb, Z3, Dtot, Xtot, DXtot, Zp, Cba, Xh, O4p, OOVVp, M1;
   DBuf<double> Ftv, Fto;
+  DBuf<double> LadAll, Sp, Am, SigP, SigM;  // batched packed ladder
+  DBuf<float> Spf, Amf, SigPf, SigMf;
   // FP32 staging for the mixed-precision contractions
   DBuf<float> fa, fb, fc;
 };
@@ -60,8 +62,9 @@ struct Context {
   DBuf<double> G, GX, g2, Gq, OVVO, OOVVx, Wh, OOOVp;
   DBuf<double> Fqvv, Fqoo, Fvv, Foo, fd_ov;
   DBuf<double> Dr, Xr, DX2, Wvo2;
-  DBuf<double> W;               // ladder matrix [(ab),(cd)] = (ac|bd)~, FP64
-  DBuf<float> Wf;               // FP32 copy when precision = FP32
+  // packed ladder: W+[(a<=b),(c<=d)] = W_abcd + W_abdc, W-[(a<b),(c<d)] = W_abcd - W_abdc
+  DBuf<double> Wp, Wm;          // FP64 (precision FP64)
+  DBuf<float> Wpf, Wmf;         // FP32 (precision FP32)
   DBuf<float> Tf, Tiaf, Tsiaf, Drf, Xrf, DX2f;
   DBuf<double> scratch;         // build-time temporaries
 
@@ -69,8 +72,10 @@ struct Context {
   PNOData pno;
 
   // timing of the last sigma / Davidson call
-  double last_total_ms = 0, last_ladder_ms = 0;
+  double last_total_ms = 0, last_ladder_ms = 0, last_ladder_flops = 0;
   int last_ladder_launches = 0;
+  double ladder_flops = 0;          // algorithmic flops of the timed ladder launches
+  int ladder_kernel_launches = 0;   // GEMM launches inside the timed ladder regions
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;  // start/stop pairs around ladder launches
   size_t ev_used = 0;
@@ -91,6 +96,9 @@ struct Context {
 void build_df(Context& c, const double* B, const double* eps, const double* t1, const double* t2,
               int precision);
 void sigma_canonical(Context& c, const double* r1, const double* r2, double* s1, double* s2, int precision);
+// nvec vectors; r1/s1 of vector q at offset q*stride1, r2/s2 at q*stride2
+void sigma_block(Context& c, int nvec, const double* r1, const double* r2, double* s1, double* s2, int64_t stride1,
+                 int64_t stride2, int precision);
 void symmetrize_r2(hipStream_t s, int o, int v, double* r2);
 // CIS lowest roots; vec (device [n][o][v]) may be null
 void cis_roots(Context& c, int n, double* omega, double* vec);

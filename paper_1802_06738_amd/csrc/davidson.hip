@@ -501,12 +501,8 @@ DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt)
   int prec = opt.precision;
   op.apply = [&](int nv, const double* X, double* S) {
     if (opt.space == PNOEOM_CANONICAL) {
-      for (int q = 0; q < nv; ++q) {
-        const double* x = X + (int64_t)q * op.N;
-        double* y = S + (int64_t)q * op.N;
-        sigma_canonical(c, x, x + ov, y, y + ov, prec);
-        symmetrize_r2(s, o, v, y + ov);
-      }
+      sigma_block(c, nv, X, X + ov, S, S + ov, op.N, op.N, prec);
+      for (int q = 0; q < nv; ++q) symmetrize_r2(s, o, v, S + (int64_t)q * op.N + ov);
     } else {
       sigma_pno(c, nv, X, S, prec);
     }

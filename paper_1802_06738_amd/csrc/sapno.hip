@@ -572,16 +572,18 @@ void precond_pno(Context& c, double* x, double theta) {
 void sigma_pno(Context& c, int nvec, const double* x, double* y, int precision) {
   PNOData& P = c.pno;
   PNO_CHECK(P.built, PNOEOM_ESTATE, "PNO sigma before build_sapno");
-  P.r1.alloc(c.ov());
-  P.r2.alloc(c.oovv());
-  P.s1.alloc(c.ov());
-  P.s2.alloc(c.oovv());
-  for (int q = 0; q < nvec; ++q) {
-    pno_expand(c, 1, x + (int64_t)q * P.len, P.r1, P.r2);
-    sigma_canonical(c, P.r1, P.r2, P.s1, P.s2, precision);
-    pno_compress(c, 1, P.s1, P.s2, y + (int64_t)q * P.len);
-    project_pno(c, y + (int64_t)q * P.len);
-  }
+  if (nvec <= 0) return;
+  auto grow = [](DBuf<double>& b, int64_t n) {
+    if ((int64_t)b.n < n) b.alloc(n);
+  };
+  grow(P.r1, (int64_t)nvec * c.ov());
+  grow(P.r2, (int64_t)nvec * c.oovv());
+  grow(P.s1, (int64_t)nvec * c.ov());
+  grow(P.s2, (int64_t)nvec * c.oovv());
+  pno_expand(c, nvec, x, P.r1, P.r2);
+  sigma_block(c, nvec, P.r1, P.r2, P.s1, P.s2, c.ov(), c.oovv(), precision);
+  pno_compress(c, nvec, P.s1, P.s2, y);
+  for (int q = 0; q < nvec; ++q) project_pno(c, y + (int64_t)q * P.len);
 }
 
 }  // namespace pnoeom

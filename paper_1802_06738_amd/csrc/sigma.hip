@@ -131,6 +131,85 @@ __global__ void symmetrize_kernel(int o, int v, double* __restrict__ r2) {
   }
 }
 
+__host__ __device__ __forceinline__ int64_t tri_idx(int64_t c, int64_t d, int64_t v) {  // c <= d
+  return c * v - c * (c - 1) / 2 + (d - c);
+}
+__host__ __device__ __forceinline__ int64_t stri_idx(int64_t c, int64_t d, int64_t v) {  // c < d
+  return c * (v - 1) - c * (c - 1) / 2 + (d - c - 1);
+}
+__device__ __forceinline__ int64_t pair_idx(int64_t i, int64_t j, int64_t o) {  // i <= j
+  return i * o - i * (i - 1) / 2 + (j - i);
+}
+
+// W+[(a<=b),(c<=d)] = W_abcd + W_abdc (c<d), W_abcc (c=d);  W-[(a<b),(c<d)] = W_abcd - W_abdc,
+// from a slab tmp[a-a0][c][b][d] = W_abcd of rows a in [a0, a0+na)
+template <typename OutT>
+__global__ void ladder_wpm_kernel(int v, int a0, int na, const double* __restrict__ tmp, OutT* __restrict__ Wp,
+                                  OutT* __restrict__ Wm) {
+  const int64_t V = v, vp = V * (V + 1) / 2, vm = V * (V - 1) / 2;
+  const int64_t total = (int64_t)na * V * V * V;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    const int64_t d = r % V; r /= V;
+    const int64_t c = r % V; r /= V;
+    const int64_t b = r % V; r /= V;
+    const int64_t al = r, a = a0 + al;
+    if (b < a || d < c) continue;
+    const double w1 = tmp[((al * V + c) * V + b) * V + d];
+    const double w2 = tmp[((al * V + d) * V + b) * V + c];
+    Wp[tri_idx(a, b, V) * vp + tri_idx(c, d, V)] = (OutT)(c < d ? w1 + w2 : w1);
+    if (a < b && c < d) Wm[stri_idx(a, b, V) * vm + stri_idx(c, d, V)] = (OutT)(w1 - w2);
+  }
+}
+
+// S[(q,p)][(c<=d)] = (R^cd + R^dc)/2 (c<d), R^cc ;  A[(q,p)][(c<d)] = (R^cd - R^dc)/2  for pairs p = (i<=j)
+template <typename OutT>
+__global__ void ladder_pack_kernel(int o, int v, int nvec, const double* __restrict__ r2, int64_t stride,
+                                   OutT* __restrict__ S, OutT* __restrict__ A) {
+  const int64_t O = o, V = v, vp = V * (V + 1) / 2, vm = V * (V - 1) / 2, npair = O * (O + 1) / 2;
+  const int64_t total = (int64_t)nvec * O * O * V * V;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    const int64_t d = r % V; r /= V;
+    const int64_t c = r % V; r /= V;
+    const int64_t j = r % O; r /= O;
+    const int64_t i = r % O; r /= O;
+    const int64_t q = r;
+    if (j < i || d < c) continue;
+    const double* R = r2 + q * stride + (i * O + j) * V * V;
+    const double x = R[c * V + d], y = R[d * V + c];
+    const int64_t row = q * npair + pair_idx(i, j, O);
+    S[row * vp + tri_idx(c, d, V)] = (OutT)(c < d ? 0.5 * (x + y) : x);
+    if (c < d) A[row * vm + stri_idx(c, d, V)] = (OutT)(0.5 * (x - y));
+  }
+}
+
+// out[q][i][j][a][b] = sigma_ij^ab of the ladder from sigma+ (a<=b) and sigma- (a<b) of pair min(i,j), max(i,j)
+template <typename InT>
+__global__ void ladder_unpack_kernel(int o, int v, int nvec, const InT* __restrict__ SP, const InT* __restrict__ SM,
+                                     double* __restrict__ out, int64_t stride) {
+  const int64_t O = o, V = v, vp = V * (V + 1) / 2, vm = V * (V - 1) / 2, npair = O * (O + 1) / 2;
+  const int64_t total = (int64_t)nvec * O * O * V * V;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    int64_t b = r % V; r /= V;
+    int64_t a = r % V; r /= V;
+    int64_t j = r % O; r /= O;
+    int64_t i = r % O; r /= O;
+    const int64_t q = r;
+    if (i > j) {  // sigma_ij^ab = sigma_ji^ba
+      int64_t t = i; i = j; j = t;
+      t = a; a = b; b = t;
+    }
+    const int64_t row = q * npair + pair_idx(i, j, O);
+    double val;
+    if (a == b) val = (double)SP[row * vp + tri_idx(a, a, V)];
+    else if (a < b) val = (double)SP[row * vp + tri_idx(a, b, V)] + (double)SM[row * vm + stri_idx(a, b, V)];
+    else val = (double)SP[row * vp + tri_idx(b, a, V)] - (double)SM[row * vm + stri_idx(b, a, V)];
+    out[q * stride + (e % (O * O * V * V))] = val;
+  }
+}
+
 unsigned grid1(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;
@@ -347,9 +426,14 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     }
   }
 
-  // ladder matrix W[(a,b),(c,d)] = (ac|bd)~ in slabs of a
-  c.W.alloc(vv * vv);
+  // packed ladder matrices W+ / W- built from slabs W_abcd = (ac|bd)~ of rows a
   {
+    const int64_t vp = (int64_t)v * (v + 1) / 2, vm = (int64_t)v * (v - 1) / 2;
+    const bool f32w = precision == PNOEOM_FP32;
+    c.Wp.release(); c.Wm.release(); c.Wpf.release(); c.Wmf.release();
+    c.Wp.alloc(vp * vp);
+    c.Wm.alloc(std::max<int64_t>(vm * vm, 1));
+    if (f32w) { c.Wpf.alloc(vp * vp); c.Wmf.alloc(std::max<int64_t>(vm * vm, 1)); }
     int64_t na = v;
     const int64_t budget = (int64_t)1 << 28;
     while (na > 1 && na * v * vv > budget) na = (na + 1) / 2;
@@ -358,12 +442,17 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     for (int64_t a0 = 0; a0 < v; a0 += na) {
       const int64_t nab = std::min<int64_t>(na, v - a0);
       gm(s, false, true, nab * v, vv, naux, 1.0, c.BvvT + a0 * v * naux, naux, c.BvvT, naux, 0.0, tmp, vv);
-      perm(s, tmp, nab, v, v, v, 0, 2, 1, 3, c.W + a0 * v * vv);
+      const int64_t tot = nab * v * vv;
+      hipLaunchKernelGGL((ladder_wpm_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, v, (int)a0, (int)nab,
+                         (const double*)tmp, (double*)c.Wp, (double*)c.Wm);
+      if (f32w)
+        hipLaunchKernelGGL((ladder_wpm_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, v, (int)a0, (int)nab,
+                           (const double*)tmp, (float*)c.Wpf, (float*)c.Wmf);
+      PNO_HIP(hipGetLastError());
     }
+    PNO_HIP(hipStreamSynchronize(s));
   }
   if (precision == PNOEOM_FP32) {
-    c.Wf.alloc(vv * vv);
-    to_float(s, vv * vv, c.W, c.Wf);
     c.Tf.alloc(oovv);
     c.Tiaf.alloc(oovv);
     c.Tsiaf.alloc(oovv);
@@ -403,11 +492,9 @@ void alloc_sigma_work(Context& c, int precision) {
 }
 }  // namespace
 
-void sigma_canonical(Context& c, const double* r1, const double* r2, double* s1, double* s2, int precision) {
-  PNO_CHECK(c.have_df, PNOEOM_ESTATE, "sigma before build_df");
-  PNO_CHECK(precision == PNOEOM_FP64 || (precision == PNOEOM_FP32 && c.Wf.p), PNOEOM_EINVAL,
-            "sigma: FP32 contractions need build_df with precision FP32");
-  alloc_sigma_work(c, precision);
+namespace {
+// every sigma term except the particle ladder, which the caller has written into Sd
+void sigma_rest(Context& c, const double* r1, const double* r2, double* s1, double* s2, int precision, double* Sd) {
   SigmaWork& w = c.sw;
   hipStream_t s = c.stream;
   const int o = c.o, v = c.v, nmo = c.nmo, naux = c.naux;
@@ -460,39 +547,18 @@ void sigma_canonical(Context& c, const double* r1, const double* r2, double* s1,
   gm(s, false, false, o, v, oo * v, -1.0, c.OOOVp, oo * v, w.URp, v, 1.0, s1, v);
 
   // ---------------------------------------------------------------- sigma2, direct (not P-symmetrised)
-  hipEvent_t lad0 = nullptr, lad1 = nullptr;
-  if (c.timing) {
-    lad0 = c.next_event();
-    lad1 = c.next_event();
-    PNO_HIP(hipEventRecord(lad0, s));
-  }
-  if (f32) {
-    to_float(s, oovv, r2, w.fa);
-    GemmDesc<float> d;
-    d.tb = true; d.M = oo; d.N = vv; d.K = vv; d.tag = 1;
-    d.A = w.fa; d.lda = vv; d.B = c.Wf; d.ldb = vv; d.C = w.fc; d.ldc = vv;
-    gemm(d, s);
-    if (c.timing) PNO_HIP(hipEventRecord(lad1, s));
-    to_double(s, oovv, w.fc, w.Sd, 0.0);
-  } else {
-    GemmDesc<double> d;
-    d.tb = true; d.M = oo; d.N = vv; d.K = vv; d.tag = 1;
-    d.A = r2; d.lda = vv; d.B = c.W; d.ldb = vv; d.C = w.Sd; d.ldc = vv;
-    gemm(d, s);
-    if (c.timing) PNO_HIP(hipEventRecord(lad1, s));
-  }
-  gm(s, false, false, oo, vv, oo, 1.0, c.Wh, oo, r2, vv, 1.0, w.Sd, vv);
+  gm(s, false, false, oo, vv, oo, 1.0, c.Wh, oo, r2, vv, 1.0, Sd, vv);
   gm(s, false, true, oo, oo, vv, 1.0, r2, vv, c.g2, vv, 0.0, w.Xh, oo);
   gm(s, false, true, oo, oo, naux, 1.0, w.BoopT, naux, c.BooT, naux, 0.0, w.O4p, oo);
   gm(s, false, true, oo, oo, naux, 1.0, c.BooT, naux, w.BoopT, naux, 1.0, w.O4p, oo);
   perm(s, w.O4p, o, o, o, o, 1, 3, 0, 2, w.Xh, 1.0, 1.0);
-  gm(s, false, false, oo, vv, oo, 1.0, w.Xh, oo, c.T, vv, 1.0, w.Sd, vv);
+  gm(s, false, false, oo, vv, oo, 1.0, w.Xh, oo, c.T, vv, 1.0, Sd, vv);
 
   // ---------------------------------------------------------------- ring terms in [(i,a),(j,b)] form
   gm(s, false, true, ov, ov, naux, 0.5, w.BvopT, naux, c.BvoT, naux, 0.0, w.Ziajb, ov);
   gm(s, false, true, ov, ov, naux, 0.5, c.BvoT, naux, w.BvopT, naux, 1.0, w.Ziajb, ov);
   // R-side intermediates D(R) and X(R)
-  gm(s, false, true, ov, ov, ov, 0.5, c.G, ov, w.UiaR, ov, 0.0, w.Dtot, ov);
+  gm(s, false, true, ov, ov, naux, 0.5, c.BovT, naux, w.M1, naux, 0.0, w.Dtot, ov);  // (1/2) G U(R)^T
   gm(s, false, true, ov, ov, ov, -0.5, c.GX, ov, w.Ria, ov, 1.0, w.Dtot, ov);
   gm(s, false, true, ov, ov, naux, 1.0, c.BovT, naux, w.BvopT, naux, 1.0, w.Dtot, ov);
   gm(s, false, true, ov, ov, ov, -0.5, c.GX, ov, w.Rsia, ov, 0.0, w.Xtot, ov);
@@ -536,9 +602,86 @@ void sigma_canonical(Context& c, const double* r1, const double* r2, double* s1,
   // -P[ sum_k r_k^a Wvo_kbij ] collected as Cba[i][j][b][a] = sum_k Wvo2[(ijb)][k] r1[k][a]
   gm(s, false, false, oo * v, v, o, 1.0, c.Wvo2, o, r1, v, 0.0, w.Cba, v);
 
-  hipLaunchKernelGGL(assemble_s2_kernel, dim3(grid1(oovv)), dim3(256), 0, s, o, v, (const double*)w.Sd,
+  hipLaunchKernelGGL(assemble_s2_kernel, dim3(grid1(oovv)), dim3(256), 0, s, o, v, (const double*)Sd,
                      (const double*)w.Zp, (const double*)w.Ziajb, (const double*)w.Z3, (const double*)w.Cba, s2);
   PNO_HIP(hipGetLastError());
+}
+}  // namespace
+
+void sigma_block(Context& c, int nvec, const double* r1, const double* r2, double* s1, double* s2, int64_t stride1,
+                 int64_t stride2, int precision) {
+  PNO_CHECK(c.have_df, PNOEOM_ESTATE, "sigma before build_df");
+  const bool f32 = precision == PNOEOM_FP32;
+  PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32, PNOEOM_EINVAL, "sigma: precision must be FP64 or FP32");
+  PNO_CHECK(f32 ? (c.Wpf.p != nullptr) : (c.Wp.p != nullptr), PNOEOM_EINVAL,
+            "sigma: the contraction precision must match the one given to build_df");
+  if (nvec <= 0) return;
+  alloc_sigma_work(c, precision);
+  SigmaWork& w = c.sw;
+  hipStream_t s = c.stream;
+  const int o = c.o, v = c.v;
+  const int64_t oovv = c.oovv();
+  const int64_t npair = (int64_t)o * (o + 1) / 2, vp = (int64_t)v * (v + 1) / 2, vm = (int64_t)v * (v - 1) / 2;
+  const int64_t rows = (int64_t)nvec * npair;
+  auto grow = [](auto& buf, int64_t n) {
+    if ((int64_t)buf.n < n) buf.alloc(n);
+  };
+  grow(w.LadAll, (int64_t)nvec * oovv);
+  const int64_t tot = (int64_t)nvec * oovv;
+  // ---------------------------------------------------------------- particle ladder, all vectors at once
+  hipEvent_t lad0 = nullptr, lad1 = nullptr;
+  if (f32) {
+    grow(w.Spf, rows * vp); grow(w.Amf, std::max<int64_t>(rows * vm, 1));
+    grow(w.SigPf, rows * vp); grow(w.SigMf, std::max<int64_t>(rows * vm, 1));
+    hipLaunchKernelGGL((ladder_pack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec, r2, stride2,
+                       (float*)w.Spf, (float*)w.Amf);
+  } else {
+    grow(w.Sp, rows * vp); grow(w.Am, std::max<int64_t>(rows * vm, 1));
+    grow(w.SigP, rows * vp); grow(w.SigM, std::max<int64_t>(rows * vm, 1));
+    hipLaunchKernelGGL((ladder_pack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec, r2, stride2,
+                       (double*)w.Sp, (double*)w.Am);
+  }
+  PNO_HIP(hipGetLastError());
+  if (c.timing) {
+    lad0 = c.next_event();
+    lad1 = c.next_event();
+    PNO_HIP(hipEventRecord(lad0, s));
+  }
+  if (f32) {
+    GemmDesc<float> d;
+    d.tb = true; d.M = rows; d.N = vp; d.K = vp; d.tag = 1;
+    d.A = w.Spf; d.lda = vp; d.B = c.Wpf; d.ldb = vp; d.C = w.SigPf; d.ldc = vp;
+    gemm(d, s);
+    d.N = vm; d.K = vm; d.A = w.Amf; d.lda = vm; d.B = c.Wmf; d.ldb = vm; d.C = w.SigMf; d.ldc = vm;
+    gemm(d, s);
+  } else {
+    GemmDesc<double> d;
+    d.tb = true; d.M = rows; d.N = vp; d.K = vp; d.tag = 1;
+    d.A = w.Sp; d.lda = vp; d.B = c.Wp; d.ldb = vp; d.C = w.SigP; d.ldc = vp;
+    gemm(d, s);
+    d.N = vm; d.K = vm; d.A = w.Am; d.lda = vm; d.B = c.Wm; d.ldb = vm; d.C = w.SigM; d.ldc = vm;
+    gemm(d, s);
+  }
+  if (c.timing) {
+    PNO_HIP(hipEventRecord(lad1, s));
+    c.ladder_flops += 2.0 * (double)rows * ((double)vp * vp + (double)vm * vm);
+    c.ladder_kernel_launches += vm > 0 ? 2 : 1;
+  }
+  if (f32)
+    hipLaunchKernelGGL((ladder_unpack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec,
+                       (const float*)w.SigPf, (const float*)w.SigMf, (double*)w.LadAll, oovv);
+  else
+    hipLaunchKernelGGL((ladder_unpack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec,
+                       (const double*)w.SigP, (const double*)w.SigM, (double*)w.LadAll, oovv);
+  PNO_HIP(hipGetLastError());
+  // ---------------------------------------------------------------- everything else, per vector
+  for (int q = 0; q < nvec; ++q)
+    sigma_rest(c, r1 + q * stride1, r2 + q * stride2, s1 + q * stride1, s2 + q * stride2, precision,
+               w.LadAll + (int64_t)q * oovv);
+}
+
+void sigma_canonical(Context& c, const double* r1, const double* r2, double* s1, double* s2, int precision) {
+  sigma_block(c, 1, r1, r2, s1, s2, c.ov(), c.oovv(), precision);
 }
 
 }  // namespace pnoeom

@@ -66,7 +66,7 @@ def load_library():
     lib.pnoeom_davidson_defaults.restype = None
     lib.pnoeom_davidson.argtypes = [vp, C.c_int, C.POINTER(DavidsonOpts), dp, dp, ip, ip]
     lib.pnoeom_host_eig.argtypes = [C.c_int, dp, dp, dp, dp]
-    lib.pnoeom_last_timing.argtypes = [vp, dp, dp, ip]
+    lib.pnoeom_last_timing.argtypes = [vp, dp, dp, ip, dp]
     _LIB = lib
     return lib
 
@@ -224,5 +224,6 @@ class PnoEom:
         t = C.c_double()
         lad = C.c_double()
         n = C.c_int()
-        self._check(self.lib.pnoeom_last_timing(self.h, C.byref(t), C.byref(lad), C.byref(n)))
-        return dict(total_ms=t.value, ladder_ms=lad.value, ladder_launches=n.value)
+        fl = C.c_double()
+        self._check(self.lib.pnoeom_last_timing(self.h, C.byref(t), C.byref(lad), C.byref(n), C.byref(fl)))
+        return dict(total_ms=t.value, ladder_ms=lad.value, ladder_launches=n.value, ladder_flops=fl.value)
