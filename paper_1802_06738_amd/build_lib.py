@@ -14,7 +14,8 @@ LIB = os.path.join(HERE, "libpnoeom.so")
 SOURCES = ["gemm.hip", "tensor.hip", "sigma.hip", "davidson.hip", "sapno.hip", "eig.cpp", "capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
-         "-packed-fp32-ops", "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
+         "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form", "-I" + os.path.join(ROOT, "include"), "-Wall",
+         "-Wno-unused-function"]
 
 
 def _compile(src: str) -> str:

@@ -166,7 +166,7 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
   const int nroots = ntarget + nextra;
   const int maxs = std::max(opt.max_sub, nroots + nguess);
   const int cap = maxs + nroots;
-  DBuf<double> V, S, X, R, cand, dY, dc, dth;
+  DBuf<double> V, S, X, R, cand, dY, dc, dcb, dth;
   V.alloc((int64_t)cap * N);
   S.alloc((int64_t)cap * N);
   X.alloc((int64_t)nroots * N);
@@ -174,6 +174,7 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
   cand.alloc(N);
   dY.alloc((int64_t)cap * nroots);
   dc.alloc(cap);
+  dcb.alloc((int64_t)cap * nroots);
   dth.alloc(nroots);
   Dots dw;
   DavidsonResult res;
@@ -281,23 +282,55 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
     }
     theta_old = theta;
     have_old = true;
-    // corrections
-    std::vector<int> fresh;  // rows of R turned into new directions, staged in X
-    int nnew = 0;
+    // corrections: preconditioned residuals of the unconverged roots, normalised,
+    // orthogonalised against V as a block (two classical Gram-Schmidt passes, each
+    // reading V once), then among themselves; staged in X
+    int nc = 0;
     for (int k = 0; k < nroots; ++k) {
       if (conv[k]) continue;
-      PNO_HIP(hipMemcpyAsync(cand, R + (int64_t)k * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-      op.precond(cand, theta[k]);
-      double n0 = 0.0;
-      dots(s, dw, cand, 1, cand, 1, N, &n0);
-      if (!(n0 > 0.0)) continue;
-      hipLaunchKernelGGL(scale_kernel, dim3(g1(N)), dim3(256), 0, s, N, 1.0 / std::sqrt(n0), (double*)cand);
-      // orthogonalise against V and the accepted new vectors (stored after V)
-      const double nrm = orth(cand, m + nnew);
-      if (nrm < 1e-10) continue;
-      hipLaunchKernelGGL(scale_kernel, dim3(g1(N)), dim3(256), 0, s, N, 1.0 / nrm, (double*)cand);
-      PNO_HIP(hipMemcpyAsync(V + (int64_t)(m + nnew) * N, cand, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-      ++nnew;
+      double* xk = X + (int64_t)nc * N;
+      PNO_HIP(hipMemcpyAsync(xk, R + (int64_t)k * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      op.precond(xk, theta[k]);
+      ++nc;
+    }
+    int nnew = 0;
+    if (nc > 0) {
+      std::vector<double> cc((size_t)nc * nc);
+      dots(s, dw, X, nc, X, nc, N, cc.data());
+      for (int q = 0; q < nc; ++q) {
+        const double n0 = cc[(size_t)q * nc + q];
+        const double sc = n0 > 0.0 ? 1.0 / std::sqrt(n0) : 0.0;
+        hipLaunchKernelGGL(scale_kernel, dim3(g1(N)), dim3(256), 0, s, N, sc, X + (int64_t)q * N);
+      }
+      std::vector<double> coef((size_t)m * nc);
+      for (int pass = 0; pass < 2; ++pass) {
+        dots(s, dw, V, m, X, nc, N, coef.data());  // coef[i][q] = V_i . X_q
+        PNO_HIP(hipMemcpyAsync(dcb, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        GemmDesc<double> d;
+        d.ta = true; d.M = nc; d.N = N; d.K = m; d.alpha = -1.0; d.beta = 1.0;
+        d.A = dcb; d.lda = nc; d.B = V; d.ldb = N; d.C = X; d.ldc = N;
+        gemm(d, s);
+      }
+      for (int q = 0; q < nc; ++q) {
+        double* xq = X + (int64_t)q * N;
+        // against the directions accepted so far in this iteration (rows m .. m+nnew-1 of V)
+        std::vector<double> cvec(std::max(nnew, 1));
+        for (int pass = 0; pass < 2 && nnew > 0; ++pass) {
+          dots(s, dw, V + (int64_t)m * N, nnew, xq, 1, N, cvec.data());
+          PNO_HIP(hipMemcpyAsync(dc, cvec.data(), nnew * sizeof(double), hipMemcpyHostToDevice, s));
+          GemmDesc<double> d;
+          d.M = 1; d.N = N; d.K = nnew; d.alpha = -1.0; d.beta = 1.0;
+          d.A = dc; d.lda = nnew; d.B = V + (int64_t)m * N; d.ldb = N; d.C = xq; d.ldc = N;
+          gemm(d, s);
+        }
+        double nn = 0.0;
+        dots(s, dw, xq, 1, xq, 1, N, &nn);
+        const double nrm = std::sqrt(nn);
+        if (!(nrm >= 1e-10)) continue;
+        hipLaunchKernelGGL(scale_kernel, dim3(g1(N)), dim3(256), 0, s, N, 1.0 / nrm, xq);
+        PNO_HIP(hipMemcpyAsync(V + (int64_t)(m + nnew) * N, xq, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        ++nnew;
+      }
     }
     PNO_CHECK(nnew > 0, PNOEOM_ENOTCONV, "Davidson stalled: no new directions");
     if (m + nnew > maxs) {

@@ -9,6 +9,17 @@
 // lane l supplies A[l%16][k0 + l/16] and B[k0 + l/16][l%16].  Accumulator r of
 // lane l holds column l%16 and row 4*(l/16) + r (FP32) or row l/16 + 4*r (FP64),
 // as measured on gfx950.
+//
+// Occupancy: the kernel is limited to 256 registers per lane so that two
+// workgroups share a CU; one workgroup's global loads, LDS stores and barriers
+// then overlap the other's MFMA stream (a single workgroup per CU leaves the
+// matrix cores idle during those phases).  The library is built with MFMA
+// accumulators in ordinary VGPRs, which avoids per-iteration copies between the
+// VGPR and AGPR halves of the register file.
+//
+// Tile order: workgroup b runs on XCD b % 8, so tiles are handed out in eight
+// contiguous chunks, one per XCD; the workgroups that share an XCD's L2 then
+// work on neighbouring tiles and share their A and B panels.
 #include <algorithm>
 
 #include "common.h"
@@ -48,14 +59,16 @@ struct KArgs {
   int64_t batch;
   int reduce;
   int tiles_m, tiles_n;
+  int64_t xper;       // tiles per XCD chunk; 0: grid index = tile index
   int64_t it_split;   // K-loop iterations per split (split-K); 0: no split
   T* ws;              // split-K partials [split][batch_out][M][N]
 };
 
 constexpr int NT = 256;
 
+
 template <typename T, int BM, int BN, int BK, bool TA, bool TB, int TAG>
-__global__ __launch_bounds__(NT) void gemm_kernel(KArgs<T> g) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void gemm_kernel(KArgs<T> g) {
   constexpr int PADA = (sizeof(T) == 8) ? 1 : 2;
   __shared__ T As[BK][BM + PADA];
   __shared__ T Bs[BK][BN + PADA];
@@ -63,6 +76,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs<T> g) {
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
   static_assert(LA * NT == BM * BK && LB * NT == BN * BK, "tile/thread mismatch");
+  static_assert(NT % BK == 0 && NT % BM == 0 && NT % BN == 0, "staging map needs NT divisible by the tile");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -72,7 +86,11 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs<T> g) {
 
   // tile index -> (tm, tn): column-of-tiles major so that consecutive workgroups
   // share the same B panel
-  const int64_t tile = blockIdx.x;
+  int64_t tile = blockIdx.x;
+  if (g.xper > 0) {
+    tile = (int64_t)(blockIdx.x % 8) * g.xper + blockIdx.x / 8;
+    if (tile >= (int64_t)g.tiles_m * g.tiles_n) return;  // padding of the last chunk
+  }
   const int64_t tmi = tile % g.tiles_m;
   const int64_t tni = tile / g.tiles_m;
   const int64_t m0 = tmi * BM, n0 = tni * BN;
@@ -91,11 +109,42 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs<T> g) {
 
   T ra[LA], rb[LB];
 
+  // Staging map: element e = tid + q * NT of the A tile sits at (mm, kk) with
+  // mm = e / BK, kk = e % BK (A row-major) or kk = e / BM, mm = e % BM (A^T given);
+  // B likewise.  Because NT is a multiple of the tile sides, a thread's elements
+  // lie on one column (or row) at a fixed stride, so a tile that lies inside the
+  // operands is fetched with one pointer per thread and unguarded loads.
+  const bool interior = (m0 + BM <= g.M) && (n0 + BN <= g.N);
   auto load = [&](int64_t it) {
     const int64_t b = g.reduce ? (it / ktiles) : bz;
     const int64_t k0 = (it % ktiles) * BK;
     const T* A = g.A + b * g.sA;
     const T* B = g.B + b * g.sB;
+    if (interior && k0 + BK <= g.K) {
+      if (!TA) {
+        const T* p = A + (m0 + tid / BK) * g.lda + k0 + tid % BK;
+        const int64_t st = (int64_t)(NT / BK) * g.lda;
+#pragma unroll
+        for (int q = 0; q < LA; ++q) ra[q] = p[q * st];
+      } else {
+        const T* p = A + (k0 + tid / BM) * g.lda + m0 + tid % BM;
+        const int64_t st = (int64_t)(NT / BM) * g.lda;
+#pragma unroll
+        for (int q = 0; q < LA; ++q) ra[q] = p[q * st];
+      }
+      if (TB) {
+        const T* p = B + (n0 + tid / BK) * g.ldb + k0 + tid % BK;
+        const int64_t st = (int64_t)(NT / BK) * g.ldb;
+#pragma unroll
+        for (int q = 0; q < LB; ++q) rb[q] = p[q * st];
+      } else {
+        const T* p = B + (k0 + tid / BN) * g.ldb + n0 + tid % BN;
+        const int64_t st = (int64_t)(NT / BN) * g.ldb;
+#pragma unroll
+        for (int q = 0; q < LB; ++q) rb[q] = p[q * st];
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < LA; ++q) {
       const int e = tid + q * NT;
@@ -133,17 +182,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs<T> g) {
       Bs[kk][nn] = rb[q];
     }
   };
-
-  int64_t it_begin = 0, it_end = total;
-  if (g.it_split > 0) {
-    it_begin = (int64_t)blockIdx.z * g.it_split;
-    it_end = it_begin + g.it_split < total ? it_begin + g.it_split : total;
-  }
-  if (it_begin < it_end) load(it_begin);
-  for (int64_t it = it_begin; it < it_end; ++it) {
-    store();
-    __syncthreads();
-    if (it + 1 < it_end) load(it + 1);
+  auto compute = [&]() {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T av[TM], bv[TN];
@@ -156,6 +195,19 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs<T> g) {
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mac(av[i], bv[j], acc[i][j]);
     }
+  };
+
+  int64_t it_begin = 0, it_end = total;
+  if (g.it_split > 0) {
+    it_begin = (int64_t)blockIdx.z * g.it_split;
+    it_end = it_begin + g.it_split < total ? it_begin + g.it_split : total;
+  }
+  if (it_begin < it_end) load(it_begin);
+  for (int64_t it = it_begin; it < it_end; ++it) {
+    store();
+    __syncthreads();
+    if (it + 1 < it_end) load(it + 1);
+    compute();
     __syncthreads();
   }
 
@@ -247,7 +299,15 @@ void launch_tile(const GemmDesc<T>& d, hipStream_t s) {
     nsplit = (loop + g.it_split - 1) / g.it_split;
     g.ws = splitk_ws<T>((size_t)nsplit * gy * d.M * d.N);
   }
-  dim3 grid((unsigned)tiles, (unsigned)gy, (unsigned)nsplit);
+  // XCD-contiguous tile order (the grid is padded to a multiple of 8)
+  g.xper = 0;
+  int64_t gx = tiles;
+  if (tiles >= 64) {
+    g.xper = (tiles + 7) / 8;
+    gx = 8 * g.xper;
+  }
+  PNO_CHECK(gx < (1ll << 31), PNOEOM_EINVAL, "gemm: too many tiles");
+  dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)nsplit);
   if (d.tag == 1 && !d.ta && d.tb)
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, true, 1>), grid, dim3(NT), 0, s, g);
   else if (!d.ta && !d.tb)
