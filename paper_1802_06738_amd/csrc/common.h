@@ -123,16 +123,18 @@ inline void mm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K,
 }
 
 // ----------------------------------------------------------------------------- tensor ops
-// out[o0,o1,o2,o3] (strides os*) = alpha * in[o0*is0 + o1*is1 + o2*is2 + o3*is3] + beta * out
+// out[o0,o1,o2,o3] (strides os*) = alpha * in[o0*is0 + o1*is1 + o2*is2 + o3*is3] + beta * out,
+// repeated for nb batches at input / output offsets ibs, obs
 struct Perm4 {
   int64_t d[4];
   int64_t is[4];
   int64_t os[4];
+  int64_t nb = 1, ibs = 0, obs = 0;
 };
 void permute4(hipStream_t s, const Perm4& p, double alpha, const double* in, double beta, double* out);
 // contiguous output of a permuted contiguous input: out axes taken from input axes perm[]
 void permute_c(hipStream_t s, const int64_t in_dims[4], const int perm[4], double alpha, const double* in,
-               double beta, double* out);
+               double beta, double* out, int64_t nb = 1);
 void axpby(hipStream_t s, int64_t n, double alpha, const double* x, double beta, double* y);
 void fill(hipStream_t s, int64_t n, double val, double* y);
 void to_float(hipStream_t s, int64_t n, const double* x, float* y);

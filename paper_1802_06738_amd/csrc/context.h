@@ -9,8 +9,8 @@ namespace pnoeom {
 struct SigmaWork {
   DBuf<double> Bp, hp, Jp, Kp, fp, dp, fp_ov, fp_vv, fp_oo;
   DBuf<double> BvopT, BoopT, BvvpT;
-  DBuf<double> Ria, Rsia, UiaR, UR, URp, Ubr;
-  DBuf<double> Sd, Ziajb, Z3, Dtot, Xtot, DXtot, Zp, Cba, Xh, O4p, OOVVp, M1;
+  DBuf<double> R2c, Ria, Rsia, UiaR, UR, URp, Ubr;
+  DBuf<double> Ziajb, Z3, Dtot, Xtot, DXtot, Zp, Cba, Xh, O4p, OOVVp, M1;
   DBuf<double> Ftv, Fto;
   DBuf<double> LadAll, Sp, Am, SigP, SigM;  // batched packed ladder
   DBuf<float> Spf, Amf, SigPf, SigMf;
@@ -65,7 +65,7 @@ struct Context {
   // packed ladder: W+[(a<=b),(c<=d)] = W_abcd + W_abdc, W-[(a<b),(c<d)] = W_abcd - W_abdc
   DBuf<double> Wp, Wm;          // FP64 (precision FP64)
   DBuf<float> Wpf, Wmf;         // FP32 (precision FP32)
-  DBuf<float> Tf, Tiaf, Tsiaf, Drf, Xrf, DX2f;
+  DBuf<float> Tf, Tiaf, Tsiaf, Drf, Xrf, DX2f, GXf;
   DBuf<double> scratch;         // build-time temporaries
 
   SigmaWork sw;

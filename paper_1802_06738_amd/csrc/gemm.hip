@@ -336,7 +336,7 @@ void gemm_impl(const GemmDesc<T>& d, hipStream_t s) {
   PNO_CHECK(d.A && d.B && d.C, PNOEOM_EINVAL, "gemm: null operand");
   // tile choice: large tiles when both output dimensions fill them
   if (d.M >= 128 && d.N >= 128)
-    launch_tile<T, 128, 128, 16>(d, s);
+    launch_tile<T, 128, 128, (sizeof(T) == 8 ? 16 : 32)>(d, s);
   else if (d.M <= 32 && d.N >= 128)
     launch_tile<T, 32, 128, 16>(d, s);
   else if (d.N <= 32 && d.M >= 128)

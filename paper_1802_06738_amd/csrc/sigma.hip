@@ -92,27 +92,6 @@ __global__ void mp2_div_kernel(int o, int v, const double* __restrict__ eps, dou
   }
 }
 
-// s2[i][j][a][b] = Sd[ijab] + Z(i,j,a,b) + Z(j,i,b,a) with
-// Z(i,j,a,b) = Zp[i][j][a][b] + Ziajb[i][a][j][b] + Z3[j][a][i][b] - Cba[i][j][b][a]
-__global__ void assemble_s2_kernel(int o, int v, const double* __restrict__ Sd, const double* __restrict__ Zp,
-                                   const double* __restrict__ Zia, const double* __restrict__ Z3,
-                                   const double* __restrict__ Cba, double* __restrict__ s2) {
-  const int64_t n = (int64_t)o * o * v * v;
-  const int64_t V = v, O = o;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t r = e;
-    const int64_t b = r % V; r /= V;
-    const int64_t a = r % V; r /= V;
-    const int64_t j = r % O; r /= O;
-    const int64_t i = r;
-    auto Z = [&](int64_t I, int64_t Jj, int64_t A, int64_t Bb) {
-      return Zp[((I * O + Jj) * V + A) * V + Bb] + Zia[((I * V + A) * O + Jj) * V + Bb] +
-             Z3[((Jj * V + A) * O + I) * V + Bb] - Cba[((I * O + Jj) * V + Bb) * V + A];
-    };
-    s2[e] = Sd[e] + Z(i, j, a, b) + Z(j, i, b, a);
-  }
-}
-
 __global__ void symmetrize_kernel(int o, int v, double* __restrict__ r2) {
   const int64_t n = (int64_t)o * o * v * v;
   const int64_t V = v, O = o;
@@ -459,151 +438,255 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     c.Drf.alloc(oovv);
     c.Xrf.alloc(oovv);
     c.DX2f.alloc(oovv);
+    c.GXf.alloc(oovv);
     to_float(s, oovv, c.T, c.Tf);
     to_float(s, oovv, c.Tia, c.Tiaf);
     to_float(s, oovv, c.Tsia, c.Tsiaf);
     to_float(s, oovv, c.Dr, c.Drf);
     to_float(s, oovv, c.Xr, c.Xrf);
     to_float(s, oovv, c.DX2, c.DX2f);
+    to_float(s, oovv, c.GX, c.GXf);
   }
   PNO_HIP(hipStreamSynchronize(s));
   c.have_df = true;
 }
 
 namespace {
-void alloc_sigma_work(Context& c, int precision) {
+template <typename T>
+void grow(DBuf<T>& b, int64_t n) {
+  if ((int64_t)b.n < n) b.alloc(std::max<int64_t>(n, 1));
+}
+
+// device memory of the per-vector work arrays of sigma_rest (bytes per vector)
+int64_t rest_bytes_per_vector(const Context& c, bool f32) {
+  const int64_t ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, oovv = c.oovv();
+  int64_t nd = 15 * oovv + (ov + oo + vv) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv + oo + vv + oo;
+  int64_t bytes = nd * (int64_t)sizeof(double);
+  if (f32) bytes += 3 * oovv * (int64_t)sizeof(float);
+  return bytes;
+}
+
+// number of vectors per sigma_rest_block call: as many as fit in the free device
+// memory (plus what the work arrays already hold), leaving 1 GiB of headroom
+int rest_chunk(const Context& c, int nvec, bool f32) {
+  const int64_t per = rest_bytes_per_vector(c, f32);
+  size_t freeb = 0, totalb = 0;
+  PNO_HIP(hipMemGetInfo(&freeb, &totalb));
+  const int64_t held = c.oovv() > 0 ? (int64_t)(c.sw.Ria.n / c.oovv()) * per : 0;
+  const int64_t avail = (int64_t)freeb + held - (1ll << 30);
+  int64_t nb = avail > 0 ? avail / per : 0;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(nb, nvec));
+}
+
+void alloc_sigma_work(Context& c, int precision, int nb) {
   SigmaWork& w = c.sw;
   const int64_t n2 = (int64_t)c.nmo * c.nmo, ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v;
-  const int64_t oovv = c.oovv();
-  w.Bp.alloc((int64_t)c.naux * n2);
-  w.hp.alloc(n2); w.Jp.alloc(n2); w.Kp.alloc(n2); w.fp.alloc(n2); w.dp.alloc(c.naux);
-  w.fp_ov.alloc(ov); w.fp_vv.alloc(vv); w.fp_oo.alloc(oo);
-  w.BvopT.alloc(ov * c.naux); w.BoopT.alloc(oo * c.naux); w.BvvpT.alloc(vv * c.naux);
-  w.Ria.alloc(oovv); w.Rsia.alloc(oovv); w.UiaR.alloc(oovv); w.UR.alloc(oovv); w.URp.alloc(oovv);
-  w.Ubr.alloc(oovv);
-  w.Sd.alloc(oovv); w.Ziajb.alloc(oovv); w.Z3.alloc(oovv); w.Dtot.alloc(oovv); w.Xtot.alloc(oovv);
-  w.DXtot.alloc(oovv); w.Zp.alloc(oovv); w.Cba.alloc(oovv); w.Xh.alloc(oo * oo); w.O4p.alloc(oo * oo);
-  w.OOVVp.alloc(oovv); w.M1.alloc(ov * c.naux);
-  w.Ftv.alloc(vv); w.Fto.alloc(oo);
+  const int64_t oovv = c.oovv(), B = nb;
+  // one-vector scratch of the R1 one-index transformation
+  grow(w.Bp, (int64_t)c.naux * n2);
+  grow(w.hp, n2); grow(w.Jp, n2); grow(w.Kp, n2); grow(w.fp, n2); grow(w.dp, c.naux);
+  // per-vector arrays, [nb][...]
+  grow(w.fp_ov, B * ov); grow(w.fp_vv, B * vv); grow(w.fp_oo, B * oo);
+  grow(w.BvopT, B * ov * c.naux); grow(w.BoopT, B * oo * c.naux); grow(w.BvvpT, B * vv * c.naux);
+  grow(w.R2c, B * oovv);
+  grow(w.Ria, B * oovv); grow(w.Rsia, B * oovv); grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
+  grow(w.URp, B * oovv); grow(w.Ubr, B * oovv);
+  grow(w.Ziajb, B * oovv); grow(w.Z3, B * oovv); grow(w.Dtot, B * oovv); grow(w.Xtot, B * oovv);
+  grow(w.DXtot, B * oovv); grow(w.Zp, B * oovv); grow(w.Cba, B * oovv); grow(w.OOVVp, B * oovv);
+  grow(w.Xh, B * oo * oo); grow(w.O4p, B * oo * oo); grow(w.M1, B * ov * c.naux);
+  grow(w.Ftv, B * vv); grow(w.Fto, B * oo);
   if (precision == PNOEOM_FP32) {
-    const int64_t big = std::max<int64_t>(oovv, 1);
-    w.fa.alloc(big); w.fb.alloc(big); w.fc.alloc(big);
+    grow(w.fa, B * oovv); grow(w.fb, B * oovv); grow(w.fc, B * oovv);
   }
+}
+
+// batched C_q = alpha op(A_q) op(B_q) + beta C_q with FP32 operands and accumulation,
+// C in FP64 with C_q contiguous (ldc = N, sC = M N); fc is FP32 staging of nb M N
+void gmbf(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const float* A, int64_t lda,
+          int64_t sA, const float* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t nb, float* fc) {
+  GemmDesc<float> d;
+  d.ta = ta; d.tb = tb; d.M = M; d.N = N; d.K = K; d.alpha = (float)alpha; d.beta = 0.f;
+  d.A = A; d.lda = lda; d.sA = sA; d.B = B; d.ldb = ldb; d.sB = sB; d.C = fc; d.ldc = N; d.sC = M * N;
+  d.batch = nb;
+  gemm(d, s);
+  to_double(s, nb * M * N, fc, C, beta);
 }
 }  // namespace
 
 namespace {
-// every sigma term except the particle ladder, which the caller has written into Sd
-void sigma_rest(Context& c, const double* r1, const double* r2, double* s1, double* s2, int precision, double* Sd) {
+// s2[q] = Sd[q] + Z(i,j,a,b) + Z(j,i,b,a) for nb vectors, with
+// Z(i,j,a,b) = Zp[i][j][a][b] + Ziajb[i][a][j][b] + Z3[j][a][i][b] - Cba[i][j][b][a]
+__global__ void assemble_s2_block_kernel(int o, int v, int nb, const double* __restrict__ Sd,
+                                         const double* __restrict__ Zp, const double* __restrict__ Zia,
+                                         const double* __restrict__ Z3, const double* __restrict__ Cba,
+                                         double* __restrict__ s2, int64_t stride2) {
+  const int64_t V = v, O = o, n = O * O * V * V;
+  const int64_t total = n * nb;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = g / n, e = g - q * n;
+    int64_t r = e;
+    const int64_t b = r % V; r /= V;
+    const int64_t a = r % V; r /= V;
+    const int64_t j = r % O;
+    const int64_t i = r / O;
+    const double* zp = Zp + q * n;
+    const double* zi = Zia + q * n;
+    const double* z3 = Z3 + q * n;
+    const double* cb = Cba + q * n;
+    auto Z = [&](int64_t I, int64_t Jj, int64_t A, int64_t Bb) {
+      return zp[((I * O + Jj) * V + A) * V + Bb] + zi[((I * V + A) * O + Jj) * V + Bb] +
+             z3[((Jj * V + A) * O + I) * V + Bb] - cb[((I * O + Jj) * V + Bb) * V + A];
+    };
+    s2[q * stride2 + e] = Sd[g] + Z(i, j, a, b) + Z(j, i, b, a);
+  }
+}
+
+// every sigma term except the particle ladder, for nb vectors at once; the caller
+// has written the ladder of vector q into Sd + q * oovv.  Contractions whose one
+// operand is a fixed intermediate run as one batched GEMM over the vectors.
+void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, const double* r2, int64_t stride2,
+                      double* s1, double* s2, int precision, double* Sd) {
   SigmaWork& w = c.sw;
   hipStream_t s = c.stream;
   const int o = c.o, v = c.v, nmo = c.nmo, naux = c.naux;
   const int64_t n2 = (int64_t)nmo * nmo, ov = c.ov(), oo = (int64_t)o * o, vv = (int64_t)v * v;
-  const int64_t oovv = c.oovv();
+  const int64_t oovv = c.oovv(), oon = oo * naux, ovn = ov * naux, vvn = vv * naux, o4 = oo * oo;
   const bool f32 = precision == PNOEOM_FP32;
+  alloc_sigma_work(c, precision, nb);
 
-  // ---------------------------------------------------------------- R1: one-index transformed factors
-  fill(s, (int64_t)naux * n2, 0.0, w.Bp);
-  gmb(s, true, false, v, nmo, o, -1.0, r1, v, 0, c.Bt, nmo, n2, 1.0, w.Bp + (int64_t)o * nmo, nmo, n2, naux);
-  gmb(s, false, true, nmo, o, v, 1.0, c.Bt + o, nmo, n2, r1, v, 0, 1.0, w.Bp, nmo, n2, naux);
-  fill(s, n2, 0.0, w.hp);
-  gm(s, true, false, v, nmo, o, -1.0, r1, v, c.hd, nmo, 1.0, w.hp + (int64_t)o * nmo, nmo);
-  gm(s, false, true, nmo, o, v, 1.0, c.hd + o, nmo, r1, v, 1.0, w.hp, nmo);
-  hipLaunchKernelGGL(trace_occ_kernel, dim3((naux + 255) / 256), dim3(256), 0, s, naux, nmo, o,
-                     (const double*)w.Bp, (double*)w.dp);
-  // J' = dt^T Bp + dp^T Bt ; K' = sum_Q Bp_Q[:,occ] Bt_Q[occ,:] + Bt_Q[:,occ] Bp_Q[occ,:]
-  gm(s, false, false, 1, n2, naux, 1.0, c.dt, naux, w.Bp, n2, 0.0, w.Jp, n2);
-  gm(s, false, false, 1, n2, naux, 1.0, w.dp, naux, c.Bt, n2, 1.0, w.Jp, n2);
-  gmb(s, false, false, nmo, nmo, o, 1.0, w.Bp, nmo, n2, c.Bt, nmo, n2, 0.0, w.Kp, nmo, 0, naux, true);
-  gmb(s, false, false, nmo, nmo, o, 1.0, c.Bt, nmo, n2, w.Bp, nmo, n2, 1.0, w.Kp, nmo, 0, naux, true);
-  PNO_HIP(hipMemcpyAsync(w.fp, w.hp, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
-  axpby(s, n2, 2.0, w.Jp, 1.0, w.fp);
-  axpby(s, n2, -1.0, w.Kp, 1.0, w.fp);
-  ext(s, o, v, 1, 1, nmo, 1, 0, 0, w.fp + o, w.fp_ov);
-  ext(s, v, v, 1, 1, nmo, 1, 0, 0, w.fp + (int64_t)o * nmo + o, w.fp_vv);
-  ext(s, o, o, 1, 1, nmo, 1, 0, 0, w.fp, w.fp_oo);
-  ext(s, o, v, naux, 1, 1, nmo, n2, 0, w.Bp + (int64_t)o * nmo, w.BvopT);
-  ext(s, o, o, naux, 1, nmo, 1, n2, 0, w.Bp, w.BoopT);
-  ext(s, v, v, naux, 1, nmo, 1, n2, 0, w.Bp + (int64_t)o * nmo + o, w.BvvpT);
+  // ---------------------------------------------------------------- R1: one-index transformed factors, per vector
+  for (int q = 0; q < nb; ++q) {
+    const double* r1q = r1 + q * stride1;
+    fill(s, (int64_t)naux * n2, 0.0, w.Bp);
+    gmb(s, true, false, v, nmo, o, -1.0, r1q, v, 0, c.Bt, nmo, n2, 1.0, w.Bp + (int64_t)o * nmo, nmo, n2, naux);
+    gmb(s, false, true, nmo, o, v, 1.0, c.Bt + o, nmo, n2, r1q, v, 0, 1.0, w.Bp, nmo, n2, naux);
+    fill(s, n2, 0.0, w.hp);
+    gm(s, true, false, v, nmo, o, -1.0, r1q, v, c.hd, nmo, 1.0, w.hp + (int64_t)o * nmo, nmo);
+    gm(s, false, true, nmo, o, v, 1.0, c.hd + o, nmo, r1q, v, 1.0, w.hp, nmo);
+    hipLaunchKernelGGL(trace_occ_kernel, dim3((naux + 255) / 256), dim3(256), 0, s, naux, nmo, o,
+                       (const double*)w.Bp, (double*)w.dp);
+    // J' = dt^T Bp + dp^T Bt ; K' = sum_Q Bp_Q[:,occ] Bt_Q[occ,:] + Bt_Q[:,occ] Bp_Q[occ,:]
+    gm(s, false, false, 1, n2, naux, 1.0, c.dt, naux, w.Bp, n2, 0.0, w.Jp, n2);
+    gm(s, false, false, 1, n2, naux, 1.0, w.dp, naux, c.Bt, n2, 1.0, w.Jp, n2);
+    gmb(s, false, false, nmo, nmo, o, 1.0, w.Bp, nmo, n2, c.Bt, nmo, n2, 0.0, w.Kp, nmo, 0, naux, true);
+    gmb(s, false, false, nmo, nmo, o, 1.0, c.Bt, nmo, n2, w.Bp, nmo, n2, 1.0, w.Kp, nmo, 0, naux, true);
+    PNO_HIP(hipMemcpyAsync(w.fp, w.hp, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    axpby(s, n2, 2.0, w.Jp, 1.0, w.fp);
+    axpby(s, n2, -1.0, w.Kp, 1.0, w.fp);
+    ext(s, o, v, 1, 1, nmo, 1, 0, 0, w.fp + o, w.fp_ov + q * ov);
+    ext(s, v, v, 1, 1, nmo, 1, 0, 0, w.fp + (int64_t)o * nmo + o, w.fp_vv + q * vv);
+    ext(s, o, o, 1, 1, nmo, 1, 0, 0, w.fp, w.fp_oo + q * oo);
+    ext(s, o, v, naux, 1, 1, nmo, n2, 0, w.Bp + (int64_t)o * nmo, w.BvopT + q * ovn);
+    ext(s, o, o, naux, 1, nmo, 1, n2, 0, w.Bp, w.BoopT + q * oon);
+    ext(s, v, v, naux, 1, nmo, 1, n2, 0, w.Bp + (int64_t)o * nmo + o, w.BvvpT + q * vvn);
+    ext(s, o, v, 1, 1, 1, nmo, 0, 0, w.fp + (int64_t)o * nmo, s1 + q * stride1);  // f'_ai
+  }
 
-  // ---------------------------------------------------------------- R2 layouts
-  perm(s, r2, o, o, v, v, 0, 2, 1, 3, w.Ria);
-  perm(s, r2, o, o, v, v, 0, 3, 1, 2, w.Rsia);
-  PNO_HIP(hipMemcpyAsync(w.UiaR, w.Ria, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
-  axpby(s, oovv, -1.0, w.Rsia, 2.0, w.UiaR);
-  perm(s, r2, o, o, v, v, 0, 1, 3, 2, w.UR, -1.0, 0.0);
-  axpby(s, oovv, 2.0, r2, 1.0, w.UR);
-  perm(s, w.UR, o, o, v, v, 0, 1, 3, 2, w.URp);
-  perm(s, w.UR, o, o, v, v, 2, 0, 1, 3, w.Ubr);
+  // ---------------------------------------------------------------- R2 layouts, [nb][...]
+  const double* R2 = r2;
+  if (stride2 != oovv) {
+    Perm4 p;
+    p.d[0] = nb; p.d[1] = 1; p.d[2] = 1; p.d[3] = oovv;
+    p.is[0] = stride2; p.is[1] = 0; p.is[2] = 0; p.is[3] = 1;
+    p.os[0] = oovv; p.os[1] = 0; p.os[2] = 0; p.os[3] = 1;
+    permute4(s, p, 1.0, r2, 0.0, w.R2c);
+    R2 = w.R2c;
+  }
+  const int64_t nbo = (int64_t)nb * o;
+  perm(s, R2, nbo, o, v, v, 0, 2, 1, 3, w.Ria);
+  perm(s, R2, nbo, o, v, v, 0, 3, 1, 2, w.Rsia);
+  PNO_HIP(hipMemcpyAsync(w.UiaR, w.Ria, nb * oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  axpby(s, nb * oovv, -1.0, w.Rsia, 2.0, w.UiaR);
+  perm(s, R2, nbo, o, v, v, 0, 1, 3, 2, w.UR, -1.0, 0.0);
+  axpby(s, nb * oovv, 2.0, R2, 1.0, w.UR);
+  perm(s, w.UR, nbo, o, v, v, 0, 1, 3, 2, w.URp);
+  {
+    const int64_t dims[4] = {o, o, v, v};
+    const int pp[4] = {2, 0, 1, 3};
+    permute_c(s, dims, pp, 1.0, w.UR, 0.0, w.Ubr, nb);
+  }
 
   // ---------------------------------------------------------------- sigma1
-  ext(s, o, v, 1, 1, 1, nmo, 0, 0, w.fp + (int64_t)o * nmo, s1);        // f'_ai
-  gm(s, false, false, ov, 1, ov, 1.0, c.UiaT, ov, w.fp_ov, 1, 1.0, s1, 1);
-  gm(s, true, false, o, v, o, -1.0, c.Fqoo, o, r1, v, 1.0, s1, v);
-  gm(s, false, true, o, v, v, 1.0, r1, v, c.Fqvv, v, 1.0, s1, v);
-  gm(s, false, false, ov, 1, ov, 1.0, w.UiaR, ov, c.fd_ov, 1, 1.0, s1, 1);
-  gm(s, false, false, ov, naux, ov, 1.0, w.UiaR, ov, c.BovT, naux, 0.0, w.M1, naux);
-  gm(s, false, false, o, v, (int64_t)v * naux, 1.0, w.M1, (int64_t)v * naux, c.Bvv2, v, 1.0, s1, v);
-  gm(s, false, false, o, v, oo * v, -1.0, c.OOOVp, oo * v, w.URp, v, 1.0, s1, v);
+  gmb(s, false, false, ov, 1, ov, 1.0, c.UiaT, ov, 0, w.fp_ov, 1, ov, 1.0, s1, 1, stride1, nb);
+  gmb(s, true, false, o, v, o, -1.0, c.Fqoo, o, 0, r1, v, stride1, 1.0, s1, v, stride1, nb);
+  gmb(s, false, true, o, v, v, 1.0, r1, v, stride1, c.Fqvv, v, 0, 1.0, s1, v, stride1, nb);
+  gmb(s, false, false, ov, 1, ov, 1.0, w.UiaR, ov, oovv, c.fd_ov, 1, 0, 1.0, s1, 1, stride1, nb);
+  gmb(s, false, false, ov, naux, ov, 1.0, w.UiaR, ov, oovv, c.BovT, naux, 0, 0.0, w.M1, naux, ovn, nb);
+  gmb(s, false, false, o, v, (int64_t)v * naux, 1.0, w.M1, (int64_t)v * naux, ovn, c.Bvv2, v, 0, 1.0, s1, v,
+      stride1, nb);
+  gmb(s, false, false, o, v, oo * v, -1.0, c.OOOVp, oo * v, 0, w.URp, v, oovv, 1.0, s1, v, stride1, nb);
 
   // ---------------------------------------------------------------- sigma2, direct (not P-symmetrised)
-  gm(s, false, false, oo, vv, oo, 1.0, c.Wh, oo, r2, vv, 1.0, Sd, vv);
-  gm(s, false, true, oo, oo, vv, 1.0, r2, vv, c.g2, vv, 0.0, w.Xh, oo);
-  gm(s, false, true, oo, oo, naux, 1.0, w.BoopT, naux, c.BooT, naux, 0.0, w.O4p, oo);
-  gm(s, false, true, oo, oo, naux, 1.0, c.BooT, naux, w.BoopT, naux, 1.0, w.O4p, oo);
-  perm(s, w.O4p, o, o, o, o, 1, 3, 0, 2, w.Xh, 1.0, 1.0);
-  gm(s, false, false, oo, vv, oo, 1.0, w.Xh, oo, c.T, vv, 1.0, Sd, vv);
+  gmb(s, false, false, oo, vv, oo, 1.0, c.Wh, oo, 0, R2, vv, oovv, 1.0, Sd, vv, oovv, nb);
+  gmb(s, false, true, oo, oo, vv, 1.0, R2, vv, oovv, c.g2, vv, 0, 0.0, w.Xh, oo, o4, nb);
+  gmb(s, false, true, oo, oo, naux, 1.0, w.BoopT, naux, oon, c.BooT, naux, 0, 0.0, w.O4p, oo, o4, nb);
+  gmb(s, false, true, oo, oo, naux, 1.0, c.BooT, naux, 0, w.BoopT, naux, oon, 1.0, w.O4p, oo, o4, nb);
+  {
+    const int64_t dims[4] = {o, o, o, o};
+    const int pp[4] = {1, 3, 0, 2};
+    permute_c(s, dims, pp, 1.0, w.O4p, 1.0, w.Xh, nb);
+  }
+  gmb(s, false, false, oo, vv, oo, 1.0, w.Xh, oo, o4, c.T, vv, 0, 1.0, Sd, vv, oovv, nb);
 
   // ---------------------------------------------------------------- ring terms in [(i,a),(j,b)] form
-  gm(s, false, true, ov, ov, naux, 0.5, w.BvopT, naux, c.BvoT, naux, 0.0, w.Ziajb, ov);
-  gm(s, false, true, ov, ov, naux, 0.5, c.BvoT, naux, w.BvopT, naux, 1.0, w.Ziajb, ov);
+  gmb(s, false, true, ov, ov, naux, 0.5, w.BvopT, naux, ovn, c.BvoT, naux, 0, 0.0, w.Ziajb, ov, oovv, nb);
+  gmb(s, false, true, ov, ov, naux, 0.5, c.BvoT, naux, 0, w.BvopT, naux, ovn, 1.0, w.Ziajb, ov, oovv, nb);
   // R-side intermediates D(R) and X(R)
-  gm(s, false, true, ov, ov, naux, 0.5, c.BovT, naux, w.M1, naux, 0.0, w.Dtot, ov);  // (1/2) G U(R)^T
-  gm(s, false, true, ov, ov, ov, -0.5, c.GX, ov, w.Ria, ov, 1.0, w.Dtot, ov);
-  gm(s, false, true, ov, ov, naux, 1.0, c.BovT, naux, w.BvopT, naux, 1.0, w.Dtot, ov);
-  gm(s, false, true, ov, ov, ov, -0.5, c.GX, ov, w.Rsia, ov, 0.0, w.Xtot, ov);
-  gm(s, false, true, oo, vv, naux, 1.0, w.BoopT, naux, c.BvvT, naux, 0.0, w.OOVVp, vv);
-  gm(s, false, true, oo, vv, naux, 1.0, c.BooT, naux, w.BvvpT, naux, 1.0, w.OOVVp, vv);
-  perm(s, w.OOVVp, o, o, v, v, 0, 3, 1, 2, w.Xtot, 1.0, 1.0);
-  PNO_HIP(hipMemcpyAsync(w.DXtot, w.Xtot, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
-  axpby(s, oovv, 2.0, w.Dtot, -1.0, w.DXtot);
+  gmb(s, false, true, ov, ov, naux, 0.5, c.BovT, naux, 0, w.M1, naux, ovn, 0.0, w.Dtot, ov, oovv, nb);
+  gmb(s, false, true, ov, ov, naux, 1.0, c.BovT, naux, 0, w.BvopT, naux, ovn, 1.0, w.Dtot, ov, oovv, nb);
+  gmb(s, false, true, oo, vv, naux, 1.0, w.BoopT, naux, oon, c.BvvT, naux, 0, 0.0, w.OOVVp, vv, oovv, nb);
+  gmb(s, false, true, oo, vv, naux, 1.0, c.BooT, naux, 0, w.BvvpT, naux, vvn, 1.0, w.OOVVp, vv, oovv, nb);
+  perm(s, w.OOVVp, nbo, o, v, v, 0, 3, 1, 2, w.Xtot, 1.0, 0.0);
   if (f32) {
     float* fa = w.fa;
     float* fb = w.fb;
-    to_float(s, oovv, w.Ria, fa);
-    gmf(s, false, false, ov, ov, ov, 1.0, fa, ov, c.DX2f, ov, 1.0, w.Ziajb, ov, w.fc);
-    to_float(s, oovv, w.Rsia, fa);
-    gmf(s, false, false, ov, ov, ov, -1.0, fa, ov, c.Drf, ov, 1.0, w.Ziajb, ov, w.fc);
-    gmf(s, false, false, ov, ov, ov, -1.0, fa, ov, c.Xrf, ov, 0.0, w.Z3, ov, w.fc);
-    to_float(s, oovv, w.DXtot, fb);
-    gmf(s, false, false, ov, ov, ov, 1.0, c.Tiaf, ov, fb, ov, 1.0, w.Ziajb, ov, w.fc);
-    to_float(s, oovv, w.Dtot, fb);
-    gmf(s, false, false, ov, ov, ov, -1.0, c.Tsiaf, ov, fb, ov, 1.0, w.Ziajb, ov, w.fc);
-    to_float(s, oovv, w.Xtot, fb);
-    gmf(s, false, false, ov, ov, ov, -1.0, c.Tsiaf, ov, fb, ov, 1.0, w.Z3, ov, w.fc);
+    float* fc = w.fc;
+    const int64_t nt = nb * oovv;
+    to_float(s, nt, w.Ria, fa);
+    gmbf(s, false, true, ov, ov, ov, -0.5, c.GXf, ov, 0, fa, ov, oovv, 1.0, w.Dtot, nb, fc);
+    gmbf(s, false, false, ov, ov, ov, 1.0, fa, ov, oovv, c.DX2f, ov, 0, 1.0, w.Ziajb, nb, fc);
+    to_float(s, nt, w.Rsia, fa);
+    gmbf(s, false, true, ov, ov, ov, -0.5, c.GXf, ov, 0, fa, ov, oovv, 1.0, w.Xtot, nb, fc);
+    gmbf(s, false, false, ov, ov, ov, -1.0, fa, ov, oovv, c.Drf, ov, 0, 1.0, w.Ziajb, nb, fc);
+    gmbf(s, false, false, ov, ov, ov, -1.0, fa, ov, oovv, c.Xrf, ov, 0, 0.0, w.Z3, nb, fc);
+    PNO_HIP(hipMemcpyAsync(w.DXtot, w.Xtot, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
+    axpby(s, nt, 2.0, w.Dtot, -1.0, w.DXtot);
+    to_float(s, nt, w.DXtot, fb);
+    gmbf(s, false, false, ov, ov, ov, 1.0, c.Tiaf, ov, 0, fb, ov, oovv, 1.0, w.Ziajb, nb, fc);
+    to_float(s, nt, w.Dtot, fb);
+    gmbf(s, false, false, ov, ov, ov, -1.0, c.Tsiaf, ov, 0, fb, ov, oovv, 1.0, w.Ziajb, nb, fc);
+    to_float(s, nt, w.Xtot, fb);
+    gmbf(s, false, false, ov, ov, ov, -1.0, c.Tsiaf, ov, 0, fb, ov, oovv, 1.0, w.Z3, nb, fc);
   } else {
-    gm(s, false, false, ov, ov, ov, 1.0, w.Ria, ov, c.DX2, ov, 1.0, w.Ziajb, ov);
-    gm(s, false, false, ov, ov, ov, -1.0, w.Rsia, ov, c.Dr, ov, 1.0, w.Ziajb, ov);
-    gm(s, false, false, ov, ov, ov, -1.0, w.Rsia, ov, c.Xr, ov, 0.0, w.Z3, ov);
-    gm(s, false, false, ov, ov, ov, 1.0, c.Tia, ov, w.DXtot, ov, 1.0, w.Ziajb, ov);
-    gm(s, false, false, ov, ov, ov, -1.0, c.Tsia, ov, w.Dtot, ov, 1.0, w.Ziajb, ov);
-    gm(s, false, false, ov, ov, ov, -1.0, c.Tsia, ov, w.Xtot, ov, 1.0, w.Z3, ov);
+    gmb(s, false, true, ov, ov, ov, -0.5, c.GX, ov, 0, w.Ria, ov, oovv, 1.0, w.Dtot, ov, oovv, nb);
+    gmb(s, false, true, ov, ov, ov, -0.5, c.GX, ov, 0, w.Rsia, ov, oovv, 1.0, w.Xtot, ov, oovv, nb);
+    PNO_HIP(hipMemcpyAsync(w.DXtot, w.Xtot, nb * oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    axpby(s, nb * oovv, 2.0, w.Dtot, -1.0, w.DXtot);
+    gmb(s, false, false, ov, ov, ov, 1.0, w.Ria, ov, oovv, c.DX2, ov, 0, 1.0, w.Ziajb, ov, oovv, nb);
+    gmb(s, false, false, ov, ov, ov, -1.0, w.Rsia, ov, oovv, c.Dr, ov, 0, 1.0, w.Ziajb, ov, oovv, nb);
+    gmb(s, false, false, ov, ov, ov, -1.0, w.Rsia, ov, oovv, c.Xr, ov, 0, 0.0, w.Z3, ov, oovv, nb);
+    gmb(s, false, false, ov, ov, ov, 1.0, c.Tia, ov, 0, w.DXtot, ov, oovv, 1.0, w.Ziajb, ov, oovv, nb);
+    gmb(s, false, false, ov, ov, ov, -1.0, c.Tsia, ov, 0, w.Dtot, ov, oovv, 1.0, w.Ziajb, ov, oovv, nb);
+    gmb(s, false, false, ov, ov, ov, -1.0, c.Tsia, ov, 0, w.Xtot, ov, oovv, 1.0, w.Z3, ov, oovv, nb);
   }
 
   // ---------------------------------------------------------------- Fock-type terms in [i][j][a][b]
-  gm(s, false, true, oo * v, v, v, 1.0, r2, v, c.Fvv, v, 0.0, w.Zp, v);
-  gmb(s, true, false, o, vv, o, -1.0, c.Foo, o, 0, r2, vv, o * vv, 1.0, w.Zp, vv, o * vv, o);
-  gm(s, false, false, v, v, oo * v, -1.0, w.Ubr, oo * v, c.Gq, v, 0.0, w.Ftv, v);
-  axpby(s, vv, 1.0, w.fp_vv, 1.0, w.Ftv);
-  gm(s, false, true, o, o, ov * v, 1.0, c.g2, ov * v, w.UR, ov * v, 0.0, w.Fto, o);
-  axpby(s, oo, 1.0, w.fp_oo, 1.0, w.Fto);
-  gm(s, false, true, oo * v, v, v, 1.0, c.T, v, w.Ftv, v, 1.0, w.Zp, v);
-  gmb(s, true, false, o, vv, o, -1.0, w.Fto, o, 0, c.T, vv, o * vv, 1.0, w.Zp, vv, o * vv, o);
+  gm(s, false, true, (int64_t)nb * oo * v, v, v, 1.0, R2, v, c.Fvv, v, 0.0, w.Zp, v);
+  gmb(s, true, false, o, vv, o, -1.0, c.Foo, o, 0, R2, vv, o * vv, 1.0, w.Zp, vv, o * vv, nbo);
+  gmb(s, false, false, v, v, oo * v, -1.0, w.Ubr, oo * v, oovv, c.Gq, v, 0, 0.0, w.Ftv, v, vv, nb);
+  axpby(s, nb * vv, 1.0, w.fp_vv, 1.0, w.Ftv);
+  gmb(s, false, true, o, o, ov * v, 1.0, c.g2, ov * v, 0, w.UR, ov * v, oovv, 0.0, w.Fto, o, oo, nb);
+  axpby(s, nb * oo, 1.0, w.fp_oo, 1.0, w.Fto);
+  gmb(s, false, true, oo * v, v, v, 1.0, c.T, v, 0, w.Ftv, v, vv, 1.0, w.Zp, v, oovv, nb);
+  for (int q = 0; q < nb; ++q)
+    gmb(s, true, false, o, vv, o, -1.0, w.Fto + q * oo, o, 0, c.T, vv, o * vv, 1.0, w.Zp + q * oovv, vv, o * vv, o);
   // -P[ sum_k r_k^a Wvo_kbij ] collected as Cba[i][j][b][a] = sum_k Wvo2[(ijb)][k] r1[k][a]
-  gm(s, false, false, oo * v, v, o, 1.0, c.Wvo2, o, r1, v, 0.0, w.Cba, v);
+  gmb(s, false, false, oo * v, v, o, 1.0, c.Wvo2, o, 0, r1, v, stride1, 0.0, w.Cba, v, oovv, nb);
 
-  hipLaunchKernelGGL(assemble_s2_kernel, dim3(grid1(oovv)), dim3(256), 0, s, o, v, (const double*)Sd,
-                     (const double*)w.Zp, (const double*)w.Ziajb, (const double*)w.Z3, (const double*)w.Cba, s2);
+  const int64_t tot = nb * oovv;
+  hipLaunchKernelGGL(assemble_s2_block_kernel, dim3(grid1(tot)), dim3(256), 0, s, o, v, nb, (const double*)Sd,
+                     (const double*)w.Zp, (const double*)w.Ziajb, (const double*)w.Z3, (const double*)w.Cba, s2,
+                     stride2);
   PNO_HIP(hipGetLastError());
 }
 }  // namespace
@@ -616,16 +699,12 @@ void sigma_block(Context& c, int nvec, const double* r1, const double* r2, doubl
   PNO_CHECK(f32 ? (c.Wpf.p != nullptr) : (c.Wp.p != nullptr), PNOEOM_EINVAL,
             "sigma: the contraction precision must match the one given to build_df");
   if (nvec <= 0) return;
-  alloc_sigma_work(c, precision);
   SigmaWork& w = c.sw;
   hipStream_t s = c.stream;
   const int o = c.o, v = c.v;
   const int64_t oovv = c.oovv();
   const int64_t npair = (int64_t)o * (o + 1) / 2, vp = (int64_t)v * (v + 1) / 2, vm = (int64_t)v * (v - 1) / 2;
   const int64_t rows = (int64_t)nvec * npair;
-  auto grow = [](auto& buf, int64_t n) {
-    if ((int64_t)buf.n < n) buf.alloc(n);
-  };
   grow(w.LadAll, (int64_t)nvec * oovv);
   const int64_t tot = (int64_t)nvec * oovv;
   // ---------------------------------------------------------------- particle ladder, all vectors at once
@@ -674,10 +753,13 @@ void sigma_block(Context& c, int nvec, const double* r1, const double* r2, doubl
     hipLaunchKernelGGL((ladder_unpack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec,
                        (const double*)w.SigP, (const double*)w.SigM, (double*)w.LadAll, oovv);
   PNO_HIP(hipGetLastError());
-  // ---------------------------------------------------------------- everything else, per vector
-  for (int q = 0; q < nvec; ++q)
-    sigma_rest(c, r1 + q * stride1, r2 + q * stride2, s1 + q * stride1, s2 + q * stride2, precision,
-               w.LadAll + (int64_t)q * oovv);
+  // ---------------------------------------------------------------- everything else, in chunks of vectors
+  const int nb = rest_chunk(c, nvec, f32);
+  for (int q0 = 0; q0 < nvec; q0 += nb) {
+    const int n = std::min(nb, nvec - q0);
+    sigma_rest_block(c, n, r1 + q0 * stride1, stride1, r2 + q0 * stride2, stride2, s1 + q0 * stride1,
+                     s2 + q0 * stride2, precision, w.LadAll + (int64_t)q0 * oovv);
+  }
 }
 
 void sigma_canonical(Context& c, const double* r1, const double* r2, double* s1, double* s2, int precision) {
