@@ -93,6 +93,98 @@ unsigned g1(int64_t n) {
   return (unsigned)b;
 }
 
+// Skinny inner products out[i][j] = sum_n A[i][n] B[j][n] for at most 64 rows of A
+// and 16 rows of B over a long n (the Davidson vectors).  The sum over n is
+// order-free, so a wave feeds each FP64 MFMA 16x16x4 with four k-indices of its
+// own choosing: in a unit of 16 consecutive n, lane l (row l%16, group g = l/16)
+// supplies n = base + 4 s + g at step s, which makes every load instruction read
+// 32 contiguous bytes per row.  Each wave accumulates the whole 64 x 16 block over
+// a strided set of units; the four waves of a workgroup are summed through LDS
+// and each workgroup writes one partial block, reduced afterwards in a fixed
+// order.  The kernel is bound by HBM reads of A and B.
+constexpr int kDotWaves = 4;
+constexpr int kDotGroups = 512;
+
+__global__ __launch_bounds__(64 * kDotWaves) void dots_kernel(int na, int nb, int64_t N, const double* __restrict__ A,
+                                                              int64_t lda, const double* __restrict__ B, int64_t ldb,
+                                                              double* __restrict__ part) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __shared__ double red[kDotWaves][64][17];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int nblk = (na + 15) >> 4;
+  v4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = v4{0, 0, 0, 0};
+  // row pointers; rows past the end read row 0 and contribute zeros
+  const double* pa[4];
+  bool ma[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = q * 16 + r;
+    pa[q] = A + (row < na ? (int64_t)row * lda : 0) + g;
+    ma[q] = row < na;
+  }
+  const double* pb = B + (r < nb ? (int64_t)r * ldb : 0) + g;
+  const bool mb = r < nb;
+  const int64_t units = N / 16;
+  const int64_t stride = (int64_t)gridDim.x * kDotWaves;
+  for (int64_t u = (int64_t)blockIdx.x * kDotWaves + wave; u < units; u += stride) {
+    const int64_t base = u * 16;
+    double bv[4], av[4][4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const double x = pb[base + 4 * st];
+      bv[st] = mb ? x : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < nblk) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const double x = pa[q][base + 4 * st];
+          av[q][st] = ma[q] ? x : 0.0;
+        }
+      }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nblk) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q][st], bv[st], acc[q], 0, 0, 0);
+  }
+  // tail n in [16 units, N): one wave of the first workgroup, zero-padded
+  if (blockIdx.x == 0 && wave == 0 && units * 16 < N) {
+    const int64_t base = units * 16;
+    double bv[4], av[4][4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int64_t n = base + 4 * st + g;
+      bv[st] = (n < N && mb) ? pb[base + 4 * st] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) av[q][st] = (n < N && q < nblk && ma[q]) ? pa[q][base + 4 * st] : 0.0;
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nblk) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q][st], bv[st], acc[q], 0, 0, 0);
+  }
+  // accumulator r4 of lane l holds row 16 q + l/16 + 4 r4, column l%16
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) red[wave][q * 16 + g + 4 * r4][r] = acc[q][r4];
+  __syncthreads();
+  double* out = part + (int64_t)blockIdx.x * na * nb;
+  for (int e = threadIdx.x; e < na * nb; e += 64 * kDotWaves) {
+    const int i = e / nb, j = e % nb;
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kDotWaves; ++w) sum += red[w][i][j];
+    out[e] = sum;
+  }
+}
+
 struct Dots {
   DBuf<double> part, out;
 };
@@ -100,35 +192,32 @@ struct Dots {
 // host out[i][j] = sum_n A[i][n] B[j][n]   (A: na rows, B: nb rows, row stride N)
 void dots(hipStream_t s, Dots& w, const double* A, int na, const double* B, int nb, int64_t N, double* host) {
   if (na == 0 || nb == 0) return;
-  int64_t chunk = (N + 511) / 512;
-  chunk = ((chunk + 63) / 64) * 64;
-  if (chunk < 64) chunk = 64;
-  const int64_t nfull = N / chunk;
-  const int64_t tail = N - nfull * chunk;
-  const int64_t nparts = nfull + (tail ? 1 : 0);
   const int64_t nout = (int64_t)na * nb;
-  w.part.alloc(std::max<int64_t>(nparts * nout, w.part.n));
-  w.out.alloc(std::max<int64_t>(nout, w.out.n));
-  if (nfull) {
-    GemmDesc<double> d;
-    d.ta = false; d.tb = true; d.M = na; d.N = nb; d.K = chunk;
-    d.A = A; d.lda = N; d.sA = chunk;
-    d.B = B; d.ldb = N; d.sB = chunk;
-    d.C = w.part; d.ldc = nb; d.sC = nout; d.batch = nfull;
-    gemm(d, s);
-  }
-  if (tail) {
-    GemmDesc<double> d;
-    d.ta = false; d.tb = true; d.M = na; d.N = nb; d.K = tail;
-    d.A = A + nfull * chunk; d.lda = N;
-    d.B = B + nfull * chunk; d.ldb = N;
-    d.C = w.part + nfull * nout; d.ldc = nb;
-    gemm(d, s);
-  }
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((nout + 255) / 256), dim3(256), 0, s, nout, nparts,
-                     (const double*)w.part, (double*)w.out);
-  PNO_HIP(hipGetLastError());
-  PNO_HIP(hipMemcpyAsync(host, w.out, nout * sizeof(double), hipMemcpyDeviceToHost, s));
+  int64_t groups = std::min<int64_t>(kDotGroups, std::max<int64_t>(1, (N / 16 + kDotWaves - 1) / kDotWaves));
+  if ((int64_t)w.part.n < groups * nout) w.part.alloc(groups * nout);
+  if ((int64_t)w.out.n < nout) w.out.alloc(nout);
+  std::vector<double> blk;
+  // blocks of at most 64 x 16 outputs
+  for (int i0 = 0; i0 < na; i0 += 64)
+    for (int j0 = 0; j0 < nb; j0 += 16) {
+      const int ni = std::min(64, na - i0), nj = std::min(16, nb - j0);
+      hipLaunchKernelGGL(dots_kernel, dim3((unsigned)groups), dim3(64 * kDotWaves), 0, s, ni, nj, N,
+                         A + (int64_t)i0 * N, N, B + (int64_t)j0 * N, N, (double*)w.part);
+      PNO_HIP(hipGetLastError());
+      const int64_t nsub = (int64_t)ni * nj;
+      hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((nsub + 255) / 256)), dim3(256), 0, s, nsub, groups,
+                         (const double*)w.part, (double*)w.out);
+      PNO_HIP(hipGetLastError());
+      if (ni == na && nj == nb) {
+        PNO_HIP(hipMemcpyAsync(host, w.out, nout * sizeof(double), hipMemcpyDeviceToHost, s));
+      } else {
+        blk.resize(nsub);
+        PNO_HIP(hipMemcpyAsync(blk.data(), w.out, nsub * sizeof(double), hipMemcpyDeviceToHost, s));
+        PNO_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < ni; ++i)
+          for (int j = 0; j < nj; ++j) host[(int64_t)(i0 + i) * nb + j0 + j] = blk[(int64_t)i * nj + j];
+      }
+    }
   PNO_HIP(hipStreamSynchronize(s));
 }
 
