@@ -24,13 +24,22 @@ __device__ __forceinline__ double clampd(double d) {
   return d;
 }
 
-__global__ void reduce_partials_kernel(int64_t nout, int64_t nparts, const double* __restrict__ part,
-                                       double* __restrict__ out) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= nout) return;
+// out[e] = sum_b part[b][e]: one workgroup per output, a fixed summation tree
+// (bitwise reproducible for a given nparts)
+__global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t nout, int64_t nparts,
+                                                              const double* __restrict__ part,
+                                                              double* __restrict__ out) {
+  __shared__ double red[256];
+  const int64_t e = blockIdx.x;
   double acc = 0.0;
-  for (int64_t b = 0; b < nparts; ++b) acc += part[b * nout + e];
-  out[e] = acc;
+  for (int64_t b = threadIdx.x; b < nparts; b += 256) acc += part[b * nout + e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[e] = red[0];
 }
 
 // R[k][n] -= theta[k] * X[k][n]
@@ -205,7 +214,7 @@ void dots(hipStream_t s, Dots& w, const double* A, int na, const double* B, int 
                          A + (int64_t)i0 * N, N, B + (int64_t)j0 * N, N, (double*)w.part);
       PNO_HIP(hipGetLastError());
       const int64_t nsub = (int64_t)ni * nj;
-      hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((nsub + 255) / 256)), dim3(256), 0, s, nsub, groups,
+      hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)nsub), dim3(256), 0, s, nsub, groups,
                          (const double*)w.part, (double*)w.out);
       PNO_HIP(hipGetLastError());
       if (ni == na && nj == nb) {

@@ -1,11 +1,12 @@
 """Write the stored reference values under tests/golden/ (calls only oracle/ and synthgen).
 
-    python tests/golden/make_golden.py c1 c1_pno pno_small c2
+    python tests/golden/make_golden.py c1 c1_pno pno_small c2 c2_sigma
 
 Each section writes <section>.json with the excitation energies of the FP64
 oracle (Davidson at tol_e = 1e-11, and for config 1 also the dense eigenvalues
 of H-bar on the singlet space), plus the setup numbers (E_ref, E_MP2, CIS
-energies, PNO counts) that the GPU tests compare against.
+energies, PNO counts) that the GPU tests compare against.  Section c2_sigma
+stores seeded samples of one oracle sigma vector at the full config-2 size.
 """
 import json
 import os
@@ -95,6 +96,25 @@ def sec_c2():
     out["davidson_resnorm"] = res["resnorm"].tolist()
     out["davidson_iters"] = res["iters"]
     out["davidson_seconds"] = time.time() - t0
+    return out
+
+
+def sec_c2_sigma():
+    """sigma of one seeded trial vector at config 2, sampled at seeded positions."""
+    from synthgen import random_r
+    s, so, out = _setup(2)
+    o, v = s.o, s.v
+    seed_r = 2024
+    r1, r2 = random_r(o, v, seed_r, nvec=1)
+    t0 = time.time()
+    s1, s2 = so.sigma(r1[0], r2[0])
+    out["sigma_seconds"] = time.time() - t0
+    rng = np.random.default_rng(77)
+    i1 = rng.choice(s1.size, size=300, replace=False)
+    i2 = rng.choice(s2.size, size=3000, replace=False)
+    out.update(seed_r=seed_r, idx1=i1.tolist(), val1=s1.ravel()[i1].tolist(), idx2=i2.tolist(),
+               val2=s2.ravel()[i2].tolist(), norm1=float(np.linalg.norm(s1)), norm2=float(np.linalg.norm(s2)),
+               max1=float(np.max(np.abs(s1))), max2=float(np.max(np.abs(s2))))
     return out
 
 

@@ -115,3 +115,26 @@ def test_davidson_c1_fp32_mixed():
     ctx = _ctx(s, precision=1)
     r = ctx.davidson(3, precision=1, tol_e=1e-8, tol_r=1e-6)
     assert np.max(np.abs(r["omega"] - np.array(gold["dense_eig"][:3]))) <= 1e-6
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-11), (1, 5e-5)])
+def test_sigma_config2_full_size_sampled(precision, tol):
+    """Full config-2 size (o=20, v=150, naux=450), the launch shapes bench.py times:
+    one seeded trial vector, compared at 3300 seeded positions (and in norm) with
+    the oracle's sigma stored by tests/golden/make_golden.py."""
+    path = os.path.join(GOLD, "c2_sigma.json")
+    if not os.path.exists(path):
+        pytest.skip("config-2 sigma samples not generated")
+    print(f"[sigma c2 sampled] precision={precision}", flush=True)
+    torch = _torch()
+    g = json.load(open(path))
+    s = config_system(2)
+    ctx = _ctx(s, precision=precision)
+    r1, r2 = random_r(s.o, s.v, g["seed_r"], nvec=1)
+    g1, g2 = ctx.sigma(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda(), precision=precision)
+    g1, g2 = g1[0].cpu().numpy().ravel(), g2[0].cpu().numpy().ravel()
+    v1, v2 = np.array(g["val1"]), np.array(g["val2"])
+    assert np.max(np.abs(g1[g["idx1"]] - v1)) <= tol * g["max1"]
+    assert np.max(np.abs(g2[g["idx2"]] - v2)) <= tol * g["max2"]
+    assert abs(np.linalg.norm(g1) - g["norm1"]) <= tol * g["norm1"]
+    assert abs(np.linalg.norm(g2) - g["norm2"]) <= tol * g["norm2"]
