@@ -10,8 +10,9 @@ HBM before the timed region.
 
 Printed: one JSON line with sigma-evaluations/s (the headline value), time to
 convergence, the live roofline of the dominant kernel (the ladder contraction),
-the FP32-MFMA mixed variant with its per-root error, and the FP64 oracle timed
-on the host cores for a bounded sample.
+the FP32-MFMA and BF16-ladder mixed variants (each finished by FP64 refinement)
+with their differences from the FP64 roots, and the FP64 oracle timed on the host
+cores for a bounded sample.
 """
 from __future__ import annotations
 
@@ -26,7 +27,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6, "fp32": 157.3}    # MI355X dense matrix TFLOP/s
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}    # MI355X dense matrix TFLOP/s
 HBM_PEAK = 8000.0                       # GB/s
 
 
@@ -84,7 +85,7 @@ def main():
 
     import torch
     from synthgen import config_system, CONFIGS
-    from paper_1802_06738_amd import PnoEom, FP64, FP32
+    from paper_1802_06738_amd import PnoEom, FP64, FP32, BF16
 
     cfg = CONFIGS[args.config]
     s = config_system(args.config)
@@ -120,7 +121,7 @@ def main():
     avg_ms = lad_ms / max(lad_n, 1)
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
     out = {
-        "metric": "sigma evals/s & Davidson time-to-convergence (canonical FP64; FP32-MFMA mixed variant)",
+        "metric": "sigma evals/s & Davidson time-to-convergence (canonical FP64; FP32 and BF16 mixed variants)",
         "value": nsig / dt64,
         "unit": "sigma-evals/s",
         "n_gpus": 1,
@@ -155,19 +156,24 @@ def main():
         if ref.size == nroots:
             out["max_abs_err_vs_oracle_eh"] = float(np.max(np.abs(omega64 - ref)))
     if not args.no_mixed:
-        res32, dt32 = measure(FP32)
-        om32 = res32[-1]["omega"]
-        l32 = sum(r["timing"]["ladder_ms"] for r in res32)
-        n32 = sum(r["timing"]["ladder_launches"] for r in res32)
-        f32fl = sum(r["timing"]["ladder_flops"] for r in res32)
-        out["mixed_fp32"] = {
-            "time_to_convergence_s": dt32 / args.steps,
-            "sigma_evals_per_s": sum(r["nsigma"] for r in res32) / dt32,
-            "max_abs_diff_vs_fp64_eh": float(np.max(np.abs(om32 - omega64))),
-            "ladder_avg_launch_ms_fp32": l32 / max(n32, 1) if n32 else None,
-            "ladder_tflops_fp32": (f32fl / (l32 * 1e-3) / 1e12) if l32 else None,
-            "note": "FP32-MFMA sigma until convergence, then FP64 sigma refinement from the FP32 roots",
-        }
+        for prec, name in ((FP32, "fp32"), (BF16, "bf16")):
+            resm, dtm = measure(prec)
+            om = resm[-1]["omega"]
+            lm = sum(r["timing"][name]["ladder_ms"] for r in resm)
+            nm = sum(r["timing"][name]["ladder_launches"] for r in resm)
+            flm = sum(r["timing"][name]["ladder_flops"] for r in resm)
+            tf = (flm / (lm * 1e-3) / 1e12) if lm else None
+            out["mixed_" + name] = {
+                "time_to_convergence_s": dtm / args.steps,
+                "speedup_vs_fp64": dt64 / dtm,
+                "sigma_evals_per_s": sum(r["nsigma"] for r in resm) / dtm,
+                "max_abs_diff_vs_fp64_eh": float(np.max(np.abs(om - omega64))),
+                "ladder_avg_launch_ms": lm / max(nm, 1) if nm else None,
+                "ladder_tflops": tf,
+                "ladder_frac_of_peak": (tf / PEAK[name]) if tf else None,
+                "note": (("FP32-MFMA" if name == "fp32" else "bfloat16-MFMA ladder (FP32 accumulation), FP32 other")
+                         + " contractions until convergence, then FP64 sigma refinement from those roots"),
+            }
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.config)

@@ -74,8 +74,11 @@ const char* pnoeom_last_error(const pnoeom_ctx* ctx);
  *   eps  : device [nmo], orbital energies; the Fock matrix is diag(eps)
  *   t1   : device [o][v] or NULL (T1 = 0)
  *   t2   : device [o][o][v][v] or NULL (first-order amplitudes (ia|jb)/(e_i+e_j-e_a-e_b))
- *   precision : PNOEOM_FP64 or PNOEOM_FP32 (precision of the large contractions
- *               used by later sigma calls; FP64 copies are always kept)
+ *   precision : PNOEOM_FP64, PNOEOM_FP32 or PNOEOM_BF16 (precision of the large
+ *               contractions used by later sigma calls; FP64 copies are always kept).
+ *               BF16: the particle ladder runs on bfloat16 operands (W+/- and the
+ *               packed trial amplitudes, rounded to nearest even) with FP32
+ *               accumulation; the other large contractions run in FP32.
  * Errors: EINVAL (null B/eps, bad precision), ENOMEM, EHIP. */
 int pnoeom_build_df(pnoeom_ctx* ctx, const double* B, const double* eps, const double* t1,
                     const double* t2, int precision);
@@ -122,19 +125,20 @@ int pnoeom_pno_transform(pnoeom_ctx* ctx, int nvec, int direction, double* r1, d
  *           s1, s2 the same shapes (outputs).
  *   space = PNOEOM_PNO: r1 = device [nvec][len] PNO-space vectors (r2 ignored, may be
  *           NULL); s1 = device [nvec][len] receives P sigma in the same layout.
- *   precision : PNOEOM_FP64 or PNOEOM_FP32 for the large contractions.
+ *   precision : PNOEOM_FP64, PNOEOM_FP32 or PNOEOM_BF16 for the large contractions
+ *               (FP32 / BF16 need build_df with the same precision; FP64 always works).
  * Requires build_df (and build_sapno for PNO).  Errors: ESTATE, EINVAL, ENOMEM, EHIP. */
 int pnoeom_apply_sigma(pnoeom_ctx* ctx, int nvec, const double* r1, const double* r2, double* s1,
                        double* s2, int space, int precision);
 
 typedef struct {
   int space;           /* PNOEOM_CANONICAL or PNOEOM_PNO */
-  int precision;       /* PNOEOM_FP64 or PNOEOM_FP32 contractions; subspace work is FP64 */
+  int precision;       /* PNOEOM_FP64, PNOEOM_FP32 or PNOEOM_BF16 contractions; subspace work is FP64 */
   double tol_e;        /* |theta_k - theta_k(previous)| bound (Eh) */
   double tol_r;        /* residual 2-norm bound; <= 0 selects 0.1*sqrt(tol_e) */
   int max_sub;         /* largest subspace before collapse to the Ritz vectors */
   int max_iter;        /* iteration limit (ENOTCONV when reached) */
-  int refine_fp64;     /* precision = FP32: finish with FP64 sigma from the converged FP32 roots */
+  int refine_fp64;     /* precision FP32/BF16: finish with FP64 sigma from the converged roots */
   int verbose;         /* 1: print one line per iteration to stdout */
   int nextra;          /* further Ritz pairs tracked and kept at collapse (need not converge) */
 } pnoeom_davidson_opts;
@@ -175,6 +179,13 @@ int pnoeom_host_eig(int n, const double* a, double* wr, double* wi, double* vr);
  * pointer may be NULL. */
 int pnoeom_last_timing(const pnoeom_ctx* ctx, double* total_ms, double* ladder_ms, int* ladder_launches,
                        double* ladder_flops);
+
+/* The ladder part of pnoeom_last_timing restricted to the launches of one
+ * contraction precision (PNOEOM_FP64, PNOEOM_FP32 or PNOEOM_BF16): a mixed-precision
+ * Davidson with FP64 refinement runs ladder launches of both kinds.
+ * Errors: EINVAL (null ctx, bad precision). */
+int pnoeom_last_ladder_timing(const pnoeom_ctx* ctx, int precision, double* ladder_ms, int* ladder_launches,
+                              double* ladder_flops);
 
 #ifdef __cplusplus
 }

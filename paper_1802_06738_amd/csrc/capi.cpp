@@ -40,8 +40,16 @@ struct Timer {
     c.last_ladder_launches = 0;
     c.ladder_flops = 0;
     c.ladder_kernel_launches = 0;
+    for (int p = 0; p < 3; ++p) {
+      c.ladder_flops_p[p] = 0;
+      c.ladder_launches_p[p] = 0;
+      c.last_ladder_ms_p[p] = 0;
+      c.last_ladder_flops_p[p] = 0;
+      c.last_ladder_launches_p[p] = 0;
+    }
     c.timing = true;
     c.ev_used = 0;
+    c.ev_prec.clear();
     PNO_HIP(hipEventCreate(&a));
     PNO_HIP(hipEventCreate(&b));
     PNO_HIP(hipEventRecord(a, c.stream));
@@ -57,10 +65,15 @@ struct Timer {
       float t = 0.f;
       PNO_HIP(hipEventElapsedTime(&t, c.ev_pool[k], c.ev_pool[k + 1]));
       lad += t;
+      if (k / 2 < c.ev_prec.size()) c.last_ladder_ms_p[c.ev_prec[k / 2]] += t;
     }
     c.last_ladder_ms = lad;
     c.last_ladder_launches = c.ladder_kernel_launches;
     c.last_ladder_flops = c.ladder_flops;
+    for (int p = 0; p < 3; ++p) {
+      c.last_ladder_flops_p[p] = c.ladder_flops_p[p];
+      c.last_ladder_launches_p[p] = c.ladder_launches_p[p];
+    }
   }
   ~Timer() {
     c.timing = false;
@@ -100,8 +113,8 @@ int pnoeom_build_df(pnoeom_ctx* ctx, const double* B, const double* eps, const d
                     int precision) {
   return guarded(ctx, [&](pnoeom::Context& c) {
     PNO_CHECK(B && eps, PNOEOM_EINVAL, "build_df: B and eps are required");
-    PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32, PNOEOM_EINVAL,
-              "build_df: precision must be PNOEOM_FP64 or PNOEOM_FP32");
+    PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32 || precision == PNOEOM_BF16, PNOEOM_EINVAL,
+              "build_df: precision must be PNOEOM_FP64, PNOEOM_FP32 or PNOEOM_BF16");
     pnoeom::build_df(c, B, eps, t1, t2, precision);
   });
 }
@@ -153,8 +166,8 @@ int pnoeom_apply_sigma(pnoeom_ctx* ctx, int nvec, const double* r1, const double
   return guarded(ctx, [&](pnoeom::Context& c) {
     PNO_CHECK(c.have_df, PNOEOM_ESTATE, "apply_sigma before build_df");
     PNO_CHECK(nvec >= 0, PNOEOM_EINVAL, "apply_sigma: nvec < 0");
-    PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32, PNOEOM_EINVAL,
-              "apply_sigma: precision must be PNOEOM_FP64 or PNOEOM_FP32");
+    PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32 || precision == PNOEOM_BF16, PNOEOM_EINVAL,
+              "apply_sigma: precision must be PNOEOM_FP64, PNOEOM_FP32 or PNOEOM_BF16");
     PNO_CHECK(space == PNOEOM_CANONICAL || space == PNOEOM_PNO, PNOEOM_EINVAL, "apply_sigma: bad space");
     if (nvec == 0) return;
     Timer t(c);
@@ -223,6 +236,16 @@ int pnoeom_last_timing(const pnoeom_ctx* ctx, double* total_ms, double* ladder_m
   if (total_ms) *total_ms = ctx->c.last_total_ms;
   if (ladder_ms) *ladder_ms = ctx->c.last_ladder_ms;
   if (ladder_launches) *ladder_launches = ctx->c.last_ladder_launches;
+  return PNOEOM_OK;
+}
+
+int pnoeom_last_ladder_timing(const pnoeom_ctx* ctx, int precision, double* ladder_ms, int* ladder_launches,
+                              double* ladder_flops) {
+  if (!ctx) return PNOEOM_EINVAL;
+  if (precision < PNOEOM_FP64 || precision > PNOEOM_BF16) return PNOEOM_EINVAL;
+  if (ladder_ms) *ladder_ms = ctx->c.last_ladder_ms_p[precision];
+  if (ladder_launches) *ladder_launches = ctx->c.last_ladder_launches_p[precision];
+  if (ladder_flops) *ladder_flops = ctx->c.last_ladder_flops_p[precision];
   return PNOEOM_OK;
 }
 

@@ -83,6 +83,25 @@ struct GemmDesc {
 void gemm(const GemmDesc<double>& d, hipStream_t s);
 void gemm(const GemmDesc<float>& d, hipStream_t s);
 
+// bfloat16 operands (stored as their 16-bit patterns), FP32 accumulation and output:
+// C[m][n] = alpha * sum_k A[m][k] B[n][k] + beta * C[m][n].  Both operands are
+// K-contiguous rows; K, lda and ldb are multiples of kBf16K (the caller zero-pads
+// the columns past the true contraction length).
+constexpr int64_t kBf16K = 64;
+inline int64_t bf16_ld(int64_t k) { return (k + kBf16K - 1) / kBf16K * kBf16K; }
+struct GemmBf16Desc {
+  int64_t M = 0, N = 0, K = 0;
+  float alpha = 1, beta = 0;
+  const uint16_t* A = nullptr;
+  int64_t lda = 0;
+  const uint16_t* B = nullptr;
+  int64_t ldb = 0;
+  float* C = nullptr;
+  int64_t ldc = 0;
+  int tag = 0;  // 1: the particle-particle ladder
+};
+void gemm_bf16(const GemmBf16Desc& d, hipStream_t s);
+
 // Grouped GEMM: many independent products of different shapes in one launch.
 // Operand addresses are offsets from per-launch base pointers, so a descriptor
 // table built once can be reused for different vectors.

@@ -14,6 +14,7 @@ struct SigmaWork {
   DBuf<double> Ftv, Fto;
   DBuf<double> LadAll, Sp, Am, SigP, SigM;  // batched packed ladder
   DBuf<float> Spf, Amf, SigPf, SigMf;
+  DBuf<uint16_t> Spb, Amb;  // bfloat16 bits, rows padded to the W+/- column padding
   // FP32 staging for the mixed-precision contractions
   DBuf<float> fa, fb, fc;
 };
@@ -63,8 +64,10 @@ struct Context {
   DBuf<double> Fqvv, Fqoo, Fvv, Foo, fd_ov;
   DBuf<double> Dr, Xr, DX2, Wvo2;
   // packed ladder: W+[(a<=b),(c<=d)] = W_abcd + W_abdc, W-[(a<b),(c<d)] = W_abcd - W_abdc
-  DBuf<double> Wp, Wm;          // FP64 (precision FP64)
+  DBuf<double> Wp, Wm;          // FP64 (always: the FP64 sigma and the refinement of mixed runs)
   DBuf<float> Wpf, Wmf;         // FP32 (precision FP32)
+  DBuf<uint16_t> Wpb, Wmb;      // bfloat16 bits (precision BF16), rows padded to ldpb / ldmb columns
+  int64_t ldpb = 0, ldmb = 0;
   DBuf<float> Tf, Tiaf, Tsiaf, Drf, Xrf, DX2f, GXf;
   DBuf<double> scratch;         // build-time temporaries
 
@@ -76,6 +79,12 @@ struct Context {
   int last_ladder_launches = 0;
   double ladder_flops = 0;          // algorithmic flops of the timed ladder launches
   int ladder_kernel_launches = 0;   // GEMM launches inside the timed ladder regions
+  // the same split by contraction precision (FP64, FP32, BF16)
+  double ladder_flops_p[3] = {0, 0, 0};
+  int ladder_launches_p[3] = {0, 0, 0};
+  double last_ladder_ms_p[3] = {0, 0, 0}, last_ladder_flops_p[3] = {0, 0, 0};
+  int last_ladder_launches_p[3] = {0, 0, 0};
+  std::vector<int> ev_prec;         // precision of each start/stop event pair
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;  // start/stop pairs around ladder launches
   size_t ev_used = 0;

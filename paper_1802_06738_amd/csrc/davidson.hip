@@ -587,8 +587,8 @@ DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt)
   PNO_CHECK(c.have_df, PNOEOM_ESTATE, "davidson before build_df");
   PNO_CHECK(nroots >= 1 && nroots <= c.ov(), PNOEOM_EINVAL, "davidson: bad number of roots");
   PNO_CHECK(opt.space == PNOEOM_CANONICAL || opt.space == PNOEOM_PNO, PNOEOM_EINVAL, "davidson: bad space");
-  PNO_CHECK(opt.precision == PNOEOM_FP64 || opt.precision == PNOEOM_FP32, PNOEOM_EINVAL,
-            "davidson: precision must be FP64 or FP32");
+  PNO_CHECK(opt.precision == PNOEOM_FP64 || opt.precision == PNOEOM_FP32 || opt.precision == PNOEOM_BF16,
+            PNOEOM_EINVAL, "davidson: precision must be FP64, FP32 or BF16");
   PNO_CHECK(opt.space == PNOEOM_CANONICAL || c.pno.built, PNOEOM_ESTATE, "PNO Davidson before build_sapno");
   PNO_CHECK(opt.nextra >= 0 && nroots + opt.nextra <= c.ov(), PNOEOM_EINVAL, "davidson: bad nextra");
   const int nk = nroots + opt.nextra;
@@ -640,9 +640,10 @@ DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt)
   };
   DBuf<double> xr;
   xr.alloc((int64_t)nroots * op.N);
-  DavidsonResult r = run_davidson(c, op, nroots, guess, nk, opt, prec == PNOEOM_FP32 ? "eom-fp32" : "eom", xr,
+  DavidsonResult r = run_davidson(c, op, nroots, guess, nk, opt,
+                                  prec == PNOEOM_FP32 ? "eom-fp32" : prec == PNOEOM_BF16 ? "eom-bf16" : "eom", xr,
                                   opt.nextra);
-  if (prec == PNOEOM_FP32 && opt.refine_fp64 && r.converged) {
+  if (prec != PNOEOM_FP64 && opt.refine_fp64 && r.converged) {
     prec = PNOEOM_FP64;
     DavidsonResult r2 = run_davidson(c, op, nroots, xr, nroots, opt, "eom-fp64-refine", nullptr, 0);
     r2.iters += r.iters;

@@ -474,6 +474,161 @@ void gemm_grouped(const GroupTable& t, double alpha, const double* A, const doub
   PNO_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------- bfloat16 x bfloat16 -> FP32, A B^T
+// v_mfma_f32_16x16x32_bf16: lane l supplies 8 consecutive-k values of row l%16 of
+// A and of column l%16 of B (the k-slot of each of the 8 values is the same for A
+// and B, so any fixed assignment of k to slots is valid; slot block l/16 takes
+// k = 8 (l/16) .. 8 (l/16) + 7, a 16-byte LDS read).  The FP32 accumulator layout
+// is the one of the 16x16x4 FP32 instruction (row 4 (l/16) + r, column l%16).
+// Tiles are staged through LDS as rows of BK = 64 k-values plus 8 of padding
+// (144-byte pitch: the 16 rows that one 16-byte read instruction touches fall on
+// disjoint bank quadruples).
+namespace {
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+struct Bf16Args {
+  int64_t M, N, K;
+  float alpha, beta;
+  const uint16_t* A;
+  int64_t lda;
+  const uint16_t* B;
+  int64_t ldb;
+  float* C;
+  int64_t ldc;
+  int tiles_m, tiles_n;
+  int64_t xper;
+};
+
+template <int BM, int BN, int TAG>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16_kernel(Bf16Args g) {
+  constexpr int BK = 64, LD = BK + 8;
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+  constexpr int CA = BM * BK / 8 / NT, CB = BN * BK / 8 / NT;  // 16-byte chunks per thread
+  static_assert(CA * NT * 8 == BM * BK && CB * NT * 8 == BN * BK, "tile/thread mismatch");
+  __shared__ __attribute__((aligned(16))) uint16_t As[BM * LD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LD];
+
+  int64_t tile = blockIdx.x;
+  if (g.xper > 0) {
+    tile = (int64_t)(blockIdx.x % 8) * g.xper + blockIdx.x / 8;
+    if (tile >= (int64_t)g.tiles_m * g.tiles_n) return;
+  }
+  const int64_t m0 = (tile % g.tiles_m) * BM, n0 = (tile / g.tiles_m) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // chunk c = tid + NT q covers row c / 8, k-chunk c % 8 (= tid % 8); rows past the
+  // end are clamped to the last row (their results are never stored)
+  const u32x4* pa[CA];
+  const u32x4* pb[CB];
+#pragma unroll
+  for (int q = 0; q < CA; ++q) {
+    int64_t row = m0 + (tid + NT * q) / 8;
+    if (row > g.M - 1) row = g.M - 1;
+    pa[q] = reinterpret_cast<const u32x4*>(g.A + row * g.lda + (tid % 8) * 8);
+  }
+#pragma unroll
+  for (int q = 0; q < CB; ++q) {
+    int64_t row = n0 + (tid + NT * q) / 8;
+    if (row > g.N - 1) row = g.N - 1;
+    pb[q] = reinterpret_cast<const u32x4*>(g.B + row * g.ldb + (tid % 8) * 8);
+  }
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+  u32x4 ra[CA], rb[CB];
+  const int64_t ktiles = g.K / BK;
+  if (ktiles > 0) {
+#pragma unroll
+    for (int q = 0; q < CA; ++q) ra[q] = pa[q][0];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) rb[q] = pb[q][0];
+  }
+  for (int64_t kt = 0; kt < ktiles; ++kt) {
+#pragma unroll
+    for (int q = 0; q < CA; ++q)
+      *reinterpret_cast<u32x4*>(&As[((tid + NT * q) / 8) * LD + (tid % 8) * 8]) = ra[q];
+#pragma unroll
+    for (int q = 0; q < CB; ++q)
+      *reinterpret_cast<u32x4*>(&Bs[((tid + NT * q) / 8) * LD + (tid % 8) * 8]) = rb[q];
+    __syncthreads();
+    if (kt + 1 < ktiles) {
+      const int64_t off = (kt + 1) * (BK / 8);  // in 16-byte chunks
+#pragma unroll
+      for (int q = 0; q < CA; ++q) ra[q] = pa[q][off];
+#pragma unroll
+      for (int q = 0; q < CB; ++q) rb[q] = pb[q][off];
+    }
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 32) {
+      bf16x8 av[TM], bv[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        av[i] = *reinterpret_cast<const bf16x8*>(&As[(wm * WM + i * 16 + lr) * LD + ks + 8 * lk]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        bv[j] = *reinterpret_cast<const bf16x8*>(&Bs[(wn * WN + j * 16 + lr) * LD + ks + 8 * lk]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int64_t gn = n0 + wn * WN + j * 16 + lr;
+      if (gn >= g.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm * WM + i * 16 + 4 * lk + r;
+        if (gm >= g.M) continue;
+        float* c = g.C + gm * g.ldc + gn;
+        float val = g.alpha * acc[i][j][r];
+        if (g.beta != 0.f) val += g.beta * (*c);
+        *c = val;
+      }
+    }
+}
+}  // namespace
+
+void gemm_bf16(const GemmBf16Desc& d, hipStream_t s) {
+  PNO_CHECK(d.M >= 0 && d.N >= 0 && d.K >= 0, PNOEOM_EINVAL, "gemm_bf16: negative size");
+  if (d.M == 0 || d.N == 0) return;
+  PNO_CHECK(d.A && d.B && d.C, PNOEOM_EINVAL, "gemm_bf16: null operand");
+  PNO_CHECK(d.K % kBf16K == 0 && d.lda % 8 == 0 && d.ldb % 8 == 0 && d.lda >= d.K && d.ldb >= d.K, PNOEOM_EINVAL,
+            "gemm_bf16: K and the leading dimensions must be padded to multiples of 64 and 8");
+  PNO_CHECK(((uintptr_t)d.A % 16) == 0 && ((uintptr_t)d.B % 16) == 0, PNOEOM_EINVAL,
+            "gemm_bf16: operands must be 16-byte aligned");
+  constexpr int BM = 128, BN = 128;
+  Bf16Args g;
+  g.M = d.M; g.N = d.N; g.K = d.K; g.alpha = d.alpha; g.beta = d.beta;
+  g.A = d.A; g.lda = d.lda; g.B = d.B; g.ldb = d.ldb; g.C = d.C; g.ldc = d.ldc;
+  g.tiles_m = (int)((d.M + BM - 1) / BM);
+  g.tiles_n = (int)((d.N + BN - 1) / BN);
+  const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n;
+  g.xper = 0;
+  int64_t gx = tiles;
+  if (tiles >= 64) {
+    g.xper = (tiles + 7) / 8;
+    gx = 8 * g.xper;
+  }
+  PNO_CHECK(gx < (1ll << 31), PNOEOM_EINVAL, "gemm_bf16: too many tiles");
+  if (d.tag == 1)
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, 1>), dim3((unsigned)gx), dim3(NT), 0, s, g);
+  else
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, 0>), dim3((unsigned)gx), dim3(NT), 0, s, g);
+  PNO_HIP(hipGetLastError());
+}
+
 void gemm(const GemmDesc<double>& d, hipStream_t s) { gemm_impl<double>(d, s); }
 void gemm(const GemmDesc<float>& d, hipStream_t s) { gemm_impl<float>(d, s); }
 

@@ -120,11 +120,28 @@ __device__ __forceinline__ int64_t pair_idx(int64_t i, int64_t j, int64_t o) {  
   return i * o - i * (i - 1) / 2 + (j - i);
 }
 
+// storage conversions of the packed ladder operands: FP64, FP32, or bfloat16 bits
+// (round to nearest even through FP32)
+__device__ __forceinline__ uint16_t bf16_bits(double x) {
+  uint32_t u = __float_as_uint((float)x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+template <typename T>
+__device__ __forceinline__ T cvt_out(double x) {
+  return (T)x;
+}
+template <>
+__device__ __forceinline__ uint16_t cvt_out<uint16_t>(double x) {
+  return bf16_bits(x);
+}
+
 // W+[(a<=b),(c<=d)] = W_abcd + W_abdc (c<d), W_abcc (c=d);  W-[(a<b),(c<d)] = W_abcd - W_abdc,
-// from a slab tmp[a-a0][c][b][d] = W_abcd of rows a in [a0, a0+na)
+// from a slab tmp[a-a0][c][b][d] = W_abcd of rows a in [a0, a0+na); row strides ldp, ldm
 template <typename OutT>
 __global__ void ladder_wpm_kernel(int v, int a0, int na, const double* __restrict__ tmp, OutT* __restrict__ Wp,
-                                  OutT* __restrict__ Wm) {
+                                  int64_t ldp, OutT* __restrict__ Wm, int64_t ldm) {
   const int64_t V = v, vp = V * (V + 1) / 2, vm = V * (V - 1) / 2;
   const int64_t total = (int64_t)na * V * V * V;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -136,15 +153,16 @@ __global__ void ladder_wpm_kernel(int v, int a0, int na, const double* __restric
     if (b < a || d < c) continue;
     const double w1 = tmp[((al * V + c) * V + b) * V + d];
     const double w2 = tmp[((al * V + d) * V + b) * V + c];
-    Wp[tri_idx(a, b, V) * vp + tri_idx(c, d, V)] = (OutT)(c < d ? w1 + w2 : w1);
-    if (a < b && c < d) Wm[stri_idx(a, b, V) * vm + stri_idx(c, d, V)] = (OutT)(w1 - w2);
+    Wp[tri_idx(a, b, V) * ldp + tri_idx(c, d, V)] = cvt_out<OutT>(c < d ? w1 + w2 : w1);
+    if (a < b && c < d) Wm[stri_idx(a, b, V) * ldm + stri_idx(c, d, V)] = cvt_out<OutT>(w1 - w2);
   }
 }
 
-// S[(q,p)][(c<=d)] = (R^cd + R^dc)/2 (c<d), R^cc ;  A[(q,p)][(c<d)] = (R^cd - R^dc)/2  for pairs p = (i<=j)
+// S[(q,p)][(c<=d)] = (R^cd + R^dc)/2 (c<d), R^cc ;  A[(q,p)][(c<d)] = (R^cd - R^dc)/2  for pairs p = (i<=j);
+// row strides ldS, ldA
 template <typename OutT>
 __global__ void ladder_pack_kernel(int o, int v, int nvec, const double* __restrict__ r2, int64_t stride,
-                                   OutT* __restrict__ S, OutT* __restrict__ A) {
+                                   OutT* __restrict__ S, int64_t ldS, OutT* __restrict__ A, int64_t ldA) {
   const int64_t O = o, V = v, vp = V * (V + 1) / 2, vm = V * (V - 1) / 2, npair = O * (O + 1) / 2;
   const int64_t total = (int64_t)nvec * O * O * V * V;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -158,8 +176,8 @@ __global__ void ladder_pack_kernel(int o, int v, int nvec, const double* __restr
     const double* R = r2 + q * stride + (i * O + j) * V * V;
     const double x = R[c * V + d], y = R[d * V + c];
     const int64_t row = q * npair + pair_idx(i, j, O);
-    S[row * vp + tri_idx(c, d, V)] = (OutT)(c < d ? 0.5 * (x + y) : x);
-    if (c < d) A[row * vm + stri_idx(c, d, V)] = (OutT)(0.5 * (x - y));
+    S[row * ldS + tri_idx(c, d, V)] = cvt_out<OutT>(c < d ? 0.5 * (x + y) : x);
+    if (c < d) A[row * ldA + stri_idx(c, d, V)] = cvt_out<OutT>(0.5 * (x - y));
   }
 }
 
@@ -409,10 +427,20 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   {
     const int64_t vp = (int64_t)v * (v + 1) / 2, vm = (int64_t)v * (v - 1) / 2;
     const bool f32w = precision == PNOEOM_FP32;
-    c.Wp.release(); c.Wm.release(); c.Wpf.release(); c.Wmf.release();
+    const bool bfw = precision == PNOEOM_BF16;
+    c.Wp.release(); c.Wm.release(); c.Wpf.release(); c.Wmf.release(); c.Wpb.release(); c.Wmb.release();
     c.Wp.alloc(vp * vp);
     c.Wm.alloc(std::max<int64_t>(vm * vm, 1));
     if (f32w) { c.Wpf.alloc(vp * vp); c.Wmf.alloc(std::max<int64_t>(vm * vm, 1)); }
+    // bfloat16 copies with rows padded to a multiple of 64 columns (zeros past the end)
+    c.ldpb = bf16_ld(vp);
+    c.ldmb = bf16_ld(std::max<int64_t>(vm, 1));
+    if (bfw) {
+      c.Wpb.alloc(vp * c.ldpb);
+      c.Wmb.alloc(std::max<int64_t>(vm, 1) * c.ldmb);
+      PNO_HIP(hipMemsetAsync(c.Wpb, 0, vp * c.ldpb * sizeof(uint16_t), s));
+      PNO_HIP(hipMemsetAsync(c.Wmb, 0, std::max<int64_t>(vm, 1) * c.ldmb * sizeof(uint16_t), s));
+    }
     int64_t na = v;
     const int64_t budget = (int64_t)1 << 28;
     while (na > 1 && na * v * vv > budget) na = (na + 1) / 2;
@@ -423,15 +451,18 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
       gm(s, false, true, nab * v, vv, naux, 1.0, c.BvvT + a0 * v * naux, naux, c.BvvT, naux, 0.0, tmp, vv);
       const int64_t tot = nab * v * vv;
       hipLaunchKernelGGL((ladder_wpm_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, v, (int)a0, (int)nab,
-                         (const double*)tmp, (double*)c.Wp, (double*)c.Wm);
+                         (const double*)tmp, (double*)c.Wp, vp, (double*)c.Wm, vm);
       if (f32w)
         hipLaunchKernelGGL((ladder_wpm_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, v, (int)a0, (int)nab,
-                           (const double*)tmp, (float*)c.Wpf, (float*)c.Wmf);
+                           (const double*)tmp, (float*)c.Wpf, vp, (float*)c.Wmf, vm);
+      if (bfw)
+        hipLaunchKernelGGL((ladder_wpm_kernel<uint16_t>), dim3(grid1(tot)), dim3(256), 0, s, v, (int)a0, (int)nab,
+                           (const double*)tmp, (uint16_t*)c.Wpb, c.ldpb, (uint16_t*)c.Wmb, c.ldmb);
       PNO_HIP(hipGetLastError());
     }
     PNO_HIP(hipStreamSynchronize(s));
   }
-  if (precision == PNOEOM_FP32) {
+  if (precision == PNOEOM_FP32 || precision == PNOEOM_BF16) {  // FP32 operands of the other contractions
     c.Tf.alloc(oovv);
     c.Tiaf.alloc(oovv);
     c.Tsiaf.alloc(oovv);
@@ -495,7 +526,7 @@ void alloc_sigma_work(Context& c, int precision, int nb) {
   grow(w.DXtot, B * oovv); grow(w.Zp, B * oovv); grow(w.Cba, B * oovv); grow(w.OOVVp, B * oovv);
   grow(w.Xh, B * oo * oo); grow(w.O4p, B * oo * oo); grow(w.M1, B * ov * c.naux);
   grow(w.Ftv, B * vv); grow(w.Fto, B * oo);
-  if (precision == PNOEOM_FP32) {
+  if (precision != PNOEOM_FP64) {
     grow(w.fa, B * oovv); grow(w.fb, B * oovv); grow(w.fc, B * oovv);
   }
 }
@@ -551,7 +582,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   const int o = c.o, v = c.v, nmo = c.nmo, naux = c.naux;
   const int64_t n2 = (int64_t)nmo * nmo, ov = c.ov(), oo = (int64_t)o * o, vv = (int64_t)v * v;
   const int64_t oovv = c.oovv(), oon = oo * naux, ovn = ov * naux, vvn = vv * naux, o4 = oo * oo;
-  const bool f32 = precision == PNOEOM_FP32;
+  const bool f32 = precision != PNOEOM_FP64;  // FP32 or BF16: FP32 contractions here
   alloc_sigma_work(c, precision, nb);
 
   // ---------------------------------------------------------------- R1: one-index transformed factors, per vector
@@ -694,9 +725,10 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
 void sigma_block(Context& c, int nvec, const double* r1, const double* r2, double* s1, double* s2, int64_t stride1,
                  int64_t stride2, int precision) {
   PNO_CHECK(c.have_df, PNOEOM_ESTATE, "sigma before build_df");
-  const bool f32 = precision == PNOEOM_FP32;
-  PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32, PNOEOM_EINVAL, "sigma: precision must be FP64 or FP32");
-  PNO_CHECK(f32 ? (c.Wpf.p != nullptr) : (c.Wp.p != nullptr), PNOEOM_EINVAL,
+  PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32 || precision == PNOEOM_BF16, PNOEOM_EINVAL,
+            "sigma: precision must be FP64, FP32 or BF16");
+  const bool f32 = precision == PNOEOM_FP32, bf = precision == PNOEOM_BF16;
+  PNO_CHECK(f32 ? (c.Wpf.p != nullptr) : bf ? (c.Wpb.p != nullptr) : (c.Wp.p != nullptr), PNOEOM_EINVAL,
             "sigma: the contraction precision must match the one given to build_df");
   if (nvec <= 0) return;
   SigmaWork& w = c.sw;
@@ -704,26 +736,41 @@ void sigma_block(Context& c, int nvec, const double* r1, const double* r2, doubl
   const int o = c.o, v = c.v;
   const int64_t oovv = c.oovv();
   const int64_t npair = (int64_t)o * (o + 1) / 2, vp = (int64_t)v * (v + 1) / 2, vm = (int64_t)v * (v - 1) / 2;
+  const int64_t vm1 = std::max<int64_t>(vm, 1);
   const int64_t rows = (int64_t)nvec * npair;
   grow(w.LadAll, (int64_t)nvec * oovv);
   const int64_t tot = (int64_t)nvec * oovv;
   // ---------------------------------------------------------------- particle ladder, all vectors at once
   hipEvent_t lad0 = nullptr, lad1 = nullptr;
-  if (f32) {
-    grow(w.Spf, rows * vp); grow(w.Amf, std::max<int64_t>(rows * vm, 1));
-    grow(w.SigPf, rows * vp); grow(w.SigMf, std::max<int64_t>(rows * vm, 1));
-    hipLaunchKernelGGL((ladder_pack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec, r2, stride2,
-                       (float*)w.Spf, (float*)w.Amf);
+  if (f32 || bf) {
+    grow(w.SigPf, rows * vp); grow(w.SigMf, rows * vm1);
   } else {
-    grow(w.Sp, rows * vp); grow(w.Am, std::max<int64_t>(rows * vm, 1));
-    grow(w.SigP, rows * vp); grow(w.SigM, std::max<int64_t>(rows * vm, 1));
+    grow(w.SigP, rows * vp); grow(w.SigM, rows * vm1);
+  }
+  if (f32) {
+    grow(w.Spf, rows * vp); grow(w.Amf, rows * vm1);
+    hipLaunchKernelGGL((ladder_pack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec, r2, stride2,
+                       (float*)w.Spf, vp, (float*)w.Amf, vm);
+  } else if (bf) {
+    // padded rows; the padding columns are zeroed once per allocation and never written
+    if ((int64_t)w.Spb.n < rows * c.ldpb || (int64_t)w.Amb.n < rows * c.ldmb) {
+      w.Spb.alloc(rows * c.ldpb);
+      w.Amb.alloc(rows * c.ldmb);
+      PNO_HIP(hipMemsetAsync(w.Spb, 0, w.Spb.n * sizeof(uint16_t), s));
+      PNO_HIP(hipMemsetAsync(w.Amb, 0, w.Amb.n * sizeof(uint16_t), s));
+    }
+    hipLaunchKernelGGL((ladder_pack_kernel<uint16_t>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec, r2, stride2,
+                       (uint16_t*)w.Spb, c.ldpb, (uint16_t*)w.Amb, c.ldmb);
+  } else {
+    grow(w.Sp, rows * vp); grow(w.Am, rows * vm1);
     hipLaunchKernelGGL((ladder_pack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec, r2, stride2,
-                       (double*)w.Sp, (double*)w.Am);
+                       (double*)w.Sp, vp, (double*)w.Am, vm);
   }
   PNO_HIP(hipGetLastError());
   if (c.timing) {
     lad0 = c.next_event();
     lad1 = c.next_event();
+    c.ev_prec.push_back(precision);
     PNO_HIP(hipEventRecord(lad0, s));
   }
   if (f32) {
@@ -733,6 +780,13 @@ void sigma_block(Context& c, int nvec, const double* r1, const double* r2, doubl
     gemm(d, s);
     d.N = vm; d.K = vm; d.A = w.Amf; d.lda = vm; d.B = c.Wmf; d.ldb = vm; d.C = w.SigMf; d.ldc = vm;
     gemm(d, s);
+  } else if (bf) {
+    GemmBf16Desc d;
+    d.M = rows; d.N = vp; d.K = c.ldpb; d.tag = 1;
+    d.A = w.Spb; d.lda = c.ldpb; d.B = c.Wpb; d.ldb = c.ldpb; d.C = w.SigPf; d.ldc = vp;
+    gemm_bf16(d, s);
+    d.N = vm; d.K = c.ldmb; d.A = w.Amb; d.lda = c.ldmb; d.B = c.Wmb; d.ldb = c.ldmb; d.C = w.SigMf; d.ldc = vm;
+    gemm_bf16(d, s);
   } else {
     GemmDesc<double> d;
     d.tb = true; d.M = rows; d.N = vp; d.K = vp; d.tag = 1;
@@ -743,10 +797,14 @@ void sigma_block(Context& c, int nvec, const double* r1, const double* r2, doubl
   }
   if (c.timing) {
     PNO_HIP(hipEventRecord(lad1, s));
-    c.ladder_flops += 2.0 * (double)rows * ((double)vp * vp + (double)vm * vm);
-    c.ladder_kernel_launches += vm > 0 ? 2 : 1;
+    const double fl = 2.0 * (double)rows * ((double)vp * vp + (double)vm * vm);
+    const int nl = vm > 0 ? 2 : 1;
+    c.ladder_flops += fl;
+    c.ladder_kernel_launches += nl;
+    c.ladder_flops_p[precision] += fl;
+    c.ladder_launches_p[precision] += nl;
   }
-  if (f32)
+  if (f32 || bf)
     hipLaunchKernelGGL((ladder_unpack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec,
                        (const float*)w.SigPf, (const float*)w.SigMf, (double*)w.LadAll, oovv);
   else
@@ -754,7 +812,7 @@ void sigma_block(Context& c, int nvec, const double* r1, const double* r2, doubl
                        (const double*)w.SigP, (const double*)w.SigM, (double*)w.LadAll, oovv);
   PNO_HIP(hipGetLastError());
   // ---------------------------------------------------------------- everything else, in chunks of vectors
-  const int nb = rest_chunk(c, nvec, f32);
+  const int nb = rest_chunk(c, nvec, f32 || bf);
   for (int q0 = 0; q0 < nvec; q0 += nb) {
     const int n = std::min(nb, nvec - q0);
     sigma_rest_block(c, n, r1 + q0 * stride1, stride1, r2 + q0 * stride2, stride2, s1 + q0 * stride1,

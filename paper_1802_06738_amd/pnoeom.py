@@ -20,7 +20,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "
           -7: "EABORTED"}
 EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pnoeom_build_df", "pnoeom_cis",
                     "pnoeom_build_sapno", "pnoeom_pno_layout", "pnoeom_pno_transform", "pnoeom_apply_sigma", "pnoeom_davidson_defaults",
-                    "pnoeom_davidson", "pnoeom_host_eig", "pnoeom_last_timing"]
+                    "pnoeom_davidson", "pnoeom_host_eig", "pnoeom_last_timing", "pnoeom_last_ladder_timing"]
 
 
 class PnoEomError(RuntimeError):
@@ -67,6 +67,7 @@ def load_library():
     lib.pnoeom_davidson.argtypes = [vp, C.c_int, C.POINTER(DavidsonOpts), dp, dp, ip, ip]
     lib.pnoeom_host_eig.argtypes = [C.c_int, dp, dp, dp, dp]
     lib.pnoeom_last_timing.argtypes = [vp, dp, dp, ip, dp]
+    lib.pnoeom_last_ladder_timing.argtypes = [vp, C.c_int, dp, ip, dp]
     _LIB = lib
     return lib
 
@@ -226,4 +227,8 @@ class PnoEom:
         n = C.c_int()
         fl = C.c_double()
         self._check(self.lib.pnoeom_last_timing(self.h, C.byref(t), C.byref(lad), C.byref(n), C.byref(fl)))
-        return dict(total_ms=t.value, ladder_ms=lad.value, ladder_launches=n.value, ladder_flops=fl.value)
+        out = dict(total_ms=t.value, ladder_ms=lad.value, ladder_launches=n.value, ladder_flops=fl.value)
+        for p, name in ((FP64, "fp64"), (FP32, "fp32"), (BF16, "bf16")):
+            self._check(self.lib.pnoeom_last_ladder_timing(self.h, p, C.byref(lad), C.byref(n), C.byref(fl)))
+            out[name] = dict(ladder_ms=lad.value, ladder_launches=n.value, ladder_flops=fl.value)
+        return out

@@ -69,6 +69,52 @@ def test_sigma_fp32_matches_oracle(o, v, naux, t1s, seed):
     assert np.max(np.abs(g2.cpu().numpy()[0] - a2)) <= 2e-5 * np.max(np.abs(a2))
 
 
+def _ladder_bf16_bound(so, r2):
+    """Elementwise bound on the bfloat16 rounding error of the packed ladder
+    sum_cd W_ab^cd R_ij^cd: each product of two rounded operands carries a relative
+    error of at most 2 u (u = 2^-8, through FP32: u (1 + 2^-16)), so
+    |err_ij^ab| <= 2.01 u (sum_{c<=d} |W+_ab,cd| |S_ij^cd| + sum_{c<d} |W-_ab,cd| |A_ij^cd|)
+    with W+- = W_abcd +- W_abdc, S/A = (R^cd +- R^dc)/2, and the FP32 accumulation
+    over K terms adds K 2^-24 of the same sum."""
+    o, v = so.o, so.v
+    W = so.Hd.ladder_matrix().reshape(v, v, v, v)
+    Wt = W.transpose(0, 1, 3, 2)
+    iu = np.triu_indices(v, 1)
+    Wp = np.abs(W + Wt)[:, :, iu[0], iu[1]]
+    Wm = np.abs(W - Wt)[:, :, iu[0], iu[1]]
+    Wd = np.abs(np.einsum("abcc->abc", W))
+    Rt = r2.transpose(0, 1, 3, 2)
+    S = np.abs(0.5 * (r2 + Rt))[:, :, iu[0], iu[1]]
+    A = np.abs(0.5 * (r2 - Rt))[:, :, iu[0], iu[1]]
+    Rd = np.abs(np.einsum("ijcc->ijc", r2))
+    plus = np.einsum("abk,ijk->ijab", Wp, S) + np.einsum("abc,ijc->ijab", Wd, Rd)
+    minus = np.einsum("abk,ijk->ijab", Wm, A)
+    K = v * (v + 1) // 2
+    return (2.01 * 2.0 ** -8 + K * 2.0 ** -24) * (plus + minus)
+
+
+@pytest.mark.parametrize("o,v,naux,t1s,seed", CASES[:2])
+def test_sigma_bf16_ladder_within_rounding_bound(o, v, naux, t1s, seed):
+    """BF16 mode: ladder on bfloat16 operands with FP32 accumulation, everything else
+    FP32.  Each sigma2 element must lie within the ladder's rounding bound plus the
+    FP32 tolerance; sigma1 (no ladder) within the FP32 tolerance."""
+    print(f"[sigma bf16] o={o} v={v} naux={naux} seed={seed}", flush=True)
+    torch = _torch()
+    from oracle.sigma import SigmaOracle
+    s = make_system(o, v, naux, seed, t1_sigma=t1s)
+    ctx = _ctx(s, precision=2)
+    r1, r2 = random_r(o, v, seed + 50)
+    g1, g2 = ctx.sigma(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda(), precision=2)
+    so = SigmaOracle(s.eps, s.B, o, s.t1)
+    a1, a2 = so.sigma(r1[0], r2[0])
+    err1 = np.abs(g1.cpu().numpy()[0] - a1)
+    err2 = np.abs(g2.cpu().numpy()[0] - a2)
+    assert np.max(err1) <= 2e-5 * np.max(np.abs(a1))
+    bound = _ladder_bf16_bound(so, r2[0]) + 2e-5 * np.max(np.abs(a2))
+    assert np.all(err2 <= bound)
+    assert np.max(err2) > 1e-6 * np.max(np.abs(a2))  # the bfloat16 path was taken
+
+
 def test_sigma_given_t2_and_zero_r():
     """Explicit T2 input path; R = 0 gives sigma = 0 exactly (linearity)."""
     torch = _torch()
@@ -115,6 +161,19 @@ def test_davidson_c1_fp32_mixed():
     ctx = _ctx(s, precision=1)
     r = ctx.davidson(3, precision=1, tol_e=1e-8, tol_r=1e-6)
     assert np.max(np.abs(r["omega"] - np.array(gold["dense_eig"][:3]))) <= 1e-6
+
+
+def test_davidson_c1_bf16_with_fp64_refinement():
+    """BF16 ladder Davidson followed by FP64 refinement reaches the FP64 roots."""
+    print("[davidson c1 bf16]", flush=True)
+    gold = json.load(open(os.path.join(GOLD, "c1.json")))
+    s = config_system(1)
+    ctx = _ctx(s, precision=2)
+    dense = np.array(gold["dense_eig"][:3])
+    r0 = ctx.davidson(3, precision=2, tol_e=1e-6, tol_r=1e-4)
+    assert np.max(np.abs(r0["omega"] - dense)) <= 2.0 ** -7 * np.max(np.abs(dense))
+    r = ctx.davidson(3, precision=2, tol_e=1e-10, tol_r=1e-7, refine_fp64=True)
+    assert np.max(np.abs(r["omega"] - dense)) <= 1e-8
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-11), (1, 5e-5)])
