@@ -31,15 +31,20 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}    # MI355X dense matrix TF
 HBM_PEAK = 8000.0                       # GB/s
 
 
-def run_steps(ctx, B, eps, t1, nroots, prec, steps, tol_e, tol_r, max_sub):
+def run_steps(ctx, B, eps, t1, nroots, prec, steps, tol_e, tol_r, max_sub, pno=None):
+    """One step: build_df (+ build_sapno when pno = (nstates, tcut)) + Davidson."""
     import torch
-    from paper_1802_06738_amd import FP64
+    from paper_1802_06738_amd import FP64, CANONICAL, PNO
     res = []
     for _ in range(steps):
         ctx.build_df(B, eps, t1, None, precision=prec)
-        r = ctx.davidson(nroots, precision=prec, tol_e=tol_e, tol_r=tol_r, max_sub=max_sub,
-                         refine_fp64=(prec != FP64))
+        npno = None
+        if pno is not None:
+            npno, _ = ctx.build_sapno(pno[0], pno[1])
+        r = ctx.davidson(nroots, space=CANONICAL if pno is None else PNO, precision=prec, tol_e=tol_e,
+                         tol_r=tol_r, max_sub=max_sub, refine_fp64=(prec != FP64))
         r["timing"] = ctx.last_timing()
+        r["npno"] = npno
         res.append(r)
     torch.cuda.synchronize()
     return res
@@ -78,6 +83,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-pno", action="store_true")
+    ap.add_argument("--tcut", type=float, default=1e-7)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -100,15 +107,16 @@ def main():
     torch.cuda.synchronize()
     ctx = PnoEom(o, v, naux)
 
-    def measure(prec):
-        run_steps(ctx, B, eps, t1, nroots, prec, args.warmup, tol_e, tol_r, max_sub)
+    def measure(prec, pno=None):
+        tag = f"precision {prec}" + ("" if pno is None else f", PNO tcut {pno[1]:g}")
+        run_steps(ctx, B, eps, t1, nroots, prec, args.warmup, tol_e, tol_r, max_sub, pno)
         torch.cuda.synchronize()
-        print(f"[bench] precision {prec}: warmup done", file=sys.stderr, flush=True)
+        print(f"[bench] {tag}: warmup done", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        res = run_steps(ctx, B, eps, t1, nroots, prec, args.steps, tol_e, tol_r, max_sub)
+        res = run_steps(ctx, B, eps, t1, nroots, prec, args.steps, tol_e, tol_r, max_sub, pno)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        print(f"[bench] precision {prec}: {args.steps} steps in {dt:.2f} s", file=sys.stderr, flush=True)
+        print(f"[bench] {tag}: {args.steps} steps in {dt:.2f} s", file=sys.stderr, flush=True)
         return res, dt
 
     res64, dt64 = measure(FP64)
@@ -173,6 +181,34 @@ def main():
                 "ladder_frac_of_peak": (tf / PEAK[name]) if tf else None,
                 "note": (("FP32-MFMA" if name == "fp32" else "bfloat16-MFMA ladder (FP32 accumulation), FP32 other")
                          + " contractions until convergence, then FP64 sigma refinement from those roots"),
+            }
+    if not args.no_pno:
+        # SA-PNO space (pair densities averaged over the nroots lowest CIS states)
+        pno = (nroots, args.tcut)
+        resp, dtp = measure(FP64, pno)
+        omp = resp[-1]["omega"]
+        npno = np.asarray(resp[-1]["npno"])
+        out["pno_fp64"] = {
+            "tcut": args.tcut, "npno_mean": float(npno.mean()), "npno_min": int(npno.min()),
+            "npno_max": int(npno.max()),
+            "time_to_convergence_s": dtp / args.steps,
+            "speedup_vs_canonical_fp64": dt64 / dtp,
+            "sigma_evals_per_s": sum(r["nsigma"] for r in resp) / dtp,
+            "omega": [float(x) for x in omp],
+            "max_abs_pno_truncation_eh": float(np.max(np.abs(omp - omega64))),
+            "note": "step = build_df + build_sapno + PNO-space Davidson (back-transform, canonical sigma, "
+                    "projection); the difference from the canonical roots is the PNO truncation",
+        }
+        if not args.no_mixed:
+            resb, dtb = measure(BF16, pno)
+            omb = resb[-1]["omega"]
+            out["pno_mixed_bf16"] = {
+                "tcut": args.tcut,
+                "time_to_convergence_s": dtb / args.steps,
+                "speedup_vs_canonical_fp64": dt64 / dtb,
+                "sigma_evals_per_s": sum(r["nsigma"] for r in resb) / dtb,
+                "max_abs_diff_vs_pno_fp64_eh": float(np.max(np.abs(omb - omp))),
+                "note": "BF16 ladder / FP32 other contractions, FP64 refinement, PNO space",
             }
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
