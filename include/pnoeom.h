@@ -170,6 +170,16 @@ int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opt
  * Errors: EINVAL (n < 1 or null), ENOTCONV (QR iteration failed). */
 int pnoeom_host_eig(int n, const double* a, double* wr, double* wi, double* vr);
 
+/* Host symmetric eigensolver used by pnoeom_build_sapno for pair-density and
+ * semicanonical blocks larger than the GPU Jacobi kernel handles well (Methods: the
+ * per-pair diagonalisation of the state-averaged densities), exposed for CPU tests.
+ * Householder tridiagonalisation + implicit QR with Wilkinson shifts.
+ *   a : host [n][n] row-major symmetric (not modified)
+ *   w : host [n] eigenvalues (unordered);  v : host [n][n], column k = unit
+ *       eigenvector of w[k].
+ * Errors: EINVAL (n < 1 or null), ENOTCONV. */
+int pnoeom_host_syev(int n, const double* a, double* w, double* v);
+
 /* Time spent in the last pnoeom_davidson / pnoeom_apply_sigma call, measured with
  * HIP events on the context's stream: total milliseconds; milliseconds inside the
  * particle-ladder contractions and the number of ladder GEMM launches (two per

@@ -221,6 +221,14 @@ int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opt
   return PNOEOM_OK;
 }
 
+int pnoeom_host_syev(int n, const double* a, double* w, double* v) {
+  try {
+    return pnoeom::host_syev(n, a, w, v);
+  } catch (...) {
+    return PNOEOM_EINVAL;
+  }
+}
+
 int pnoeom_host_eig(int n, const double* a, double* wr, double* wi, double* vr) {
   try {
     return pnoeom::host_eig(n, a, wr, wi, vr);

@@ -128,5 +128,7 @@ DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt)
 
 // host eigen-solver (eig.cpp); returns 0 or a negative status
 int host_eig(int n, const double* a, double* wr, double* wi, double* vr);
+int host_syev(int n, const double* a, double* w, double* v);
+int host_syev_batched(int nmat, const int* nsz, int ld, double* A, double* ev, double* Vt, int nthreads);
 
 }  // namespace pnoeom

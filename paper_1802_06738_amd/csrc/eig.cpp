@@ -10,7 +10,9 @@
 #include <cfloat>
 #include <cmath>
 #include <complex>
+#include <atomic>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "../../include/pnoeom.h"
@@ -271,6 +273,174 @@ int host_eig(int n, const double* a, double* wr, double* wi, double* vr) {
     }
   }
   return PNOEOM_OK;
+}
+
+// ----------------------------------------------------------------------------- symmetric
+// Real symmetric eigensolver for the large per-pair density matrices of the PNO build:
+// Householder reduction to tridiagonal form (A = Q T Q^T, reflectors I - 2 v v^T with
+// unit v, trailing block updated as A <- A - 2 (v q^T + q v^T), q = A v - (v^T A v) v),
+// backward accumulation of Q, then the implicit symmetric QR iteration with the
+// Wilkinson shift of the trailing 2 x 2 block, chasing the bulge with Givens rotations
+// G = [[c, s], [-s, c]] (T <- G^T T G, Z <- Z G) and deflating when
+// |t_{k,k+1}| <= eps (|t_kk| + |t_{k+1,k+1}|).
+namespace {
+
+int syev_one(int n, double* a, double* w, double* z) {
+  // a: n x n row-major symmetric (destroyed); w: eigenvalues; z: n x n, column k = vector k
+  std::vector<double> d(n), e(n > 1 ? n - 1 : 1, 0.0);
+  std::vector<std::vector<double>> vs(n > 2 ? n - 2 : 0);
+  std::vector<double> p(n), q(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    double* row = a + (int64_t)k * n + k + 1;
+    double sig = 0.0;
+    for (int i = 0; i < m; ++i) sig += row[i] * row[i];
+    sig = std::sqrt(sig);
+    d[k] = a[(int64_t)k * n + k];
+    if (sig == 0.0) {
+      e[k] = 0.0;
+      continue;
+    }
+    const double alpha = row[0] >= 0.0 ? -sig : sig;
+    std::vector<double>& v = vs[k];
+    v.assign(row, row + m);
+    v[0] -= alpha;
+    double vn = 0.0;
+    for (int i = 0; i < m; ++i) vn += v[i] * v[i];
+    vn = std::sqrt(vn);
+    if (vn == 0.0) {
+      v.clear();
+      e[k] = row[0];
+      continue;
+    }
+    for (int i = 0; i < m; ++i) v[i] /= vn;
+    e[k] = alpha;
+    // p = A' v over the trailing block (rows / columns k+1..n-1)
+    double kap = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double* ar = a + (int64_t)(k + 1 + i) * n + k + 1;
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += ar[j] * v[j];
+      p[i] = acc;
+      kap += v[i] * acc;
+    }
+    for (int i = 0; i < m; ++i) q[i] = p[i] - kap * v[i];
+    for (int i = 0; i < m; ++i) {
+      double* ar = a + (int64_t)(k + 1 + i) * n + k + 1;
+      const double vi = 2.0 * v[i], qi = 2.0 * q[i];
+      for (int j = 0; j < m; ++j) ar[j] -= vi * q[j] + qi * v[j];
+    }
+  }
+  if (n >= 2) {
+    d[n - 2] = a[(int64_t)(n - 2) * n + n - 2];
+    e[n - 2] = a[(int64_t)(n - 2) * n + n - 1];
+  }
+  d[n - 1] = a[(int64_t)(n - 1) * n + n - 1];
+  // Z = H_0 H_1 ... H_{n-3}, accumulated backwards on rows k+1..n-1
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) z[(int64_t)i * n + j] = i == j ? 1.0 : 0.0;
+  for (int k = n - 3; k >= 0; --k) {
+    const std::vector<double>& v = vs[k];
+    if (v.empty()) continue;
+    const int m = n - k - 1;
+    // rows k+1.. of Z have nonzeros only in columns k+1..n-1
+    std::fill(p.begin(), p.end(), 0.0);
+    for (int i = 0; i < m; ++i) {
+      const double* zr = z + (int64_t)(k + 1 + i) * n + k + 1;
+      for (int j = 0; j < m; ++j) p[j] += v[i] * zr[j];
+    }
+    for (int i = 0; i < m; ++i) {
+      double* zr = z + (int64_t)(k + 1 + i) * n + k + 1;
+      const double vi = 2.0 * v[i];
+      for (int j = 0; j < m; ++j) zr[j] -= vi * p[j];
+    }
+  }
+  // implicit symmetric QR on (d, e); Z columns rotated along
+  int hi = n - 1, iters = 0;
+  const int max_iters = 60 * n + 100;
+  while (hi > 0) {
+    if (std::fabs(e[hi - 1]) <= DBL_EPSILON * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && std::fabs(e[lo - 1]) > DBL_EPSILON * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+    if (++iters > max_iters) return PNOEOM_ENOTCONV;
+    const double dd = 0.5 * (d[hi - 1] - d[hi]);
+    const double bb = e[hi - 1];
+    const double den = dd + (dd >= 0.0 ? 1.0 : -1.0) * std::hypot(dd, bb);
+    const double mu = den != 0.0 ? d[hi] - bb * bb / den : d[hi] - std::fabs(bb);
+    double x = d[lo] - mu, y = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = std::hypot(x, y);
+      double c = 1.0, s = 0.0;
+      if (r != 0.0) {
+        c = x / r;
+        s = -y / r;
+      }
+      if (k > lo) e[k - 1] = r;
+      const double pk = d[k], qk = d[k + 1], tk = e[k];
+      d[k] = c * c * pk - 2.0 * c * s * tk + s * s * qk;
+      d[k + 1] = s * s * pk + 2.0 * c * s * tk + c * c * qk;
+      e[k] = c * s * (pk - qk) + (c * c - s * s) * tk;
+      if (k + 1 < hi) {
+        y = -s * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+        x = e[k];
+      }
+      for (int i = 0; i < n; ++i) {
+        double* zr = z + (int64_t)i * n;
+        const double zk = zr[k], zk1 = zr[k + 1];
+        zr[k] = c * zk - s * zk1;
+        zr[k + 1] = s * zk + c * zk1;
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) w[i] = d[i];
+  return PNOEOM_OK;
+}
+
+}  // namespace
+
+int host_syev(int n, const double* a, double* w, double* v) {
+  if (n < 1 || !a || !w || !v) return PNOEOM_EINVAL;
+  std::vector<double> work(a, a + (int64_t)n * n);
+  return syev_one(n, work.data(), w, v);
+}
+
+int host_syev_batched(int nmat, const int* nsz, int ld, double* A, double* ev, double* Vt, int nthreads) {
+  // A[m]: nsz[m] x nsz[m] in an ld x ld slot (destroyed); ev[m*ld + k]; Vt[m] row k = eigenvector k
+  if (nmat <= 0) return PNOEOM_OK;
+  if (nthreads < 1) nthreads = 1;
+  std::atomic<int> next(0), status(PNOEOM_OK);
+  auto work = [&]() {
+    std::vector<double> a, z, w;
+    for (;;) {
+      const int m = next.fetch_add(1);
+      if (m >= nmat) break;
+      const int n = nsz[m];
+      if (n <= 0) continue;
+      a.resize((size_t)n * n);
+      z.resize((size_t)n * n);
+      w.resize(n);
+      const int64_t base = (int64_t)m * ld * ld;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) a[(size_t)i * n + j] = A[base + (int64_t)i * ld + j];
+      const int st = syev_one(n, a.data(), w.data(), z.data());
+      if (st != PNOEOM_OK) status = st;
+      for (int k = 0; k < n; ++k) {
+        ev[(int64_t)m * ld + k] = w[k];
+        for (int i = 0; i < n; ++i) Vt[base + (int64_t)k * ld + i] = z[(size_t)i * n + k];
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  const int nt = std::min(nthreads, nmat);
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
+  return status.load();
 }
 
 }  // namespace pnoeom

@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <thread>
+
 #include "context.h"
 
 namespace pnoeom {
@@ -230,11 +232,41 @@ __global__ void sym_diag_blocks_kernel(int ndiag, const int64_t* __restrict__ of
 
 }  // namespace
 
+// Batched symmetric eigenproblems of matrices up to nmax: the one-workgroup Jacobi
+// kernel while its O(n^3) HBM traffic per sweep is small (n <= kJacobiMaxN); above
+// that, the matrices go to the host and are solved there in parallel (Householder
+// tridiagonalisation + implicit QR, csrc/eig.cpp), which is far faster than a
+// memory-bound per-matrix sweep.  Same output layout either way.
+constexpr int kJacobiMaxN = 128;
+
+void batched_syev(hipStream_t s, int nmat, const std::vector<int>& nsz, int ld, double* A, double* Vt, double* ev,
+                  int* dn) {
+  int nmax = 0;
+  for (int m = 0; m < nmat; ++m) nmax = std::max(nmax, nsz[m]);
+  if (nmax <= kJacobiMaxN) {
+    PNO_HIP(hipMemcpyAsync(dn, nsz.data(), nmat * sizeof(int), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(jacobi_kernel, dim3(nmat), dim3(256), 0, s, ld, (const int*)dn, A, Vt, ev, 60);
+    PNO_HIP(hipGetLastError());
+    PNO_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  const size_t tot = (size_t)nmat * ld * ld;
+  std::vector<double> Ah(tot), Vh(tot, 0.0), eh((size_t)nmat * ld, 0.0);
+  PNO_HIP(hipMemcpyAsync(Ah.data(), A, tot * sizeof(double), hipMemcpyDeviceToHost, s));
+  PNO_HIP(hipStreamSynchronize(s));
+  const int hw = (int)std::thread::hardware_concurrency();
+  const int nthreads = std::max(1, std::min(16, hw));
+  const int st = host_syev_batched(nmat, nsz.data(), ld, Ah.data(), eh.data(), Vh.data(), nthreads);
+  PNO_CHECK(st == PNOEOM_OK, st, "build_sapno: symmetric eigensolver did not converge");
+  PNO_HIP(hipMemcpyAsync(Vt, Vh.data(), tot * sizeof(double), hipMemcpyHostToDevice, s));
+  PNO_HIP(hipMemcpyAsync(ev, eh.data(), eh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  PNO_HIP(hipStreamSynchronize(s));
+}
+
 // ----------------------------------------------------------------------------- build
 void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
   PNO_CHECK(c.have_df, PNOEOM_ESTATE, "build_sapno before build_df");
   PNO_CHECK(nstates >= 1 && nstates <= c.ov(), PNOEOM_EINVAL, "build_sapno: bad nstates");
-  PNO_CHECK(c.v <= 2048, PNOEOM_EINVAL, "build_sapno: v > 2048 exceeds the Jacobi kernel's pair table");
   hipStream_t s = c.stream;
   PNOData& P = c.pno;
   P.reset();
@@ -311,10 +343,7 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
   D.release();
   {
     std::vector<int> nv(npair, v);
-    PNO_HIP(hipMemcpyAsync(dn, nv.data(), npair * sizeof(int), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(256), 0, s, v, (const int*)dn, (double*)Dp, (double*)Vt,
-                       (double*)ev, 60);
-    PNO_HIP(hipGetLastError());
+    batched_syev(s, npair, nv, v, Dp, Vt, ev, dn);
   }
   std::vector<double> evh((size_t)npair * v);
   PNO_HIP(hipMemcpyAsync(evh.data(), ev, evh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -409,10 +438,7 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
     gemm_grouped(t2, 1.0, U0, Tb, 0.0, Fb, s);
     DBuf<int> dnb;
     dnb.alloc(nblk);
-    PNO_HIP(hipMemcpyAsync(dnb, bn.data(), nblk * sizeof(int), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(jacobi_kernel, dim3(nblk), dim3(256), 0, s, nmax, (const int*)dnb, (double*)Fb, (double*)Wt,
-                       (double*)fev, 60);
-    PNO_HIP(hipGetLastError());
+    batched_syev(s, nblk, bn, nmax, Fb, Wt, fev, dnb);
     P.U.alloc(std::max<int64_t>(utot, 1));
     gemm_grouped(t3, 1.0, U0, Wt, 0.0, P.U, s);
     PNO_HIP(hipStreamSynchronize(s));

@@ -20,7 +20,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "
           -7: "EABORTED"}
 EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pnoeom_build_df", "pnoeom_cis",
                     "pnoeom_build_sapno", "pnoeom_pno_layout", "pnoeom_pno_transform", "pnoeom_apply_sigma", "pnoeom_davidson_defaults",
-                    "pnoeom_davidson", "pnoeom_host_eig", "pnoeom_last_timing", "pnoeom_last_ladder_timing"]
+                    "pnoeom_davidson", "pnoeom_host_eig", "pnoeom_last_timing", "pnoeom_last_ladder_timing",
+                    "pnoeom_host_syev"]
 
 
 class PnoEomError(RuntimeError):
@@ -68,6 +69,7 @@ def load_library():
     lib.pnoeom_host_eig.argtypes = [C.c_int, dp, dp, dp, dp]
     lib.pnoeom_last_timing.argtypes = [vp, dp, dp, ip, dp]
     lib.pnoeom_last_ladder_timing.argtypes = [vp, C.c_int, dp, ip, dp]
+    lib.pnoeom_host_syev.argtypes = [C.c_int, dp, dp, dp]
     _LIB = lib
     return lib
 
@@ -88,6 +90,20 @@ def host_eig(a: np.ndarray, vectors: bool = True):
     if st != 0:
         raise PnoEomError(st, "host_eig failed")
     return wr + 1j * wi, vr
+
+
+def host_syev(a: np.ndarray):
+    """Eigenvalues (unordered) and unit eigenvectors (columns) of a symmetric matrix,
+    by the library's host solver (the one the PNO build uses for large blocks)."""
+    lib = load_library()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    n = a.shape[0]
+    w = np.zeros(n)
+    v = np.zeros((n, n))
+    st = lib.pnoeom_host_syev(n, _dptr(a), _dptr(w), _dptr(v))
+    if st != 0:
+        raise PnoEomError(st, "host_syev failed")
+    return w, v
 
 
 def _dev(t, shape=None, name="tensor"):

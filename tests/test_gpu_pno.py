@@ -75,6 +75,26 @@ def test_sapno_counts_and_projector(o, v, naux, kappa, nst, tcut, seed):
     assert np.max(np.abs(f2[0] - q2)) <= 1e-9 * np.max(np.abs(q2))
 
 
+def test_sapno_large_blocks_use_host_eigensolver():
+    """v = 136 > 128: the pair densities (and large semicanonical blocks) are
+    diagonalised by the library's host solver; counts exact, projector 1e-9."""
+    print("[sapno large v]", flush=True)
+    import torch
+    o, v, naux, nst, tcut = 3, 136, 60, 2, 1e-6
+    s = make_system(o, v, naux, 31, kappa=0.5, t1_sigma=1e-3)
+    ctx = _ctx(s)
+    npno, nosv = ctx.build_sapno(nst, tcut)
+    _, pb, _ = _oracle_basis(s, nst, tcut)
+    assert np.array_equal(npno, pb.npno()) and np.array_equal(nosv, pb.nosv())
+    assert npno.max() > 0 and npno.sum() < v * v * len(npno)
+    r1, r2 = random_r(o, v, 41, nvec=1)
+    x = ctx.pno_compress(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda())
+    e1, e2 = ctx.pno_expand(x)
+    p1, p2 = pb.project(r1[0], r2[0])
+    assert np.max(np.abs(e1.cpu().numpy()[0] - p1)) <= 1e-9 * np.max(np.abs(p1))
+    assert np.max(np.abs(e2.cpu().numpy()[0] - p2)) <= 1e-9 * np.max(np.abs(p2))
+
+
 def test_pno_davidson_matches_oracle_dense():
     print("[pno davidson dense]", flush=True)
     from oracle.davidson import dense_eom

@@ -59,3 +59,37 @@ def test_host_eig_nearly_symmetric_degenerate():
 def test_host_eig_rejects_bad_input():
     lib = _lib()
     assert lib.pnoeom_host_eig(0, None, None, None, None) == -1
+
+
+@pytest.mark.parametrize("n,seed,kind", [(1, 0, "rand"), (2, 1, "rand"), (3, 2, "rand"), (40, 3, "rand"),
+                                         (161, 4, "rand"), (130, 5, "decay"), (50, 6, "degenerate"),
+                                         (30, 7, "zero"), (60, 8, "diag")])
+def test_host_syev_matches_lapack(n, seed, kind):
+    """The host symmetric eigensolver of the PNO build: eigenvalues against LAPACK,
+    residual and orthonormality of the vectors, on random, fast-decaying (pair-density
+    like), degenerate, zero and diagonal matrices."""
+    _lib()
+    from paper_1802_06738_amd import host_syev
+    rng = np.random.default_rng(seed)
+    if kind == "rand":
+        x = rng.standard_normal((n, n))
+        a = x + x.T
+    elif kind == "decay":
+        q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        d = np.sign(rng.standard_normal(n)) * 10.0 ** rng.uniform(-14, -1, n)
+        a = (q * d) @ q.T
+    elif kind == "degenerate":
+        q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        d = np.repeat(np.arange(n // 5), 5).astype(float)
+        a = (q * d) @ q.T
+    elif kind == "zero":
+        a = np.zeros((n, n))
+    else:
+        a = np.diag(rng.standard_normal(n))
+    a = 0.5 * (a + a.T)
+    w, v = host_syev(a)
+    ref = np.linalg.eigvalsh(a)
+    scale = max(1.0, np.abs(ref).max())
+    assert np.max(np.abs(np.sort(w) - ref)) <= 1e-12 * scale
+    assert np.max(np.abs(a @ v - v * w)) <= 1e-12 * scale
+    assert np.max(np.abs(v.T @ v - np.eye(n))) <= 1e-12
