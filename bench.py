@@ -84,7 +84,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-pno", action="store_true")
-    ap.add_argument("--tcut", type=float, default=1e-7)
+    ap.add_argument("--tcut", type=float, default=None, help="PNO cut (default: the config's, else 1e-7)")
+    ap.add_argument("--mixed", default="fp32,bf16", help="mixed precisions to run (comma list)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -98,7 +99,7 @@ def main():
     s = config_system(args.config)
     o, v, naux, nroots = s.o, s.v, s.naux, cfg["nroots"]
     tol_e = cfg["tol_e"]
-    tol_r = 1e-5
+    tol_r = cfg.get("tol_r", 1e-5)
     max_sub = cfg.get("max_sub", 60)
     dev = torch.device("cuda:0")
     B = torch.from_numpy(s.B).to(dev)
@@ -119,7 +120,12 @@ def main():
         print(f"[bench] {tag}: {args.steps} steps in {dt:.2f} s", file=sys.stderr, flush=True)
         return res, dt
 
-    res64, dt64 = measure(FP64)
+    # configs defined in the PNO space run there only: the canonical Davidson subspace
+    # (2 x max_sub full vectors) does not fit next to W+/- at v = 400
+    pno_only = cfg.get("space", "canonical") == "pno"
+    tcut = args.tcut if args.tcut is not None else cfg.get("tcut", 1e-7)
+    head_pno = (nroots, tcut) if pno_only else None
+    res64, dt64 = measure(FP64, head_pno)
     nsig = sum(r["nsigma"] for r in res64)
     lad_ms = sum(r["timing"]["ladder_ms"] for r in res64)
     lad_fl = sum(r["timing"]["ladder_flops"] for r in res64)
@@ -129,7 +135,7 @@ def main():
     avg_ms = lad_ms / max(lad_n, 1)
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
     out = {
-        "metric": "sigma evals/s & Davidson time-to-convergence (canonical FP64; FP32 and BF16 mixed variants)",
+        "metric": "sigma evals/s & Davidson time-to-convergence (FP64; FP32 and BF16 mixed variants; PNO vs canonical)",
         "value": nsig / dt64,
         "unit": "sigma-evals/s",
         "n_gpus": 1,
@@ -141,9 +147,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"config {args.config}: canonical EOM-CCSD, o={o}, v={v}, naux={naux}, "
-                               f"{nroots} roots, tol_e={tol_e}, max_sub={max_sub}",
-                   "o": o, "v": v, "naux": naux, "nroots": nroots},
+        "config": {"workload": f"config {args.config}: "
+                               + (f"SA-PNO-EOM-CCSD (T_cut={tcut:g})" if pno_only else "canonical EOM-CCSD")
+                               + f", o={o}, v={v}, naux={naux}, {nroots} roots, tol_e={tol_e}, max_sub={max_sub}",
+                   "o": o, "v": v, "naux": naux, "nroots": nroots, "space": "pno" if pno_only else "canonical"},
         "time_to_convergence_s": dt64 / args.steps,
         "sigma_per_step": nsig / args.steps,
         "iters_per_step": res64[-1]["iters"],
@@ -163,9 +170,18 @@ def main():
         ref = np.array(g.get("davidson", g.get("dense_eig", []))[:nroots])
         if ref.size == nroots:
             out["max_abs_err_vs_oracle_eh"] = float(np.max(np.abs(omega64 - ref)))
-    if not args.no_mixed:
+    if pno_only:
+        npno = np.asarray(res64[-1]["npno"])
+        out["pno"] = {"tcut": tcut, "npno_mean": float(npno.mean()), "npno_min": int(npno.min()),
+                      "npno_max": int(npno.max()),
+                      "note": "step = build_df + build_sapno + PNO-space Davidson (back-transform, canonical "
+                              "sigma, projection)"}
+    mixed = [] if args.no_mixed else [m for m in args.mixed.split(",") if m]
+    if mixed:
         for prec, name in ((FP32, "fp32"), (BF16, "bf16")):
-            resm, dtm = measure(prec)
+            if name not in mixed:
+                continue
+            resm, dtm = measure(prec, head_pno)
             om = resm[-1]["omega"]
             lm = sum(r["timing"][name]["ladder_ms"] for r in resm)
             nm = sum(r["timing"][name]["ladder_launches"] for r in resm)
@@ -182,14 +198,14 @@ def main():
                 "note": (("FP32-MFMA" if name == "fp32" else "bfloat16-MFMA ladder (FP32 accumulation), FP32 other")
                          + " contractions until convergence, then FP64 sigma refinement from those roots"),
             }
-    if not args.no_pno:
+    if not args.no_pno and not pno_only:
         # SA-PNO space (pair densities averaged over the nroots lowest CIS states)
-        pno = (nroots, args.tcut)
+        pno = (nroots, tcut)
         resp, dtp = measure(FP64, pno)
         omp = resp[-1]["omega"]
         npno = np.asarray(resp[-1]["npno"])
         out["pno_fp64"] = {
-            "tcut": args.tcut, "npno_mean": float(npno.mean()), "npno_min": int(npno.min()),
+            "tcut": tcut, "npno_mean": float(npno.mean()), "npno_min": int(npno.min()),
             "npno_max": int(npno.max()),
             "time_to_convergence_s": dtp / args.steps,
             "speedup_vs_canonical_fp64": dt64 / dtp,
@@ -199,11 +215,11 @@ def main():
             "note": "step = build_df + build_sapno + PNO-space Davidson (back-transform, canonical sigma, "
                     "projection); the difference from the canonical roots is the PNO truncation",
         }
-        if not args.no_mixed:
+        if "bf16" in mixed:
             resb, dtb = measure(BF16, pno)
             omb = resb[-1]["omega"]
             out["pno_mixed_bf16"] = {
-                "tcut": args.tcut,
+                "tcut": tcut,
                 "time_to_convergence_s": dtb / args.steps,
                 "speedup_vs_canonical_fp64": dt64 / dtb,
                 "sigma_evals_per_s": sum(r["nsigma"] for r in resb) / dtb,
@@ -211,8 +227,12 @@ def main():
                 "note": "BF16 ladder / FP32 other contractions, FP64 refinement, PNO space",
             }
     if not args.no_cpu_baseline:
-        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.config)
+        if v > 200:
+            # the oracle's sigma holds the dense v^4 ladder matrix (205 GB at v = 400)
+            out["cpu_baseline"] = None
+        else:
+            print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+            out["cpu_baseline"] = cpu_baseline(args.config)
     print(json.dumps(out), flush=True)
 
 

@@ -79,6 +79,7 @@ const char* pnoeom_last_error(const pnoeom_ctx* ctx);
  *               BF16: the particle ladder runs on bfloat16 operands (W+/- and the
  *               packed trial amplitudes, rounded to nearest even) with FP32
  *               accumulation; the other large contractions run in FP32.
+ * Discards the workspaces and SA-PNOs of an earlier build_df (build_sapno again).
  * Errors: EINVAL (null B/eps, bad precision), ENOMEM, EHIP. */
 int pnoeom_build_df(pnoeom_ctx* ctx, const double* B, const double* eps, const double* t1,
                     const double* t2, int precision);

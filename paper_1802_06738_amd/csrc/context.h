@@ -17,6 +17,15 @@ struct SigmaWork {
   DBuf<uint16_t> Spb, Amb;  // bfloat16 bits, rows padded to the W+/- column padding
   // FP32 staging for the mixed-precision contractions
   DBuf<float> fa, fb, fc;
+  void release() {
+    for (DBuf<double>* b : {&Bp, &hp, &Jp, &Kp, &fp, &dp, &fp_ov, &fp_vv, &fp_oo, &BvopT, &BoopT, &BvvpT, &R2c, &Ria,
+                            &Rsia, &UiaR, &UR, &URp, &Ubr, &Ziajb, &Z3, &Dtot, &Xtot, &DXtot, &Zp, &Cba, &Xh, &O4p,
+                            &OOVVp, &M1, &Ftv, &Fto, &LadAll, &Sp, &Am, &SigP, &SigM})
+      b->release();
+    for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fb, &fc}) b->release();
+    Spb.release();
+    Amb.release();
+  }
 };
 
 struct PNOData {

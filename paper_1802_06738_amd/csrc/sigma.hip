@@ -255,6 +255,12 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   const int64_t oovv = c.oovv();
   c.have_df = false;
   c.precision = precision;
+  // workspaces and bases of the previous intermediates are dropped first, so that the
+  // new ones (e.g. a second copy of W+/- in another precision) have the memory
+  c.sw.release();
+  c.pno.reset();
+  if (precision == PNOEOM_FP64)
+    for (DBuf<float>* b : {&c.Tf, &c.Tiaf, &c.Tsiaf, &c.Drf, &c.Xrf, &c.DX2f, &c.GXf}) b->release();
 
   c.B.alloc((int64_t)naux * n2);
   c.eps.alloc(nmo);
@@ -498,13 +504,15 @@ int64_t rest_bytes_per_vector(const Context& c, bool f32) {
 }
 
 // number of vectors per sigma_rest_block call: as many as fit in the free device
-// memory (plus what the work arrays already hold), leaving 1 GiB of headroom
+// memory (plus what the work arrays already hold), leaving a tenth of the device
+// (at least 2 GiB) to the caller
 int rest_chunk(const Context& c, int nvec, bool f32) {
   const int64_t per = rest_bytes_per_vector(c, f32);
   size_t freeb = 0, totalb = 0;
   PNO_HIP(hipMemGetInfo(&freeb, &totalb));
   const int64_t held = c.oovv() > 0 ? (int64_t)(c.sw.Ria.n / c.oovv()) * per : 0;
-  const int64_t avail = (int64_t)freeb + held - (1ll << 30);
+  const int64_t headroom = std::max<int64_t>(2ll << 30, (int64_t)totalb / 10);
+  const int64_t avail = (int64_t)freeb + held - headroom;
   int64_t nb = avail > 0 ? avail / per : 0;
   return (int)std::max<int64_t>(1, std::min<int64_t>(nb, nvec));
 }
