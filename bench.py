@@ -31,7 +31,7 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}    # MI355X dense matrix TF
 HBM_PEAK = 8000.0                       # GB/s
 
 
-def run_steps(ctx, B, eps, t1, nroots, prec, steps, tol_e, tol_r, max_sub, pno=None):
+def run_steps(ctx, B, eps, t1, nroots, prec, steps, tol_e, tol_r, max_sub, pno=None, verbose=False):
     """One step: build_df (+ build_sapno when pno = (nstates, tcut)) + Davidson."""
     import torch
     from paper_1802_06738_amd import FP64, CANONICAL, PNO
@@ -42,7 +42,7 @@ def run_steps(ctx, B, eps, t1, nroots, prec, steps, tol_e, tol_r, max_sub, pno=N
         if pno is not None:
             npno, _ = ctx.build_sapno(pno[0], pno[1])
         r = ctx.davidson(nroots, space=CANONICAL if pno is None else PNO, precision=prec, tol_e=tol_e,
-                         tol_r=tol_r, max_sub=max_sub, refine_fp64=(prec != FP64))
+                         tol_r=tol_r, max_sub=max_sub, refine_fp64=(prec != FP64), verbose=verbose)
         r["timing"] = ctx.last_timing()
         r["npno"] = npno
         res.append(r)
@@ -107,14 +107,16 @@ def main():
     t1 = torch.from_numpy(s.t1).to(dev)
     torch.cuda.synchronize()
     ctx = PnoEom(o, v, naux)
+    # long steps (v = 400: minutes) report each Davidson iteration on stderr
+    verbose = v > 200
 
     def measure(prec, pno=None):
         tag = f"precision {prec}" + ("" if pno is None else f", PNO tcut {pno[1]:g}")
-        run_steps(ctx, B, eps, t1, nroots, prec, args.warmup, tol_e, tol_r, max_sub, pno)
+        run_steps(ctx, B, eps, t1, nroots, prec, args.warmup, tol_e, tol_r, max_sub, pno, verbose)
         torch.cuda.synchronize()
         print(f"[bench] {tag}: warmup done", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        res = run_steps(ctx, B, eps, t1, nroots, prec, args.steps, tol_e, tol_r, max_sub, pno)
+        res = run_steps(ctx, B, eps, t1, nroots, prec, args.steps, tol_e, tol_r, max_sub, pno, verbose)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         print(f"[bench] {tag}: {args.steps} steps in {dt:.2f} s", file=sys.stderr, flush=True)

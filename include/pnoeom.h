@@ -140,7 +140,7 @@ typedef struct {
   int max_sub;         /* largest subspace before collapse to the Ritz vectors */
   int max_iter;        /* iteration limit (ENOTCONV when reached) */
   int refine_fp64;     /* precision FP32/BF16: finish with FP64 sigma from the converged roots */
-  int verbose;         /* 1: print one line per iteration to stdout */
+  int verbose;         /* 1: print one line per iteration to stderr */
   int nextra;          /* further Ritz pairs tracked and kept at collapse (need not converge) */
 } pnoeom_davidson_opts;
 

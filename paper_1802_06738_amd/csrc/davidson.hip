@@ -366,10 +366,10 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
     res.omega.assign(theta.begin(), theta.begin() + ntarget);
     res.resnorm.assign(rn.begin(), rn.begin() + ntarget);
     if (opt.verbose) {
-      printf("[%s] it %3d m %3d", tag, it, m);
-      for (int k = 0; k < ntarget; ++k) printf(" %.10f(%.1e)", theta[k], rn[k]);
-      printf("\n");
-      fflush(stdout);
+      fprintf(stderr, "[%s] it %3d m %3d", tag, it, m);
+      for (int k = 0; k < ntarget; ++k) fprintf(stderr, " %.10f(%.1e)", theta[k], rn[k]);
+      fprintf(stderr, "\n");
+      fflush(stderr);
     }
     if (all) {
       res.converged = true;
