@@ -97,11 +97,11 @@ def make_system(o: int, v: int, naux: int, seed: int, *, sigma_b: float | None =
 CONFIGS = {
     1: dict(o=4, v=20, naux=60, t1_sigma=0.0, kappa=0.0, nroots=3, tol_e=1e-8,
             space="canonical"),
-    2: dict(o=20, v=150, naux=450, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-8,
-            max_sub=60, space="canonical"),
-    3: dict(o=40, v=400, naux=1200, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-6, tol_r=1e-4,
+    2: dict(o=20, v=150, naux=450, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-8, tol_r=3e-6,
+            max_sub=60, nextra=4, space="canonical"),
+    3: dict(o=40, v=400, naux=1200, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-6, tol_r=1e-4, nextra=4,
             tcut=1e-7, space="pno"),
-    4: dict(o=40, v=400, naux=1200, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-6, tol_r=1e-4,
+    4: dict(o=40, v=400, naux=1200, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-6, tol_r=1e-4, nextra=4,
             tcut=1e-7, space="pno"),
     5: dict(o=60, v=900, naux=2700, t1_sigma=1e-3, kappa=0.0, nroots=12, tol_e=1e-6, tol_r=1e-4,
             tcut=1e-7, space="pno"),
