@@ -32,7 +32,8 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}    # MI355X dense matrix TF
 HBM_PEAK = 8000.0                       # GB/s
 
 
-def run_steps(ctx, B, eps, t1, nroots, prec, steps, tol_e, tol_r, max_sub, pno=None, verbose=False, nextra=0):
+def run_steps(ctx, B, eps, t1, nroots, prec, steps, tol_e, tol_r, max_sub, pno=None, verbose=False, nextra=0,
+              mixed_tol=(0.0, 0.0)):
     """One step: build_df (+ build_sapno when pno = (nstates, tcut)) + Davidson."""
     import torch
     from paper_1802_06738_amd import FP64, CANONICAL, PNO
@@ -44,7 +45,7 @@ def run_steps(ctx, B, eps, t1, nroots, prec, steps, tol_e, tol_r, max_sub, pno=N
             npno, _ = ctx.build_sapno(pno[0], pno[1])
         r = ctx.davidson(nroots, space=CANONICAL if pno is None else PNO, precision=prec, tol_e=tol_e,
                          tol_r=tol_r, max_sub=max_sub, refine_fp64=(prec != FP64), verbose=verbose,
-                         nextra=nextra)
+                         nextra=nextra, mixed_tol_e=mixed_tol[0], mixed_tol_r=mixed_tol[1])
         r["timing"] = ctx.last_timing()
         r["npno"] = npno
         res.append(r)
@@ -104,6 +105,7 @@ def main():
     tol_r = cfg.get("tol_r", 1e-5)
     max_sub = cfg.get("max_sub", 60)
     nextra = cfg.get("nextra", 0)   # further Ritz pairs tracked (speeds up the highest wanted root)
+    mixed_tol = (cfg.get("mixed_tol_e", 0.0), cfg.get("mixed_tol_r", 0.0))  # mixed phase before FP64 refinement
     dev = torch.device("cuda:0")
     B = torch.from_numpy(s.B).to(dev)
     eps = torch.from_numpy(s.eps).to(dev)
@@ -115,11 +117,12 @@ def main():
 
     def measure(prec, pno=None):
         tag = f"precision {prec}" + ("" if pno is None else f", PNO tcut {pno[1]:g}")
-        run_steps(ctx, B, eps, t1, nroots, prec, args.warmup, tol_e, tol_r, max_sub, pno, verbose, nextra)
+        run_steps(ctx, B, eps, t1, nroots, prec, args.warmup, tol_e, tol_r, max_sub, pno, verbose, nextra, mixed_tol)
         torch.cuda.synchronize()
         print(f"[bench] {tag}: warmup done", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        res = run_steps(ctx, B, eps, t1, nroots, prec, args.steps, tol_e, tol_r, max_sub, pno, verbose, nextra)
+        res = run_steps(ctx, B, eps, t1, nroots, prec, args.steps, tol_e, tol_r, max_sub, pno, verbose, nextra,
+                        mixed_tol)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         print(f"[bench] {tag}: {args.steps} steps in {dt:.2f} s", file=sys.stderr, flush=True)

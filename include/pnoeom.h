@@ -142,10 +142,12 @@ typedef struct {
   int refine_fp64;     /* precision FP32/BF16: finish with FP64 sigma from the converged roots */
   int verbose;         /* 1: print one line per iteration to stderr */
   int nextra;          /* further Ritz pairs tracked and kept at collapse (need not converge) */
+  double mixed_tol_e;  /* refine_fp64: bounds of the FP32/BF16 phase before the FP64 refinement; */
+  double mixed_tol_r;  /*   <= 0 selects tol_e / tol_r (the final bounds are always tol_e, tol_r) */
 } pnoeom_davidson_opts;
 
 /* Fill opts with the defaults (canonical, FP64, tol_e 1e-8, tol_r 1e-5, max_sub 60,
- * max_iter 200, nextra 0). */
+ * max_iter 200, nextra 0, mixed_tol_e = mixed_tol_r = 0). */
 void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts);
 
 /* Lowest-real-part EOM-CCSD roots by the Davidson method with the PNO

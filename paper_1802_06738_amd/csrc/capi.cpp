@@ -194,6 +194,8 @@ void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts) {
   opts->refine_fp64 = 0;
   opts->verbose = 0;
   opts->nextra = 0;
+  opts->mixed_tol_e = 0.0;
+  opts->mixed_tol_r = 0.0;
 }
 
 int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opts, double* omega_out,

@@ -640,7 +640,13 @@ DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt)
   };
   DBuf<double> xr;
   xr.alloc((int64_t)nroots * op.N);
-  DavidsonResult r = run_davidson(c, op, nroots, guess, nk, opt,
+  // a mixed phase that is refined afterwards stops at its own (looser) bounds
+  pnoeom_davidson_opts mopt = opt;
+  if (prec != PNOEOM_FP64 && opt.refine_fp64) {
+    if (opt.mixed_tol_e > 0) mopt.tol_e = opt.mixed_tol_e;
+    if (opt.mixed_tol_r > 0) mopt.tol_r = opt.mixed_tol_r;
+  }
+  DavidsonResult r = run_davidson(c, op, nroots, guess, nk, mopt,
                                   prec == PNOEOM_FP32 ? "eom-fp32" : prec == PNOEOM_BF16 ? "eom-bf16" : "eom", xr,
                                   opt.nextra);
   if (prec != PNOEOM_FP64 && opt.refine_fp64 && r.converged) {

@@ -98,7 +98,7 @@ CONFIGS = {
     1: dict(o=4, v=20, naux=60, t1_sigma=0.0, kappa=0.0, nroots=3, tol_e=1e-8,
             space="canonical"),
     2: dict(o=20, v=150, naux=450, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-8, tol_r=3e-6,
-            max_sub=60, nextra=4, space="canonical"),
+            max_sub=60, nextra=4, mixed_tol_e=1e-7, mixed_tol_r=1e-5, space="canonical"),
     3: dict(o=40, v=400, naux=1200, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-6, tol_r=1e-4, nextra=4,
             tcut=1e-7, space="pno"),
     4: dict(o=40, v=400, naux=1200, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-6, tol_r=1e-4, nextra=4,
