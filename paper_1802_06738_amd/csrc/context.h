@@ -10,19 +10,19 @@ struct SigmaWork {
   DBuf<double> Bp, hp, Jp, Kp, fp, dp, fp_ov, fp_vv, fp_oo;
   DBuf<double> BvopT, BoopT, BvvpT;
   DBuf<double> R2c, Ria, Rsia, UiaR, UR, URp, Ubr;
-  DBuf<double> Ziajb, Z3, Dtot, Xtot, DXtot, Zp, Cba, Xh, O4p, OOVVp, M1;
+  DBuf<double> Ziajb, Z3, EXT, Zp, Cba, Xh, O4p, OOVVp, M1;
   DBuf<double> Ftv, Fto;
   DBuf<double> LadAll, Sp, Am, SigP, SigM;  // batched packed ladder
   DBuf<float> Spf, Amf, SigPf, SigMf;
   DBuf<uint16_t> Spb, Amb;  // bfloat16 bits, rows padded to the W+/- column padding
   // FP32 staging for the mixed-precision contractions
-  DBuf<float> fa, fb, fc;
+  DBuf<float> fa, fc;
   void release() {
     for (DBuf<double>* b : {&Bp, &hp, &Jp, &Kp, &fp, &dp, &fp_ov, &fp_vv, &fp_oo, &BvopT, &BoopT, &BvvpT, &R2c, &Ria,
-                            &Rsia, &UiaR, &UR, &URp, &Ubr, &Ziajb, &Z3, &Dtot, &Xtot, &DXtot, &Zp, &Cba, &Xh, &O4p,
+                            &Rsia, &UiaR, &UR, &URp, &Ubr, &Ziajb, &Z3, &EXT, &Zp, &Cba, &Xh, &O4p,
                             &OOVVp, &M1, &Ftv, &Fto, &LadAll, &Sp, &Am, &SigP, &SigM})
       b->release();
-    for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fb, &fc}) b->release();
+    for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fc}) b->release();
     Spb.release();
     Amb.release();
   }
@@ -71,13 +71,13 @@ struct Context {
   // integrals / intermediates
   DBuf<double> G, GX, g2, Gq, OVVO, OOVVx, Wh, OOOVp;
   DBuf<double> Fqvv, Fqoo, Fvv, Foo, fd_ov;
-  DBuf<double> Dr, Xr, DX2, Wvo2;
+  DBuf<double> Dr, Xr, DX2, Wvo2, YU;
   // packed ladder: W+[(a<=b),(c<=d)] = W_abcd + W_abdc, W-[(a<b),(c<d)] = W_abcd - W_abdc
   DBuf<double> Wp, Wm;          // FP64 (always: the FP64 sigma and the refinement of mixed runs)
   DBuf<float> Wpf, Wmf;         // FP32 (precision FP32)
   DBuf<uint16_t> Wpb, Wmb;      // bfloat16 bits (precision BF16), rows padded to ldpb / ldmb columns
   int64_t ldpb = 0, ldmb = 0;
-  DBuf<float> Tf, Tiaf, Tsiaf, Drf, Xrf, DX2f, GXf;
+  DBuf<float> Tf, Tiaf, Tsiaf, Drf, Xrf, DX2f;
   DBuf<double> scratch;         // build-time temporaries
 
   SigmaWork sw;

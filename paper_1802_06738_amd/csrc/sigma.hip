@@ -37,18 +37,6 @@ void gmb(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, doubl
   gemm(d, s);
 }
 
-// mixed precision: C(double) = alpha op(A) op(B) + beta C with FP32 operands and FP32
-// accumulation; fa/fb/fc are staging buffers large enough for A, B and C.
-void gmf(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const float* A,
-         int64_t lda, const float* B, int64_t ldb, double beta, double* C, int64_t ldc, float* fc) {
-  GemmDesc<float> d;
-  d.ta = ta; d.tb = tb; d.M = M; d.N = N; d.K = K; d.alpha = (float)alpha; d.beta = 0.f;
-  d.A = A; d.lda = lda; d.B = B; d.ldb = ldb; d.C = fc; d.ldc = N;
-  gemm(d, s);
-  PNO_CHECK(ldc == N, PNOEOM_EINVAL, "gmf: C must be contiguous");
-  to_double(s, M * N, fc, C, beta);
-}
-
 // contiguous out[d0][d1][d2][d3] = alpha * in[i0*is0 + ...] + beta * out
 void ext(hipStream_t s, int64_t d0, int64_t d1, int64_t d2, int64_t d3, int64_t is0, int64_t is1, int64_t is2,
          int64_t is3, const double* in, double* out, double alpha = 1.0, double beta = 0.0) {
@@ -260,7 +248,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   c.sw.release();
   c.pno.reset();
   if (precision == PNOEOM_FP64)
-    for (DBuf<float>* b : {&c.Tf, &c.Tiaf, &c.Tsiaf, &c.Drf, &c.Xrf, &c.DX2f, &c.GXf}) b->release();
+    for (DBuf<float>* b : {&c.Tf, &c.Tiaf, &c.Tsiaf, &c.Drf, &c.Xrf, &c.DX2f}) b->release();
 
   c.B.alloc((int64_t)naux * n2);
   c.eps.alloc(nmo);
@@ -393,17 +381,30 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   axpby(s, oo, 1.0, c.Fqoo, 1.0, c.Foo);
   ext(s, o, v, 1, 1, nmo, 1, 0, 0, c.fd + o, c.fd_ov);
 
-  // ring intermediates: D = (kc|bj)~ + Dq(T), X = (kj|bc)~ + Xq(T)  as [(k,c),(j,b)]
+  // ring intermediates as [(k,c),(j,b)]: D = (kc|bj)~ + Dq(T), X = (kj|bc)~ + Xq(T), where the
+  // exchange parts -1/2 GX T carry a second -1/2 GX T: the bilinear T-side ring terms
+  // T (GX R) of sigma are folded into them (see sigma_rest_block), hence GX T in full
   c.Dr.alloc(oovv);
   c.Xr.alloc(oovv);
   c.DX2.alloc(oovv);
   PNO_HIP(hipMemcpyAsync(c.Dr, c.OVVO, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
   gm(s, false, true, ov, ov, ov, 0.5, c.G, ov, c.UiaT, ov, 1.0, c.Dr, ov);
-  gm(s, false, true, ov, ov, ov, -0.5, c.GX, ov, c.Tia, ov, 1.0, c.Dr, ov);
+  gm(s, false, true, ov, ov, ov, -1.0, c.GX, ov, c.Tia, ov, 1.0, c.Dr, ov);
   PNO_HIP(hipMemcpyAsync(c.Xr, c.OOVVx, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
-  gm(s, false, true, ov, ov, ov, -0.5, c.GX, ov, c.Tsia, ov, 1.0, c.Xr, ov);
+  gm(s, false, true, ov, ov, ov, -1.0, c.GX, ov, c.Tsia, ov, 1.0, c.Xr, ov);
   PNO_HIP(hipMemcpyAsync(c.DX2, c.Xr, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
   axpby(s, oovv, 2.0, c.Dr, -1.0, c.DX2);
+  // YU[Q][(k,c)] = sum_(j,b) B_jb^Q (2 T - T^s)[(j,b),(k,c)]: the Coulomb (DF) part of the
+  // R-side ring intermediate contracted with T ahead of time
+  {
+    DBuf<double> U2;
+    U2.alloc(oovv);
+    PNO_HIP(hipMemcpyAsync(U2, c.Tsia, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    axpby(s, oovv, 2.0, c.Tia, -1.0, U2);
+    c.YU.alloc((int64_t)naux * ov);
+    gm(s, true, false, naux, ov, ov, 1.0, c.BovT, naux, U2, ov, 0.0, c.YU, ov);
+    PNO_HIP(hipStreamSynchronize(s));
+  }
 
   // Wvo_kbij = sum_cd (kc|bd)~ T_ij^cd stored as [(i,j,b)][k]; built in slabs of b
   c.Wvo2.alloc(oo * v * o);
@@ -475,14 +476,12 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     c.Drf.alloc(oovv);
     c.Xrf.alloc(oovv);
     c.DX2f.alloc(oovv);
-    c.GXf.alloc(oovv);
     to_float(s, oovv, c.T, c.Tf);
     to_float(s, oovv, c.Tia, c.Tiaf);
     to_float(s, oovv, c.Tsia, c.Tsiaf);
     to_float(s, oovv, c.Dr, c.Drf);
     to_float(s, oovv, c.Xr, c.Xrf);
     to_float(s, oovv, c.DX2, c.DX2f);
-    to_float(s, oovv, c.GX, c.GXf);
   }
   PNO_HIP(hipStreamSynchronize(s));
   c.have_df = true;
@@ -497,9 +496,9 @@ void grow(DBuf<T>& b, int64_t n) {
 // device memory of the per-vector work arrays of sigma_rest (bytes per vector)
 int64_t rest_bytes_per_vector(const Context& c, bool f32) {
   const int64_t ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, oovv = c.oovv();
-  int64_t nd = 15 * oovv + (ov + oo + vv) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv + oo + vv + oo;
+  int64_t nd = 13 * oovv + (ov + oo + vv) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv + oo + vv + oo;
   int64_t bytes = nd * (int64_t)sizeof(double);
-  if (f32) bytes += 3 * oovv * (int64_t)sizeof(float);
+  if (f32) bytes += 2 * oovv * (int64_t)sizeof(float);
   return bytes;
 }
 
@@ -530,12 +529,12 @@ void alloc_sigma_work(Context& c, int precision, int nb) {
   grow(w.R2c, B * oovv);
   grow(w.Ria, B * oovv); grow(w.Rsia, B * oovv); grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
   grow(w.URp, B * oovv); grow(w.Ubr, B * oovv);
-  grow(w.Ziajb, B * oovv); grow(w.Z3, B * oovv); grow(w.Dtot, B * oovv); grow(w.Xtot, B * oovv);
-  grow(w.DXtot, B * oovv); grow(w.Zp, B * oovv); grow(w.Cba, B * oovv); grow(w.OOVVp, B * oovv);
+  grow(w.Ziajb, B * oovv); grow(w.Z3, B * oovv); grow(w.EXT, B * oovv);
+  grow(w.Zp, B * oovv); grow(w.Cba, B * oovv); grow(w.OOVVp, B * oovv);
   grow(w.Xh, B * oo * oo); grow(w.O4p, B * oo * oo); grow(w.M1, B * ov * c.naux);
   grow(w.Ftv, B * vv); grow(w.Fto, B * oo);
   if (precision != PNOEOM_FP64) {
-    grow(w.fa, B * oovv); grow(w.fb, B * oovv); grow(w.fc, B * oovv);
+    grow(w.fa, B * oovv); grow(w.fc, B * oovv);
   }
 }
 
@@ -668,45 +667,43 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   gmb(s, false, false, oo, vv, oo, 1.0, w.Xh, oo, o4, c.T, vv, 0, 1.0, Sd, vv, oovv, nb);
 
   // ---------------------------------------------------------------- ring terms in [(i,a),(j,b)] form
-  gmb(s, false, true, ov, ov, naux, 0.5, w.BvopT, naux, ovn, c.BvoT, naux, 0, 0.0, w.Ziajb, ov, oovv, nb);
-  gmb(s, false, true, ov, ov, naux, 0.5, c.BvoT, naux, 0, w.BvopT, naux, ovn, 1.0, w.Ziajb, ov, oovv, nb);
-  // R-side intermediates D(R) and X(R)
-  gmb(s, false, true, ov, ov, naux, 0.5, c.BovT, naux, 0, w.M1, naux, ovn, 0.0, w.Dtot, ov, oovv, nb);
-  gmb(s, false, true, ov, ov, naux, 1.0, c.BovT, naux, 0, w.BvopT, naux, ovn, 1.0, w.Dtot, ov, oovv, nb);
+  // Ziajb and Z3 enter sigma2 only as Z + Z^T (assembly below), so any term may be
+  // added transposed.  With R_ia, R^s_ia, T_ia, T^s_ia and GX symmetric, the T-side
+  // products T (2 D(R) - X(R)) - T^s D(R) and -T^s X(R), where D(R) = E_D - 1/2 GX R,
+  // X(R) = E_X - 1/2 GX R^s, become R-side products with the T-only intermediates
+  // (whose GX T parts are doubled in build_df) plus
+  //   E_D^T (2T - T^s) = (1/2 M1 + B'_vo) YU   (DF rank naux)
+  //   -E_X^T T, -E_X^T T^s                       (E_X = (ij|ab)' in ring order)
+  // so that five (ov x ov x ov) products per vector remain.
+  gmb(s, false, true, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.BvoT, naux, 0, 0.0, w.Ziajb, ov, oovv, nb);
+  gmb(s, false, false, ov, ov, naux, 0.5, w.M1, naux, ovn, c.YU, ov, 0, 1.0, w.Ziajb, ov, oovv, nb);
+  gmb(s, false, false, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.YU, ov, 0, 1.0, w.Ziajb, ov, oovv, nb);
   gmb(s, false, true, oo, vv, naux, 1.0, w.BoopT, naux, oon, c.BvvT, naux, 0, 0.0, w.OOVVp, vv, oovv, nb);
   gmb(s, false, true, oo, vv, naux, 1.0, c.BooT, naux, 0, w.BvvpT, naux, vvn, 1.0, w.OOVVp, vv, oovv, nb);
-  perm(s, w.OOVVp, nbo, o, v, v, 0, 3, 1, 2, w.Xtot, 1.0, 0.0);
+  {
+    // EXT[(j,a),(i,b)] = (ij|ab)' = OOVVp[i][j][a][b]
+    const int64_t dims[4] = {o, o, v, v};
+    const int pp[4] = {1, 2, 0, 3};
+    permute_c(s, dims, pp, 1.0, w.OOVVp, 0.0, w.EXT, nb);
+  }
   if (f32) {
     float* fa = w.fa;
-    float* fb = w.fb;
     float* fc = w.fc;
     const int64_t nt = nb * oovv;
     to_float(s, nt, w.Ria, fa);
-    gmbf(s, false, true, ov, ov, ov, -0.5, c.GXf, ov, 0, fa, ov, oovv, 1.0, w.Dtot, nb, fc);
     gmbf(s, false, false, ov, ov, ov, 1.0, fa, ov, oovv, c.DX2f, ov, 0, 1.0, w.Ziajb, nb, fc);
     to_float(s, nt, w.Rsia, fa);
-    gmbf(s, false, true, ov, ov, ov, -0.5, c.GXf, ov, 0, fa, ov, oovv, 1.0, w.Xtot, nb, fc);
     gmbf(s, false, false, ov, ov, ov, -1.0, fa, ov, oovv, c.Drf, ov, 0, 1.0, w.Ziajb, nb, fc);
     gmbf(s, false, false, ov, ov, ov, -1.0, fa, ov, oovv, c.Xrf, ov, 0, 0.0, w.Z3, nb, fc);
-    PNO_HIP(hipMemcpyAsync(w.DXtot, w.Xtot, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
-    axpby(s, nt, 2.0, w.Dtot, -1.0, w.DXtot);
-    to_float(s, nt, w.DXtot, fb);
-    gmbf(s, false, false, ov, ov, ov, 1.0, c.Tiaf, ov, 0, fb, ov, oovv, 1.0, w.Ziajb, nb, fc);
-    to_float(s, nt, w.Dtot, fb);
-    gmbf(s, false, false, ov, ov, ov, -1.0, c.Tsiaf, ov, 0, fb, ov, oovv, 1.0, w.Ziajb, nb, fc);
-    to_float(s, nt, w.Xtot, fb);
-    gmbf(s, false, false, ov, ov, ov, -1.0, c.Tsiaf, ov, 0, fb, ov, oovv, 1.0, w.Z3, nb, fc);
+    to_float(s, nt, w.EXT, fa);
+    gmbf(s, false, false, ov, ov, ov, -1.0, fa, ov, oovv, c.Tiaf, ov, 0, 1.0, w.Ziajb, nb, fc);
+    gmbf(s, false, false, ov, ov, ov, -1.0, fa, ov, oovv, c.Tsiaf, ov, 0, 1.0, w.Z3, nb, fc);
   } else {
-    gmb(s, false, true, ov, ov, ov, -0.5, c.GX, ov, 0, w.Ria, ov, oovv, 1.0, w.Dtot, ov, oovv, nb);
-    gmb(s, false, true, ov, ov, ov, -0.5, c.GX, ov, 0, w.Rsia, ov, oovv, 1.0, w.Xtot, ov, oovv, nb);
-    PNO_HIP(hipMemcpyAsync(w.DXtot, w.Xtot, nb * oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
-    axpby(s, nb * oovv, 2.0, w.Dtot, -1.0, w.DXtot);
     gmb(s, false, false, ov, ov, ov, 1.0, w.Ria, ov, oovv, c.DX2, ov, 0, 1.0, w.Ziajb, ov, oovv, nb);
     gmb(s, false, false, ov, ov, ov, -1.0, w.Rsia, ov, oovv, c.Dr, ov, 0, 1.0, w.Ziajb, ov, oovv, nb);
     gmb(s, false, false, ov, ov, ov, -1.0, w.Rsia, ov, oovv, c.Xr, ov, 0, 0.0, w.Z3, ov, oovv, nb);
-    gmb(s, false, false, ov, ov, ov, 1.0, c.Tia, ov, 0, w.DXtot, ov, oovv, 1.0, w.Ziajb, ov, oovv, nb);
-    gmb(s, false, false, ov, ov, ov, -1.0, c.Tsia, ov, 0, w.Dtot, ov, oovv, 1.0, w.Ziajb, ov, oovv, nb);
-    gmb(s, false, false, ov, ov, ov, -1.0, c.Tsia, ov, 0, w.Xtot, ov, oovv, 1.0, w.Z3, ov, oovv, nb);
+    gmb(s, false, false, ov, ov, ov, -1.0, w.EXT, ov, oovv, c.Tia, ov, 0, 1.0, w.Ziajb, ov, oovv, nb);
+    gmb(s, false, false, ov, ov, ov, -1.0, w.EXT, ov, oovv, c.Tsia, ov, 0, 1.0, w.Z3, ov, oovv, nb);
   }
 
   // ---------------------------------------------------------------- Fock-type terms in [i][j][a][b]
