@@ -409,26 +409,42 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
         d.A = dcb; d.lda = nc; d.B = V; d.ldb = N; d.C = X; d.ldc = N;
         gemm(d, s);
       }
-      for (int q = 0; q < nc; ++q) {
-        double* xq = X + (int64_t)q * N;
-        // against the directions accepted so far in this iteration (rows m .. m+nnew-1 of V)
-        std::vector<double> cvec(std::max(nnew, 1));
-        for (int pass = 0; pass < 2 && nnew > 0; ++pass) {
-          dots(s, dw, V + (int64_t)m * N, nnew, xq, 1, N, cvec.data());
-          PNO_HIP(hipMemcpyAsync(dc, cvec.data(), nnew * sizeof(double), hipMemcpyHostToDevice, s));
-          GemmDesc<double> d;
-          d.M = 1; d.N = N; d.K = nnew; d.alpha = -1.0; d.beta = 1.0;
-          d.A = dc; d.lda = nnew; d.B = V + (int64_t)m * N; d.ldb = N; d.C = xq; d.ldc = N;
-          gemm(d, s);
+      // orthonormal basis of the block itself: two Gram passes, each X <- T^T X with
+      // T = W_k diag(w_k^-1/2) from the eigenpairs (w_k, W_k) of the block's Gram
+      // matrix, directions with w_k < 1e-20 (norm below 1e-10 after the projection
+      // against V, the vectors having been unit before it) dropped.  Two dot-product
+      // sweeps and two GEMMs replace the vector-by-vector loop.
+      int nb = nc;
+      double* src = X;
+      double* dst = V + (int64_t)m * N;
+      for (int pass = 0; pass < 2 && nb > 0; ++pass) {
+        std::vector<double> gm((size_t)nb * nb), w(nb), W((size_t)nb * nb);
+        dots(s, dw, src, nb, src, nb, N, gm.data());
+        PNO_CHECK(host_syev(nb, gm.data(), w.data(), W.data()) == PNOEOM_OK, PNOEOM_ENOTCONV,
+                  "Davidson: block Gram eigenproblem did not converge");
+        std::vector<double> Tt;  // [kept][nb], row r = (W_k / sqrt(w_k))^T
+        for (int k = 0; k < nb; ++k) {
+          if (!(w[k] >= 1e-20)) continue;
+          const double sc = 1.0 / std::sqrt(w[k]);
+          for (int i = 0; i < nb; ++i) Tt.push_back(W[(size_t)i * nb + k] * sc);
         }
-        double nn = 0.0;
-        dots(s, dw, xq, 1, xq, 1, N, &nn);
-        const double nrm = std::sqrt(nn);
-        if (!(nrm >= 1e-10)) continue;
-        hipLaunchKernelGGL(scale_kernel, dim3(g1(N)), dim3(256), 0, s, N, 1.0 / nrm, xq);
-        PNO_HIP(hipMemcpyAsync(V + (int64_t)(m + nnew) * N, xq, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-        ++nnew;
+        const int nk = (int)(Tt.size() / (size_t)std::max(nb, 1));
+        if (nk == 0) {
+          nb = 0;
+          break;
+        }
+        PNO_HIP(hipMemcpyAsync(dcb, Tt.data(), Tt.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        GemmDesc<double> d;
+        d.M = nk; d.N = N; d.K = nb; d.alpha = 1.0; d.beta = 0.0;
+        d.A = dcb; d.lda = nb; d.B = src; d.ldb = N; d.C = dst; d.ldc = N;
+        gemm(d, s);
+        nb = nk;
+        std::swap(src, dst);
       }
+      // after an even number of passes the block is back in X: move it into V
+      if (nb > 0 && src != V + (int64_t)m * N)
+        PNO_HIP(hipMemcpyAsync(V + (int64_t)m * N, src, (int64_t)nb * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      nnew = nb;
     }
     PNO_CHECK(nnew > 0, PNOEOM_ENOTCONV, "Davidson stalled: no new directions");
     if (m + nnew > maxs) {
