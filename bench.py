@@ -53,6 +53,20 @@ def run_steps(ctx, B, eps, t1, nroots, prec, steps, tol_e, tol_r, max_sub, pno=N
     return res
 
 
+def region_rate(res, name):
+    """Achieved HBM bandwidth (algorithmic bytes / event time) and flop rate of a timed
+    region summed over steps: the Davidson inner products or the PNO transforms."""
+    ms = sum(r["timing"][name]["ms"] for r in res)
+    by = sum(r["timing"][name]["bytes"] for r in res)
+    fl = sum(r["timing"][name]["flops"] for r in res)
+    if ms <= 0:
+        return None
+    gbs = by / (ms * 1e-3) / 1e9
+    return {"ms": ms / len(res), "launches": sum(r["timing"][name]["launches"] for r in res) // len(res),
+            "GB/s": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK, "TFLOP/s": fl / (ms * 1e-3) / 1e12,
+            "bytes_per_step": by / len(res)}
+
+
 def cpu_baseline(cfg_id, seconds_budget=30.0):
     """The oracle (FP64, NumPy/OpenBLAS) timed on the host: sigma vectors per second."""
     from synthgen import config_system, random_r
@@ -112,6 +126,7 @@ def main():
     t1 = torch.from_numpy(s.t1).to(dev)
     torch.cuda.synchronize()
     ctx = PnoEom(o, v, naux)
+    peaks = ctx.probe_peaks()   # measured ceilings next to the published ones
     # long steps (v = 400: minutes) report each Davidson iteration on stderr
     verbose = v > 200
 
@@ -166,6 +181,7 @@ def main():
         "omega": [float(x) for x in omega64],
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK["fp64"], "traffic": None,
+                     "peak_measured": peaks["fp64_tflops"], "frac_of_measured": achieved / peaks["fp64_tflops"],
                      "kernel": "particle ladder sum_cd W_ab^cd R_ij^cd, +/- packed, all trial vectors of a "
                                "block in one contraction (gemm_kernel tag 1, FP64 MFMA)",
                      "algorithmic_flops_per_launch": flops_launch,
@@ -173,6 +189,11 @@ def main():
                      "launch_unit": "one MFMA GEMM launch: the + or - half of the packed ladder for "
                                     "all trial vectors of a sigma block"},
     }
+    out["measured_peaks"] = dict(peaks, note="register-only MFMA loops on every CU; HBM = 1 GiB device copy, "
+                                             "read + write bytes")
+    out["hbm_kernels"] = {"dots": region_rate(res64, "dots")}
+    if pno_only:
+        out["hbm_kernels"]["pno_transform"] = region_rate(res64, "pno_transform")
     gold = os.path.join(ROOT, "tests", "golden", f"c{args.config}.json")
     if os.path.exists(gold):
         g = json.load(open(gold))
@@ -221,6 +242,8 @@ def main():
             "sigma_evals_per_s": sum(r["nsigma"] for r in resp) / dtp,
             "omega": [float(x) for x in omp],
             "max_abs_pno_truncation_eh": float(np.max(np.abs(omp - omega64))),
+            "pno_transform": region_rate(resp, "pno_transform"),
+            "dots": region_rate(resp, "dots"),
             "note": "step = build_df + build_sapno + PNO-space Davidson (back-transform, canonical sigma, "
                     "projection); the difference from the canonical roots is the PNO truncation",
         }

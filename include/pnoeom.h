@@ -173,6 +173,15 @@ int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opt
  * Errors: EINVAL (n < 1 or null), ENOTCONV (QR iteration failed). */
 int pnoeom_host_eig(int n, const double* a, double* wr, double* wi, double* vr);
 
+/* Measured ceilings of the device, for roofline reports next to the published
+ * figures: dense MFMA TFLOP/s (FP64 16x16x4, FP32 16x16x4, BF16 16x16x32 with FP32
+ * accumulation) from register-only loops on every CU, and HBM GB/s of a plain
+ * device copy of 1 GiB (read + write bytes).  Any output pointer may be NULL.
+ * Allocates 2 GiB of device memory for the duration of the call.
+ * Errors: EHIP, ENOMEM. */
+int pnoeom_probe_peaks(pnoeom_ctx* ctx, double* fp64_tflops, double* fp32_tflops, double* bf16_tflops,
+                       double* copy_gbs);
+
 /* Host symmetric eigensolver used by pnoeom_build_sapno for pair-density and
  * semicanonical blocks larger than the GPU Jacobi kernel handles well (Methods: the
  * per-pair diagonalisation of the state-averaged densities), exposed for CPU tests.
@@ -199,6 +208,19 @@ int pnoeom_last_timing(const pnoeom_ctx* ctx, double* total_ms, double* ladder_m
  * Errors: EINVAL (null ctx, bad precision). */
 int pnoeom_last_ladder_timing(const pnoeom_ctx* ctx, int precision, double* ladder_ms, int* ladder_launches,
                               double* ladder_flops);
+
+/* Two further timed regions of the last pnoeom_davidson / pnoeom_apply_sigma call, for
+ * the roofline of the bandwidth-side kernels:
+ *   region 0: the Davidson inner products (Gram-Schmidt, subspace matrix, residual
+ *             norms); bytes = 8 (n_a + n_b) N per sweep over n_a x n_b products of
+ *             length-N vectors, flops = 2 n_a n_b N;
+ *   region 1: the PNO back-transform and projection (Methods, PNO simulation):
+ *             per vector and direction, bytes = 8 (ov + o^2 v^2 + len + |U|) (canonical
+ *             vector, compressed vector and bases each moved once), flops =
+ *             sum over pairs of (2 n_p v^2 + 2 n_p^2 v) plus 2 n_i v per occupied i.
+ * ms are HIP-event times on the context stream.  Errors: EINVAL (null ctx, bad region). */
+int pnoeom_last_region_timing(const pnoeom_ctx* ctx, int region, double* ms, int* launches, double* flops,
+                              double* bytes);
 
 #ifdef __cplusplus
 }

@@ -40,6 +40,12 @@ struct Timer {
     c.last_ladder_launches = 0;
     c.ladder_flops = 0;
     c.ladder_kernel_launches = 0;
+    for (int r = 0; r < pnoeom::Context::kRegions; ++r) {
+      c.reg_flops[r] = c.reg_bytes[r] = 0;
+      c.reg_launches[r] = 0;
+      c.last_reg_ms[r] = c.last_reg_flops[r] = c.last_reg_bytes[r] = 0;
+      c.last_reg_launches[r] = 0;
+    }
     for (int p = 0; p < 3; ++p) {
       c.ladder_flops_p[p] = 0;
       c.ladder_launches_p[p] = 0;
@@ -64,8 +70,18 @@ struct Timer {
     for (size_t k = 0; k + 1 < c.ev_used; k += 2) {
       float t = 0.f;
       PNO_HIP(hipEventElapsedTime(&t, c.ev_pool[k], c.ev_pool[k + 1]));
-      lad += t;
-      if (k / 2 < c.ev_prec.size()) c.last_ladder_ms_p[c.ev_prec[k / 2]] += t;
+      const int cat = k / 2 < c.ev_prec.size() ? c.ev_prec[k / 2] : 0;
+      if (cat < 3) {
+        lad += t;
+        c.last_ladder_ms_p[cat] += t;
+      } else {
+        c.last_reg_ms[cat - 3] += t;
+      }
+    }
+    for (int r = 0; r < pnoeom::Context::kRegions; ++r) {
+      c.last_reg_flops[r] = c.reg_flops[r];
+      c.last_reg_bytes[r] = c.reg_bytes[r];
+      c.last_reg_launches[r] = c.reg_launches[r];
     }
     c.last_ladder_ms = lad;
     c.last_ladder_launches = c.ladder_kernel_launches;
@@ -223,6 +239,13 @@ int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opt
   return PNOEOM_OK;
 }
 
+int pnoeom_probe_peaks(pnoeom_ctx* ctx, double* fp64_tflops, double* fp32_tflops, double* bf16_tflops,
+                       double* copy_gbs) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom::probe_peaks(c.stream, fp64_tflops, fp32_tflops, bf16_tflops, copy_gbs);
+  });
+}
+
 int pnoeom_host_syev(int n, const double* a, double* w, double* v) {
   try {
     return pnoeom::host_syev(n, a, w, v);
@@ -246,6 +269,17 @@ int pnoeom_last_timing(const pnoeom_ctx* ctx, double* total_ms, double* ladder_m
   if (total_ms) *total_ms = ctx->c.last_total_ms;
   if (ladder_ms) *ladder_ms = ctx->c.last_ladder_ms;
   if (ladder_launches) *ladder_launches = ctx->c.last_ladder_launches;
+  return PNOEOM_OK;
+}
+
+int pnoeom_last_region_timing(const pnoeom_ctx* ctx, int region, double* ms, int* launches, double* flops,
+                              double* bytes) {
+  if (!ctx) return PNOEOM_EINVAL;
+  if (region < 0 || region >= pnoeom::Context::kRegions) return PNOEOM_EINVAL;
+  if (ms) *ms = ctx->c.last_reg_ms[region];
+  if (launches) *launches = ctx->c.last_reg_launches[region];
+  if (flops) *flops = ctx->c.last_reg_flops[region];
+  if (bytes) *bytes = ctx->c.last_reg_bytes[region];
   return PNOEOM_OK;
 }
 

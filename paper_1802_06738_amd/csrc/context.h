@@ -45,6 +45,7 @@ struct PNOData {
   DBuf<int> d_n;                //                       sizes
   GroupTable t_c1, t_c3, t_c2d, t_c2o, t_e1, t_e3, t_e2d, t_e2o;  // compress / expand
   DBuf<double> Tw, r1, r2, s1, s2;
+  double xf_flops = 0;          // flops of one compress (or expand) of one vector
   void reset() {
     built = false;
     npno.clear(); nosv.clear(); off.clear(); uoff.clear(); toff.clear();
@@ -93,7 +94,28 @@ struct Context {
   int ladder_launches_p[3] = {0, 0, 0};
   double last_ladder_ms_p[3] = {0, 0, 0}, last_ladder_flops_p[3] = {0, 0, 0};
   int last_ladder_launches_p[3] = {0, 0, 0};
-  std::vector<int> ev_prec;         // precision of each start/stop event pair
+  std::vector<int> ev_prec;         // per start/stop event pair: ladder precision (0..2) or 3 + region
+  // other timed regions: 0 = Davidson inner products, 1 = PNO back-transform / projection
+  static constexpr int kRegions = 2;
+  double reg_flops[kRegions] = {0, 0}, reg_bytes[kRegions] = {0, 0};
+  int reg_launches[kRegions] = {0, 0};
+  double last_reg_ms[kRegions] = {0, 0}, last_reg_flops[kRegions] = {0, 0}, last_reg_bytes[kRegions] = {0, 0};
+  int last_reg_launches[kRegions] = {0, 0};
+  // events around a timed region (returns the stop event to record, or nullptr when not timing)
+  hipEvent_t region_begin(int region, hipStream_t s) {
+    if (!timing) return nullptr;
+    hipEvent_t a = next_event(), b = next_event();
+    ev_prec.push_back(3 + region);
+    if (hipEventRecord(a, s) != hipSuccess) return nullptr;
+    return b;
+  }
+  void region_end(hipEvent_t b, int region, hipStream_t s, int launches, double flops, double bytes) {
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    reg_launches[region] += launches;
+    reg_flops[region] += flops;
+    reg_bytes[region] += bytes;
+  }
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;  // start/stop pairs around ladder launches
   size_t ev_used = 0;
@@ -138,6 +160,7 @@ DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt)
 // host eigen-solver (eig.cpp); returns 0 or a negative status
 int host_eig(int n, const double* a, double* wr, double* wi, double* vr);
 int host_syev(int n, const double* a, double* w, double* v);
+void probe_peaks(hipStream_t s, double* fp64_tflops, double* fp32_tflops, double* bf16_tflops, double* copy_gbs);
 int host_syev_batched(int nmat, const int* nsz, int ld, double* A, double* ev, double* Vt, int nthreads);
 
 }  // namespace pnoeom

@@ -196,6 +196,7 @@ __global__ __launch_bounds__(64 * kDotWaves) void dots_kernel(int na, int nb, in
 
 struct Dots {
   DBuf<double> part, out;
+  Context* ctx = nullptr;  // for the timed region of the inner products
 };
 
 // host out[i][j] = sum_n A[i][n] B[j][n]   (A: na rows, B: nb rows, row stride N)
@@ -210,6 +211,7 @@ void dots(hipStream_t s, Dots& w, const double* A, int na, const double* B, int 
   for (int i0 = 0; i0 < na; i0 += 64)
     for (int j0 = 0; j0 < nb; j0 += 16) {
       const int ni = std::min(64, na - i0), nj = std::min(16, nb - j0);
+      hipEvent_t ev = w.ctx ? w.ctx->region_begin(0, s) : nullptr;
       hipLaunchKernelGGL(dots_kernel, dim3((unsigned)groups), dim3(64 * kDotWaves), 0, s, ni, nj, N,
                          A + (int64_t)i0 * N, N, B + (int64_t)j0 * N, N, (double*)w.part);
       PNO_HIP(hipGetLastError());
@@ -217,6 +219,7 @@ void dots(hipStream_t s, Dots& w, const double* A, int na, const double* B, int 
       hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)nsub), dim3(256), 0, s, nsub, groups,
                          (const double*)w.part, (double*)w.out);
       PNO_HIP(hipGetLastError());
+      if (w.ctx) w.ctx->region_end(ev, 0, s, 2, 2.0 * ni * nj * (double)N, 8.0 * (ni + nj) * (double)N);
       if (ni == na && nj == nb) {
         PNO_HIP(hipMemcpyAsync(host, w.out, nout * sizeof(double), hipMemcpyDeviceToHost, s));
       } else {
@@ -275,6 +278,7 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
   dcb.alloc((int64_t)cap * nroots);
   dth.alloc(nroots);
   Dots dw;
+  dw.ctx = &c;
   DavidsonResult res;
   const double tol_r = opt.tol_r > 0 ? opt.tol_r : 0.1 * std::sqrt(opt.tol_e);
 

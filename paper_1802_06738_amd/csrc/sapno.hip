@@ -454,6 +454,10 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
   for (int p = 0; p < npair; ++p) P.off[o + p + 1] = P.off[o + p] + (int64_t)P.npno[p] * P.npno[p];
   P.len = P.off[o + npair];
   P.uoff = uoff;
+  P.xf_flops = 0;
+  for (int p = 0; p < npair; ++p)
+    P.xf_flops += 2.0 * P.npno[p] * (double)v * v + 2.0 * (double)P.npno[p] * P.npno[p] * v;
+  for (int i = 0; i < o; ++i) P.xf_flops += 2.0 * P.nosv[i] * (double)v;
   P.nmax = nmax;
   PNO_CHECK(P.len > 0, PNOEOM_EINVAL, "build_sapno: every PNO and OSV was truncated");
   // preconditioner base: F_ii (+ F_jj) - fbar_a (- fbar_b); weights
@@ -547,6 +551,7 @@ void pno_compress(Context& c, int nvec, const double* r1, const double* r2, doub
   PNO_CHECK(P.built, PNOEOM_ESTATE, "PNO compress before build_sapno");
   hipStream_t s = c.stream;
   const double sq2 = std::sqrt(2.0);
+  hipEvent_t ev = c.region_begin(1, s);
   for (int q = 0; q < nvec; ++q) {
     const double* a1 = r1 + (int64_t)q * c.ov();
     const double* a2 = r2 + (int64_t)q * c.oovv();
@@ -556,6 +561,8 @@ void pno_compress(Context& c, int nvec, const double* r1, const double* r2, doub
     gemm_grouped(P.t_c2d, 1.0, P.U, P.Tw, 0.0, y, s);
     gemm_grouped(P.t_c2o, sq2, P.U, P.Tw, 0.0, y, s);
   }
+  c.region_end(ev, 1, s, 4 * nvec, nvec * P.xf_flops,
+               8.0 * nvec * ((double)c.ov() + (double)c.oovv() + (double)P.len + (double)P.U.n));
 }
 
 void pno_expand(Context& c, int nvec, const double* x, double* r1, double* r2) {
@@ -563,6 +570,7 @@ void pno_expand(Context& c, int nvec, const double* x, double* r1, double* r2) {
   PNO_CHECK(P.built, PNOEOM_ESTATE, "PNO expand before build_sapno");
   hipStream_t s = c.stream;
   const double isq2 = 1.0 / std::sqrt(2.0);
+  hipEvent_t ev = c.region_begin(1, s);
   for (int q = 0; q < nvec; ++q) {
     double* b1 = r1 + (int64_t)q * c.ov();
     double* b2 = r2 + (int64_t)q * c.oovv();
@@ -576,6 +584,8 @@ void pno_expand(Context& c, int nvec, const double* x, double* r1, double* r2) {
     hipLaunchKernelGGL(mirror_pairs_kernel, dim3(gsz(c.oovv())), dim3(256), 0, s, c.o, c.v, b2);
     PNO_HIP(hipGetLastError());
   }
+  c.region_end(ev, 1, s, 7 * nvec, nvec * P.xf_flops,
+               8.0 * nvec * ((double)c.ov() + (double)c.oovv() + (double)P.len + (double)P.U.n));
 }
 
 void project_pno(Context& c, double* x) {

@@ -21,7 +21,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "
 EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pnoeom_build_df", "pnoeom_cis",
                     "pnoeom_build_sapno", "pnoeom_pno_layout", "pnoeom_pno_transform", "pnoeom_apply_sigma", "pnoeom_davidson_defaults",
                     "pnoeom_davidson", "pnoeom_host_eig", "pnoeom_last_timing", "pnoeom_last_ladder_timing",
-                    "pnoeom_host_syev"]
+                    "pnoeom_last_region_timing", "pnoeom_host_syev", "pnoeom_probe_peaks"]
 
 
 class PnoEomError(RuntimeError):
@@ -69,7 +69,9 @@ def load_library():
     lib.pnoeom_host_eig.argtypes = [C.c_int, dp, dp, dp, dp]
     lib.pnoeom_last_timing.argtypes = [vp, dp, dp, ip, dp]
     lib.pnoeom_last_ladder_timing.argtypes = [vp, C.c_int, dp, ip, dp]
+    lib.pnoeom_last_region_timing.argtypes = [vp, C.c_int, dp, ip, dp, dp]
     lib.pnoeom_host_syev.argtypes = [C.c_int, dp, dp, dp]
+    lib.pnoeom_probe_peaks.argtypes = [vp, dp, dp, dp, dp]
     _LIB = lib
     return lib
 
@@ -238,6 +240,12 @@ class PnoEom:
             self._check(st)
         return dict(omega=om, resnorm=rn, iters=it.value, nsigma=ns.value, complex=(st == -6))
 
+    def probe_peaks(self):
+        """Measured MFMA TFLOP/s (fp64, fp32, bf16) and device-copy HBM GB/s."""
+        v = [C.c_double() for _ in range(4)]
+        self._check(self.lib.pnoeom_probe_peaks(self.h, *[C.byref(x) for x in v]))
+        return dict(fp64_tflops=v[0].value, fp32_tflops=v[1].value, bf16_tflops=v[2].value, copy_gbs=v[3].value)
+
     def last_timing(self):
         t = C.c_double()
         lad = C.c_double()
@@ -248,4 +256,9 @@ class PnoEom:
         for p, name in ((FP64, "fp64"), (FP32, "fp32"), (BF16, "bf16")):
             self._check(self.lib.pnoeom_last_ladder_timing(self.h, p, C.byref(lad), C.byref(n), C.byref(fl)))
             out[name] = dict(ladder_ms=lad.value, ladder_launches=n.value, ladder_flops=fl.value)
+        by = C.c_double()
+        for r, name in ((0, "dots"), (1, "pno_transform")):
+            self._check(self.lib.pnoeom_last_region_timing(self.h, r, C.byref(lad), C.byref(n), C.byref(fl),
+                                                           C.byref(by)))
+            out[name] = dict(ms=lad.value, launches=n.value, flops=fl.value, bytes=by.value)
         return out
