@@ -173,6 +173,19 @@ int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opt
  * Errors: EINVAL (n < 1 or null), ENOTCONV (QR iteration failed). */
 int pnoeom_host_eig(int n, const double* a, double* wr, double* wi, double* vr);
 
+/* Graph mode: sigma blocks applied by pnoeom_davidson and pnoeom_apply_sigma are
+ * captured once per (number of vectors, precision, space) into a HIP graph and
+ * replayed afterwards (launch-bound small systems gain most).  The first call of a
+ * shape runs eagerly on a second stream of the context and its calls are captured;
+ * replays read and write fixed staging buffers (copied from / to the caller's vectors
+ * on the context stream) and are re-captured whenever a workspace the graph refers to
+ * has moved.  build_df and build_sapno discard the graphs.  While a graph replays, the
+ * ladder / region timings of pnoeom_last_timing cover only the eager calls.
+ * pnoeom_graph_stats reports captures, replays and cached graphs.
+ * Errors: EINVAL (null ctx), EHIP. */
+int pnoeom_set_graph_mode(pnoeom_ctx* ctx, int enable);
+int pnoeom_graph_stats(const pnoeom_ctx* ctx, int* captures, int* launches, int* cached);
+
 /* Measured ceilings of the device, for roofline reports next to the published
  * figures: dense MFMA TFLOP/s (FP64 16x16x4, FP32 16x16x4, BF16 16x16x32 with FP32
  * accumulation) from register-only loops on every CU, and HBM GB/s of a plain
@@ -181,6 +194,26 @@ int pnoeom_host_eig(int n, const double* a, double* wr, double* wi, double* vr);
  * Errors: EHIP, ENOMEM. */
 int pnoeom_probe_peaks(pnoeom_ctx* ctx, double* fp64_tflops, double* fp32_tflops, double* bf16_tflops,
                        double* copy_gbs);
+
+/* GEMM tile tuning (process-wide).  Every contraction of the library goes through one
+ * MFMA GEMM whose tile shape (128x128, 64x64, 32x128, 128x32) and split of the K loop
+ * (automatic when the output has fewer tiles than CUs, none, or wider) can be chosen
+ * per shape.  A shape key is 8 integers {element size 8|4, ta, tb, reduce (batched
+ * products summed), M, N, K, batch}; a variant is 3 * tile kind + split mode.
+ *   pnoeom_gemm_record(1) starts collecting the keys launched (clearing earlier ones),
+ *     (0) stops;  pnoeom_gemm_recorded copies up to cap keys into keys[8*i..] (host)
+ *     and returns their number.
+ *   pnoeom_gemm_time runs a variant reps times on scratch operands of the key's shape
+ *     (allocated and freed by the call; shapes above 8 GiB of operands are not run and
+ *     give *ms = -1) and returns the mean milliseconds on hip_stream (NULL = default).
+ *   pnoeom_gemm_set_table replaces the table: shapes listed use their variant, the
+ *     others the built-in rule.  The tuner that writes the table is
+ *     paper_1802_06738_amd/autotune.py.
+ * Errors: EINVAL (bad key, variant or count), EHIP, ENOMEM. */
+int pnoeom_gemm_record(int enable);
+int pnoeom_gemm_recorded(long long* keys, int cap);
+int pnoeom_gemm_time(void* hip_stream, const long long* key, int variant, int reps, double* ms);
+int pnoeom_gemm_set_table(int n, const long long* keys, const int* variants);
 
 /* Host symmetric eigensolver used by pnoeom_build_sapno for pair-density and
  * semicanonical blocks larger than the GPU Jacobi kernel handles well (Methods: the

@@ -189,14 +189,49 @@ int pnoeom_apply_sigma(pnoeom_ctx* ctx, int nvec, const double* r1, const double
     Timer t(c);
     if (space == PNOEOM_CANONICAL) {
       PNO_CHECK(r1 && r2 && s1 && s2, PNOEOM_EINVAL, "apply_sigma: null vector pointer");
-      pnoeom::sigma_block(c, nvec, r1, r2, s1, s2, c.ov(), c.oovv(), precision);
+      if (c.graph_mode) {
+        // packed [r1 | r2] vectors for the captured path
+        const int64_t ov = c.ov(), oovv = c.oovv(), N = ov + oovv;
+        if ((int64_t)c.pack_in.n < nvec * N) c.pack_in.alloc(nvec * N);
+        if ((int64_t)c.pack_out.n < nvec * N) c.pack_out.alloc(nvec * N);
+        for (int q = 0; q < nvec; ++q) {
+          PNO_HIP(hipMemcpyAsync(c.pack_in + q * N, r1 + q * ov, ov * sizeof(double), hipMemcpyDeviceToDevice,
+                                 c.stream));
+          PNO_HIP(hipMemcpyAsync(c.pack_in + q * N + ov, r2 + q * oovv, oovv * sizeof(double),
+                                 hipMemcpyDeviceToDevice, c.stream));
+        }
+        pnoeom::sigma_apply(c, PNOEOM_CANONICAL, nvec, c.pack_in, c.pack_out, N, precision);
+        for (int q = 0; q < nvec; ++q) {
+          PNO_HIP(hipMemcpyAsync(s1 + q * ov, c.pack_out + q * N, ov * sizeof(double), hipMemcpyDeviceToDevice,
+                                 c.stream));
+          PNO_HIP(hipMemcpyAsync(s2 + q * oovv, c.pack_out + q * N + ov, oovv * sizeof(double),
+                                 hipMemcpyDeviceToDevice, c.stream));
+        }
+      } else {
+        pnoeom::sigma_block(c, nvec, r1, r2, s1, s2, c.ov(), c.oovv(), precision);
+      }
     } else {
       PNO_CHECK(c.pno.built, PNOEOM_ESTATE, "apply_sigma(PNO) before build_sapno");
       PNO_CHECK(r1 && s1, PNOEOM_EINVAL, "apply_sigma: null vector pointer");
-      pnoeom::sigma_pno(c, nvec, r1, s1, precision);
+      pnoeom::sigma_apply(c, PNOEOM_PNO, nvec, r1, s1, c.pno.len, precision);
     }
     t.stop();
   });
+}
+
+int pnoeom_set_graph_mode(pnoeom_ctx* ctx, int enable) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    c.graph_mode = enable != 0;
+    if (!c.graph_mode) c.drop_graphs();
+  });
+}
+
+int pnoeom_graph_stats(const pnoeom_ctx* ctx, int* captures, int* launches, int* cached) {
+  if (!ctx) return PNOEOM_EINVAL;
+  if (captures) *captures = ctx->c.graph_captures;
+  if (launches) *launches = ctx->c.graph_launches;
+  if (cached) *cached = (int)ctx->c.graphs.size();
+  return PNOEOM_OK;
 }
 
 void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts) {
@@ -244,6 +279,48 @@ int pnoeom_probe_peaks(pnoeom_ctx* ctx, double* fp64_tflops, double* fp32_tflops
   return guarded(ctx, [&](pnoeom::Context& c) {
     pnoeom::probe_peaks(c.stream, fp64_tflops, fp32_tflops, bf16_tflops, copy_gbs);
   });
+}
+
+int pnoeom_gemm_record(int enable) {
+  pnoeom::gemm_tune_record(enable != 0);
+  return PNOEOM_OK;
+}
+
+int pnoeom_gemm_recorded(long long* keys, int cap) {
+  const std::vector<pnoeom::GemmKey> k = pnoeom::gemm_tune_recorded();
+  if (keys)
+    for (int i = 0; i < (int)k.size() && i < cap; ++i)
+      for (int j = 0; j < 8; ++j) keys[(size_t)i * 8 + j] = (long long)k[i][j];
+  return (int)k.size();
+}
+
+int pnoeom_gemm_time(void* hip_stream, const long long* key, int variant, int reps, double* ms) {
+  if (!key || !ms || reps < 1) return PNOEOM_EINVAL;
+  try {
+    pnoeom::GemmKey k;
+    for (int j = 0; j < 8; ++j) k[j] = key[j];
+    *ms = pnoeom::gemm_tune_time((hipStream_t)hip_stream, k, variant, reps);
+    return PNOEOM_OK;
+  } catch (const pnoeom::Error& e) {
+    (void)hipGetLastError();
+    return e.code;
+  } catch (...) {
+    (void)hipGetLastError();
+    return PNOEOM_EHIP;
+  }
+}
+
+int pnoeom_gemm_set_table(int n, const long long* keys, const int* variants) {
+  if (n < 0 || (n > 0 && (!keys || !variants))) return PNOEOM_EINVAL;
+  std::vector<pnoeom::GemmKey> k(n);
+  std::vector<int> v(n);
+  for (int i = 0; i < n; ++i) {
+    if (variants[i] < 0 || variants[i] >= pnoeom::kGemmVariants) return PNOEOM_EINVAL;
+    for (int j = 0; j < 8; ++j) k[i][j] = keys[(size_t)i * 8 + j];
+    v[i] = variants[i];
+  }
+  pnoeom::gemm_tune_set(k, v);
+  return PNOEOM_OK;
 }
 
 int pnoeom_host_syev(int n, const double* a, double* w, double* v) {

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "../../include/pnoeom.h"
@@ -82,6 +83,18 @@ struct GemmDesc {
 
 void gemm(const GemmDesc<double>& d, hipStream_t s);
 void gemm(const GemmDesc<float>& d, hipStream_t s);
+
+// tuning of the tile / split-K choice per shape: key {element size, ta, tb, reduce, M, N, K, batch},
+// variant = 3 * tile kind (128x128, 64x64, 32x128, 128x32) + split mode (auto, none, wide)
+typedef std::array<int64_t, 8> GemmKey;
+constexpr int kGemmVariants = 12;
+void gemm_tune_record(bool on);
+std::vector<GemmKey> gemm_tune_recorded();
+void gemm_tune_set(const std::vector<GemmKey>& keys, const std::vector<int>& variants);
+double gemm_tune_time(hipStream_t s, const GemmKey& key, int variant, int reps);  // ms; < 0: not timed
+// address of the split-K workspace of a stream (0 if none): part of the buffer
+// signature that a captured graph depends on
+uint64_t gemm_workspace_signature(hipStream_t s);
 
 // bfloat16 operands (stored as their 16-bit patterns), FP32 accumulation and output:
 // C[m][n] = alpha * sum_k A[m][k] B[n][k] + beta * C[m][n].  Both operands are

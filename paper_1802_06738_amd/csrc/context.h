@@ -128,6 +128,35 @@ struct Context {
     return ev_pool[ev_used++];
   }
 
+  // replay of sigma blocks from captured HIP graphs (pnoeom_set_graph_mode)
+  struct SigmaGraph {
+    int nv = 0, prec = 0, space = 0;
+    int64_t N = 0;
+    uint64_t sig = 0;                 // buffer signature at capture
+    hipGraphExec_t exec = nullptr;
+  };
+  bool graph_mode = false;
+  std::vector<SigmaGraph> graphs;
+  hipStream_t gstream = nullptr;      // stream the graphs are captured on and launched on
+  hipEvent_t gev[2] = {nullptr, nullptr};
+  DBuf<double> gin, gout;             // fixed input / output of the captured blocks
+  DBuf<double> pack_in, pack_out;     // packed canonical vectors of apply_sigma in graph mode
+  int fixed_chunk = 0;                // > 0: vectors per sigma chunk (set while capturing)
+  int last_chunk = 0;
+  int graph_launches = 0, graph_captures = 0;
+  void drop_graphs() {
+    for (SigmaGraph& g : graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
+  ~Context() {
+    drop_graphs();
+    for (hipEvent_t& e : gev)
+      if (e) (void)hipEventDestroy(e);
+    if (gstream) (void)hipStreamDestroy(gstream);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+
   int64_t ov() const { return (int64_t)o * v; }
   int64_t oovv() const { return (int64_t)o * o * v * v; }
   int64_t vlen() const { return ov() + oovv(); }  // canonical vector length
@@ -147,6 +176,12 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv);
 void pno_compress(Context& c, int nvec, const double* r1, const double* r2, double* x);
 void pno_expand(Context& c, int nvec, const double* x, double* r1, double* r2);
 void sigma_pno(Context& c, int nvec, const double* x, double* y, int precision);
+// vectors per sigma chunk that fit the free device memory (pno: with the canonical
+// expansions of the PNO-space sigma)
+int sigma_chunk(Context& c, int nvec, int precision, bool pno);
+// sigma of nv packed vectors X[q] = x + q*N (canonical: [r1 | r2], PNO: compressed)
+// into S; through captured graphs when c.graph_mode
+void sigma_apply(Context& c, int space, int nv, const double* X, double* S, int64_t N, int precision);
 
 struct DavidsonResult {
   std::vector<double> omega, resnorm;

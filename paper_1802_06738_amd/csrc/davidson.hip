@@ -651,12 +651,9 @@ DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt)
   }
   int prec = opt.precision;
   op.apply = [&](int nv, const double* X, double* S) {
-    if (opt.space == PNOEOM_CANONICAL) {
-      sigma_block(c, nv, X, X + ov, S, S + ov, op.N, op.N, prec);
+    sigma_apply(c, opt.space, nv, X, S, op.N, prec);
+    if (opt.space == PNOEOM_CANONICAL)
       for (int q = 0; q < nv; ++q) symmetrize_r2(s, o, v, S + (int64_t)q * op.N + ov);
-    } else {
-      sigma_pno(c, nv, X, S, prec);
-    }
   };
   DBuf<double> xr;
   xr.alloc((int64_t)nroots * op.N);

@@ -21,6 +21,9 @@
 // contiguous chunks, one per XCD; the workgroups that share an XCD's L2 then
 // work on neighbouring tiles and share their A and B panels.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <set>
 
 #include "common.h"
 
@@ -256,23 +259,41 @@ __global__ void splitk_reduce_kernel(int64_t M, int64_t N, int64_t nb, int64_t n
   }
 }
 
-// split-K workspace, grown on demand and kept for the life of the process
-template <typename T>
-T* splitk_ws(size_t count) {
-  static T* p = nullptr;
-  static size_t cap = 0;
-  if (count > cap) {
-    if (p) PNO_HIP(hipFree(p));
-    p = nullptr;
-    cap = 0;
-    PNO_HIP(hipMalloc(&p, count * sizeof(T)));
-    cap = count;
-  }
-  return p;
+// split-K workspace: one per stream (work on one stream is ordered, so launches on it
+// can share it), grown on demand and kept for the life of the process.  hipFree of a
+// smaller one synchronises the device first.
+struct SplitWs {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+std::mutex& splitk_mu() {
+  static std::mutex mu;
+  return mu;
+}
+std::map<hipStream_t, SplitWs>& splitk_map() {
+  static std::map<hipStream_t, SplitWs> m;
+  return m;
 }
 
+template <typename T>
+T* splitk_ws(hipStream_t s, size_t count) {
+  std::lock_guard<std::mutex> lock(splitk_mu());
+  SplitWs& w = splitk_map()[s];
+  const size_t bytes = count * sizeof(T);
+  if (bytes > w.bytes) {
+    if (w.p) PNO_HIP(hipFree(w.p));
+    w.p = nullptr;
+    w.bytes = 0;
+    PNO_HIP(hipMalloc(&w.p, bytes));
+    w.bytes = bytes;
+  }
+  return (T*)w.p;
+}
+
+// split_mode: 0 = split K when the output has fewer tiles than CUs (target 512 work
+// items), 1 = never split, 2 = split towards 1024 work items
 template <typename T, int BM, int BN, int BK>
-void launch_tile(const GemmDesc<T>& d, hipStream_t s) {
+void launch_tile(const GemmDesc<T>& d, hipStream_t s, int split_mode = 0) {
   KArgs<T> g;
   g.M = d.M; g.N = d.N; g.K = d.K; g.alpha = d.alpha; g.beta = d.beta;
   g.A = d.A; g.lda = d.lda; g.sA = d.sA;
@@ -288,8 +309,9 @@ void launch_tile(const GemmDesc<T>& d, hipStream_t s) {
   // split the K loop when the output has too few tiles to fill the 256 CUs
   const int64_t loop = ((d.K + BK - 1) / BK) * (d.reduce ? d.batch : 1);
   int64_t nsplit = 1;
-  if (tiles * gy < 256 && loop >= 32) {
-    nsplit = std::min<int64_t>(loop / 8, (512 + tiles * gy - 1) / (tiles * gy));
+  if (split_mode != 1 && tiles * gy < (split_mode == 2 ? 512 : 256) && loop >= 32) {
+    const int64_t target = split_mode == 2 ? 1024 : 512;
+    nsplit = std::min<int64_t>(loop / 8, (target + tiles * gy - 1) / (tiles * gy));
     nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, 1024));
   }
   g.it_split = 0;
@@ -297,7 +319,7 @@ void launch_tile(const GemmDesc<T>& d, hipStream_t s) {
   if (nsplit > 1) {
     g.it_split = (loop + nsplit - 1) / nsplit;
     nsplit = (loop + g.it_split - 1) / g.it_split;
-    g.ws = splitk_ws<T>((size_t)nsplit * gy * d.M * d.N);
+    g.ws = splitk_ws<T>(s, (size_t)nsplit * gy * d.M * d.N);
   }
   // XCD-contiguous tile order (the grid is padded to a multiple of 8)
   g.xper = 0;
@@ -329,12 +351,56 @@ void launch_tile(const GemmDesc<T>& d, hipStream_t s) {
   }
 }
 
+// ---------------------------------------------------------------- tile selection and tuning
+// A tuning table (filled by the project's autotuner, paper_1802_06738_amd/autotune.py)
+// maps a GEMM shape key {element size, ta, tb, reduce, M, N, K, batch} to a variant
+// = 3 * tile kind + split mode, tile kinds 128x128, 64x64, 32x128, 128x32.  Shapes
+// without an entry use the built-in rule.  Recording collects the keys a workload
+// launches, for the tuner.
+struct TuneState {
+  std::mutex mu;
+  bool recording = false;
+  std::set<GemmKey> recorded;
+  std::map<GemmKey, int> table;
+};
+TuneState& tune_state() {
+  static TuneState st;
+  return st;
+}
+
+template <typename T>
+GemmKey key_of(const GemmDesc<T>& d) {
+  return GemmKey{(int64_t)sizeof(T), d.ta ? 1 : 0, d.tb ? 1 : 0, d.reduce ? 1 : 0, d.M, d.N, d.K, d.batch};
+}
+
+template <typename T>
+void launch_variant(const GemmDesc<T>& d, hipStream_t s, int variant) {
+  const int kind = variant / 3, split = variant % 3;
+  switch (kind) {
+    case 0: launch_tile<T, 128, 128, (sizeof(T) == 8 ? 16 : 32)>(d, s, split); break;
+    case 1: launch_tile<T, 64, 64, 16>(d, s, split); break;
+    case 2: launch_tile<T, 32, 128, 16>(d, s, split); break;
+    default: launch_tile<T, 128, 32, 16>(d, s, split); break;
+  }
+}
+
 template <typename T>
 void gemm_impl(const GemmDesc<T>& d, hipStream_t s) {
   PNO_CHECK(d.M >= 0 && d.N >= 0 && d.K >= 0 && d.batch >= 0, PNOEOM_EINVAL, "gemm: negative size");
   if (d.M == 0 || d.N == 0 || d.batch == 0) return;
   PNO_CHECK(d.A && d.B && d.C, PNOEOM_EINVAL, "gemm: null operand");
-  // tile choice: large tiles when both output dimensions fill them
+  {
+    TuneState& ts = tune_state();
+    std::lock_guard<std::mutex> lock(ts.mu);
+    const GemmKey key = key_of(d);
+    if (ts.recording) ts.recorded.insert(key);
+    auto it = ts.table.find(key);
+    if (it != ts.table.end()) {
+      launch_variant(d, s, it->second);
+      return;
+    }
+  }
+  // built-in rule: large tiles when both output dimensions fill them
   if (d.M >= 128 && d.N >= 128)
     launch_tile<T, 128, 128, (sizeof(T) == 8 ? 16 : 32)>(d, s);
   else if (d.M <= 32 && d.N >= 128)
@@ -627,6 +693,86 @@ void gemm_bf16(const GemmBf16Desc& d, hipStream_t s) {
   else
     hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, 0>), dim3((unsigned)gx), dim3(NT), 0, s, g);
   PNO_HIP(hipGetLastError());
+}
+
+namespace {
+__global__ void tune_fill_kernel(int64_t n, double* x) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    x[e] = 1e-3 * (double)((e * 2654435761ll) % 1000) - 0.5;
+}
+__global__ void tune_fill_kernel_f(int64_t n, float* x) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    x[e] = 1e-3f * (float)((e * 2654435761ll) % 1000) - 0.5f;
+}
+
+template <typename T>
+double time_variant(hipStream_t s, const GemmKey& k, int variant, int reps) {
+  GemmDesc<T> d;
+  d.ta = k[1] != 0; d.tb = k[2] != 0; d.reduce = k[3] != 0;
+  d.M = k[4]; d.N = k[5]; d.K = k[6]; d.batch = k[7];
+  const int64_t na = d.batch * d.M * d.K, nbv = d.K * d.N;
+  const int64_t nc = (d.reduce ? 1 : d.batch) * d.M * d.N;
+  if ((na + nbv + nc) * (int64_t)sizeof(T) > (8ll << 30)) return -1.0;  // not timed: too large
+  DBuf<T> A, B, C;
+  A.alloc(std::max<int64_t>(na, 1)); B.alloc(std::max<int64_t>(nbv, 1)); C.alloc(std::max<int64_t>(nc, 1));
+  if (sizeof(T) == 8) {
+    hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, s, na, (double*)(void*)A.p);
+    hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, s, nbv, (double*)(void*)B.p);
+  } else {
+    hipLaunchKernelGGL(tune_fill_kernel_f, dim3(1024), dim3(256), 0, s, na, (float*)(void*)A.p);
+    hipLaunchKernelGGL(tune_fill_kernel_f, dim3(1024), dim3(256), 0, s, nbv, (float*)(void*)B.p);
+  }
+  d.A = A; d.lda = d.ta ? d.M : d.K; d.sA = d.M * d.K;
+  d.B = B; d.ldb = d.tb ? d.K : d.N; d.sB = 0;
+  d.C = C; d.ldc = d.N; d.sC = d.reduce ? 0 : d.M * d.N;
+  d.alpha = 1; d.beta = 0;
+  launch_variant(d, s, variant);  // warm-up (sizes the split-K workspace)
+  hipEvent_t e0, e1;
+  PNO_HIP(hipEventCreate(&e0));
+  PNO_HIP(hipEventCreate(&e1));
+  PNO_HIP(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) launch_variant(d, s, variant);
+  PNO_HIP(hipEventRecord(e1, s));
+  PNO_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  PNO_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return (double)ms / std::max(reps, 1);
+}
+}  // namespace
+
+uint64_t gemm_workspace_signature(hipStream_t s) {
+  std::lock_guard<std::mutex> lock(splitk_mu());
+  auto it = splitk_map().find(s);
+  return it == splitk_map().end() ? 0 : (uint64_t)(uintptr_t)it->second.p;
+}
+
+void gemm_tune_record(bool on) {
+  TuneState& ts = tune_state();
+  std::lock_guard<std::mutex> lock(ts.mu);
+  ts.recording = on;
+  if (on) ts.recorded.clear();
+}
+
+std::vector<GemmKey> gemm_tune_recorded() {
+  TuneState& ts = tune_state();
+  std::lock_guard<std::mutex> lock(ts.mu);
+  return std::vector<GemmKey>(ts.recorded.begin(), ts.recorded.end());
+}
+
+void gemm_tune_set(const std::vector<GemmKey>& keys, const std::vector<int>& variants) {
+  TuneState& ts = tune_state();
+  std::lock_guard<std::mutex> lock(ts.mu);
+  ts.table.clear();
+  for (size_t i = 0; i < keys.size(); ++i) ts.table[keys[i]] = variants[i];
+}
+
+double gemm_tune_time(hipStream_t s, const GemmKey& key, int variant, int reps) {
+  PNO_CHECK(variant >= 0 && variant < kGemmVariants, PNOEOM_EINVAL, "gemm_tune_time: bad variant");
+  PNO_CHECK((key[0] == 8 || key[0] == 4) && key[4] > 0 && key[5] > 0 && key[6] >= 0 && key[7] >= 1, PNOEOM_EINVAL,
+            "gemm_tune_time: bad shape key");
+  return key[0] == 8 ? time_variant<double>(s, key, variant, reps) : time_variant<float>(s, key, variant, reps);
 }
 
 void gemm(const GemmDesc<double>& d, hipStream_t s) { gemm_impl<double>(d, s); }

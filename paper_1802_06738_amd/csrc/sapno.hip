@@ -269,6 +269,7 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
   PNO_CHECK(nstates >= 1 && nstates <= c.ov(), PNOEOM_EINVAL, "build_sapno: bad nstates");
   hipStream_t s = c.stream;
   PNOData& P = c.pno;
+  c.drop_graphs();
   P.reset();
   const int o = c.o, v = c.v, naux = c.naux, nmo = c.nmo;
   const int64_t n2 = (int64_t)nmo * nmo, ov = c.ov(), oovv = c.oovv(), vv = (int64_t)v * v;
@@ -612,13 +613,18 @@ void sigma_pno(Context& c, int nvec, const double* x, double* y, int precision) 
   auto grow = [](DBuf<double>& b, int64_t n) {
     if ((int64_t)b.n < n) b.alloc(n);
   };
-  grow(P.r1, (int64_t)nvec * c.ov());
-  grow(P.r2, (int64_t)nvec * c.oovv());
-  grow(P.s1, (int64_t)nvec * c.ov());
-  grow(P.s2, (int64_t)nvec * c.oovv());
-  pno_expand(c, nvec, x, P.r1, P.r2);
-  sigma_block(c, nvec, P.r1, P.r2, P.s1, P.s2, c.ov(), c.oovv(), precision);
-  pno_compress(c, nvec, P.s1, P.s2, y);
+  // chunks whose canonical expansions, ladder operands and work arrays fit in HBM
+  const int nb = sigma_chunk(c, nvec, precision, true);
+  grow(P.r1, (int64_t)nb * c.ov());
+  grow(P.r2, (int64_t)nb * c.oovv());
+  grow(P.s1, (int64_t)nb * c.ov());
+  grow(P.s2, (int64_t)nb * c.oovv());
+  for (int q0 = 0; q0 < nvec; q0 += nb) {
+    const int n = std::min(nb, nvec - q0);
+    pno_expand(c, n, x + (int64_t)q0 * P.len, P.r1, P.r2);
+    sigma_block(c, n, P.r1, P.r2, P.s1, P.s2, c.ov(), c.oovv(), precision);
+    pno_compress(c, n, P.s1, P.s2, y + (int64_t)q0 * P.len);
+  }
   for (int q = 0; q < nvec; ++q) project_pno(c, y + (int64_t)q * P.len);
 }
 

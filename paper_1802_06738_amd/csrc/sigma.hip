@@ -108,6 +108,11 @@ __device__ __forceinline__ int64_t pair_idx(int64_t i, int64_t j, int64_t o) {  
   return i * o - i * (i - 1) / 2 + (j - i);
 }
 
+__global__ void zero_u16_kernel(int64_t n, uint16_t* __restrict__ x) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    x[e] = 0;
+}
+
 // storage conversions of the packed ladder operands: FP64, FP32, or bfloat16 bits
 // (round to nearest even through FP32)
 __device__ __forceinline__ uint16_t bf16_bits(double x) {
@@ -245,6 +250,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   c.precision = precision;
   // workspaces and bases of the previous intermediates are dropped first, so that the
   // new ones (e.g. a second copy of W+/- in another precision) have the memory
+  c.drop_graphs();
   c.sw.release();
   c.pno.reset();
   if (precision == PNOEOM_FP64)
@@ -445,8 +451,10 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     if (bfw) {
       c.Wpb.alloc(vp * c.ldpb);
       c.Wmb.alloc(std::max<int64_t>(vm, 1) * c.ldmb);
-      PNO_HIP(hipMemsetAsync(c.Wpb, 0, vp * c.ldpb * sizeof(uint16_t), s));
-      PNO_HIP(hipMemsetAsync(c.Wmb, 0, std::max<int64_t>(vm, 1) * c.ldmb * sizeof(uint16_t), s));
+      hipLaunchKernelGGL(zero_u16_kernel, dim3(grid1(vp * c.ldpb)), dim3(256), 0, s, vp * c.ldpb, (uint16_t*)c.Wpb);
+      hipLaunchKernelGGL(zero_u16_kernel, dim3(grid1(std::max<int64_t>(vm, 1) * c.ldmb)), dim3(256), 0, s,
+                         std::max<int64_t>(vm, 1) * c.ldmb, (uint16_t*)c.Wmb);
+      PNO_HIP(hipGetLastError());
     }
     int64_t na = v;
     const int64_t budget = (int64_t)1 << 28;
@@ -502,20 +510,55 @@ int64_t rest_bytes_per_vector(const Context& c, bool f32) {
   return bytes;
 }
 
-// number of vectors per sigma_rest_block call: as many as fit in the free device
-// memory (plus what the work arrays already hold), leaving a tenth of the device
-// (at least 2 GiB) to the caller
-int rest_chunk(const Context& c, int nvec, bool f32) {
-  const int64_t per = rest_bytes_per_vector(c, f32);
-  size_t freeb = 0, totalb = 0;
-  PNO_HIP(hipMemGetInfo(&freeb, &totalb));
-  const int64_t held = c.oovv() > 0 ? (int64_t)(c.sw.Ria.n / c.oovv()) * per : 0;
-  const int64_t headroom = std::max<int64_t>(2ll << 30, (int64_t)totalb / 10);
-  const int64_t avail = (int64_t)freeb + held - headroom;
-  int64_t nb = avail > 0 ? avail / per : 0;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(nb, nvec));
+}  // namespace
+
+// device bytes per trial vector of one sigma chunk: the rest's work arrays, the
+// ladder's packed operands / results and unpacked output, and (PNO space) the
+// canonical expansion of the vector and of its sigma
+int64_t sigma_bytes_per_vector(const Context& c, int precision, bool pno) {
+  const int64_t npair = (int64_t)c.o * (c.o + 1) / 2, vp = (int64_t)c.v * (c.v + 1) / 2;
+  const int64_t vm = std::max<int64_t>((int64_t)c.v * (c.v - 1) / 2, 1);
+  const bool f32 = precision != PNOEOM_FP64;
+  int64_t b = rest_bytes_per_vector(c, f32) + c.oovv() * (int64_t)sizeof(double);  // + LadAll
+  const int64_t in_elt = precision == PNOEOM_FP64 ? 8 : precision == PNOEOM_FP32 ? 4 : 2;
+  const int64_t out_elt = precision == PNOEOM_FP64 ? 8 : 4;
+  const int64_t kp = precision == PNOEOM_BF16 ? c.ldpb + c.ldmb : vp + vm;
+  b += npair * (kp * in_elt + (vp + vm) * out_elt);
+  if (pno) b += 2 * c.vlen() * (int64_t)sizeof(double);
+  return b;
 }
 
+// bytes currently held by the sigma workspaces (reused by the next chunk)
+int64_t sigma_held_bytes(const Context& c) {
+  const SigmaWork& w = c.sw;
+  int64_t b = 0;
+  for (const DBuf<double>* x : {&w.Bp, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT,
+                                &w.BoopT, &w.BvvpT, &w.R2c, &w.Ria, &w.Rsia, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.Ziajb,
+                                &w.Z3, &w.EXT, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.Ftv, &w.Fto,
+                                &w.LadAll, &w.Sp, &w.Am, &w.SigP, &w.SigM, &c.pno.r1, &c.pno.r2, &c.pno.s1,
+                                &c.pno.s2})
+    b += (int64_t)x->n * 8;
+  for (const DBuf<float>* x : {&w.Spf, &w.Amf, &w.SigPf, &w.SigMf, &w.fa, &w.fc}) b += (int64_t)x->n * 4;
+  b += (int64_t)(w.Spb.n + w.Amb.n) * 2;
+  return b;
+}
+
+// vectors per sigma chunk: as many as fit in the free device memory plus what the
+// workspaces already hold, leaving a tenth of the device (at least 2 GiB) to the
+// caller.  While a graph is captured the decision of the eager run is reused.
+int sigma_chunk(Context& c, int nvec, int precision, bool pno) {
+  if (c.fixed_chunk > 0) return std::max(1, std::min(c.fixed_chunk, nvec));
+  const int64_t per = sigma_bytes_per_vector(c, precision, pno);
+  size_t freeb = 0, totalb = 0;
+  PNO_HIP(hipMemGetInfo(&freeb, &totalb));
+  const int64_t headroom = std::max<int64_t>(2ll << 30, (int64_t)totalb / 10);
+  const int64_t avail = (int64_t)freeb + sigma_held_bytes(c) - headroom;
+  const int64_t nb = avail > 0 ? avail / per : 0;
+  c.last_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nb, nvec));
+  return c.last_chunk;
+}
+
+namespace {
 void alloc_sigma_work(Context& c, int precision, int nb) {
   SigmaWork& w = c.sw;
   const int64_t n2 = (int64_t)c.nmo * c.nmo, ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v;
@@ -727,8 +770,10 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
 }
 }  // namespace
 
-void sigma_block(Context& c, int nvec, const double* r1, const double* r2, double* s1, double* s2, int64_t stride1,
-                 int64_t stride2, int precision) {
+namespace {
+// one chunk of trial vectors: all of them go through the ladder and the rest together
+void sigma_block_chunk(Context& c, int nvec, const double* r1, const double* r2, double* s1, double* s2,
+                       int64_t stride1, int64_t stride2, int precision) {
   PNO_CHECK(c.have_df, PNOEOM_ESTATE, "sigma before build_df");
   PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32 || precision == PNOEOM_BF16, PNOEOM_EINVAL,
             "sigma: precision must be FP64, FP32 or BF16");
@@ -761,8 +806,11 @@ void sigma_block(Context& c, int nvec, const double* r1, const double* r2, doubl
     if ((int64_t)w.Spb.n < rows * c.ldpb || (int64_t)w.Amb.n < rows * c.ldmb) {
       w.Spb.alloc(rows * c.ldpb);
       w.Amb.alloc(rows * c.ldmb);
-      PNO_HIP(hipMemsetAsync(w.Spb, 0, w.Spb.n * sizeof(uint16_t), s));
-      PNO_HIP(hipMemsetAsync(w.Amb, 0, w.Amb.n * sizeof(uint16_t), s));
+      hipLaunchKernelGGL(zero_u16_kernel, dim3(grid1((int64_t)w.Spb.n)), dim3(256), 0, s, (int64_t)w.Spb.n,
+                         (uint16_t*)w.Spb);
+      hipLaunchKernelGGL(zero_u16_kernel, dim3(grid1((int64_t)w.Amb.n)), dim3(256), 0, s, (int64_t)w.Amb.n,
+                         (uint16_t*)w.Amb);
+      PNO_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL((ladder_pack_kernel<uint16_t>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec, r2, stride2,
                        (uint16_t*)w.Spb, c.ldpb, (uint16_t*)w.Amb, c.ldmb);
@@ -816,13 +864,140 @@ void sigma_block(Context& c, int nvec, const double* r1, const double* r2, doubl
     hipLaunchKernelGGL((ladder_unpack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec,
                        (const double*)w.SigP, (const double*)w.SigM, (double*)w.LadAll, oovv);
   PNO_HIP(hipGetLastError());
-  // ---------------------------------------------------------------- everything else, in chunks of vectors
-  const int nb = rest_chunk(c, nvec, f32 || bf);
+  // ---------------------------------------------------------------- everything else
+  sigma_rest_block(c, nvec, r1, stride1, r2, stride2, s1, s2, precision, w.LadAll);
+}
+}  // namespace
+
+void sigma_block(Context& c, int nvec, const double* r1, const double* r2, double* s1, double* s2, int64_t stride1,
+                 int64_t stride2, int precision) {
+  PNO_CHECK(c.have_df, PNOEOM_ESTATE, "sigma before build_df");
+  if (nvec <= 0) return;
+  const int nb = sigma_chunk(c, nvec, precision, false);
   for (int q0 = 0; q0 < nvec; q0 += nb) {
     const int n = std::min(nb, nvec - q0);
-    sigma_rest_block(c, n, r1 + q0 * stride1, stride1, r2 + q0 * stride2, stride2, s1 + q0 * stride1,
-                     s2 + q0 * stride2, precision, w.LadAll + (int64_t)q0 * oovv);
+    sigma_block_chunk(c, n, r1 + q0 * stride1, r2 + q0 * stride2, s1 + q0 * stride1, s2 + q0 * stride2, stride1,
+                      stride2, precision);
   }
+}
+
+
+namespace {
+// every device address the sigma path may touch besides the context's fixed
+// intermediates (those change only in build_df / build_sapno, which drop the graphs)
+uint64_t sigma_signature(Context& c, hipStream_t s) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    h ^= (uint64_t)(uintptr_t)p + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    h ^= (uint64_t)n * 0x100000001b3ull;
+  };
+  SigmaWork& w = c.sw;
+  for (DBuf<double>* b : {&w.Bp, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT, &w.BoopT,
+                          &w.BvvpT, &w.R2c, &w.Ria, &w.Rsia, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.Ziajb, &w.Z3,
+                          &w.EXT, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.Ftv, &w.Fto, &w.LadAll, &w.Sp,
+                          &w.Am, &w.SigP, &w.SigM, &c.pno.Tw, &c.pno.r1, &c.pno.r2, &c.pno.s1, &c.pno.s2, &c.gin,
+                          &c.gout})
+    mix(b->p, b->n);
+  for (DBuf<float>* b : {&w.Spf, &w.Amf, &w.SigPf, &w.SigMf, &w.fa, &w.fc}) mix(b->p, b->n);
+  mix(w.Spb.p, w.Spb.n);
+  mix(w.Amb.p, w.Amb.n);
+  mix((const void*)(uintptr_t)gemm_workspace_signature(s), 0);
+  return h;
+}
+
+void sigma_packed(Context& c, int space, int nv, const double* X, double* S, int64_t N, int precision) {
+  if (space == PNOEOM_CANONICAL) {
+    const int64_t ov = c.ov();
+    sigma_block(c, nv, X, X + ov, S, S + ov, N, N, precision);
+  } else {
+    sigma_pno(c, nv, X, S, precision);
+  }
+}
+}  // namespace
+
+void sigma_apply(Context& c, int space, int nv, const double* X, double* S, int64_t N, int precision) {
+  if (nv <= 0) return;
+  if (!c.graph_mode) {
+    sigma_packed(c, space, nv, X, S, N, precision);
+    return;
+  }
+  hipStream_t s = c.stream;
+  if (!c.gstream) {
+    PNO_HIP(hipStreamCreateWithFlags(&c.gstream, hipStreamNonBlocking));
+    PNO_HIP(hipEventCreateWithFlags(&c.gev[0], hipEventDisableTiming));
+    PNO_HIP(hipEventCreateWithFlags(&c.gev[1], hipEventDisableTiming));
+  }
+  const int64_t need = (int64_t)nv * N;
+  if ((int64_t)c.gin.n < need || (int64_t)c.gout.n < need) {  // new staging addresses: recapture all
+    c.drop_graphs();
+    c.gin.alloc(need);
+    c.gout.alloc(need);
+  }
+  PNO_HIP(hipMemcpyAsync(c.gin, X, need * sizeof(double), hipMemcpyDeviceToDevice, s));
+  Context::SigmaGraph* hit = nullptr;
+  for (Context::SigmaGraph& g : c.graphs)
+    if (g.nv == nv && g.prec == precision && g.space == space && g.N == N) hit = &g;
+  if (hit && hit->sig == sigma_signature(c, c.gstream) && hit->sig != 0) {
+    // replay on the graph stream, ordered after and before the context stream's work
+    PNO_HIP(hipEventRecord(c.gev[0], s));
+    PNO_HIP(hipStreamWaitEvent(c.gstream, c.gev[0], 0));
+    PNO_HIP(hipGraphLaunch(hit->exec, c.gstream));
+    PNO_HIP(hipEventRecord(c.gev[1], c.gstream));
+    PNO_HIP(hipStreamWaitEvent(s, c.gev[1], 0));
+    ++c.graph_launches;
+  } else {
+    if (hit) {  // a buffer moved since the capture
+      (void)hipGraphExecDestroy(hit->exec);
+      c.graphs.erase(c.graphs.begin() + (hit - c.graphs.data()));
+    }
+    // eager evaluation on the graph stream (its result is this call's answer and it
+    // sizes every workspace), then the same calls, with the same chunking, captured
+    // into a graph
+    PNO_HIP(hipEventRecord(c.gev[0], s));
+    PNO_HIP(hipStreamWaitEvent(c.gstream, c.gev[0], 0));
+    c.stream = c.gstream;
+    try {
+      c.fixed_chunk = sigma_chunk(c, nv, precision, space == PNOEOM_PNO);
+      sigma_packed(c, space, nv, c.gin, c.gout, N, precision);
+      PNO_HIP(hipStreamSynchronize(c.gstream));
+    } catch (...) {
+      c.stream = s;
+      c.fixed_chunk = 0;
+      throw;
+    }
+    const uint64_t sig = sigma_signature(c, c.gstream);
+    const bool saved_timing = c.timing;
+    c.timing = false;
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(c.gstream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    hipError_t ec = hipErrorUnknown;
+    if (ok) {
+      try {
+        sigma_packed(c, space, nv, c.gin, c.gout, N, precision);
+      } catch (...) {
+        ok = false;
+      }
+      ec = hipStreamEndCapture(c.gstream, &graph);
+    }
+    c.stream = s;
+    c.timing = saved_timing;
+    c.fixed_chunk = 0;
+    (void)hipGetLastError();
+    if (ok && ec == hipSuccess && graph && sigma_signature(c, c.gstream) == sig) {
+      Context::SigmaGraph g;
+      g.nv = nv; g.prec = precision; g.space = space; g.N = N; g.sig = sig;
+      if (hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+        c.graphs.push_back(g);
+        ++c.graph_captures;
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    PNO_HIP(hipEventRecord(c.gev[1], c.gstream));
+    PNO_HIP(hipStreamWaitEvent(s, c.gev[1], 0));
+  }
+  PNO_HIP(hipMemcpyAsync(S, c.gout, need * sizeof(double), hipMemcpyDeviceToDevice, s));
 }
 
 void sigma_canonical(Context& c, const double* r1, const double* r2, double* s1, double* s2, int precision) {

@@ -21,7 +21,9 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "
 EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pnoeom_build_df", "pnoeom_cis",
                     "pnoeom_build_sapno", "pnoeom_pno_layout", "pnoeom_pno_transform", "pnoeom_apply_sigma", "pnoeom_davidson_defaults",
                     "pnoeom_davidson", "pnoeom_host_eig", "pnoeom_last_timing", "pnoeom_last_ladder_timing",
-                    "pnoeom_last_region_timing", "pnoeom_host_syev", "pnoeom_probe_peaks"]
+                    "pnoeom_last_region_timing", "pnoeom_host_syev", "pnoeom_probe_peaks",
+                    "pnoeom_gemm_record", "pnoeom_gemm_recorded", "pnoeom_gemm_time", "pnoeom_gemm_set_table",
+                    "pnoeom_set_graph_mode", "pnoeom_graph_stats"]
 
 
 class PnoEomError(RuntimeError):
@@ -72,7 +74,17 @@ def load_library():
     lib.pnoeom_last_region_timing.argtypes = [vp, C.c_int, dp, ip, dp, dp]
     lib.pnoeom_host_syev.argtypes = [C.c_int, dp, dp, dp]
     lib.pnoeom_probe_peaks.argtypes = [vp, dp, dp, dp, dp]
+    lib.pnoeom_gemm_record.argtypes = [C.c_int]
+    lib.pnoeom_gemm_recorded.argtypes = [C.POINTER(C.c_longlong), C.c_int]
+    lib.pnoeom_gemm_time.argtypes = [vp, C.POINTER(C.c_longlong), C.c_int, C.c_int, dp]
+    lib.pnoeom_gemm_set_table.argtypes = [C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_int)]
+    lib.pnoeom_set_graph_mode.argtypes = [vp, C.c_int]
+    lib.pnoeom_graph_stats.argtypes = [vp, ip, ip, ip]
     _LIB = lib
+    # the autotuner's table of GEMM tile choices for this device, when present
+    from .autotune import DEFAULT_TABLE, load_table
+    if os.path.exists(DEFAULT_TABLE):
+        load_table(DEFAULT_TABLE, lib)
     return lib
 
 
@@ -239,6 +251,14 @@ class PnoEom:
         if st not in (0, -6):
             self._check(st)
         return dict(omega=om, resnorm=rn, iters=it.value, nsigma=ns.value, complex=(st == -6))
+
+    def set_graph_mode(self, enable=True):
+        self._check(self.lib.pnoeom_set_graph_mode(self.h, int(bool(enable))))
+
+    def graph_stats(self):
+        v = [C.c_int() for _ in range(3)]
+        self._check(self.lib.pnoeom_graph_stats(self.h, *[C.byref(x) for x in v]))
+        return dict(captures=v[0].value, launches=v[1].value, cached=v[2].value)
 
     def probe_peaks(self):
         """Measured MFMA TFLOP/s (fp64, fp32, bf16) and device-copy HBM GB/s."""

@@ -115,6 +115,45 @@ def test_sigma_bf16_ladder_within_rounding_bound(o, v, naux, t1s, seed):
     assert np.max(err2) > 1e-6 * np.max(np.abs(a2))  # the bfloat16 path was taken
 
 
+def test_gemm_variants_keep_sigma_parity():
+    """Every tile / split-K variant the autotuner may select gives the same sigma:
+    the shapes of one sigma call are recorded, then each variant is forced on all of
+    them through the tuning table."""
+    import ctypes as C
+    torch = _torch()
+    from oracle.sigma import SigmaOracle
+    from paper_1802_06738_amd import load_library
+    from paper_1802_06738_amd.autotune import DEFAULT_TABLE, load_table, clear_table, record_shapes  # noqa: F401
+    lib = load_library()
+    o, v, naux = 5, 37, 53
+    s = make_system(o, v, naux, 2, t1_sigma=1e-2)
+    ctx = _ctx(s)
+    r1, r2 = random_r(o, v, 52, nvec=2)
+    R1, R2 = torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda()
+    lib.pnoeom_gemm_record(1)
+    ctx.sigma(R1, R2)
+    lib.pnoeom_gemm_record(0)
+    n = lib.pnoeom_gemm_recorded(None, 0)
+    keys = (C.c_longlong * (8 * n))()
+    lib.pnoeom_gemm_recorded(keys, n)
+    so = SigmaOracle(s.eps, s.B, o, s.t1)
+    refs = [so.sigma(r1[k], r2[k]) for k in range(2)]
+    try:
+        for var in range(12):
+            print(f"[gemm variant] {var} on {n} shapes", flush=True)
+            vv = (C.c_int * n)(*([var] * n))
+            assert lib.pnoeom_gemm_set_table(n, keys, vv) == 0
+            g1, g2 = ctx.sigma(R1, R2)
+            g1, g2 = g1.cpu().numpy(), g2.cpu().numpy()
+            for k in range(2):
+                assert np.max(np.abs(g1[k] - refs[k][0])) <= 1e-12 * np.max(np.abs(refs[k][0]))
+                assert np.max(np.abs(g2[k] - refs[k][1])) <= 1e-12 * np.max(np.abs(refs[k][1]))
+    finally:
+        clear_table(lib)
+        if os.path.exists(DEFAULT_TABLE):
+            load_table(DEFAULT_TABLE, lib)
+
+
 def test_sigma_given_t2_and_zero_r():
     """Explicit T2 input path; R = 0 gives sigma = 0 exactly (linearity)."""
     torch = _torch()
@@ -197,3 +236,47 @@ def test_sigma_config2_full_size_sampled(precision, tol):
     assert np.max(np.abs(g2[g["idx2"]] - v2)) <= tol * g["max2"]
     assert abs(np.linalg.norm(g1) - g["norm1"]) <= tol * g["norm1"]
     assert abs(np.linalg.norm(g2) - g["norm2"]) <= tol * g["norm2"]
+
+
+def test_graph_replays_match_eager():
+    """Graph mode: sigma blocks captured once and replayed.  Every replay, with eager
+    work of another shape and host synchronisation in between, reproduces the eager
+    result of the same input."""
+    torch = _torch()
+    o, v, naux = 5, 37, 53
+    s = make_system(o, v, naux, 2, t1_sigma=1e-2)
+    ctx = _ctx(s)
+    r1, r2 = random_r(o, v, 61, nvec=3)
+    R1, R2 = torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda()
+    e1, e2 = ctx.sigma(R1, R2)
+    e1, e2 = e1.cpu().numpy(), e2.cpu().numpy()
+    q1, q2 = random_r(o, v, 62, nvec=1)
+    Q1, Q2 = torch.from_numpy(q1).cuda(), torch.from_numpy(q2).cuda()
+    f1, f2 = ctx.sigma(Q1, Q2)
+    f2 = f2.cpu().numpy()
+    ctx.set_graph_mode(True)
+    try:
+        for rep in range(5):
+            print(f"[graph replay] {rep}", flush=True)
+            g1, g2 = ctx.sigma(R1, R2)
+            torch.cuda.synchronize()
+            assert np.max(np.abs(g1.cpu().numpy() - e1)) <= 1e-13 * np.max(np.abs(e1))
+            assert np.max(np.abs(g2.cpu().numpy() - e2)) <= 1e-13 * np.max(np.abs(e2))
+            h1, h2 = ctx.sigma(Q1, Q2)  # another captured shape in between
+            assert np.max(np.abs(h2.cpu().numpy() - f2)) <= 1e-13 * np.max(np.abs(f2))
+            _ = (R2 * 2.0).sum().item()  # eager torch work and a host sync
+        st = ctx.graph_stats()
+        assert st["captures"] == 2 and st["launches"] == 8 and st["cached"] == 2
+    finally:
+        ctx.set_graph_mode(False)
+
+
+def test_davidson_c1_graph_mode_matches_dense_eig():
+    print("[davidson c1 graph]", flush=True)
+    gold = json.load(open(os.path.join(GOLD, "c1.json")))
+    s = config_system(1)
+    ctx = _ctx(s)
+    ctx.set_graph_mode(True)
+    r = ctx.davidson(3, tol_e=1e-10, tol_r=1e-7, nextra=2)
+    assert ctx.graph_stats()["launches"] > 0
+    assert np.max(np.abs(r["omega"] - np.array(gold["dense_eig"][:3]))) <= 1e-8

@@ -133,3 +133,19 @@ def test_pno_small_workload_vs_golden():
     assert np.array_equal(npno, np.array(g["npno"])) and np.array_equal(nosv, np.array(g["nosv"]))
     r = ctx.davidson(c["nroots"], space=1, tol_e=1e-10, tol_r=1e-6)
     assert np.max(np.abs(r["omega"] - np.array(g["davidson_pno"]))) <= 1e-8
+
+
+def test_pno_small_graph_mode_vs_golden():
+    path = os.path.join(GOLD, "pno_small.json")
+    if not os.path.exists(path):
+        pytest.skip("pno_small golden values not generated")
+    print("[pno_small graph]", flush=True)
+    g = json.load(open(path))
+    s = config_system("pno_small")
+    c = CONFIGS["pno_small"]
+    ctx = _ctx(s)
+    ctx.build_sapno(g["nstates_avg"], g["tcut_pno"])
+    ctx.set_graph_mode(True)
+    r = ctx.davidson(c["nroots"], space=1, tol_e=1e-10, tol_r=1e-6, nextra=2)
+    assert ctx.graph_stats()["launches"] > 0
+    assert np.max(np.abs(r["omega"] - np.array(g["davidson_pno"]))) <= 1e-8

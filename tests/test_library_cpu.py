@@ -93,3 +93,25 @@ def test_host_syev_matches_lapack(n, seed, kind):
     assert np.max(np.abs(np.sort(w) - ref)) <= 1e-12 * scale
     assert np.max(np.abs(a @ v - v * w)) <= 1e-12 * scale
     assert np.max(np.abs(v.T @ v - np.eye(n))) <= 1e-12
+
+
+def test_gemm_tuning_table_validation():
+    """The tuning entry points validate their input without touching the GPU."""
+    import ctypes as C
+    lib = _lib()
+    keys = (C.c_longlong * 8)(8, 0, 0, 0, 64, 64, 64, 1)
+    bad = (C.c_int * 1)(12)
+    assert lib.pnoeom_gemm_set_table(1, keys, bad) != 0
+    assert lib.pnoeom_gemm_set_table(-1, keys, bad) != 0
+    ok = (C.c_int * 1)(4)
+    assert lib.pnoeom_gemm_set_table(1, keys, ok) == 0
+    assert lib.pnoeom_gemm_record(1) == 0
+    assert lib.pnoeom_gemm_recorded(None, 0) == 0
+    assert lib.pnoeom_gemm_record(0) == 0
+    from paper_1802_06738_amd.autotune import DEFAULT_TABLE, load_table, clear_table, default_variant
+    clear_table(lib)
+    if os.path.exists(DEFAULT_TABLE):
+        assert load_table(DEFAULT_TABLE, lib) >= 0
+    assert default_variant((8, 0, 0, 0, 3000, 3000, 3000, 1)) == 0
+    assert default_variant((8, 0, 1, 0, 6, 9000000, 40, 1)) == 6
+    assert default_variant((8, 0, 0, 0, 40, 40, 9000000, 1)) == 3
