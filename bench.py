@@ -103,6 +103,7 @@ def main():
     ap.add_argument("--no-pno", action="store_true")
     ap.add_argument("--tcut", type=float, default=None, help="PNO cut (default: the config's, else 1e-7)")
     ap.add_argument("--mixed", default="fp32,bf16", help="mixed precisions to run (comma list)")
+    ap.add_argument("--graph", type=int, default=1, help="also time the FP64 steps in graph mode (0/1)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -228,6 +229,17 @@ def main():
                 "note": (("FP32-MFMA" if name == "fp32" else "bfloat16-MFMA ladder (FP32 accumulation), FP32 other")
                          + " contractions until convergence, then FP64 sigma refinement from those roots"),
             }
+    if args.graph:
+        # the same FP64 steps with sigma blocks replayed from captured HIP graphs
+        ctx.set_graph_mode(True)
+        resg, dtg = measure(FP64, head_pno)
+        st = ctx.graph_stats()
+        ctx.set_graph_mode(False)
+        out["graph_mode_fp64"] = {
+            "time_to_convergence_s": dtg / args.steps, "speedup_vs_fp64": dt64 / dtg,
+            "max_abs_diff_vs_fp64_eh": float(np.max(np.abs(resg[-1]["omega"] - omega64))),
+            "graph_captures": st["captures"], "graph_replays": st["launches"],
+            "note": "sigma blocks captured once per block size into HIP graphs and replayed"}
     if not args.no_pno and not pno_only:
         # SA-PNO space (pair densities averaged over the nroots lowest CIS states)
         pno = (nroots, tcut)

@@ -87,6 +87,8 @@ def record_shapes(config, log=print):
     runs = [(FP64, CANONICAL), (FP32, CANONICAL), (FP64, PNO)]
     if cfg.get("space") == "pno":
         runs = [(FP64, PNO), (FP32, PNO)]
+    free, total = torch.cuda.mem_get_info()
+    log(f"[autotune] device memory free {free / 2**30:.1f} of {total / 2**30:.1f} GiB")
     for prec, space in runs:
         t0 = time.time()
         ctx.build_df(B, eps, t1, None, precision=prec)

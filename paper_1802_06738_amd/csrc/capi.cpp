@@ -119,8 +119,7 @@ int pnoeom_create(int o, int v, int naux, void* hip_stream, pnoeom_ctx** out) {
 
 void pnoeom_destroy(pnoeom_ctx* ctx) {
   if (!ctx) return;
-  for (hipEvent_t e : ctx->c.ev_pool) (void)hipEventDestroy(e);
-  delete ctx;
+  delete ctx;  // the context's destructor releases its graphs, events, stream and buffers
 }
 
 const char* pnoeom_last_error(const pnoeom_ctx* ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }

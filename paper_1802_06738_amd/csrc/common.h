@@ -52,7 +52,8 @@ struct DBuf {
     hipError_t e = hipMalloc(&p, count * sizeof(T));
     if (e != hipSuccess) {
       p = nullptr;
-      throw Error(PNOEOM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+      throw Error(PNOEOM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed (" +
+                                     hipGetErrorString(e) + ")");
     }
     n = count;
   }

@@ -52,6 +52,9 @@ def load_library():
     path = library_path()
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} is missing: build it with __graft_entry__.build()")
+    # torch first: the library then binds to the HIP runtime torch already loaded (the
+    # one whose memory and streams it is handed), not to a second copy
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
     lib.pnoeom_create.argtypes = [C.c_int, C.c_int, C.c_int, vp, C.POINTER(vp)]
