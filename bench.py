@@ -31,6 +31,26 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}    # MI355X dense matrix TFLOP/s
 HBM_PEAK = 8000.0                       # GB/s
 
+# HBM bytes per launch of the FP64 ladder GEMM on the o=20, v=150 canonical workload,
+# from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; profiles/ladder_fp64_config2_traffic.md),
+# each scaled by what the counter reads for a 1 GiB + 1 GiB device copy.  Valid only for the
+# GEMM source it was taken on: reported as null once that source changes.
+LADDER_TRAFFIC = {"config": 2, "gemm_sha256": "52af29a3451e45dc47546ae148688311cc2cef3de719d92891463c36e7c6c22b",
+                  "fetch_kib": 2727883.9, "fetch_scale": 1048576.0 / 524303.8,
+                  "write_kib": 134911.3, "write_scale": 1048576.0 / 1048576.1}
+
+
+def ladder_traffic(config, pno_only):
+    import hashlib
+    t = LADDER_TRAFFIC
+    if config != t["config"] or pno_only:
+        return None
+    src = os.path.join(ROOT, "paper_1802_06738_amd", "csrc", "gemm.hip")
+    with open(src, "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != t["gemm_sha256"]:
+            return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def run_steps(ctx, B, eps, t1, nroots, prec, steps, tol_e, tol_r, max_sub, pno=None, verbose=False, nextra=0,
               mixed_tol=(0.0, 0.0)):
@@ -181,7 +201,8 @@ def main():
         "iters_per_step": res64[-1]["iters"],
         "omega": [float(x) for x in omega64],
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["fp64"], "traffic": None,
+                     "frac": achieved / PEAK["fp64"], "traffic": ladder_traffic(args.config, pno_only),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "peak_measured": peaks["fp64_tflops"], "frac_of_measured": achieved / peaks["fp64_tflops"],
                      "kernel": "particle ladder sum_cd W_ab^cd R_ij^cd, +/- packed, all trial vectors of a "
                                "block in one contraction (gemm_kernel tag 1, FP64 MFMA)",
