@@ -111,6 +111,128 @@ def cpu_baseline(cfg_id, seconds_budget=30.0):
             "sample": f"{n} sigma vector(s) of the same workload (o={s.o}, v={s.v}, naux={s.naux}), "
                       f"{dt:.1f} s wall, setup excluded"}
 
+def config5_share(args):
+    """o=60, v=900, naux=2700: one GPU's share of a pair-sharded sigma block.
+
+    W+/- take 1.3 TB in FP64 (330 GB in bfloat16) and the canonical sigma work arrays
+    23 GB per o^2 v^2 array, so this workload does not run whole on one GPU.  The step
+    here is the part one GPU of eight owns: the particle-particle ladder (the dominant
+    term) of all 12 trial vectors of a block on ceil(P_o / 8) = 229 pairs, with W
+    streamed from the dressed factors inside the step.  Reports the FP64 and the
+    BF16-MFMA rates, their difference, and the oracle's row-by-row form on the host for
+    a sample of rows, extrapolated to the share."""
+    import math
+    import torch
+    from synthgen import config_system, CONFIGS
+    from paper_1802_06738_amd import PnoEom, FP64, BF16
+
+    cfg = CONFIGS[5]
+    t0 = time.perf_counter()
+    print("[bench] config 5: generating o=60, v=900, naux=2700", file=sys.stderr, flush=True)
+    s = config_system(5)
+    o, v, naux, nvec = s.o, s.v, s.naux, cfg["nroots"]
+    npair_all = o * (o + 1) // 2
+    npair = math.ceil(npair_all / 8)
+    nmat = nvec * npair
+    print(f"[bench] config 5: generated in {time.perf_counter() - t0:.0f} s; share {npair} pairs x {nvec} vectors",
+          file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1807)
+    X = torch.randn((nmat, v, v), generator=gen, dtype=torch.float64, device=dev)
+    Y = torch.empty_like(X)
+    ctx = PnoEom(o, v, naux)
+    peaks = ctx.probe_peaks()
+    out_runs = {}
+    for prec, name in ((FP64, "fp64"), (BF16, "bf16")):
+        Bd = torch.from_numpy(s.B).to(dev)
+        t1 = torch.from_numpy(s.t1).to(dev)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ctx.build_ladder(Bd, t1, precision=prec)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - tb
+        del Bd
+        torch.cuda.empty_cache()
+        for _ in range(args.warmup):
+            ctx.ladder_apply(X, precision=prec, out=Y)
+        torch.cuda.synchronize()
+        print(f"[bench] config 5 {name}: factors in {t_build:.1f} s, warmup done", file=sys.stderr, flush=True)
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.ladder_apply(X, precision=prec, out=Y)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - ts) / args.steps
+        t = ctx.last_timing()
+        lt = t[name]
+        wb = t["ladder_w_build"]
+        print(f"[bench] config 5 {name}: {dt:.2f} s per step", file=sys.stderr, flush=True)
+        run = {"seconds_per_step": dt, "sigma_vectors_per_s": nvec / dt, "factor_build_s": t_build,
+               "ladder_contraction": {"ms": lt["ladder_ms"], "launches": lt["ladder_launches"],
+                                      "flops": lt["ladder_flops"],
+                                      "TFLOP/s": lt["ladder_flops"] / (lt["ladder_ms"] * 1e-3) / 1e12},
+               "w_slab_build": {"ms": wb["ms"], "launches": wb["launches"], "flops": wb["flops"],
+                                "TFLOP/s": wb["flops"] / (wb["ms"] * 1e-3) / 1e12 if wb["ms"] > 0 else None}}
+        if name == "fp64":
+            Y64 = Y.clone()
+        else:
+            run["max_abs_diff_vs_fp64"] = float((Y - Y64).abs().max())
+            run["max_rel_diff_vs_fp64"] = run["max_abs_diff_vs_fp64"] / float(Y64.abs().max())
+        out_runs[name] = run
+    r64 = out_runs["fp64"]
+    lc = r64["ladder_contraction"]
+    achieved = lc["TFLOP/s"]
+    out = {
+        "metric": "sigma evals/s & Davidson time-to-convergence (FP64; FP32 and BF16 mixed variants; PNO vs canonical)",
+        "value": r64["sigma_vectors_per_s"],
+        "unit": "sigma-evals/s (ladder term, one GPU's share of the pairs)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * r64["seconds_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"config 5 share: particle-particle ladder of {nvec} vectors on {npair} of "
+                               f"{npair_all} pairs (one GPU of eight), o={o}, v={v}, naux={naux}, W streamed "
+                               f"from the dressed factors in every step",
+                   "o": o, "v": v, "naux": naux, "nvec": nvec, "pairs": npair, "matrices": nmat},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK["fp64"], "traffic": None,
+                     "peak_measured": peaks["fp64_tflops"], "frac_of_measured": achieved / peaks["fp64_tflops"],
+                     "kernel": "ladder contraction with the streamed W+/- slab rows (gemm_kernel tag 1, FP64 MFMA)",
+                     "algorithmic_flops_per_launch": lc["flops"] / max(lc["launches"], 1),
+                     "avg_launch_ms": lc["ms"] / max(lc["launches"], 1), "launches": lc["launches"]},
+        "runs": out_runs,
+        "measured_peaks": peaks,
+    }
+    if not args.no_cpu_baseline:
+        # the oracle's row form on the host: each sampled (m, a) costs one naux x v x v
+        # product and each entry one length naux*v dot; both unit costs are measured (runs
+        # with 1 and with 41 entries per row) and the share's rows and entries priced with them
+        from oracle.ladder import ladder_entries
+        Xh = X[:2].cpu().numpy()
+        rng = np.random.default_rng(5)
+        rows_s = [(m, int(a)) for m in range(2) for a in rng.integers(0, v, 2)]
+        bs = [int(b) for b in rng.integers(0, v, 41)]
+        tc = time.perf_counter()
+        ladder_entries(s.B, o, s.t1, Xh, [(m, a, bs[0]) for m, a in rows_s])
+        t_one = time.perf_counter() - tc
+        tc = time.perf_counter()
+        ladder_entries(s.B, o, s.t1, Xh, [(m, a, b) for m, a in rows_s for b in bs])
+        t_many = time.perf_counter() - tc
+        k = len(rows_s)
+        t_entry = max(t_many - t_one, 0.0) / (k * (len(bs) - 1))
+        t_row = max(t_one / k - t_entry, 0.0)
+        share_s = nmat * v * t_row + nmat * v * v * t_entry
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max(int(p.get("num_threads", 1)) for p in threadpool_info()) if threadpool_info() else 1
+        except Exception:
+            threads = os.cpu_count() or 1
+        out["cpu_baseline"] = {"value": nvec / share_s, "unit": out["unit"], "cores": threads, "kind": "oracle",
+                               "sample": f"oracle row form on {k} rows (m, a) with 1 and with {len(bs)} entries "
+                                         f"each ({t_one + t_many:.1f} s wall): {t_row:.3f} s per row, "
+                                         f"{1e3 * t_entry:.2f} ms per entry, extrapolated to the share's "
+                                         f"{nmat * v} rows and {nmat * v * v} entries"}
+    print(json.dumps(out))
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -128,6 +250,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.config == 5:
+        config5_share(args)
+        return
 
     import torch
     from synthgen import config_system, CONFIGS

@@ -132,6 +132,45 @@ int pnoeom_pno_transform(pnoeom_ctx* ctx, int nvec, int direction, double* r1, d
 int pnoeom_apply_sigma(pnoeom_ctx* ctx, int nvec, const double* r1, const double* r2, double* s1,
                        double* s2, int space, int precision);
 
+/* Storage of the particle-particle ladder W_ab^cd = sum_Q B~^Q_ac B~^Q_bd (Methods: the
+ * largest intermediate; B~ the T1-dressed factors), for the next pnoeom_build_df:
+ *   mode PNOEOM_LADDER_AUTO (0): cached when the packed W+/- fit in 60% of the free
+ *        device memory, else streamed;
+ *   mode PNOEOM_LADDER_CACHED (1): W+/- (v^4/2 words) built once and kept;
+ *   mode PNOEOM_LADDER_STREAMED (2): never stored; every sigma rebuilds the rows of
+ *        W+/- from B~_vv one slab of a-values at a time (an MFMA GEMM over Q per slab)
+ *        and contracts them at once with all trial vectors of the call.  The results
+ *        equal those of the cached mode up to rounding order.
+ *   max_slab : upper bound on the a-values per slab (0 = from the memory budget: 30%
+ *        of the free device memory, 256 MB to 64 GB).
+ * Errors: EINVAL (null ctx, bad mode, max_slab < 0). */
+enum { PNOEOM_LADDER_AUTO = 0, PNOEOM_LADDER_CACHED = 1, PNOEOM_LADDER_STREAMED = 2 };
+int pnoeom_set_ladder_mode(pnoeom_ctx* ctx, int mode, int max_slab);
+
+/* Prepare the context for pnoeom_ladder_apply alone: the dressed virtual factors
+ * B~^Q_ac = B^Q_ac - sum_k t_k^a B^Q_kc (the virtual block of the T1 similarity
+ * transformation of the Methods section) and the streamed-ladder workspace, without
+ * the other intermediates of build_df.  For workloads whose W does not fit one GPU
+ * (v = 900: W+/- take 1.3 TB in FP64): each GPU of a pair-sharded sigma applies the
+ * ladder to the pair blocks it owns.
+ *   B  : device [naux][nmo][nmo] as in pnoeom_build_df (read during the call only)
+ *   t1 : device [o][v] or NULL (T1 = 0)
+ *   precision : as in pnoeom_build_df (FP32 / BF16 copies of B~ for those precisions)
+ * Discards the intermediates of an earlier build_df (apply_sigma then needs build_df
+ * again).  Device memory held: B~ (v^2 naux words FP64, plus the low-precision copy)
+ * and the slab workspace.  Errors: EINVAL, ENOMEM, EHIP. */
+int pnoeom_build_ladder(pnoeom_ctx* ctx, const double* B, const double* t1, int precision);
+
+/* The particle-particle ladder of nmat doubles blocks:
+ *   Y[m][a][b] = sum_cd W_ab^cd X[m][c][d],   W_ab^cd = sum_Q B~^Q_ac B~^Q_bd,
+ * i.e. the ladder term of sigma2 for the pair blocks X[m] = R_ij (any pairs, any
+ * vectors).  X, Y : device [nmat][v][v] FP64 (may not overlap).  precision as in
+ * pnoeom_apply_sigma: FP32 / BF16 contract in that precision (BF16: bfloat16
+ * operands, FP32 accumulation) and need the same precision at build time.
+ * Uses the cached W+/- when build_df cached them, else streams W from B~.
+ * Requires build_df or build_ladder.  Errors: ESTATE, EINVAL, ENOMEM, EHIP. */
+int pnoeom_ladder_apply(pnoeom_ctx* ctx, int nmat, const double* X, double* Y, int precision);
+
 typedef struct {
   int space;           /* PNOEOM_CANONICAL or PNOEOM_PNO */
   int precision;       /* PNOEOM_FP64, PNOEOM_FP32 or PNOEOM_BF16 contractions; subspace work is FP64 */
@@ -242,7 +281,8 @@ int pnoeom_last_timing(const pnoeom_ctx* ctx, double* total_ms, double* ladder_m
 int pnoeom_last_ladder_timing(const pnoeom_ctx* ctx, int precision, double* ladder_ms, int* ladder_launches,
                               double* ladder_flops);
 
-/* Two further timed regions of the last pnoeom_davidson / pnoeom_apply_sigma call, for
+/* Further timed regions of the last pnoeom_davidson / pnoeom_apply_sigma /
+ * pnoeom_ladder_apply call, for
  * the roofline of the bandwidth-side kernels:
  *   region 0: the Davidson inner products (Gram-Schmidt, subspace matrix, residual
  *             norms); bytes = 8 (n_a + n_b) N per sweep over n_a x n_b products of
@@ -250,7 +290,12 @@ int pnoeom_last_ladder_timing(const pnoeom_ctx* ctx, int precision, double* ladd
  *   region 1: the PNO back-transform and projection (Methods, PNO simulation):
  *             per vector and direction, bytes = 8 (ov + o^2 v^2 + len + |U|) (canonical
  *             vector, compressed vector and bases each moved once), flops =
- *             sum over pairs of (2 n_p v^2 + 2 n_p^2 v) plus 2 n_i v per occupied i.
+ *             sum over pairs of (2 n_p v^2 + 2 n_p^2 v) plus 2 n_i v per occupied i;
+ *   region 2: the W slab builds of the streamed ladder (factor GEMM and pack of W+/-
+ *             rows); flops = 2 (na v)(nb v) naux per slab of na rows a and nb columns
+ *             b >= a0, bytes = the slab block written and read (3 passes) plus the
+ *             packed rows written.  The contraction with the slab rows counts as ladder
+ *             time in pnoeom_last_timing / pnoeom_last_ladder_timing.
  * ms are HIP-event times on the context stream.  Errors: EINVAL (null ctx, bad region). */
 int pnoeom_last_region_timing(const pnoeom_ctx* ctx, int region, double* ms, int* launches, double* flops,
                               double* bytes);

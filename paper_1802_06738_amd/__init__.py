@@ -5,7 +5,7 @@ this package holds its ctypes binding.  PyTorch provides device memory and
 streams only.
 """
 from .pnoeom import (PnoEom, PnoEomError, load_library, library_path, host_eig, host_syev, FP64, FP32, BF16,
-                     CANONICAL, PNO, EXPORTED_SYMBOLS)
+                     CANONICAL, PNO, LADDER_AUTO, LADDER_CACHED, LADDER_STREAMED, EXPORTED_SYMBOLS)
 
 __all__ = ["PnoEom", "PnoEomError", "load_library", "library_path", "host_eig", "host_syev", "FP64", "FP32", "BF16",
-           "CANONICAL", "PNO", "EXPORTED_SYMBOLS"]
+           "CANONICAL", "PNO", "LADDER_AUTO", "LADDER_CACHED", "LADDER_STREAMED", "EXPORTED_SYMBOLS"]

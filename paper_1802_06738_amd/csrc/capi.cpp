@@ -218,6 +218,38 @@ int pnoeom_apply_sigma(pnoeom_ctx* ctx, int nvec, const double* r1, const double
   });
 }
 
+int pnoeom_set_ladder_mode(pnoeom_ctx* ctx, int mode, int max_slab) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(mode == PNOEOM_LADDER_AUTO || mode == PNOEOM_LADDER_CACHED || mode == PNOEOM_LADDER_STREAMED,
+              PNOEOM_EINVAL, "set_ladder_mode: unknown mode");
+    PNO_CHECK(max_slab >= 0, PNOEOM_EINVAL, "set_ladder_mode: max_slab < 0");
+    c.lad_mode = mode;
+    c.lad_max_slab = max_slab;
+  });
+}
+
+int pnoeom_build_ladder(pnoeom_ctx* ctx, const double* B, const double* t1, int precision) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(B, PNOEOM_EINVAL, "build_ladder: B is required");
+    PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32 || precision == PNOEOM_BF16, PNOEOM_EINVAL,
+              "build_ladder: precision must be PNOEOM_FP64, PNOEOM_FP32 or PNOEOM_BF16");
+    pnoeom::build_ladder(c, B, t1, precision, pnoeom::ladder_budget());
+  });
+}
+
+int pnoeom_ladder_apply(pnoeom_ctx* ctx, int nmat, const double* X, double* Y, int precision) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(nmat >= 0, PNOEOM_EINVAL, "ladder_apply: nmat < 0");
+    if (nmat == 0) return;
+    PNO_CHECK(X && Y, PNOEOM_EINVAL, "ladder_apply: null matrix pointer");
+    const int64_t vv = (int64_t)c.v * c.v;
+    PNO_CHECK(X + nmat * vv <= Y || Y + nmat * vv <= X, PNOEOM_EINVAL, "ladder_apply: X and Y overlap");
+    Timer t(c);
+    pnoeom::ladder_apply(c, nmat, X, Y, precision);
+    t.stop();
+  });
+}
+
 int pnoeom_set_graph_mode(pnoeom_ctx* ctx, int enable) {
   return guarded(ctx, [&](pnoeom::Context& c) {
     c.graph_mode = enable != 0;

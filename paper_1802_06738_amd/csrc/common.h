@@ -79,7 +79,7 @@ struct GemmDesc {
   int64_t ldc = 0, sC = 0;
   int64_t batch = 1;
   bool reduce = false;
-  int tag = 0;  // 1: the particle-particle ladder (own kernel symbol, for profiling)
+  int tag = 0;  // 1: the particle-particle ladder, 2: its W slab build (own kernel symbols, for profiling)
 };
 
 void gemm(const GemmDesc<double>& d, hipStream_t s);
@@ -112,7 +112,7 @@ struct GemmBf16Desc {
   int64_t ldb = 0;
   float* C = nullptr;
   int64_t ldc = 0;
-  int tag = 0;  // 1: the particle-particle ladder
+  int tag = 0;  // 1: the particle-particle ladder, 2: its W slab build
 };
 void gemm_bf16(const GemmBf16Desc& d, hipStream_t s);
 

@@ -81,6 +81,15 @@ struct Context {
   DBuf<float> Tf, Tiaf, Tsiaf, Drf, Xrf, DX2f;
   DBuf<double> scratch;         // build-time temporaries
 
+  // ladder storage (pnoeom_set_ladder_mode): 0 auto, 1 cached W+/-, 2 streamed from B~_vv
+  int lad_mode = 0, lad_max_slab = 0;
+  bool lad_streamed = false;    // W+/- not stored: rebuilt slab by slab in every sigma
+  bool have_lad = false;        // the ladder can be applied (build_df or build_ladder done)
+  DBuf<float> BvvTf;            // FP32 copy of BvvT (streamed, precision FP32)
+  DBuf<uint16_t> BvvTb;         // bfloat16 copy of BvvT, rows padded to ldq columns (streamed, BF16)
+  int64_t ldq = 0;
+  DBuf<double> lad_tmp, lad_wp, lad_wm;  // slab workspace (raw storage, element type per precision)
+
   SigmaWork sw;
   PNOData pno;
 
@@ -95,12 +104,13 @@ struct Context {
   double last_ladder_ms_p[3] = {0, 0, 0}, last_ladder_flops_p[3] = {0, 0, 0};
   int last_ladder_launches_p[3] = {0, 0, 0};
   std::vector<int> ev_prec;         // per start/stop event pair: ladder precision (0..2) or 3 + region
-  // other timed regions: 0 = Davidson inner products, 1 = PNO back-transform / projection
-  static constexpr int kRegions = 2;
-  double reg_flops[kRegions] = {0, 0}, reg_bytes[kRegions] = {0, 0};
-  int reg_launches[kRegions] = {0, 0};
-  double last_reg_ms[kRegions] = {0, 0}, last_reg_flops[kRegions] = {0, 0}, last_reg_bytes[kRegions] = {0, 0};
-  int last_reg_launches[kRegions] = {0, 0};
+  // other timed regions: 0 = Davidson inner products, 1 = PNO back-transform / projection,
+  // 2 = W slab builds of the streamed ladder (factor GEMM + pack)
+  static constexpr int kRegions = 3;
+  double reg_flops[kRegions] = {}, reg_bytes[kRegions] = {};
+  int reg_launches[kRegions] = {};
+  double last_reg_ms[kRegions] = {}, last_reg_flops[kRegions] = {}, last_reg_bytes[kRegions] = {};
+  int last_reg_launches[kRegions] = {};
   // events around a timed region (returns the stop event to record, or nullptr when not timing)
   hipEvent_t region_begin(int region, hipStream_t s) {
     if (!timing) return nullptr;
@@ -164,6 +174,15 @@ struct Context {
 
 void build_df(Context& c, const double* B, const double* eps, const double* t1, const double* t2,
               int precision);
+// streamed ladder (ladder.hip)
+int64_t ladder_budget();
+int64_t streamed_ladder_bytes(const Context& c, int64_t na0, int precision);
+void prepare_streamed_ladder(Context& c, int precision, int64_t budget_bytes);
+void ladder_streamed(Context& c, int precision, int64_t rows, const void* S, int64_t ldS, const void* A,
+                     int64_t ldA, void* SigP, void* SigM);
+void build_ladder(Context& c, const double* B, const double* t1, int precision, int64_t budget_bytes);
+// Y_m = sum_cd W_abcd X_m[c][d] for nmat v x v matrices (cached or streamed W)
+void ladder_apply(Context& c, int nmat, const double* X, double* Y, int precision);
 void sigma_canonical(Context& c, const double* r1, const double* r2, double* s1, double* s2, int precision);
 // nvec vectors; r1/s1 of vector q at offset q*stride1, r2/s2 at q*stride2
 void sigma_block(Context& c, int nvec, const double* r1, const double* r2, double* s1, double* s2, int64_t stride1,

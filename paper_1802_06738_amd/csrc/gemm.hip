@@ -332,6 +332,8 @@ void launch_tile(const GemmDesc<T>& d, hipStream_t s, int split_mode = 0) {
   dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)nsplit);
   if (d.tag == 1 && !d.ta && d.tb)
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, true, 1>), grid, dim3(NT), 0, s, g);
+  else if (d.tag == 2 && !d.ta && d.tb)
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, true, 2>), grid, dim3(NT), 0, s, g);
   else if (!d.ta && !d.tb)
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, false, 0>), grid, dim3(NT), 0, s, g);
   else if (d.ta && !d.tb)
@@ -690,6 +692,8 @@ void gemm_bf16(const GemmBf16Desc& d, hipStream_t s) {
   PNO_CHECK(gx < (1ll << 31), PNOEOM_EINVAL, "gemm_bf16: too many tiles");
   if (d.tag == 1)
     hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, 1>), dim3((unsigned)gx), dim3(NT), 0, s, g);
+  else if (d.tag == 2)
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, 2>), dim3((unsigned)gx), dim3(NT), 0, s, g);
   else
     hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, 0>), dim3((unsigned)gx), dim3(NT), 0, s, g);
   PNO_HIP(hipGetLastError());

@@ -247,6 +247,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   const int64_t n2 = (int64_t)nmo * nmo, ov = c.ov(), oo = (int64_t)o * o, vv = (int64_t)v * v;
   const int64_t oovv = c.oovv();
   c.have_df = false;
+  c.have_lad = false;
   c.precision = precision;
   // workspaces and bases of the previous intermediates are dropped first, so that the
   // new ones (e.g. a second copy of W+/- in another precision) have the memory
@@ -436,18 +437,35 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     }
   }
 
-  // packed ladder matrices W+ / W- built from slabs W_abcd = (ac|bd)~ of rows a
-  {
+  // packed ladder matrices W+ / W- built from slabs W_abcd = (ac|bd)~ of rows a, cached for
+  // every sigma; or, when they do not fit (or streaming is asked for), rebuilt per sigma
+  const int64_t lad_vp = (int64_t)v * (v + 1) / 2, lad_vm = std::max<int64_t>((int64_t)v * (v - 1) / 2, 1);
+  c.Wp.release(); c.Wm.release(); c.Wpf.release(); c.Wmf.release(); c.Wpb.release(); c.Wmb.release();
+  c.ldpb = bf16_ld(lad_vp);
+  c.ldmb = bf16_ld(lad_vm);
+  bool stream_w = c.lad_mode == 2;
+  if (c.lad_mode == 0) {
+    double need = 8.0 * ((double)lad_vp * lad_vp + (double)lad_vm * lad_vm);
+    if (precision == PNOEOM_FP32) need *= 1.5;
+    if (precision == PNOEOM_BF16) need += 2.0 * ((double)lad_vp * c.ldpb + (double)lad_vm * c.ldmb);
+    size_t fr = 0, tot = 0;
+    PNO_HIP(hipMemGetInfo(&fr, &tot));
+    stream_w = need > 0.6 * (double)fr;
+  }
+  if (stream_w) {
+    prepare_streamed_ladder(c, precision, ladder_budget());
+  } else {
+    c.lad_streamed = false;
+    c.BvvTf.release(); c.BvvTb.release(); c.lad_tmp.release(); c.lad_wp.release(); c.lad_wm.release();
+  }
+  if (!stream_w) {
     const int64_t vp = (int64_t)v * (v + 1) / 2, vm = (int64_t)v * (v - 1) / 2;
     const bool f32w = precision == PNOEOM_FP32;
     const bool bfw = precision == PNOEOM_BF16;
-    c.Wp.release(); c.Wm.release(); c.Wpf.release(); c.Wmf.release(); c.Wpb.release(); c.Wmb.release();
     c.Wp.alloc(vp * vp);
     c.Wm.alloc(std::max<int64_t>(vm * vm, 1));
     if (f32w) { c.Wpf.alloc(vp * vp); c.Wmf.alloc(std::max<int64_t>(vm * vm, 1)); }
     // bfloat16 copies with rows padded to a multiple of 64 columns (zeros past the end)
-    c.ldpb = bf16_ld(vp);
-    c.ldmb = bf16_ld(std::max<int64_t>(vm, 1));
     if (bfw) {
       c.Wpb.alloc(vp * c.ldpb);
       c.Wmb.alloc(std::max<int64_t>(vm, 1) * c.ldmb);
@@ -493,6 +511,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   }
   PNO_HIP(hipStreamSynchronize(s));
   c.have_df = true;
+  c.have_lad = true;
 }
 
 namespace {
@@ -771,55 +790,33 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
 }  // namespace
 
 namespace {
-// one chunk of trial vectors: all of them go through the ladder and the rest together
-void sigma_block_chunk(Context& c, int nvec, const double* r1, const double* r2, double* s1, double* s2,
-                       int64_t stride1, int64_t stride2, int precision) {
-  PNO_CHECK(c.have_df, PNOEOM_ESTATE, "sigma before build_df");
+// the ladder can run in this precision: FP64 always; FP32 / BF16 only in the precision of the build
+void ladder_check(const Context& c, int precision) {
   PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32 || precision == PNOEOM_BF16, PNOEOM_EINVAL,
-            "sigma: precision must be FP64, FP32 or BF16");
+            "ladder: precision must be FP64, FP32 or BF16");
   const bool f32 = precision == PNOEOM_FP32, bf = precision == PNOEOM_BF16;
-  PNO_CHECK(f32 ? (c.Wpf.p != nullptr) : bf ? (c.Wpb.p != nullptr) : (c.Wp.p != nullptr), PNOEOM_EINVAL,
-            "sigma: the contraction precision must match the one given to build_df");
-  if (nvec <= 0) return;
+  const bool ok = c.lad_streamed ? (f32 ? c.BvvTf.p != nullptr : bf ? c.BvvTb.p != nullptr : c.BvvT.p != nullptr)
+                                 : (f32 ? c.Wpf.p != nullptr : bf ? c.Wpb.p != nullptr : c.Wp.p != nullptr);
+  PNO_CHECK(ok, PNOEOM_EINVAL, "ladder: the contraction precision must match the one given to build_df");
+}
+
+// sigma+/- of `rows` packed rows of the work arrays (Sp/Am, Spf/Amf or Spb/Amb -> SigP/SigM or
+// SigPf/SigMf): the cached W+/- in one GEMM each, or the streamed slabs
+void ladder_contract(Context& c, int precision, int64_t rows) {
   SigmaWork& w = c.sw;
   hipStream_t s = c.stream;
-  const int o = c.o, v = c.v;
-  const int64_t oovv = c.oovv();
-  const int64_t npair = (int64_t)o * (o + 1) / 2, vp = (int64_t)v * (v + 1) / 2, vm = (int64_t)v * (v - 1) / 2;
-  const int64_t vm1 = std::max<int64_t>(vm, 1);
-  const int64_t rows = (int64_t)nvec * npair;
-  grow(w.LadAll, (int64_t)nvec * oovv);
-  const int64_t tot = (int64_t)nvec * oovv;
-  // ---------------------------------------------------------------- particle ladder, all vectors at once
+  const int64_t v = c.v, vp = v * (v + 1) / 2, vm = v * (v - 1) / 2;
+  const bool f32 = precision == PNOEOM_FP32, bf = precision == PNOEOM_BF16;
+  if (c.lad_streamed) {
+    if (f32)
+      ladder_streamed(c, precision, rows, w.Spf, vp, w.Amf, vm, w.SigPf, w.SigMf);
+    else if (bf)
+      ladder_streamed(c, precision, rows, w.Spb, c.ldpb, w.Amb, c.ldmb, w.SigPf, w.SigMf);
+    else
+      ladder_streamed(c, precision, rows, w.Sp, vp, w.Am, vm, w.SigP, w.SigM);
+    return;
+  }
   hipEvent_t lad0 = nullptr, lad1 = nullptr;
-  if (f32 || bf) {
-    grow(w.SigPf, rows * vp); grow(w.SigMf, rows * vm1);
-  } else {
-    grow(w.SigP, rows * vp); grow(w.SigM, rows * vm1);
-  }
-  if (f32) {
-    grow(w.Spf, rows * vp); grow(w.Amf, rows * vm1);
-    hipLaunchKernelGGL((ladder_pack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec, r2, stride2,
-                       (float*)w.Spf, vp, (float*)w.Amf, vm);
-  } else if (bf) {
-    // padded rows; the padding columns are zeroed once per allocation and never written
-    if ((int64_t)w.Spb.n < rows * c.ldpb || (int64_t)w.Amb.n < rows * c.ldmb) {
-      w.Spb.alloc(rows * c.ldpb);
-      w.Amb.alloc(rows * c.ldmb);
-      hipLaunchKernelGGL(zero_u16_kernel, dim3(grid1((int64_t)w.Spb.n)), dim3(256), 0, s, (int64_t)w.Spb.n,
-                         (uint16_t*)w.Spb);
-      hipLaunchKernelGGL(zero_u16_kernel, dim3(grid1((int64_t)w.Amb.n)), dim3(256), 0, s, (int64_t)w.Amb.n,
-                         (uint16_t*)w.Amb);
-      PNO_HIP(hipGetLastError());
-    }
-    hipLaunchKernelGGL((ladder_pack_kernel<uint16_t>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec, r2, stride2,
-                       (uint16_t*)w.Spb, c.ldpb, (uint16_t*)w.Amb, c.ldmb);
-  } else {
-    grow(w.Sp, rows * vp); grow(w.Am, rows * vm1);
-    hipLaunchKernelGGL((ladder_pack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec, r2, stride2,
-                       (double*)w.Sp, vp, (double*)w.Am, vm);
-  }
-  PNO_HIP(hipGetLastError());
   if (c.timing) {
     lad0 = c.next_event();
     lad1 = c.next_event();
@@ -857,13 +854,91 @@ void sigma_block_chunk(Context& c, int nvec, const double* r1, const double* r2,
     c.ladder_flops_p[precision] += fl;
     c.ladder_launches_p[precision] += nl;
   }
-  if (f32 || bf)
-    hipLaunchKernelGGL((ladder_unpack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec,
-                       (const float*)w.SigPf, (const float*)w.SigMf, (double*)w.LadAll, oovv);
-  else
-    hipLaunchKernelGGL((ladder_unpack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, o, v, nvec,
-                       (const double*)w.SigP, (const double*)w.SigM, (double*)w.LadAll, oovv);
+}
+
+// packs nvec vectors (pairs of o occupied) into the ladder work arrays of a precision
+void ladder_pack(Context& c, int precision, int o, int nvec, const double* r2, int64_t stride2) {
+  SigmaWork& w = c.sw;
+  hipStream_t s = c.stream;
+  const int64_t v = c.v, vp = v * (v + 1) / 2, vm = v * (v - 1) / 2, vm1 = std::max<int64_t>(vm, 1);
+  const int64_t rows = (int64_t)nvec * o * (o + 1) / 2;
+  const int64_t tot = (int64_t)nvec * o * o * v * v;
+  const bool f32 = precision == PNOEOM_FP32, bf = precision == PNOEOM_BF16;
+  if (f32 || bf) {
+    grow(w.SigPf, rows * vp); grow(w.SigMf, rows * vm1);
+  } else {
+    grow(w.SigP, rows * vp); grow(w.SigM, rows * vm1);
+  }
+  if (f32) {
+    grow(w.Spf, rows * vp); grow(w.Amf, rows * vm1);
+    hipLaunchKernelGGL((ladder_pack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, o, (int)v, nvec, r2, stride2,
+                       (float*)w.Spf, vp, (float*)w.Amf, vm);
+  } else if (bf) {
+    // padded rows; the padding columns are zeroed once per allocation and never written
+    if ((int64_t)w.Spb.n < rows * c.ldpb || (int64_t)w.Amb.n < rows * c.ldmb) {
+      w.Spb.alloc(rows * c.ldpb);
+      w.Amb.alloc(rows * c.ldmb);
+      hipLaunchKernelGGL(zero_u16_kernel, dim3(grid1((int64_t)w.Spb.n)), dim3(256), 0, s, (int64_t)w.Spb.n,
+                         (uint16_t*)w.Spb);
+      hipLaunchKernelGGL(zero_u16_kernel, dim3(grid1((int64_t)w.Amb.n)), dim3(256), 0, s, (int64_t)w.Amb.n,
+                         (uint16_t*)w.Amb);
+      PNO_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL((ladder_pack_kernel<uint16_t>), dim3(grid1(tot)), dim3(256), 0, s, o, (int)v, nvec, r2,
+                       stride2, (uint16_t*)w.Spb, c.ldpb, (uint16_t*)w.Amb, c.ldmb);
+  } else {
+    grow(w.Sp, rows * vp); grow(w.Am, rows * vm1);
+    hipLaunchKernelGGL((ladder_pack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, o, (int)v, nvec, r2,
+                       stride2, (double*)w.Sp, vp, (double*)w.Am, vm);
+  }
   PNO_HIP(hipGetLastError());
+}
+
+// unpacks the ladder result of nvec vectors into full [q][i][j][a][b] arrays (stride per vector)
+void ladder_unpack(Context& c, int precision, int o, int nvec, double* out, int64_t stride) {
+  SigmaWork& w = c.sw;
+  const int64_t v = c.v, tot = (int64_t)nvec * o * o * v * v;
+  if (precision != PNOEOM_FP64)
+    hipLaunchKernelGGL((ladder_unpack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, c.stream, o, (int)v, nvec,
+                       (const float*)w.SigPf, (const float*)w.SigMf, out, stride);
+  else
+    hipLaunchKernelGGL((ladder_unpack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, c.stream, o, (int)v, nvec,
+                       (const double*)w.SigP, (const double*)w.SigM, out, stride);
+  PNO_HIP(hipGetLastError());
+}
+}  // namespace
+
+void ladder_apply(Context& c, int nmat, const double* X, double* Y, int precision) {
+  PNO_CHECK(c.have_lad, PNOEOM_ESTATE, "ladder_apply before build_df or build_ladder");
+  PNO_CHECK(nmat >= 0, PNOEOM_EINVAL, "ladder_apply: nmat < 0");
+  ladder_check(c, precision);
+  if (nmat == 0) return;
+  PNO_CHECK(X && Y, PNOEOM_EINVAL, "ladder_apply: null matrix pointer");
+  const int64_t vv = (int64_t)c.v * c.v;
+  // each matrix is the doubles block of one pair: the packing of a single occupied index
+  ladder_pack(c, precision, 1, nmat, X, vv);
+  ladder_contract(c, precision, nmat);
+  ladder_unpack(c, precision, 1, nmat, Y, vv);
+}
+
+namespace {
+// one chunk of trial vectors: all of them go through the ladder and the rest together
+void sigma_block_chunk(Context& c, int nvec, const double* r1, const double* r2, double* s1, double* s2,
+                       int64_t stride1, int64_t stride2, int precision) {
+  PNO_CHECK(c.have_df, PNOEOM_ESTATE, "sigma before build_df");
+  PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32 || precision == PNOEOM_BF16, PNOEOM_EINVAL,
+            "sigma: precision must be FP64, FP32 or BF16");
+  ladder_check(c, precision);
+  if (nvec <= 0) return;
+  SigmaWork& w = c.sw;
+  const int o = c.o;
+  const int64_t oovv = c.oovv();
+  const int64_t rows = (int64_t)nvec * o * (o + 1) / 2;
+  grow(w.LadAll, (int64_t)nvec * oovv);
+  // ---------------------------------------------------------------- particle ladder, all vectors at once
+  ladder_pack(c, precision, o, nvec, r2, stride2);
+  ladder_contract(c, precision, rows);
+  ladder_unpack(c, precision, o, nvec, w.LadAll, oovv);
   // ---------------------------------------------------------------- everything else
   sigma_rest_block(c, nvec, r1, stride1, r2, stride2, s1, s2, precision, w.LadAll);
 }

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 FP64, FP32, BF16 = 0, 1, 2
 CANONICAL, PNO = 0, 1
+LADDER_AUTO, LADDER_CACHED, LADDER_STREAMED = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "ESTATE", -6: "ECOMPLEX",
           -7: "EABORTED"}
 EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pnoeom_build_df", "pnoeom_cis",
@@ -23,7 +24,8 @@ EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pno
                     "pnoeom_davidson", "pnoeom_host_eig", "pnoeom_last_timing", "pnoeom_last_ladder_timing",
                     "pnoeom_last_region_timing", "pnoeom_host_syev", "pnoeom_probe_peaks",
                     "pnoeom_gemm_record", "pnoeom_gemm_recorded", "pnoeom_gemm_time", "pnoeom_gemm_set_table",
-                    "pnoeom_set_graph_mode", "pnoeom_graph_stats"]
+                    "pnoeom_set_graph_mode", "pnoeom_graph_stats", "pnoeom_set_ladder_mode",
+                    "pnoeom_build_ladder", "pnoeom_ladder_apply"]
 
 
 class PnoEomError(RuntimeError):
@@ -83,6 +85,9 @@ def load_library():
     lib.pnoeom_gemm_set_table.argtypes = [C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_int)]
     lib.pnoeom_set_graph_mode.argtypes = [vp, C.c_int]
     lib.pnoeom_graph_stats.argtypes = [vp, ip, ip, ip]
+    lib.pnoeom_set_ladder_mode.argtypes = [vp, C.c_int, C.c_int]
+    lib.pnoeom_build_ladder.argtypes = [vp, vp, vp, C.c_int]
+    lib.pnoeom_ladder_apply.argtypes = [vp, C.c_int, vp, vp, C.c_int]
     _LIB = lib
     # the autotuner's table of GEMM tile choices for this device, when present
     from .autotune import DEFAULT_TABLE, load_table
@@ -255,6 +260,26 @@ class PnoEom:
             self._check(st)
         return dict(omega=om, resnorm=rn, iters=it.value, nsigma=ns.value, complex=(st == -6))
 
+    def set_ladder_mode(self, mode=LADDER_AUTO, max_slab=0):
+        """Cached or streamed W+/- for the next build_df (LADDER_AUTO / _CACHED / _STREAMED)."""
+        self._check(self.lib.pnoeom_set_ladder_mode(self.h, int(mode), int(max_slab)))
+
+    def build_ladder(self, B, t1=None, precision=FP64):
+        """Dressed virtual factors and the streamed-ladder workspace only (no other intermediates)."""
+        o, v, n = self.o, self.v, self.nmo
+        self._check(self.lib.pnoeom_build_ladder(self.h, _dev(B, (self.naux, n, n), "B"),
+                                                 _dev(t1, (o, v), "t1") if t1 is not None else None, precision))
+
+    def ladder_apply(self, X, precision=FP64, out=None):
+        """Y[m] = sum_cd W_ab^cd X[m][c][d] for X [nmat, v, v] (torch float64 on device)."""
+        import torch
+        nmat = X.shape[0]
+        v = self.v
+        Y = torch.empty_like(X) if out is None else out
+        self._check(self.lib.pnoeom_ladder_apply(self.h, nmat, _dev(X, (nmat, v, v), "X"),
+                                                 _dev(Y, (nmat, v, v), "Y"), precision))
+        return Y
+
     def set_graph_mode(self, enable=True):
         self._check(self.lib.pnoeom_set_graph_mode(self.h, int(bool(enable))))
 
@@ -280,7 +305,7 @@ class PnoEom:
             self._check(self.lib.pnoeom_last_ladder_timing(self.h, p, C.byref(lad), C.byref(n), C.byref(fl)))
             out[name] = dict(ladder_ms=lad.value, ladder_launches=n.value, ladder_flops=fl.value)
         by = C.c_double()
-        for r, name in ((0, "dots"), (1, "pno_transform")):
+        for r, name in ((0, "dots"), (1, "pno_transform"), (2, "ladder_w_build")):
             self._check(self.lib.pnoeom_last_region_timing(self.h, r, C.byref(lad), C.byref(n), C.byref(fl),
                                                            C.byref(by)))
             out[name] = dict(ms=lad.value, launches=n.value, flops=fl.value, bytes=by.value)

@@ -31,7 +31,7 @@ import math
 
 import numpy as np
 
-__all__ = ["System", "make_system", "default_sigma_b", "CONFIGS", "config_system", "random_r"]
+__all__ = ["System", "make_system", "default_sigma_b", "CONFIGS", "config_system", "random_r", "random_blocks"]
 
 
 @dataclasses.dataclass
@@ -66,14 +66,16 @@ def make_system(o: int, v: int, naux: int, seed: int, *, sigma_b: float | None =
     eps_v = np.sort(rng.uniform(0.1, 3.0, v))
     eps = np.concatenate([eps_o, eps_v])
     nmo = o + v
-    iu, ju = np.triu_indices(nmo)
-    B = np.empty((naux, nmo, nmo), dtype=np.float64)
+    upper = np.triu(np.ones((nmo, nmo), dtype=bool))   # boolean order = row-major upper triangle
+    ntri = nmo * (nmo + 1) // 2
+    B = np.zeros((naux, nmo, nmo), dtype=np.float64)
     for q0 in range(0, naux, chunk):
         q1 = min(naux, q0 + chunk)
-        vals = rng.standard_normal((q1 - q0, iu.size)) * sigma_b
-        blk = B[q0:q1]
-        blk[:, iu, ju] = vals
-        blk[:, ju, iu] = vals
+        vals = rng.standard_normal((q1 - q0, ntri)) * sigma_b
+        for k in range(q1 - q0):
+            m = B[q0 + k]
+            m[upper] = vals[k]
+            m += np.triu(m, 1).T      # mirror: the lower triangle still holds zeros
     if kappa != 0.0:
         g = np.ones(nmo)
         g[o:] = np.exp(-kappa * (eps_v - eps_v[0]))
@@ -129,3 +131,10 @@ def random_r(o: int, v: int, seed: int, nvec: int = 1):
     x = rng.standard_normal((nvec, o, o, v, v))
     r2 = 0.5 * (x + x.transpose(0, 2, 1, 4, 3))
     return r1, r2
+
+
+def random_blocks(v: int, nmat: int, seed: int):
+    """nmat random v x v doubles blocks (one pair of one trial vector each), N(0, 1)
+    entries with no symmetry imposed.  Returns an array of shape (nmat, v, v), float64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal((nmat, v, v))

@@ -1,0 +1,227 @@
+"""GPU parity of the streamed particle-particle ladder against the oracle, through
+the C ABI: W_ab^cd never stored, its packed rows rebuilt from the dressed factors
+one slab of a-values at a time inside each call.
+
+Tolerances (elementwise, Y = ladder, L = sum_Q sum_cd |B~_ac| (|X_cd| + |X_dc|) |B~_bd|,
+which bounds the sum of absolute values of every product behind Y_ab through the
+packed W+/- and S/A):
+  FP64  small sizes: |gpu - oracle| <= 1e-12 max|oracle| (summation order only, as
+        for sigma); at v = 900 the first-order bound (naux + v+ + 6) 2^-53 L
+        (v+ = v(v+1)/2: the two accumulation lengths);
+  FP32  (naux + v+ + 6) 2^-24 L: factors, pack and packed operands each rounded
+        once (unit 2^-24), FP32 accumulation over naux and over v+ terms;
+  BF16  (4.1 u + (naux + v+ + 4) 2^-24) L, u = 2^-8: factors (twice, in the products),
+        W+/- and S/A rounded to bfloat16 once each, products exact, FP32 accumulation.
+"""
+import numpy as np
+import pytest
+
+from synthgen import make_system, random_r, random_blocks, config_system, CONFIGS
+from oracle.ladder import ladder_apply, ladder_entries, dressed_virtual_factors, ladder_from_factors
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+UBF = 2.0 ** -8
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _bound_scale(s, X):
+    F = np.abs(dressed_virtual_factors(s.B, s.o, s.t1))
+    Z = np.abs(X) + np.abs(X).transpose(0, 2, 1)
+    return ladder_from_factors(F, Z)
+
+
+def _tol(prec, naux, v):
+    vp = v * (v + 1) // 2
+    if prec == 1:
+        return (naux + vp + 6) * U32
+    return 4.1 * UBF + (naux + vp + 4) * U32
+
+
+# o, v, naux, sigma_t1, max_slab (0 = from the memory budget), seed
+CASES = [(3, 20, 40, 0.05, 7, 31), (4, 37, 53, 1e-2, 5, 32), (5, 45, 90, 1e-3, 0, 33), (2, 64, 30, 0.0, 1, 34)]
+
+
+@pytest.mark.parametrize("o,v,naux,t1s,slab,seed", CASES)
+def test_streamed_ladder_fp64_matches_oracle(o, v, naux, t1s, slab, seed):
+    print(f"[ladder streamed fp64] o={o} v={v} naux={naux} slab={slab} seed={seed}", flush=True)
+    torch = _torch()
+    from paper_1802_06738_amd import PnoEom, LADDER_STREAMED
+    s = make_system(o, v, naux, seed, t1_sigma=t1s)
+    ctx = PnoEom(o, v, naux)
+    ctx.set_ladder_mode(LADDER_STREAMED, slab)
+    ctx.build_ladder(torch.from_numpy(s.B).cuda(), torch.from_numpy(s.t1).cuda())
+    X = random_blocks(v, 5, seed + 1)
+    Y = ctx.ladder_apply(torch.from_numpy(X).cuda()).cpu().numpy()
+    ref = ladder_apply(s.B, o, s.t1, X)
+    assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
+    t = ctx.last_timing()
+    assert t["fp64"]["ladder_launches"] >= 2 and t["ladder_w_build"]["launches"] >= 2
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("o,v,naux,t1s,slab,seed", CASES[:2])
+def test_streamed_ladder_low_precision_within_bound(o, v, naux, t1s, slab, seed, prec):
+    print(f"[ladder streamed prec {prec}] o={o} v={v} naux={naux} slab={slab} seed={seed}", flush=True)
+    torch = _torch()
+    from paper_1802_06738_amd import PnoEom, LADDER_STREAMED
+    s = make_system(o, v, naux, seed, t1_sigma=t1s)
+    ctx = PnoEom(o, v, naux)
+    ctx.set_ladder_mode(LADDER_STREAMED, slab)
+    ctx.build_ladder(torch.from_numpy(s.B).cuda(), torch.from_numpy(s.t1).cuda(), precision=prec)
+    X = random_blocks(v, 3, seed + 2)
+    Y = ctx.ladder_apply(torch.from_numpy(X).cuda(), precision=prec).cpu().numpy()
+    ref = ladder_apply(s.B, o, s.t1, X)
+    bound = _tol(prec, naux, v) * _bound_scale(s, X)
+    err = np.abs(Y - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+    # the low-precision path is really taken (its error is far above FP64 rounding)
+    assert np.max(err) > 1e-9 * np.max(np.abs(ref))
+    # FP64 still works on a low-precision build
+    Y64 = ctx.ladder_apply(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert np.max(np.abs(Y64 - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_ladder_apply_cached_after_build_df():
+    print("[ladder cached]", flush=True)
+    torch = _torch()
+    from paper_1802_06738_amd import PnoEom, LADDER_CACHED
+    o, v, naux = 4, 30, 50
+    s = make_system(o, v, naux, 35, t1_sigma=1e-2)
+    ctx = PnoEom(o, v, naux)
+    ctx.set_ladder_mode(LADDER_CACHED)
+    ctx.build_df(torch.from_numpy(s.B).cuda(), torch.from_numpy(s.eps).cuda(), torch.from_numpy(s.t1).cuda())
+    X = random_blocks(v, 4, 36)
+    Y = ctx.ladder_apply(torch.from_numpy(X).cuda()).cpu().numpy()
+    ref = ladder_apply(s.B, o, s.t1, X)
+    assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert ctx.last_timing()["ladder_w_build"]["launches"] == 0
+
+
+def test_ladder_apply_edge_cases():
+    print("[ladder edge cases]", flush=True)
+    torch = _torch()
+    from paper_1802_06738_amd import PnoEom, PnoEomError, LADDER_STREAMED
+    o, v, naux = 2, 9, 12
+    s = make_system(o, v, naux, 37, t1_sigma=0.1)
+    ctx = PnoEom(o, v, naux)
+    X = torch.from_numpy(random_blocks(v, 2, 38)).cuda()
+    with pytest.raises(PnoEomError):           # before build_ladder / build_df
+        ctx.ladder_apply(X)
+    ctx.set_ladder_mode(LADDER_STREAMED, 2)
+    ctx.build_ladder(torch.from_numpy(s.B).cuda(), torch.from_numpy(s.t1).cuda())
+    with pytest.raises(PnoEomError):           # FP32 not built
+        ctx.ladder_apply(X, precision=1)
+    Y0 = ctx.ladder_apply(X[:0])               # empty batch
+    assert Y0.shape == (0, v, v)
+    with pytest.raises(PnoEomError):           # sigma needs build_df
+        ctx.sigma(torch.zeros((1, o, v), dtype=torch.float64, device="cuda"),
+                  torch.zeros((1, o, o, v, v), dtype=torch.float64, device="cuda"))
+    Y = ctx.ladder_apply(X).cpu().numpy()
+    ref = ladder_apply(s.B, o, s.t1, X.cpu().numpy())
+    assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("o,v,naux,t1s,seed", [(4, 20, 60, 0.0, 1), (5, 37, 53, 1e-2, 2), (7, 45, 90, 1e-3, 3)])
+def test_sigma_with_streamed_ladder_matches_oracle(o, v, naux, t1s, seed):
+    print(f"[sigma streamed] o={o} v={v} naux={naux} seed={seed}", flush=True)
+    torch = _torch()
+    from paper_1802_06738_amd import PnoEom, LADDER_STREAMED
+    from oracle.sigma import SigmaOracle
+    s = make_system(o, v, naux, seed, t1_sigma=t1s)
+    ctx = PnoEom(o, v, naux)
+    ctx.set_ladder_mode(LADDER_STREAMED, 3)
+    ctx.build_df(torch.from_numpy(s.B).cuda(), torch.from_numpy(s.eps).cuda(), torch.from_numpy(s.t1).cuda(),
+                 precision=2)
+    r1, r2 = random_r(o, v, seed + 50, nvec=2)
+    so = SigmaOracle(s.eps, s.B, o, s.t1)
+    g1, g2 = ctx.sigma(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda())
+    g1, g2 = g1.cpu().numpy(), g2.cpu().numpy()
+    for k in range(2):
+        a1, a2 = so.sigma(r1[k], r2[k])
+        assert np.max(np.abs(g1[k] - a1)) <= 1e-12 * np.max(np.abs(a1))
+        assert np.max(np.abs(g2[k] - a2)) <= 1e-12 * np.max(np.abs(a2))
+    # BF16: ladder within the streamed bound, the other contractions in FP32 (2e-5 relative)
+    b1, b2 = ctx.sigma(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda(), precision=2)
+    b2 = b2.cpu().numpy()
+    for k in range(2):
+        _, a2 = so.sigma(r1[k], r2[k])
+        X = r2[k].reshape(o * o, v, v)
+        bound = (_tol(2, naux, v) * _bound_scale(s, X)).reshape(o, o, v, v) + 2e-5 * np.max(np.abs(a2))
+        assert np.all(np.abs(b2[k] - a2) <= bound)
+
+
+def test_davidson_c1_streamed_ladder_matches_dense_eig():
+    print("[davidson c1 streamed]", flush=True)
+    import json
+    import os
+    torch = _torch()
+    from paper_1802_06738_amd import PnoEom, LADDER_STREAMED
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1.json")))
+    cfg = CONFIGS[1]
+    s = config_system(1)
+    ctx = PnoEom(s.o, s.v, s.naux)
+    ctx.set_ladder_mode(LADDER_STREAMED, 6)
+    ctx.build_df(torch.from_numpy(s.B).cuda(), torch.from_numpy(s.eps).cuda(), torch.from_numpy(s.t1).cuda())
+    r = ctx.davidson(cfg["nroots"], tol_e=1e-10, tol_r=1e-7)
+    ref = np.array(gold["dense_eig"])[: cfg["nroots"]]
+    assert np.max(np.abs(r["omega"] - ref)) <= 1e-8
+
+
+# ---------------------------------------------------------------- one GPU's share at v = 900
+@pytest.fixture(scope="module")
+def config5():
+    print("[config 5] generating o=60, v=900, naux=2700", flush=True)
+    s = config_system(5)
+    print("[config 5] generated", flush=True)
+    return s
+
+
+def _samples(v, nmat, seed):
+    rng = np.random.default_rng(seed)
+    rows = [0, 1, 2, 3, v // 2, v - 3, v - 2, v - 1] + [int(x) for x in rng.integers(0, v, 4)]
+    out = []
+    for m in (0, nmat - 1):
+        for a in rows:
+            for b in sorted({0, a, min(a + 1, v - 1), v - 1, int(rng.integers(0, v))}):
+                out.append((m, a, b))
+    return out
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [0, 2])
+def test_config5_share_streamed_ladder_sampled(config5, prec):
+    """The ladder at o=60, v=900, naux=2700 (W+/- would take 1.3 TB in FP64): streamed,
+    checked on sampled entries computed one row at a time by the oracle."""
+    print(f"[config 5 ladder] precision {prec}", flush=True)
+    torch = _torch()
+    from paper_1802_06738_amd import PnoEom
+    s = config5
+    o, v, naux = s.o, s.v, s.naux
+    ctx = PnoEom(o, v, naux)
+    Bd = torch.from_numpy(s.B).cuda()
+    ctx.build_ladder(Bd, torch.from_numpy(s.t1).cuda(), precision=prec)
+    del Bd
+    torch.cuda.empty_cache()
+    nmat = 4
+    X = random_blocks(v, nmat, 51)
+    Y = ctx.ladder_apply(torch.from_numpy(X).cuda(), precision=prec).cpu().numpy()
+    print(f"[config 5 ladder] gpu done, {ctx.last_timing()['total_ms']:.0f} ms", flush=True)
+    smp = _samples(v, nmat, 52)
+    ref = ladder_entries(s.B, o, s.t1, X, smp)
+    scale = ladder_entries(s.B, o, s.t1, X, smp, absolute=True)
+    got = np.array([Y[m, a, b] for m, a, b in smp])
+    vp = v * (v + 1) // 2
+    tol = (naux + vp + 6) * 2.0 ** -53 if prec == 0 else _tol(prec, naux, v)
+    err = np.abs(got - ref)
+    print(f"[config 5 ladder] max err {err.max():.3e}, max rel {float(np.max(err) / np.max(np.abs(ref))):.3e}",
+          flush=True)
+    assert np.all(err <= tol * scale)
+    if prec == 0:
+        assert np.max(err) <= 1e-10 * np.max(np.abs(ref))
