@@ -31,19 +31,23 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}    # MI355X dense matrix TFLOP/s
 HBM_PEAK = 8000.0                       # GB/s
 
-# HBM bytes per launch of the FP64 ladder GEMM on the o=20, v=150 canonical workload,
-# from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; profiles/ladder_fp64_config2_traffic.md),
-# each scaled by what the counter reads for a 1 GiB + 1 GiB device copy.  Valid only for the
-# GEMM source it was taken on: reported as null once that source changes.
-LADDER_TRAFFIC = {"config": 2, "gemm_sha256": "52af29a3451e45dc47546ae148688311cc2cef3de719d92891463c36e7c6c22b",
-                  "fetch_kib": 2727883.9, "fetch_scale": 1048576.0 / 524303.8,
-                  "write_kib": 134911.3, "write_scale": 1048576.0 / 1048576.1}
+# HBM bytes per launch of the dominant FP64 GEMMs on the o=20, v=150 canonical workload, from
+# two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; profiles/gemm_fp64_config2_traffic.md), scaled by
+# what the counter reads for a 1 GiB + 1 GiB device copy.  Valid only for the GEMM source
+# they were taken on: reported as null once that source changes (or before a measurement).
+_GEMM_SHA = "126875b2b511e6707e498d076c6b7455dec2feb2fca769c10f4bc505ca6e815b"
+KERNEL_TRAFFIC = {
+    "ring": {"config": 2, "gemm_sha256": _GEMM_SHA, "fetch_kib": 6755368.1, "fetch_scale": 1048576.0 / 524300.9,
+             "write_kib": 441051.1, "write_scale": 1048576.0 / 1048576.2},
+    "ladder": {"config": 2, "gemm_sha256": _GEMM_SHA, "fetch_kib": 2992097.9, "fetch_scale": 1048576.0 / 524300.9,
+               "write_kib": 130350.0, "write_scale": 1048576.0 / 1048576.2},
+}
 
 
-def ladder_traffic(config, pno_only):
+def kernel_traffic(name, config, pno_only):
     import hashlib
-    t = LADDER_TRAFFIC
-    if config != t["config"] or pno_only:
+    t = KERNEL_TRAFFIC.get(name)
+    if t is None or config != t["config"] or pno_only:
         return None
     src = os.path.join(ROOT, "paper_1802_06738_amd", "csrc", "gemm.hip")
     with open(src, "rb") as fh:
@@ -296,13 +300,33 @@ def main():
     head_pno = (nroots, tcut) if pno_only else None
     res64, dt64 = measure(FP64, head_pno)
     nsig = sum(r["nsigma"] for r in res64)
-    lad_ms = sum(r["timing"]["ladder_ms"] for r in res64)
-    lad_fl = sum(r["timing"]["ladder_flops"] for r in res64)
-    lad_n = sum(r["timing"]["ladder_launches"] for r in res64)
     omega64 = res64[-1]["omega"]
-    flops_launch = lad_fl / max(lad_n, 1)
-    avg_ms = lad_ms / max(lad_n, 1)
-    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+
+    def rf(kind, ms, fl, n, kernel, unit_text):
+        fpl = fl / max(n, 1)
+        avg = ms / max(n, 1)
+        ach = fpl / (avg * 1e-3) / 1e12 if avg > 0 else 0.0
+        return {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                "frac": ach / PEAK["fp64"], "traffic": kernel_traffic(kind, args.config, pno_only),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                "peak_measured": peaks["fp64_tflops"], "frac_of_measured": ach / peaks["fp64_tflops"],
+                "kernel": kernel, "algorithmic_flops_per_launch": fpl, "avg_launch_ms": avg, "launches": n,
+                "launch_unit": unit_text, "ms_per_step": ms / len(res64)}
+
+    def tsum(key, field):
+        return sum(r["timing"][key][field] for r in res64)
+
+    lad = rf("ladder", sum(r["timing"]["ladder_ms"] for r in res64), sum(r["timing"]["ladder_flops"] for r in res64),
+             sum(r["timing"]["ladder_launches"] for r in res64),
+             "particle ladder sum_cd W_ab^cd R_ij^cd, +/- packed, all trial vectors of a block in one contraction "
+             "(gemm_kernel tag 1, FP64 MFMA)",
+             "one MFMA GEMM launch: the + or - half of the packed ladder for all trial vectors of a sigma block")
+    ring = rf("ring", tsum("ring", "ms"), tsum("ring", "flops"), tsum("ring", "launches"),
+              "ring (particle-hole) products of sigma2: R^s [Dr | Xr], E_X [T_ia | T^s_ia], R DX2 over the "
+              "stacked vectors of a block (gemm_kernel tag 3, FP64 MFMA)",
+              "one MFMA GEMM launch (M = vectors x ov rows, N = 2 ov or ov, K = ov)")
+    # the roofline line reports the kernel family that takes the most time in the step
+    primary, other = (ring, lad) if ring["ms_per_step"] > lad["ms_per_step"] else (lad, ring)
     out = {
         "metric": "sigma evals/s & Davidson time-to-convergence (FP64; FP32 and BF16 mixed variants; PNO vs canonical)",
         "value": nsig / dt64,
@@ -325,16 +349,8 @@ def main():
         "sigma_per_step": nsig / args.steps,
         "iters_per_step": res64[-1]["iters"],
         "omega": [float(x) for x in omega64],
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["fp64"], "traffic": ladder_traffic(args.config, pno_only),
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                     "peak_measured": peaks["fp64_tflops"], "frac_of_measured": achieved / peaks["fp64_tflops"],
-                     "kernel": "particle ladder sum_cd W_ab^cd R_ij^cd, +/- packed, all trial vectors of a "
-                               "block in one contraction (gemm_kernel tag 1, FP64 MFMA)",
-                     "algorithmic_flops_per_launch": flops_launch,
-                     "avg_launch_ms": avg_ms, "launches": lad_n,
-                     "launch_unit": "one MFMA GEMM launch: the + or - half of the packed ladder for "
-                                    "all trial vectors of a sigma block"},
+        "roofline": primary,
+        "roofline_next": other,
     }
     out["measured_peaks"] = dict(peaks, note="register-only MFMA loops on every CU; HBM = 1 GiB device copy, "
                                              "read + write bytes")

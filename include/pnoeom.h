@@ -295,7 +295,11 @@ int pnoeom_last_ladder_timing(const pnoeom_ctx* ctx, int precision, double* ladd
  *             rows); flops = 2 (na v)(nb v) naux per slab of na rows a and nb columns
  *             b >= a0, bytes = the slab block written and read (3 passes) plus the
  *             packed rows written.  The contraction with the slab rows counts as ladder
- *             time in pnoeom_last_timing / pnoeom_last_ladder_timing.
+ *             time in pnoeom_last_timing / pnoeom_last_ladder_timing;
+ *   region 3: the ring (particle-hole) products of sigma2, three GEMMs per sigma
+ *             block of nb vectors (R^s [Dr | Xr], E_X [T_ia | T^s_ia], R DX2 with
+ *             M = nb o v rows); flops = 10 nb (ov)^3, bytes = the operands and the
+ *             output moved once.
  * ms are HIP-event times on the context stream.  Errors: EINVAL (null ctx, bad region). */
 int pnoeom_last_region_timing(const pnoeom_ctx* ctx, int region, double* ms, int* launches, double* flops,
                               double* bytes);

@@ -79,7 +79,7 @@ struct GemmDesc {
   int64_t ldc = 0, sC = 0;
   int64_t batch = 1;
   bool reduce = false;
-  int tag = 0;  // 1: the particle-particle ladder, 2: its W slab build (own kernel symbols, for profiling)
+  int tag = 0;  // 1: particle-particle ladder, 2: its W slab build, 3: ring products (own kernel symbols, for profiling)
 };
 
 void gemm(const GemmDesc<double>& d, hipStream_t s);

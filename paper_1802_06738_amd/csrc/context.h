@@ -10,7 +10,7 @@ struct SigmaWork {
   DBuf<double> Bp, hp, Jp, Kp, fp, dp, fp_ov, fp_vv, fp_oo;
   DBuf<double> BvopT, BoopT, BvvpT;
   DBuf<double> R2c, Ria, Rsia, UiaR, UR, URp, Ubr;
-  DBuf<double> Ziajb, Z3, EXT, Zp, Cba, Xh, O4p, OOVVp, M1;
+  DBuf<double> ZZ, EXT, Zp, Cba, Xh, O4p, OOVVp, M1;  // ZZ[(q,i,a)][Ziajb row | Z3 row]
   DBuf<double> Ftv, Fto;
   DBuf<double> LadAll, Sp, Am, SigP, SigM;  // batched packed ladder
   DBuf<float> Spf, Amf, SigPf, SigMf;
@@ -19,7 +19,7 @@ struct SigmaWork {
   DBuf<float> fa, fc;
   void release() {
     for (DBuf<double>* b : {&Bp, &hp, &Jp, &Kp, &fp, &dp, &fp_ov, &fp_vv, &fp_oo, &BvopT, &BoopT, &BvvpT, &R2c, &Ria,
-                            &Rsia, &UiaR, &UR, &URp, &Ubr, &Ziajb, &Z3, &EXT, &Zp, &Cba, &Xh, &O4p,
+                            &Rsia, &UiaR, &UR, &URp, &Ubr, &ZZ, &EXT, &Zp, &Cba, &Xh, &O4p,
                             &OOVVp, &M1, &Ftv, &Fto, &LadAll, &Sp, &Am, &SigP, &SigM})
       b->release();
     for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fc}) b->release();
@@ -73,12 +73,15 @@ struct Context {
   DBuf<double> G, GX, g2, Gq, OVVO, OOVVx, Wh, OOOVp;
   DBuf<double> Fqvv, Fqoo, Fvv, Foo, fd_ov;
   DBuf<double> Dr, Xr, DX2, Wvo2, YU;
+  // ring operands side by side, rows of 2 ov: [Dr | Xr] and [Tia | Tsia] (the products
+  // with R^s and with E_X share their left operand)
+  DBuf<double> DXr, TTs;
   // packed ladder: W+[(a<=b),(c<=d)] = W_abcd + W_abdc, W-[(a<b),(c<d)] = W_abcd - W_abdc
   DBuf<double> Wp, Wm;          // FP64 (always: the FP64 sigma and the refinement of mixed runs)
   DBuf<float> Wpf, Wmf;         // FP32 (precision FP32)
   DBuf<uint16_t> Wpb, Wmb;      // bfloat16 bits (precision BF16), rows padded to ldpb / ldmb columns
   int64_t ldpb = 0, ldmb = 0;
-  DBuf<float> Tf, Tiaf, Tsiaf, Drf, Xrf, DX2f;
+  DBuf<float> DX2f, DXrf, TTsf;
   DBuf<double> scratch;         // build-time temporaries
 
   // ladder storage (pnoeom_set_ladder_mode): 0 auto, 1 cached W+/-, 2 streamed from B~_vv
@@ -105,8 +108,8 @@ struct Context {
   int last_ladder_launches_p[3] = {0, 0, 0};
   std::vector<int> ev_prec;         // per start/stop event pair: ladder precision (0..2) or 3 + region
   // other timed regions: 0 = Davidson inner products, 1 = PNO back-transform / projection,
-  // 2 = W slab builds of the streamed ladder (factor GEMM + pack)
-  static constexpr int kRegions = 3;
+  // 2 = W slab builds of the streamed ladder (factor GEMM + pack), 3 = ring (ov)^3 products
+  static constexpr int kRegions = 4;
   double reg_flops[kRegions] = {}, reg_bytes[kRegions] = {};
   int reg_launches[kRegions] = {};
   double last_reg_ms[kRegions] = {}, last_reg_flops[kRegions] = {}, last_reg_bytes[kRegions] = {};

@@ -202,6 +202,15 @@ struct Dots {
 // host out[i][j] = sum_n A[i][n] B[j][n]   (A: na rows, B: nb rows, row stride N)
 void dots(hipStream_t s, Dots& w, const double* A, int na, const double* B, int nb, int64_t N, double* host) {
   if (na == 0 || nb == 0) return;
+  if (na <= 16 && nb > 16 && nb <= 64) {
+    // one launch with the long side as A (64 rows) instead of one per 16 rows of B,
+    // each re-reading A: out = (B A^T)^T
+    std::vector<double> t((size_t)na * nb);
+    dots(s, w, B, nb, A, na, N, t.data());
+    for (int i = 0; i < na; ++i)
+      for (int j = 0; j < nb; ++j) host[(int64_t)i * nb + j] = t[(size_t)j * na + i];
+    return;
+  }
   const int64_t nout = (int64_t)na * nb;
   int64_t groups = std::min<int64_t>(kDotGroups, std::max<int64_t>(1, (N / 16 + kDotWaves - 1) / kDotWaves));
   if ((int64_t)w.part.n < groups * nout) w.part.alloc(groups * nout);

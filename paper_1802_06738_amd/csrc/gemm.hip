@@ -334,6 +334,8 @@ void launch_tile(const GemmDesc<T>& d, hipStream_t s, int split_mode = 0) {
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, true, 1>), grid, dim3(NT), 0, s, g);
   else if (d.tag == 2 && !d.ta && d.tb)
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, true, 2>), grid, dim3(NT), 0, s, g);
+  else if (d.tag == 3 && !d.ta && !d.tb)
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, false, 3>), grid, dim3(NT), 0, s, g);
   else if (!d.ta && !d.tb)
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, false, 0>), grid, dim3(NT), 0, s, g);
   else if (d.ta && !d.tb)

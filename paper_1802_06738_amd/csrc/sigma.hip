@@ -255,7 +255,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   c.sw.release();
   c.pno.reset();
   if (precision == PNOEOM_FP64)
-    for (DBuf<float>* b : {&c.Tf, &c.Tiaf, &c.Tsiaf, &c.Drf, &c.Xrf, &c.DX2f}) b->release();
+    for (DBuf<float>* b : {&c.DX2f, &c.DXrf, &c.TTsf}) b->release();
 
   c.B.alloc((int64_t)naux * n2);
   c.eps.alloc(nmo);
@@ -401,6 +401,16 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   gm(s, false, true, ov, ov, ov, -1.0, c.GX, ov, c.Tsia, ov, 1.0, c.Xr, ov);
   PNO_HIP(hipMemcpyAsync(c.DX2, c.Xr, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
   axpby(s, oovv, 2.0, c.Dr, -1.0, c.DX2);
+  // side-by-side copies for the ring products: [Dr | Xr] and [Tia | Tsia], rows of 2 ov
+  c.DXr.alloc(2 * oovv);
+  c.TTs.alloc(2 * oovv);
+  {
+    const size_t row = (size_t)ov * sizeof(double), pitch = 2 * row;
+    PNO_HIP(hipMemcpy2DAsync(c.DXr, pitch, c.Dr, row, row, ov, hipMemcpyDeviceToDevice, s));
+    PNO_HIP(hipMemcpy2DAsync(c.DXr + ov, pitch, c.Xr, row, row, ov, hipMemcpyDeviceToDevice, s));
+    PNO_HIP(hipMemcpy2DAsync(c.TTs, pitch, c.Tia, row, row, ov, hipMemcpyDeviceToDevice, s));
+    PNO_HIP(hipMemcpy2DAsync(c.TTs + ov, pitch, c.Tsia, row, row, ov, hipMemcpyDeviceToDevice, s));
+  }
   // YU[Q][(k,c)] = sum_(j,b) B_jb^Q (2 T - T^s)[(j,b),(k,c)]: the Coulomb (DF) part of the
   // R-side ring intermediate contracted with T ahead of time
   {
@@ -496,20 +506,16 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     PNO_HIP(hipStreamSynchronize(s));
   }
   if (precision == PNOEOM_FP32 || precision == PNOEOM_BF16) {  // FP32 operands of the other contractions
-    c.Tf.alloc(oovv);
-    c.Tiaf.alloc(oovv);
-    c.Tsiaf.alloc(oovv);
-    c.Drf.alloc(oovv);
-    c.Xrf.alloc(oovv);
     c.DX2f.alloc(oovv);
-    to_float(s, oovv, c.T, c.Tf);
-    to_float(s, oovv, c.Tia, c.Tiaf);
-    to_float(s, oovv, c.Tsia, c.Tsiaf);
-    to_float(s, oovv, c.Dr, c.Drf);
-    to_float(s, oovv, c.Xr, c.Xrf);
+    c.DXrf.alloc(2 * oovv);
+    c.TTsf.alloc(2 * oovv);
     to_float(s, oovv, c.DX2, c.DX2f);
+    to_float(s, 2 * oovv, c.DXr, c.DXrf);
+    to_float(s, 2 * oovv, c.TTs, c.TTsf);
   }
   PNO_HIP(hipStreamSynchronize(s));
+  // kept only side by side (DXr, TTs) from here on
+  c.Dr.release(); c.Xr.release(); c.Tia.release(); c.Tsia.release();
   c.have_df = true;
   c.have_lad = true;
 }
@@ -525,7 +531,7 @@ int64_t rest_bytes_per_vector(const Context& c, bool f32) {
   const int64_t ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, oovv = c.oovv();
   int64_t nd = 13 * oovv + (ov + oo + vv) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv + oo + vv + oo;
   int64_t bytes = nd * (int64_t)sizeof(double);
-  if (f32) bytes += 2 * oovv * (int64_t)sizeof(float);
+  if (f32) bytes += 3 * oovv * (int64_t)sizeof(float);  // fa (one oovv) and fc (two)
   return bytes;
 }
 
@@ -552,8 +558,8 @@ int64_t sigma_held_bytes(const Context& c) {
   const SigmaWork& w = c.sw;
   int64_t b = 0;
   for (const DBuf<double>* x : {&w.Bp, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT,
-                                &w.BoopT, &w.BvvpT, &w.R2c, &w.Ria, &w.Rsia, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.Ziajb,
-                                &w.Z3, &w.EXT, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.Ftv, &w.Fto,
+                                &w.BoopT, &w.BvvpT, &w.R2c, &w.Ria, &w.Rsia, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.ZZ,
+                                &w.EXT, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.Ftv, &w.Fto,
                                 &w.LadAll, &w.Sp, &w.Am, &w.SigP, &w.SigM, &c.pno.r1, &c.pno.r2, &c.pno.s1,
                                 &c.pno.s2})
     b += (int64_t)x->n * 8;
@@ -591,12 +597,12 @@ void alloc_sigma_work(Context& c, int precision, int nb) {
   grow(w.R2c, B * oovv);
   grow(w.Ria, B * oovv); grow(w.Rsia, B * oovv); grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
   grow(w.URp, B * oovv); grow(w.Ubr, B * oovv);
-  grow(w.Ziajb, B * oovv); grow(w.Z3, B * oovv); grow(w.EXT, B * oovv);
+  grow(w.ZZ, 2 * B * oovv); grow(w.EXT, B * oovv);
   grow(w.Zp, B * oovv); grow(w.Cba, B * oovv); grow(w.OOVVp, B * oovv);
   grow(w.Xh, B * oo * oo); grow(w.O4p, B * oo * oo); grow(w.M1, B * ov * c.naux);
   grow(w.Ftv, B * vv); grow(w.Fto, B * oo);
   if (precision != PNOEOM_FP64) {
-    grow(w.fa, B * oovv); grow(w.fc, B * oovv);
+    grow(w.fa, B * oovv); grow(w.fc, 2 * B * oovv);
   }
 }
 
@@ -616,11 +622,12 @@ void gmbf(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, doub
 namespace {
 // s2[q] = Sd[q] + Z(i,j,a,b) + Z(j,i,b,a) for nb vectors, with
 // Z(i,j,a,b) = Zp[i][j][a][b] + Ziajb[i][a][j][b] + Z3[j][a][i][b] - Cba[i][j][b][a]
+// where Ziajb and Z3 of vector q are the two halves of the rows of ZZ[q] ([(i,a)][2 ov])
 __global__ void assemble_s2_block_kernel(int o, int v, int nb, const double* __restrict__ Sd,
-                                         const double* __restrict__ Zp, const double* __restrict__ Zia,
-                                         const double* __restrict__ Z3, const double* __restrict__ Cba,
-                                         double* __restrict__ s2, int64_t stride2) {
-  const int64_t V = v, O = o, n = O * O * V * V;
+                                         const double* __restrict__ Zp, const double* __restrict__ ZZ,
+                                         const double* __restrict__ Cba, double* __restrict__ s2,
+                                         int64_t stride2) {
+  const int64_t V = v, O = o, n = O * O * V * V, ov2 = 2 * O * V;
   const int64_t total = n * nb;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t q = g / n, e = g - q * n;
@@ -630,12 +637,11 @@ __global__ void assemble_s2_block_kernel(int o, int v, int nb, const double* __r
     const int64_t j = r % O;
     const int64_t i = r / O;
     const double* zp = Zp + q * n;
-    const double* zi = Zia + q * n;
-    const double* z3 = Z3 + q * n;
+    const double* zz = ZZ + q * 2 * n;
     const double* cb = Cba + q * n;
     auto Z = [&](int64_t I, int64_t Jj, int64_t A, int64_t Bb) {
-      return zp[((I * O + Jj) * V + A) * V + Bb] + zi[((I * V + A) * O + Jj) * V + Bb] +
-             z3[((Jj * V + A) * O + I) * V + Bb] - cb[((I * O + Jj) * V + Bb) * V + A];
+      return zp[((I * O + Jj) * V + A) * V + Bb] + zz[(I * V + A) * ov2 + Jj * V + Bb] +
+             zz[(Jj * V + A) * ov2 + O * V + I * V + Bb] - cb[((I * O + Jj) * V + Bb) * V + A];
     };
     s2[q * stride2 + e] = Sd[g] + Z(i, j, a, b) + Z(j, i, b, a);
   }
@@ -737,9 +743,6 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   //   E_D^T (2T - T^s) = (1/2 M1 + B'_vo) YU   (DF rank naux)
   //   -E_X^T T, -E_X^T T^s                       (E_X = (ij|ab)' in ring order)
   // so that five (ov x ov x ov) products per vector remain.
-  gmb(s, false, true, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.BvoT, naux, 0, 0.0, w.Ziajb, ov, oovv, nb);
-  gmb(s, false, false, ov, ov, naux, 0.5, w.M1, naux, ovn, c.YU, ov, 0, 1.0, w.Ziajb, ov, oovv, nb);
-  gmb(s, false, false, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.YU, ov, 0, 1.0, w.Ziajb, ov, oovv, nb);
   gmb(s, false, true, oo, vv, naux, 1.0, w.BoopT, naux, oon, c.BvvT, naux, 0, 0.0, w.OOVVp, vv, oovv, nb);
   gmb(s, false, true, oo, vv, naux, 1.0, c.BooT, naux, 0, w.BvvpT, naux, vvn, 1.0, w.OOVVp, vv, oovv, nb);
   {
@@ -748,25 +751,44 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     const int pp[4] = {1, 2, 0, 3};
     permute_c(s, dims, pp, 1.0, w.OOVVp, 0.0, w.EXT, nb);
   }
+  // The per-vector operands are stacked ([nb][ov][ov] is nb*ov rows), so each product
+  // with a fixed right operand is one tall GEMM; R^s and E_X multiply [Dr | Xr] and
+  // [Tia | Tsia] at once, filling both halves of the rows of ZZ = [Ziajb | Z3].
+  const int64_t M = (int64_t)nb * ov, ov2 = 2 * ov;
+  hipEvent_t ring_ev = c.region_begin(3, s);
   if (f32) {
     float* fa = w.fa;
     float* fc = w.fc;
     const int64_t nt = nb * oovv;
-    to_float(s, nt, w.Ria, fa);
-    gmbf(s, false, false, ov, ov, ov, 1.0, fa, ov, oovv, c.DX2f, ov, 0, 1.0, w.Ziajb, nb, fc);
+    GemmDesc<float> d;
+    d.M = M; d.N = ov2; d.K = ov; d.alpha = -1.f; d.beta = 0.f; d.lda = ov; d.ldb = ov2; d.C = fc; d.ldc = ov2;
+    d.tag = 3;
     to_float(s, nt, w.Rsia, fa);
-    gmbf(s, false, false, ov, ov, ov, -1.0, fa, ov, oovv, c.Drf, ov, 0, 1.0, w.Ziajb, nb, fc);
-    gmbf(s, false, false, ov, ov, ov, -1.0, fa, ov, oovv, c.Xrf, ov, 0, 0.0, w.Z3, nb, fc);
+    d.A = fa; d.B = c.DXrf;
+    gemm(d, s);
     to_float(s, nt, w.EXT, fa);
-    gmbf(s, false, false, ov, ov, ov, -1.0, fa, ov, oovv, c.Tiaf, ov, 0, 1.0, w.Ziajb, nb, fc);
-    gmbf(s, false, false, ov, ov, ov, -1.0, fa, ov, oovv, c.Tsiaf, ov, 0, 1.0, w.Z3, nb, fc);
+    d.B = c.TTsf; d.beta = 1.f;
+    gemm(d, s);
+    to_float(s, nt, w.Ria, fa);
+    d.N = ov; d.alpha = 1.f; d.B = c.DX2f; d.ldb = ov;
+    gemm(d, s);
+    to_double(s, 2 * nt, fc, w.ZZ, 0.0);
   } else {
-    gmb(s, false, false, ov, ov, ov, 1.0, w.Ria, ov, oovv, c.DX2, ov, 0, 1.0, w.Ziajb, ov, oovv, nb);
-    gmb(s, false, false, ov, ov, ov, -1.0, w.Rsia, ov, oovv, c.Dr, ov, 0, 1.0, w.Ziajb, ov, oovv, nb);
-    gmb(s, false, false, ov, ov, ov, -1.0, w.Rsia, ov, oovv, c.Xr, ov, 0, 0.0, w.Z3, ov, oovv, nb);
-    gmb(s, false, false, ov, ov, ov, -1.0, w.EXT, ov, oovv, c.Tia, ov, 0, 1.0, w.Ziajb, ov, oovv, nb);
-    gmb(s, false, false, ov, ov, ov, -1.0, w.EXT, ov, oovv, c.Tsia, ov, 0, 1.0, w.Z3, ov, oovv, nb);
+    GemmDesc<double> d;
+    d.M = M; d.N = ov2; d.K = ov; d.alpha = -1.0; d.beta = 0.0; d.lda = ov; d.ldb = ov2; d.C = w.ZZ; d.ldc = ov2;
+    d.tag = 3;
+    d.A = w.Rsia; d.B = c.DXr;
+    gemm(d, s);
+    d.A = w.EXT; d.B = c.TTs; d.beta = 1.0;
+    gemm(d, s);
+    d.N = ov; d.alpha = 1.0; d.A = w.Ria; d.B = c.DX2; d.ldb = ov;
+    gemm(d, s);
   }
+  c.region_end(ring_ev, 3, s, 3, 10.0 * (double)M * ov * ov, 8.0 * (3.0 * M * ov + 5.0 * oovv + 6.0 * M * ov));
+  // the DF-factorised parts of the ring terms, into the Ziajb half
+  gmb(s, false, true, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.BvoT, naux, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
+  gmb(s, false, false, ov, ov, naux, 0.5, w.M1, naux, ovn, c.YU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
+  gmb(s, false, false, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.YU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
 
   // ---------------------------------------------------------------- Fock-type terms in [i][j][a][b]
   gm(s, false, true, (int64_t)nb * oo * v, v, v, 1.0, R2, v, c.Fvv, v, 0.0, w.Zp, v);
@@ -783,8 +805,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
 
   const int64_t tot = nb * oovv;
   hipLaunchKernelGGL(assemble_s2_block_kernel, dim3(grid1(tot)), dim3(256), 0, s, o, v, nb, (const double*)Sd,
-                     (const double*)w.Zp, (const double*)w.Ziajb, (const double*)w.Z3, (const double*)w.Cba, s2,
-                     stride2);
+                     (const double*)w.Zp, (const double*)w.ZZ, (const double*)w.Cba, s2, stride2);
   PNO_HIP(hipGetLastError());
 }
 }  // namespace
@@ -968,7 +989,7 @@ uint64_t sigma_signature(Context& c, hipStream_t s) {
   };
   SigmaWork& w = c.sw;
   for (DBuf<double>* b : {&w.Bp, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT, &w.BoopT,
-                          &w.BvvpT, &w.R2c, &w.Ria, &w.Rsia, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.Ziajb, &w.Z3,
+                          &w.BvvpT, &w.R2c, &w.Ria, &w.Rsia, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.ZZ,
                           &w.EXT, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.Ftv, &w.Fto, &w.LadAll, &w.Sp,
                           &w.Am, &w.SigP, &w.SigM, &c.pno.Tw, &c.pno.r1, &c.pno.r2, &c.pno.s1, &c.pno.s2, &c.gin,
                           &c.gout})

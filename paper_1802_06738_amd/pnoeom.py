@@ -305,7 +305,7 @@ class PnoEom:
             self._check(self.lib.pnoeom_last_ladder_timing(self.h, p, C.byref(lad), C.byref(n), C.byref(fl)))
             out[name] = dict(ladder_ms=lad.value, ladder_launches=n.value, ladder_flops=fl.value)
         by = C.c_double()
-        for r, name in ((0, "dots"), (1, "pno_transform"), (2, "ladder_w_build")):
+        for r, name in ((0, "dots"), (1, "pno_transform"), (2, "ladder_w_build"), (3, "ring")):
             self._check(self.lib.pnoeom_last_region_timing(self.h, r, C.byref(lad), C.byref(n), C.byref(fl),
                                                            C.byref(by)))
             out[name] = dict(ms=lad.value, launches=n.value, flops=fl.value, bytes=by.value)
