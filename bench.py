@@ -65,13 +65,16 @@ def run_steps(ctx, B, eps, t1, nroots, prec, steps, tol_e, tol_r, max_sub, pno=N
     for _ in range(steps):
         ctx.build_df(B, eps, t1, None, precision=prec)
         npno = None
+        split = None
         if pno is not None:
             npno, _ = ctx.build_sapno(pno[0], pno[1])
+            split = ctx.pno_ladder_stats()
         r = ctx.davidson(nroots, space=CANONICAL if pno is None else PNO, precision=prec, tol_e=tol_e,
                          tol_r=tol_r, max_sub=max_sub, refine_fp64=(prec != FP64), verbose=verbose,
                          nextra=nextra, mixed_tol_e=mixed_tol[0], mixed_tol_r=mixed_tol[1])
         r["timing"] = ctx.last_timing()
         r["npno"] = npno
+        r["ladder_split"] = split
         res.append(r)
     torch.cuda.synchronize()
     return res
@@ -250,6 +253,8 @@ def main():
     ap.add_argument("--tcut", type=float, default=None, help="PNO cut (default: the config's, else 1e-7)")
     ap.add_argument("--mixed", default="fp32,bf16", help="mixed precisions to run (comma list)")
     ap.add_argument("--graph", type=int, default=1, help="also time the FP64 steps in graph mode (0/1)")
+    ap.add_argument("--pno-ladder", type=int, default=-1,
+                    help="PNO-space ladder for pairs with n_p up to this (-1 automatic, 0 none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -276,6 +281,7 @@ def main():
     t1 = torch.from_numpy(s.t1).to(dev)
     torch.cuda.synchronize()
     ctx = PnoEom(o, v, naux)
+    ctx.set_pno_ladder(args.pno_ladder)
     peaks = ctx.probe_peaks()   # measured ceilings next to the published ones
     # long steps (v = 400: minutes) report each Davidson iteration on stderr
     verbose = v > 200
@@ -366,9 +372,10 @@ def main():
     if pno_only:
         npno = np.asarray(res64[-1]["npno"])
         out["pno"] = {"tcut": tcut, "npno_mean": float(npno.mean()), "npno_min": int(npno.min()),
-                      "npno_max": int(npno.max()),
+                      "npno_max": int(npno.max()), "ladder_split": res64[-1]["ladder_split"],
+                      "native_ladder": region_rate(res64, "pno_native_ladder"),
                       "note": "step = build_df + build_sapno + PNO-space Davidson (back-transform, canonical "
-                              "sigma, projection)"}
+                              "sigma, projection; the ladder of the pairs with n_p <= cut in the PNO space)"}
     mixed = [] if args.no_mixed else [m for m in args.mixed.split(",") if m]
     if mixed:
         for prec, name in ((FP32, "fp32"), (BF16, "bf16")):
@@ -418,6 +425,8 @@ def main():
             "max_abs_pno_truncation_eh": float(np.max(np.abs(omp - omega64))),
             "pno_transform": region_rate(resp, "pno_transform"),
             "dots": region_rate(resp, "dots"),
+            "ladder_split": resp[-1]["ladder_split"],
+            "native_ladder": region_rate(resp, "pno_native_ladder"),
             "note": "step = build_df + build_sapno + PNO-space Davidson (back-transform, canonical sigma, "
                     "projection); the difference from the canonical roots is the PNO truncation",
         }

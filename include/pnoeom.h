@@ -132,6 +132,24 @@ int pnoeom_pno_transform(pnoeom_ctx* ctx, int nvec, int direction, double* r1, d
 int pnoeom_apply_sigma(pnoeom_ctx* ctx, int nvec, const double* r1, const double* r2, double* s1,
                        double* s2, int space, int precision);
 
+/* Ladder of the PNO-space sigma, for the next pnoeom_build_sapno.  The projected ladder of
+ * a pair is U^T [sum_cd W_ab^cd (U Rbar U^T)_cd] U = sum_Q Bbar^Q Rbar Bbar^Q^T with the
+ * pair's factors Bbar^Q = U^T B~^Q U (W_ab^cd = sum_Q B~^Q_ac B~^Q_bd; Methods, the PNO
+ * simulation of the Davidson step): 4 n_p^3 naux flop per pair and vector instead of the
+ * pair's rows of the canonical ladder (about v^4).  Pairs with n_p <= max_native take that
+ * route (their per-pair factors, n_p^2 naux words each, are built by build_sapno); the others
+ * keep the canonical ladder.  max_native = -1 (default): automatic, the n_p where
+ * 128 n_p^3 naux = v^4, lowered until the factors fit in a fifth of the free memory;
+ * 0: every pair canonical.  Results equal up to rounding order.
+ * Errors: EINVAL (null ctx, max_native < -1). */
+int pnoeom_set_pno_ladder(pnoeom_ctx* ctx, int max_native);
+
+/* The split chosen by the last build_sapno: the n_p bound, the number of pairs with the
+ * PNO-space ladder and with the canonical one, and the PNO-space ladder's flops per vector.
+ * Any output may be NULL.  Errors: EINVAL (null ctx), ESTATE (before build_sapno). */
+int pnoeom_pno_ladder_stats(const pnoeom_ctx* ctx, int* cut, int* native_pairs, int* canonical_pairs,
+                            double* native_flops);
+
 /* Storage of the particle-particle ladder W_ab^cd = sum_Q B~^Q_ac B~^Q_bd (Methods: the
  * largest intermediate; B~ the T1-dressed factors), for the next pnoeom_build_df:
  *   mode PNOEOM_LADDER_AUTO (0): cached when the packed W+/- fit in 60% of the free
@@ -299,7 +317,9 @@ int pnoeom_last_ladder_timing(const pnoeom_ctx* ctx, int precision, double* ladd
  *   region 3: the ring (particle-hole) products of sigma2, three GEMMs per sigma
  *             block of nb vectors (R^s [Dr | Xr], E_X [T_ia | T^s_ia], R DX2 with
  *             M = nb o v rows); flops = 10 nb (ov)^3, bytes = the operands and the
- *             output moved once.
+ *             output moved once;
+ *   region 4: the PNO-space ladder of the native pairs (pnoeom_set_pno_ladder), two
+ *             grouped GEMMs per vector; flops = sum over those pairs of 4 n_p^3 naux.
  * ms are HIP-event times on the context stream.  Errors: EINVAL (null ctx, bad region). */
 int pnoeom_last_region_timing(const pnoeom_ctx* ctx, int region, double* ms, int* launches, double* flops,
                               double* bytes);

@@ -250,6 +250,24 @@ int pnoeom_ladder_apply(pnoeom_ctx* ctx, int nmat, const double* X, double* Y, i
   });
 }
 
+int pnoeom_set_pno_ladder(pnoeom_ctx* ctx, int max_native) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(max_native >= -1, PNOEOM_EINVAL, "set_pno_ladder: max_native < -1");
+    c.pno.nat_max = max_native;
+  });
+}
+
+int pnoeom_pno_ladder_stats(const pnoeom_ctx* ctx, int* cut, int* native_pairs, int* canonical_pairs,
+                            double* native_flops) {
+  if (!ctx) return PNOEOM_EINVAL;
+  if (!ctx->c.pno.built) return PNOEOM_ESTATE;
+  if (cut) *cut = ctx->c.pno.nat_cut;
+  if (native_pairs) *native_pairs = ctx->c.pno.nat_pairs;
+  if (canonical_pairs) *canonical_pairs = ctx->c.pno.canon_pairs;
+  if (native_flops) *native_flops = ctx->c.pno.nat_flops;
+  return PNOEOM_OK;
+}
+
 int pnoeom_set_graph_mode(pnoeom_ctx* ctx, int enable) {
   return guarded(ctx, [&](pnoeom::Context& c) {
     c.graph_mode = enable != 0;

@@ -46,12 +46,27 @@ struct PNOData {
   GroupTable t_c1, t_c3, t_c2d, t_c2o, t_e1, t_e3, t_e2d, t_e2o;  // compress / expand
   DBuf<double> Tw, r1, r2, s1, s2;
   double xf_flops = 0;          // flops of one compress (or expand) of one vector
+  // ladder of the pairs with n_p <= nat_cut evaluated in the PNO space with per-pair
+  // factors Bbar_p[a][Q][c] = (U_p^T B~^Q U_p)[a][c]; the other pairs keep the canonical
+  // ladder (rows listed by prow: slot in the packed ladder, -1 for a native pair)
+  int nat_max = -1;             // requested bound (-1 auto, 0 none)
+  int nat_cut = 0, nat_pairs = 0, canon_pairs = 0;
+  std::vector<int> prow;
+  DBuf<int> d_prow;
+  DBuf<double> Bbar, Y1, Ypart;  // Ypart: split-K partial blocks of the second product
+  GroupTable t_na, t_nb;
+  DBuf<int> d_nn, d_nch;         // per native pair: n_p, K chunks
+  DBuf<int64_t> d_poff, d_yoff;  // per native pair: first partial block, block in the compressed vector
+  double nat_flops = 0;         // flops of the native ladder of one vector
   void reset() {
     built = false;
     npno.clear(); nosv.clear(); off.clear(); uoff.clear(); toff.clear();
     len = 0; nmax = 0;
     U.release(); denom_base.release(); d_off.release(); d_n.release();
     Tw.release(); r1.release(); r2.release(); s1.release(); s2.release();
+    nat_cut = nat_pairs = canon_pairs = 0;
+    prow.clear(); d_prow.release(); Bbar.release(); Y1.release(); Ypart.release(); nat_flops = 0;
+    d_nn.release(); d_nch.release(); d_poff.release(); d_yoff.release();
   }
 };
 
@@ -86,6 +101,9 @@ struct Context {
 
   // ladder storage (pnoeom_set_ladder_mode): 0 auto, 1 cached W+/-, 2 streamed from B~_vv
   int lad_mode = 0, lad_max_slab = 0;
+  // restricted canonical ladder (PNO sigma with native pairs): slot per pair or -1, slots per vector
+  const int* lad_prow = nullptr;
+  int64_t lad_nsub = -1;
   bool lad_streamed = false;    // W+/- not stored: rebuilt slab by slab in every sigma
   bool have_lad = false;        // the ladder can be applied (build_df or build_ladder done)
   DBuf<float> BvvTf;            // FP32 copy of BvvT (streamed, precision FP32)
@@ -108,8 +126,9 @@ struct Context {
   int last_ladder_launches_p[3] = {0, 0, 0};
   std::vector<int> ev_prec;         // per start/stop event pair: ladder precision (0..2) or 3 + region
   // other timed regions: 0 = Davidson inner products, 1 = PNO back-transform / projection,
-  // 2 = W slab builds of the streamed ladder (factor GEMM + pack), 3 = ring (ov)^3 products
-  static constexpr int kRegions = 4;
+  // 2 = W slab builds of the streamed ladder (factor GEMM + pack), 3 = ring (ov)^3 products,
+  // 4 = ladder of the native PNO pairs
+  static constexpr int kRegions = 5;
   double reg_flops[kRegions] = {}, reg_bytes[kRegions] = {};
   int reg_launches[kRegions] = {};
   double last_reg_ms[kRegions] = {}, last_reg_flops[kRegions] = {}, last_reg_bytes[kRegions] = {};

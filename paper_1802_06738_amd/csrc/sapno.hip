@@ -264,6 +264,137 @@ void batched_syev(hipStream_t s, int nmat, const std::vector<int>& nsz, int ld, 
 }
 
 // ----------------------------------------------------------------------------- build
+namespace {
+// y[yoff[g] + e] += sum_ch part[poff[g] + ch n^2 + e] for e < n^2 = nn[g]^2 (one workgroup per pair g)
+__global__ void sum_chunks_kernel(const int* __restrict__ nn, const int* __restrict__ nch,
+                                  const int64_t* __restrict__ poff, const int64_t* __restrict__ yoff,
+                                  const double* __restrict__ part, double* __restrict__ y) {
+  const int g = blockIdx.x;
+  const int64_t n2 = (int64_t)nn[g] * nn[g];
+  const double* pp = part + poff[g];
+  double* yy = y + yoff[g];
+  for (int64_t e = threadIdx.x; e < n2; e += blockDim.x) {
+    double acc = 0.0;
+    for (int ch = 0; ch < nch[g]; ++ch) acc += pp[ch * n2 + e];
+    yy[e] += acc;
+  }
+}
+
+// Ladder of the small pairs in the PNO space (the reduced-cost sigma the Methods section
+// points to).  W_ab^cd = sum_Q B~^Q_ac B~^Q_bd, so the projected ladder of a pair is
+//   U^T [sum_cd W_abcd (U Rbar U^T)_cd] U = sum_Q Bbar^Q Rbar Bbar^Q^T,  Bbar^Q = U^T B~^Q U,
+// exactly: 4 n^3 naux flop per pair instead of the v(v+1)/2 x v(v+1)/2 packed rows of the
+// canonical ladder (~v^4).  Pairs with n_p up to the cut (where 128 n^3 naux = v^4: the
+// grouped 64 x 64 kernel on n x n blocks, n ~ 10-50, runs at 1-3 TFLOP/s against 40-60
+// for the large canonical GEMM) take this route; the others keep the canonical ladder.  Bbar_p is stored [a][Q][c] so that both products
+// are plain GEMMs: Y1 = Bbar_p (rows (a,Q)) Rbar, sigma_p += Y1 (n x naux n) Bbar_p^T.
+void build_native_ladder(Context& c, const std::vector<int>& pi, const std::vector<int>& pj) {
+  PNOData& P = c.pno;
+  hipStream_t s = c.stream;
+  const int o = c.o, v = c.v, naux = c.naux, nmo = c.nmo;
+  const int npair = o * (o + 1) / 2;
+  const int64_t n2 = (int64_t)nmo * nmo;
+  int cut = P.nat_max;
+  if (cut < 0) cut = (int)std::floor(std::cbrt((double)v * v * v * v / (128.0 * naux)));
+  // memory: Bbar and Y1 take 2 sum n^2 naux words; keep them within a fifth of the free HBM
+  size_t fr = 0, tot = 0;
+  PNO_HIP(hipMemGetInfo(&fr, &tot));
+  auto words = [&](int k) {
+    int64_t w = 0;
+    for (int p = 0; p < npair; ++p)
+      if (P.npno[p] > 0 && P.npno[p] <= k) w += (int64_t)P.npno[p] * P.npno[p] * naux;
+    return w;
+  };
+  while (cut > 0 && 16.0 * (double)words(cut) > 0.2 * (double)fr) cut = cut * 3 / 4;
+  P.nat_cut = cut;
+  P.prow.assign(npair, -1);
+  std::vector<int64_t> boff(npair, -1);
+  int64_t bw = 0;
+  int nmax = 0;
+  P.nat_pairs = P.canon_pairs = 0;
+  P.nat_flops = 0;
+  for (int p = 0; p < npair; ++p) {
+    const int n = P.npno[p];
+    if (n > 0 && n <= cut) {
+      boff[p] = bw;
+      bw += (int64_t)n * n * naux;
+      nmax = std::max(nmax, n);
+      ++P.nat_pairs;
+      P.nat_flops += 4.0 * (double)n * n * n * naux;
+    } else if (n > 0) {
+      P.prow[p] = P.canon_pairs++;
+    }
+  }
+  P.d_prow.alloc(npair);
+  PNO_HIP(hipMemcpy(P.d_prow, P.prow.data(), npair * sizeof(int), hipMemcpyHostToDevice));
+  if (P.nat_pairs == 0) return;
+  P.Bbar.alloc(bw);
+  P.Y1.alloc(bw);
+  // Bbar_p[a][Q][k] = sum_xy U_p[x][a] B~^Q[o+x][o+y] U_p[y][k], two batched GEMMs over Q per pair
+  DBuf<double> T1;
+  T1.alloc((int64_t)naux * v * nmax);
+  for (int p = 0; p < npair; ++p) {
+    if (boff[p] < 0) continue;
+    const int n = P.npno[p];
+    const double* Up = P.U + P.uoff[p];
+    GemmDesc<double> d;
+    d.M = v; d.N = n; d.K = v; d.batch = naux;
+    d.A = c.Bt + (int64_t)o * nmo + o; d.lda = nmo; d.sA = n2;
+    d.B = Up; d.ldb = n; d.sB = 0;
+    d.C = T1; d.ldc = n; d.sC = (int64_t)v * n;
+    gemm(d, s);
+    GemmDesc<double> e;
+    e.ta = true; e.M = n; e.N = n; e.K = v; e.batch = naux;
+    e.A = Up; e.lda = n; e.sA = 0;
+    e.B = T1; e.ldb = n; e.sB = (int64_t)v * n;
+    e.C = P.Bbar + boff[p]; e.ldc = (int64_t)naux * n; e.sC = n;
+    gemm(e, s);
+  }
+  // one vector's tables (bases shifted per vector): Y1 = Bbar_p Rbar_p, then the n x n result
+  // over K = naux n in chunks of about 2048 (whole Q blocks), each chunk its own partial
+  // block (so that every pair spreads over several workgroups), summed by a reduction
+  std::vector<GroupDesc> ga, gb;
+  std::vector<int> hn, hch;
+  std::vector<int64_t> hpoff, hyoff;
+  int64_t pw = 0;
+  for (int p = 0; p < npair; ++p) {
+    if (boff[p] < 0) continue;
+    const int64_t n = P.npno[p];
+    GroupDesc d{};
+    d.M = n * naux; d.N = n; d.K = n; d.offA = boff[p]; d.lda = n; d.offB = P.off[o + p]; d.ldb = n;
+    d.offC = boff[p]; d.ldc = n;
+    ga.push_back(d);
+    const int64_t qc = std::max<int64_t>(1, 2048 / n);
+    const int64_t nch = (naux + qc - 1) / qc;
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      const int64_t q0 = ch * qc, nq = std::min<int64_t>(qc, naux - q0);
+      GroupDesc e{};
+      e.M = n; e.N = n; e.K = nq * n;
+      e.offA = boff[p] + q0 * n; e.lda = n * naux; e.offB = boff[p] + q0 * n; e.ldb = n * naux;
+      e.offC = pw + ch * n * n; e.ldc = n;
+      gb.push_back(e);
+    }
+    hn.push_back((int)n);
+    hch.push_back((int)nch);
+    hpoff.push_back(pw);
+    hyoff.push_back(P.off[o + p]);
+    pw += nch * n * n;
+  }
+  gemm_grouped_prepare(ga, false, false, P.t_na);
+  gemm_grouped_prepare(gb, false, true, P.t_nb);
+  P.Ypart.alloc(pw);
+  const int nn = (int)hn.size();
+  P.d_nn.alloc(nn); P.d_nch.alloc(nn); P.d_poff.alloc(nn); P.d_yoff.alloc(nn);
+  PNO_HIP(hipMemcpy(P.d_nn, hn.data(), nn * sizeof(int), hipMemcpyHostToDevice));
+  PNO_HIP(hipMemcpy(P.d_nch, hch.data(), nn * sizeof(int), hipMemcpyHostToDevice));
+  PNO_HIP(hipMemcpy(P.d_poff, hpoff.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice));
+  PNO_HIP(hipMemcpy(P.d_yoff, hyoff.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice));
+  PNO_HIP(hipStreamSynchronize(s));
+  (void)pi;
+  (void)pj;
+}
+}  // namespace
+
 void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
   PNO_CHECK(c.have_df, PNOEOM_ESTATE, "build_sapno before build_df");
   PNO_CHECK(nstates >= 1 && nstates <= c.ov(), PNOEOM_EINVAL, "build_sapno: bad nstates");
@@ -543,6 +674,7 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
     gemm_grouped_prepare(ex2o, false, true, P.t_e2o);
     P.Tw.alloc(std::max<int64_t>(P.toff[npair], 1));
   }
+  build_native_ladder(c, pi, pj);
   P.built = true;
 }
 
@@ -619,11 +751,39 @@ void sigma_pno(Context& c, int nvec, const double* x, double* y, int precision) 
   grow(P.r2, (int64_t)nb * c.oovv());
   grow(P.s1, (int64_t)nb * c.ov());
   grow(P.s2, (int64_t)nb * c.oovv());
+  // canonical sigma with the ladder restricted to the pairs that keep it
+  struct Restrict {
+    Context& c;
+    Restrict(Context& cc, const int* prow, int64_t nsub) : c(cc) {
+      c.lad_prow = prow;
+      c.lad_nsub = nsub;
+    }
+    ~Restrict() {
+      c.lad_prow = nullptr;
+      c.lad_nsub = -1;
+    }
+  };
   for (int q0 = 0; q0 < nvec; q0 += nb) {
     const int n = std::min(nb, nvec - q0);
     pno_expand(c, n, x + (int64_t)q0 * P.len, P.r1, P.r2);
-    sigma_block(c, n, P.r1, P.r2, P.s1, P.s2, c.ov(), c.oovv(), precision);
+    {
+      Restrict r(c, P.nat_pairs > 0 ? (const int*)P.d_prow : nullptr, P.nat_pairs > 0 ? P.canon_pairs : -1);
+      sigma_block(c, n, P.r1, P.r2, P.s1, P.s2, c.ov(), c.oovv(), precision);
+    }
     pno_compress(c, n, P.s1, P.s2, y + (int64_t)q0 * P.len);
+  }
+  // the native pairs' ladder, added in the PNO space (FP64 grouped MFMA GEMMs)
+  if (P.nat_pairs > 0) {
+    hipEvent_t ev = c.region_begin(4, c.stream);
+    for (int q = 0; q < nvec; ++q) {
+      gemm_grouped(P.t_na, 1.0, P.Bbar, x + (int64_t)q * P.len, 0.0, P.Y1, c.stream);
+      gemm_grouped(P.t_nb, 1.0, P.Y1, P.Bbar, 0.0, P.Ypart, c.stream);
+      hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)P.nat_pairs), dim3(256), 0, c.stream,
+                         (const int*)P.d_nn, (const int*)P.d_nch, (const int64_t*)P.d_poff,
+                         (const int64_t*)P.d_yoff, (const double*)P.Ypart, y + (int64_t)q * P.len);
+      PNO_HIP(hipGetLastError());
+    }
+    c.region_end(ev, 4, c.stream, 3 * nvec, nvec * P.nat_flops, 8.0 * nvec * 3.0 * (double)P.Bbar.n);
   }
   for (int q = 0; q < nvec; ++q) project_pno(c, y + (int64_t)q * P.len);
 }

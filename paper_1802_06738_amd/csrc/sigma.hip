@@ -152,11 +152,12 @@ __global__ void ladder_wpm_kernel(int v, int a0, int na, const double* __restric
 }
 
 // S[(q,p)][(c<=d)] = (R^cd + R^dc)/2 (c<d), R^cc ;  A[(q,p)][(c<d)] = (R^cd - R^dc)/2  for pairs p = (i<=j);
-// row strides ldS, ldA
+// row strides ldS, ldA.  With prow, pair p goes to slot prow[p] of nrow slots per vector (none if < 0)
 template <typename OutT>
 __global__ void ladder_pack_kernel(int o, int v, int nvec, const double* __restrict__ r2, int64_t stride,
-                                   OutT* __restrict__ S, int64_t ldS, OutT* __restrict__ A, int64_t ldA) {
-  const int64_t O = o, V = v, vp = V * (V + 1) / 2, vm = V * (V - 1) / 2, npair = O * (O + 1) / 2;
+                                   OutT* __restrict__ S, int64_t ldS, OutT* __restrict__ A, int64_t ldA,
+                                   const int* __restrict__ prow, int64_t nrow) {
+  const int64_t O = o, V = v, vp = V * (V + 1) / 2, vm = V * (V - 1) / 2;
   const int64_t total = (int64_t)nvec * O * O * V * V;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     int64_t r = e;
@@ -166,19 +167,23 @@ __global__ void ladder_pack_kernel(int o, int v, int nvec, const double* __restr
     const int64_t i = r % O; r /= O;
     const int64_t q = r;
     if (j < i || d < c) continue;
+    const int64_t slot = prow ? (int64_t)prow[pair_idx(i, j, O)] : pair_idx(i, j, O);
+    if (slot < 0) continue;
     const double* R = r2 + q * stride + (i * O + j) * V * V;
     const double x = R[c * V + d], y = R[d * V + c];
-    const int64_t row = q * npair + pair_idx(i, j, O);
+    const int64_t row = q * nrow + slot;
     S[row * ldS + tri_idx(c, d, V)] = cvt_out<OutT>(c < d ? 0.5 * (x + y) : x);
     if (c < d) A[row * ldA + stri_idx(c, d, V)] = cvt_out<OutT>(0.5 * (x - y));
   }
 }
 
 // out[q][i][j][a][b] = sigma_ij^ab of the ladder from sigma+ (a<=b) and sigma- (a<b) of pair min(i,j), max(i,j)
+// (rows as in ladder_pack_kernel; zero for a pair without a slot)
 template <typename InT>
 __global__ void ladder_unpack_kernel(int o, int v, int nvec, const InT* __restrict__ SP, const InT* __restrict__ SM,
-                                     double* __restrict__ out, int64_t stride) {
-  const int64_t O = o, V = v, vp = V * (V + 1) / 2, vm = V * (V - 1) / 2, npair = O * (O + 1) / 2;
+                                     double* __restrict__ out, int64_t stride, const int* __restrict__ prow,
+                                     int64_t nrow) {
+  const int64_t O = o, V = v, vp = V * (V + 1) / 2, vm = V * (V - 1) / 2;
   const int64_t total = (int64_t)nvec * O * O * V * V;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     int64_t r = e;
@@ -191,7 +196,12 @@ __global__ void ladder_unpack_kernel(int o, int v, int nvec, const InT* __restri
       int64_t t = i; i = j; j = t;
       t = a; a = b; b = t;
     }
-    const int64_t row = q * npair + pair_idx(i, j, O);
+    const int64_t slot = prow ? (int64_t)prow[pair_idx(i, j, O)] : pair_idx(i, j, O);
+    if (slot < 0) {
+      out[q * stride + (e % (O * O * V * V))] = 0.0;
+      continue;
+    }
+    const int64_t row = q * nrow + slot;
     double val;
     if (a == b) val = (double)SP[row * vp + tri_idx(a, a, V)];
     else if (a < b) val = (double)SP[row * vp + tri_idx(a, b, V)] + (double)SM[row * vm + stri_idx(a, b, V)];
@@ -877,12 +887,15 @@ void ladder_contract(Context& c, int precision, int64_t rows) {
   }
 }
 
-// packs nvec vectors (pairs of o occupied) into the ladder work arrays of a precision
-void ladder_pack(Context& c, int precision, int o, int nvec, const double* r2, int64_t stride2) {
+// packs nvec vectors (pairs of o occupied) into the ladder work arrays of a precision; with
+// prow, only the pairs with a slot (nrow slots per vector), else all o(o+1)/2 pairs
+void ladder_pack(Context& c, int precision, int o, int nvec, const double* r2, int64_t stride2,
+                 const int* prow = nullptr, int64_t nrow = -1) {
   SigmaWork& w = c.sw;
   hipStream_t s = c.stream;
   const int64_t v = c.v, vp = v * (v + 1) / 2, vm = v * (v - 1) / 2, vm1 = std::max<int64_t>(vm, 1);
-  const int64_t rows = (int64_t)nvec * o * (o + 1) / 2;
+  if (!prow) nrow = (int64_t)o * (o + 1) / 2;
+  const int64_t rows = std::max<int64_t>((int64_t)nvec * nrow, 1);
   const int64_t tot = (int64_t)nvec * o * o * v * v;
   const bool f32 = precision == PNOEOM_FP32, bf = precision == PNOEOM_BF16;
   if (f32 || bf) {
@@ -893,7 +906,7 @@ void ladder_pack(Context& c, int precision, int o, int nvec, const double* r2, i
   if (f32) {
     grow(w.Spf, rows * vp); grow(w.Amf, rows * vm1);
     hipLaunchKernelGGL((ladder_pack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, o, (int)v, nvec, r2, stride2,
-                       (float*)w.Spf, vp, (float*)w.Amf, vm);
+                       (float*)w.Spf, vp, (float*)w.Amf, vm, prow, nrow);
   } else if (bf) {
     // padded rows; the padding columns are zeroed once per allocation and never written
     if ((int64_t)w.Spb.n < rows * c.ldpb || (int64_t)w.Amb.n < rows * c.ldmb) {
@@ -906,25 +919,27 @@ void ladder_pack(Context& c, int precision, int o, int nvec, const double* r2, i
       PNO_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL((ladder_pack_kernel<uint16_t>), dim3(grid1(tot)), dim3(256), 0, s, o, (int)v, nvec, r2,
-                       stride2, (uint16_t*)w.Spb, c.ldpb, (uint16_t*)w.Amb, c.ldmb);
+                       stride2, (uint16_t*)w.Spb, c.ldpb, (uint16_t*)w.Amb, c.ldmb, prow, nrow);
   } else {
     grow(w.Sp, rows * vp); grow(w.Am, rows * vm1);
     hipLaunchKernelGGL((ladder_pack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, o, (int)v, nvec, r2,
-                       stride2, (double*)w.Sp, vp, (double*)w.Am, vm);
+                       stride2, (double*)w.Sp, vp, (double*)w.Am, vm, prow, nrow);
   }
   PNO_HIP(hipGetLastError());
 }
 
 // unpacks the ladder result of nvec vectors into full [q][i][j][a][b] arrays (stride per vector)
-void ladder_unpack(Context& c, int precision, int o, int nvec, double* out, int64_t stride) {
+void ladder_unpack(Context& c, int precision, int o, int nvec, double* out, int64_t stride,
+                   const int* prow = nullptr, int64_t nrow = -1) {
   SigmaWork& w = c.sw;
   const int64_t v = c.v, tot = (int64_t)nvec * o * o * v * v;
+  if (!prow) nrow = (int64_t)o * (o + 1) / 2;
   if (precision != PNOEOM_FP64)
     hipLaunchKernelGGL((ladder_unpack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, c.stream, o, (int)v, nvec,
-                       (const float*)w.SigPf, (const float*)w.SigMf, out, stride);
+                       (const float*)w.SigPf, (const float*)w.SigMf, out, stride, prow, nrow);
   else
     hipLaunchKernelGGL((ladder_unpack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, c.stream, o, (int)v, nvec,
-                       (const double*)w.SigP, (const double*)w.SigM, out, stride);
+                       (const double*)w.SigP, (const double*)w.SigM, out, stride, prow, nrow);
   PNO_HIP(hipGetLastError());
 }
 }  // namespace
@@ -954,12 +969,15 @@ void sigma_block_chunk(Context& c, int nvec, const double* r1, const double* r2,
   SigmaWork& w = c.sw;
   const int o = c.o;
   const int64_t oovv = c.oovv();
-  const int64_t rows = (int64_t)nvec * o * (o + 1) / 2;
+  // all pairs, or (PNO space with native pairs) the pairs that keep the canonical ladder
+  const int* prow = c.lad_nsub >= 0 ? c.lad_prow : nullptr;
+  const int64_t nrow = c.lad_nsub >= 0 ? c.lad_nsub : (int64_t)o * (o + 1) / 2;
+  const int64_t rows = (int64_t)nvec * nrow;
   grow(w.LadAll, (int64_t)nvec * oovv);
   // ---------------------------------------------------------------- particle ladder, all vectors at once
-  ladder_pack(c, precision, o, nvec, r2, stride2);
+  ladder_pack(c, precision, o, nvec, r2, stride2, prow, nrow);
   ladder_contract(c, precision, rows);
-  ladder_unpack(c, precision, o, nvec, w.LadAll, oovv);
+  ladder_unpack(c, precision, o, nvec, w.LadAll, oovv, prow, nrow);
   // ---------------------------------------------------------------- everything else
   sigma_rest_block(c, nvec, r1, stride1, r2, stride2, s1, s2, precision, w.LadAll);
 }

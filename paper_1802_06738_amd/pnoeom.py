@@ -25,7 +25,8 @@ EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pno
                     "pnoeom_last_region_timing", "pnoeom_host_syev", "pnoeom_probe_peaks",
                     "pnoeom_gemm_record", "pnoeom_gemm_recorded", "pnoeom_gemm_time", "pnoeom_gemm_set_table",
                     "pnoeom_set_graph_mode", "pnoeom_graph_stats", "pnoeom_set_ladder_mode",
-                    "pnoeom_build_ladder", "pnoeom_ladder_apply"]
+                    "pnoeom_build_ladder", "pnoeom_ladder_apply", "pnoeom_set_pno_ladder",
+                    "pnoeom_pno_ladder_stats"]
 
 
 class PnoEomError(RuntimeError):
@@ -88,6 +89,8 @@ def load_library():
     lib.pnoeom_set_ladder_mode.argtypes = [vp, C.c_int, C.c_int]
     lib.pnoeom_build_ladder.argtypes = [vp, vp, vp, C.c_int]
     lib.pnoeom_ladder_apply.argtypes = [vp, C.c_int, vp, vp, C.c_int]
+    lib.pnoeom_set_pno_ladder.argtypes = [vp, C.c_int]
+    lib.pnoeom_pno_ladder_stats.argtypes = [vp, ip, ip, ip, dp]
     _LIB = lib
     # the autotuner's table of GEMM tile choices for this device, when present
     from .autotune import DEFAULT_TABLE, load_table
@@ -280,6 +283,16 @@ class PnoEom:
                                                  _dev(Y, (nmat, v, v), "Y"), precision))
         return Y
 
+    def set_pno_ladder(self, max_native=-1):
+        """PNO-space ladder for pairs with n_p <= max_native at the next build_sapno (-1 auto, 0 none)."""
+        self._check(self.lib.pnoeom_set_pno_ladder(self.h, int(max_native)))
+
+    def pno_ladder_stats(self):
+        v = [C.c_int() for _ in range(3)]
+        f = C.c_double()
+        self._check(self.lib.pnoeom_pno_ladder_stats(self.h, *[C.byref(x) for x in v], C.byref(f)))
+        return dict(cut=v[0].value, native_pairs=v[1].value, canonical_pairs=v[2].value, native_flops=f.value)
+
     def set_graph_mode(self, enable=True):
         self._check(self.lib.pnoeom_set_graph_mode(self.h, int(bool(enable))))
 
@@ -305,7 +318,8 @@ class PnoEom:
             self._check(self.lib.pnoeom_last_ladder_timing(self.h, p, C.byref(lad), C.byref(n), C.byref(fl)))
             out[name] = dict(ladder_ms=lad.value, ladder_launches=n.value, ladder_flops=fl.value)
         by = C.c_double()
-        for r, name in ((0, "dots"), (1, "pno_transform"), (2, "ladder_w_build"), (3, "ring")):
+        for r, name in ((0, "dots"), (1, "pno_transform"), (2, "ladder_w_build"), (3, "ring"),
+                        (4, "pno_native_ladder")):
             self._check(self.lib.pnoeom_last_region_timing(self.h, r, C.byref(lad), C.byref(n), C.byref(fl),
                                                            C.byref(by)))
             out[name] = dict(ms=lad.value, launches=n.value, flops=fl.value, bytes=by.value)

@@ -149,3 +149,40 @@ def test_pno_small_graph_mode_vs_golden():
     r = ctx.davidson(c["nroots"], space=1, tol_e=1e-10, tol_r=1e-6, nextra=2)
     assert ctx.graph_stats()["launches"] > 0
     assert np.max(np.abs(r["omega"] - np.array(g["davidson_pno"]))) <= 1e-8
+
+
+@pytest.mark.parametrize("max_native,streamed", [(0, False), (6, False), (1000, False), (6, True)])
+def test_pno_sigma_ladder_split_matches_oracle(max_native, streamed):
+    """The ladder of pairs with n_p <= max_native evaluated in the PNO space with per-pair
+    factors, the rest canonically (W cached or streamed): P sigma vs the oracle at 1e-9."""
+    print(f"[pno ladder split] max_native={max_native} streamed={streamed}", flush=True)
+    import torch
+    from paper_1802_06738_amd import PnoEom, LADDER_STREAMED
+    o, v, naux, kappa, nst, tcut, seed = SMALL[1]
+    s = make_system(o, v, naux, seed, kappa=kappa, t1_sigma=1e-3)
+    ctx = PnoEom(o, v, naux)
+    if streamed:
+        ctx.set_ladder_mode(LADDER_STREAMED, 4)
+    ctx.build_df(torch.from_numpy(s.B).cuda(), torch.from_numpy(s.eps).cuda(), torch.from_numpy(s.t1).cuda())
+    ctx.set_pno_ladder(max_native)
+    npno, _ = ctx.build_sapno(nst, tcut)
+    st = ctx.pno_ladder_stats()
+    nz = int(np.count_nonzero(npno))
+    assert st["native_pairs"] == int(np.count_nonzero((npno > 0) & (npno <= max_native)))
+    assert st["native_pairs"] + st["canonical_pairs"] == nz
+    if max_native == 6:
+        assert 0 < st["native_pairs"] < nz                 # both routes taken
+    so, pb, _ = _oracle_basis(s, nst, tcut)
+    r1, r2 = random_r(o, v, seed + 5, nvec=3)
+    x = ctx.pno_compress(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda())
+    y = ctx.sigma_pno(x)
+    f1, f2 = ctx.pno_expand(y)
+    f1, f2 = f1.cpu().numpy(), f2.cpu().numpy()
+    for k in range(3):
+        p1, p2 = pb.project(r1[k], r2[k])
+        q1, q2 = so.sigma(p1, p2)
+        q1, q2 = pb.project(q1, q2)
+        assert np.max(np.abs(f1[k] - q1)) <= 1e-9 * np.max(np.abs(q1))
+        assert np.max(np.abs(f2[k] - q2)) <= 1e-9 * np.max(np.abs(q2))
+    t = ctx.last_timing()
+    assert (t["pno_native_ladder"]["launches"] > 0) == (st["native_pairs"] > 0)
