@@ -313,6 +313,11 @@ void launch_tile(const GemmDesc<T>& d, hipStream_t s, int split_mode = 0) {
     const int64_t target = split_mode == 2 ? 1024 : 512;
     nsplit = std::min<int64_t>(loop / 8, (target + tiles * gy - 1) / (tiles * gy));
     nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, 1024));
+  } else if (split_mode == 0 && loop >= 4096 && tiles * gy < 2048) {
+    // very long K with a few waves of tiles: the last, partly filled wave of workgroups
+    // idles most of the chip for a whole K loop; splitting K gives at least four waves
+    nsplit = std::min<int64_t>(loop / 1024, (2048 + tiles * gy - 1) / (tiles * gy));
+    nsplit = std::max<int64_t>(1, nsplit);
   }
   g.it_split = 0;
   g.ws = nullptr;
