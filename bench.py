@@ -242,6 +242,54 @@ def config5_share(args):
     print(json.dumps(out))
 
 
+def states_compare(args):
+    """PNO truncation error against the number of averaged states, on the reduced PNO
+    workload (o=10, v=100, naux=300, 4 roots): state averages over the lowest 1..4 CIS
+    states and the state-specific PNOs of each state, each PNO-space Davidson compared
+    root by root with the canonical FP64 Davidson (the comparison of PNO counts and
+    errors against nStates in the paper's Results, on synthetic data)."""
+    import torch
+    from synthgen import config_system, CONFIGS
+    from paper_1802_06738_amd import PnoEom, FP64, CANONICAL, PNO
+    cfg = CONFIGS["pno_small"]
+    s = config_system("pno_small")
+    o, v, naux, nroots = s.o, s.v, s.naux, cfg["nroots"]
+    tcut = args.tcut if args.tcut is not None else cfg["tcut"]
+    dev = torch.device("cuda:0")
+    B = torch.from_numpy(s.B).to(dev)
+    eps = torch.from_numpy(s.eps).to(dev)
+    t1 = torch.from_numpy(s.t1).to(dev)
+    ctx = PnoEom(o, v, naux)
+    ctx.build_df(B, eps, t1)
+    t0 = time.perf_counter()
+    can = ctx.davidson(nroots, space=CANONICAL, tol_e=1e-9, tol_r=1e-6)["omega"]
+    t_can = time.perf_counter() - t0
+    rows = []
+    for n in range(1, nroots + 1):
+        ctx.set_pno_states([])
+        npno, _ = ctx.build_sapno(n, tcut)
+        t0 = time.perf_counter()
+        om = ctx.davidson(nroots, space=PNO, tol_e=1e-9, tol_r=1e-6)["omega"]
+        rows.append({"pnos": f"state average over the lowest {n}", "npno_mean": float(np.mean(npno)),
+                     "err_eh": [float(x) for x in (om - can)], "davidson_s": time.perf_counter() - t0})
+    for k in range(nroots):
+        ctx.set_pno_states([k])
+        npno, _ = ctx.build_sapno(1, tcut)
+        t0 = time.perf_counter()
+        om = ctx.davidson(k + 1, space=PNO, tol_e=1e-9, tol_r=1e-6)["omega"]
+        rows.append({"pnos": f"state-specific, state {k}", "npno_mean": float(np.mean(npno)),
+                     "err_eh": [None] * k + [float(om[k] - can[k])] + [None] * (nroots - k - 1),
+                     "davidson_s": time.perf_counter() - t0})
+    ctx.set_pno_states([])
+    out = {"metric": METRIC, "value": None, "unit": "Eh (PNO truncation error per root)",
+           "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * t_can, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"reduced PNO workload o={o}, v={v}, naux={naux}, {nroots} roots, T_cut={tcut:g}: "
+                                  "PNO truncation error vs the number of averaged states"},
+           "canonical_omega": [float(x) for x in can], "rows": rows}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -254,6 +302,8 @@ def main():
     ap.add_argument("--tcut", type=float, default=None, help="PNO cut (default: the config's, else 1e-7)")
     ap.add_argument("--mixed", default="fp32,bf16", help="mixed precisions to run (comma list)")
     ap.add_argument("--graph", type=int, default=1, help="also time the FP64 steps in graph mode (0/1)")
+    ap.add_argument("--states-compare", action="store_true",
+                    help="PNO truncation error vs the number of averaged states (reduced PNO workload)")
     ap.add_argument("--pno-ladder", type=int, default=-1,
                     help="PNO-space ladder for pairs with n_p up to this (-1 automatic, 0 none)")
     args = ap.parse_args()
@@ -262,6 +312,9 @@ def main():
         sys.exit(2)
     if args.config == 5:
         config5_share(args)
+        return
+    if args.states_compare:
+        states_compare(args)
         return
 
     import torch

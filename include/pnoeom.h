@@ -132,6 +132,14 @@ int pnoeom_pno_transform(pnoeom_ctx* ctx, int nvec, int direction, double* r1, d
 int pnoeom_apply_sigma(pnoeom_ctx* ctx, int nvec, const double* r1, const double* r2, double* s1,
                        double* s2, int space, int precision);
 
+/* States whose CIS(D) pair densities pnoeom_build_sapno averages (Methods: the
+ * state-specific density of one state and the state average over several).
+ *   states : host [n] distinct CIS state indices, 0 = the lowest root; n = 1 gives the
+ *            state-specific PNOs of that state; n = 0 restores the default (the lowest
+ *            nstates of the build_sapno call, whose nstates is ignored while a list is set).
+ * Errors: EINVAL (null ctx, negative or repeated index, states NULL with n > 0). */
+int pnoeom_set_pno_states(pnoeom_ctx* ctx, int n, const int* states);
+
 /* Ladder of the PNO-space sigma, for the next pnoeom_build_sapno.  The projected ladder of
  * a pair is U^T [sum_cd W_ab^cd (U Rbar U^T)_cd] U = sum_Q Bbar^Q Rbar Bbar^Q^T with the
  * pair's factors Bbar^Q = U^T B~^Q U (W_ab^cd = sum_Q B~^Q_ac B~^Q_bd; Methods, the PNO

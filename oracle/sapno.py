@@ -90,15 +90,17 @@ def pair_density(bij, diag):
     return (2.0 / (2.0 if diag else 1.0)) * (bij @ bt.T + bij.T @ bt)
 
 
-def sa_densities(eps, B, o, nstates):
-    """Average of the CIS(D) pair densities over the lowest nstates CIS roots.
+def sa_densities(eps, B, o, nstates, states=None):
+    """Average of the CIS(D) pair densities over the lowest nstates CIS roots, or over
+    the listed CIS states (one state: the state-specific density of that state).
 
     Returns (D [i, j, v, v] for all i, j with D[j,i] = D[i,j], omegas, cis vectors).
     """
-    w, b = cis_roots(eps, B, o, nstates)
+    states = list(range(nstates)) if states is None else [int(k) for k in states]
+    w, b = cis_roots(eps, B, o, max(states) + 1)
     v = B.shape[1] - o
     D = np.zeros((o, o, v, v))
-    for k in range(nstates):
+    for k in states:
         bk = cisd_doubles(eps, B, o, w[k], b[k])
         for i in range(o):
             for j in range(i, o):
@@ -106,7 +108,7 @@ def sa_densities(eps, B, o, nstates):
                 D[i, j] += d
                 if j != i:
                     D[j, i] += d
-    D /= nstates
+    D /= len(states)
     return D, w, b
 
 

@@ -1,6 +1,7 @@
 // C ABI of libpnoeom: argument checks, exception-to-status mapping, timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 
@@ -247,6 +248,18 @@ int pnoeom_ladder_apply(pnoeom_ctx* ctx, int nmat, const double* X, double* Y, i
     Timer t(c);
     pnoeom::ladder_apply(c, nmat, X, Y, precision);
     t.stop();
+  });
+}
+
+int pnoeom_set_pno_states(pnoeom_ctx* ctx, int n, const int* states) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(n >= 0 && (n == 0 || states), PNOEOM_EINVAL, "set_pno_states: bad list");
+    std::vector<int> l(states, states + n);
+    std::vector<int> sorted = l;
+    std::sort(sorted.begin(), sorted.end());
+    PNO_CHECK(n == 0 || (sorted.front() >= 0 && std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end()),
+              PNOEOM_EINVAL, "set_pno_states: indices must be distinct and >= 0");
+    c.pno.states = l;
   });
 }
 

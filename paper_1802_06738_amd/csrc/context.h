@@ -50,6 +50,7 @@ struct PNOData {
   // factors Bbar_p[a][Q][c] = (U_p^T B~^Q U_p)[a][c]; the other pairs keep the canonical
   // ladder (rows listed by prow: slot in the packed ladder, -1 for a native pair)
   int nat_max = -1;             // requested bound (-1 auto, 0 none)
+  std::vector<int> states;      // CIS states averaged by build_sapno (empty: the lowest nstates)
   int nat_cut = 0, nat_pairs = 0, canon_pairs = 0;
   std::vector<int> prow;
   DBuf<int> d_prow;

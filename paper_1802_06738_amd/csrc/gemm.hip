@@ -65,6 +65,7 @@ struct KArgs {
   int64_t xper;       // tiles per XCD chunk; 0: grid index = tile index
   int64_t it_split;   // K-loop iterations per split (split-K); 0: no split
   T* ws;              // split-K partials [split][batch_out][M][N]
+  int vec_a, vec_b;   // FP32 operands whose interior tiles load as 16-byte vectors (aligned rows)
 };
 
 constexpr int NT = 256;
@@ -111,6 +112,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
   const int64_t total = ktiles * nb;
 
   T ra[LA], rb[LB];
+  // which staging map the registers hold: scalar (element e = tid + q NT) or, for FP32
+  // interior tiles of 16-byte aligned operands, vector (four consecutive elements of the
+  // contiguous dimension per load: float4 f = tid + q NT holds elements 4f .. 4f + 3)
+  bool va = false, vb = false;
+  constexpr bool kVec = sizeof(T) == 4 && LA % 4 == 0 && LB % 4 == 0;
 
   // Staging map: element e = tid + q * NT of the A tile sits at (mm, kk) with
   // mm = e / BK, kk = e % BK (A row-major) or kk = e / BM, mm = e % BM (A^T given);
@@ -124,23 +130,47 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
     const T* A = g.A + b * g.sA;
     const T* B = g.B + b * g.sB;
     if (interior && k0 + BK <= g.K) {
-      if (!TA) {
+      if constexpr (kVec) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        va = g.vec_a != 0;
+        vb = g.vec_b != 0;
+        if (va) {
+#pragma unroll
+          for (int q = 0; q < LA / 4; ++q) {
+            const int f = tid + q * NT;
+            const f4 x = TA ? *(const f4*)(A + (k0 + f / (BM / 4)) * g.lda + m0 + 4 * (f % (BM / 4)))
+                            : *(const f4*)(A + (m0 + f / (BK / 4)) * g.lda + k0 + 4 * (f % (BK / 4)));
+            ra[4 * q] = x.x; ra[4 * q + 1] = x.y; ra[4 * q + 2] = x.z; ra[4 * q + 3] = x.w;
+          }
+        }
+        if (vb) {
+#pragma unroll
+          for (int q = 0; q < LB / 4; ++q) {
+            const int f = tid + q * NT;
+            const f4 x = TB ? *(const f4*)(B + (n0 + f / (BK / 4)) * g.ldb + k0 + 4 * (f % (BK / 4)))
+                            : *(const f4*)(B + (k0 + f / (BN / 4)) * g.ldb + n0 + 4 * (f % (BN / 4)));
+            rb[4 * q] = x.x; rb[4 * q + 1] = x.y; rb[4 * q + 2] = x.z; rb[4 * q + 3] = x.w;
+          }
+        }
+        if (va && vb) return;
+      }
+      if (!TA && !va) {
         const T* p = A + (m0 + tid / BK) * g.lda + k0 + tid % BK;
         const int64_t st = (int64_t)(NT / BK) * g.lda;
 #pragma unroll
         for (int q = 0; q < LA; ++q) ra[q] = p[q * st];
-      } else {
+      } else if (TA && !va) {
         const T* p = A + (k0 + tid / BM) * g.lda + m0 + tid % BM;
         const int64_t st = (int64_t)(NT / BM) * g.lda;
 #pragma unroll
         for (int q = 0; q < LA; ++q) ra[q] = p[q * st];
       }
-      if (TB) {
+      if (TB && !vb) {
         const T* p = B + (n0 + tid / BK) * g.ldb + k0 + tid % BK;
         const int64_t st = (int64_t)(NT / BK) * g.ldb;
 #pragma unroll
         for (int q = 0; q < LB; ++q) rb[q] = p[q * st];
-      } else {
+      } else if (!TB && !vb) {
         const T* p = B + (k0 + tid / BN) * g.ldb + n0 + tid % BN;
         const int64_t st = (int64_t)(NT / BN) * g.ldb;
 #pragma unroll
@@ -148,6 +178,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
       }
       return;
     }
+    va = vb = false;
 #pragma unroll
     for (int q = 0; q < LA; ++q) {
       const int e = tid + q * NT;
@@ -170,19 +201,43 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
     }
   };
   auto store = [&]() {
+    if (kVec && va) {
 #pragma unroll
-    for (int q = 0; q < LA; ++q) {
-      const int e = tid + q * NT;
-      int mm, kk;
-      if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }
-      As[kk][mm] = ra[q];
+      for (int q = 0; q < LA / 4; ++q) {
+        const int f = tid + q * NT;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (TA) As[f / (BM / 4)][4 * (f % (BM / 4)) + t] = ra[4 * q + t];
+          else As[4 * (f % (BK / 4)) + t][f / (BK / 4)] = ra[4 * q + t];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        const int e = tid + q * NT;
+        int mm, kk;
+        if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }
+        As[kk][mm] = ra[q];
+      }
     }
+    if (kVec && vb) {
 #pragma unroll
-    for (int q = 0; q < LB; ++q) {
-      const int e = tid + q * NT;
-      int nn, kk;
-      if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
-      Bs[kk][nn] = rb[q];
+      for (int q = 0; q < LB / 4; ++q) {
+        const int f = tid + q * NT;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (TB) Bs[4 * (f % (BK / 4)) + t][f / (BK / 4)] = rb[4 * q + t];
+          else Bs[f / (BN / 4)][4 * (f % (BN / 4)) + t] = rb[4 * q + t];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        const int e = tid + q * NT;
+        int nn, kk;
+        if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
+        Bs[kk][nn] = rb[q];
+      }
     }
   };
   auto compute = [&]() {
@@ -300,6 +355,14 @@ void launch_tile(const GemmDesc<T>& d, hipStream_t s, int split_mode = 0) {
   g.B = d.B; g.ldb = d.ldb; g.sB = d.sB;
   g.C = d.C; g.ldc = d.ldc; g.sC = d.sC;
   g.batch = d.batch; g.reduce = d.reduce ? 1 : 0;
+  // 16-byte vector loads of FP32 interior tiles: rows (and batch strides) of whole float4s
+  g.vec_a = g.vec_b = 0;
+#ifndef PNO_NO_F32_VEC
+  if (sizeof(T) == 4) {
+    g.vec_a = (d.lda % 4 == 0 && d.sA % 4 == 0 && ((uintptr_t)d.A % 16) == 0) ? 1 : 0;
+    g.vec_b = (d.ldb % 4 == 0 && d.sB % 4 == 0 && ((uintptr_t)d.B % 16) == 0) ? 1 : 0;
+  }
+#endif
   g.tiles_m = (int)((d.M + BM - 1) / BM);
   g.tiles_n = (int)((d.N + BN - 1) / BN);
   const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n;

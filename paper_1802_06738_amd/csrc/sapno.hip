@@ -405,15 +405,22 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
   const int o = c.o, v = c.v, naux = c.naux, nmo = c.nmo;
   const int64_t n2 = (int64_t)nmo * nmo, ov = c.ov(), oovv = c.oovv(), vv = (int64_t)v * v;
   const int npair = o * (o + 1) / 2;
-  P.nstates = nstates;
+  // states whose densities are averaged: the lowest nstates, or the list set by
+  // pnoeom_set_pno_states (one state: the state-specific PNOs of that state)
+  std::vector<int> avg = P.states;
+  if (avg.empty())
+    for (int k = 0; k < nstates; ++k) avg.push_back(k);
+  const int ncis = *std::max_element(avg.begin(), avg.end()) + 1;
+  PNO_CHECK(ncis <= c.ov(), PNOEOM_EINVAL, "build_sapno: state index beyond the CIS space");
+  P.nstates = (int)avg.size();
   P.tcut_pno = tcut_pno;
   P.tcut_osv = tcut_osv;
 
   // 1. CIS roots
-  std::vector<double> w(nstates);
+  std::vector<double> w(ncis);
   DBuf<double> bvec;
-  bvec.alloc((int64_t)nstates * ov);
-  cis_roots(c, nstates, w.data(), bvec);
+  bvec.alloc((int64_t)ncis * ov);
+  cis_roots(c, ncis, w.data(), bvec);
 
   // 2. averaged pair densities D[i][j] (all pairs, unscaled sum over states)
   DBuf<double> D, Bk, Bt2, Kt, Bp, XT, BvoT0;
@@ -432,7 +439,7 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
     p.os[0] = (int64_t)v * naux; p.os[1] = naux; p.os[2] = 1; p.os[3] = 0;
     permute4(s, p, 1.0, c.B + (int64_t)o * nmo, 0.0, BvoT0);
   }
-  for (int k = 0; k < nstates; ++k) {
+  for (int k : avg) {
     const double* b = bvec + (int64_t)k * ov;
     // B'_vo[Q][a][i] = -sum_l b_l^a B[Q][l][i] + sum_c B[Q][o+a][o+c] b_i^c
     gm(s, true, false, v, o, o, -1.0, b, v, 0, c.B, nmo, n2, 0.0, Bp, o, (int64_t)v * o, naux);
@@ -470,7 +477,7 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
   Vt.alloc((int64_t)npair * vv);
   ev.alloc((int64_t)npair * v);
   hipLaunchKernelGGL(gather_pairs_kernel, dim3(gsz((int64_t)npair * vv)), dim3(256), 0, s, o, v, npair,
-                     (const int*)dpi, (const int*)dpj, 1.0 / nstates, (const double*)D, (double*)Dp);
+                     (const int*)dpi, (const int*)dpj, 1.0 / (double)avg.size(), (const double*)D, (double*)Dp);
   PNO_HIP(hipGetLastError());
   D.release();
   {

@@ -26,7 +26,7 @@ EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pno
                     "pnoeom_gemm_record", "pnoeom_gemm_recorded", "pnoeom_gemm_time", "pnoeom_gemm_set_table",
                     "pnoeom_set_graph_mode", "pnoeom_graph_stats", "pnoeom_set_ladder_mode",
                     "pnoeom_build_ladder", "pnoeom_ladder_apply", "pnoeom_set_pno_ladder",
-                    "pnoeom_pno_ladder_stats"]
+                    "pnoeom_pno_ladder_stats", "pnoeom_set_pno_states"]
 
 
 class PnoEomError(RuntimeError):
@@ -90,6 +90,7 @@ def load_library():
     lib.pnoeom_build_ladder.argtypes = [vp, vp, vp, C.c_int]
     lib.pnoeom_ladder_apply.argtypes = [vp, C.c_int, vp, vp, C.c_int]
     lib.pnoeom_set_pno_ladder.argtypes = [vp, C.c_int]
+    lib.pnoeom_set_pno_states.argtypes = [vp, C.c_int, ip]
     lib.pnoeom_pno_ladder_stats.argtypes = [vp, ip, ip, ip, dp]
     _LIB = lib
     # the autotuner's table of GEMM tile choices for this device, when present
@@ -282,6 +283,11 @@ class PnoEom:
         self._check(self.lib.pnoeom_ladder_apply(self.h, nmat, _dev(X, (nmat, v, v), "X"),
                                                  _dev(Y, (nmat, v, v), "Y"), precision))
         return Y
+
+    def set_pno_states(self, states=()):
+        """CIS states averaged by the next build_sapno (one state: state-specific PNOs; () = default)."""
+        arr = (C.c_int * max(len(states), 1))(*[int(k) for k in states])
+        self._check(self.lib.pnoeom_set_pno_states(self.h, len(states), arr if len(states) else None))
 
     def set_pno_ladder(self, max_native=-1):
         """PNO-space ladder for pairs with n_p <= max_native at the next build_sapno (-1 auto, 0 none)."""

@@ -30,12 +30,12 @@ def _ctx(s):
     return ctx
 
 
-def _oracle_basis(s, nst, tcut):
+def _oracle_basis(s, nst, tcut, states=None):
     from oracle.sapno import sa_densities, PNOBasis
     from oracle.sigma import SigmaOracle
     so = SigmaOracle(s.eps, s.B, s.o, s.t1)
     eo, _, fvv = so.dressed_fock_diagonals()
-    D, w, b = sa_densities(s.eps, s.B, s.o, nst)
+    D, w, b = sa_densities(s.eps, s.B, s.o, nst, states=states)
     return so, PNOBasis(D, s.eps, s.o, tcut, fvv=fvv, eo=eo), b
 
 
@@ -186,3 +186,27 @@ def test_pno_sigma_ladder_split_matches_oracle(max_native, streamed):
         assert np.max(np.abs(f2[k] - q2)) <= 1e-9 * np.max(np.abs(q2))
     t = ctx.last_timing()
     assert (t["pno_native_ladder"]["launches"] > 0) == (st["native_pairs"] > 0)
+
+
+@pytest.mark.parametrize("states", [[2], [0, 2], [1]])
+def test_state_specific_and_listed_state_pnos(states):
+    """PNOs from the densities of listed CIS states (one state: state-specific PNOs):
+    counts exact, projector 1e-9, and the state list reset restores the default."""
+    print(f"[pno states] {states}", flush=True)
+    import torch
+    o, v, naux, kappa, nst, tcut, seed = SMALL[0]
+    s = make_system(o, v, naux, seed, kappa=kappa, t1_sigma=1e-3)
+    ctx = _ctx(s)
+    ctx.set_pno_states(states)
+    npno, nosv = ctx.build_sapno(nst, tcut)
+    so, pb, _ = _oracle_basis(s, nst, tcut, states=states)
+    assert np.array_equal(npno, pb.npno()) and np.array_equal(nosv, pb.nosv())
+    r1, r2 = random_r(o, v, seed + 7, nvec=1)
+    x = ctx.pno_compress(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda())
+    e1, e2 = ctx.pno_expand(x)
+    p1, p2 = pb.project(r1[0], r2[0])
+    assert np.max(np.abs(e2.cpu().numpy()[0] - p2)) <= 1e-9 * np.max(np.abs(p2))
+    ctx.set_pno_states([])
+    npno0, _ = ctx.build_sapno(nst, tcut)
+    _, pb0, _ = _oracle_basis(s, nst, tcut)
+    assert np.array_equal(npno0, pb0.npno())

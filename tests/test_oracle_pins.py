@@ -288,6 +288,24 @@ def test_sa_density_rotation_invariance_and_single_state():
     assert np.allclose(D1[0, 1], pair_density(bk[0, 1], False), atol=1e-15)
 
 
+def test_state_list_densities():
+    """A listed set of states: one state gives that state's own density (state-specific
+    PNOs); the default list is the lowest nstates; the state average is the mean of the
+    state-specific densities."""
+    s = make_system(3, 6, 12, 19)
+    o = 3
+    w, b = cis_roots(s.eps, s.B, o, 3)
+    D2, _, _ = sa_densities(s.eps, s.B, o, 1, states=[2])
+    bk = cisd_doubles(s.eps, s.B, o, w[2], b[2])
+    assert np.allclose(D2[0, 2], pair_density(bk[0, 2], False), atol=1e-15)
+    assert np.allclose(D2[1, 1], pair_density(bk[1, 1], True), atol=1e-15)
+    Da, _, _ = sa_densities(s.eps, s.B, o, 3)
+    Db, _, _ = sa_densities(s.eps, s.B, o, 1, states=[0, 1, 2])
+    assert np.array_equal(Da, Db)
+    Dss = [sa_densities(s.eps, s.B, o, 1, states=[k])[0] for k in range(3)]
+    assert np.allclose(sum(Dss) / 3.0, Da, atol=1e-15)
+
+
 def test_truncation_monotone_and_tcut0_identity():
     s = make_system(3, 8, 16, 23, kappa=2.0)
     o = 3
