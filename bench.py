@@ -36,12 +36,12 @@ HBM_PEAK = 8000.0                       # GB/s
 # two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; profiles/gemm_fp64_config2_traffic.md), scaled by
 # what the counter reads for a 1 GiB + 1 GiB device copy.  Valid only for the GEMM source
 # they were taken on: reported as null once that source changes (or before a measurement).
-_GEMM_SHA = "a0efbc7a96c6a967674d048c0b0ad43fa3c01e196abd15d73628544d50185179"
+_GEMM_SHA = "5162c6f377ec23cc1623fd14603858747fc909f816f131c9288f960950e7d773"
 KERNEL_TRAFFIC = {
-    "ring": {"config": 2, "gemm_sha256": _GEMM_SHA, "fetch_kib": 6757468.3, "fetch_scale": 1048576.0 / 524304.0,
-             "write_kib": 441051.1, "write_scale": 1048576.0 / 1048576.1},
-    "ladder": {"config": 2, "gemm_sha256": _GEMM_SHA, "fetch_kib": 3008318.0, "fetch_scale": 1048576.0 / 524304.0,
-               "write_kib": 130357.2, "write_scale": 1048576.0 / 1048576.1},
+    "ring": {"config": 2, "gemm_sha256": _GEMM_SHA, "fetch_kib": 6831362.8, "fetch_scale": 1048576.0 / 524303.3,
+             "write_kib": 441051.1, "write_scale": 1048576.0 / 1048576.3},
+    "ladder": {"config": 2, "gemm_sha256": _GEMM_SHA, "fetch_kib": 2875681.3, "fetch_scale": 1048576.0 / 524303.3,
+               "write_kib": 130211.0, "write_scale": 1048576.0 / 1048576.3},
 }
 
 
