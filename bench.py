@@ -34,9 +34,10 @@ HBM_PEAK = 8000.0                       # GB/s
 
 # HBM bytes per launch of the dominant FP64 GEMMs on the o=20, v=150 canonical workload, from
 # two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; profiles/gemm_fp64_config2_traffic.md), scaled by
-# what the counter reads for a 1 GiB + 1 GiB device copy.  Valid only for the GEMM source
-# they were taken on: reported as null once that source changes (or before a measurement).
-_GEMM_SHA = "5162c6f377ec23cc1623fd14603858747fc909f816f131c9288f960950e7d773"
+# what the counter reads for a 1 GiB + 1 GiB device copy.  Valid only for the dense GEMM kernel
+# and launch code they were taken on (the marked region of gemm.hip, by hash): reported as null
+# once that code changes.
+_GEMM_SHA = "7f0ba202620fb461f47a1224df63e9f2906f95f683fde2523dfa5fe4cf870b04"
 KERNEL_TRAFFIC = {
     "ring": {"config": 2, "gemm_sha256": _GEMM_SHA, "fetch_kib": 6831362.8, "fetch_scale": 1048576.0 / 524303.3,
              "write_kib": 441051.1, "write_scale": 1048576.0 / 1048576.3},
@@ -45,15 +46,23 @@ KERNEL_TRAFFIC = {
 }
 
 
-def kernel_traffic(name, config, pno_only):
+def gemm_kernel_sha():
+    """sha256 of the dense GEMM kernel and its launch code (the marked region of gemm.hip)."""
     import hashlib
+    src = os.path.join(ROOT, "paper_1802_06738_amd", "csrc", "gemm.hip")
+    with open(src) as fh:
+        text = fh.read()
+    a = text.index("// ==== dense GEMM kernel and its launch: begin")
+    b = text.index("// ==== dense GEMM kernel and its launch: end")
+    return hashlib.sha256(text[text.index("\n", a) + 1:b].encode()).hexdigest()
+
+
+def kernel_traffic(name, config, pno_only):
     t = KERNEL_TRAFFIC.get(name)
     if t is None or config != t["config"] or pno_only:
         return None
-    src = os.path.join(ROOT, "paper_1802_06738_amd", "csrc", "gemm.hip")
-    with open(src, "rb") as fh:
-        if hashlib.sha256(fh.read()).hexdigest() != t["gemm_sha256"]:
-            return None
+    if gemm_kernel_sha() != t["gemm_sha256"]:
+        return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 

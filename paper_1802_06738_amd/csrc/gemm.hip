@@ -71,6 +71,7 @@ struct KArgs {
 constexpr int NT = 256;
 
 
+// ==== dense GEMM kernel and its launch: begin
 template <typename T, int BM, int BN, int BK, bool TA, bool TB, int TAG>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void gemm_kernel(KArgs<T> g) {
   constexpr int PADA = (sizeof(T) == 8) ? 1 : 2;
@@ -423,6 +424,8 @@ void launch_tile(const GemmDesc<T>& d, hipStream_t s, int split_mode = 0) {
   }
 }
 
+// ==== dense GEMM kernel and its launch: end
+
 // ---------------------------------------------------------------- tile selection and tuning
 // A tuning table (filled by the project's autotuner, paper_1802_06738_amd/autotune.py)
 // maps a GEMM shape key {element size, ta, tb, reduce, M, N, K, batch} to a variant
@@ -486,9 +489,12 @@ void gemm_impl(const GemmDesc<T>& d, hipStream_t s) {
 // ---------------------------------------------------------------- grouped (64 x 64 tiles, FP64)
 constexpr int GBM = 64, GBN = 64, GBK = 16;
 
+// Persistent: a fixed grid of workgroups walks the tiles of all groups (tile t, t + grid,
+// ...); every workgroup leaves once it is past the last tile.
 template <bool TA, bool TB>
 __global__ __launch_bounds__(NT) void gemm_grouped_kernel(const GroupDesc* __restrict__ groups, int ngroups,
-                                                          double alpha, const double* __restrict__ Abase,
+                                                          int64_t total_tiles, double alpha,
+                                                          const double* __restrict__ Abase,
                                                           const double* __restrict__ Bbase, double beta,
                                                           double* __restrict__ Cbase) {
   typedef double T;
@@ -496,80 +502,81 @@ __global__ __launch_bounds__(NT) void gemm_grouped_kernel(const GroupDesc* __res
   __shared__ T Bs[GBK][GBN + 1];
   constexpr int WM = GBM / 2, WN = GBN / 2, TM = WM / 16, TN = WN / 16;
   constexpr int LA = GBM * GBK / NT, LB = GBN * GBK / NT;
-  const int64_t tile = blockIdx.x;
-  int lo = 0, hi = ngroups - 1;
-  while (lo < hi) {  // last group with tile_start <= tile
-    const int mid = (lo + hi + 1) / 2;
-    if (groups[mid].tile_start <= tile) lo = mid; else hi = mid - 1;
-  }
-  const GroupDesc g = groups[lo];
-  const int64_t local = tile - g.tile_start;
-  const int64_t m0 = (local % g.tiles_m) * GBM, n0 = (local / g.tiles_m) * GBN;
-  const T* A = Abase + g.offA;
-  const T* B = Bbase + g.offB;
-  T* C = Cbase + g.offC;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1, lr = lane & 15, lk = lane >> 4;
-  typedef Mfma<T>::v4 v4;
-  v4 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = v4{0, 0, 0, 0};
-  const int64_t kt = (g.K + GBK - 1) / GBK;
-  for (int64_t it = 0; it < kt; ++it) {
-    const int64_t k0 = it * GBK;
-#pragma unroll
-    for (int q = 0; q < LA; ++q) {
-      const int e = tid + q * NT;
-      int mm, kk;
-      if (TA) { kk = e / GBM; mm = e % GBM; } else { mm = e / GBK; kk = e % GBK; }
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      T val = 0;
-      if (gm < g.M && gk < g.K) val = TA ? A[gk * g.lda + gm] : A[gm * g.lda + gk];
-      As[kk][mm] = val;
+  for (int64_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
+    int lo = 0, hi = ngroups - 1;
+    while (lo < hi) {  // last group with tile_start <= tile
+      const int mid = (lo + hi + 1) / 2;
+      if (groups[mid].tile_start <= tile) lo = mid; else hi = mid - 1;
     }
-#pragma unroll
-    for (int q = 0; q < LB; ++q) {
-      const int e = tid + q * NT;
-      int nn, kk;
-      if (TB) { nn = e / GBK; kk = e % GBK; } else { kk = e / GBN; nn = e % GBN; }
-      const int64_t gn = n0 + nn, gk = k0 + kk;
-      T val = 0;
-      if (gn < g.N && gk < g.K) val = TB ? B[gn * g.ldb + gk] : B[gk * g.ldb + gn];
-      Bs[kk][nn] = val;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GBK; kk += 4) {
-      T av[TM], bv[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) av[i] = As[kk + lk][wm * WM + i * 16 + lr];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) bv[j] = Bs[kk + lk][wn * WN + j * 16 + lr];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mac(av[i], bv[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int64_t gn = n0 + wn * WN + j * 16 + lr;
-      if (gn >= g.N) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t gm = m0 + wm * WM + i * 16 + Mfma<T>::row(lk, r);
-        if (gm >= g.M) continue;
-        T* c = C + gm * g.ldc + gn;
-        T val = alpha * acc[i][j][r];
-        if (beta != 0.0) val += beta * (*c);
-        *c = val;
+    const GroupDesc g = groups[lo];
+    const int64_t local = tile - g.tile_start;
+    const int64_t m0 = (local % g.tiles_m) * GBM, n0 = (local / g.tiles_m) * GBN;
+    const T* A = Abase + g.offA;
+    const T* B = Bbase + g.offB;
+    T* C = Cbase + g.offC;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1, lr = lane & 15, lk = lane >> 4;
+    typedef Mfma<T>::v4 v4;
+    v4 acc[TM][TN];
+  #pragma unroll
+    for (int i = 0; i < TM; ++i)
+  #pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = v4{0, 0, 0, 0};
+    const int64_t kt = (g.K + GBK - 1) / GBK;
+    for (int64_t it = 0; it < kt; ++it) {
+      const int64_t k0 = it * GBK;
+  #pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        const int e = tid + q * NT;
+        int mm, kk;
+        if (TA) { kk = e / GBM; mm = e % GBM; } else { mm = e / GBK; kk = e % GBK; }
+        const int64_t gm = m0 + mm, gk = k0 + kk;
+        T val = 0;
+        if (gm < g.M && gk < g.K) val = TA ? A[gk * g.lda + gm] : A[gm * g.lda + gk];
+        As[kk][mm] = val;
       }
+  #pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        const int e = tid + q * NT;
+        int nn, kk;
+        if (TB) { nn = e / GBK; kk = e % GBK; } else { kk = e / GBN; nn = e % GBN; }
+        const int64_t gn = n0 + nn, gk = k0 + kk;
+        T val = 0;
+        if (gn < g.N && gk < g.K) val = TB ? B[gn * g.ldb + gk] : B[gk * g.ldb + gn];
+        Bs[kk][nn] = val;
+      }
+      __syncthreads();
+  #pragma unroll
+      for (int kk = 0; kk < GBK; kk += 4) {
+        T av[TM], bv[TN];
+  #pragma unroll
+        for (int i = 0; i < TM; ++i) av[i] = As[kk + lk][wm * WM + i * 16 + lr];
+  #pragma unroll
+        for (int j = 0; j < TN; ++j) bv[j] = Bs[kk + lk][wn * WN + j * 16 + lr];
+  #pragma unroll
+        for (int i = 0; i < TM; ++i)
+  #pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mac(av[i], bv[j], acc[i][j]);
+      }
+      __syncthreads();
     }
+  #pragma unroll
+    for (int i = 0; i < TM; ++i)
+  #pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t gn = n0 + wn * WN + j * 16 + lr;
+        if (gn >= g.N) continue;
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gm = m0 + wm * WM + i * 16 + Mfma<T>::row(lk, r);
+          if (gm >= g.M) continue;
+          T* c = C + gm * g.ldc + gn;
+          T val = alpha * acc[i][j][r];
+          if (beta != 0.0) val += beta * (*c);
+          *c = val;
+        }
+      }
+  }
 }
 
 }  // namespace
@@ -600,15 +607,17 @@ void gemm_grouped(const GroupTable& t, double alpha, const double* A, const doub
                   hipStream_t s) {
   if (t.n == 0 || t.total_tiles == 0) return;
   PNO_CHECK(t.total_tiles < (1ll << 31), PNOEOM_EINVAL, "grouped gemm: too many tiles");
-  dim3 grid((unsigned)t.total_tiles);
+  // eight workgroups per CU at most; each walks its share of the tiles
+  dim3 grid((unsigned)std::min<int64_t>(t.total_tiles, 8 * 256));
+  const int64_t nt = t.total_tiles;
   if (!t.ta && !t.tb)
-    hipLaunchKernelGGL((gemm_grouped_kernel<false, false>), grid, dim3(NT), 0, s, t.d, t.n, alpha, A, B, beta, C);
+    hipLaunchKernelGGL((gemm_grouped_kernel<false, false>), grid, dim3(NT), 0, s, t.d, t.n, nt, alpha, A, B, beta, C);
   else if (t.ta && !t.tb)
-    hipLaunchKernelGGL((gemm_grouped_kernel<true, false>), grid, dim3(NT), 0, s, t.d, t.n, alpha, A, B, beta, C);
+    hipLaunchKernelGGL((gemm_grouped_kernel<true, false>), grid, dim3(NT), 0, s, t.d, t.n, nt, alpha, A, B, beta, C);
   else if (!t.ta && t.tb)
-    hipLaunchKernelGGL((gemm_grouped_kernel<false, true>), grid, dim3(NT), 0, s, t.d, t.n, alpha, A, B, beta, C);
+    hipLaunchKernelGGL((gemm_grouped_kernel<false, true>), grid, dim3(NT), 0, s, t.d, t.n, nt, alpha, A, B, beta, C);
   else
-    hipLaunchKernelGGL((gemm_grouped_kernel<true, true>), grid, dim3(NT), 0, s, t.d, t.n, alpha, A, B, beta, C);
+    hipLaunchKernelGGL((gemm_grouped_kernel<true, true>), grid, dim3(NT), 0, s, t.d, t.n, nt, alpha, A, B, beta, C);
   PNO_HIP(hipGetLastError());
 }
 
