@@ -235,7 +235,8 @@ struct DavidsonResult {
 DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt);
 
 // host eigen-solver (eig.cpp); returns 0 or a negative status
-int host_eig(int n, const double* a, double* wr, double* wi, double* vr);
+// vectors of the first nvec eigenvalues in sorted order (nvec < 0: all); the others are zero
+int host_eig(int n, const double* a, double* wr, double* wi, double* vr, int nvec = -1);
 int host_syev(int n, const double* a, double* w, double* v);
 void probe_peaks(hipStream_t s, double* fp64_tflops, double* fp32_tflops, double* bf16_tflops, double* copy_gbs);
 int host_syev_batched(int nmat, const int* nsz, int ld, double* A, double* ev, double* Vt, int nthreads);

@@ -342,7 +342,7 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
     std::vector<double> Gm((size_t)m * m), wr(m), wi(m), vr((size_t)m * m);
     for (int i = 0; i < m; ++i)
       for (int j = 0; j < m; ++j) Gm[(size_t)i * m + j] = G[(size_t)i * maxs + j];
-    const int st = host_eig(m, Gm.data(), wr.data(), wi.data(), vr.data());
+    const int st = host_eig(m, Gm.data(), wr.data(), wi.data(), vr.data(), std::min(nroots, m));
     PNO_CHECK(st == PNOEOM_OK, PNOEOM_ENOTCONV, "subspace eigenproblem did not converge");
     std::vector<double> theta(nroots), Y((size_t)m * nroots);
     for (int k = 0; k < nroots; ++k) {

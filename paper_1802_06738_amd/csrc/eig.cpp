@@ -4,8 +4,9 @@
 // 2. Francis implicit double-shift QR iteration on the active window with
 //    deflation of negligible subdiagonals (eigenvalues only).
 // 3. Right eigenvectors by inverse iteration on the original matrix (complex
-//    arithmetic for complex pairs), re-orthogonalised against the vectors of
-//    numerically coincident eigenvalues.
+//    arithmetic for complex pairs; one LU factorisation per eigenvalue, three
+//    solves), re-orthogonalised against the vectors of numerically coincident
+//    eigenvalues; only for the first nvec eigenvalues in sorted order when asked.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -172,11 +173,11 @@ bool francis(int n, std::vector<double>& H, double* wr, double* wi) {
   return true;
 }
 
-// Solve M x = b in place with LU and partial pivoting (complex); tiny pivots are
-// replaced by tiny * scale so that a (nearly) singular shifted matrix still yields
-// the inverse-iteration direction.
-void lu_solve(int n, std::vector<cd> M, std::vector<cd>& b, double tiny) {
-  std::vector<int> piv(n);
+// LU factorisation with partial pivoting (complex, in place); tiny pivots are replaced
+// by tiny * scale so that a (nearly) singular shifted matrix still yields the
+// inverse-iteration direction.
+void lu_factor(int n, std::vector<cd>& M, std::vector<int>& piv, double tiny) {
+  piv.resize(n);
   for (int k = 0; k < n; ++k) {
     int pr = k;
     double best = std::abs(M[(size_t)k * n + k]);
@@ -184,18 +185,25 @@ void lu_solve(int n, std::vector<cd> M, std::vector<cd>& b, double tiny) {
       const double a = std::abs(M[(size_t)i * n + k]);
       if (a > best) { best = a; pr = i; }
     }
-    if (pr != k) {
+    piv[k] = pr;
+    if (pr != k)
       for (int j = 0; j < n; ++j) std::swap(M[(size_t)k * n + j], M[(size_t)pr * n + j]);
-      std::swap(b[k], b[pr]);
-    }
     if (std::abs(M[(size_t)k * n + k]) < tiny) M[(size_t)k * n + k] = tiny;
     const cd d = M[(size_t)k * n + k];
     for (int i = k + 1; i < n; ++i) {
-      const cd f = M[(size_t)i * n + k] / d;
+      cd& f = M[(size_t)i * n + k];
+      f /= d;
       if (f == cd(0.0)) continue;
       for (int j = k + 1; j < n; ++j) M[(size_t)i * n + j] -= f * M[(size_t)k * n + j];
-      b[i] -= f * b[k];
     }
+  }
+}
+
+// solve with the factors of lu_factor (b overwritten by x)
+void lu_solve(int n, const std::vector<cd>& M, const std::vector<int>& piv, std::vector<cd>& b) {
+  for (int k = 0; k < n; ++k) {
+    if (piv[k] != k) std::swap(b[k], b[piv[k]]);
+    for (int i = k + 1; i < n; ++i) b[i] -= M[(size_t)i * n + k] * b[k];
   }
   for (int i = n - 1; i >= 0; --i) {
     cd s = b[i];
@@ -206,8 +214,9 @@ void lu_solve(int n, std::vector<cd> M, std::vector<cd>& b, double tiny) {
 
 }  // namespace
 
-int host_eig(int n, const double* a, double* wr, double* wi, double* vr) {
+int host_eig(int n, const double* a, double* wr, double* wi, double* vr, int nvec) {
   if (n < 1 || !a || !wr || !wi) return PNOEOM_EINVAL;
+  if (nvec < 0 || nvec > n) nvec = n;
   std::vector<double> H(a, a + (size_t)n * n);
   hessenberg(n, H);
   std::vector<double> er(n), ei(n);
@@ -229,15 +238,18 @@ int host_eig(int n, const double* a, double* wr, double* wi, double* vr) {
   const double tiny = anorm * 1e-14;
   std::vector<std::vector<double>> done;
   std::vector<double> done_lam;
-  for (int k = 0; k < n; ++k) {
+  std::fill(vr, vr + (size_t)n * n, 0.0);
+  std::vector<cd> M((size_t)n * n);
+  std::vector<int> piv;
+  for (int k = 0; k < nvec; ++k) {
     const cd lam(wr[k], wi[k]);
-    std::vector<cd> M((size_t)n * n);
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) M[(size_t)i * n + j] = cd(a[(size_t)i * n + j], 0.0) - (i == j ? lam : cd(0.0));
+    lu_factor(n, M, piv, tiny);
     std::vector<cd> x(n);
     for (int i = 0; i < n; ++i) x[i] = cd(1.0 + 0.01 * ((i * 7919) % 101), 0.0);
     for (int it = 0; it < 3; ++it) {
-      lu_solve(n, M, x, tiny);
+      lu_solve(n, M, piv, x);
       // keep away from vectors already found for (numerically) the same eigenvalue
       if (wi[k] == 0.0) {
         for (size_t q = 0; q < done.size(); ++q) {
