@@ -209,10 +209,19 @@ typedef struct {
   int nextra;          /* further Ritz pairs tracked and kept at collapse (need not converge) */
   double mixed_tol_e;  /* refine_fp64: bounds of the FP32/BF16 phase before the FP64 refinement; */
   double mixed_tol_r;  /*   <= 0 selects tol_e / tol_r (the final bounds are always tol_e, tol_r) */
+  /* Checkpoint / resume (host files).  A checkpoint holds the Ritz values and Ritz vectors
+   * of all tracked roots after an iteration, in the layout of the space (canonical
+   * [r1 | r2] or compressed PNO vectors), plus the phase (main run or FP64 refinement). */
+  int ckpt_every;          /* > 0: write ckpt_path every ckpt_every iterations (counted over both phases) */
+  int abort_after_iter;    /* > 0: after that iteration write ckpt_path (if set) and return PNOEOM_EABORTED */
+  const char* ckpt_path;   /* checkpoint file, or NULL */
+  const char* resume_path; /* NULL, or a checkpoint of the same space and vector length: its Ritz
+                              vectors replace the CIS guess (a refinement-phase checkpoint resumes
+                              in the FP64 refinement) */
 } pnoeom_davidson_opts;
 
 /* Fill opts with the defaults (canonical, FP64, tol_e 1e-8, tol_r 1e-5, max_sub 60,
- * max_iter 200, nextra 0, mixed_tol_e = mixed_tol_r = 0). */
+ * max_iter 200, nextra 0, mixed_tol_e = mixed_tol_r = 0, no checkpoints, no resume). */
 void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts);
 
 /* Lowest-real-part EOM-CCSD roots by the Davidson method with the PNO
@@ -223,8 +232,10 @@ void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts);
  *   iters_out   : host, iterations used, or NULL
  *   nsigma_out  : host, number of sigma vectors evaluated, or NULL
  * Requires build_df (and build_sapno for PNO).
- * Errors: ESTATE, EINVAL, ENOMEM, EHIP, ENOTCONV (omega_out holds the last Ritz
- * values), ECOMPLEX (converged; real parts returned). */
+ * Errors: ESTATE, EINVAL (also an unreadable or mismatched resume file), ENOMEM, EHIP,
+ * ENOTCONV (omega_out holds the last Ritz values), ECOMPLEX (converged; real parts
+ * returned), EABORTED (abort_after_iter reached; omega_out holds that iteration's Ritz
+ * values and the checkpoint, if asked for, is written). */
 int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opts, double* omega_out,
                     double* resnorm_out, int* iters_out, int* nsigma_out);
 

@@ -309,12 +309,17 @@ void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts) {
   opts->nextra = 0;
   opts->mixed_tol_e = 0.0;
   opts->mixed_tol_r = 0.0;
+  opts->ckpt_every = 0;
+  opts->abort_after_iter = 0;
+  opts->ckpt_path = nullptr;
+  opts->resume_path = nullptr;
 }
 
 int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opts, double* omega_out,
                     double* resnorm_out, int* iters_out, int* nsigma_out) {
   int complex_pair = 0;
   int converged = 1;
+  int aborted = 0;
   int st = guarded(ctx, [&](pnoeom::Context& c) {
     PNO_CHECK(opts && omega_out, PNOEOM_EINVAL, "davidson: opts and omega_out are required");
     Timer t(c);
@@ -328,9 +333,14 @@ int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opt
     if (nsigma_out) *nsigma_out = r.nsigma;
     complex_pair = r.complex_pair;
     converged = r.converged;
-    if (!converged) c.err = "Davidson did not converge within max_iter";
+    aborted = r.aborted;
+    if (aborted)
+      c.err = "Davidson stopped at abort_after_iter";
+    else if (!converged)
+      c.err = "Davidson did not converge within max_iter";
   });
   if (st != PNOEOM_OK) return st;
+  if (aborted) return PNOEOM_EABORTED;
   if (!converged) return PNOEOM_ENOTCONV;
   if (complex_pair) return PNOEOM_ECOMPLEX;
   return PNOEOM_OK;

@@ -231,6 +231,7 @@ struct DavidsonResult {
   int nsigma = 0;
   bool converged = false;
   bool complex_pair = false;
+  bool aborted = false;   // stopped at abort_after_iter
 };
 DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt);
 

@@ -267,10 +267,63 @@ std::vector<double> orth_cols(int m, int k, const std::vector<double>& Y) {
   return Q;
 }
 
+// ----------------------------------------------------------------------------- checkpoints
+// File: "PNOEOMCK", int32 version 1, int64 N, int32 nvec, space, precision, phase, then
+// double theta[nvec] and the vectors [nvec][N] (host byte order).
+constexpr char kCkptMagic[8] = {'P', 'N', 'O', 'E', 'O', 'M', 'C', 'K'};
+
+void write_checkpoint(hipStream_t s, const char* path, int64_t N, int nvec, int space, int precision, int phase,
+                      const std::vector<double>& theta, const double* dX) {
+  std::vector<double> h((size_t)nvec * N);
+  PNO_HIP(hipMemcpyAsync(h.data(), dX, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  PNO_HIP(hipStreamSynchronize(s));
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "wb");
+  PNO_CHECK(f != nullptr, PNOEOM_EINVAL, std::string("checkpoint: cannot write ") + tmp);
+  const int32_t hdr[5] = {1, nvec, space, precision, phase};
+  bool ok = fwrite(kCkptMagic, 1, 8, f) == 8 && fwrite(&hdr[0], 4, 1, f) == 1 && fwrite(&N, 8, 1, f) == 1 &&
+            fwrite(&hdr[1], 4, 4, f) == 4 && fwrite(theta.data(), 8, nvec, f) == (size_t)nvec &&
+            fwrite(h.data(), 8, h.size(), f) == h.size();
+  ok = (fclose(f) == 0) && ok;
+  PNO_CHECK(ok, PNOEOM_EINVAL, std::string("checkpoint: write failed for ") + tmp);
+  PNO_CHECK(std::rename(tmp.c_str(), path) == 0, PNOEOM_EINVAL, std::string("checkpoint: cannot rename to ") + path);
+}
+
+struct Checkpoint {
+  int64_t N = 0;
+  int nvec = 0, space = 0, precision = 0, phase = 0;
+  std::vector<double> theta, x;
+};
+
+Checkpoint read_checkpoint(const char* path) {
+  Checkpoint k;
+  FILE* f = fopen(path, "rb");
+  PNO_CHECK(f != nullptr, PNOEOM_EINVAL, std::string("resume: cannot open ") + path);
+  char magic[8];
+  int32_t ver = 0, h4[4];
+  bool ok = fread(magic, 1, 8, f) == 8 && std::equal(magic, magic + 8, kCkptMagic) && fread(&ver, 4, 1, f) == 1 &&
+            ver == 1 && fread(&k.N, 8, 1, f) == 1 && fread(h4, 4, 4, f) == 4;
+  if (ok) {
+    k.nvec = h4[0]; k.space = h4[1]; k.precision = h4[2]; k.phase = h4[3];
+    ok = k.N > 0 && k.nvec > 0 && k.nvec < (1 << 20) && k.N < (int64_t(1) << 40);
+  }
+  if (ok) {
+    k.theta.resize(k.nvec);
+    k.x.resize((size_t)k.nvec * k.N);
+    ok = fread(k.theta.data(), 8, k.nvec, f) == (size_t)k.nvec && fread(k.x.data(), 8, k.x.size(), f) == k.x.size();
+  }
+  fclose(f);
+  PNO_CHECK(ok, PNOEOM_EINVAL, std::string("resume: not a readable checkpoint: ") + path);
+  return k;
+}
+
 // nroots roots must converge; nextra further Ritz pairs are tracked (and kept at
-// collapse) to speed up convergence of the highest target root.
+// collapse) to speed up convergence of the highest target root.  Iterations are
+// numbered from it_base + 1 for checkpoints and aborts (phase 0: main run, 1: FP64
+// refinement).
 DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double* guess, int nguess,
-                            const pnoeom_davidson_opts& opt, const char* tag, double* xout, int nextra = 0) {
+                            const pnoeom_davidson_opts& opt, const char* tag, double* xout, int nextra = 0,
+                            int it_base = 0, int phase = 0) {
   hipStream_t s = c.stream;
   const int64_t N = op.N;
   const int nroots = ntarget + nextra;
@@ -388,6 +441,15 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
       res.converged = true;
       if (xout)
         PNO_HIP(hipMemcpyAsync(xout, X, (int64_t)ntarget * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PNO_HIP(hipStreamSynchronize(s));
+      return res;
+    }
+    const int itg = it_base + it;
+    const bool abort_now = opt.abort_after_iter > 0 && itg >= opt.abort_after_iter;
+    if (opt.ckpt_path && (abort_now || (opt.ckpt_every > 0 && itg % opt.ckpt_every == 0)))
+      write_checkpoint(s, opt.ckpt_path, N, nroots, opt.space, opt.precision, phase, theta, X);
+    if (abort_now) {
+      res.aborted = true;
       PNO_HIP(hipStreamSynchronize(s));
       return res;
     }
@@ -664,6 +726,17 @@ DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt)
     if (opt.space == PNOEOM_CANONICAL)
       for (int q = 0; q < nv; ++q) symmetrize_r2(s, o, v, S + (int64_t)q * op.N + ov);
   };
+  // resume: the Ritz vectors of a checkpoint replace the CIS guess
+  int phase0 = 0, nguess = nk;
+  if (opt.resume_path) {
+    const Checkpoint k = read_checkpoint(opt.resume_path);
+    PNO_CHECK(k.N == op.N && k.space == opt.space, PNOEOM_EINVAL,
+              "resume: the checkpoint is of another space or vector length");
+    nguess = std::min(k.nvec, nk);
+    PNO_HIP(hipMemcpyAsync(guess, k.x.data(), (size_t)nguess * op.N * sizeof(double), hipMemcpyHostToDevice, s));
+    PNO_HIP(hipStreamSynchronize(s));
+    phase0 = k.phase;
+  }
   DBuf<double> xr;
   xr.alloc((int64_t)nroots * op.N);
   // a mixed phase that is refined afterwards stops at its own (looser) bounds
@@ -672,12 +745,18 @@ DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt)
     if (opt.mixed_tol_e > 0) mopt.tol_e = opt.mixed_tol_e;
     if (opt.mixed_tol_r > 0) mopt.tol_r = opt.mixed_tol_r;
   }
-  DavidsonResult r = run_davidson(c, op, nroots, guess, nk, mopt,
+  const bool refine = prec != PNOEOM_FP64 && opt.refine_fp64;
+  if (refine && phase0 == 1) {
+    // a checkpoint of the refinement phase: continue there
+    prec = PNOEOM_FP64;
+    return run_davidson(c, op, nroots, guess, std::min(nguess, nroots), opt, "eom-fp64-refine", nullptr, 0, 0, 1);
+  }
+  DavidsonResult r = run_davidson(c, op, nroots, guess, nguess, mopt,
                                   prec == PNOEOM_FP32 ? "eom-fp32" : prec == PNOEOM_BF16 ? "eom-bf16" : "eom", xr,
                                   opt.nextra);
-  if (prec != PNOEOM_FP64 && opt.refine_fp64 && r.converged) {
+  if (refine && r.converged) {
     prec = PNOEOM_FP64;
-    DavidsonResult r2 = run_davidson(c, op, nroots, xr, nroots, opt, "eom-fp64-refine", nullptr, 0);
+    DavidsonResult r2 = run_davidson(c, op, nroots, xr, nroots, opt, "eom-fp64-refine", nullptr, 0, r.iters, 1);
     r2.iters += r.iters;
     r2.nsigma += r.nsigma;
     r = r2;
