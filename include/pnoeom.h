@@ -218,10 +218,13 @@ typedef struct {
   const char* resume_path; /* NULL, or a checkpoint of the same space and vector length: its Ritz
                               vectors replace the CIS guess (a refinement-phase checkpoint resumes
                               in the FP64 refinement) */
+  const char* log_path;    /* NULL, or a file to which one JSON line per iteration is appended:
+                              phase, iteration, subspace size, sigma count, Ritz values, residual
+                              norms, changes of the Ritz values, seconds since the call began */
 } pnoeom_davidson_opts;
 
 /* Fill opts with the defaults (canonical, FP64, tol_e 1e-8, tol_r 1e-5, max_sub 60,
- * max_iter 200, nextra 0, mixed_tol_e = mixed_tol_r = 0, no checkpoints, no resume). */
+ * max_iter 200, nextra 0, mixed_tol_e = mixed_tol_r = 0, no checkpoints, no resume, no log). */
 void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts);
 
 /* Lowest-real-part EOM-CCSD roots by the Davidson method with the PNO

@@ -313,6 +313,7 @@ void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts) {
   opts->abort_after_iter = 0;
   opts->ckpt_path = nullptr;
   opts->resume_path = nullptr;
+  opts->log_path = nullptr;
 }
 
 int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opts, double* omega_out,

@@ -9,6 +9,7 @@
 // OSV/PNO basis) -> diagonal preconditioner -> back to the vector space.
 #include <algorithm>
 #include <cmath>
+#include <chrono>
 #include <cstdio>
 #include <functional>
 
@@ -325,6 +326,7 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
                             const pnoeom_davidson_opts& opt, const char* tag, double* xout, int nextra = 0,
                             int it_base = 0, int phase = 0) {
   hipStream_t s = c.stream;
+  const auto t_start = std::chrono::steady_clock::now();
   const int64_t N = op.N;
   const int nroots = ntarget + nextra;
   const int maxs = std::max(opt.max_sub, nroots + nguess);
@@ -431,6 +433,24 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
     }
     res.omega.assign(theta.begin(), theta.begin() + ntarget);
     res.resnorm.assign(rn.begin(), rn.begin() + ntarget);
+    if (opt.log_path) {
+      FILE* lf = fopen(opt.log_path, "a");
+      PNO_CHECK(lf != nullptr, PNOEOM_EINVAL, std::string("davidson: cannot append to ") + opt.log_path);
+      const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+      fprintf(lf, "{\"phase\": %d, \"it\": %d, \"m\": %d, \"nsigma\": %d, \"seconds\": %.6f", phase, it_base + it,
+              m, res.nsigma, secs);
+      const char* keys[3] = {"omega", "resnorm", "domega"};
+      for (int f = 0; f < 3; ++f) {
+        fprintf(lf, ", \"%s\": [", keys[f]);
+        for (int k = 0; k < ntarget; ++k) {
+          const double x = f == 0 ? theta[k] : f == 1 ? rn[k] : (have_old ? theta[k] - theta_old[k] : 0.0);
+          fprintf(lf, "%s%.17g", k ? ", " : "", x);
+        }
+        fprintf(lf, "]");
+      }
+      fprintf(lf, "}\n");
+      fclose(lf);
+    }
     if (opt.verbose) {
       fprintf(stderr, "[%s] it %3d m %3d", tag, it, m);
       for (int k = 0; k < ntarget; ++k) fprintf(stderr, " %.10f(%.1e)", theta[k], rn[k]);

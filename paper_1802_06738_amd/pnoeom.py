@@ -40,7 +40,7 @@ class DavidsonOpts(C.Structure):
                 ("max_sub", C.c_int), ("max_iter", C.c_int), ("refine_fp64", C.c_int), ("verbose", C.c_int),
                 ("nextra", C.c_int), ("mixed_tol_e", C.c_double), ("mixed_tol_r", C.c_double),
                 ("ckpt_every", C.c_int), ("abort_after_iter", C.c_int), ("ckpt_path", C.c_char_p),
-                ("resume_path", C.c_char_p)]
+                ("resume_path", C.c_char_p), ("log_path", C.c_char_p)]
 
 
 _LIB = None
@@ -250,7 +250,7 @@ class PnoEom:
 
     def davidson(self, nroots, space=CANONICAL, precision=FP64, tol_e=1e-8, tol_r=-1.0, max_sub=60,
                  max_iter=200, refine_fp64=False, verbose=False, nextra=0, mixed_tol_e=0.0, mixed_tol_r=0.0,
-                 ckpt_every=0, abort_after_iter=0, ckpt_path=None, resume_path=None):
+                 ckpt_every=0, abort_after_iter=0, ckpt_path=None, resume_path=None, log_path=None):
         opts = DavidsonOpts()
         self.lib.pnoeom_davidson_defaults(C.byref(opts))
         opts.space, opts.precision, opts.tol_e, opts.tol_r = space, precision, tol_e, tol_r
@@ -260,6 +260,7 @@ class PnoEom:
         opts.ckpt_every, opts.abort_after_iter = int(ckpt_every), int(abort_after_iter)
         opts.ckpt_path = os.fsencode(ckpt_path) if ckpt_path else None
         opts.resume_path = os.fsencode(resume_path) if resume_path else None
+        opts.log_path = os.fsencode(log_path) if log_path else None
         om = np.zeros(nroots)
         rn = np.zeros(nroots)
         it = C.c_int()

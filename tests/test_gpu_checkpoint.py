@@ -85,3 +85,18 @@ def test_resume_refuses_mismatched_or_broken_files(tmp_path):
     with pytest.raises(PnoEomError) as e:
         ctx.davidson(3, resume_path=str(tmp_path / "missing.ckpt"), **TOL)
     assert e.value.code == -1
+
+
+def test_iteration_log(tmp_path):
+    print("[davidson log]", flush=True)
+    import json
+    s = config_system(1)
+    ctx = _ctx(s)
+    log = tmp_path / "it.jsonl"
+    r = ctx.davidson(3, log_path=str(log), **TOL)
+    lines = [json.loads(x) for x in log.read_text().splitlines()]
+    assert len(lines) == r["iters"]
+    assert [x["it"] for x in lines] == list(range(1, r["iters"] + 1))
+    assert np.allclose(lines[-1]["omega"], r["omega"], atol=0, rtol=0)
+    assert all(len(x["resnorm"]) == 3 and x["m"] >= 3 for x in lines)
+    assert lines[-1]["resnorm"][0] <= 1e-8 and lines[-1]["nsigma"] == r["nsigma"]
