@@ -96,18 +96,31 @@ def davidson(sigma, basis, guess, o, v, nroots, tol_e=1e-8, tol_r=None, max_sub=
                         complex=had_complex)
         theta_old = theta
         new = []
-        for k in range(ntarget):
-            if conv[k]:
-                continue
-            c1, c2 = basis.precondition(*unpack(Rr[:, k], o, v), theta[k])
-            x = pack(*basis.project(c1, c2))
-            x = x / np.linalg.norm(x)
-            x = _orth_against(V + new, x)
-            nrm = np.linalg.norm(x)
-            if nrm < 1e-10:
-                continue
-            new.append(x / nrm)
+        # preconditioned residuals; if every one of them lies in span(V), the residuals
+        # themselves (orthogonal to V by the Galerkin condition V^T r = 0)
+        for precondition in (True, False):
+            for k in range(ntarget):
+                if conv[k]:
+                    continue
+                if precondition:
+                    c1, c2 = basis.precondition(*unpack(Rr[:, k], o, v), theta[k])
+                    x = pack(*basis.project(c1, c2))
+                else:
+                    x = Rr[:, k].copy()
+                x = x / np.linalg.norm(x)
+                x = _orth_against(V + new, x)
+                nrm = np.linalg.norm(x)
+                if nrm < 1e-10:
+                    continue
+                new.append(x / nrm)
+            if new:
+                break
         if not new:
+            # nothing outside span(V) is left: the Ritz values cannot change any more, so
+            # residuals within tol_r are final
+            if np.all(rn[:ntarget] <= tol_r):
+                return dict(omega=theta[:ntarget], resnorm=rn[:ntarget], iters=it, vectors=X[:, :ntarget],
+                            complex=had_complex)
             raise RuntimeError("Davidson stalled: no new directions")
         if len(V) + len(new) > max_sub:
             Q, _ = np.linalg.qr(Y)

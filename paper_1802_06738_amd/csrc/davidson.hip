@@ -478,68 +478,91 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
     // corrections: preconditioned residuals of the unconverged roots, normalised,
     // orthogonalised against V as a block (two classical Gram-Schmidt passes, each
     // reading V once), then among themselves; staged in X
-    int nc = 0;
-    for (int k = 0; k < nroots; ++k) {
-      if (conv[k]) continue;
-      double* xk = X + (int64_t)nc * N;
-      PNO_HIP(hipMemcpyAsync(xk, R + (int64_t)k * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-      op.precond(xk, theta[k]);
-      ++nc;
-    }
+    // When every preconditioned direction lies in span(V) (a preconditioner close to the
+    // exact operator maps r_k back onto the Ritz vector), the plain residuals are taken:
+    // the Galerkin condition V^T r_k = 0 makes them new directions whenever r_k != 0.
     int nnew = 0;
-    if (nc > 0) {
-      std::vector<double> cc((size_t)nc * nc);
-      dots(s, dw, X, nc, X, nc, N, cc.data());
-      for (int q = 0; q < nc; ++q) {
-        const double n0 = cc[(size_t)q * nc + q];
-        const double sc = n0 > 0.0 ? 1.0 / std::sqrt(n0) : 0.0;
-        hipLaunchKernelGGL(scale_kernel, dim3(g1(N)), dim3(256), 0, s, N, sc, X + (int64_t)q * N);
+    for (int attempt = 0; attempt < 2 && nnew == 0; ++attempt) {
+      int nc = 0;
+      for (int k = 0; k < nroots; ++k) {
+        if (conv[k]) continue;
+        double* xk = X + (int64_t)nc * N;
+        PNO_HIP(hipMemcpyAsync(xk, R + (int64_t)k * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (attempt == 0) op.precond(xk, theta[k]);
+        ++nc;
       }
-      std::vector<double> coef((size_t)m * nc);
-      for (int pass = 0; pass < 2; ++pass) {
-        dots(s, dw, V, m, X, nc, N, coef.data());  // coef[i][q] = V_i . X_q
-        PNO_HIP(hipMemcpyAsync(dcb, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        GemmDesc<double> d;
-        d.ta = true; d.M = nc; d.N = N; d.K = m; d.alpha = -1.0; d.beta = 1.0;
-        d.A = dcb; d.lda = nc; d.B = V; d.ldb = N; d.C = X; d.ldc = N;
-        gemm(d, s);
-      }
-      // orthonormal basis of the block itself: two Gram passes, each X <- T^T X with
-      // T = W_k diag(w_k^-1/2) from the eigenpairs (w_k, W_k) of the block's Gram
-      // matrix, directions with w_k < 1e-20 (norm below 1e-10 after the projection
-      // against V, the vectors having been unit before it) dropped.  Two dot-product
-      // sweeps and two GEMMs replace the vector-by-vector loop.
-      int nb = nc;
-      double* src = X;
-      double* dst = V + (int64_t)m * N;
-      for (int pass = 0; pass < 2 && nb > 0; ++pass) {
-        std::vector<double> gm((size_t)nb * nb), w(nb), W((size_t)nb * nb);
-        dots(s, dw, src, nb, src, nb, N, gm.data());
-        PNO_CHECK(host_syev(nb, gm.data(), w.data(), W.data()) == PNOEOM_OK, PNOEOM_ENOTCONV,
-                  "Davidson: block Gram eigenproblem did not converge");
-        std::vector<double> Tt;  // [kept][nb], row r = (W_k / sqrt(w_k))^T
-        for (int k = 0; k < nb; ++k) {
-          if (!(w[k] >= 1e-20)) continue;
-          const double sc = 1.0 / std::sqrt(w[k]);
-          for (int i = 0; i < nb; ++i) Tt.push_back(W[(size_t)i * nb + k] * sc);
+      if (nc > 0) {
+        std::vector<double> cc((size_t)nc * nc);
+        dots(s, dw, X, nc, X, nc, N, cc.data());
+        for (int q = 0; q < nc; ++q) {
+          const double n0 = cc[(size_t)q * nc + q];
+          const double sc = n0 > 0.0 ? 1.0 / std::sqrt(n0) : 0.0;
+          hipLaunchKernelGGL(scale_kernel, dim3(g1(N)), dim3(256), 0, s, N, sc, X + (int64_t)q * N);
         }
-        const int nk = (int)(Tt.size() / (size_t)std::max(nb, 1));
-        if (nk == 0) {
-          nb = 0;
-          break;
+        std::vector<double> coef((size_t)m * nc);
+        for (int pass = 0; pass < 2; ++pass) {
+          dots(s, dw, V, m, X, nc, N, coef.data());  // coef[i][q] = V_i . X_q
+          PNO_HIP(hipMemcpyAsync(dcb, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
+          GemmDesc<double> d;
+          d.ta = true; d.M = nc; d.N = N; d.K = m; d.alpha = -1.0; d.beta = 1.0;
+          d.A = dcb; d.lda = nc; d.B = V; d.ldb = N; d.C = X; d.ldc = N;
+          gemm(d, s);
         }
-        PNO_HIP(hipMemcpyAsync(dcb, Tt.data(), Tt.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        GemmDesc<double> d;
-        d.M = nk; d.N = N; d.K = nb; d.alpha = 1.0; d.beta = 0.0;
-        d.A = dcb; d.lda = nb; d.B = src; d.ldb = N; d.C = dst; d.ldc = N;
-        gemm(d, s);
-        nb = nk;
-        std::swap(src, dst);
+        // orthonormal basis of the block itself: two Gram passes, each X <- T^T X with
+        // T = W_k diag(w_k^-1/2) from the eigenpairs (w_k, W_k) of the block's Gram
+        // matrix, directions with w_k < 1e-20 (norm below 1e-10 after the projection
+        // against V, the vectors having been unit before it) dropped.  Two dot-product
+        // sweeps and two GEMMs replace the vector-by-vector loop.
+        int nb = nc;
+        double* src = X;
+        double* dst = V + (int64_t)m * N;
+        for (int pass = 0; pass < 2 && nb > 0; ++pass) {
+          std::vector<double> gm((size_t)nb * nb), w(nb), W((size_t)nb * nb);
+          dots(s, dw, src, nb, src, nb, N, gm.data());
+          PNO_CHECK(host_syev(nb, gm.data(), w.data(), W.data()) == PNOEOM_OK, PNOEOM_ENOTCONV,
+                    "Davidson: block Gram eigenproblem did not converge");
+          std::vector<double> Tt;  // [kept][nb], row r = (W_k / sqrt(w_k))^T
+          for (int k = 0; k < nb; ++k) {
+            if (!(w[k] >= 1e-20)) continue;
+            const double sc = 1.0 / std::sqrt(w[k]);
+            for (int i = 0; i < nb; ++i) Tt.push_back(W[(size_t)i * nb + k] * sc);
+          }
+          const int nk = (int)(Tt.size() / (size_t)std::max(nb, 1));
+          if (nk == 0) {
+            nb = 0;
+            break;
+          }
+          PNO_HIP(hipMemcpyAsync(dcb, Tt.data(), Tt.size() * sizeof(double), hipMemcpyHostToDevice, s));
+          GemmDesc<double> d;
+          d.M = nk; d.N = N; d.K = nb; d.alpha = 1.0; d.beta = 0.0;
+          d.A = dcb; d.lda = nb; d.B = src; d.ldb = N; d.C = dst; d.ldc = N;
+          gemm(d, s);
+          nb = nk;
+          std::swap(src, dst);
+        }
+        // after an even number of passes the block is back in X: move it into V
+        if (nb > 0 && src != V + (int64_t)m * N)
+          PNO_HIP(hipMemcpyAsync(V + (int64_t)m * N, src, (int64_t)nb * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        nnew = nb;
       }
-      // after an even number of passes the block is back in X: move it into V
-      if (nb > 0 && src != V + (int64_t)m * N)
-        PNO_HIP(hipMemcpyAsync(V + (int64_t)m * N, src, (int64_t)nb * N * sizeof(double), hipMemcpyDeviceToDevice, s));
-      nnew = nb;
+    }
+    if (nnew == 0) {
+      // no direction outside span(V) is left (e.g. V spans the whole space): the Ritz values
+      // cannot change any more, so residuals within tol_r are final
+      bool small = true;
+      for (int k = 0; k < ntarget; ++k) small = small && rn[k] <= tol_r;
+      if (small) {
+        res.converged = true;
+        if (xout) {  // X held the corrections: the Ritz vectors again, from V and Y
+          GemmDesc<double> d;
+          d.ta = true; d.M = ntarget; d.N = N; d.K = m;  // xout holds the ntarget roots only
+          d.A = dY; d.lda = nroots; d.B = V; d.ldb = N; d.C = xout; d.ldc = N;
+          PNO_HIP(hipMemcpyAsync(dY, Y.data(), Y.size() * sizeof(double), hipMemcpyHostToDevice, s));
+          gemm(d, s);
+        }
+        PNO_HIP(hipStreamSynchronize(s));
+        return res;
+      }
     }
     PNO_CHECK(nnew > 0, PNOEOM_ENOTCONV, "Davidson stalled: no new directions");
     if (m + nnew > maxs) {

@@ -376,3 +376,15 @@ def test_c1_davidson_matches_stored_dense_eig():
     guess = [(b[k], np.zeros((o, o, v, v))) for k in range(3)]
     res = davidson(so.sigma, CanonicalBasis(s.eps, o), guess, o, v, 3, tol_e=1e-11, tol_r=1e-8)
     assert np.max(np.abs(res["omega"] - np.array(gold["dense_eig"][:3]))) < 1e-10
+
+
+def test_davidson_exhausted_subspace_equals_dense():
+    """A space smaller than the subspace limit: once V spans it the Ritz pairs are exact."""
+    o, v = 1, 3
+    s = make_system(o, v, 8, 21, sigma_b=0.15)
+    so = SigmaOracle(s.eps, s.B, o, s.t1)
+    wd, _ = dense_eom(so.sigma, o, v)
+    w, b = cis_roots(s.eps, s.B, o, 3)
+    guess = [(b[k], np.zeros((o, o, v, v))) for k in range(3)]
+    res = davidson(so.sigma, CanonicalBasis(s.eps, o), guess, o, v, 3, tol_e=1e-13, tol_r=1e-10, max_sub=40)
+    assert np.max(np.abs(res["omega"] - np.sort(wd.real)[:3])) < 1e-10
