@@ -242,6 +242,52 @@ void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts);
 int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opts, double* omega_out,
                     double* resnorm_out, int* iters_out, int* nsigma_out);
 
+/* ---------------------------------------------------------------- CCSD ground state
+ * The CC energy E_CC = <0| exp(-T) H exp(T) |0> and the projected amplitude equations
+ * <mu| exp(-T) H exp(T) |0> = 0 for all singles and doubles mu (Methods: the CC ground
+ * state whose H-bar the EOM step uses).  With such T, the EOM-CCSD sigma of build_df is
+ * the H-bar block minus E_CC, and for two electrons (o = 1) CCSD and EOM-CCSD are exact. */
+typedef struct {
+  int max_iter;     /* Jacobi/DIIS steps at most (ENOTCONV when reached) */
+  double tol_e;     /* |E_CC change| of the last step (Eh) */
+  double tol_r;     /* largest |Omega| over singles and doubles (Eh) */
+  int diis_size;    /* (amplitude, step) pairs kept for Pulay's DIIS; <= 1: plain Jacobi steps */
+  int precision;    /* contraction precision of the build_df done at the final amplitudes */
+} pnoeom_ccsd_opts;
+
+/* Fill opts with the defaults (max_iter 100, tol_e 1e-10, tol_r 1e-8, diis_size 8, FP64). */
+void pnoeom_ccsd_defaults(pnoeom_ccsd_opts* opts);
+
+/* CCSD residual Omega_mu = <mu| exp(-T) H exp(T) |0> and correlation energy of given
+ * amplitudes (all device pointers; B, eps as for build_df; t2 must satisfy
+ * t2[j][i][b][a] = t2[i][j][a][b]).
+ *   r1_out : device [o][v];  r2_out : device [o][o][v][v];  e_corr_out : host, E_CC - E_ref
+ * Rebuilds the context's intermediates for its own use and leaves none behind: call
+ * build_df again before apply_sigma / davidson.  Errors: EINVAL, ENOMEM, EHIP. */
+int pnoeom_ccsd_residual(pnoeom_ctx* ctx, const double* B, const double* eps, const double* t1,
+                         const double* t2, double* r1_out, double* r2_out, double* e_corr_out);
+
+/* Solve the CCSD equations by Jacobi steps (denominators e_i - e_a, e_i + e_j - e_a - e_b)
+ * with Pulay's DIIS, from T1 = 0 and the first-order T2 (start = 0) or from the given
+ * t1, t2 (start = 1).
+ *   t1, t2 : device [o][v], [o][o][v][v]; the converged (or last) amplitudes on return
+ *   e_corr_out : host, E_CC - E_ref;  resmax_out : host, largest |Omega|, or NULL
+ *   iters_out  : host, steps taken, or NULL
+ * On return the context holds the intermediates of build_df at those amplitudes in
+ * opts->precision (ready for apply_sigma / davidson); earlier SA-PNOs are discarded.
+ * opts NULL selects the defaults.  Device memory: 2 (diis_size + 2) vectors of o v + o^2 v^2
+ * doubles besides the intermediates.
+ * Errors: EINVAL, ENOMEM, EHIP, ENOTCONV (max_iter reached or the iteration diverged; the
+ * last amplitudes are returned). */
+int pnoeom_ccsd(pnoeom_ctx* ctx, const double* B, const double* eps, double* t1, double* t2, int start,
+                const pnoeom_ccsd_opts* opts, double* e_corr_out, double* resmax_out, int* iters_out);
+
+/* Convergence history of the last pnoeom_ccsd on ctx: E_CC - E_ref and the largest |Omega|
+ * of every amplitude set it evaluated (the start, then one per step).
+ *   energies, resmax : host [cap] (may be NULL when cap = 0);  n_out : host, number of entries
+ *                      (entries past cap are not copied).  Errors: EINVAL. */
+int pnoeom_ccsd_history(const pnoeom_ctx* ctx, int cap, double* energies, double* resmax, int* n_out);
+
 /* Eigenvalues and right eigenvectors of a small dense real matrix on the host
  * (Householder reduction to Hessenberg form, shifted QR iteration, inverse
  * iteration for the vectors).  Used for the Davidson subspace matrix.

@@ -316,6 +316,62 @@ void pnoeom_davidson_defaults(pnoeom_davidson_opts* opts) {
   opts->log_path = nullptr;
 }
 
+void pnoeom_ccsd_defaults(pnoeom_ccsd_opts* opts) {
+  if (!opts) return;
+  opts->max_iter = 100;
+  opts->tol_e = 1e-10;
+  opts->tol_r = 1e-8;
+  opts->diis_size = 8;
+  opts->precision = PNOEOM_FP64;
+}
+
+int pnoeom_ccsd_residual(pnoeom_ctx* ctx, const double* B, const double* eps, const double* t1, const double* t2,
+                         double* r1_out, double* r2_out, double* e_corr_out) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(B && eps && t1 && t2 && r1_out && r2_out && e_corr_out, PNOEOM_EINVAL,
+              "ccsd_residual: null pointer");
+    *e_corr_out = pnoeom::ccsd_residual(c, B, eps, t1, t2, r1_out, r2_out);
+  });
+}
+
+int pnoeom_ccsd(pnoeom_ctx* ctx, const double* B, const double* eps, double* t1, double* t2, int start,
+                const pnoeom_ccsd_opts* opts, double* e_corr_out, double* resmax_out, int* iters_out) {
+  bool converged = false;
+  const int st = guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom_ccsd_opts o;
+    pnoeom_ccsd_defaults(&o);
+    if (opts) o = *opts;
+    PNO_CHECK(B && eps && t1 && t2 && e_corr_out, PNOEOM_EINVAL, "ccsd: null pointer");
+    PNO_CHECK(start == 0 || start == 1, PNOEOM_EINVAL, "ccsd: start must be 0 (MP1) or 1 (given amplitudes)");
+    PNO_CHECK(o.max_iter >= 0 && o.tol_e > 0.0 && o.tol_r > 0.0 && o.diis_size >= 0 && o.diis_size <= 64,
+              PNOEOM_EINVAL, "ccsd: bad options");
+    PNO_CHECK(o.precision == PNOEOM_FP64 || o.precision == PNOEOM_FP32 || o.precision == PNOEOM_BF16,
+              PNOEOM_EINVAL, "ccsd: bad precision");
+    const pnoeom::CcsdResult r = pnoeom::ccsd_solve(c, B, eps, t1, t2, start == 0, o);
+    *e_corr_out = r.e_corr;
+    if (resmax_out) *resmax_out = r.rmax;
+    if (iters_out) *iters_out = r.iters;
+    c.ccsd_energies = r.energies;
+    c.ccsd_resmax = r.resmax;
+    converged = r.converged;
+    if (!converged) c.err = "ccsd: not converged";
+  });
+  if (st != PNOEOM_OK) return st;
+  return converged ? PNOEOM_OK : PNOEOM_ENOTCONV;
+}
+
+int pnoeom_ccsd_history(const pnoeom_ctx* ctx, int cap, double* energies, double* resmax, int* n_out) {
+  if (!ctx || !n_out || cap < 0 || (cap > 0 && (!energies || !resmax))) return PNOEOM_EINVAL;
+  const pnoeom::Context& c = ctx->c;
+  const int n = (int)c.ccsd_energies.size();
+  *n_out = n;
+  for (int k = 0; k < std::min(n, cap); ++k) {
+    energies[k] = c.ccsd_energies[k];
+    resmax[k] = c.ccsd_resmax[k];
+  }
+  return PNOEOM_OK;
+}
+
 int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opts, double* omega_out,
                     double* resnorm_out, int* iters_out, int* nsigma_out) {
   int complex_pair = 0;

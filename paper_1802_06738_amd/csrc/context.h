@@ -115,6 +115,8 @@ struct Context {
   SigmaWork sw;
   PNOData pno;
 
+  // E_CC - E_ref and largest |Omega| of every amplitude set of the last pnoeom_ccsd
+  std::vector<double> ccsd_energies, ccsd_resmax;
   // timing of the last sigma / Davidson call
   double last_total_ms = 0, last_ladder_ms = 0, last_ladder_flops = 0;
   int last_ladder_launches = 0;
@@ -234,6 +236,18 @@ struct DavidsonResult {
   bool aborted = false;   // stopped at abort_after_iter
 };
 DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt);
+
+// CCSD ground state (ccsd.hip)
+struct CcsdResult {
+  std::vector<double> energies, resmax;  // per evaluated amplitude set
+  double e_corr = 0, rmax = 0;
+  int iters = 0;
+  bool converged = false;
+};
+double ccsd_residual(Context& c, const double* B, const double* eps, const double* t1, const double* t2,
+                     double* r1, double* r2);
+CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1, double* t2, bool start_mp1,
+                      const pnoeom_ccsd_opts& opt);
 
 // host eigen-solver (eig.cpp); returns 0 or a negative status
 // vectors of the first nvec eigenvalues in sorted order (nvec < 0: all); the others are zero

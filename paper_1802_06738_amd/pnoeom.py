@@ -26,7 +26,8 @@ EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pno
                     "pnoeom_gemm_record", "pnoeom_gemm_recorded", "pnoeom_gemm_time", "pnoeom_gemm_set_table",
                     "pnoeom_set_graph_mode", "pnoeom_graph_stats", "pnoeom_set_ladder_mode",
                     "pnoeom_build_ladder", "pnoeom_ladder_apply", "pnoeom_set_pno_ladder",
-                    "pnoeom_pno_ladder_stats", "pnoeom_set_pno_states"]
+                    "pnoeom_pno_ladder_stats", "pnoeom_set_pno_states", "pnoeom_ccsd_defaults",
+                    "pnoeom_ccsd_residual", "pnoeom_ccsd", "pnoeom_ccsd_history"]
 
 
 class PnoEomError(RuntimeError):
@@ -41,6 +42,11 @@ class DavidsonOpts(C.Structure):
                 ("nextra", C.c_int), ("mixed_tol_e", C.c_double), ("mixed_tol_r", C.c_double),
                 ("ckpt_every", C.c_int), ("abort_after_iter", C.c_int), ("ckpt_path", C.c_char_p),
                 ("resume_path", C.c_char_p), ("log_path", C.c_char_p)]
+
+
+class CcsdOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("tol_e", C.c_double), ("tol_r", C.c_double), ("diis_size", C.c_int),
+                ("precision", C.c_int)]
 
 
 _LIB = None
@@ -94,6 +100,11 @@ def load_library():
     lib.pnoeom_set_pno_ladder.argtypes = [vp, C.c_int]
     lib.pnoeom_set_pno_states.argtypes = [vp, C.c_int, ip]
     lib.pnoeom_pno_ladder_stats.argtypes = [vp, ip, ip, ip, dp]
+    lib.pnoeom_ccsd_defaults.argtypes = [C.POINTER(CcsdOpts)]
+    lib.pnoeom_ccsd_defaults.restype = None
+    lib.pnoeom_ccsd_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp, dp]
+    lib.pnoeom_ccsd.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.POINTER(CcsdOpts), dp, dp, ip]
+    lib.pnoeom_ccsd_history.argtypes = [vp, C.c_int, dp, dp, ip]
     _LIB = lib
     # the autotuner's table of GEMM tile choices for this device, when present
     from .autotune import DEFAULT_TABLE, load_table
@@ -270,6 +281,53 @@ class PnoEom:
         if st not in (0, -6):
             self._check(st)
         return dict(omega=om, resnorm=rn, iters=it.value, nsigma=ns.value, complex=(st == -6))
+
+    def ccsd_residual(self, B, eps, t1, t2):
+        """CCSD residual (Omega1 [o][v], Omega2 [o][o][v][v]) and E_CC - E_ref of given amplitudes.
+        Leaves no intermediates behind (build_df again before sigma / davidson)."""
+        import torch
+        o, v, n = self.o, self.v, self.nmo
+        r1 = torch.empty((o, v), dtype=torch.float64, device="cuda")
+        r2 = torch.empty((o, o, v, v), dtype=torch.float64, device="cuda")
+        e = C.c_double()
+        self._check(self.lib.pnoeom_ccsd_residual(self.h, _dev(B, (self.naux, n, n), "B"), _dev(eps, (n,), "eps"),
+                                                  _dev(t1, (o, v), "t1"), _dev(t2, (o, o, v, v), "t2"),
+                                                  _dev(r1), _dev(r2), C.byref(e)))
+        return r1, r2, e.value
+
+    def ccsd(self, B, eps, t1=None, t2=None, max_iter=100, tol_e=1e-10, tol_r=1e-8, diis_size=8,
+             precision=FP64, raise_on_notconv=True):
+        """Solve the CCSD equations (Jacobi + DIIS) from T1 = 0 and first-order T2, or from the
+        given t1 and t2 (both or neither).  Returns dict(t1, t2, e_corr, resmax, iters, converged);
+        the context then holds the intermediates at those amplitudes (contraction precision
+        `precision`), ready for sigma / davidson."""
+        import torch
+        o, v, n = self.o, self.v, self.nmo
+        if (t1 is None) != (t2 is None):
+            raise ValueError("give both t1 and t2, or neither")
+        start = 0 if t1 is None else 1
+        t1 = torch.zeros((o, v), dtype=torch.float64, device="cuda") if t1 is None else t1.clone()
+        t2 = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda") if t2 is None else t2.clone()
+        opts = CcsdOpts()
+        self.lib.pnoeom_ccsd_defaults(C.byref(opts))
+        opts.max_iter, opts.tol_e, opts.tol_r = int(max_iter), float(tol_e), float(tol_r)
+        opts.diis_size, opts.precision = int(diis_size), int(precision)
+        e = C.c_double()
+        rm = C.c_double()
+        it = C.c_int()
+        st = self.lib.pnoeom_ccsd(self.h, _dev(B, (self.naux, n, n), "B"), _dev(eps, (n,), "eps"),
+                                  _dev(t1, (o, v), "t1"), _dev(t2, (o, o, v, v), "t2"), start, C.byref(opts),
+                                  C.byref(e), C.byref(rm), C.byref(it))
+        if st != 0 and (st != -4 or raise_on_notconv):
+            self._check(st)
+        self._pno_len = None
+        n = C.c_int()
+        self._check(self.lib.pnoeom_ccsd_history(self.h, 0, None, None, C.byref(n)))
+        he = np.zeros(n.value)
+        hr = np.zeros(n.value)
+        self._check(self.lib.pnoeom_ccsd_history(self.h, n.value, _dptr(he), _dptr(hr), C.byref(n)))
+        return dict(t1=t1, t2=t2, e_corr=e.value, resmax=rm.value, iters=it.value, converged=(st == 0),
+                    energies=he, resmax_history=hr)
 
     def set_ladder_mode(self, mode=LADDER_AUTO, max_slab=0):
         """Cached or streamed W+/- for the next build_df (LADDER_AUTO / _CACHED / _STREAMED)."""
