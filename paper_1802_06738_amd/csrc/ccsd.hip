@@ -234,10 +234,15 @@ CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1
   const int64_t ov = c.ov(), oovv = c.oovv(), N = ov + oovv;
   const int m = std::max(1, opt.diis_size);
   CcsdWork w;
-  DBuf<double> x, r, st, X, E;
+  // the build-time temporaries stay allocated across the repeated builds of the iteration
+  struct KeepTmp {
+    Context& c;
+    explicit KeepTmp(Context& cc) : c(cc) { c.keep_build_tmp = true; }
+    ~KeepTmp() { c.keep_build_tmp = false; }
+  } keep(c);
+  DBuf<double> x, r, X, E;
   x.alloc(N);
   r.alloc(N);
-  st.alloc(N);
   X.alloc((int64_t)m * N);
   E.alloc((int64_t)m * N);
   if (start_mp1) {
@@ -303,7 +308,9 @@ CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1
   }
   PNO_HIP(hipMemcpyAsync(t1, x, ov * sizeof(double), hipMemcpyDeviceToDevice, s));
   PNO_HIP(hipMemcpyAsync(t2, x + ov, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
-  // intermediates of the final amplitudes, in the contraction precision asked for
+  // intermediates of the final amplitudes, in the contraction precision asked for (this
+  // build releases the temporaries)
+  c.keep_build_tmp = false;
   build_df(c, B, eps, t1, t2, opt.precision);
   PNO_HIP(hipStreamSynchronize(s));
   return res;

@@ -81,7 +81,7 @@ struct Context {
   // inputs
   DBuf<double> B, eps, t1;
   // dressed Hamiltonian
-  DBuf<double> C1, Bt, h, hd, fd, dt, dtmp, J, K;
+  DBuf<double> Bt, h, hd, fd, dt, dtmp, J, K;
   DBuf<double> BovT, BvoT, BooT, BvvT, Bvv2;
   // amplitudes
   DBuf<double> T, U, Tia, Tsia, UiaT;
@@ -98,7 +98,15 @@ struct Context {
   DBuf<uint16_t> Wpb, Wmb;      // bfloat16 bits (precision BF16), rows padded to ldpb / ldmb columns
   int64_t ldpb = 0, ldmb = 0;
   DBuf<float> DX2f, DXrf, TTsf;
-  DBuf<double> scratch;         // build-time temporaries
+  // build-time temporaries of build_df, by slot (each slot's uses follow one another on the
+  // stream); kept between builds while keep_build_tmp is set (the repeated builds of the
+  // CCSD solver then allocate nothing), else released at the end of each build
+  DBuf<double> btmp[4];
+  bool keep_build_tmp = false;
+  double* build_tmp(int slot, int64_t n) {
+    if ((int64_t)btmp[slot].n < n) btmp[slot].alloc(n);
+    return btmp[slot];
+  }
 
   // ladder storage (pnoeom_set_ladder_mode): 0 auto, 1 cached W+/-, 2 streamed from B~_vv
   int lad_mode = 0, lad_max_slab = 0;

@@ -262,7 +262,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   // workspaces and bases of the previous intermediates are dropped first, so that the
   // new ones (e.g. a second copy of W+/- in another precision) have the memory
   c.drop_graphs();
-  c.sw.release();
+  if (!c.keep_build_tmp) c.sw.release();  // (the CCSD iteration keeps its FP64 sigma workspaces)
   c.pno.reset();
   if (precision == PNOEOM_FP64)
     for (DBuf<float>* b : {&c.DX2f, &c.DXrf, &c.TTsf}) b->release();
@@ -278,10 +278,8 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     fill(s, ov, 0.0, c.t1);
 
   // ---------------------------------------------------------------- dressing
-  c.C1.alloc((int64_t)naux * n2);
   c.Bt.alloc((int64_t)naux * n2);
-  dress(c, c.B, c.Bt, c.C1, naux);
-  c.C1.release();
+  dress(c, c.B, c.Bt, c.build_tmp(0, (int64_t)naux * n2), naux);
 
   // core operator h = diag(eps) - (2 J - K) from the bare factors; dressed h~ and f~
   c.dt.alloc(naux);
@@ -298,11 +296,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   axpby(s, n2, 1.0, c.K, 1.0, c.h);
   hipLaunchKernelGGL(add_diag_kernel, dim3((nmo + 255) / 256), dim3(256), 0, s, nmo, (const double*)c.eps,
                      (double*)c.h);
-  {
-    DBuf<double> w;
-    w.alloc(n2);
-    dress(c, c.h, c.hd, w, 1);
-  }
+  dress(c, c.h, c.hd, c.build_tmp(1, n2), 1);
   hipLaunchKernelGGL(trace_occ_kernel, dim3((naux + 255) / 256), dim3(256), 0, s, naux, nmo, o,
                      (const double*)c.Bt, (double*)c.dt);
   coulomb_exchange(c, c.Bt, c.Bt, c.dt, c.J, c.K, 0.0);
@@ -358,23 +352,20 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   gm(s, false, true, ov, ov, naux, 1.0, c.BovT, naux, c.BvoT, naux, 0.0, c.OVVO, ov);
   c.OOVVx.alloc(oovv);
   {
-    DBuf<double> tmp;
-    tmp.alloc(oovv);
+    double* tmp = c.build_tmp(1, oovv);
     gm(s, false, true, oo, vv, naux, 1.0, c.BooT, naux, c.BvvT, naux, 0.0, tmp, vv);
     perm(s, tmp, o, o, v, v, 0, 3, 1, 2, c.OOVVx);
   }
   c.Wh.alloc(oo * oo);
   {
-    DBuf<double> tmp;
-    tmp.alloc(oo * oo);
+    double* tmp = c.build_tmp(1, oo * oo);
     gm(s, false, true, oo, oo, naux, 1.0, c.BooT, naux, c.BooT, naux, 0.0, tmp, oo);
     perm(s, tmp, o, o, o, o, 1, 3, 0, 2, c.Wh);
     gm(s, false, true, oo, oo, vv, 1.0, c.T, vv, c.g2, vv, 1.0, c.Wh, oo);
   }
   c.OOOVp.alloc(oo * ov);
   {
-    DBuf<double> tmp;
-    tmp.alloc(oo * ov);
+    double* tmp = c.build_tmp(1, oo * ov);
     gm(s, false, true, oo, ov, naux, 1.0, c.BooT, naux, c.BovT, naux, 0.0, tmp, ov);
     perm(s, tmp, o, o, o, v, 1, 0, 2, 3, c.OOOVp);
   }
@@ -386,8 +377,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   c.Foo.alloc(oo);
   c.fd_ov.alloc(ov);
   {
-    DBuf<double> Ub;
-    Ub.alloc(oovv);
+    double* Ub = c.build_tmp(1, oovv);
     perm(s, c.U, o, o, v, v, 2, 0, 1, 3, Ub);
     gm(s, false, false, v, v, oo * v, -1.0, Ub, oo * v, c.Gq, v, 0.0, c.Fqvv, v);
   }
@@ -424,8 +414,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   // YU[Q][(k,c)] = sum_(j,b) B_jb^Q (2 T - T^s)[(j,b),(k,c)]: the Coulomb (DF) part of the
   // R-side ring intermediate contracted with T ahead of time
   {
-    DBuf<double> U2;
-    U2.alloc(oovv);
+    double* U2 = c.build_tmp(1, oovv);
     PNO_HIP(hipMemcpyAsync(U2, c.Tsia, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
     axpby(s, oovv, 2.0, c.Tia, -1.0, U2);
     c.YU.alloc((int64_t)naux * ov);
@@ -439,10 +428,9 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     int64_t nb = v;
     const int64_t budget = (int64_t)1 << 28;  // doubles per temporary
     while (nb > 1 && (int64_t)o * nb * vv > budget) nb = (nb + 1) / 2;
-    DBuf<double> t1b, t2b, t3b;
-    t1b.alloc(ov * nb * v);
-    t2b.alloc(ov * nb * v);
-    t3b.alloc(oo * o * nb);
+    double* t1b = c.build_tmp(1, ov * nb * v);
+    double* t2b = c.build_tmp(2, ov * nb * v);
+    double* t3b = c.build_tmp(3, oo * o * nb);
     for (int64_t b0 = 0; b0 < v; b0 += nb) {
       const int64_t nbb = std::min<int64_t>(nb, v - b0);
       // OVVV[(k,c),(b,d)] for b in slab
@@ -497,8 +485,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     int64_t na = v;
     const int64_t budget = (int64_t)1 << 28;
     while (na > 1 && na * v * vv > budget) na = (na + 1) / 2;
-    DBuf<double> tmp;
-    tmp.alloc(na * v * vv);
+    double* tmp = c.build_tmp(0, na * v * vv);
     for (int64_t a0 = 0; a0 < v; a0 += na) {
       const int64_t nab = std::min<int64_t>(na, v - a0);
       gm(s, false, true, nab * v, vv, naux, 1.0, c.BvvT + a0 * v * naux, naux, c.BvvT, naux, 0.0, tmp, vv);
@@ -526,6 +513,8 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   PNO_HIP(hipStreamSynchronize(s));
   // kept only side by side (DXr, TTs) from here on
   c.Dr.release(); c.Xr.release(); c.Tia.release(); c.Tsia.release();
+  if (!c.keep_build_tmp)
+    for (DBuf<double>& b : c.btmp) b.release();
   c.have_df = true;
   c.have_lad = true;
 }
