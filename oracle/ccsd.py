@@ -42,12 +42,53 @@ def denominators(eps, o):
     return d1, d2
 
 
-def solve_ccsd(eps, B, o, t1=None, t2=None, tol_r=1e-10, tol_e=1e-12, max_iter=200, diis=8):
+def gs_densities(t2):
+    """Ground-state pair densities D_(0)^ij = 2/(1 + d_ij) (T T~^T + T^T T~), T~ = 2T - T^T,
+    of the guess amplitudes (Methods, ground-state PNOs), for all pairs [i, j, v, v]."""
+    from .sapno import pair_density
+    o, v = t2.shape[0], t2.shape[2]
+    D = np.zeros((o, o, v, v))
+    for i in range(o):
+        for j in range(o):
+            D[i, j] = pair_density(t2[i, j], i == j)
+    return D
+
+
+def gs_pno_basis(eps, B, o, tcut_pno, tcut_osv=None):
+    """GS-PNOs / OSVs from the MP1 pair densities, semicanonical in the Fock matrix diag(eps)."""
+    from .ham import mp2_amplitudes
+    from .sapno import PNOBasis
+    return PNOBasis(gs_densities(mp2_amplitudes(eps, B, o)), np.asarray(eps, dtype=np.float64), o, tcut_pno,
+                    tcut_osv)
+
+
+def compressed_max(basis, w1, w2):
+    """Largest element of the residual in the OSV / PNO basis (U^i^T w^i, U^ij^T w^ij U^ij for
+    pairs i <= j, off-diagonal pairs weighted by sqrt 2, the weight that makes the compressed
+    inner product the full-array one)."""
+    m = 0.0
+    for i in range(basis.o):
+        if basis.osv[i].shape[1]:
+            m = max(m, float(np.abs(basis.osv[i].T @ w1[i]).max()))
+    for (i, j), U in basis.pno.items():
+        if U.shape[1]:
+            m = max(m, float(np.abs(U.T @ w2[i, j] @ U).max()) * (1.0 if i == j else np.sqrt(2.0)))
+    return m
+
+
+def solve_ccsd(eps, B, o, t1=None, t2=None, tol_r=1e-10, tol_e=1e-12, max_iter=200, diis=8, basis=None):
     """Jacobi + DIIS solution of the CCSD equations.
 
     Starts from (t1, t2), default T1 = 0 and the first-order T2 (MP1).  Converged when
     the largest |Omega| is below tol_r and the last step changed the energy by less than
     tol_e.  Returns (t1, t2, e_corr, steps taken, max|Omega|).
+
+    basis (a sapno.PNOBasis, e.g. gs_pno_basis): the ground-state PNO simulation of the
+    Methods section.  The start is projected onto the OSV / PNO space; every step takes the
+    residual into the semicanonical OSV / PNO basis, divides it by f_ii (+ f_jj) - fbar_a
+    (- fbar_b) there and transforms it back (basis.precondition at omega = 0), so the
+    amplitudes stay in the space and the fixed point is P Omega = 0; max|Omega| is then
+    measured in that basis (compressed_max).
     """
     from .ham import mp2_amplitudes
     eps = np.asarray(eps, dtype=np.float64)
@@ -55,15 +96,24 @@ def solve_ccsd(eps, B, o, t1=None, t2=None, tol_r=1e-10, tol_e=1e-12, max_iter=2
     v = B.shape[1] - o
     t1 = np.zeros((o, v)) if t1 is None else np.array(t1, dtype=np.float64)
     t2 = mp2_amplitudes(eps, B, o) if t2 is None else np.array(t2, dtype=np.float64)
+    if basis is not None:
+        t1, t2 = basis.project(t1, t2)
     d1, d2 = denominators(eps, o)
     xs, es = [], []
     e, e_prev = ccsd_energy(eps, B, o, t1, t2), np.inf
     for it in range(max_iter + 1):
         w1, w2 = ccsd_residual(eps, B, o, t1, t2)
-        rmax = max(float(np.abs(w1).max()), float(np.abs(w2).max()))
+        if basis is None:
+            rmax = max(float(np.abs(w1).max()), float(np.abs(w2).max()))
+        else:
+            rmax = compressed_max(basis, w1, w2)
         if (rmax < tol_r and abs(e - e_prev) < tol_e) or it == max_iter:
             return t1, t2, e, it, rmax
-        s = np.concatenate([(w1 / d1).ravel(), (w2 / d2).ravel()])
+        if basis is None:
+            s = np.concatenate([(w1 / d1).ravel(), (w2 / d2).ravel()])
+        else:
+            p1, p2 = basis.precondition(w1, w2, 0.0)
+            s = np.concatenate([p1.ravel(), p2.ravel()])
         x = np.concatenate([t1.ravel(), t2.ravel()]) + s
         xs.append(x)
         es.append(s)
