@@ -253,9 +253,19 @@ typedef struct {
   double tol_r;     /* largest |Omega| over singles and doubles (Eh) */
   int diis_size;    /* (amplitude, step) pairs kept for Pulay's DIIS; <= 1: plain Jacobi steps */
   int precision;    /* contraction precision of the build_df done at the final amplitudes */
+  /* Ground-state PNO-CCSD simulation (Methods: the modified Jacobi update) when gs_tcut_pno >= 0:
+   * PNOs / OSVs of the pair densities of the first-order amplitudes, kept when |occupation| >=
+   * gs_tcut_pno (pairs) or gs_tcut_osv (diagonal pairs; < 0 selects gs_tcut_pno / 10), made
+   * semicanonical in the Fock matrix; the start is projected onto that space, every residual is
+   * transformed into the OSV / PNO basis, divided there by f_ii (+ f_jj) - fbar_a (- fbar_b),
+   * extrapolated by DIIS and transformed back, and tol_r bounds that transformed residual
+   * (off-diagonal pair blocks weighted by sqrt 2).  gs_tcut_pno = 0 keeps every PNO. */
+  double gs_tcut_pno;
+  double gs_tcut_osv;
 } pnoeom_ccsd_opts;
 
-/* Fill opts with the defaults (max_iter 100, tol_e 1e-10, tol_r 1e-8, diis_size 8, FP64). */
+/* Fill opts with the defaults (max_iter 100, tol_e 1e-10, tol_r 1e-8, diis_size 8, FP64,
+ * canonical: gs_tcut_pno = gs_tcut_osv = -1). */
 void pnoeom_ccsd_defaults(pnoeom_ccsd_opts* opts);
 
 /* CCSD residual Omega_mu = <mu| exp(-T) H exp(T) |0> and correlation energy of given
@@ -287,6 +297,11 @@ int pnoeom_ccsd(pnoeom_ctx* ctx, const double* B, const double* eps, double* t1,
  *   energies, resmax : host [cap] (may be NULL when cap = 0);  n_out : host, number of entries
  *                      (entries past cap are not copied).  Errors: EINVAL. */
 int pnoeom_ccsd_history(const pnoeom_ctx* ctx, int cap, double* energies, double* resmax, int* n_out);
+
+/* PNO and OSV counts of the ground-state PNOs of the last pnoeom_ccsd with gs_tcut_pno >= 0.
+ *   npno_out : host [o(o+1)/2] (pairs i <= j, row-major) or NULL;  nosv_out : host [o] or NULL
+ * Errors: ESTATE (no ground-state PNOs built on ctx), EINVAL. */
+int pnoeom_ccsd_gs_counts(const pnoeom_ctx* ctx, int* npno_out, int* nosv_out);
 
 /* Eigenvalues and right eigenvectors of a small dense real matrix on the host
  * (Householder reduction to Hessenberg form, shifted QR iteration, inverse

@@ -323,6 +323,8 @@ void pnoeom_ccsd_defaults(pnoeom_ccsd_opts* opts) {
   opts->tol_r = 1e-8;
   opts->diis_size = 8;
   opts->precision = PNOEOM_FP64;
+  opts->gs_tcut_pno = -1.0;
+  opts->gs_tcut_osv = -1.0;
 }
 
 int pnoeom_ccsd_residual(pnoeom_ctx* ctx, const double* B, const double* eps, const double* t1, const double* t2,
@@ -358,6 +360,17 @@ int pnoeom_ccsd(pnoeom_ctx* ctx, const double* B, const double* eps, double* t1,
   });
   if (st != PNOEOM_OK) return st;
   return converged ? PNOEOM_OK : PNOEOM_ENOTCONV;
+}
+
+int pnoeom_ccsd_gs_counts(const pnoeom_ctx* ctx, int* npno_out, int* nosv_out) {
+  if (!ctx) return PNOEOM_EINVAL;
+  const pnoeom::Context& c = ctx->c;
+  if (!c.gs.built) return PNOEOM_ESTATE;
+  if (npno_out)
+    for (size_t p = 0; p < c.gs.npno.size(); ++p) npno_out[p] = c.gs.npno[p];
+  if (nosv_out)
+    for (size_t i = 0; i < c.gs.nosv.size(); ++i) nosv_out[i] = c.gs.nosv[i];
+  return PNOEOM_OK;
 }
 
 int pnoeom_ccsd_history(const pnoeom_ctx* ctx, int cap, double* energies, double* resmax, int* n_out) {

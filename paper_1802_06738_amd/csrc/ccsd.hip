@@ -233,6 +233,7 @@ CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1
   const int o = c.o, v = c.v;
   const int64_t ov = c.ov(), oovv = c.oovv(), N = ov + oovv;
   const int m = std::max(1, opt.diis_size);
+  const bool gs = opt.gs_tcut_pno >= 0.0;  // ground-state PNO simulation
   CcsdWork w;
   // the build-time temporaries stay allocated across the repeated builds of the iteration
   struct KeepTmp {
@@ -240,27 +241,49 @@ CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1
     explicit KeepTmp(Context& cc) : c(cc) { c.keep_build_tmp = true; }
     ~KeepTmp() { c.keep_build_tmp = false; }
   } keep(c);
-  DBuf<double> x, r, X, E;
+  DBuf<double> x, r;
   x.alloc(N);
   r.alloc(N);
-  X.alloc((int64_t)m * N);
-  E.alloc((int64_t)m * N);
-  if (start_mp1) {
-    // T1 = 0 and the first-order T2 that build_df forms when no T2 is given
+  if (start_mp1 || gs) {
+    // the first-order T2 that build_df forms when no T2 is given: the start, and the guess
+    // amplitudes of the ground-state pair densities
     build_df(c, B, eps, nullptr, nullptr, PNOEOM_FP64);
+    if (gs) {
+      const double tosv = opt.gs_tcut_osv < 0.0 ? opt.gs_tcut_pno / 10.0 : opt.gs_tcut_osv;
+      build_gs_pnos(c, c.T, opt.gs_tcut_pno, tosv);
+    }
+  }
+  if (start_mp1) {
     fill(s, ov, 0.0, x);
     PNO_HIP(hipMemcpyAsync(x + ov, c.T, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
   } else {
     PNO_HIP(hipMemcpyAsync(x, t1, ov * sizeof(double), hipMemcpyDeviceToDevice, s));
     PNO_HIP(hipMemcpyAsync(x + ov, t2, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
+  // the iterated vector: the canonical amplitudes, or (PNO simulation) their components in
+  // the semicanonical OSV / PNO basis (the start projected onto that space); DIIS runs on it
+  PNOData& P = c.gs;
+  const int64_t Nd = gs ? P.len : N;
+  DBuf<double> xb, rb, X, E;
+  if (gs) {
+    xb.alloc(Nd);
+    rb.alloc(Nd);
+    pno_compress(c, P, 1, x, x + ov, xb);
+    project_pno(c, P, xb);
+  }
+  double* xs = gs ? (double*)xb : (double*)x;
+  X.alloc((int64_t)m * Nd);
+  E.alloc((int64_t)m * Nd);
   CcsdResult res;
   std::vector<double> gram((size_t)m * m, 0.0);
   int stored = 0;
   double e_prev = INFINITY;
   for (int it = 0;; ++it) {
+    if (gs) pno_expand(c, P, 1, xs, x, x + ov);
     const double e = residual(c, w, B, eps, x, x + ov, r, r + ov);
-    const double rmax = maxabs(s, w, N, r);
+    if (gs) pno_compress(c, P, 1, r, r + ov, rb);
+    const double* rs = gs ? (const double*)rb : (const double*)r;
+    const double rmax = maxabs(s, w, Nd, rs);
     res.energies.push_back(e);
     res.resmax.push_back(rmax);
     res.e_corr = e;
@@ -274,14 +297,22 @@ CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1
     if (it == opt.max_iter) break;
     // Jacobi step into DIIS slot k (the oldest entry is overwritten once m are stored)
     const int k = it % m;
-    double* Xk = X + (int64_t)k * N;
-    double* Ek = E + (int64_t)k * N;
-    hipLaunchKernelGGL(jacobi_kernel, dim3(grid_of(N)), dim3(256), 0, s, o, v, (const double*)c.eps,
-                       (const double*)r, (const double*)x, Ek, Xk);
-    PNO_HIP(hipGetLastError());
+    double* Xk = X + (int64_t)k * Nd;
+    double* Ek = E + (int64_t)k * Nd;
+    if (gs) {
+      // step in the semicanonical OSV / PNO basis: rbar / (f_ii (+ f_jj) - fbar_a (- fbar_b))
+      PNO_HIP(hipMemcpyAsync(Ek, rs, Nd * sizeof(double), hipMemcpyDeviceToDevice, s));
+      precond_pno(c, P, Ek, 0.0);
+      PNO_HIP(hipMemcpyAsync(Xk, xs, Nd * sizeof(double), hipMemcpyDeviceToDevice, s));
+      axpby(s, Nd, 1.0, Ek, 1.0, Xk);
+    } else {
+      hipLaunchKernelGGL(jacobi_kernel, dim3(grid_of(N)), dim3(256), 0, s, o, v, (const double*)c.eps,
+                         (const double*)r, (const double*)x, Ek, Xk);
+      PNO_HIP(hipGetLastError());
+    }
     stored = std::min(stored + 1, m);
     for (int l = 0; l < stored; ++l) {
-      const double g = dot(s, w, N, Ek, E + (int64_t)l * N);
+      const double g = dot(s, w, Nd, Ek, E + (int64_t)l * Nd);
       gram[(size_t)k * m + l] = gram[(size_t)l * m + k] = g;
     }
     bool extrapolated = false;
@@ -298,14 +329,15 @@ CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1
       }
       rhs[stored] = -1.0;
       if (small_solve(n, A, rhs)) {
-        axpby(s, N, rhs[0], X, 0.0, x);
-        for (int l = 1; l < stored; ++l) axpby(s, N, rhs[l], X + (int64_t)l * N, 1.0, x);
+        axpby(s, Nd, rhs[0], X, 0.0, xs);
+        for (int l = 1; l < stored; ++l) axpby(s, Nd, rhs[l], X + (int64_t)l * Nd, 1.0, xs);
         extrapolated = true;
       }
     }
-    if (!extrapolated) PNO_HIP(hipMemcpyAsync(x, Xk, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (!extrapolated) PNO_HIP(hipMemcpyAsync(xs, Xk, Nd * sizeof(double), hipMemcpyDeviceToDevice, s));
     e_prev = e;
   }
+  if (gs) pno_expand(c, P, 1, xs, x, x + ov);
   PNO_HIP(hipMemcpyAsync(t1, x, ov * sizeof(double), hipMemcpyDeviceToDevice, s));
   PNO_HIP(hipMemcpyAsync(t2, x + ov, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
   // intermediates of the final amplitudes, in the contraction precision asked for (this

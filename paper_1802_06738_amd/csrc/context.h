@@ -122,6 +122,7 @@ struct Context {
 
   SigmaWork sw;
   PNOData pno;
+  PNOData gs;   // ground-state PNOs / OSVs of the PNO-CCSD simulation (build_gs_pnos; build_df keeps them)
 
   // E_CC - E_ref and largest |Omega| of every amplitude set of the last pnoeom_ccsd
   std::vector<double> ccsd_energies, ccsd_resmax;
@@ -227,6 +228,12 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv);
 // PNO compress / expand of nvec vectors (canonical full arrays <-> compressed)
 void pno_compress(Context& c, int nvec, const double* r1, const double* r2, double* x);
 void pno_expand(Context& c, int nvec, const double* x, double* r1, double* r2);
+// the same with another set of PNOs (the ground-state ones)
+void pno_compress(Context& c, PNOData& P, int nvec, const double* r1, const double* r2, double* x);
+void pno_expand(Context& c, PNOData& P, int nvec, const double* x, double* r1, double* r2);
+void project_pno(Context& c, PNOData& P, double* x);
+void precond_pno(Context& c, PNOData& P, double* x, double theta);
+void build_gs_pnos(Context& c, const double* t2, double tcut_pno, double tcut_osv);
 void sigma_pno(Context& c, int nvec, const double* x, double* y, int precision);
 // vectors per sigma chunk that fit the free device memory (pno: with the canonical
 // expansions of the PNO-space sigma)

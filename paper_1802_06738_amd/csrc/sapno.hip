@@ -395,74 +395,34 @@ void build_native_ladder(Context& c, const std::vector<int>& pi, const std::vect
 }
 }  // namespace
 
-void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
-  PNO_CHECK(c.have_df, PNOEOM_ESTATE, "build_sapno before build_df");
-  PNO_CHECK(nstates >= 1 && nstates <= c.ov(), PNOEOM_EINVAL, "build_sapno: bad nstates");
+// D[i][j] += B_ij Bt_ij^T + B_ij^T Bt_ij with Bt = 2 B - B^T per pair block, for all o^2
+// pairs of the doubles amplitudes B (device [o][o][v][v]); work: o^2 v^2 doubles
+void add_pair_densities(Context& c, const double* Bk, double* work, double* D) {
   hipStream_t s = c.stream;
-  PNOData& P = c.pno;
-  c.drop_graphs();
-  P.reset();
-  const int o = c.o, v = c.v, naux = c.naux, nmo = c.nmo;
-  const int64_t n2 = (int64_t)nmo * nmo, ov = c.ov(), oovv = c.oovv(), vv = (int64_t)v * v;
+  const int o = c.o, v = c.v;
+  const int64_t vv = (int64_t)v * v, oovv = c.oovv();
+  perm(s, Bk, o, o, v, v, 0, 1, 3, 2, work, -1.0, 0.0);
+  axpby(s, oovv, 2.0, Bk, 1.0, work);
+  gm(s, false, true, v, v, v, 1.0, Bk, v, vv, work, v, vv, 1.0, D, v, vv, (int64_t)o * o);
+  gm(s, true, false, v, v, v, 1.0, Bk, v, vv, work, v, vv, 1.0, D, v, vv, (int64_t)o * o);
+}
+
+// PNOs and OSVs of pair densities (Methods: per-pair eigenvectors of the density kept when
+// |occupation| >= tcut_pno; OSVs from the diagonal pairs with tcut_osv), rotated to the
+// semicanonical basis of the symmetric virtual matrix Fs (device v x v); focc: occupied
+// energies of the preconditioner.  D holds sums over states for all o^2 pairs, D[i][j] of
+// pair (i, j) scaled by inv_n (2 inv_n off the diagonal).  Fills P except its state list,
+// cuts, native ladder and `built`; returns the pair tables (pairs i <= j, row-major).
+void pnos_from_density(Context& c, PNOData& P, const double* D, double inv_n, double tcut_pno, double tcut_osv,
+                       const double* Fs, const std::vector<double>& focc, std::vector<int>& pi,
+                       std::vector<int>& pj) {
+  hipStream_t s = c.stream;
+  const int o = c.o, v = c.v;
+  const int64_t vv = (int64_t)v * v;
   const int npair = o * (o + 1) / 2;
-  // states whose densities are averaged: the lowest nstates, or the list set by
-  // pnoeom_set_pno_states (one state: the state-specific PNOs of that state)
-  std::vector<int> avg = P.states;
-  if (avg.empty())
-    for (int k = 0; k < nstates; ++k) avg.push_back(k);
-  const int ncis = *std::max_element(avg.begin(), avg.end()) + 1;
-  PNO_CHECK(ncis <= c.ov(), PNOEOM_EINVAL, "build_sapno: state index beyond the CIS space");
-  P.nstates = (int)avg.size();
-  P.tcut_pno = tcut_pno;
-  P.tcut_osv = tcut_osv;
-
-  // 1. CIS roots
-  std::vector<double> w(ncis);
-  DBuf<double> bvec;
-  bvec.alloc((int64_t)ncis * ov);
-  cis_roots(c, ncis, w.data(), bvec);
-
-  // 2. averaged pair densities D[i][j] (all pairs, unscaled sum over states)
-  DBuf<double> D, Bk, Bt2, Kt, Bp, XT, BvoT0;
-  D.alloc(oovv);
-  Bk.alloc(oovv);
-  Bt2.alloc(oovv);
-  Kt.alloc(oovv);
-  Bp.alloc((int64_t)naux * v * o);
-  XT.alloc(ov * naux);
-  BvoT0.alloc(ov * naux);
-  fill(s, oovv, 0.0, D);
-  {
-    Perm4 p;  // BvoT0[(j,b)][Q] = B[Q][o+b][j]
-    p.d[0] = o; p.d[1] = v; p.d[2] = naux; p.d[3] = 1;
-    p.is[0] = 1; p.is[1] = nmo; p.is[2] = n2; p.is[3] = 0;
-    p.os[0] = (int64_t)v * naux; p.os[1] = naux; p.os[2] = 1; p.os[3] = 0;
-    permute4(s, p, 1.0, c.B + (int64_t)o * nmo, 0.0, BvoT0);
-  }
-  for (int k : avg) {
-    const double* b = bvec + (int64_t)k * ov;
-    // B'_vo[Q][a][i] = -sum_l b_l^a B[Q][l][i] + sum_c B[Q][o+a][o+c] b_i^c
-    gm(s, true, false, v, o, o, -1.0, b, v, 0, c.B, nmo, n2, 0.0, Bp, o, (int64_t)v * o, naux);
-    gm(s, false, true, v, o, v, 1.0, c.B + (int64_t)o * nmo + o, nmo, n2, b, v, 0, 1.0, Bp, o, (int64_t)v * o, naux);
-    perm(s, Bp, naux, v, o, 1, 2, 1, 0, 3, XT);  // XT[(i,a)][Q]
-    // K[(i,a),(j,b)] = sum_Q B'_ai B_bj + B_ai B'_bj  ->  [i][j][a][b]
-    gm(s, false, true, ov, ov, naux, 1.0, XT, naux, 0, BvoT0, naux, 0, 0.0, Bt2, ov, 0, 1);
-    gm(s, false, true, ov, ov, naux, 1.0, BvoT0, naux, 0, XT, naux, 0, 1.0, Bt2, ov, 0, 1);
-    perm(s, Bt2, o, v, o, v, 0, 2, 1, 3, Kt);
-    hipLaunchKernelGGL(cisd_div_kernel, dim3(gsz(oovv)), dim3(256), 0, s, o, v, (const double*)c.eps, w[k],
-                       (const double*)Kt, (double*)Bk);
-    PNO_HIP(hipGetLastError());
-    // Bt = 2B - B^T per pair block
-    perm(s, Bk, o, o, v, v, 0, 1, 3, 2, Bt2, -1.0, 0.0);
-    axpby(s, oovv, 2.0, Bk, 1.0, Bt2);
-    // D += B Bt^T + B^T Bt   (all o^2 pairs, batched)
-    gm(s, false, true, v, v, v, 1.0, Bk, v, vv, Bt2, v, vv, 1.0, D, v, vv, (int64_t)o * o);
-    gm(s, true, false, v, v, v, 1.0, Bk, v, vv, Bt2, v, vv, 1.0, D, v, vv, (int64_t)o * o);
-  }
-  Bk.release(); Bt2.release(); Kt.release(); Bp.release(); XT.release(); BvoT0.release();
-
   // 3. pair tables and per-pair eigenproblems
-  std::vector<int> pi(npair), pj(npair);
+  pi.assign(npair, 0);
+  pj.assign(npair, 0);
   {
     int p = 0;
     for (int i = 0; i < o; ++i)
@@ -477,9 +437,8 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
   Vt.alloc((int64_t)npair * vv);
   ev.alloc((int64_t)npair * v);
   hipLaunchKernelGGL(gather_pairs_kernel, dim3(gsz((int64_t)npair * vv)), dim3(256), 0, s, o, v, npair,
-                     (const int*)dpi, (const int*)dpj, 1.0 / (double)avg.size(), (const double*)D, (double*)Dp);
+                     (const int*)dpi, (const int*)dpj, inv_n, D, (double*)Dp);
   PNO_HIP(hipGetLastError());
-  D.release();
   {
     std::vector<int> nv(npair, v);
     batched_syev(s, npair, nv, v, Dp, Vt, ev, dn);
@@ -540,12 +499,8 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
   Vt.release();
   ev.release();
 
-  // 5. semicanonical rotation: eigenvectors of U0^T Fs U0, Fs = symmetric part of the
-  //    one-particle virtual block of H-bar
-  DBuf<double> Fs, Tb, Fb, Wt, fev;
-  Fs.alloc(vv);
-  perm(s, c.Fvv, v, v, 1, 1, 1, 0, 2, 3, Fs, 0.5, 0.0);
-  axpby(s, vv, 0.5, c.Fvv, 1.0, Fs);
+  // 5. semicanonical rotation: eigenvectors of U0^T Fs U0
+  DBuf<double> Tb, Fb, Wt, fev;
   Tb.alloc(std::max<int64_t>(utot, 1));
   Fb.alloc((int64_t)nblk * nmax * nmax);
   Wt.alloc((int64_t)nblk * nmax * nmax);
@@ -598,19 +553,17 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
     P.xf_flops += 2.0 * P.npno[p] * (double)v * v + 2.0 * (double)P.npno[p] * P.npno[p] * v;
   for (int i = 0; i < o; ++i) P.xf_flops += 2.0 * P.nosv[i] * (double)v;
   P.nmax = nmax;
-  PNO_CHECK(P.len > 0, PNOEOM_EINVAL, "build_sapno: every PNO and OSV was truncated");
+  PNO_CHECK(P.len > 0, PNOEOM_EINVAL, "PNO build: every PNO and OSV was truncated");
   // preconditioner base: F_ii (+ F_jj) - fbar_a (- fbar_b); weights
-  std::vector<double> Fooh((size_t)o * o);
-  PNO_HIP(hipMemcpy(Fooh.data(), c.Foo, Fooh.size() * sizeof(double), hipMemcpyDeviceToHost));
   std::vector<double> base(P.len);
   for (int i = 0; i < o; ++i) {
     const int b = npair + i;
     for (int a = 0; a < P.nosv[i]; ++a)
-      base[P.off[i] + a] = Fooh[(size_t)i * o + i] - fevh[(size_t)b * nmax + a];
+      base[P.off[i] + a] = focc[i] - fevh[(size_t)b * nmax + a];
   }
   for (int p = 0; p < npair; ++p) {
     const int n = P.npno[p];
-    const double e = Fooh[(size_t)pi[p] * o + pi[p]] + Fooh[(size_t)pj[p] * o + pj[p]];
+    const double e = focc[pi[p]] + focc[pj[p]];
     for (int a = 0; a < n; ++a)
       for (int b2 = 0; b2 < n; ++b2)
         base[P.off[o + p] + (int64_t)a * n + b2] = e - fevh[(size_t)p * nmax + a] - fevh[(size_t)p * nmax + b2];
@@ -681,14 +634,128 @@ void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
     gemm_grouped_prepare(ex2o, false, true, P.t_e2o);
     P.Tw.alloc(std::max<int64_t>(P.toff[npair], 1));
   }
+}
+
+void build_sapno(Context& c, int nstates, double tcut_pno, double tcut_osv) {
+  PNO_CHECK(c.have_df, PNOEOM_ESTATE, "build_sapno before build_df");
+  PNO_CHECK(nstates >= 1 && nstates <= c.ov(), PNOEOM_EINVAL, "build_sapno: bad nstates");
+  hipStream_t s = c.stream;
+  PNOData& P = c.pno;
+  c.drop_graphs();
+  P.reset();
+  const int o = c.o, v = c.v, naux = c.naux, nmo = c.nmo;
+  const int64_t n2 = (int64_t)nmo * nmo, ov = c.ov(), oovv = c.oovv(), vv = (int64_t)v * v;
+  const int npair = o * (o + 1) / 2;
+  // states whose densities are averaged: the lowest nstates, or the list set by
+  // pnoeom_set_pno_states (one state: the state-specific PNOs of that state)
+  std::vector<int> avg = P.states;
+  if (avg.empty())
+    for (int k = 0; k < nstates; ++k) avg.push_back(k);
+  const int ncis = *std::max_element(avg.begin(), avg.end()) + 1;
+  PNO_CHECK(ncis <= c.ov(), PNOEOM_EINVAL, "build_sapno: state index beyond the CIS space");
+  P.nstates = (int)avg.size();
+  P.tcut_pno = tcut_pno;
+  P.tcut_osv = tcut_osv;
+
+  // 1. CIS roots
+  std::vector<double> w(ncis);
+  DBuf<double> bvec;
+  bvec.alloc((int64_t)ncis * ov);
+  cis_roots(c, ncis, w.data(), bvec);
+
+  // 2. averaged pair densities D[i][j] (all pairs, unscaled sum over states)
+  DBuf<double> D, Bk, Bt2, Kt, Bp, XT, BvoT0;
+  D.alloc(oovv);
+  Bk.alloc(oovv);
+  Bt2.alloc(oovv);
+  Kt.alloc(oovv);
+  Bp.alloc((int64_t)naux * v * o);
+  XT.alloc(ov * naux);
+  BvoT0.alloc(ov * naux);
+  fill(s, oovv, 0.0, D);
+  {
+    Perm4 p;  // BvoT0[(j,b)][Q] = B[Q][o+b][j]
+    p.d[0] = o; p.d[1] = v; p.d[2] = naux; p.d[3] = 1;
+    p.is[0] = 1; p.is[1] = nmo; p.is[2] = n2; p.is[3] = 0;
+    p.os[0] = (int64_t)v * naux; p.os[1] = naux; p.os[2] = 1; p.os[3] = 0;
+    permute4(s, p, 1.0, c.B + (int64_t)o * nmo, 0.0, BvoT0);
+  }
+  for (int k : avg) {
+    const double* b = bvec + (int64_t)k * ov;
+    // B'_vo[Q][a][i] = -sum_l b_l^a B[Q][l][i] + sum_c B[Q][o+a][o+c] b_i^c
+    gm(s, true, false, v, o, o, -1.0, b, v, 0, c.B, nmo, n2, 0.0, Bp, o, (int64_t)v * o, naux);
+    gm(s, false, true, v, o, v, 1.0, c.B + (int64_t)o * nmo + o, nmo, n2, b, v, 0, 1.0, Bp, o, (int64_t)v * o, naux);
+    perm(s, Bp, naux, v, o, 1, 2, 1, 0, 3, XT);  // XT[(i,a)][Q]
+    // K[(i,a),(j,b)] = sum_Q B'_ai B_bj + B_ai B'_bj  ->  [i][j][a][b]
+    gm(s, false, true, ov, ov, naux, 1.0, XT, naux, 0, BvoT0, naux, 0, 0.0, Bt2, ov, 0, 1);
+    gm(s, false, true, ov, ov, naux, 1.0, BvoT0, naux, 0, XT, naux, 0, 1.0, Bt2, ov, 0, 1);
+    perm(s, Bt2, o, v, o, v, 0, 2, 1, 3, Kt);
+    hipLaunchKernelGGL(cisd_div_kernel, dim3(gsz(oovv)), dim3(256), 0, s, o, v, (const double*)c.eps, w[k],
+                       (const double*)Kt, (double*)Bk);
+    PNO_HIP(hipGetLastError());
+    add_pair_densities(c, Bk, Bt2, D);
+  }
+  Bk.release(); Bt2.release(); Kt.release(); Bp.release(); XT.release(); BvoT0.release();
+
+  // 3.-6. PNOs / OSVs, semicanonical in the symmetric part of the virtual block of the
+  //       one-particle part of H-bar, occupied energies from its occupied block
+  std::vector<int> pi, pj;
+  {
+    DBuf<double> Fs;
+    Fs.alloc(vv);
+    perm(s, c.Fvv, v, v, 1, 1, 1, 0, 2, 3, Fs, 0.5, 0.0);
+    axpby(s, vv, 0.5, c.Fvv, 1.0, Fs);
+    std::vector<double> Fooh((size_t)o * o), focc(o);
+    PNO_HIP(hipMemcpy(Fooh.data(), c.Foo, Fooh.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int i = 0; i < o; ++i) focc[i] = Fooh[(size_t)i * o + i];
+    pnos_from_density(c, P, D, 1.0 / (double)avg.size(), tcut_pno, tcut_osv, Fs, focc, pi, pj);
+  }
+  D.release();
   build_native_ladder(c, pi, pj);
+  P.built = true;
+}
+
+// Ground-state PNOs / OSVs (Methods: pair densities D_(0) of the guess amplitudes, the same
+// eigenvector truncation), semicanonical in the Fock matrix diag(eps) with occupied
+// energies eps_i: the basis of the ground-state PNO-CCSD simulation.  Kept in c.gs, which
+// build_df leaves alone.
+void build_gs_pnos(Context& c, const double* t2, double tcut_pno, double tcut_osv) {
+  hipStream_t s = c.stream;
+  const int o = c.o, v = c.v, nmo = c.nmo;
+  const int64_t vv = (int64_t)v * v, oovv = c.oovv();
+  PNOData& P = c.gs;
+  P.reset();
+  {
+    DBuf<double> D, work;
+    D.alloc(oovv);
+    work.alloc(oovv);
+    fill(s, oovv, 0.0, D);
+    add_pair_densities(c, t2, work, D);
+    work.release();
+    std::vector<double> eh(nmo), Fh((size_t)vv, 0.0), focc(o);
+    PNO_HIP(hipMemcpyAsync(eh.data(), c.eps, nmo * sizeof(double), hipMemcpyDeviceToHost, s));
+    PNO_HIP(hipStreamSynchronize(s));
+    for (int a = 0; a < v; ++a) Fh[(size_t)a * v + a] = eh[o + a];
+    for (int i = 0; i < o; ++i) focc[i] = eh[i];
+    DBuf<double> Fs;
+    Fs.alloc(vv);
+    PNO_HIP(hipMemcpy(Fs, Fh.data(), vv * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<int> pi, pj;
+    pnos_from_density(c, P, D, 1.0, tcut_pno, tcut_osv, Fs, focc, pi, pj);
+  }
+  P.nstates = 0;
+  P.tcut_pno = tcut_pno;
+  P.tcut_osv = tcut_osv;
   P.built = true;
 }
 
 // ----------------------------------------------------------------------------- transforms
 void pno_compress(Context& c, int nvec, const double* r1, const double* r2, double* x) {
-  PNOData& P = c.pno;
-  PNO_CHECK(P.built, PNOEOM_ESTATE, "PNO compress before build_sapno");
+  pno_compress(c, c.pno, nvec, r1, r2, x);
+}
+
+void pno_compress(Context& c, PNOData& P, int nvec, const double* r1, const double* r2, double* x) {
+  PNO_CHECK(P.built, PNOEOM_ESTATE, "PNO compress before the PNOs are built");
   hipStream_t s = c.stream;
   const double sq2 = std::sqrt(2.0);
   hipEvent_t ev = c.region_begin(1, s);
@@ -706,8 +773,11 @@ void pno_compress(Context& c, int nvec, const double* r1, const double* r2, doub
 }
 
 void pno_expand(Context& c, int nvec, const double* x, double* r1, double* r2) {
-  PNOData& P = c.pno;
-  PNO_CHECK(P.built, PNOEOM_ESTATE, "PNO expand before build_sapno");
+  pno_expand(c, c.pno, nvec, x, r1, r2);
+}
+
+void pno_expand(Context& c, PNOData& P, int nvec, const double* x, double* r1, double* r2) {
+  PNO_CHECK(P.built, PNOEOM_ESTATE, "PNO expand before the PNOs are built");
   hipStream_t s = c.stream;
   const double isq2 = 1.0 / std::sqrt(2.0);
   hipEvent_t ev = c.region_begin(1, s);
@@ -728,8 +798,9 @@ void pno_expand(Context& c, int nvec, const double* x, double* r1, double* r2) {
                8.0 * nvec * ((double)c.ov() + (double)c.oovv() + (double)P.len + (double)P.U.n));
 }
 
-void project_pno(Context& c, double* x) {
-  PNOData& P = c.pno;
+void project_pno(Context& c, double* x) { project_pno(c, c.pno, x); }
+
+void project_pno(Context& c, PNOData& P, double* x) {
   const int nd = (int)P.d_n.n;
   if (nd == 0) return;
   hipLaunchKernelGGL(sym_diag_blocks_kernel, dim3(nd), dim3(256), 0, c.stream, nd, (const int64_t*)P.d_off,
@@ -737,12 +808,13 @@ void project_pno(Context& c, double* x) {
   PNO_HIP(hipGetLastError());
 }
 
-void precond_pno(Context& c, double* x, double theta) {
-  PNOData& P = c.pno;
+void precond_pno(Context& c, double* x, double theta) { precond_pno(c, c.pno, x, theta); }
+
+void precond_pno(Context& c, PNOData& P, double* x, double theta) {
   hipLaunchKernelGGL(precond_pno_kernel, dim3(gsz(P.len)), dim3(256), 0, c.stream, P.len, theta,
                      (const double*)P.denom_base, x);
   PNO_HIP(hipGetLastError());
-  project_pno(c, x);
+  project_pno(c, P, x);
 }
 
 void sigma_pno(Context& c, int nvec, const double* x, double* y, int precision) {

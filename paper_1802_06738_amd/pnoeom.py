@@ -27,7 +27,7 @@ EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pno
                     "pnoeom_set_graph_mode", "pnoeom_graph_stats", "pnoeom_set_ladder_mode",
                     "pnoeom_build_ladder", "pnoeom_ladder_apply", "pnoeom_set_pno_ladder",
                     "pnoeom_pno_ladder_stats", "pnoeom_set_pno_states", "pnoeom_ccsd_defaults",
-                    "pnoeom_ccsd_residual", "pnoeom_ccsd", "pnoeom_ccsd_history"]
+                    "pnoeom_ccsd_residual", "pnoeom_ccsd", "pnoeom_ccsd_history", "pnoeom_ccsd_gs_counts"]
 
 
 class PnoEomError(RuntimeError):
@@ -46,7 +46,7 @@ class DavidsonOpts(C.Structure):
 
 class CcsdOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("tol_e", C.c_double), ("tol_r", C.c_double), ("diis_size", C.c_int),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("gs_tcut_pno", C.c_double), ("gs_tcut_osv", C.c_double)]
 
 
 _LIB = None
@@ -105,6 +105,7 @@ def load_library():
     lib.pnoeom_ccsd_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp, dp]
     lib.pnoeom_ccsd.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.POINTER(CcsdOpts), dp, dp, ip]
     lib.pnoeom_ccsd_history.argtypes = [vp, C.c_int, dp, dp, ip]
+    lib.pnoeom_ccsd_gs_counts.argtypes = [vp, ip, ip]
     _LIB = lib
     # the autotuner's table of GEMM tile choices for this device, when present
     from .autotune import DEFAULT_TABLE, load_table
@@ -296,11 +297,12 @@ class PnoEom:
         return r1, r2, e.value
 
     def ccsd(self, B, eps, t1=None, t2=None, max_iter=100, tol_e=1e-10, tol_r=1e-8, diis_size=8,
-             precision=FP64, raise_on_notconv=True):
+             precision=FP64, raise_on_notconv=True, gs_tcut_pno=-1.0, gs_tcut_osv=-1.0):
         """Solve the CCSD equations (Jacobi + DIIS) from T1 = 0 and first-order T2, or from the
         given t1 and t2 (both or neither).  Returns dict(t1, t2, e_corr, resmax, iters, converged);
         the context then holds the intermediates at those amplitudes (contraction precision
-        `precision`), ready for sigma / davidson."""
+        `precision`), ready for sigma / davidson.  gs_tcut_pno >= 0: the ground-state PNO
+        simulation (then also npno / nosv, the ground-state PNO and OSV counts)."""
         import torch
         o, v, n = self.o, self.v, self.nmo
         if (t1 is None) != (t2 is None):
@@ -312,6 +314,7 @@ class PnoEom:
         self.lib.pnoeom_ccsd_defaults(C.byref(opts))
         opts.max_iter, opts.tol_e, opts.tol_r = int(max_iter), float(tol_e), float(tol_r)
         opts.diis_size, opts.precision = int(diis_size), int(precision)
+        opts.gs_tcut_pno, opts.gs_tcut_osv = float(gs_tcut_pno), float(gs_tcut_osv)
         e = C.c_double()
         rm = C.c_double()
         it = C.c_int()
@@ -326,8 +329,15 @@ class PnoEom:
         he = np.zeros(n.value)
         hr = np.zeros(n.value)
         self._check(self.lib.pnoeom_ccsd_history(self.h, n.value, _dptr(he), _dptr(hr), C.byref(n)))
-        return dict(t1=t1, t2=t2, e_corr=e.value, resmax=rm.value, iters=it.value, converged=(st == 0),
-                    energies=he, resmax_history=hr)
+        out = dict(t1=t1, t2=t2, e_corr=e.value, resmax=rm.value, iters=it.value, converged=(st == 0),
+                   energies=he, resmax_history=hr)
+        if gs_tcut_pno >= 0:
+            npno = np.zeros(self.o * (self.o + 1) // 2, dtype=np.int32)
+            nosv = np.zeros(self.o, dtype=np.int32)
+            self._check(self.lib.pnoeom_ccsd_gs_counts(self.h, npno.ctypes.data_as(C.POINTER(C.c_int)),
+                                                       nosv.ctypes.data_as(C.POINTER(C.c_int))))
+            out["npno"], out["nosv"] = npno, nosv
+        return out
 
     def set_ladder_mode(self, mode=LADDER_AUTO, max_slab=0):
         """Cached or streamed W+/- for the next build_df (LADDER_AUTO / _CACHED / _STREAMED)."""
