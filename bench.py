@@ -354,6 +354,67 @@ def ccsd_run(args):
     print(json.dumps(out), flush=True)
 
 
+def gs_es_study(args):
+    """Ground- and excited-state PNO truncation errors and their combination, on the reduced
+    PNO workload (o=10, v=100, naux=300, 4 roots): the CCSD ground state canonical or in the
+    ground-state PNO simulation (GS-PNOs of the MP1 pair densities at T_cut,GS), then the
+    EOM-CCSD roots canonical or in the state-averaged PNO space (T_cut,ES), each compared
+    with canonical CCSD + canonical EOM (the comparison of the paper's Results, on synthetic
+    data)."""
+    import torch
+    from synthgen import config_system, CONFIGS
+    from paper_1802_06738_amd import PnoEom, CANONICAL, PNO
+    cfg = CONFIGS["pno_small"]
+    s = config_system("pno_small")
+    o, v, naux, nroots = s.o, s.v, s.naux, cfg["nroots"]
+    dev = torch.device("cuda:0")
+    B = torch.from_numpy(s.B).to(dev)
+    eps = torch.from_numpy(s.eps).to(dev)
+    ctx = PnoEom(o, v, naux)
+    dav = dict(tol_e=1e-9, tol_r=1e-6)
+    gs_cuts = [None, 1e-5, 1e-6, 1e-7]
+    es_cuts = [None, 1e-6, 1e-7]
+    t0 = time.perf_counter()
+    rows = []
+    ref_e = ref_w = None
+    for g in gs_cuts:
+        r = ctx.ccsd(B, eps, tol_r=1e-9, tol_e=1e-11, gs_tcut_pno=-1.0 if g is None else g)
+        t1, t2 = r["t1"], r["t2"]
+        for e_cut in es_cuts:
+            if e_cut is None:
+                w = ctx.davidson(nroots, space=CANONICAL, **dav)["omega"]
+                npno_es = None
+            else:
+                npno_es, _ = ctx.build_sapno(nroots, e_cut)
+                w = ctx.davidson(nroots, space=PNO, **dav)["omega"]
+            if g is None and e_cut is None:
+                ref_e, ref_w = r["e_corr"], w
+            rows.append({"gs_tcut": g, "es_tcut": e_cut,
+                         "gs_npno_mean": None if g is None else float(np.mean(r["npno"])),
+                         "es_npno_mean": None if npno_es is None else float(np.mean(npno_es)),
+                         "ccsd_iters": r["iters"], "e_corr_eh": r["e_corr"],
+                         "omega": [float(x) for x in w]})
+            # the next EOM starts from the intermediates of these amplitudes again
+            ctx.build_df(B, eps, t1, t2)
+    for row in rows:
+        row["d_ecorr_eh"] = row["e_corr_eh"] - ref_e
+        row["d_omega_eh"] = [a - b for a, b in zip(row["omega"], ref_w)]
+    # the combined error against the sum of the separate ones
+    sep = {(r["gs_tcut"], r["es_tcut"]): r["d_omega_eh"] for r in rows}
+    for row in rows:
+        g, e_cut = row["gs_tcut"], row["es_tcut"]
+        if g is not None and e_cut is not None:
+            row["sum_of_separate_eh"] = [a + b for a, b in zip(sep[(g, None)], sep[(None, e_cut)])]
+    out = {"metric": METRIC, "value": None, "unit": "Eh (PNO truncation error per root)",
+           "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * (time.perf_counter() - t0),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"reduced PNO workload o={o}, v={v}, naux={naux}, {nroots} roots: "
+                                  "ground-state (CCSD) and excited-state (EOM) PNO truncation errors"},
+           "reference": {"e_corr_eh": ref_e, "omega": [float(x) for x in ref_w]}, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,6 +429,8 @@ def main():
     ap.add_argument("--graph", type=int, default=1, help="also time the FP64 steps in graph mode (0/1)")
     ap.add_argument("--states-compare", action="store_true",
                     help="PNO truncation error vs the number of averaged states (reduced PNO workload)")
+    ap.add_argument("--gs-es-study", action="store_true",
+                    help="ground- vs excited-state PNO truncation errors (reduced PNO workload)")
     ap.add_argument("--ccsd", action="store_true",
                     help="CCSD ground state, then EOM-CCSD on its amplitudes (config 1-3)")
     ap.add_argument("--pno-ladder", type=int, default=-1,
@@ -384,6 +447,9 @@ def main():
         return
     if args.ccsd:
         ccsd_run(args)
+        return
+    if args.gs_es_study:
+        gs_es_study(args)
         return
 
     import torch
