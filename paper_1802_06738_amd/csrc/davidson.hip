@@ -195,6 +195,104 @@ __global__ __launch_bounds__(64 * kDotWaves) void dots_kernel(int na, int nb, in
   }
 }
 
+// The same products with 16-byte loads, for rows that start 16-byte aligned (even row
+// stride, aligned bases): units of 32 consecutive n, lane (row r, group g) reads the two
+// columns base + 8 j + 2 g + {0, 1} for j = 0..3 (64 contiguous bytes of a row per load
+// instruction) and MFMA step 2 j + h takes column 8 j + 2 g + h, identically for A and B.
+// The operands of a wave's next unit are loaded before the MFMAs of the current one, so two
+// units' reads are in flight per wave (≈ 6 TB/s against ≈ 3 TB/s for the kernel above).
+// NQ = blocks of 16 rows of A (1..4).
+template <int NQ>
+__global__ __launch_bounds__(64 * kDotWaves) void dots_vec_kernel(int na, int nb, int64_t N,
+                                                                  const double* __restrict__ A, int64_t lda,
+                                                                  const double* __restrict__ B, int64_t ldb,
+                                                                  double* __restrict__ part) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  __shared__ double red[kDotWaves][64][17];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  v4 acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = v4{0, 0, 0, 0};
+  // row pointers; rows past the end read row 0 and contribute zeros
+  const double* pa[NQ];
+  bool ma[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int row = q * 16 + r;
+    pa[q] = A + (row < na ? (int64_t)row * lda : 0) + 2 * g;
+    ma[q] = row < na;
+  }
+  const double* pb = B + (r < nb ? (int64_t)r * ldb : 0) + 2 * g;
+  const bool mb = r < nb;
+  const int64_t units = N / 32;
+  const int64_t stride = (int64_t)gridDim.x * kDotWaves;
+  d2 bv[4], av[NQ][4];
+  auto load = [&](int64_t u, d2(&b)[4], d2(&a)[NQ][4]) {
+    const int64_t base = u * 32;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = *(const d2*)(pb + base + 8 * j);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[q][j] = *(const d2*)(pa[q] + base + 8 * j);
+  };
+  int64_t u = (int64_t)blockIdx.x * kDotWaves + wave;
+  if (u < units) load(u, bv, av);
+  while (u < units) {
+    const int64_t un = u + stride;
+    d2 bn[4], an[NQ][4];
+    if (un < units) load(un, bn, an);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double bb = mb ? bv[j][h] : 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[q] ? av[q][j][h] : 0.0, bb, acc[q], 0, 0, 0);
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bv[j] = bn[j];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) av[q][j] = an[q][j];
+    u = un;
+  }
+  // tail n in [32 units, N): one wave of the first workgroup, zero-padded
+  if (blockIdx.x == 0 && wave == 0 && units * 32 < N) {
+    const int64_t base = units * 32;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t n = base + 8 * j + 2 * g + h;
+        const double bb = (n < N && mb) ? pb[base + 8 * j + h] : 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const double aa = (n < N && ma[q]) ? pa[q][base + 8 * j + h] : 0.0;
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa, bb, acc[q], 0, 0, 0);
+        }
+      }
+  }
+  // accumulator r4 of lane l holds row 16 q + l/16 + 4 r4, column l%16
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) red[wave][q * 16 + g + 4 * r4][r] = acc[q][r4];
+  __syncthreads();
+  double* out = part + (int64_t)blockIdx.x * na * nb;
+  for (int e = threadIdx.x; e < na * nb; e += 64 * kDotWaves) {
+    const int i = e / nb, j = e % nb;
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kDotWaves; ++w) sum += red[w][i][j];
+    out[e] = sum;
+  }
+}
+
 struct Dots {
   DBuf<double> part, out;
   Context* ctx = nullptr;  // for the timed region of the inner products
@@ -217,13 +315,25 @@ void dots(hipStream_t s, Dots& w, const double* A, int na, const double* B, int 
   if ((int64_t)w.part.n < groups * nout) w.part.alloc(groups * nout);
   if ((int64_t)w.out.n < nout) w.out.alloc(nout);
   std::vector<double> blk;
+  // 16-byte loads when every row starts 16-byte aligned
+  const bool vec = N % 2 == 0 && (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0;
   // blocks of at most 64 x 16 outputs
   for (int i0 = 0; i0 < na; i0 += 64)
     for (int j0 = 0; j0 < nb; j0 += 16) {
       const int ni = std::min(64, na - i0), nj = std::min(16, nb - j0);
       hipEvent_t ev = w.ctx ? w.ctx->region_begin(0, s) : nullptr;
-      hipLaunchKernelGGL(dots_kernel, dim3((unsigned)groups), dim3(64 * kDotWaves), 0, s, ni, nj, N,
-                         A + (int64_t)i0 * N, N, B + (int64_t)j0 * N, N, (double*)w.part);
+      const double* a0 = A + (int64_t)i0 * N;
+      const double* b0 = B + (int64_t)j0 * N;
+      if (vec) {
+        const int nq = (ni + 15) / 16;
+        auto kern = nq == 1 ? dots_vec_kernel<1> : nq == 2 ? dots_vec_kernel<2> : nq == 3 ? dots_vec_kernel<3>
+                                                                                        : dots_vec_kernel<4>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(64 * kDotWaves), 0, s, ni, nj, N, a0, N, b0, N,
+                           (double*)w.part);
+      } else {
+        hipLaunchKernelGGL(dots_kernel, dim3((unsigned)groups), dim3(64 * kDotWaves), 0, s, ni, nj, N, a0, N, b0, N,
+                           (double*)w.part);
+      }
       PNO_HIP(hipGetLastError());
       const int64_t nsub = (int64_t)ni * nj;
       hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)nsub), dim3(256), 0, s, nsub, groups,
