@@ -621,28 +621,44 @@ void gmbf(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, doub
 namespace {
 // s2[q] = Sd[q] + Z(i,j,a,b) + Z(j,i,b,a) for nb vectors, with
 // Z(i,j,a,b) = Zp[i][j][a][b] + Ziajb[i][a][j][b] + Z3[j][a][i][b] - Cba[i][j][b][a]
-// where Ziajb and Z3 of vector q are the two halves of the rows of ZZ[q] ([(i,a)][2 ov])
-__global__ void assemble_s2_block_kernel(int o, int v, int nb, const double* __restrict__ Sd,
-                                         const double* __restrict__ Zp, const double* __restrict__ ZZ,
-                                         const double* __restrict__ Cba, double* __restrict__ s2,
-                                         int64_t stride2) {
-  const int64_t V = v, O = o, n = O * O * V * V, ov2 = 2 * O * V;
-  const int64_t total = n * nb;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t q = g / n, e = g - q * n;
-    int64_t r = e;
-    const int64_t b = r % V; r /= V;
-    const int64_t a = r % V; r /= V;
-    const int64_t j = r % O;
-    const int64_t i = r / O;
-    const double* zp = Zp + q * n;
-    const double* zz = ZZ + q * 2 * n;
-    const double* cb = Cba + q * n;
-    auto Z = [&](int64_t I, int64_t Jj, int64_t A, int64_t Bb) {
-      return zp[((I * O + Jj) * V + A) * V + Bb] + zz[(I * V + A) * ov2 + Jj * V + Bb] +
-             zz[(Jj * V + A) * ov2 + O * V + I * V + Bb] - cb[((I * O + Jj) * V + Bb) * V + A];
-    };
-    s2[q * stride2 + e] = Sd[g] + Z(i, j, a, b) + Z(j, i, b, a);
+// where Ziajb and Z3 of vector q are the two halves of the rows of ZZ[q] ([(i,a)][2 ov]).
+// Four of the eight reads run along a for fixed b (Cba[i][j][b][:], Zp[j][i][b][:] and the
+// (j,b) / (i,b) rows of ZZ), the other four along b: one workgroup takes a 32 x 32 (a, b)
+// tile of one pair (i, j) of one vector, sums the a-contiguous terms into LDS with lanes
+// along a, and adds them transposed to the b-contiguous terms read and written with lanes
+// along b, so that every global access is a contiguous 256-byte row segment.
+constexpr int kAsmTile = 32;
+__global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, const double* __restrict__ Sd,
+                                                                const double* __restrict__ Zp,
+                                                                const double* __restrict__ ZZ,
+                                                                const double* __restrict__ Cba,
+                                                                double* __restrict__ s2, int64_t stride2) {
+  __shared__ double tile[kAsmTile][kAsmTile + 1];
+  const int64_t V = v, O = o, n = O * O * V * V, ov = O * V, ov2 = 2 * ov;
+  const int ntb = (v + kAsmTile - 1) / kAsmTile;
+  const int a0 = (int)(blockIdx.x / ntb) * kAsmTile, b0 = (int)(blockIdx.x % ntb) * kAsmTile;
+  const int64_t i = blockIdx.y / o, j = blockIdx.y % o, q = blockIdx.z;
+  const int tx = threadIdx.x % kAsmTile, ty = threadIdx.x / kAsmTile;  // 32 x 8
+  const double* zp = Zp + q * n;
+  const double* zz = ZZ + q * 2 * n;
+  const double* cb = Cba + q * n;
+  // terms contiguous along a: tile[b][a]
+  for (int bb = ty; bb < kAsmTile; bb += 256 / kAsmTile) {
+    const int64_t a = a0 + tx, b = b0 + bb;
+    if (a < V && b < V)
+      tile[bb][tx] = zp[((j * O + i) * V + b) * V + a] + zz[(j * V + b) * ov2 + i * V + a] +
+                     zz[(i * V + b) * ov2 + ov + j * V + a] - cb[((i * O + j) * V + b) * V + a];
+  }
+  __syncthreads();
+  // terms contiguous along b, plus the tile transposed
+  for (int aa = ty; aa < kAsmTile; aa += 256 / kAsmTile) {
+    const int64_t a = a0 + aa, b = b0 + tx;
+    if (a < V && b < V) {
+      const int64_t e = ((i * O + j) * V + a) * V + b;
+      s2[q * stride2 + e] = Sd[q * n + e] + zp[e] + zz[(i * V + a) * ov2 + j * V + b] +
+                            zz[(j * V + a) * ov2 + ov + i * V + b] - cb[((j * O + i) * V + a) * V + b] +
+                            tile[tx][aa];
+    }
   }
 }
 
@@ -802,10 +818,14 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   // -P[ sum_k r_k^a Wvo_kbij ] collected as Cba[i][j][b][a] = sum_k Wvo2[(ijb)][k] r1[k][a]
   gmb(s, false, false, oo * v, v, o, 1.0, c.Wvo2, o, 0, r1, v, stride1, 0.0, w.Cba, v, oovv, nb);
 
-  const int64_t tot = nb * oovv;
-  hipLaunchKernelGGL(assemble_s2_block_kernel, dim3(grid1(tot)), dim3(256), 0, s, o, v, nb, (const double*)Sd,
-                     (const double*)w.Zp, (const double*)w.ZZ, (const double*)w.Cba, s2, stride2);
-  PNO_HIP(hipGetLastError());
+  {
+    const unsigned ntb = (unsigned)((v + kAsmTile - 1) / kAsmTile);
+    PNO_CHECK((int64_t)o * o <= 65535 && nb <= 65535, PNOEOM_EINVAL, "sigma: too many pairs or vectors per block");
+    hipLaunchKernelGGL(assemble_s2_tiled_kernel, dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb), dim3(256), 0, s,
+                       o, v, (const double*)Sd, (const double*)w.Zp, (const double*)w.ZZ, (const double*)w.Cba, s2,
+                       stride2);
+    PNO_HIP(hipGetLastError());
+  }
 }
 }  // namespace
 
