@@ -1,6 +1,8 @@
 // Layout kernels: strided 4-index permutation with accumulate, axpby, fill, casts.
 // All are HBM-bound grid-stride loops; consecutive threads write consecutive
 // output elements.
+#include <algorithm>
+
 #include "common.h"
 
 namespace pnoeom {
@@ -22,6 +24,44 @@ __global__ void permute4_kernel(Perm4 p, double alpha, const double* __restrict_
     double val = alpha * x;
     if (beta != 0.0) val += beta * (*y);
     *y = val;
+  }
+}
+
+// The same permutation when the output's innermost axis L (unit output stride) is not the
+// input's unit-stride axis K: 32 x 32 tiles over (K, L) pass through LDS, read with lanes
+// along K and written with lanes along L, so both sides move contiguous row segments.  The
+// other two axes U, W and the batch are enumerated by blockIdx.y (grid-stride).
+template <typename I>
+__global__ __launch_bounds__(256) void permute4_tiled_kernel(Perm4 p, int K, int L, int U, int W, double alpha,
+                                                             const double* __restrict__ in, double beta,
+                                                             double* __restrict__ out, I nrest) {
+  __shared__ double tile[32][33];
+  const I dK = (I)p.d[K], dL = (I)p.d[L], dU = (I)p.d[U], dW = (I)p.d[W];
+  const I ntl = (dL + 31) / 32;
+  const I k0 = (I)(blockIdx.x / ntl) * 32, l0 = (I)(blockIdx.x % ntl) * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 32 x 8
+  for (I rest = blockIdx.y; rest < nrest; rest += gridDim.y) {
+    const I iw = rest % dW;
+    const I t = rest / dW;
+    const I iu = t % dU;
+    const I q = t / dU;
+    const int64_t ib = (int64_t)q * p.ibs + (int64_t)iu * p.is[U] + (int64_t)iw * p.is[W];
+    const int64_t ob = (int64_t)q * p.obs + (int64_t)iu * p.os[U] + (int64_t)iw * p.os[W];
+    for (int l = ty; l < 32; l += 8) {
+      const I ik = k0 + tx, il = l0 + l;
+      if (ik < dK && il < dL) tile[l][tx] = in[ib + (int64_t)ik * p.is[K] + (int64_t)il * p.is[L]];
+    }
+    __syncthreads();
+    for (int kk = ty; kk < 32; kk += 8) {
+      const I ik = k0 + kk, il = l0 + tx;
+      if (ik < dK && il < dL) {
+        double* y = out + ob + (int64_t)ik * p.os[K] + (int64_t)il * p.os[L];
+        double val = alpha * tile[tx][kk];
+        if (beta != 0.0) val += beta * (*y);
+        *y = val;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -65,6 +105,33 @@ void permute4(hipStream_t s, const Perm4& p, double alpha, const double* in, dou
   const int64_t per = p.d[0] * p.d[1] * p.d[2] * p.d[3];
   const int64_t total = per * p.nb;
   if (total == 0) return;
+  // tiled path: L = innermost output axis of extent > 1 (unit output stride), K = an axis
+  // of unit input stride, both at least 8 long
+  int L = -1, K = -1;
+  for (int k = 3; k >= 0; --k)
+    if (p.d[k] > 1) { L = k; break; }
+  if (L >= 0 && p.os[L] == 1 && p.is[L] != 1)
+    for (int k = 0; k < 4; ++k)
+      if (k != L && p.d[k] > 1 && p.is[k] == 1) K = k;
+  if (L >= 0 && K >= 0 && p.d[L] >= 8 && p.d[K] >= 8) {
+    int rest_ax[2], nr = 0;
+    for (int k = 0; k < 4; ++k)
+      if (k != K && k != L) rest_ax[nr++] = k;
+    const int U = rest_ax[0], W = rest_ax[1];
+    const int64_t nrest = p.nb * p.d[U] * p.d[W];
+    const int64_t tiles = ((p.d[K] + 31) / 32) * ((p.d[L] + 31) / 32);
+    if (tiles <= 0x7fffffff) {
+      const unsigned gy = (unsigned)std::min<int64_t>(nrest, 65535);
+      if (total < (1ll << 31))
+        hipLaunchKernelGGL(permute4_tiled_kernel<uint32_t>, dim3((unsigned)tiles, gy), dim3(256), 0, s, p, K, L, U, W,
+                           alpha, in, beta, out, (uint32_t)nrest);
+      else
+        hipLaunchKernelGGL(permute4_tiled_kernel<int64_t>, dim3((unsigned)tiles, gy), dim3(256), 0, s, p, K, L, U, W,
+                           alpha, in, beta, out, nrest);
+      PNO_HIP(hipGetLastError());
+      return;
+    }
+  }
   // 32-bit index arithmetic when the element count allows it (integer division is
   // the cost of this kernel besides the HBM traffic)
   if (total < (1ll << 31))
