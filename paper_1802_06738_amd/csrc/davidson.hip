@@ -293,6 +293,77 @@ __global__ __launch_bounds__(64 * kDotWaves) void dots_vec_kernel(int na, int nb
   }
 }
 
+// Skinny subspace updates C[q][n] = alpha sum_i a(i, q) B[i][n] + beta C[q][n] with a few
+// output rows (q < M <= MQ) and a short sum (i < K) over long rows of length N (the
+// Davidson's Ritz vectors, residuals, Gram-Schmidt and block-orthonormalisation updates):
+// HBM-bound.  Each thread streams two adjacent columns with 16-byte loads, eight rows of B
+// in flight at a time; a(i, q) = A[i sai + q saq] is the same for the whole wave.
+// (at least four waves per SIMD: the loads in flight set its speed)
+template <int MQ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void skinny_kernel(
+    int M, int K, int64_t N, const double* __restrict__ A,
+    int64_t sai, int64_t saq, double alpha, const double* __restrict__ B, double beta, double* __restrict__ C) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const int64_t np = N / 2;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    d2 acc[MQ];
+#pragma unroll
+    for (int q = 0; q < MQ; ++q) acc[q] = d2{0.0, 0.0};
+    const double* b = B + 2 * p;
+    int i = 0;
+    for (; i + 8 <= K; i += 8) {
+      d2 bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) bv[u] = *(const d2*)(b + (int64_t)(i + u) * N);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int q = 0; q < MQ; ++q)
+          if (q < M) acc[q] += A[(int64_t)(i + u) * sai + q * saq] * bv[u];
+    }
+    for (; i < K; ++i) {
+      const d2 bv = *(const d2*)(b + (int64_t)i * N);
+#pragma unroll
+      for (int q = 0; q < MQ; ++q)
+        if (q < M) acc[q] += A[(int64_t)i * sai + q * saq] * bv;
+    }
+#pragma unroll
+    for (int q = 0; q < MQ; ++q)
+      if (q < M) {
+        d2* c = (d2*)(C + (int64_t)q * N + 2 * p);
+        d2 val = alpha * acc[q];
+        if (beta != 0.0) val += beta * (*c);
+        *c = val;
+      }
+  }
+}
+
+// C = alpha op(A) B + beta C for the Davidson's subspace updates (rows of length N, row
+// stride N): a(i, q) = A[i sai + q saq] with sai = 1 or saq = 1.  The streaming kernel when
+// the rows are 16-byte aligned and M <= 16, else the tiled GEMM.
+void skinny(hipStream_t s, int M, int K, int64_t N, const double* A, int64_t sai, int64_t saq, double alpha,
+            const double* B, double beta, double* C) {
+  if (M <= 0 || N <= 0) return;
+  if (M <= 16 && N % 2 == 0 && (uintptr_t)B % 16 == 0 && (uintptr_t)C % 16 == 0) {
+    const int64_t np = N / 2;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (np + 255) / 256));
+    // (an 8-row instance compiles to twice the registers of the 16-row one, so 5..16 rows
+    // share the latter; rows past M are skipped)
+    if (M <= 4)
+      hipLaunchKernelGGL(skinny_kernel<4>, dim3(grid), dim3(256), 0, s, M, K, N, A, sai, saq, alpha, B, beta, C);
+    else
+      hipLaunchKernelGGL(skinny_kernel<16>, dim3(grid), dim3(256), 0, s, M, K, N, A, sai, saq, alpha, B, beta, C);
+    PNO_HIP(hipGetLastError());
+    return;
+  }
+  GemmDesc<double> d;
+  d.ta = saq == 1;
+  d.lda = d.ta ? sai : saq;
+  d.M = M; d.N = N; d.K = K; d.alpha = alpha; d.beta = beta;
+  d.A = A; d.B = B; d.ldb = N; d.C = C; d.ldc = N;
+  gemm(d, s);
+}
+
 struct Dots {
   DBuf<double> part, out;
   Context* ctx = nullptr;  // for the timed region of the inner products
@@ -463,10 +534,7 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
       if (m > 0) {
         dots(s, dw, V, m, x, 1, N, cvec.data());
         PNO_HIP(hipMemcpyAsync(dc, cvec.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
-        GemmDesc<double> d;
-        d.M = 1; d.N = N; d.K = m; d.alpha = -1.0; d.beta = 1.0;
-        d.A = dc; d.lda = m; d.B = V; d.ldb = N; d.C = x; d.ldc = N;
-        gemm(d, s);
+        skinny(s, 1, m, N, dc, 1, m, -1.0, V, 1.0, x);
       }
     }
     double nn = 0.0;
@@ -520,14 +588,8 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
     }
     PNO_HIP(hipMemcpyAsync(dY, Y.data(), Y.size() * sizeof(double), hipMemcpyHostToDevice, s));
     PNO_HIP(hipMemcpyAsync(dth, theta.data(), nroots * sizeof(double), hipMemcpyHostToDevice, s));
-    {
-      GemmDesc<double> d;
-      d.ta = true; d.M = nroots; d.N = N; d.K = m;
-      d.A = dY; d.lda = nroots; d.B = V; d.ldb = N; d.C = X; d.ldc = N;
-      gemm(d, s);
-      d.B = S; d.C = R;
-      gemm(d, s);
-    }
+    skinny(s, nroots, m, N, dY, nroots, 1, 1.0, V, 0.0, X);
+    skinny(s, nroots, m, N, dY, nroots, 1, 1.0, S, 0.0, R);
     hipLaunchKernelGGL(sub_scaled_rows_kernel, dim3(g1(nroots * N)), dim3(256), 0, s, nroots, N,
                        (const double*)dth, (const double*)X, (double*)R);
     std::vector<double> rr((size_t)nroots * nroots);
@@ -613,10 +675,7 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
         for (int pass = 0; pass < 2; ++pass) {
           dots(s, dw, V, m, X, nc, N, coef.data());  // coef[i][q] = V_i . X_q
           PNO_HIP(hipMemcpyAsync(dcb, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
-          GemmDesc<double> d;
-          d.ta = true; d.M = nc; d.N = N; d.K = m; d.alpha = -1.0; d.beta = 1.0;
-          d.A = dcb; d.lda = nc; d.B = V; d.ldb = N; d.C = X; d.ldc = N;
-          gemm(d, s);
+          skinny(s, nc, m, N, dcb, nc, 1, -1.0, V, 1.0, X);
         }
         // orthonormal basis of the block itself: two Gram passes, each X <- T^T X with
         // T = W_k diag(w_k^-1/2) from the eigenpairs (w_k, W_k) of the block's Gram
@@ -643,10 +702,7 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
             break;
           }
           PNO_HIP(hipMemcpyAsync(dcb, Tt.data(), Tt.size() * sizeof(double), hipMemcpyHostToDevice, s));
-          GemmDesc<double> d;
-          d.M = nk; d.N = N; d.K = nb; d.alpha = 1.0; d.beta = 0.0;
-          d.A = dcb; d.lda = nb; d.B = src; d.ldb = N; d.C = dst; d.ldc = N;
-          gemm(d, s);
+          skinny(s, nk, nb, N, dcb, 1, nb, 1.0, src, 0.0, dst);
           nb = nk;
           std::swap(src, dst);
         }
@@ -664,11 +720,8 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
       if (small) {
         res.converged = true;
         if (xout) {  // X held the corrections: the Ritz vectors again, from V and Y
-          GemmDesc<double> d;
-          d.ta = true; d.M = ntarget; d.N = N; d.K = m;  // xout holds the ntarget roots only
-          d.A = dY; d.lda = nroots; d.B = V; d.ldb = N; d.C = xout; d.ldc = N;
           PNO_HIP(hipMemcpyAsync(dY, Y.data(), Y.size() * sizeof(double), hipMemcpyHostToDevice, s));
-          gemm(d, s);
+          skinny(s, ntarget, m, N, dY, nroots, 1, 1.0, V, 0.0, xout);  // xout holds the ntarget roots only
         }
         PNO_HIP(hipStreamSynchronize(s));
         return res;
@@ -679,12 +732,8 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
       // collapse onto the Ritz vectors: V <- V Q, S <- S Q, G <- Q^T G Q
       const std::vector<double> Q = orth_cols(m, nroots, Y);
       PNO_HIP(hipMemcpyAsync(dY, Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice, s));
-      GemmDesc<double> d;
-      d.ta = true; d.M = nroots; d.N = N; d.K = m;
-      d.A = dY; d.lda = nroots; d.B = V; d.ldb = N; d.C = X; d.ldc = N;
-      gemm(d, s);
-      d.B = S; d.C = R;
-      gemm(d, s);
+      skinny(s, nroots, m, N, dY, nroots, 1, 1.0, V, 0.0, X);
+      skinny(s, nroots, m, N, dY, nroots, 1, 1.0, S, 0.0, R);
       // keep the staged new vectors: move them right after the collapsed block
       DBuf<double> stage;
       stage.alloc((int64_t)std::max(nnew, 1) * N);
