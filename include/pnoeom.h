@@ -103,7 +103,9 @@ int pnoeom_build_sapno(pnoeom_ctx* ctx, int nstates, double tcut_pno, double tcu
 /* Length of one PNO-space vector and its layout: singles block [sum_i nosv_i]
  * followed by the pair blocks i <= j, each n_p x n_p row-major.
  *   offsets : host [o + o(o+1)/2 + 1] start of each block (singles of i = 0..o-1,
- *             then pairs) or NULL;  len : host, total length.
+ *             then pairs; the last entry is the end of the blocks) or NULL;
+ *   len : host, total length: the end of the blocks rounded up to an even count (an odd
+ *         total is followed by one padding element, which compress sets to zero).
  * Off-diagonal pair blocks are stored multiplied by sqrt(2), so the plain dot
  * product of two PNO-space vectors is the full-array Frobenius inner product.
  * Requires build_sapno.  Errors: ESTATE. */

@@ -546,7 +546,9 @@ void pnos_from_density(Context& c, PNOData& P, const double* D, double inv_n, do
   P.off.assign(o + npair + 1, 0);
   for (int i = 0; i < o; ++i) P.off[i + 1] = P.off[i] + P.nosv[i];
   for (int p = 0; p < npair; ++p) P.off[o + p + 1] = P.off[o + p] + (int64_t)P.npno[p] * P.npno[p];
-  P.len = P.off[o + npair];
+  // an odd total gets one trailing zero element: rows of even length start 16-byte aligned,
+  // which the Davidson's streaming inner products and updates need
+  P.len = P.off[o + npair] + (P.off[o + npair] & 1);
   P.uoff = uoff;
   P.xf_flops = 0;
   for (int p = 0; p < npair; ++p)
@@ -555,7 +557,7 @@ void pnos_from_density(Context& c, PNOData& P, const double* D, double inv_n, do
   P.nmax = nmax;
   PNO_CHECK(P.len > 0, PNOEOM_EINVAL, "PNO build: every PNO and OSV was truncated");
   // preconditioner base: F_ii (+ F_jj) - fbar_a (- fbar_b); weights
-  std::vector<double> base(P.len);
+  std::vector<double> base(P.len, 1.0);  // (the padding element: 1, so that it stays 0)
   for (int i = 0; i < o; ++i) {
     const int b = npair + i;
     for (int a = 0; a < P.nosv[i]; ++a)
@@ -767,6 +769,8 @@ void pno_compress(Context& c, PNOData& P, int nvec, const double* r1, const doub
     gemm_grouped(P.t_c3, 1.0, a2, P.U, 0.0, P.Tw, s);
     gemm_grouped(P.t_c2d, 1.0, P.U, P.Tw, 0.0, y, s);
     gemm_grouped(P.t_c2o, sq2, P.U, P.Tw, 0.0, y, s);
+    const int64_t end = P.off.back();
+    if (P.len > end) fill(s, P.len - end, 0.0, y + end);  // padding
   }
   c.region_end(ev, 1, s, 4 * nvec, nvec * P.xf_flops,
                8.0 * nvec * ((double)c.ov() + (double)c.oovv() + (double)P.len + (double)P.U.n));
