@@ -9,8 +9,10 @@ namespace pnoeom {
 struct SigmaWork {
   DBuf<double> Bp, hp, Jp, Kp, fp, dp, fp_ov, fp_vv, fp_oo;
   DBuf<double> BvopT, BoopT, BvvpT;
-  DBuf<double> R2c, Ria, Rsia, UiaR, UR, URp, Ubr;
-  DBuf<double> ZZ, EXT, Zp, Cba, Xh, O4p, OOVVp, M1;  // ZZ[(q,i,a)][Ziajb row | Z3 row]
+  DBuf<double> R2c, Ria, UiaR, UR, URp, Ubr;
+  // ZZ[(q,i,a)][Ziajb row | Z3 row]; RE[(q,i,a)][R^s row | E_X row] (the stacked left operand
+  // of the fused ring product)
+  DBuf<double> ZZ, RE, Zp, Cba, Xh, O4p, OOVVp, M1;
   DBuf<double> Ftv, Fto;
   DBuf<double> LadAll, Sp, Am, SigP, SigM;  // batched packed ladder
   DBuf<float> Spf, Amf, SigPf, SigMf;
@@ -19,7 +21,7 @@ struct SigmaWork {
   DBuf<float> fa, fc;
   void release() {
     for (DBuf<double>* b : {&Bp, &hp, &Jp, &Kp, &fp, &dp, &fp_ov, &fp_vv, &fp_oo, &BvopT, &BoopT, &BvvpT, &R2c, &Ria,
-                            &Rsia, &UiaR, &UR, &URp, &Ubr, &ZZ, &EXT, &Zp, &Cba, &Xh, &O4p,
+                            &UiaR, &UR, &URp, &Ubr, &ZZ, &RE, &Zp, &Cba, &Xh, &O4p,
                             &OOVVp, &M1, &Ftv, &Fto, &LadAll, &Sp, &Am, &SigP, &SigM})
       b->release();
     for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fc}) b->release();
@@ -89,15 +91,15 @@ struct Context {
   DBuf<double> G, GX, g2, Gq, OVVO, OOVVx, Wh, OOOVp;
   DBuf<double> Fqvv, Fqoo, Fvv, Foo, fd_ov;
   DBuf<double> Dr, Xr, DX2, Wvo2, YU;
-  // ring operands side by side, rows of 2 ov: [Dr | Xr] and [Tia | Tsia] (the products
-  // with R^s and with E_X share their left operand)
-  DBuf<double> DXr, TTs;
+  // ring operands, rows of 2 ov: [Dr | Xr] (rows 0..ov-1) stacked on [Tia | Tsia] (rows
+  // ov..2ov-1), the right operand of the fused product [R^s | E_X] DXTT
+  DBuf<double> DXTT;
   // packed ladder: W+[(a<=b),(c<=d)] = W_abcd + W_abdc, W-[(a<b),(c<d)] = W_abcd - W_abdc
   DBuf<double> Wp, Wm;          // FP64 (always: the FP64 sigma and the refinement of mixed runs)
   DBuf<float> Wpf, Wmf;         // FP32 (precision FP32)
   DBuf<uint16_t> Wpb, Wmb;      // bfloat16 bits (precision BF16), rows padded to ldpb / ldmb columns
   int64_t ldpb = 0, ldmb = 0;
-  DBuf<float> DX2f, DXrf, TTsf;
+  DBuf<float> DX2f, DXTTf;
   // build-time temporaries of build_df, by slot (each slot's uses follow one another on the
   // stream); kept between builds while keep_build_tmp is set (the repeated builds of the
   // CCSD solver then allocate nothing), else released at the end of each build

@@ -265,7 +265,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   if (!c.keep_build_tmp) c.sw.release();  // (the CCSD iteration keeps its FP64 sigma workspaces)
   c.pno.reset();
   if (precision == PNOEOM_FP64)
-    for (DBuf<float>* b : {&c.DX2f, &c.DXrf, &c.TTsf}) b->release();
+    for (DBuf<float>* b : {&c.DX2f, &c.DXTTf}) b->release();
 
   c.B.alloc((int64_t)naux * n2);
   c.eps.alloc(nmo);
@@ -401,15 +401,15 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   gm(s, false, true, ov, ov, ov, -1.0, c.GX, ov, c.Tsia, ov, 1.0, c.Xr, ov);
   PNO_HIP(hipMemcpyAsync(c.DX2, c.Xr, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
   axpby(s, oovv, 2.0, c.Dr, -1.0, c.DX2);
-  // side-by-side copies for the ring products: [Dr | Xr] and [Tia | Tsia], rows of 2 ov
-  c.DXr.alloc(2 * oovv);
-  c.TTs.alloc(2 * oovv);
+  // the right operand of the fused ring product: [Dr | Xr] stacked on [Tia | Tsia], rows of 2 ov
+  c.DXTT.alloc(4 * oovv);
   {
     const size_t row = (size_t)ov * sizeof(double), pitch = 2 * row;
-    PNO_HIP(hipMemcpy2DAsync(c.DXr, pitch, c.Dr, row, row, ov, hipMemcpyDeviceToDevice, s));
-    PNO_HIP(hipMemcpy2DAsync(c.DXr + ov, pitch, c.Xr, row, row, ov, hipMemcpyDeviceToDevice, s));
-    PNO_HIP(hipMemcpy2DAsync(c.TTs, pitch, c.Tia, row, row, ov, hipMemcpyDeviceToDevice, s));
-    PNO_HIP(hipMemcpy2DAsync(c.TTs + ov, pitch, c.Tsia, row, row, ov, hipMemcpyDeviceToDevice, s));
+    double* tt = c.DXTT + 2 * oovv;
+    PNO_HIP(hipMemcpy2DAsync(c.DXTT, pitch, c.Dr, row, row, ov, hipMemcpyDeviceToDevice, s));
+    PNO_HIP(hipMemcpy2DAsync(c.DXTT + ov, pitch, c.Xr, row, row, ov, hipMemcpyDeviceToDevice, s));
+    PNO_HIP(hipMemcpy2DAsync(tt, pitch, c.Tia, row, row, ov, hipMemcpyDeviceToDevice, s));
+    PNO_HIP(hipMemcpy2DAsync(tt + ov, pitch, c.Tsia, row, row, ov, hipMemcpyDeviceToDevice, s));
   }
   // YU[Q][(k,c)] = sum_(j,b) B_jb^Q (2 T - T^s)[(j,b),(k,c)]: the Coulomb (DF) part of the
   // R-side ring intermediate contracted with T ahead of time
@@ -504,14 +504,12 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   }
   if (precision == PNOEOM_FP32 || precision == PNOEOM_BF16) {  // FP32 operands of the other contractions
     c.DX2f.alloc(oovv);
-    c.DXrf.alloc(2 * oovv);
-    c.TTsf.alloc(2 * oovv);
+    c.DXTTf.alloc(4 * oovv);
     to_float(s, oovv, c.DX2, c.DX2f);
-    to_float(s, 2 * oovv, c.DXr, c.DXrf);
-    to_float(s, 2 * oovv, c.TTs, c.TTsf);
+    to_float(s, 4 * oovv, c.DXTT, c.DXTTf);
   }
   PNO_HIP(hipStreamSynchronize(s));
-  // kept only side by side (DXr, TTs) from here on
+  // kept only stacked (DXTT) from here on
   c.Dr.release(); c.Xr.release(); c.Tia.release(); c.Tsia.release();
   if (!c.keep_build_tmp)
     for (DBuf<double>& b : c.btmp) b.release();
@@ -530,7 +528,7 @@ int64_t rest_bytes_per_vector(const Context& c, bool f32) {
   const int64_t ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, oovv = c.oovv();
   int64_t nd = 13 * oovv + (ov + oo + vv) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv + oo + vv + oo;
   int64_t bytes = nd * (int64_t)sizeof(double);
-  if (f32) bytes += 3 * oovv * (int64_t)sizeof(float);  // fa (one oovv) and fc (two)
+  if (f32) bytes += 4 * oovv * (int64_t)sizeof(float);  // fa and fc (two oovv each)
   return bytes;
 }
 
@@ -557,8 +555,8 @@ int64_t sigma_held_bytes(const Context& c) {
   const SigmaWork& w = c.sw;
   int64_t b = 0;
   for (const DBuf<double>* x : {&w.Bp, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT,
-                                &w.BoopT, &w.BvvpT, &w.R2c, &w.Ria, &w.Rsia, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.ZZ,
-                                &w.EXT, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.Ftv, &w.Fto,
+                                &w.BoopT, &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.ZZ,
+                                &w.RE, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.Ftv, &w.Fto,
                                 &w.LadAll, &w.Sp, &w.Am, &w.SigP, &w.SigM, &c.pno.r1, &c.pno.r2, &c.pno.s1,
                                 &c.pno.s2})
     b += (int64_t)x->n * 8;
@@ -594,14 +592,14 @@ void alloc_sigma_work(Context& c, int precision, int nb) {
   grow(w.fp_ov, B * ov); grow(w.fp_vv, B * vv); grow(w.fp_oo, B * oo);
   grow(w.BvopT, B * ov * c.naux); grow(w.BoopT, B * oo * c.naux); grow(w.BvvpT, B * vv * c.naux);
   grow(w.R2c, B * oovv);
-  grow(w.Ria, B * oovv); grow(w.Rsia, B * oovv); grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
+  grow(w.Ria, B * oovv); grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
   grow(w.URp, B * oovv); grow(w.Ubr, B * oovv);
-  grow(w.ZZ, 2 * B * oovv); grow(w.EXT, B * oovv);
+  grow(w.ZZ, 2 * B * oovv); grow(w.RE, 2 * B * oovv);
   grow(w.Zp, B * oovv); grow(w.Cba, B * oovv); grow(w.OOVVp, B * oovv);
   grow(w.Xh, B * oo * oo); grow(w.O4p, B * oo * oo); grow(w.M1, B * ov * c.naux);
   grow(w.Ftv, B * vv); grow(w.Fto, B * oo);
   if (precision != PNOEOM_FP64) {
-    grow(w.fa, B * oovv); grow(w.fc, 2 * B * oovv);
+    grow(w.fa, 2 * B * oovv); grow(w.fc, 2 * B * oovv);
   }
 }
 
@@ -715,9 +713,24 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   }
   const int64_t nbo = (int64_t)nb * o;
   perm(s, R2, nbo, o, v, v, 0, 2, 1, 3, w.Ria);
-  perm(s, R2, nbo, o, v, v, 0, 3, 1, 2, w.Rsia);
+  const int64_t ov2 = 2 * ov;
+  {
+    // R^s[(q,i,b)][(j,a)] = R[q][i][j][a][b] into the left half of the rows of RE
+    Perm4 p;
+    p.d[0] = nbo; p.d[1] = v; p.d[2] = o; p.d[3] = v;
+    p.is[0] = (int64_t)o * vv; p.is[1] = 1; p.is[2] = vv; p.is[3] = v;
+    p.os[0] = (int64_t)v * ov2; p.os[1] = ov2; p.os[2] = v; p.os[3] = 1;
+    permute4(s, p, 1.0, R2, 0.0, w.RE);
+  }
   PNO_HIP(hipMemcpyAsync(w.UiaR, w.Ria, nb * oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
-  axpby(s, nb * oovv, -1.0, w.Rsia, 2.0, w.UiaR);
+  {
+    // UiaR = 2 R_ia - R^s (R^s read from RE)
+    Perm4 p;
+    p.d[0] = (int64_t)nb * ov; p.d[1] = ov; p.d[2] = 1; p.d[3] = 1;
+    p.is[0] = ov2; p.is[1] = 1; p.is[2] = 0; p.is[3] = 0;
+    p.os[0] = ov; p.os[1] = 1; p.os[2] = 0; p.os[3] = 0;
+    permute4(s, p, -1.0, w.RE, 2.0, w.UiaR);
+  }
   perm(s, R2, nbo, o, v, v, 0, 1, 3, 2, w.UR, -1.0, 0.0);
   axpby(s, nb * oovv, 2.0, R2, 1.0, w.UR);
   perm(s, w.UR, nbo, o, v, v, 0, 1, 3, 2, w.URp);
@@ -761,45 +774,45 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   gmb(s, false, true, oo, vv, naux, 1.0, w.BoopT, naux, oon, c.BvvT, naux, 0, 0.0, w.OOVVp, vv, oovv, nb);
   gmb(s, false, true, oo, vv, naux, 1.0, c.BooT, naux, 0, w.BvvpT, naux, vvn, 1.0, w.OOVVp, vv, oovv, nb);
   {
-    // EXT[(j,a),(i,b)] = (ij|ab)' = OOVVp[i][j][a][b]
-    const int64_t dims[4] = {o, o, v, v};
-    const int pp[4] = {1, 2, 0, 3};
-    permute_c(s, dims, pp, 1.0, w.OOVVp, 0.0, w.EXT, nb);
+    // E_X[(j,a),(i,b)] = (ij|ab)' = OOVVp[i][j][a][b] into the right half of the rows of RE
+    Perm4 p;
+    p.d[0] = o; p.d[1] = v; p.d[2] = o; p.d[3] = v;
+    p.is[0] = vv; p.is[1] = v; p.is[2] = (int64_t)o * vv; p.is[3] = 1;
+    p.os[0] = (int64_t)v * ov2; p.os[1] = ov2; p.os[2] = v; p.os[3] = 1;
+    p.nb = nb; p.ibs = oovv; p.obs = 2 * oovv;
+    permute4(s, p, 1.0, w.OOVVp, 0.0, w.RE + ov);
   }
-  // The per-vector operands are stacked ([nb][ov][ov] is nb*ov rows), so each product
-  // with a fixed right operand is one tall GEMM; R^s and E_X multiply [Dr | Xr] and
-  // [Tia | Tsia] at once, filling both halves of the rows of ZZ = [Ziajb | Z3].
-  const int64_t M = (int64_t)nb * ov, ov2 = 2 * ov;
+  // The per-vector operands are stacked ([nb][ov][...] is nb*ov rows), so each product
+  // with a fixed right operand is one tall GEMM.  R^s [Dr | Xr] + E_X [Tia | Tsia] is one
+  // product with K = 2 ov: [R^s | E_X] (rows of RE) times [Dr | Xr] stacked on [Tia | Tsia]
+  // (DXTT), filling both halves of the rows of ZZ = [Ziajb | Z3]; R_ia DX2 adds into the
+  // Ziajb half.
+  const int64_t M = (int64_t)nb * ov;
   hipEvent_t ring_ev = c.region_begin(3, s);
   if (f32) {
     float* fa = w.fa;
     float* fc = w.fc;
     const int64_t nt = nb * oovv;
     GemmDesc<float> d;
-    d.M = M; d.N = ov2; d.K = ov; d.alpha = -1.f; d.beta = 0.f; d.lda = ov; d.ldb = ov2; d.C = fc; d.ldc = ov2;
+    d.M = M; d.N = ov2; d.K = ov2; d.alpha = -1.f; d.beta = 0.f; d.lda = ov2; d.ldb = ov2; d.C = fc; d.ldc = ov2;
     d.tag = 3;
-    to_float(s, nt, w.Rsia, fa);
-    d.A = fa; d.B = c.DXrf;
-    gemm(d, s);
-    to_float(s, nt, w.EXT, fa);
-    d.B = c.TTsf; d.beta = 1.f;
+    to_float(s, 2 * nt, w.RE, fa);
+    d.A = fa; d.B = c.DXTTf;
     gemm(d, s);
     to_float(s, nt, w.Ria, fa);
-    d.N = ov; d.alpha = 1.f; d.B = c.DX2f; d.ldb = ov;
+    d.N = ov; d.K = ov; d.alpha = 1.f; d.beta = 1.f; d.A = fa; d.lda = ov; d.B = c.DX2f; d.ldb = ov;
     gemm(d, s);
     to_double(s, 2 * nt, fc, w.ZZ, 0.0);
   } else {
     GemmDesc<double> d;
-    d.M = M; d.N = ov2; d.K = ov; d.alpha = -1.0; d.beta = 0.0; d.lda = ov; d.ldb = ov2; d.C = w.ZZ; d.ldc = ov2;
+    d.M = M; d.N = ov2; d.K = ov2; d.alpha = -1.0; d.beta = 0.0; d.lda = ov2; d.ldb = ov2; d.C = w.ZZ; d.ldc = ov2;
     d.tag = 3;
-    d.A = w.Rsia; d.B = c.DXr;
+    d.A = w.RE; d.B = c.DXTT;
     gemm(d, s);
-    d.A = w.EXT; d.B = c.TTs; d.beta = 1.0;
-    gemm(d, s);
-    d.N = ov; d.alpha = 1.0; d.A = w.Ria; d.B = c.DX2; d.ldb = ov;
+    d.N = ov; d.K = ov; d.alpha = 1.0; d.beta = 1.0; d.A = w.Ria; d.lda = ov; d.B = c.DX2; d.ldb = ov;
     gemm(d, s);
   }
-  c.region_end(ring_ev, 3, s, 3, 10.0 * (double)M * ov * ov, 8.0 * (3.0 * M * ov + 5.0 * oovv + 6.0 * M * ov));
+  c.region_end(ring_ev, 3, s, 2, 10.0 * (double)M * ov * ov, 8.0 * (3.0 * M * ov + 5.0 * oovv + 4.0 * M * ov));
   // the DF-factorised parts of the ring terms, into the Ziajb half
   gmb(s, false, true, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.BvoT, naux, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
   gmb(s, false, false, ov, ov, naux, 0.5, w.M1, naux, ovn, c.YU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
@@ -1016,8 +1029,8 @@ uint64_t sigma_signature(Context& c, hipStream_t s) {
   };
   SigmaWork& w = c.sw;
   for (DBuf<double>* b : {&w.Bp, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT, &w.BoopT,
-                          &w.BvvpT, &w.R2c, &w.Ria, &w.Rsia, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.ZZ,
-                          &w.EXT, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.Ftv, &w.Fto, &w.LadAll, &w.Sp,
+                          &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.ZZ,
+                          &w.RE, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.Ftv, &w.Fto, &w.LadAll, &w.Sp,
                           &w.Am, &w.SigP, &w.SigM, &c.pno.Tw, &c.pno.r1, &c.pno.r2, &c.pno.s1, &c.pno.s2, &c.gin,
                           &c.gout})
     mix(b->p, b->n);
