@@ -34,27 +34,37 @@ HBM_PEAK = 8000.0                       # GB/s
 
 # HBM bytes per launch of the dominant FP64 GEMMs on the o=20, v=150 canonical workload, from
 # two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; profiles/gemm_fp64_config2_traffic.md), scaled by
-# what the counter reads for a 1 GiB + 1 GiB device copy.  Valid only for the dense GEMM kernel
-# and launch code they were taken on (the marked region of gemm.hip, by hash): reported as null
-# once that code changes.
-_GEMM_SHA = "7f0ba202620fb461f47a1224df63e9f2906f95f683fde2523dfa5fe4cf870b04"
+# what the counter reads for a 1 GiB + 1 GiB device copy.  Valid only for the code and tile
+# choices they were taken on: the marked dense GEMM region of gemm.hip, the marked ring launches
+# of sigma.hip and the GEMM tile table, by hash; reported as null once any of them changes.
+_GEMM_SHA = "63d45d328083567bd01aabee800cbc55ca81199ee0a00688df8093bd24fc4ff1"
 KERNEL_TRAFFIC = {
-    "ring": {"config": 2, "gemm_sha256": _GEMM_SHA, "fetch_kib": 6831362.8, "fetch_scale": 1048576.0 / 524303.3,
-             "write_kib": 441051.1, "write_scale": 1048576.0 / 1048576.3},
-    "ladder": {"config": 2, "gemm_sha256": _GEMM_SHA, "fetch_kib": 2875681.3, "fetch_scale": 1048576.0 / 524303.3,
-               "write_kib": 130211.0, "write_scale": 1048576.0 / 1048576.3},
+    "ring": {"config": 2, "gemm_sha256": _GEMM_SHA, "fetch_kib": 10493238.1, "fetch_scale": 1048576.0 / 524303.7,
+             "write_kib": 396946.0, "write_scale": 1048576.0 / 1048576.2},
+    "ladder": {"config": 2, "gemm_sha256": _GEMM_SHA, "fetch_kib": 2815741.7, "fetch_scale": 1048576.0 / 524303.7,
+               "write_kib": 132203.1, "write_scale": 1048576.0 / 1048576.2},
 }
 
 
-def gemm_kernel_sha():
-    """sha256 of the dense GEMM kernel and its launch code (the marked region of gemm.hip)."""
-    import hashlib
-    src = os.path.join(ROOT, "paper_1802_06738_amd", "csrc", "gemm.hip")
-    with open(src) as fh:
+def _region(path, tag):
+    with open(path) as fh:
         text = fh.read()
-    a = text.index("// ==== dense GEMM kernel and its launch: begin")
-    b = text.index("// ==== dense GEMM kernel and its launch: end")
-    return hashlib.sha256(text[text.index("\n", a) + 1:b].encode()).hexdigest()
+    a = text.index(f"// ==== {tag}: begin")
+    b = text.index(f"// ==== {tag}: end")
+    return text[text.index("\n", a) + 1:b]
+
+
+def gemm_kernel_sha():
+    """sha256 over the dense GEMM kernel and its launch code (the marked region of gemm.hip),
+    the ring product launches (the marked region of sigma.hip) and the GEMM tile table."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1802_06738_amd", "csrc")
+    h = hashlib.sha256()
+    h.update(_region(os.path.join(csrc, "gemm.hip"), "dense GEMM kernel and its launch").encode())
+    h.update(_region(os.path.join(csrc, "sigma.hip"), "ring product launches").encode())
+    with open(os.path.join(ROOT, "paper_1802_06738_amd", "tuning", "gemm_gfx950.json"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
 
 
 def kernel_traffic(name, config, pno_only):

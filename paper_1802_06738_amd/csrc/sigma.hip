@@ -788,6 +788,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   // (DXTT), filling both halves of the rows of ZZ = [Ziajb | Z3]; R_ia DX2 adds into the
   // Ziajb half.
   const int64_t M = (int64_t)nb * ov;
+  // ==== ring product launches: begin
   hipEvent_t ring_ev = c.region_begin(3, s);
   if (f32) {
     float* fa = w.fa;
@@ -813,6 +814,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     gemm(d, s);
   }
   c.region_end(ring_ev, 3, s, 2, 10.0 * (double)M * ov * ov, 8.0 * (3.0 * M * ov + 5.0 * oovv + 4.0 * M * ov));
+  // ==== ring product launches: end
   // the DF-factorised parts of the ring terms, into the Ziajb half
   gmb(s, false, true, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.BvoT, naux, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
   gmb(s, false, false, ov, ov, naux, 0.5, w.M1, naux, ovn, c.YU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
