@@ -91,6 +91,7 @@ struct Context {
   DBuf<double> G, GX, g2, Gq, OVVO, OOVVx, Wh, OOOVp;
   DBuf<double> Fqvv, Fqoo, Fvv, Foo, fd_ov;
   DBuf<double> Dr, Xr, DX2, Wvo2, YU;
+  DBuf<double> BYU;  // [Q][(j,b)] = B~^Q_bj + YU[Q][(j,b)]: the right factor of the DF ring terms of B'_vo
   // ring operands, rows of 2 ov: [Dr | Xr] (rows 0..ov-1) stacked on [Tia | Tsia] (rows
   // ov..2ov-1), the right operand of the fused product [R^s | E_X] DXTT
   DBuf<double> DXTT;

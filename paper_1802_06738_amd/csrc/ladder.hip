@@ -368,7 +368,7 @@ void build_ladder(Context& c, const double* B, const double* t1, int precision, 
   c.precision = precision;
   // the cached ladder and the other intermediates of a previous build_df are not valid any more
   for (DBuf<double>* b : {&c.Wp, &c.Wm, &c.Bt, &c.BovT, &c.BvoT, &c.BooT, &c.BvvT, &c.Bvv2, &c.G, &c.GX, &c.T,
-                          &c.U, &c.Tia, &c.Tsia, &c.UiaT, &c.OVVO, &c.OOVVx, &c.Dr, &c.Xr, &c.DX2, &c.YU, &c.B,
+                          &c.U, &c.Tia, &c.Tsia, &c.UiaT, &c.OVVO, &c.OOVVx, &c.Dr, &c.Xr, &c.DX2, &c.YU, &c.BYU, &c.B,
                           &c.DXTT})
     b->release();
   for (DBuf<float>* b : {&c.Wpf, &c.Wmf, &c.DX2f, &c.DXTTf}) b->release();

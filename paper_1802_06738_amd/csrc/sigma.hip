@@ -419,6 +419,10 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     axpby(s, oovv, 2.0, c.Tia, -1.0, U2);
     c.YU.alloc((int64_t)naux * ov);
     gm(s, true, false, naux, ov, ov, 1.0, c.BovT, naux, U2, ov, 0.0, c.YU, ov);
+    // B'_vo enters the ring terms through B'_vo (B~_vo^T + YU): one factor for both
+    c.BYU.alloc((int64_t)naux * ov);
+    perm(s, c.BvoT, ov, naux, 1, 1, 1, 0, 2, 3, c.BYU);
+    axpby(s, (int64_t)naux * ov, 1.0, c.YU, 1.0, c.BYU);
     PNO_HIP(hipStreamSynchronize(s));
   }
 
@@ -816,9 +820,8 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   c.region_end(ring_ev, 3, s, 2, 10.0 * (double)M * ov * ov, 8.0 * (3.0 * M * ov + 5.0 * oovv + 4.0 * M * ov));
   // ==== ring product launches: end
   // the DF-factorised parts of the ring terms, into the Ziajb half
-  gmb(s, false, true, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.BvoT, naux, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
+  gmb(s, false, false, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.BYU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
   gmb(s, false, false, ov, ov, naux, 0.5, w.M1, naux, ovn, c.YU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
-  gmb(s, false, false, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.YU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
 
   // ---------------------------------------------------------------- Fock-type terms in [i][j][a][b]
   gm(s, false, true, (int64_t)nb * oo * v, v, v, 1.0, R2, v, c.Fvv, v, 0.0, w.Zp, v);
