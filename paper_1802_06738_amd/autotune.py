@@ -12,7 +12,7 @@ wider) are chosen per shape.  This tuner
      present, when the library is loaded).
 
 Run on the GPU:
-    python -m paper_1802_06738_amd.autotune --config 2 --out gpurun_out/gemm_gfx950.json
+    python -m paper_1802_06738_amd.autotune --config 2 --out /tmp/gemm_gfx950.json
 """
 from __future__ import annotations
 
