@@ -222,7 +222,9 @@ typedef struct {
                               in the FP64 refinement) */
   const char* log_path;    /* NULL, or a file to which one JSON line per iteration is appended:
                               phase, iteration, subspace size, sigma count, Ritz values, residual
-                              norms, changes of the Ritz values, seconds since the call began */
+                              norms, changes of the Ritz values, seconds since the call began and
+                              seconds spent in sigma so far (the stream is synchronised around
+                              each sigma block only when a log is written) */
 } pnoeom_davidson_opts;
 
 /* Fill opts with the defaults (canonical, FP64, tol_e 1e-8, tol_r 1e-5, max_sub 60,

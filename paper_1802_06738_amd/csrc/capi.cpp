@@ -128,6 +128,7 @@ const char* pnoeom_last_error(const pnoeom_ctx* ctx) { return ctx ? ctx->c.err.c
 int pnoeom_build_df(pnoeom_ctx* ctx, const double* B, const double* eps, const double* t1, const double* t2,
                     int precision) {
   return guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom::TraceRange tr_("pnoeom_build_df");
     PNO_CHECK(B && eps, PNOEOM_EINVAL, "build_df: B and eps are required");
     PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32 || precision == PNOEOM_BF16, PNOEOM_EINVAL,
               "build_df: precision must be PNOEOM_FP64, PNOEOM_FP32 or PNOEOM_BF16");
@@ -137,6 +138,7 @@ int pnoeom_build_df(pnoeom_ctx* ctx, const double* B, const double* eps, const d
 
 int pnoeom_cis(pnoeom_ctx* ctx, int nroots, double* omega_out, double* vec_out) {
   return guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom::TraceRange tr_("pnoeom_cis");
     PNO_CHECK(omega_out, PNOEOM_EINVAL, "cis: omega_out is required");
     pnoeom::cis_roots(c, nroots, omega_out, vec_out);
   });
@@ -145,6 +147,7 @@ int pnoeom_cis(pnoeom_ctx* ctx, int nroots, double* omega_out, double* vec_out) 
 int pnoeom_build_sapno(pnoeom_ctx* ctx, int nstates, double tcut_pno, double tcut_osv, int* npno_out,
                        int* nosv_out) {
   return guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom::TraceRange tr_("pnoeom_build_sapno");
     PNO_CHECK(c.have_df, PNOEOM_ESTATE, "build_sapno before build_df");
     PNO_CHECK(nstates >= 1 && tcut_pno >= 0.0, PNOEOM_EINVAL, "build_sapno: bad arguments");
     pnoeom::build_sapno(c, nstates, tcut_pno, tcut_osv < 0 ? tcut_pno / 10.0 : tcut_osv);
@@ -166,6 +169,7 @@ int pnoeom_pno_layout(const pnoeom_ctx* cctx, long long* offsets, long long* len
 
 int pnoeom_pno_transform(pnoeom_ctx* ctx, int nvec, int direction, double* r1, double* r2, double* x) {
   return guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom::TraceRange tr_("pnoeom_pno_transform");
     PNO_CHECK(c.pno.built, PNOEOM_ESTATE, "pno_transform before build_sapno");
     PNO_CHECK(nvec >= 0 && (direction == 0 || direction == 1), PNOEOM_EINVAL, "pno_transform: bad arguments");
     PNO_CHECK(r1 && r2 && x, PNOEOM_EINVAL, "pno_transform: null pointer");
@@ -180,6 +184,7 @@ int pnoeom_pno_transform(pnoeom_ctx* ctx, int nvec, int direction, double* r1, d
 int pnoeom_apply_sigma(pnoeom_ctx* ctx, int nvec, const double* r1, const double* r2, double* s1, double* s2,
                        int space, int precision) {
   return guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom::TraceRange tr_("pnoeom_apply_sigma");
     PNO_CHECK(c.have_df, PNOEOM_ESTATE, "apply_sigma before build_df");
     PNO_CHECK(nvec >= 0, PNOEOM_EINVAL, "apply_sigma: nvec < 0");
     PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32 || precision == PNOEOM_BF16, PNOEOM_EINVAL,
@@ -231,6 +236,7 @@ int pnoeom_set_ladder_mode(pnoeom_ctx* ctx, int mode, int max_slab) {
 
 int pnoeom_build_ladder(pnoeom_ctx* ctx, const double* B, const double* t1, int precision) {
   return guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom::TraceRange tr_("pnoeom_build_ladder");
     PNO_CHECK(B, PNOEOM_EINVAL, "build_ladder: B is required");
     PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32 || precision == PNOEOM_BF16, PNOEOM_EINVAL,
               "build_ladder: precision must be PNOEOM_FP64, PNOEOM_FP32 or PNOEOM_BF16");
@@ -240,6 +246,7 @@ int pnoeom_build_ladder(pnoeom_ctx* ctx, const double* B, const double* t1, int 
 
 int pnoeom_ladder_apply(pnoeom_ctx* ctx, int nmat, const double* X, double* Y, int precision) {
   return guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom::TraceRange tr_("pnoeom_ladder_apply");
     PNO_CHECK(nmat >= 0, PNOEOM_EINVAL, "ladder_apply: nmat < 0");
     if (nmat == 0) return;
     PNO_CHECK(X && Y, PNOEOM_EINVAL, "ladder_apply: null matrix pointer");
@@ -330,6 +337,7 @@ void pnoeom_ccsd_defaults(pnoeom_ccsd_opts* opts) {
 int pnoeom_ccsd_residual(pnoeom_ctx* ctx, const double* B, const double* eps, const double* t1, const double* t2,
                          double* r1_out, double* r2_out, double* e_corr_out) {
   return guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom::TraceRange tr_("pnoeom_ccsd_residual");
     PNO_CHECK(B && eps && t1 && t2 && r1_out && r2_out && e_corr_out, PNOEOM_EINVAL,
               "ccsd_residual: null pointer");
     *e_corr_out = pnoeom::ccsd_residual(c, B, eps, t1, t2, r1_out, r2_out);
@@ -340,6 +348,7 @@ int pnoeom_ccsd(pnoeom_ctx* ctx, const double* B, const double* eps, double* t1,
                 const pnoeom_ccsd_opts* opts, double* e_corr_out, double* resmax_out, int* iters_out) {
   bool converged = false;
   const int st = guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom::TraceRange tr_("pnoeom_ccsd");
     pnoeom_ccsd_opts o;
     pnoeom_ccsd_defaults(&o);
     if (opts) o = *opts;
@@ -391,6 +400,7 @@ int pnoeom_davidson(pnoeom_ctx* ctx, int nroots, const pnoeom_davidson_opts* opt
   int converged = 1;
   int aborted = 0;
   int st = guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom::TraceRange tr_("pnoeom_davidson");
     PNO_CHECK(opts && omega_out, PNOEOM_EINVAL, "davidson: opts and omega_out are required");
     Timer t(c);
     pnoeom::DavidsonResult r = pnoeom::davidson(c, nroots, *opts);

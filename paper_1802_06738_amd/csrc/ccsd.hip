@@ -279,6 +279,7 @@ CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1
   int stored = 0;
   double e_prev = INFINITY;
   for (int it = 0;; ++it) {
+    TraceRange tr_("ccsd step");
     if (gs) pno_expand(c, P, 1, xs, x, x + ov);
     const double e = residual(c, w, B, eps, x, x + ov, r, r + ov);
     if (gs) pno_compress(c, P, 1, r, r + ov, rb);

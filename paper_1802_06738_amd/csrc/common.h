@@ -9,9 +9,19 @@
 #include <array>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/pnoeom.h"
 
 namespace pnoeom {
+
+// Named roctx range for the lifetime of a scope (seen by rocprofv3 --marker-trace).
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 struct Error : std::runtime_error {
   int code;

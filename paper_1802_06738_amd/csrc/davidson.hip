@@ -559,7 +559,21 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
   }
   PNO_CHECK(m >= nroots, PNOEOM_EINVAL, "Davidson: fewer independent guess vectors than roots");
   PNO_CHECK(m <= maxs, PNOEOM_EINVAL, "Davidson: more guess vectors than the subspace holds");
-  op.apply(m, V, S);
+  // sigma applications; with an iteration log their wall time is measured (the stream is
+  // synchronised around them only then)
+  double sigma_s = 0.0;
+  auto apply = [&](int nv, const double* X_, double* S_) {
+    if (!opt.log_path) {
+      op.apply(nv, X_, S_);
+      return;
+    }
+    PNO_HIP(hipStreamSynchronize(s));
+    const auto t0 = std::chrono::steady_clock::now();
+    op.apply(nv, X_, S_);
+    PNO_HIP(hipStreamSynchronize(s));
+    sigma_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  apply(m, V, S);
   res.nsigma += m;
   std::vector<double> G((size_t)maxs * maxs);
   {
@@ -571,6 +585,7 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
   std::vector<double> theta_old(nroots, 0.0);
   bool have_old = false;
   for (int it = 1; it <= opt.max_iter; ++it) {
+    TraceRange tr_("davidson iteration");
     res.iters = it;
     std::vector<double> Gm((size_t)m * m), wr(m), wi(m), vr((size_t)m * m);
     for (int i = 0; i < m; ++i)
@@ -609,8 +624,8 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
       FILE* lf = fopen(opt.log_path, "a");
       PNO_CHECK(lf != nullptr, PNOEOM_EINVAL, std::string("davidson: cannot append to ") + opt.log_path);
       const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-      fprintf(lf, "{\"phase\": %d, \"it\": %d, \"m\": %d, \"nsigma\": %d, \"seconds\": %.6f", phase, it_base + it,
-              m, res.nsigma, secs);
+      fprintf(lf, "{\"phase\": %d, \"it\": %d, \"m\": %d, \"nsigma\": %d, \"seconds\": %.6f, \"sigma_seconds\": %.6f",
+              phase, it_base + it, m, res.nsigma, secs, sigma_s);
       const char* keys[3] = {"omega", "resnorm", "domega"};
       for (int f = 0; f < 3; ++f) {
         fprintf(lf, ", \"%s\": [", keys[f]);
@@ -762,7 +777,7 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
       nnew = kept;
       PNO_CHECK(nnew > 0, PNOEOM_ENOTCONV, "Davidson stalled after collapse");
     }
-    op.apply(nnew, V + (int64_t)m * N, S + (int64_t)m * N);
+    apply(nnew, V + (int64_t)m * N, S + (int64_t)m * N);
     res.nsigma += nnew;
     const int m1 = m + nnew;
     {

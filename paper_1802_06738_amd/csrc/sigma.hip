@@ -1012,6 +1012,7 @@ void sigma_block_chunk(Context& c, int nvec, const double* r1, const double* r2,
 
 void sigma_block(Context& c, int nvec, const double* r1, const double* r2, double* s1, double* s2, int64_t stride1,
                  int64_t stride2, int precision) {
+  TraceRange tr_("sigma block");
   PNO_CHECK(c.have_df, PNOEOM_ESTATE, "sigma before build_df");
   if (nvec <= 0) return;
   const int nb = sigma_chunk(c, nvec, precision, false);

@@ -100,3 +100,7 @@ def test_iteration_log(tmp_path):
     assert np.allclose(lines[-1]["omega"], r["omega"], atol=0, rtol=0)
     assert all(len(x["resnorm"]) == 3 and x["m"] >= 3 for x in lines)
     assert lines[-1]["resnorm"][0] <= 1e-8 and lines[-1]["nsigma"] == r["nsigma"]
+    # cumulative sigma time: positive, non-decreasing, below the elapsed time
+    sig = [x["sigma_seconds"] for x in lines]
+    assert sig[0] > 0 and all(b >= a for a, b in zip(sig, sig[1:]))
+    assert all(x["sigma_seconds"] <= x["seconds"] + 1e-6 for x in lines)

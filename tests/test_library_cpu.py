@@ -115,3 +115,16 @@ def test_gemm_tuning_table_validation():
     assert default_variant((8, 0, 0, 0, 3000, 3000, 3000, 1)) == 0
     assert default_variant((8, 0, 1, 0, 6, 9000000, 40, 1)) == 6
     assert default_variant((8, 0, 0, 0, 40, 40, 9000000, 1)) == 3
+
+
+def test_library_emits_roctx_ranges():
+    """The library links the roctx marker library and opens named ranges (entry points,
+    sigma blocks, Davidson iterations, CCSD steps) that rocprofv3 --marker-trace records."""
+    import shutil
+    import subprocess
+    from paper_1802_06738_amd.pnoeom import library_path
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--undefined-only", library_path()], capture_output=True, text=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out
