@@ -95,28 +95,40 @@ def make_system(o: int, v: int, naux: int, seed: int, *, sigma_b: float | None =
 # occupied energies), so the state-averaged densities of pairs not touching those
 # orbitals have rank ~8 whatever kappa is; the mean count at T_cut = 1e-7 is largest
 # without an envelope (kappa = 0: 46 PNOs/pair, 8-9 for most pairs, up to v for the
-# pairs of the excited orbitals; kappa = 0.5 / 1 / 2: 41 / 27 / 17).
-CONFIGS = {
-    1: dict(o=4, v=20, naux=60, t1_sigma=0.0, kappa=0.0, nroots=3, tol_e=1e-8,
-            space="canonical"),
-    2: dict(o=20, v=150, naux=450, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-8, tol_r=3e-6,
-            max_sub=60, nextra=4, mixed_tol_e=1e-7, mixed_tol_r=1e-5, space="canonical"),
-    3: dict(o=40, v=400, naux=1200, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-6, tol_r=1e-4, nextra=4,
-            tcut=1e-7, space="pno"),
-    4: dict(o=40, v=400, naux=1200, t1_sigma=1e-3, kappa=0.0, nroots=6, tol_e=1e-6, tol_r=1e-4, nextra=4,
-            tcut=1e-7, space="pno"),
-    5: dict(o=60, v=900, naux=2700, t1_sigma=1e-3, kappa=0.0, nroots=12, tol_e=1e-6, tol_r=1e-4,
-            tcut=1e-7, space="pno"),
-    # reduced PNO workload (o=10, v=100) small enough for the oracle to converge
-    "pno_small": dict(o=10, v=100, naux=300, t1_sigma=1e-3, kappa=1.0, nroots=4,
-                      tol_e=1e-8, tcut=1e-7, space="pno"),
-}
+# pairs of the excited orbitals; kappa = 0.5 / 1 / 2: 41 / 27 / 17).  The reduced PNO
+# workload (o=10, v=100, kappa = 1) is small enough for the oracle to converge.
+
+
+def _load_configs():
+    """The workloads, one JSON file each under configs/: system sizes and generator knobs,
+    the seed, the number of roots and space, the Davidson options (named as the fields of
+    pnoeom_davidson_opts) and the PNO cut.  Returned flattened, keyed 1..5 and "pno_small"."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
+    out = {}
+    for fn in sorted(os.listdir(here)):
+        if not fn.endswith(".json"):
+            continue
+        with open(os.path.join(here, fn)) as fh:
+            d = json.load(fh)
+        key = int(d["name"]) if d["name"].isdigit() else d["name"]
+        flat = dict(d["system"])
+        flat.update(nroots=d["nroots"], space=d["space"], seed=d["seed"])
+        flat.update(d.get("davidson", {}))
+        if "pno" in d:
+            flat["tcut"] = d["pno"]["tcut_pno"]
+        out[key] = flat
+    return out
+
+
+CONFIGS = _load_configs()
 
 
 def config_system(cfg, seed: int | None = None) -> System:
     c = CONFIGS[cfg]
     if seed is None:
-        seed = 1802 + (cfg if isinstance(cfg, int) else 100)
+        seed = c["seed"]
     return make_system(c["o"], c["v"], c["naux"], seed, kappa=c["kappa"],
                        t1_sigma=c["t1_sigma"])
 
