@@ -304,7 +304,8 @@ int pnoeom_ccsd_history(const pnoeom_ctx* ctx, int cap, double* energies, double
 
 /* PNO and OSV counts of the ground-state PNOs of the last pnoeom_ccsd with gs_tcut_pno >= 0.
  *   npno_out : host [o(o+1)/2] (pairs i <= j, row-major) or NULL;  nosv_out : host [o] or NULL
- * Errors: ESTATE (no ground-state PNOs built on ctx), EINVAL. */
+ * Errors: ESTATE (no ground-state PNOs on ctx: none built, or a canonical pnoeom_ccsd ran
+ * since), EINVAL. */
 int pnoeom_ccsd_gs_counts(const pnoeom_ctx* ctx, int* npno_out, int* nosv_out);
 
 /* Eigenvalues and right eigenvectors of a small dense real matrix on the host

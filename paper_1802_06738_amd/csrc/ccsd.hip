@@ -253,6 +253,7 @@ CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1
       build_gs_pnos(c, c.T, opt.gs_tcut_pno, tosv);
     }
   }
+  if (!gs) c.gs.reset();  // ground-state PNOs of an earlier simulation describe other amplitudes
   if (start_mp1) {
     fill(s, ov, 0.0, x);
     PNO_HIP(hipMemcpyAsync(x + ov, c.T, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));

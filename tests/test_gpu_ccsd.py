@@ -155,5 +155,12 @@ def test_gs_pno_ccsd_matches_oracle(tcut):
     r1, r2 = random_r(o, v, 78, nvec=1)
     g1, g2 = ctx.sigma(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda())
     x1, x2 = SigmaOracle(s.eps, s.B, o, a1, a2).sigma(r1[0], r2[0])
+    # a canonical solve afterwards discards the ground-state PNOs
+    if tcut > 0.0:
+        ctx2 = PnoEom(o, v, naux)
+        ctx2.ccsd(B, eps, gs_tcut_pno=tcut, max_iter=2, raise_on_notconv=False)
+        assert ctx2.lib.pnoeom_ccsd_gs_counts(ctx2.h, None, None) == 0
+        ctx2.ccsd(B, eps, max_iter=2, raise_on_notconv=False)
+        assert ctx2.lib.pnoeom_ccsd_gs_counts(ctx2.h, None, None) == -5   # ESTATE
     assert np.max(np.abs(g1.cpu().numpy()[0] - x1)) <= 1e-9 * np.max(np.abs(x1))
     assert np.max(np.abs(g2.cpu().numpy()[0] - x2)) <= 1e-9 * np.max(np.abs(x2))
