@@ -164,3 +164,38 @@ def test_gs_pno_ccsd_matches_oracle(tcut):
         assert ctx2.lib.pnoeom_ccsd_gs_counts(ctx2.h, None, None) == -5   # ESTATE
     assert np.max(np.abs(g1.cpu().numpy()[0] - x1)) <= 1e-9 * np.max(np.abs(x1))
     assert np.max(np.abs(g2.cpu().numpy()[0] - x2)) <= 1e-9 * np.max(np.abs(x2))
+
+
+def test_ccsd_error_paths():
+    """Bad options and missing buffers are refused with EINVAL before any work."""
+    print("[ccsd errors]", flush=True)
+    import ctypes as C
+    import torch
+    from paper_1802_06738_amd import PnoEom
+    from paper_1802_06738_amd.pnoeom import PnoEomError, CcsdOpts, _dev
+    s = make_system(2, 6, 12, 5)
+    ctx = PnoEom(2, 6, 12)
+    B, eps = torch.from_numpy(s.B).cuda(), torch.from_numpy(s.eps).cuda()
+    for kw in (dict(max_iter=-1), dict(tol_r=0.0), dict(tol_e=-1.0), dict(diis_size=65), dict(precision=7)):
+        with pytest.raises(PnoEomError) as e:
+            ctx.ccsd(B, eps, **kw)
+        assert e.value.code == -1, kw
+    with pytest.raises(ValueError):
+        ctx.ccsd(B, eps, t1=torch.zeros((2, 6), dtype=torch.float64, device="cuda"))   # t2 missing
+    t1 = torch.zeros((2, 6), dtype=torch.float64, device="cuda")
+    t2 = torch.zeros((2, 2, 6, 6), dtype=torch.float64, device="cuda")
+    opts = CcsdOpts()
+    ctx.lib.pnoeom_ccsd_defaults(C.byref(opts))
+    e_out = C.c_double()
+    st = ctx.lib.pnoeom_ccsd(ctx.h, _dev(B), None, _dev(t1), _dev(t2), 0, C.byref(opts), C.byref(e_out), None, None)
+    assert st == -1                                                   # null eps
+    st = ctx.lib.pnoeom_ccsd(ctx.h, _dev(B), _dev(eps), _dev(t1), _dev(t2), 2, C.byref(opts), C.byref(e_out),
+                             None, None)
+    assert st == -1                                                   # start must be 0 or 1
+    r1 = torch.empty_like(t1)
+    r2 = torch.empty_like(t2)
+    st = ctx.lib.pnoeom_ccsd_residual(ctx.h, _dev(B), _dev(eps), _dev(t1), _dev(t2), _dev(r1), _dev(r2), None)
+    assert st == -1                                                   # null energy output
+    # the context is still usable afterwards
+    r = ctx.ccsd(B, eps, tol_r=1e-10)
+    assert r["converged"]
