@@ -216,15 +216,28 @@ bool small_solve(int n, std::vector<double> A, std::vector<double>& b) {
   return true;
 }
 
+// Marks the context's intermediates invalid when the scope is left without done(): the
+// iterations build them around T2 / 2, which sigma must never use.
+struct InvalidateUnlessDone {
+  Context& c;
+  bool ok = false;
+  explicit InvalidateUnlessDone(Context& cc) : c(cc) {}
+  void done() { ok = true; }
+  ~InvalidateUnlessDone() {
+    if (!ok) {
+      c.have_df = false;
+      c.have_lad = false;
+    }
+  }
+};
+
 }  // namespace
 
 double ccsd_residual(Context& c, const double* B, const double* eps, const double* t1, const double* t2,
                      double* r1, double* r2) {
+  InvalidateUnlessDone guard(c);  // never done: the intermediates are those of T2 / 2
   CcsdWork w;
-  const double e = residual(c, w, B, eps, t1, t2, r1, r2);
-  c.have_df = false;  // the intermediates are those of T2 / 2
-  c.have_lad = false;
-  return e;
+  return residual(c, w, B, eps, t1, t2, r1, r2);
 }
 
 CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1, double* t2, bool start_mp1,
@@ -235,6 +248,7 @@ CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1
   const int m = std::max(1, opt.diis_size);
   const bool gs = opt.gs_tcut_pno >= 0.0;  // ground-state PNO simulation
   CcsdWork w;
+  InvalidateUnlessDone guard(c);  // done only after the final build at the solution
   // the build-time temporaries stay allocated across the repeated builds of the iteration
   struct KeepTmp {
     Context& c;
@@ -347,6 +361,7 @@ CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1
   c.keep_build_tmp = false;
   build_df(c, B, eps, t1, t2, opt.precision);
   PNO_HIP(hipStreamSynchronize(s));
+  guard.done();
   return res;
 }
 
