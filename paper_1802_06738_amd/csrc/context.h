@@ -101,6 +101,9 @@ struct Context {
   DBuf<uint16_t> Wpb, Wmb;      // bfloat16 bits (precision BF16), rows padded to ldpb / ldmb columns
   int64_t ldpb = 0, ldmb = 0;
   DBuf<float> DX2f, DXTTf;
+  // FP32 copies of the T-only right factors of the hole-ladder and three-body products and of
+  // B~_ov (precision FP32 / BF16: those products then run on FP32 MFMA)
+  DBuf<float> Whf, g2f, T32, BovTf;
   // build-time temporaries of build_df, by slot (each slot's uses follow one another on the
   // stream); kept between builds while keep_build_tmp is set (the repeated builds of the
   // CCSD solver then allocate nothing), else released at the end of each build

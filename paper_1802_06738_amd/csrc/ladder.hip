@@ -371,7 +371,7 @@ void build_ladder(Context& c, const double* B, const double* t1, int precision, 
                           &c.U, &c.Tia, &c.Tsia, &c.UiaT, &c.OVVO, &c.OOVVx, &c.Dr, &c.Xr, &c.DX2, &c.YU, &c.BYU, &c.B,
                           &c.DXTT})
     b->release();
-  for (DBuf<float>* b : {&c.Wpf, &c.Wmf, &c.DX2f, &c.DXTTf}) b->release();
+  for (DBuf<float>* b : {&c.Wpf, &c.Wmf, &c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf}) b->release();
   c.Wpb.release();
   c.Wmb.release();
   {

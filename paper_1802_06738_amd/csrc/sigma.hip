@@ -265,7 +265,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   if (!c.keep_build_tmp) c.sw.release();  // (the CCSD iteration keeps its FP64 sigma workspaces)
   c.pno.reset();
   if (precision == PNOEOM_FP64)
-    for (DBuf<float>* b : {&c.DX2f, &c.DXTTf}) b->release();
+    for (DBuf<float>* b : {&c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf}) b->release();
 
   c.B.alloc((int64_t)naux * n2);
   c.eps.alloc(nmo);
@@ -511,6 +511,14 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     c.DXTTf.alloc(4 * oovv);
     to_float(s, oovv, c.DX2, c.DX2f);
     to_float(s, 4 * oovv, c.DXTT, c.DXTTf);
+    c.Whf.alloc(oo * oo);
+    c.g2f.alloc(oovv);
+    c.T32.alloc(oovv);
+    c.BovTf.alloc(ov * naux);
+    to_float(s, oo * oo, c.Wh, c.Whf);
+    to_float(s, oovv, c.g2, c.g2f);
+    to_float(s, oovv, c.T, c.T32);
+    to_float(s, ov * naux, c.BovT, c.BovTf);
   }
   PNO_HIP(hipStreamSynchronize(s));
   // kept only stacked (DXTT) from here on
@@ -749,14 +757,30 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   gmb(s, true, false, o, v, o, -1.0, c.Fqoo, o, 0, r1, v, stride1, 1.0, s1, v, stride1, nb);
   gmb(s, false, true, o, v, v, 1.0, r1, v, stride1, c.Fqvv, v, 0, 1.0, s1, v, stride1, nb);
   gmb(s, false, false, ov, 1, ov, 1.0, w.UiaR, ov, oovv, c.fd_ov, 1, 0, 1.0, s1, 1, stride1, nb);
-  gmb(s, false, false, ov, naux, ov, 1.0, w.UiaR, ov, oovv, c.BovT, naux, 0, 0.0, w.M1, naux, ovn, nb);
+  // (FP32 / BF16: the products with a T-only right factor below run on FP32 MFMA, their
+  // per-vector left operands staged in FP32 in fa; the staging holds 2 nb o^2 v^2 floats)
+  const bool f32x = f32 && ovn <= 2 * oovv;
+  if (f32x) {
+    to_float(s, nb * oovv, w.UiaR, w.fa);
+    gmbf(s, false, false, ov, naux, ov, 1.0, w.fa, ov, oovv, c.BovTf, naux, 0, 0.0, w.M1, nb, w.fc);
+  } else {
+    gmb(s, false, false, ov, naux, ov, 1.0, w.UiaR, ov, oovv, c.BovT, naux, 0, 0.0, w.M1, naux, ovn, nb);
+  }
   gmb(s, false, false, o, v, (int64_t)v * naux, 1.0, w.M1, (int64_t)v * naux, ovn, c.Bvv2, v, 0, 1.0, s1, v,
       stride1, nb);
   gmb(s, false, false, o, v, oo * v, -1.0, c.OOOVp, oo * v, 0, w.URp, v, oovv, 1.0, s1, v, stride1, nb);
 
   // ---------------------------------------------------------------- sigma2, direct (not P-symmetrised)
-  gmb(s, false, false, oo, vv, oo, 1.0, c.Wh, oo, 0, R2, vv, oovv, 1.0, Sd, vv, oovv, nb);
-  gmb(s, false, true, oo, oo, vv, 1.0, R2, vv, oovv, c.g2, vv, 0, 0.0, w.Xh, oo, o4, nb);
+  float* R2f = w.fa;             // FP32 staging of R2, then of Xh after it
+  float* Xhf = w.fa + nb * oovv;
+  if (f32x) {
+    to_float(s, nb * oovv, R2, R2f);
+    gmbf(s, false, false, oo, vv, oo, 1.0, c.Whf, oo, 0, R2f, vv, oovv, 1.0, Sd, nb, w.fc);
+    gmbf(s, false, true, oo, oo, vv, 1.0, R2f, vv, oovv, c.g2f, vv, 0, 0.0, w.Xh, nb, w.fc);
+  } else {
+    gmb(s, false, false, oo, vv, oo, 1.0, c.Wh, oo, 0, R2, vv, oovv, 1.0, Sd, vv, oovv, nb);
+    gmb(s, false, true, oo, oo, vv, 1.0, R2, vv, oovv, c.g2, vv, 0, 0.0, w.Xh, oo, o4, nb);
+  }
   gmb(s, false, true, oo, oo, naux, 1.0, w.BoopT, naux, oon, c.BooT, naux, 0, 0.0, w.O4p, oo, o4, nb);
   gmb(s, false, true, oo, oo, naux, 1.0, c.BooT, naux, 0, w.BoopT, naux, oon, 1.0, w.O4p, oo, o4, nb);
   {
@@ -764,7 +788,12 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     const int pp[4] = {1, 3, 0, 2};
     permute_c(s, dims, pp, 1.0, w.O4p, 1.0, w.Xh, nb);
   }
-  gmb(s, false, false, oo, vv, oo, 1.0, w.Xh, oo, o4, c.T, vv, 0, 1.0, Sd, vv, oovv, nb);
+  if (f32x) {
+    to_float(s, nb * o4, w.Xh, Xhf);
+    gmbf(s, false, false, oo, vv, oo, 1.0, Xhf, oo, o4, c.T32, vv, 0, 1.0, Sd, nb, w.fc);
+  } else {
+    gmb(s, false, false, oo, vv, oo, 1.0, w.Xh, oo, o4, c.T, vv, 0, 1.0, Sd, vv, oovv, nb);
+  }
 
   // ---------------------------------------------------------------- ring terms in [(i,a),(j,b)] form
   // Ziajb and Z3 enter sigma2 only as Z + Z^T (assembly below), so any term may be
