@@ -37,10 +37,16 @@ def unpack(x, o, v):
 
 
 def _orth_against(V, x, passes=2):
-    for _ in range(passes):
-        if V:
-            M = np.array(V)
-            x = x - M.T @ (M @ x)
+    """Classical Gram-Schmidt against the orthonormal V; the second pass only when the first
+    removed more than half of the squared norm ("twice is enough")."""
+    if not V:
+        return x
+    M = np.array(V)
+    n0 = float(x @ x)
+    for p in range(passes):
+        x = x - M.T @ (M @ x)
+        if p == 0 and float(x @ x) >= 0.5 * n0:
+            break
     return x
 
 

@@ -535,6 +535,11 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
         dots(s, dw, V, m, x, 1, N, cvec.data());
         PNO_HIP(hipMemcpyAsync(dc, cvec.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
         skinny(s, 1, m, N, dc, 1, m, -1.0, V, 1.0, x);
+        // second pass only if the first removed more than half the squared norm (x is a unit
+        // vector and V orthonormal, so 1 - sum c_i^2 is left)
+        double c2 = 0.0;
+        for (int i = 0; i < m; ++i) c2 += cvec[i] * cvec[i];
+        if (pass == 0 && 1.0 - c2 >= 0.5) break;
       }
     }
     double nn = 0.0;
@@ -691,6 +696,18 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
           dots(s, dw, V, m, X, nc, N, coef.data());  // coef[i][q] = V_i . X_q
           PNO_HIP(hipMemcpyAsync(dcb, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
           skinny(s, nc, m, N, dcb, nc, 1, -1.0, V, 1.0, X);
+          // "twice is enough": a second pass only if the first removed more than half of a
+          // correction's squared norm (unit corrections, orthonormal V: 1 - sum_i c_iq^2 is
+          // left); otherwise one projection is exact to working precision
+          if (pass == 0) {
+            bool again = false;
+            for (int q = 0; q < nc && !again; ++q) {
+              double c2 = 0.0;
+              for (int i = 0; i < m; ++i) c2 += coef[(size_t)i * nc + q] * coef[(size_t)i * nc + q];
+              again = 1.0 - c2 < 0.5;
+            }
+            if (!again) break;
+          }
         }
         // orthonormal basis of the block itself: two Gram passes, each X <- T^T X with
         // T = W_k diag(w_k^-1/2) from the eigenpairs (w_k, W_k) of the block's Gram
