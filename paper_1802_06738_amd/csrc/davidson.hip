@@ -668,8 +668,8 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
     theta_old = theta;
     have_old = true;
     // corrections: preconditioned residuals of the unconverged roots, normalised,
-    // orthogonalised against V as a block (two classical Gram-Schmidt passes, each
-    // reading V once), then among themselves; staged in X
+    // orthogonalised against V as a block (classical Gram-Schmidt, each pass reading V
+    // once, the second only when needed), then among themselves; staged in X
     // When every preconditioned direction lies in span(V) (a preconditioner close to the
     // exact operator maps r_k back onto the Ritz vector), the plain residuals are taken:
     // the Galerkin condition V^T r_k = 0 makes them new directions whenever r_k != 0.
