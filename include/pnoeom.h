@@ -292,7 +292,8 @@ int pnoeom_ccsd_residual(pnoeom_ctx* ctx, const double* B, const double* eps, co
  * opts NULL selects the defaults.  Device memory: 2 (diis_size + 2) vectors of o v + o^2 v^2
  * doubles besides the intermediates.
  * Errors: EINVAL, ENOMEM, EHIP, ENOTCONV (max_iter reached or the iteration diverged; the
- * last amplitudes are returned). */
+ * last amplitudes are returned; after a divergence to non-finite values the context holds
+ * no intermediates, and apply_sigma / davidson return ESTATE until the next build_df). */
 int pnoeom_ccsd(pnoeom_ctx* ctx, const double* B, const double* eps, double* t1, double* t2, int start,
                 const pnoeom_ccsd_opts* opts, double* e_corr_out, double* resmax_out, int* iters_out);
 

@@ -356,9 +356,17 @@ CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1
   if (gs) pno_expand(c, P, 1, xs, x, x + ov);
   PNO_HIP(hipMemcpyAsync(t1, x, ov * sizeof(double), hipMemcpyDeviceToDevice, s));
   PNO_HIP(hipMemcpyAsync(t2, x + ov, oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  c.keep_build_tmp = false;
+  if (!std::isfinite(res.e_corr) || !std::isfinite(res.rmax)) {
+    // diverged: the amplitudes are returned as they are, and the context is left without
+    // intermediates (the guard marks them invalid) rather than holding them at non-finite T
+    for (DBuf<double>& b : c.btmp) b.release();
+    c.sw.release();
+    PNO_HIP(hipStreamSynchronize(s));
+    return res;
+  }
   // intermediates of the final amplitudes, in the contraction precision asked for (this
   // build releases the temporaries)
-  c.keep_build_tmp = false;
   build_df(c, B, eps, t1, t2, opt.precision);
   PNO_HIP(hipStreamSynchronize(s));
   guard.done();

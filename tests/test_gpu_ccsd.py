@@ -199,3 +199,29 @@ def test_ccsd_error_paths():
     # the context is still usable afterwards
     r = ctx.ccsd(B, eps, tol_r=1e-10)
     assert r["converged"]
+
+
+def test_ccsd_divergence_leaves_no_intermediates():
+    """A non-finite iteration (forced from the host by a NaN orbital energy) ends with ENOTCONV,
+    returns its amplitudes and leaves the context without intermediates: sigma is refused
+    with ESTATE until a finite solve builds them again."""
+    print("[ccsd divergence] o=2 v=8", flush=True)
+    torch = _torch()
+    from paper_1802_06738_amd import PnoEom
+    from paper_1802_06738_amd.pnoeom import PnoEomError
+    s = make_system(2, 8, 20, 6)
+    ctx = PnoEom(2, 8, 20)
+    B, eps = _dev(s)
+    bad = eps.clone()
+    bad[3] = float("nan")
+    a = ctx.ccsd(B, bad, raise_on_notconv=False)
+    assert not a["converged"] and a["iters"] == 0 and not np.isfinite(a["e_corr"])
+    r1, r2 = random_r(2, 8, 79, nvec=1)
+    R1, R2 = torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda()
+    with pytest.raises(PnoEomError) as e:
+        ctx.sigma(R1, R2)
+    assert e.value.code == -5
+    b = ctx.ccsd(B, eps, tol_r=1e-10)
+    assert b["converged"] and np.isfinite(b["e_corr"])
+    g1, g2 = ctx.sigma(R1, R2)
+    assert torch.isfinite(g1).all() and torch.isfinite(g2).all()
