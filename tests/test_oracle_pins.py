@@ -388,3 +388,23 @@ def test_davidson_exhausted_subspace_equals_dense():
     guess = [(b[k], np.zeros((o, o, v, v))) for k in range(3)]
     res = davidson(so.sigma, CanonicalBasis(s.eps, o), guess, o, v, 3, tol_e=1e-13, tol_r=1e-10, max_sub=40)
     assert np.max(np.abs(res["omega"] - np.sort(wd.real)[:3])) < 1e-10
+
+
+def test_gram_schmidt_one_and_two_pass_branches():
+    """The Davidson's projection against an orthonormal basis: whether it stops after one
+    classical pass (most of the norm kept) or takes the second (most of it removed), the
+    result is orthogonal to the basis to working precision and equals the exact projector
+    (I - V^T V) x."""
+    from oracle.davidson import _orth_against
+    rng = np.random.default_rng(5)
+    n, m = 400, 30
+    Q, _ = np.linalg.qr(rng.standard_normal((n, m)))
+    V = list(Q.T)
+    x_far = rng.standard_normal(n)                         # keeps ~ (n - m) / n of its norm
+    x_near = Q @ rng.standard_normal(m) + 1e-9 * rng.standard_normal(n)   # almost in span(V)
+    for x in (x_far, x_near):
+        y = _orth_against(V, x.copy())
+        exact = x - Q @ (Q.T @ x)
+        assert np.max(np.abs(Q.T @ y)) <= 1e-13 * np.linalg.norm(y)   # relative to what is left
+        assert np.max(np.abs(y - exact)) <= 1e-12 * np.linalg.norm(x)
+    assert np.array_equal(_orth_against([], x_far), x_far)
