@@ -87,11 +87,14 @@ def sec_pno_small():
 def sec_c2():
     s, so, out = _setup(2)
     o, v, k = s.o, s.v, CONFIGS[2]["nroots"]
-    w, b = cis_roots(s.eps, s.B, o, k)
-    out["cis"] = w.tolist()
+    ne = CONFIGS[2]["nextra"]
+    w, b = cis_roots(s.eps, s.B, o, k + ne)
+    out["cis"] = w[:k].tolist()
+    out["nextra"] = ne
     t0 = time.time()
-    res = davidson(so.sigma, CanonicalBasis(s.eps, o, *so.dressed_fock_diagonals()[:2]), _guess(b, o, v, k), o, v, k,
-                   tol_e=1e-11, tol_r=3e-8, max_sub=CONFIGS[2]["max_sub"], verbose=True)
+    res = davidson(so.sigma, CanonicalBasis(s.eps, o, *so.dressed_fock_diagonals()[:2]), _guess(b, o, v, k + ne), o, v, k,
+                   tol_e=1e-10, tol_r=1e-7, max_sub=CONFIGS[2]["max_sub"], nextra=CONFIGS[2]["nextra"],
+                   max_iter=400, verbose=True)
     out["davidson"] = res["omega"].tolist()
     out["davidson_resnorm"] = res["resnorm"].tolist()
     out["davidson_iters"] = res["iters"]

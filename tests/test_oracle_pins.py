@@ -267,6 +267,59 @@ def test_pair_density_properties():
     assert np.allclose(pair_density(bs, True), 2.0 * bs @ bs)
 
 
+@pytest.mark.parametrize("o,v,seed,state", [(2, 3, 31, 0), (3, 4, 32, 1), (2, 4, 33, 2)])
+def test_cisd_doubles_vs_brute_force_first_order(o, v, seed, state):
+    """CIS(D) doubles of a CIS state b (Methods, the state-specific doubles equation) are the
+    first-order doubles of the perturbed CIS state: per determinant D,
+    c_D = <D|H - E_ref|b> / (omega - (E0_D - E0_0)) with the zeroth-order energies the sums of
+    occupied orbital energies, read off in the alpha-beta convention.  H is the brute-force
+    determinant Hamiltonian; a wrong sign of omega or of any orbital energy fails."""
+    s, h, eref, f = _tiny(o, v, seed=seed)
+    w, b = cis_roots(s.eps, s.B, o, state + 1)
+    x = f.space.excitation_op(b[state], np.zeros((o, o, v, v))) @ f.space.ref()
+    y = f.H(x) - eref * x
+    e0 = f.orbital_energy_sum(s.eps)
+    lev = f.excitation_level()
+    c = np.where(lev == 2, y / (w[state] - (e0 - e0[f.space.hf])), 0.0)
+    _, c2 = f.space.readoff(c, v)
+    d2 = cisd_doubles(s.eps, s.B, o, w[state], b[state])
+    assert np.max(np.abs(d2 - c2)) < 1e-12 * np.max(np.abs(c2))
+    # the CIS state is an eigenvector of H - E_ref on the singles (brute force)
+    y1, _ = f.space.readoff(y, v)
+    assert np.allclose(y1, w[state] * b[state], atol=1e-12)
+
+
+@pytest.mark.parametrize("o,v,seed", [(2, 3, 41), (3, 4, 42), (2, 4, 43)])
+def test_pair_densities_sum_to_brute_force_virtual_density(o, v, seed):
+    """Sum over pairs i <= j of the pair densities (Methods, the pair-density equation, with its
+    weight 2/(1 + delta_ij)) is the virtual block of the one-particle density
+    <Psi|E_ab|Psi> of Psi = T|0>, T = 1/2 sum B_ij^ab E_ai E_bj, by brute force.  Off-diagonal
+    pair blocks are random and non-symmetric (B^ji = B^ij^T), diagonal ones symmetric, so a
+    wrong off-diagonal weight, a missing transpose or a wrong exchange sign fails."""
+    s, h, eref, f = _tiny(o, v, seed=seed)
+    rng = np.random.default_rng(seed)
+    bb = np.zeros((o, o, v, v))
+    for i in range(o):
+        for j in range(i, o):
+            blk = rng.standard_normal((v, v))
+            if i == j:
+                blk = blk + blk.T
+            bb[i, j] = blk
+            bb[j, i] = blk.T
+    psi = f.space.excitation_op(np.zeros((o, v)), bb) @ f.space.ref()
+    gam = np.array([[psi @ (f.space.E(o + a, o + c) @ psi) for c in range(v)] for a in range(v)])
+    dsum = sum(pair_density(bb[i, j], i == j) for i in range(o) for j in range(i, o))
+    assert np.max(np.abs(dsum - gam)) < 1e-12 * np.max(np.abs(gam))
+    # and the same holds pair by pair where one pair alone is excited
+    for (i, j) in [(0, 1), (1, 1)]:
+        one = np.zeros_like(bb)
+        one[i, j] = bb[i, j]
+        one[j, i] = bb[j, i]
+        psi = f.space.excitation_op(np.zeros((o, v)), one) @ f.space.ref()
+        g1 = np.array([[psi @ (f.space.E(o + a, o + c) @ psi) for c in range(v)] for a in range(v)])
+        assert np.max(np.abs(pair_density(bb[i, j], i == j) - g1)) < 1e-12 * np.max(np.abs(g1))
+
+
 def test_sa_density_rotation_invariance_and_single_state():
     s = make_system(3, 6, 12, 17)
     o = 3
