@@ -362,6 +362,7 @@ CcsdResult ccsd_solve(Context& c, const double* B, const double* eps, double* t1
     // intermediates (the guard marks them invalid) rather than holding them at non-finite T
     for (DBuf<double>& b : c.btmp) b.release();
     c.sw.release();
+    c.gs.reset();  // ground-state PNOs built in this call come from the same diverged run
     PNO_HIP(hipStreamSynchronize(s));
     return res;
   }

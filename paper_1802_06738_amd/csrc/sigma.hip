@@ -758,8 +758,10 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   gmb(s, false, true, o, v, v, 1.0, r1, v, stride1, c.Fqvv, v, 0, 1.0, s1, v, stride1, nb);
   gmb(s, false, false, ov, 1, ov, 1.0, w.UiaR, ov, oovv, c.fd_ov, 1, 0, 1.0, s1, 1, stride1, nb);
   // (FP32 / BF16: the products with a T-only right factor below run on FP32 MFMA, their
-  // per-vector left operands staged in FP32 in fa; the staging holds 2 nb o^2 v^2 floats)
-  const bool f32x = f32 && ovn <= 2 * oovv;
+  // per-vector left operands staged in FP32 in fa; the staging holds 2 nb o^2 v^2 floats in
+  // each of fa and fc: M1 stages nb o v naux floats in fc, R2 and Xh take nb (o^2 v^2 + o^4)
+  // in fa and Xh's product nb o^4 in fc, so o <= v is needed besides o v naux <= 2 o^2 v^2)
+  const bool f32x = f32 && ovn <= 2 * oovv && o4 <= oovv;
   if (f32x) {
     to_float(s, nb * oovv, w.UiaR, w.fa);
     gmbf(s, false, false, ov, naux, ov, 1.0, w.fa, ov, oovv, c.BovTf, naux, 0, 0.0, w.M1, nb, w.fc);

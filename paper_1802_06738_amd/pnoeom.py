@@ -334,8 +334,12 @@ class PnoEom:
         if gs_tcut_pno >= 0:
             npno = np.zeros(self.o * (self.o + 1) // 2, dtype=np.int32)
             nosv = np.zeros(self.o, dtype=np.int32)
-            self._check(self.lib.pnoeom_ccsd_gs_counts(self.h, npno.ctypes.data_as(C.POINTER(C.c_int)),
-                                                       nosv.ctypes.data_as(C.POINTER(C.c_int))))
+            st = self.lib.pnoeom_ccsd_gs_counts(self.h, npno.ctypes.data_as(C.POINTER(C.c_int)),
+                                                nosv.ctypes.data_as(C.POINTER(C.c_int)))
+            if st == -5 and not out["converged"]:
+                npno = nosv = None   # a diverged simulation keeps no ground-state PNOs
+            else:
+                self._check(st)
             out["npno"], out["nosv"] = npno, nosv
         return out
 

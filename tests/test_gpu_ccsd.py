@@ -225,3 +225,17 @@ def test_ccsd_divergence_leaves_no_intermediates():
     assert b["converged"] and np.isfinite(b["e_corr"])
     g1, g2 = ctx.sigma(R1, R2)
     assert torch.isfinite(g1).all() and torch.isfinite(g2).all()
+    # ground-state PNO simulation: PNOs from finite first-order densities, then NaN start
+    # amplitudes (set on the host) make the first step non-finite; the PNOs built in that call
+    # are dropped with the intermediates
+    print("[ccsd divergence] ground-state PNO simulation", flush=True)
+    g = ctx.ccsd(B, eps, tol_r=1e-10, gs_tcut_pno=1e-6)
+    assert g["converged"] and g["npno"] is not None
+    t2n = torch.full((2, 2, 8, 8), float("nan"), dtype=torch.float64, device="cuda")
+    t1n = torch.zeros((2, 8), dtype=torch.float64, device="cuda")
+    d = ctx.ccsd(B, eps, t1=t1n, t2=t2n, gs_tcut_pno=1e-6, raise_on_notconv=False)
+    assert not d["converged"] and d["npno"] is None and d["nosv"] is None
+    assert ctx.lib.pnoeom_ccsd_gs_counts(ctx.h, None, None) == -5   # ESTATE
+    with pytest.raises(PnoEomError) as e:
+        ctx.sigma(R1, R2)
+    assert e.value.code == -5
