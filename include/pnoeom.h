@@ -199,6 +199,25 @@ int pnoeom_build_ladder(pnoeom_ctx* ctx, const double* B, const double* t1, int 
  * Requires build_df or build_ladder.  Errors: ESTATE, EINVAL, ENOMEM, EHIP. */
 int pnoeom_ladder_apply(pnoeom_ctx* ctx, int nmat, const double* X, double* Y, int precision);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): pnoeom_ladder_apply without any
+ * device allocation, hipFree or allocating library call.  Same arguments, layout and
+ * result as pnoeom_ladder_apply (same kernels; K is never split, so FP64 / FP32 results
+ * may differ from it in the last bits of the summation order; BF16 results are equal).
+ * The packed operands and sigma+/- rows of the call are staged in a fixed device array
+ * of 128 MiB per GPU (a global of the library's device code: the HIP runtime places one
+ * copy on each GPU the library runs on, held until the process ends), so calls that overlap on one GPU (other streams,
+ * other threads, other contexts) race for it: serialise them.  The array keeps what the
+ * last call left; each call clears what it needs cleared.  Needs W+/- cached by build_df
+ * (EINVAL when the ladder is streamed, which needs its slab workspace).  EINVAL when
+ * nmat v^2 exceeds the array (pnoeom_ladder_noalloc_limit gives the largest nmat).
+ * Errors: ESTATE, EINVAL, EHIP. */
+int pnoeom_ladder_apply_noalloc(pnoeom_ctx* ctx, int nmat, const double* X, double* Y, int precision);
+
+/* Largest nmat pnoeom_ladder_apply_noalloc accepts for this context's v in a precision
+ * (host arithmetic only); -1 for a null context or an unknown precision. */
+long long pnoeom_ladder_noalloc_limit(const pnoeom_ctx* ctx, int precision);
+
 typedef struct {
   int space;           /* PNOEOM_CANONICAL or PNOEOM_PNO */
   int precision;       /* PNOEOM_FP64, PNOEOM_FP32 or PNOEOM_BF16 contractions; subspace work is FP64 */

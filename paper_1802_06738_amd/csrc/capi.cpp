@@ -258,6 +258,32 @@ int pnoeom_ladder_apply(pnoeom_ctx* ctx, int nmat, const double* X, double* Y, i
   });
 }
 
+int pnoeom_ladder_apply_noalloc(pnoeom_ctx* ctx, int nmat, const double* X, double* Y, int precision) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    pnoeom::TraceRange tr_("pnoeom_ladder_apply_noalloc");
+    PNO_CHECK(nmat >= 0, PNOEOM_EINVAL, "ladder_apply_noalloc: nmat < 0");
+    if (nmat == 0) return;
+    PNO_CHECK(X && Y, PNOEOM_EINVAL, "ladder_apply_noalloc: null matrix pointer");
+    const int64_t vv = (int64_t)c.v * c.v;
+    PNO_CHECK(X + nmat * vv <= Y || Y + nmat * vv <= X, PNOEOM_EINVAL, "ladder_apply_noalloc: X and Y overlap");
+    pnoeom::ladder_apply_noalloc(c, nmat, X, Y, precision);
+  });
+}
+
+long long pnoeom_ladder_noalloc_limit(const pnoeom_ctx* ctx, int precision) {
+  if (!ctx || precision < PNOEOM_FP64 || precision > PNOEOM_BF16) return -1;
+  // the staging size grows with nmat: bisection for the largest count that fits
+  int64_t lo = 0, hi = 1 << 30;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (pnoeom::ladder_noalloc_bytes(ctx->c, (int)mid, precision) <= pnoeom::kNoAllocScratchBytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 int pnoeom_set_pno_states(pnoeom_ctx* ctx, int n, const int* states) {
   return guarded(ctx, [&](pnoeom::Context& c) {
     PNO_CHECK(n >= 0 && (n == 0 || states), PNOEOM_EINVAL, "set_pno_states: bad list");

@@ -90,6 +90,7 @@ struct GemmDesc {
   int64_t batch = 1;
   bool reduce = false;
   int tag = 0;  // 1: particle-particle ladder, 2: its W slab build, 3: ring products (own kernel symbols, for profiling)
+  bool no_split = false;  // never split K (split-K partials live in a workspace the library allocates)
 };
 
 void gemm(const GemmDesc<double>& d, hipStream_t s);

@@ -223,6 +223,10 @@ void ladder_streamed(Context& c, int precision, int64_t rows, const void* S, int
 void build_ladder(Context& c, const double* B, const double* t1, int precision, int64_t budget_bytes);
 // Y_m = sum_cd W_abcd X_m[c][d] for nmat v x v matrices (cached or streamed W)
 void ladder_apply(Context& c, int nmat, const double* X, double* Y, int precision);
+// the same without any device allocation: staging in a fixed per-GPU scratch array
+constexpr int64_t kNoAllocScratchBytes = 128ll << 20;
+int64_t ladder_noalloc_bytes(const Context& c, int nmat, int precision);
+void ladder_apply_noalloc(Context& c, int nmat, const double* X, double* Y, int precision);
 void sigma_canonical(Context& c, const double* r1, const double* r2, double* s1, double* s2, int precision);
 // nvec vectors; r1/s1 of vector q at offset q*stride1, r2/s2 at q*stride2
 void sigma_block(Context& c, int nvec, const double* r1, const double* r2, double* s1, double* s2, int64_t stride1,

@@ -471,19 +471,19 @@ void gemm_impl(const GemmDesc<T>& d, hipStream_t s) {
     if (ts.recording) ts.recorded.insert(key);
     auto it = ts.table.find(key);
     if (it != ts.table.end()) {
-      launch_variant(d, s, it->second);
+      launch_variant(d, s, d.no_split ? 3 * (it->second / 3) + 1 : it->second);
       return;
     }
   }
   // built-in rule: large tiles when both output dimensions fill them
+  int kind = 1;
   if (d.M >= 128 && d.N >= 128)
-    launch_tile<T, 128, 128, (sizeof(T) == 8 ? 16 : 32)>(d, s);
+    kind = 0;
   else if (d.M <= 32 && d.N >= 128)
-    launch_tile<T, 32, 128, 16>(d, s);
+    kind = 2;
   else if (d.N <= 32 && d.M >= 128)
-    launch_tile<T, 128, 32, 16>(d, s);
-  else
-    launch_tile<T, 64, 64, 16>(d, s);
+    kind = 3;
+  launch_variant(d, s, 3 * kind + (d.no_split ? 1 : 0));
 }
 
 // ---------------------------------------------------------------- grouped (64 x 64 tiles, FP64)

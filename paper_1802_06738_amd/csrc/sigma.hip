@@ -14,6 +14,8 @@
 // intermediate W_ab^cd = (ac|bd)~, which contains the first three terms and the
 // T1.T1 term of the paper's W_ab^cd; its T2 G_ij^cd part is applied as the
 // bilinear hole-ladder term X_klij = sum_cd (kc|ld) R_ij^cd.
+#include <mutex>
+
 #include "context.h"
 
 namespace pnoeom {
@@ -1013,6 +1015,117 @@ void ladder_apply(Context& c, int nmat, const double* X, double* Y, int precisio
   ladder_pack(c, precision, 1, nmat, X, vv);
   ladder_contract(c, precision, nmat);
   ladder_unpack(c, precision, 1, nmat, Y, vv);
+}
+
+// ---------------------------------------------------------------- allocation-free ladder
+// Staging of ladder_apply_noalloc (packed S/A rows and the sigma+/- rows of one call) in a
+// file-scope device array: each GPU the library runs on holds its own copy until the
+// process ends.  Host code never passes the array's name to a kernel (on the host it is
+// only a stand-in for the symbol); it resolves the device address once per device with
+// hipGetSymbolAddress and uses that.
+namespace {
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex& scratch_mu() {
+  static std::mutex m;
+  return m;
+}
+unsigned char* scratch_dev[kMaxDevices] = {};
+
+// device address of this GPU's copy of the scratch array (resolved at the first call on it)
+unsigned char* scratch_address() {
+  int dev = -1;
+  PNO_HIP(hipGetDevice(&dev));
+  PNO_CHECK(dev >= 0 && dev < kMaxDevices, PNOEOM_EINVAL, "ladder_apply_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(scratch_mu());
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    PNO_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    PNO_CHECK(p != nullptr, PNOEOM_EHIP, "ladder_apply_noalloc: no device address for the scratch array");
+    scratch_dev[dev] = static_cast<unsigned char*>(p);
+  }
+  return scratch_dev[dev];
+}
+
+int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
+int64_t ladder_noalloc_bytes(const Context& c, int nmat, int precision) {
+  const int64_t v = c.v, vp = v * (v + 1) / 2, vm1 = std::max<int64_t>(v * (v - 1) / 2, 1);
+  const bool bf = precision == PNOEOM_BF16;
+  const int64_t in = precision == PNOEOM_FP64 ? 8 : precision == PNOEOM_FP32 ? 4 : 2;
+  const int64_t out = precision == PNOEOM_FP64 ? 8 : 4;
+  const int64_t lds = bf ? c.ldpb : vp, lda = bf ? c.ldmb : vm1;
+  return align256(nmat * lds * in) + align256(nmat * lda * in) + align256(nmat * vp * out) +
+         align256(nmat * vm1 * out);
+}
+
+void ladder_apply_noalloc(Context& c, int nmat, const double* X, double* Y, int precision) {
+  PNO_CHECK(c.have_lad, PNOEOM_ESTATE, "ladder_apply_noalloc before build_df or build_ladder");
+  PNO_CHECK(nmat >= 0, PNOEOM_EINVAL, "ladder_apply_noalloc: nmat < 0");
+  ladder_check(c, precision);
+  PNO_CHECK(!c.lad_streamed, PNOEOM_EINVAL,
+            "ladder_apply_noalloc: needs the cached W+/- (the streamed ladder needs its slab workspace)");
+  if (nmat == 0) return;
+  PNO_CHECK(X && Y, PNOEOM_EINVAL, "ladder_apply_noalloc: null matrix pointer");
+  const int64_t need = ladder_noalloc_bytes(c, nmat, precision);
+  PNO_CHECK(need <= kNoAllocScratchBytes, PNOEOM_EINVAL,
+            "ladder_apply_noalloc: nmat v^2 too large for the scratch array (" + std::to_string(need) + " > " +
+                std::to_string(kNoAllocScratchBytes) + " bytes)");
+  hipStream_t s = c.stream;
+  const int64_t v = c.v, vp = v * (v + 1) / 2, vm = v * (v - 1) / 2, vm1 = std::max<int64_t>(vm, 1);
+  const int64_t tot = (int64_t)nmat * v * v;
+  const bool f32 = precision == PNOEOM_FP32, bf = precision == PNOEOM_BF16;
+  const int64_t in = precision == PNOEOM_FP64 ? 8 : f32 ? 4 : 2, out = precision == PNOEOM_FP64 ? 8 : 4;
+  const int64_t lds = bf ? c.ldpb : vp, lda = bf ? c.ldmb : vm1;
+  unsigned char* p = scratch_address();
+  unsigned char* Sb = p;
+  unsigned char* Ab = Sb + align256(nmat * lds * in);
+  unsigned char* Pb = Ab + align256(nmat * lda * in);
+  unsigned char* Mb = Pb + align256(nmat * vp * out);
+  // each matrix is the doubles block of one pair: the packing of a single occupied index
+  if (f32) {
+    hipLaunchKernelGGL((ladder_pack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, 1, (int)v, nmat, X, v * v,
+                       (float*)Sb, vp, (float*)Ab, vm, (const int*)nullptr, (int64_t)1);
+    GemmDesc<float> d;
+    d.tb = true; d.M = nmat; d.N = vp; d.K = vp; d.tag = 1; d.no_split = true;
+    d.A = (const float*)Sb; d.lda = vp; d.B = c.Wpf; d.ldb = vp; d.C = (float*)Pb; d.ldc = vp;
+    gemm(d, s);
+    d.N = vm; d.K = vm; d.A = (const float*)Ab; d.lda = vm; d.B = c.Wmf; d.ldb = vm; d.C = (float*)Mb; d.ldc = vm;
+    gemm(d, s);
+  } else if (bf) {
+    // the padding columns of the packed rows must be zero; the array keeps what the last
+    // call on this GPU left, so the whole staging of this call is cleared first
+    hipLaunchKernelGGL(zero_u16_kernel, dim3(grid1(nmat * lds)), dim3(256), 0, s, nmat * lds, (uint16_t*)Sb);
+    hipLaunchKernelGGL(zero_u16_kernel, dim3(grid1(nmat * lda)), dim3(256), 0, s, nmat * lda, (uint16_t*)Ab);
+    hipLaunchKernelGGL((ladder_pack_kernel<uint16_t>), dim3(grid1(tot)), dim3(256), 0, s, 1, (int)v, nmat, X,
+                       v * v, (uint16_t*)Sb, lds, (uint16_t*)Ab, lda, (const int*)nullptr, (int64_t)1);
+    GemmBf16Desc d;
+    d.M = nmat; d.N = vp; d.K = c.ldpb; d.tag = 1;
+    d.A = (const uint16_t*)Sb; d.lda = c.ldpb; d.B = c.Wpb; d.ldb = c.ldpb; d.C = (float*)Pb; d.ldc = vp;
+    gemm_bf16(d, s);
+    d.N = vm; d.K = c.ldmb; d.A = (const uint16_t*)Ab; d.lda = c.ldmb; d.B = c.Wmb; d.ldb = c.ldmb;
+    d.C = (float*)Mb; d.ldc = vm;
+    gemm_bf16(d, s);
+  } else {
+    hipLaunchKernelGGL((ladder_pack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, 1, (int)v, nmat, X, v * v,
+                       (double*)Sb, vp, (double*)Ab, vm, (const int*)nullptr, (int64_t)1);
+    GemmDesc<double> d;
+    d.tb = true; d.M = nmat; d.N = vp; d.K = vp; d.tag = 1; d.no_split = true;
+    d.A = (const double*)Sb; d.lda = vp; d.B = c.Wp; d.ldb = vp; d.C = (double*)Pb; d.ldc = vp;
+    gemm(d, s);
+    d.N = vm; d.K = vm; d.A = (const double*)Ab; d.lda = vm; d.B = c.Wm; d.ldb = vm; d.C = (double*)Mb; d.ldc = vm;
+    gemm(d, s);
+  }
+  PNO_HIP(hipGetLastError());
+  if (precision != PNOEOM_FP64)
+    hipLaunchKernelGGL((ladder_unpack_kernel<float>), dim3(grid1(tot)), dim3(256), 0, s, 1, (int)v, nmat,
+                       (const float*)Pb, (const float*)Mb, Y, v * v, (const int*)nullptr, (int64_t)1);
+  else
+    hipLaunchKernelGGL((ladder_unpack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, 1, (int)v, nmat,
+                       (const double*)Pb, (const double*)Mb, Y, v * v, (const int*)nullptr, (int64_t)1);
+  PNO_HIP(hipGetLastError());
 }
 
 namespace {

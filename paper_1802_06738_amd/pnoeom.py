@@ -25,7 +25,8 @@ EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pno
                     "pnoeom_last_region_timing", "pnoeom_host_syev", "pnoeom_probe_peaks",
                     "pnoeom_gemm_record", "pnoeom_gemm_recorded", "pnoeom_gemm_time", "pnoeom_gemm_set_table",
                     "pnoeom_set_graph_mode", "pnoeom_graph_stats", "pnoeom_set_ladder_mode",
-                    "pnoeom_build_ladder", "pnoeom_ladder_apply", "pnoeom_set_pno_ladder",
+                    "pnoeom_build_ladder", "pnoeom_ladder_apply", "pnoeom_ladder_apply_noalloc",
+                    "pnoeom_ladder_noalloc_limit", "pnoeom_set_pno_ladder",
                     "pnoeom_pno_ladder_stats", "pnoeom_set_pno_states", "pnoeom_ccsd_defaults",
                     "pnoeom_ccsd_residual", "pnoeom_ccsd", "pnoeom_ccsd_history", "pnoeom_ccsd_gs_counts"]
 
@@ -97,6 +98,9 @@ def load_library():
     lib.pnoeom_set_ladder_mode.argtypes = [vp, C.c_int, C.c_int]
     lib.pnoeom_build_ladder.argtypes = [vp, vp, vp, C.c_int]
     lib.pnoeom_ladder_apply.argtypes = [vp, C.c_int, vp, vp, C.c_int]
+    lib.pnoeom_ladder_apply_noalloc.argtypes = [vp, C.c_int, vp, vp, C.c_int]
+    lib.pnoeom_ladder_noalloc_limit.argtypes = [vp, C.c_int]
+    lib.pnoeom_ladder_noalloc_limit.restype = C.c_longlong
     lib.pnoeom_set_pno_ladder.argtypes = [vp, C.c_int]
     lib.pnoeom_set_pno_states.argtypes = [vp, C.c_int, ip]
     lib.pnoeom_pno_ladder_stats.argtypes = [vp, ip, ip, ip, dp]
@@ -362,6 +366,19 @@ class PnoEom:
         self._check(self.lib.pnoeom_ladder_apply(self.h, nmat, _dev(X, (nmat, v, v), "X"),
                                                  _dev(Y, (nmat, v, v), "Y"), precision))
         return Y
+
+    def ladder_apply_noalloc(self, X, out, precision=FP64):
+        """ladder_apply into the caller's `out` with no device allocation in the library
+        (staging in its fixed per-GPU scratch array; see pnoeom_ladder_apply_noalloc)."""
+        nmat = X.shape[0]
+        v = self.v
+        self._check(self.lib.pnoeom_ladder_apply_noalloc(self.h, nmat, _dev(X, (nmat, v, v), "X"),
+                                                         _dev(out, (nmat, v, v), "Y"), precision))
+        return out
+
+    def ladder_noalloc_limit(self, precision=FP64):
+        """Largest batch ladder_apply_noalloc accepts at this context's v."""
+        return int(self.lib.pnoeom_ladder_noalloc_limit(self.h, precision))
 
     def set_pno_states(self, states=()):
         """CIS states averaged by the next build_sapno (one state: state-specific PNOs; () = default)."""
