@@ -1,19 +1,16 @@
-"""Benchmark: closed-shell EOM-CCSD sigma evaluations and Davidson time-to-convergence
+"""Benchmark: closed-shell SA-PNO-EOM-CCSD sigma evaluations and Davidson time-to-convergence
 on one MI355X, through the C-ABI library.
 
-One step = the whole hot path once for the config-2 workload (o=20 occupied,
-v=150 virtual, naux=450, T1 ~ N(0, 1e-3^2), T2 = first-order amplitudes, 6 roots,
-subspace <= 60): build the DF intermediates of H-bar, the CIS guess, and the
-Davidson iterations (sigma of every new trial vector, subspace algebra,
-preconditioner; 4 further Ritz pairs tracked) until every root meets
-tol_e = 1e-8 Eh and a residual norm of 3e-6.  Inputs are uploaded to HBM before the
-timed region.  `--config 3` runs the o=40, v=400 workload in the SA-PNO space.
-
-Printed: one JSON line with sigma-evaluations/s (the headline value), time to
-convergence, the live roofline of the dominant kernel (the ladder contraction),
-the FP32-MFMA and BF16-ladder mixed variants (each finished by FP64 refinement)
-with their differences from the FP64 roots, and the FP64 oracle timed on the host
-cores for a bounded sample.
+Default (config 4: o=40 occupied, v=400 virtual, naux=1200, T1 ~ N(0, 1e-3^2), T2 = first-order
+amplitudes, 6 roots, pair densities averaged over the 6 lowest CIS states, T_cut = 1e-7): after
+the untimed setup (DF intermediates, SA-PNO build; both reported), one step = one sigma block of
+6 trial vectors in the PNO space with bfloat16 MFMA contractions (FP32 accumulation): back-
+transform, canonical sigma, projection, PNO-space ladder.  `value` = sigma evaluations per
+second over the timed steps.  Then, once each, the Davidson time to convergence in FP64 and in
+BF16-mixed (mixed phase + FP64 refinement) with per-root differences, the FP64 canonical
+o=20, v=150 workload against its oracle Davidson reference, and the oracle timed on the host
+cores for a sample of sigma outputs.  `--config 2` runs the canonical-workload flow in which
+one step is a whole Davidson solve; `--config 5` one GPU's share of the o=60, v=900 ladder.
 """
 from __future__ import annotations
 
@@ -425,12 +422,259 @@ def gs_es_study(args):
     print(json.dumps(out), flush=True)
 
 
+def cpu_info():
+    """Host CPU model and the threads the oracle's BLAS uses."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max(int(p.get("num_threads", 1)) for p in threadpool_info()) if threadpool_info() else 1
+    except Exception:
+        threads = os.cpu_count() or 1
+    return model, threads
+
+
+def cpu_baseline_pairs(s, npair_all, nvec_unit=1):
+    """The oracle's sampled-output sigma (oracle/sigma_pairs.py) timed on the host for one trial
+    vector of the workload: its per-vector setup (R1-transformed Hamiltonian, the T2 / R2
+    intermediates shared by all pairs), one pair whose two occupied indices are new (their
+    per-occupied ring intermediates formed) and one pair whose are not; priced for all pairs
+    and the o per-occupied intermediates."""
+    from synthgen import random_r
+    from oracle.sigma_pairs import PairSigmaOracle
+    model, threads = cpu_info()
+    po = PairSigmaOracle(s.eps, s.B, s.o, s.t1)
+    r1, r2 = random_r(s.o, s.v, 7)
+    t0 = time.perf_counter()
+    st = po.prepare(r1[0], r2[0])
+    t_prep = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    po.pair(st, 0, 1)
+    t_new = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    po.pair(st, 0, 0)
+    t_cached = time.perf_counter() - t0
+    t_occ = max(t_new - t_cached, 0.0) / 2.0
+    t_vec = t_prep + npair_all * t_cached + s.o * t_occ
+    return {"value": nvec_unit / t_vec, "unit": "sigma-evals/s", "cores": threads, "cpu_model": model,
+            "kind": "oracle",
+            "sample": f"oracle sigma of one trial vector of the same workload (o={s.o}, v={s.v}, naux={s.naux}) at "
+                      f"two pairs: setup {t_prep:.1f} s, pair (0,1) {t_new:.1f} s with its two occupied "
+                      f"intermediates, pair (0,0) {t_cached:.1f} s without; priced as setup + {npair_all} pairs + "
+                      f"{s.o} occupied intermediates = {t_vec:.0f} s per vector (sigma1 and the PNO projection not "
+                      f"timed)"}
+
+
+def headline_pno(args):
+    """SA-PNO-EOM-CCSD at o=40, v=400, naux=1200 (the config-4 workload): sigma blocks of the
+    bfloat16-mixed contraction in the PNO space, timed as steps, then the Davidson time to
+    convergence in FP64 and BF16-mixed (+ FP64 refinement), per-root errors, and the
+    FP64 canonical o=20, v=150 workload against its oracle reference."""
+    import torch
+    from synthgen import config_system, CONFIGS
+    from paper_1802_06738_amd import PnoEom, FP64, BF16, CANONICAL, PNO
+
+    cfgid = args.config
+    cfg = CONFIGS[cfgid]
+    tcut = args.tcut if args.tcut is not None else cfg.get("tcut_pno", cfg.get("tcut", 1e-7))
+    t_gen = time.perf_counter()
+    s = config_system(cfgid)
+    o, v, naux, nroots = s.o, s.v, s.naux, cfg["nroots"]
+    t_gen = time.perf_counter() - t_gen
+    dav = dict(tol_e=cfg["tol_e"], tol_r=cfg.get("tol_r", 1e-5), max_sub=cfg.get("max_sub", 60),
+               nextra=cfg.get("nextra", 0), mixed_tol_e=cfg.get("mixed_tol_e", 0.0),
+               mixed_tol_r=cfg.get("mixed_tol_r", 0.0))
+    dev = torch.device("cuda:0")
+    B = torch.from_numpy(s.B).to(dev)
+    eps = torch.from_numpy(s.eps).to(dev)
+    t1 = torch.from_numpy(s.t1).to(dev)
+    torch.cuda.synchronize()
+    ctx = PnoEom(o, v, naux)
+    ctx.set_pno_ladder(args.pno_ladder)
+    ctx.set_bf16_passes(args.bf16_passes)
+    peaks = ctx.probe_peaks()
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)   # noqa: E731
+    t0 = time.perf_counter()
+    ctx.build_df(B, eps, t1, precision=BF16)
+    torch.cuda.synchronize()
+    t_df = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    npno, nosv = ctx.build_sapno(nroots, tcut)
+    torch.cuda.synchronize()
+    t_pno = time.perf_counter() - t0
+    split = ctx.pno_ladder_stats()
+    log(f"setup: build_df {t_df:.1f} s, build_sapno {t_pno:.1f} s, {npno.mean():.1f} PNOs/pair")
+    _, plen = ctx.pno_layout()
+    # one sigma block = the trial vectors one Davidson iteration adds (one per root)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1808)
+    X = torch.randn((nroots, plen), generator=gen, dtype=torch.float64, device=dev)
+
+    def block_steps(prec, k, w):
+        for _ in range(w):
+            ctx.sigma_pno(X, precision=prec)
+        torch.cuda.synchronize()
+        regs = []
+        t0 = time.perf_counter()
+        for _ in range(k):
+            ctx.sigma_pno(X, precision=prec)
+            regs.append(ctx.last_timing())
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, regs
+
+    dt, regs = block_steps(BF16, args.steps, args.warmup)
+    log(f"BF16 sigma blocks: {args.steps} in {dt:.2f} s")
+    dt64, regs64 = block_steps(FP64, max(1, min(args.steps, 3)), 1)
+    log(f"FP64 sigma blocks: {max(1, min(args.steps, 3))} in {dt64:.2f} s")
+    nb64 = max(1, min(args.steps, 3))
+
+    def region(regs_, key, sub=None):
+        ms = sum((r[key][sub] if sub else r[key])["ms" if not sub else "ladder_ms"] for r in regs_)
+        return ms
+
+    def family(regs_, name, peak, kernel, unit_text):
+        if name == "ladder_bf16":
+            ms = sum(r["bf16"]["ladder_ms"] for r in regs_)
+            n = sum(r["bf16"]["ladder_launches"] for r in regs_)
+            fl = sum(r["bf16"]["ladder_flops"] for r in regs_)
+            by = None
+        elif name == "ladder_fp64":
+            ms = sum(r["fp64"]["ladder_ms"] for r in regs_)
+            n = sum(r["fp64"]["ladder_launches"] for r in regs_)
+            fl = sum(r["fp64"]["ladder_flops"] for r in regs_)
+            by = None
+        else:
+            ms = sum(r[name]["ms"] for r in regs_)
+            n = sum(r[name]["launches"] for r in regs_)
+            fl = sum(r[name]["flops"] for r in regs_)
+            by = sum(r[name]["bytes"] for r in regs_)
+        if ms <= 0 or n <= 0:
+            return None
+        avg = ms / n
+        out = {"kernel": kernel, "launch_unit": unit_text, "launches": n, "avg_launch_ms": avg,
+               "ms_per_step": ms / len(regs_)}
+        if peak[0] == "hbm":
+            gbs = (by / n) / (avg * 1e-3) / 1e9
+            out.update({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK, "unit": "GB/s", "frac": gbs / HBM_PEAK,
+                        "algorithmic_bytes_per_launch": by / n})
+        else:
+            tf = (fl / n) / (avg * 1e-3) / 1e12
+            out.update({"bound": "mfma", "achieved": tf, "peak": PEAK[peak[1]], "unit": "TFLOP/s",
+                        "frac": tf / PEAK[peak[1]], "algorithmic_flops_per_launch": fl / n})
+        return out
+
+    ring_txt = (f"ring products R^s [Dr | Xr] and R_ia DX2 of all vectors of a block on bfloat16 MFMA "
+                f"(gemm_bf16 tag 3, {args.bf16_passes} pass(es): algorithmic flops counted once)")
+    fams = {
+        "ring": family(regs, "ring", ("mfma", "bf16"), ring_txt,
+                       "one bfloat16 GEMM launch (M = vectors x ov, N = 2 ov or ov, K = ov)"),
+        "ladder": family(regs, "ladder_bf16", ("mfma", "bf16"),
+                         "particle ladder of the pairs kept canonical, +/- packed (gemm_bf16 tag 1)",
+                         "one bfloat16 GEMM launch (+ or - half)"),
+        "pno_transform": family(regs, "pno_transform", ("hbm",), "grouped per-pair PNO back-transform / "
+                                "projection (gemm_grouped_kernel)", "one grouped launch"),
+        "pno_native_ladder": family(regs, "pno_native_ladder", ("mfma", "fp64"),
+                                    "PNO-space ladder of the small pairs (grouped FP64 GEMMs)", "one launch"),
+    }
+    fams = {k: v_ for k, v_ in fams.items() if v_ is not None}
+    dom = max(fams, key=lambda k: fams[k]["ms_per_step"])
+    roof = dict(fams[dom])
+    roof["traffic"] = None
+    roof["peak_measured"] = peaks["bf16_tflops"] if roof["unit"] == "TFLOP/s" else peaks["copy_gbs"]
+    out = {
+        "metric": METRIC,
+        "value": nroots * args.steps / dt,
+        "unit": "sigma-evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"config {cfgid}: SA-PNO-EOM-CCSD sigma blocks of {nroots} trial vectors in the "
+                               f"PNO space (T_cut={tcut:g}, {npno.mean():.1f} PNOs/pair), o={o}, v={v}, "
+                               f"naux={naux}; bfloat16 MFMA contractions (ladder and ring; ring split into "
+                               f"{args.bf16_passes} pass(es)) with FP32 accumulation, FP32 / FP64 others",
+                   "o": o, "v": v, "naux": naux, "nroots": nroots, "space": "pno", "tcut": tcut,
+                   "step": "one sigma block: back-transform, canonical sigma, projection, PNO-space ladder"},
+        "roofline": roof,
+        "roofline_all": fams,
+        "sigma_block_fp64": {"ms_per_block": 1e3 * dt64 / nb64, "sigma_evals_per_s": nroots * nb64 / dt64,
+                             "speedup_bf16_vs_fp64": (dt64 / nb64) / (dt / args.steps),
+                             "ring": family(regs64, "ring", ("mfma", "fp64"), "ring products (gemm_kernel tag 3)",
+                                            "one FP64 GEMM launch")},
+        "setup": {"generate_s": t_gen, "build_df_s": t_df, "build_sapno_s": t_pno, "npno_mean": float(npno.mean()),
+                  "npno_min": int(npno.min()), "npno_max": int(npno.max()), "nosv_mean": float(nosv.mean()),
+                  "pno_len": plen, "ladder_split": split},
+        "measured_peaks": dict(peaks, note="register-only MFMA loops on every CU; HBM = 1 GiB device copy"),
+    }
+    if not args.no_ttc:
+        # time to convergence: FP64, then BF16 contractions with the FP64 refinement
+        t0 = time.perf_counter()
+        r64 = ctx.davidson(nroots, space=PNO, precision=FP64, verbose=True, **dav)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        log(f"FP64 Davidson: {t64:.1f} s, {r64['nsigma']} sigma")
+        t0 = time.perf_counter()
+        rb = ctx.davidson(nroots, space=PNO, precision=BF16, refine_fp64=True, verbose=True, **dav)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        log(f"BF16-mixed Davidson: {tb:.1f} s, {rb['nsigma']} sigma")
+        om64 = r64["omega"]
+        mp = rb.get("main_phase")
+        out["time_to_convergence"] = {
+            "fp64": {"seconds": t64, "iters": r64["iters"], "sigma": r64["nsigma"], "omega": list(map(float, om64))},
+            "bf16_mixed": {"seconds": tb, "iters": rb["iters"], "sigma": rb["nsigma"],
+                           "omega": list(map(float, rb["omega"])),
+                           "speedup_vs_fp64": t64 / tb,
+                           "abs_err_per_root_vs_fp64_eh": [float(abs(a - b)) for a, b in zip(rb["omega"], om64)],
+                           "mixed_phase": None if mp is None else {
+                               "seconds": mp["seconds"], "iters": mp["iters"], "sigma": mp["nsigma"],
+                               "abs_err_per_root_vs_fp64_eh": [float(abs(a - b)) for a, b in zip(mp["omega"], om64)]},
+                           "refinement": None if rb.get("refine_phase") is None else {
+                               k: rb["refine_phase"][k] for k in ("seconds", "iters", "nsigma")}},
+            "note": "Davidson only (setup above); the FP64 PNO-space run is the reference of the per-root errors "
+                    "(the oracle cannot run this workload's Davidson: see the config-2 comparison below and the "
+                    "sampled sigma parity tests at this size)"}
+    del ctx
+    torch.cuda.empty_cache()
+    if not args.no_config2:
+        # FP64 canonical o=20, v=150: per-root error against the oracle's Davidson reference
+        s2 = config_system(2)
+        c2 = CONFIGS[2]
+        ctx2 = PnoEom(s2.o, s2.v, s2.naux)
+        B2, e2, t12 = (torch.from_numpy(x).to(dev) for x in (s2.B, s2.eps, s2.t1))
+        t0 = time.perf_counter()
+        ctx2.build_df(B2, e2, t12)
+        r2 = ctx2.davidson(c2["nroots"], tol_e=c2["tol_e"], tol_r=c2.get("tol_r", 1e-5), max_sub=c2.get("max_sub", 60),
+                           nextra=c2.get("nextra", 0))
+        torch.cuda.synchronize()
+        tc2 = time.perf_counter() - t0
+        ent = {"seconds_incl_build_df": tc2, "sigma": r2["nsigma"], "omega": list(map(float, r2["omega"]))}
+        gold = os.path.join(ROOT, "tests", "golden", "c2.json")
+        if os.path.exists(gold):
+            ref = np.array(json.load(open(gold))["davidson"][:c2["nroots"]])
+            ent["abs_err_per_root_vs_oracle_eh"] = [float(x) for x in np.abs(r2["omega"] - ref)]
+        out["config2_fp64_canonical"] = ent
+        del ctx2
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline_pairs(s, o * (o + 1) // 2)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=None,
+                    help="workload (default 4; the --ccsd run and the config-2 flow default to 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-pno", action="store_true")
@@ -443,12 +687,19 @@ def main():
                     help="ground- vs excited-state PNO truncation errors (reduced PNO workload)")
     ap.add_argument("--ccsd", action="store_true",
                     help="CCSD ground state, then EOM-CCSD on its amplitudes (config 1-3)")
+    ap.add_argument("--bf16-passes", type=int, default=3, help="passes of the bfloat16 ring products (1 or 3)")
+    ap.add_argument("--no-ttc", action="store_true", help="skip the Davidson time-to-convergence runs")
+    ap.add_argument("--no-config2", action="store_true", help="skip the o=20, v=150 oracle comparison")
+    ap.add_argument("--legacy", action="store_true",
+                    help="config 3/4: the whole-Davidson steps of the canonical-workload flow instead")
     ap.add_argument("--pno-ladder", type=int, default=-1,
                     help="PNO-space ladder for pairs with n_p up to this (-1 automatic, 0 none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.config is None:
+        args.config = 2 if args.ccsd else 4
     if args.config == 5:
         config5_share(args)
         return
@@ -460,6 +711,9 @@ def main():
         return
     if args.gs_es_study:
         gs_es_study(args)
+        return
+    if args.config in (3, 4) and not args.legacy:
+        headline_pno(args)
         return
 
     import torch

@@ -175,6 +175,27 @@ int pnoeom_pno_ladder_stats(const pnoeom_ctx* ctx, int* cut, int* native_pairs, 
 enum { PNOEOM_LADDER_AUTO = 0, PNOEOM_LADDER_CACHED = 1, PNOEOM_LADDER_STREAMED = 2 };
 int pnoeom_set_ladder_mode(pnoeom_ctx* ctx, int mode, int max_slab);
 
+/* Evaluation of the R1-driven three-body ring terms of sigma2 (Methods: the EOM sigma
+ * equations of the cited Stanton-Bartlett formalism), for the next pnoeom_build_df.  The
+ * integrals (ij|ab)' of the R1-transformed factors are sum_c r_j^c (ic|ab)~ - sum_l r_l^a
+ * (ij|lb)~, so their products with T2 can go through two T-only intermediates built
+ * once per T: Y = (ic|ab)~ T (v^2 x 2ov words) and Z = (ij|lb)~ T (o^2 x 2ov words),
+ * at 4 o^2 v^3 + 4 o^3 v^2 flop per trial vector, or through (ij|ab)' itself as an
+ * ov x ov operand of the ring product (4 (ov)^3 flop per vector, no extra storage).
+ *   mode 0: the intermediates when they take at most a third of the free device memory;
+ *   mode 1: never;  mode 2: always (ENOMEM at build_df if they do not fit).
+ * pnoeom_ring_mode_used returns 2 (intermediates) or 1 for the current build, ESTATE
+ * before build_df.  Errors: EINVAL (null ctx, bad mode). */
+int pnoeom_set_ring_mode(pnoeom_ctx* ctx, int mode);
+int pnoeom_ring_mode_used(const pnoeom_ctx* ctx);
+
+/* Passes of the bfloat16 ring products of PNOEOM_BF16 contractions (next pnoeom_build_df;
+ * only with the T-only ring intermediates, else those products run on FP32 MFMA): 1 = one
+ * bfloat16 product (inputs rounded to bfloat16, relative error ~2^-8), 3 = each operand
+ * split as hi + lo (both bfloat16) and hi hi + hi lo + lo hi summed in FP32 by one GEMM of
+ * three times the depth (relative error ~2^-16).  Default 3.  Errors: EINVAL. */
+int pnoeom_set_bf16_passes(pnoeom_ctx* ctx, int passes);
+
 /* Prepare the context for pnoeom_ladder_apply alone: the dressed virtual factors
  * B~^Q_ac = B^Q_ac - sum_k t_k^a B^Q_kc (the virtual block of the T1 similarity
  * transformation of the Methods section) and the streamed-ladder workspace, without
@@ -217,6 +238,14 @@ int pnoeom_ladder_apply_noalloc(pnoeom_ctx* ctx, int nmat, const double* X, doub
 /* Largest nmat pnoeom_ladder_apply_noalloc accepts for this context's v in a precision
  * (host arithmetic only); -1 for a null context or an unknown precision. */
 long long pnoeom_ladder_noalloc_limit(const pnoeom_ctx* ctx, int precision);
+
+/* The phases of the last pnoeom_davidson call on this context: phase 0 = the main run
+ * (with precision FP32 / BF16 and refine_fp64 the mixed-precision run before the
+ * refinement, else the whole run), phase 1 = the FP64 refinement.  Copies up to cap
+ * Ritz values and residual norms (host), the iterations, sigma evaluations and the wall
+ * seconds of that phase.  ESTATE when the phase did not run; EINVAL for bad arguments. */
+int pnoeom_davidson_phase(const pnoeom_ctx* ctx, int phase, int cap, double* omega_out, double* resnorm_out,
+                          int* iters_out, int* nsigma_out, double* seconds_out);
 
 typedef struct {
   int space;           /* PNOEOM_CANONICAL or PNOEOM_PNO */
@@ -379,6 +408,20 @@ int pnoeom_gemm_record(int enable);
 int pnoeom_gemm_recorded(long long* keys, int cap);
 int pnoeom_gemm_time(void* hip_stream, const long long* key, int variant, int reps, double* ms);
 int pnoeom_gemm_set_table(int n, const long long* keys, const int* variants);
+
+/* bfloat16 GEMM with FP32 accumulation, the kernel of every BF16 contraction (ladder, W
+ * slab builds, ring products): C = alpha A B^T + beta C with A [M][lda] and B [N][ldb]
+ * device bfloat16 bit patterns (K contiguous; K, lda, ldb multiples of 64 with the
+ * padding columns zero; 16-byte aligned), C [M][ldc] device FP32, ldc >= N.  variant:
+ * 0 = chosen by shape, 1 = 128 x 128 tiles (16x16x32 MFMA), 2 = 256 x 256 tiles
+ * (32x32x16 MFMA; needs M, N >= 256).  Stream-ordered on hip_stream (NULL = default).
+ * pnoeom_gemm_bf16_time times a variant on scratch operands of shape M x N x K that it
+ * allocates (reps launches; *ms = mean milliseconds, -1 above 16 GiB of operands).
+ * Errors: EINVAL (shape, padding, alignment, variant), EHIP, ENOMEM. */
+int pnoeom_gemm_bf16(void* hip_stream, long long M, long long N, long long K, float alpha, const void* A,
+                     long long lda, const void* B, long long ldb, float beta, float* C, long long ldc, int variant);
+int pnoeom_gemm_bf16_time(void* hip_stream, long long M, long long N, long long K, int variant, int reps,
+                          double* ms);
 
 /* Host symmetric eigensolver used by pnoeom_build_sapno for pair-density and
  * semicanonical blocks larger than the GPU Jacobi kernel handles well (Methods: the

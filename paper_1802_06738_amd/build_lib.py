@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpnoeom.so")
-SOURCES = ["gemm.hip", "tensor.hip", "sigma.hip", "ladder.hip", "davidson.hip", "sapno.hip", "ccsd.hip", "probe.hip", "eig.cpp",
+SOURCES = ["gemm.hip", "gemm_bf16.hip", "tensor.hip", "sigma.hip", "ladder.hip", "davidson.hip", "sapno.hip", "ccsd.hip", "probe.hip", "eig.cpp",
            "capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
@@ -19,9 +19,17 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-tar
          "-Wno-unused-function"]
 
 
+# kernels whose MFMA accumulators exceed the ordinary VGPRs keep them in the accumulation
+# registers: these files are built without the VGPR-form option
+ACC_FORM = {"gemm_bf16.hip"}
+
+
 def _compile(src: str) -> str:
     out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
+    flags = FLAGS
+    if src in ACC_FORM:
+        flags = [f for f in FLAGS if f not in ("-mllvm", "-amdgpu-mfma-vgpr-form")]
+    cmd = [HIPCC, *flags, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

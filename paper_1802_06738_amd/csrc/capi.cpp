@@ -224,6 +224,41 @@ int pnoeom_apply_sigma(pnoeom_ctx* ctx, int nvec, const double* r1, const double
   });
 }
 
+int pnoeom_set_ring_mode(pnoeom_ctx* ctx, int mode) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(mode >= 0 && mode <= 2, PNOEOM_EINVAL, "set_ring_mode: unknown mode");
+    c.ring_mode = mode;
+  });
+}
+
+int pnoeom_davidson_phase(const pnoeom_ctx* ctx, int phase, int cap, double* omega_out, double* resnorm_out,
+                          int* iters_out, int* nsigma_out, double* seconds_out) {
+  if (!ctx || phase < 0 || phase > 1 || cap < 0) return PNOEOM_EINVAL;
+  const pnoeom::Context::PhaseRecord& pr = ctx->c.dav_phase[phase];
+  if (pr.n == 0) return PNOEOM_ESTATE;
+  for (int k = 0; k < cap && k < pr.n; ++k) {
+    if (omega_out) omega_out[k] = pr.omega[k];
+    if (resnorm_out) resnorm_out[k] = k < (int)pr.resnorm.size() ? pr.resnorm[k] : 0.0;
+  }
+  if (iters_out) *iters_out = pr.iters;
+  if (nsigma_out) *nsigma_out = pr.nsigma;
+  if (seconds_out) *seconds_out = pr.seconds;
+  return PNOEOM_OK;
+}
+
+int pnoeom_set_bf16_passes(pnoeom_ctx* ctx, int passes) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(passes == 1 || passes == 3, PNOEOM_EINVAL, "set_bf16_passes: 1 or 3");
+    c.ring_passes = passes;
+  });
+}
+
+int pnoeom_ring_mode_used(const pnoeom_ctx* ctx) {
+  if (!ctx) return PNOEOM_EINVAL;
+  if (!ctx->c.have_df) return PNOEOM_ESTATE;
+  return ctx->c.ring_y ? 2 : 1;
+}
+
 int pnoeom_set_ladder_mode(pnoeom_ctx* ctx, int mode, int max_slab) {
   return guarded(ctx, [&](pnoeom::Context& c) {
     PNO_CHECK(mode == PNOEOM_LADDER_AUTO || mode == PNOEOM_LADDER_CACHED || mode == PNOEOM_LADDER_STREAMED,
@@ -478,6 +513,40 @@ int pnoeom_gemm_time(void* hip_stream, const long long* key, int variant, int re
     pnoeom::GemmKey k;
     for (int j = 0; j < 8; ++j) k[j] = key[j];
     *ms = pnoeom::gemm_tune_time((hipStream_t)hip_stream, k, variant, reps);
+    return PNOEOM_OK;
+  } catch (const pnoeom::Error& e) {
+    (void)hipGetLastError();
+    return e.code;
+  } catch (...) {
+    (void)hipGetLastError();
+    return PNOEOM_EHIP;
+  }
+}
+
+int pnoeom_gemm_bf16(void* hip_stream, long long M, long long N, long long K, float alpha, const void* A,
+                     long long lda, const void* B, long long ldb, float beta, float* C, long long ldc, int variant) {
+  try {
+    pnoeom::GemmBf16Desc d;
+    d.M = M; d.N = N; d.K = K; d.alpha = alpha; d.beta = beta;
+    d.A = (const uint16_t*)A; d.lda = lda; d.B = (const uint16_t*)B; d.ldb = ldb; d.C = C; d.ldc = ldc;
+    d.variant = variant;
+    PNO_CHECK(M >= 0 && N >= 0 && K >= 0 && ldc >= N, PNOEOM_EINVAL, "gemm_bf16: bad shape");
+    pnoeom::gemm_bf16(d, (hipStream_t)hip_stream);
+    return PNOEOM_OK;
+  } catch (const pnoeom::Error& e) {
+    (void)hipGetLastError();
+    return e.code;
+  } catch (...) {
+    (void)hipGetLastError();
+    return PNOEOM_EHIP;
+  }
+}
+
+int pnoeom_gemm_bf16_time(void* hip_stream, long long M, long long N, long long K, int variant, int reps,
+                          double* ms) {
+  if (!ms) return PNOEOM_EINVAL;
+  try {
+    *ms = pnoeom::gemm_bf16_time((hipStream_t)hip_stream, M, N, K, variant, reps);
     return PNOEOM_OK;
   } catch (const pnoeom::Error& e) {
     (void)hipGetLastError();

@@ -11,8 +11,9 @@ struct SigmaWork {
   DBuf<double> BvopT, BoopT, BvvpT;
   DBuf<double> R2c, Ria, UiaR, UR, URp, Ubr;
   // ZZ[(q,i,a)][Ziajb row | Z3 row]; RE[(q,i,a)][R^s row | E_X row] (the stacked left operand
-  // of the fused ring product)
+  // of the fused ring product; R^s rows only when the E_X products go through Yr / Zr)
   DBuf<double> ZZ, RE, Zp, Cba, Xh, O4p, OOVVp, M1;
+  DBuf<double> R1c;  // the block's R1 compacted as [(q,j)][c] (ring terms through Yr / Zr)
   DBuf<double> Ftv, Fto;
   DBuf<double> LadAll, Sp, Am, SigP, SigM;  // batched packed ladder
   DBuf<float> Spf, Amf, SigPf, SigMf;
@@ -22,7 +23,7 @@ struct SigmaWork {
   void release() {
     for (DBuf<double>* b : {&Bp, &hp, &Jp, &Kp, &fp, &dp, &fp_ov, &fp_vv, &fp_oo, &BvopT, &BoopT, &BvvpT, &R2c, &Ria,
                             &UiaR, &UR, &URp, &Ubr, &ZZ, &RE, &Zp, &Cba, &Xh, &O4p,
-                            &OOVVp, &M1, &Ftv, &Fto, &LadAll, &Sp, &Am, &SigP, &SigM})
+                            &OOVVp, &M1, &R1c, &Ftv, &Fto, &LadAll, &Sp, &Am, &SigP, &SigM})
       b->release();
     for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fc}) b->release();
     Spb.release();
@@ -45,7 +46,8 @@ struct PNOData {
   DBuf<double> denom_base;      // per compressed element: F_ii (+ F_jj) - fbar_a (- fbar_b)
   DBuf<int64_t> d_off;          // diagonal pair blocks: offsets
   DBuf<int> d_n;                //                       sizes
-  GroupTable t_c1, t_c3, t_c2d, t_c2o, t_e1, t_e3, t_e2d, t_e2o;  // compress / expand
+  GroupTable t_c1, t_c3, t_c2d, t_c2o, t_e1, t_e3;  // compress / expand (first stage)
+  DBuf<int64_t> d_xpair;        // per pair: i, j, n_p, offset of its v x n_p block in Tw, in U
   DBuf<double> Tw, r1, r2, s1, s2;
   double xf_flops = 0;          // flops of one compress (or expand) of one vector
   // ladder of the pairs with n_p <= nat_cut evaluated in the PNO space with per-pair
@@ -65,7 +67,7 @@ struct PNOData {
     built = false;
     npno.clear(); nosv.clear(); off.clear(); uoff.clear(); toff.clear();
     len = 0; nmax = 0;
-    U.release(); denom_base.release(); d_off.release(); d_n.release();
+    U.release(); denom_base.release(); d_off.release(); d_n.release(); d_xpair.release();
     Tw.release(); r1.release(); r2.release(); s1.release(); s2.release();
     nat_cut = nat_pairs = canon_pairs = 0;
     prow.clear(); d_prow.release(); Bbar.release(); Y1.release(); Ypart.release(); nat_flops = 0;
@@ -95,6 +97,20 @@ struct Context {
   // ring operands, rows of 2 ov: [Dr | Xr] (rows 0..ov-1) stacked on [Tia | Tsia] (rows
   // ov..2ov-1), the right operand of the fused product [R^s | E_X] DXTT
   DBuf<double> DXTT;
+  // R1-driven three-body ring terms through T-only intermediates (ring_y): with
+  // TT = [T_ia | T^s_ia] (rows of 2 ov),
+  //   Yr[(a,c)][2 ov] = sum_(i,b) (ic|ab)~ TT[(i,b)],   Zr[(j,l)][2 ov] = sum_(i,b) (ij|lb)~ TT[(i,b)]
+  // (then DXTT holds only its [Dr | Xr] rows).  ring_mode: 0 when Yr fits, 1 never, 2 always.
+  DBuf<double> Yr, Zr;
+  bool ring_y = false;
+  int ring_mode = 0;
+  // BF16 ring products (precision BF16 with ring_y): right operands [Dr | Xr]^T and DX2^T as
+  // bfloat16 rows of ring_passes blocks of ldr (= ov padded to 64) values: one pass takes
+  // bf16(x), three passes the split x = hi + lo as [hi | lo | hi] (left operands [hi | hi | lo]),
+  // so that the products sum to hi hi + hi lo + lo hi
+  DBuf<uint16_t> DXb, DX2b;
+  int64_t ldr = 0;
+  int ring_passes = 3;
   // packed ladder: W+[(a<=b),(c<=d)] = W_abcd + W_abdc, W-[(a<b),(c<d)] = W_abcd - W_abdc
   DBuf<double> Wp, Wm;          // FP64 (always: the FP64 sigma and the refinement of mixed runs)
   DBuf<float> Wpf, Wmf;         // FP32 (precision FP32)
@@ -128,6 +144,13 @@ struct Context {
 
   SigmaWork sw;
   PNOData pno;
+  // the phases of the last Davidson call: [0] the main run (FP32 / BF16 before a refinement,
+  // or the whole FP64 run), [1] the FP64 refinement; n = 0 when the phase did not run
+  struct PhaseRecord {
+    std::vector<double> omega, resnorm;
+    int iters = 0, nsigma = 0, n = 0;
+    double seconds = 0;
+  } dav_phase[2];
   PNOData gs;   // ground-state PNOs / OSVs of the PNO-CCSD simulation (build_gs_pnos; build_df keeps them)
 
   // E_CC - E_ref and largest |Omega| of every amplitude set of the last pnoeom_ccsd

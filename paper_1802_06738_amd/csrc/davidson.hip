@@ -985,12 +985,29 @@ DavidsonResult davidson(Context& c, int nroots, const pnoeom_davidson_opts& opt)
     prec = PNOEOM_FP64;
     return run_davidson(c, op, nroots, guess, std::min(nguess, nroots), opt, "eom-fp64-refine", nullptr, 0, 0, 1);
   }
+  auto record = [&](int ph, const DavidsonResult& rr, double secs) {
+    Context::PhaseRecord& pr = c.dav_phase[ph];
+    pr.omega = rr.omega;
+    pr.resnorm = rr.resnorm;
+    pr.iters = rr.iters;
+    pr.nsigma = rr.nsigma;
+    pr.n = (int)rr.omega.size();
+    pr.seconds = secs;
+  };
+  c.dav_phase[0] = Context::PhaseRecord();
+  c.dav_phase[1] = Context::PhaseRecord();
+  const auto t0 = std::chrono::steady_clock::now();
   DavidsonResult r = run_davidson(c, op, nroots, guess, nguess, mopt,
                                   prec == PNOEOM_FP32 ? "eom-fp32" : prec == PNOEOM_BF16 ? "eom-bf16" : "eom", xr,
                                   opt.nextra);
+  PNO_HIP(hipStreamSynchronize(s));
+  const auto t1 = std::chrono::steady_clock::now();
+  record(0, r, std::chrono::duration<double>(t1 - t0).count());
   if (refine && r.converged) {
     prec = PNOEOM_FP64;
     DavidsonResult r2 = run_davidson(c, op, nroots, xr, nroots, opt, "eom-fp64-refine", nullptr, 0, r.iters, 1);
+    PNO_HIP(hipStreamSynchronize(s));
+    record(1, r2, std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count());
     r2.iters += r.iters;
     r2.nsigma += r.nsigma;
     r = r2;

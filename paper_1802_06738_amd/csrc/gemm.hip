@@ -755,6 +755,14 @@ void gemm_bf16(const GemmBf16Desc& d, hipStream_t s) {
             "gemm_bf16: K and the leading dimensions must be padded to multiples of 64 and 8");
   PNO_CHECK(((uintptr_t)d.A % 16) == 0 && ((uintptr_t)d.B % 16) == 0, PNOEOM_EINVAL,
             "gemm_bf16: operands must be 16-byte aligned");
+  PNO_CHECK(d.variant >= 0 && d.variant <= 2, PNOEOM_EINVAL, "gemm_bf16: unknown variant");
+  PNO_CHECK(d.variant != 2 || gemm_bf16_big_fits(d.M, d.N), PNOEOM_EINVAL,
+            "gemm_bf16: the 256 x 256 tiles need M, N >= 256");
+  if (d.variant == 2 || (d.variant == 0 && gemm_bf16_big_fits(d.M, d.N) &&
+                         ((d.M + 255) / 256) * ((d.N + 255) / 256) >= 256)) {
+    gemm_bf16_big(d, s);
+    return;
+  }
   constexpr int BM = 128, BN = 128;
   Bf16Args g;
   g.M = d.M; g.N = d.N; g.K = d.K; g.alpha = d.alpha; g.beta = d.beta;
@@ -773,9 +781,48 @@ void gemm_bf16(const GemmBf16Desc& d, hipStream_t s) {
     hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, 1>), dim3((unsigned)gx), dim3(NT), 0, s, g);
   else if (d.tag == 2)
     hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, 2>), dim3((unsigned)gx), dim3(NT), 0, s, g);
+  else if (d.tag == 3)
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, 3>), dim3((unsigned)gx), dim3(NT), 0, s, g);
   else
     hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, 0>), dim3((unsigned)gx), dim3(NT), 0, s, g);
   PNO_HIP(hipGetLastError());
+}
+
+namespace {
+__global__ void fill_bf16_kernel(int64_t n, uint16_t* x) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const float f = 1e-3f * (float)((e * 2654435761ll) % 1000) - 0.5f;
+    x[e] = (uint16_t)(__float_as_uint(f) >> 16);
+  }
+}
+}  // namespace
+
+double gemm_bf16_time(hipStream_t s, int64_t M, int64_t N, int64_t K, int variant, int reps) {
+  PNO_CHECK(M > 0 && N > 0 && K > 0 && K % kBf16K == 0 && reps > 0, PNOEOM_EINVAL, "gemm_bf16_time: bad shape");
+  if ((M * K + N * K) * 2 + M * N * 4 > (16ll << 30)) return -1.0;  // not timed: too large
+  DBuf<uint16_t> A, B;
+  DBuf<float> C;
+  A.alloc(M * K);
+  B.alloc(N * K);
+  C.alloc(M * N);
+  hipLaunchKernelGGL(fill_bf16_kernel, dim3(1024), dim3(256), 0, s, M * K, (uint16_t*)A);
+  hipLaunchKernelGGL(fill_bf16_kernel, dim3(1024), dim3(256), 0, s, N * K, (uint16_t*)B);
+  PNO_HIP(hipGetLastError());
+  GemmBf16Desc d;
+  d.M = M; d.N = N; d.K = K; d.A = A; d.lda = K; d.B = B; d.ldb = K; d.C = C; d.ldc = N; d.variant = variant;
+  gemm_bf16(d, s);  // warm-up
+  hipEvent_t e0, e1;
+  PNO_HIP(hipEventCreate(&e0));
+  PNO_HIP(hipEventCreate(&e1));
+  PNO_HIP(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) gemm_bf16(d, s);
+  PNO_HIP(hipEventRecord(e1, s));
+  PNO_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  PNO_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return (double)ms / reps;
 }
 
 namespace {

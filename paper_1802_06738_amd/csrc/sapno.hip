@@ -195,15 +195,77 @@ __global__ void gather_kept_kernel(int ld, int v, int nsel, const int* __restric
   }
 }
 
-// r2[j][i][b][a] = r2[i][j][a][b] for i < j
-__global__ void mirror_pairs_kernel(int o, int v, double* __restrict__ r2) {
-  const int64_t vv = (int64_t)v * v, n = (int64_t)o * o * vv;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t pr = e / vv, r = e % vv;
-    const int i = (int)(pr / o), j = (int)(pr % o);
-    if (i >= j) continue;
-    const int a = (int)(r / v), b = (int)(r % v);
-    r2[((int64_t)j * o + i) * vv + (int64_t)b * v + a] = r2[e];
+// Second stage of the back-transform, one pair block per workgroup row and one 64 x 64 tile
+// (a, b) of it per workgroup: R^{ij}[a][b] = w sum_d T_p[a][d] U_p[b][d] (T_p = U_p X_p, both
+// v x n_p row-major; w = 1 on diagonal pairs, 1/sqrt 2 off the diagonal), written into
+// r2[i][j][a][b] and, for i < j, into r2[j][i][b][a] through an LDS copy of the tile so that
+// both writes run along rows.  Every element of r2 belongs to one tile of one pair (a pair
+// with n_p = 0 writes zeros), so the array needs no clearing and no mirror pass.
+// FP64 MFMA 16x16x4: 4 waves in 2 x 2, each a 32 x 32 block; operand lane l supplies
+// A[l%16][k0 + l/16] and B[k0 + l/16][l%16], accumulator r holds row l/16 + 4 r, column l%16.
+constexpr int kXT = 64, kXK = 16;
+__global__ __launch_bounds__(256) void expand_pairs_kernel(int o, int v, const int64_t* __restrict__ xpair,
+                                                           const double* __restrict__ Tw,
+                                                           const double* __restrict__ U, double w_off,
+                                                           double* __restrict__ r2) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __shared__ double As[kXK][kXT + 1];
+  __shared__ double Bs[kXK][kXT + 1];
+  __shared__ double Cs[kXT][kXT + 1];
+  const int64_t* d = xpair + 5 * (int64_t)blockIdx.y;
+  const int i = (int)d[0], j = (int)d[1], n = (int)d[2];
+  const double* T = Tw + d[3];
+  const double* Up = U + d[4];
+  const int nt = (v + kXT - 1) / kXT;
+  const int a0 = (int)(blockIdx.x / nt) * kXT, b0 = (int)(blockIdx.x % nt) * kXT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < n; k0 += kXK) {
+    for (int e = tid; e < kXT * kXK; e += 256) {
+      const int r = e / kXK, k = e % kXK;
+      As[k][r] = (a0 + r < v && k0 + k < n) ? T[(int64_t)(a0 + r) * n + k0 + k] : 0.0;
+      Bs[k][r] = (b0 + r < v && k0 + k < n) ? Up[(int64_t)(b0 + r) * n + k0 + k] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kXK; kk += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) av[x] = As[kk + lk][wm * 32 + x * 16 + lr];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = Bs[kk + lk][wn * 32 + y * 16 + lr];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const double w = i == j ? 1.0 : w_off;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Cs[wm * 32 + x * 16 + lk + 4 * r][wn * 32 + y * 16 + lr] = w * acc[x][y][r];
+  __syncthreads();
+  const int64_t vv = (int64_t)v * v;
+  double* Rij = r2 + ((int64_t)i * o + j) * vv;
+  for (int e = tid; e < kXT * kXT; e += 256) {
+    const int a = e / kXT, b = e % kXT;
+    if (a0 + a < v && b0 + b < v) Rij[(int64_t)(a0 + a) * v + b0 + b] = Cs[a][b];
+  }
+  if (i != j) {
+    double* Rji = r2 + ((int64_t)j * o + i) * vv;
+    for (int e = tid; e < kXT * kXT; e += 256) {
+      const int b = e / kXT, a = e % kXT;
+      if (a0 + a < v && b0 + b < v) Rji[(int64_t)(b0 + b) * v + a0 + a] = Cs[a][b];
+    }
   }
 }
 
@@ -585,7 +647,7 @@ void pnos_from_density(Context& c, PNOData& P, const double* D, double inv_n, do
   }
   // grouped-GEMM tables for compress / expand (one vector; bases shifted per vector)
   {
-    std::vector<GroupDesc> cs1, cs2d, cs2o, cs3, ex1, ex2d, ex2o, ex3;
+    std::vector<GroupDesc> cs1, cs2d, cs2o, cs3, ex1, ex3;
     int64_t toff = 0;
     P.toff.assign(npair + 1, 0);
     for (int p = 0; p < npair; ++p) {
@@ -622,9 +684,7 @@ void pnos_from_density(Context& c, PNOData& P, const double* D, double inv_n, do
       d.M = v; d.N = n; d.K = n; d.offA = uoff[p]; d.lda = n; d.offB = P.off[o + p]; d.ldb = n; d.offC = P.toff[p];
       d.ldc = n;
       ex3.push_back(d);
-      // R^{ij} = T_p U_p^T / w  (v x v)
-      d.M = v; d.N = v; d.K = n; d.offA = P.toff[p]; d.lda = n; d.offB = uoff[p]; d.ldb = n; d.offC = rof; d.ldc = v;
-      (pi[p] == pj[p] ? ex2d : ex2o).push_back(d);
+      // R^{ij} = T_p U_p^T / w (v x v, and its transpose for ji): expand_pairs_kernel
     }
     gemm_grouped_prepare(cs1, false, false, P.t_c1);
     gemm_grouped_prepare(cs3, false, false, P.t_c3);
@@ -632,9 +692,14 @@ void pnos_from_density(Context& c, PNOData& P, const double* D, double inv_n, do
     gemm_grouped_prepare(cs2o, true, false, P.t_c2o);
     gemm_grouped_prepare(ex1, false, true, P.t_e1);
     gemm_grouped_prepare(ex3, false, false, P.t_e3);
-    gemm_grouped_prepare(ex2d, false, true, P.t_e2d);
-    gemm_grouped_prepare(ex2o, false, true, P.t_e2o);
     P.Tw.alloc(std::max<int64_t>(P.toff[npair], 1));
+    std::vector<int64_t> xp(5 * (size_t)npair);
+    for (int p = 0; p < npair; ++p) {
+      xp[5 * p] = pi[p]; xp[5 * p + 1] = pj[p]; xp[5 * p + 2] = P.npno[p];
+      xp[5 * p + 3] = P.toff[p]; xp[5 * p + 4] = uoff[p];
+    }
+    P.d_xpair.alloc(std::max<int64_t>(5 * npair, 1));
+    PNO_HIP(hipMemcpy(P.d_xpair, xp.data(), xp.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   }
 }
 
@@ -790,15 +855,16 @@ void pno_expand(Context& c, PNOData& P, int nvec, const double* x, double* r1, d
     double* b2 = r2 + (int64_t)q * c.oovv();
     const double* y = x + (int64_t)q * P.len;
     fill(s, c.ov(), 0.0, b1);
-    fill(s, c.oovv(), 0.0, b2);
     gemm_grouped(P.t_e1, 1.0, y, P.U, 0.0, b1, s);
     gemm_grouped(P.t_e3, 1.0, P.U, y, 0.0, P.Tw, s);
-    gemm_grouped(P.t_e2d, 1.0, P.Tw, P.U, 0.0, b2, s);
-    gemm_grouped(P.t_e2o, isq2, P.Tw, P.U, 0.0, b2, s);
-    hipLaunchKernelGGL(mirror_pairs_kernel, dim3(gsz(c.oovv())), dim3(256), 0, s, c.o, c.v, b2);
+    const int npair = c.o * (c.o + 1) / 2;
+    const int nt = (c.v + kXT - 1) / kXT;
+    PNO_CHECK(npair <= 65535, PNOEOM_EINVAL, "pno_expand: too many pairs for one launch");
+    hipLaunchKernelGGL(expand_pairs_kernel, dim3((unsigned)(nt * nt), (unsigned)npair), dim3(256), 0, s, c.o, c.v,
+                       (const int64_t*)P.d_xpair, (const double*)P.Tw, (const double*)P.U, isq2, b2);
     PNO_HIP(hipGetLastError());
   }
-  c.region_end(ev, 1, s, 7 * nvec, nvec * P.xf_flops,
+  c.region_end(ev, 1, s, 4 * nvec, nvec * P.xf_flops,
                8.0 * nvec * ((double)c.ov() + (double)c.oovv() + (double)P.len + (double)P.U.n));
 }
 

@@ -132,6 +132,27 @@ __device__ __forceinline__ uint16_t cvt_out<uint16_t>(double x) {
   return bf16_bits(x);
 }
 
+// bfloat16 operand rows of the BF16 ring products: row m of out holds `passes` blocks of ldk
+// values; with x = src[m sm + k sk] (0 for k >= K), hi = bf16(x) and lo = bf16(x - hi), a left
+// operand (right = 0) takes [hi | hi | lo] and a right operand [hi | lo | hi], so that the
+// three passes of one product sum to hi hi + hi lo + lo hi; one pass takes hi alone
+__global__ void bf16_split_kernel(int64_t M, int64_t K, const double* __restrict__ src, int64_t sm, int64_t sk,
+                                  uint16_t* __restrict__ out, int64_t ldk, int passes, int right) {
+  const int64_t total = M * ldk, row = ldk * passes;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = e / ldk, k = e % ldk;
+    const double x = k < K ? src[m * sm + k * sk] : 0.0;
+    const uint16_t hi = bf16_bits(x);
+    uint16_t* o = out + m * row + k;
+    o[0] = hi;
+    if (passes == 3) {
+      const uint16_t lo = bf16_bits(x - (double)__uint_as_float((uint32_t)hi << 16));
+      o[ldk] = right ? lo : hi;
+      o[2 * ldk] = right ? hi : lo;
+    }
+  }
+}
+
 // W+[(a<=b),(c<=d)] = W_abcd + W_abdc (c<d), W_abcc (c=d);  W-[(a<b),(c<d)] = W_abcd - W_abdc,
 // from a slab tmp[a-a0][c][b][d] = W_abcd of rows a in [a0, a0+na); row strides ldp, ldm
 template <typename OutT>
@@ -268,6 +289,9 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   c.pno.reset();
   if (precision == PNOEOM_FP64)
     for (DBuf<float>* b : {&c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf}) b->release();
+  c.ring_y = false;
+  c.Yr.release();
+  c.Zr.release();
 
   c.B.alloc((int64_t)naux * n2);
   c.eps.alloc(nmo);
@@ -428,6 +452,53 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     PNO_HIP(hipStreamSynchronize(s));
   }
 
+  // R1-driven three-body ring terms.  The one-index transformed factors give
+  // (ij|ab)' = sum_c r_j^c (ic|ab)~ - sum_l r_l^a (ij|lb)~, so the products of E_X = (ij|ab)'
+  // with T_ia and T^s_ia are r1 times the T-only intermediates Yr (v^2 x 2 ov) and Zr
+  // (o^2 x 2 ov): 4 o^2 v^3 + 4 o^3 v^2 flop per vector instead of 4 (ov)^3 (and no E_X).
+  // Built when Yr and Zr take at most a third of the free memory (or when asked for).
+  {
+    size_t fr = 0, tot = 0;
+    PNO_HIP(hipMemGetInfo(&fr, &tot));
+    const double need = 8.0 * 2.0 * (double)ov * ((double)vv + (double)oo);
+    c.ring_y = c.ring_mode == 2 || (c.ring_mode == 0 && need <= (double)fr / 3.0);
+  }
+  if (c.ring_y) {
+    const double* TT = c.DXTT + 2 * oovv;  // [Tia | Tsia], rows of 2 ov
+    const int64_t ov2 = 2 * ov;
+    c.Yr.alloc(vv * ov2);
+    c.Zr.alloc(oo * ov2);
+    {
+      // (ij|lb)~ as [(i,j)][(l,b)] -> [(j,l)][(i,b)] -> Zr
+      double* t1 = c.build_tmp(1, oo * ov);
+      double* t2 = c.build_tmp(2, oo * ov);
+      gm(s, false, true, oo, ov, naux, 1.0, c.BooT, naux, c.BovT, naux, 0.0, t1, ov);
+      perm(s, t1, o, o, o, v, 1, 2, 0, 3, t2);
+      gm(s, false, false, oo, ov2, ov, 1.0, t2, ov, TT, ov2, 0.0, c.Zr, ov2);
+    }
+    {
+      // slabs of a: (ic|ab)~ as [(a,b)][(i,c)] -> [(a,c)][(i,b)] -> rows (a,c) of Yr
+      int64_t na = v;
+      const int64_t budget = (int64_t)1 << 28;  // doubles per temporary
+      while (na > 1 && na * v * ov > budget) na = (na + 1) / 2;
+      double* t1 = c.build_tmp(1, na * v * ov);
+      double* t2 = c.build_tmp(2, na * v * ov);
+      for (int64_t a0 = 0; a0 < v; a0 += na) {
+        const int64_t nab = std::min<int64_t>(na, v - a0);
+        gm(s, false, true, nab * v, ov, naux, 1.0, c.BvvT + a0 * v * naux, naux, c.BovT, naux, 0.0, t1, ov);
+        perm(s, t1, nab, v, o, v, 0, 3, 2, 1, t2);
+        gm(s, false, false, nab * v, ov2, ov, 1.0, t2, ov, TT, ov2, 0.0, c.Yr + a0 * v * ov2, ov2);
+      }
+    }
+    // only the [Dr | Xr] rows of DXTT are used from here on
+    DBuf<double> top;
+    top.alloc(2 * oovv);
+    PNO_HIP(hipMemcpyAsync(top, c.DXTT, 2 * oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PNO_HIP(hipStreamSynchronize(s));
+    std::swap(c.DXTT.p, top.p);
+    std::swap(c.DXTT.n, top.n);
+  }
+
   // Wvo_kbij = sum_cd (kc|bd)~ T_ij^cd stored as [(i,j,b)][k]; built in slabs of b
   c.Wvo2.alloc(oo * v * o);
   {
@@ -510,9 +581,10 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   }
   if (precision == PNOEOM_FP32 || precision == PNOEOM_BF16) {  // FP32 operands of the other contractions
     c.DX2f.alloc(oovv);
-    c.DXTTf.alloc(4 * oovv);
+    const int64_t ndx = c.ring_y ? 2 * oovv : 4 * oovv;
+    c.DXTTf.alloc(ndx);
     to_float(s, oovv, c.DX2, c.DX2f);
-    to_float(s, 4 * oovv, c.DXTT, c.DXTTf);
+    to_float(s, ndx, c.DXTT, c.DXTTf);
     c.Whf.alloc(oo * oo);
     c.g2f.alloc(oovv);
     c.T32.alloc(oovv);
@@ -521,6 +593,20 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     to_float(s, oovv, c.g2, c.g2f);
     to_float(s, oovv, c.T, c.T32);
     to_float(s, ov * naux, c.BovT, c.BovTf);
+  }
+  c.DXb.release();
+  c.DX2b.release();
+  if (precision == PNOEOM_BF16 && c.ring_y) {  // bfloat16 right operands of the ring products
+    const int64_t ov2 = 2 * ov;
+    c.ldr = bf16_ld(ov);
+    const int64_t kr = c.ring_passes * c.ldr;
+    c.DXb.alloc(ov2 * kr);
+    c.DX2b.alloc(ov * kr);
+    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(ov2 * c.ldr)), dim3(256), 0, s, ov2, ov, (const double*)c.DXTT,
+                       (int64_t)1, ov2, (uint16_t*)c.DXb, c.ldr, c.ring_passes, 1);
+    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(ov * c.ldr)), dim3(256), 0, s, ov, ov, (const double*)c.DX2,
+                       (int64_t)1, ov, (uint16_t*)c.DX2b, c.ldr, c.ring_passes, 1);
+    PNO_HIP(hipGetLastError());
   }
   PNO_HIP(hipStreamSynchronize(s));
   // kept only stacked (DXTT) from here on
@@ -537,12 +623,24 @@ void grow(DBuf<T>& b, int64_t n) {
   if ((int64_t)b.n < n) b.alloc(std::max<int64_t>(n, 1));
 }
 
+// floats of FP32 staging (fa) the bfloat16 left operands of the BF16 ring products take
+// (nb ov rows of ring_passes x ldr bfloat16 values); 0 when the ring is not run in BF16
+int64_t bf16_ring_floats(const Context& c, int precision, int64_t nb) {
+  if (precision != PNOEOM_BF16 || !c.ring_y || !c.DXb.p) return 0;
+  return nb * c.ov() * c.ring_passes * c.ldr;  // two left operands of nb ov rows
+}
+
 // device memory of the per-vector work arrays of sigma_rest (bytes per vector)
 int64_t rest_bytes_per_vector(const Context& c, bool f32) {
   const int64_t ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, oovv = c.oovv();
-  int64_t nd = 13 * oovv + (ov + oo + vv) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv + oo + vv + oo;
+  // 13 o^2 v^2 arrays, 11 when the E_X products go through Yr / Zr (RE holds R^s only, no OOVVp)
+  const int64_t narr = c.ring_y ? 11 : 13;
+  int64_t nd = narr * oovv + (ov + oo + vv) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv + oo + vv + oo +
+               (c.ring_y ? ov : 0);
   int64_t bytes = nd * (int64_t)sizeof(double);
-  if (f32) bytes += 4 * oovv * (int64_t)sizeof(float);  // fa and fc (two oovv each)
+  if (f32)  // fa and fc (two oovv each; fa larger when it stages the BF16 ring operands)
+    bytes += (2 * oovv + std::max<int64_t>(2 * oovv, bf16_ring_floats(c, PNOEOM_BF16, 1) + 1)) *
+             (int64_t)sizeof(float);
   return bytes;
 }
 
@@ -570,7 +668,7 @@ int64_t sigma_held_bytes(const Context& c) {
   int64_t b = 0;
   for (const DBuf<double>* x : {&w.Bp, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT,
                                 &w.BoopT, &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.ZZ,
-                                &w.RE, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.Ftv, &w.Fto,
+                                &w.RE, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.R1c, &w.Ftv, &w.Fto,
                                 &w.LadAll, &w.Sp, &w.Am, &w.SigP, &w.SigM, &c.pno.r1, &c.pno.r2, &c.pno.s1,
                                 &c.pno.s2})
     b += (int64_t)x->n * 8;
@@ -608,12 +706,17 @@ void alloc_sigma_work(Context& c, int precision, int nb) {
   grow(w.R2c, B * oovv);
   grow(w.Ria, B * oovv); grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
   grow(w.URp, B * oovv); grow(w.Ubr, B * oovv);
-  grow(w.ZZ, 2 * B * oovv); grow(w.RE, 2 * B * oovv);
-  grow(w.Zp, B * oovv); grow(w.Cba, B * oovv); grow(w.OOVVp, B * oovv);
+  grow(w.ZZ, 2 * B * oovv); grow(w.RE, (c.ring_y ? 1 : 2) * B * oovv);
+  grow(w.Zp, B * oovv); grow(w.Cba, B * oovv);
+  if (c.ring_y)
+    grow(w.R1c, B * ov);
+  else
+    grow(w.OOVVp, B * oovv);
   grow(w.Xh, B * oo * oo); grow(w.O4p, B * oo * oo); grow(w.M1, B * ov * c.naux);
   grow(w.Ftv, B * vv); grow(w.Fto, B * oo);
   if (precision != PNOEOM_FP64) {
-    grow(w.fa, 2 * B * oovv); grow(w.fc, 2 * B * oovv);
+    grow(w.fa, std::max<int64_t>(2 * B * oovv, bf16_ring_floats(c, precision, nb)));
+    grow(w.fc, 2 * B * oovv);
   }
 }
 
@@ -728,12 +831,13 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   const int64_t nbo = (int64_t)nb * o;
   perm(s, R2, nbo, o, v, v, 0, 2, 1, 3, w.Ria);
   const int64_t ov2 = 2 * ov;
+  const int64_t ldre = c.ring_y ? ov : ov2;  // RE rows: [R^s] or [R^s | E_X]
   {
     // R^s[(q,i,b)][(j,a)] = R[q][i][j][a][b] into the left half of the rows of RE
     Perm4 p;
     p.d[0] = nbo; p.d[1] = v; p.d[2] = o; p.d[3] = v;
     p.is[0] = (int64_t)o * vv; p.is[1] = 1; p.is[2] = vv; p.is[3] = v;
-    p.os[0] = (int64_t)v * ov2; p.os[1] = ov2; p.os[2] = v; p.os[3] = 1;
+    p.os[0] = (int64_t)v * ldre; p.os[1] = ldre; p.os[2] = v; p.os[3] = 1;
     permute4(s, p, 1.0, R2, 0.0, w.RE);
   }
   PNO_HIP(hipMemcpyAsync(w.UiaR, w.Ria, nb * oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -741,7 +845,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     // UiaR = 2 R_ia - R^s (R^s read from RE)
     Perm4 p;
     p.d[0] = (int64_t)nb * ov; p.d[1] = ov; p.d[2] = 1; p.d[3] = 1;
-    p.is[0] = ov2; p.is[1] = 1; p.is[2] = 0; p.is[3] = 0;
+    p.is[0] = ldre; p.is[1] = 1; p.is[2] = 0; p.is[3] = 0;
     p.os[0] = ov; p.os[1] = 1; p.os[2] = 0; p.os[3] = 0;
     permute4(s, p, -1.0, w.RE, 2.0, w.UiaR);
   }
@@ -808,9 +912,9 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   //   E_D^T (2T - T^s) = (1/2 M1 + B'_vo) YU   (DF rank naux)
   //   -E_X^T T, -E_X^T T^s                       (E_X = (ij|ab)' in ring order)
   // so that five (ov x ov x ov) products per vector remain.
-  gmb(s, false, true, oo, vv, naux, 1.0, w.BoopT, naux, oon, c.BvvT, naux, 0, 0.0, w.OOVVp, vv, oovv, nb);
-  gmb(s, false, true, oo, vv, naux, 1.0, c.BooT, naux, 0, w.BvvpT, naux, vvn, 1.0, w.OOVVp, vv, oovv, nb);
-  {
+  if (!c.ring_y) {
+    gmb(s, false, true, oo, vv, naux, 1.0, w.BoopT, naux, oon, c.BvvT, naux, 0, 0.0, w.OOVVp, vv, oovv, nb);
+    gmb(s, false, true, oo, vv, naux, 1.0, c.BooT, naux, 0, w.BvvpT, naux, vvn, 1.0, w.OOVVp, vv, oovv, nb);
     // E_X[(j,a),(i,b)] = (ij|ab)' = OOVVp[i][j][a][b] into the right half of the rows of RE
     Perm4 p;
     p.d[0] = o; p.d[1] = v; p.d[2] = o; p.d[3] = v;
@@ -824,17 +928,41 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   // product with K = 2 ov: [R^s | E_X] (rows of RE) times [Dr | Xr] stacked on [Tia | Tsia]
   // (DXTT), filling both halves of the rows of ZZ = [Ziajb | Z3]; R_ia DX2 adds into the
   // Ziajb half.
+  // With Yr / Zr the first product is R^s [Dr | Xr] alone (K = ov) and the E_X parts follow it.
   const int64_t M = (int64_t)nb * ov;
+  const int64_t K1 = c.ring_y ? ov : ov2;
   // ==== ring product launches: begin
+  const bool bf_ring = precision == PNOEOM_BF16 && c.ring_y && c.DXb.p;
+  uint16_t* ab1 = nullptr;
+  uint16_t* ab2 = nullptr;
+  const int64_t kr = c.ring_passes * c.ldr;
+  if (bf_ring) {
+    // the left operands R^s and R_ia as bfloat16 rows of ring_passes x ldr values, staged in fa
+    ab1 = reinterpret_cast<uint16_t*>((float*)w.fa);
+    ab2 = ab1 + M * kr;
+    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(M * c.ldr)), dim3(256), 0, s, M, ov, (const double*)w.RE, ldre,
+                       (int64_t)1, ab1, c.ldr, c.ring_passes, 0);
+    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(M * c.ldr)), dim3(256), 0, s, M, ov, (const double*)w.Ria, ov,
+                       (int64_t)1, ab2, c.ldr, c.ring_passes, 0);
+    PNO_HIP(hipGetLastError());
+  }
   hipEvent_t ring_ev = c.region_begin(3, s);
-  if (f32) {
+  if (bf_ring) {
+    // bfloat16 MFMA with FP32 accumulation: -R^s [Dr | Xr], then + R_ia DX2 into the left half
+    GemmBf16Desc d;
+    d.M = M; d.N = ov2; d.K = kr; d.alpha = -1.f; d.beta = 0.f; d.A = ab1; d.lda = kr; d.B = c.DXb; d.ldb = kr;
+    d.C = w.fc; d.ldc = ov2; d.tag = 3;
+    gemm_bf16(d, s);
+    d.N = ov; d.alpha = 1.f; d.beta = 1.f; d.A = ab2; d.B = c.DX2b;
+    gemm_bf16(d, s);
+  } else if (f32) {
     float* fa = w.fa;
     float* fc = w.fc;
     const int64_t nt = nb * oovv;
     GemmDesc<float> d;
-    d.M = M; d.N = ov2; d.K = ov2; d.alpha = -1.f; d.beta = 0.f; d.lda = ov2; d.ldb = ov2; d.C = fc; d.ldc = ov2;
+    d.M = M; d.N = ov2; d.K = K1; d.alpha = -1.f; d.beta = 0.f; d.lda = ldre; d.ldb = ov2; d.C = fc; d.ldc = ov2;
     d.tag = 3;
-    to_float(s, 2 * nt, w.RE, fa);
+    to_float(s, (c.ring_y ? 1 : 2) * nt, w.RE, fa);
     d.A = fa; d.B = c.DXTTf;
     gemm(d, s);
     to_float(s, nt, w.Ria, fa);
@@ -843,15 +971,35 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     to_double(s, 2 * nt, fc, w.ZZ, 0.0);
   } else {
     GemmDesc<double> d;
-    d.M = M; d.N = ov2; d.K = ov2; d.alpha = -1.0; d.beta = 0.0; d.lda = ov2; d.ldb = ov2; d.C = w.ZZ; d.ldc = ov2;
+    d.M = M; d.N = ov2; d.K = K1; d.alpha = -1.0; d.beta = 0.0; d.lda = ldre; d.ldb = ov2; d.C = w.ZZ; d.ldc = ov2;
     d.tag = 3;
     d.A = w.RE; d.B = c.DXTT;
     gemm(d, s);
     d.N = ov; d.K = ov; d.alpha = 1.0; d.beta = 1.0; d.A = w.Ria; d.lda = ov; d.B = c.DX2; d.ldb = ov;
     gemm(d, s);
   }
-  c.region_end(ring_ev, 3, s, 2, 10.0 * (double)M * ov * ov, 8.0 * (3.0 * M * ov + 5.0 * oovv + 4.0 * M * ov));
+  c.region_end(ring_ev, 3, s, 2, 2.0 * (double)M * ov2 * K1 + 2.0 * (double)M * ov * ov,
+               8.0 * ((double)M * K1 + (double)K1 * ov2 + 5.0 * M * ov + (double)oovv));
   // ==== ring product launches: end
+  if (bf_ring) to_double(s, 2 * (int64_t)nb * oovv, w.fc, w.ZZ, 0.0);
+  if (c.ring_y) {
+    // E_X [T_ia | T^s_ia] = sum_c r_j^c Yr[(a,c)] - sum_l r_l^a Zr[(j,l)], with the sign of the
+    // fused product: ZZ[(q,j,a)] -= sum_c R1[q][j][c] Yr[(a,c)], += sum_l R1[q][l][a] Zr[(j,l)]
+    {
+      Perm4 p;  // R1 of the block compacted to [(q,j)][c]
+      p.d[0] = nb; p.d[1] = 1; p.d[2] = 1; p.d[3] = ov;
+      p.is[0] = stride1; p.is[1] = 0; p.is[2] = 0; p.is[3] = 1;
+      p.os[0] = ov; p.os[1] = 0; p.os[2] = 0; p.os[3] = 1;
+      permute4(s, p, 1.0, r1, 0.0, w.R1c);
+    }
+    // one product per a over all vectors: [(q,j)] x [c] times Yr[(a,c)] into rows (q,j,a)
+    gmb(s, false, false, (int64_t)nb * o, ov2, v, -1.0, w.R1c, v, 0, c.Yr, ov2, v * ov2, 1.0, w.ZZ, v * ov2,
+        ov2, v);
+    // per vector, one product per j: R1[q]^T (v x o) times Zr[(j,l)] (o x 2 ov) into rows (q,j,a)
+    for (int q = 0; q < nb; ++q)
+      gmb(s, true, false, v, ov2, o, 1.0, w.R1c + q * ov, v, 0, c.Zr, ov2, (int64_t)o * ov2, 1.0,
+          w.ZZ + (int64_t)q * ov * ov2, ov2, v * ov2, o);
+  }
   // the DF-factorised parts of the ring terms, into the Ziajb half
   gmb(s, false, false, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.BYU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
   gmb(s, false, false, ov, ov, naux, 0.5, w.M1, naux, ovn, c.YU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
@@ -1180,7 +1328,7 @@ uint64_t sigma_signature(Context& c, hipStream_t s) {
   SigmaWork& w = c.sw;
   for (DBuf<double>* b : {&w.Bp, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT, &w.BoopT,
                           &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.ZZ,
-                          &w.RE, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.Ftv, &w.Fto, &w.LadAll, &w.Sp,
+                          &w.RE, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.R1c, &w.Ftv, &w.Fto, &w.LadAll, &w.Sp,
                           &w.Am, &w.SigP, &w.SigM, &c.pno.Tw, &c.pno.r1, &c.pno.r2, &c.pno.s1, &c.pno.s2, &c.gin,
                           &c.gout})
     mix(b->p, b->n);

@@ -24,7 +24,10 @@ EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pno
                     "pnoeom_davidson", "pnoeom_host_eig", "pnoeom_last_timing", "pnoeom_last_ladder_timing",
                     "pnoeom_last_region_timing", "pnoeom_host_syev", "pnoeom_probe_peaks",
                     "pnoeom_gemm_record", "pnoeom_gemm_recorded", "pnoeom_gemm_time", "pnoeom_gemm_set_table",
+                    "pnoeom_gemm_bf16", "pnoeom_gemm_bf16_time",
                     "pnoeom_set_graph_mode", "pnoeom_graph_stats", "pnoeom_set_ladder_mode",
+                    "pnoeom_set_ring_mode", "pnoeom_ring_mode_used", "pnoeom_set_bf16_passes",
+                    "pnoeom_davidson_phase",
                     "pnoeom_build_ladder", "pnoeom_ladder_apply", "pnoeom_ladder_apply_noalloc",
                     "pnoeom_ladder_noalloc_limit", "pnoeom_set_pno_ladder",
                     "pnoeom_pno_ladder_stats", "pnoeom_set_pno_states", "pnoeom_ccsd_defaults",
@@ -93,9 +96,16 @@ def load_library():
     lib.pnoeom_gemm_recorded.argtypes = [C.POINTER(C.c_longlong), C.c_int]
     lib.pnoeom_gemm_time.argtypes = [vp, C.POINTER(C.c_longlong), C.c_int, C.c_int, dp]
     lib.pnoeom_gemm_set_table.argtypes = [C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_int)]
+    ll = C.c_longlong
+    lib.pnoeom_gemm_bf16.argtypes = [vp, ll, ll, ll, C.c_float, vp, ll, vp, ll, C.c_float, vp, ll, C.c_int]
+    lib.pnoeom_gemm_bf16_time.argtypes = [vp, ll, ll, ll, C.c_int, C.c_int, dp]
     lib.pnoeom_set_graph_mode.argtypes = [vp, C.c_int]
     lib.pnoeom_graph_stats.argtypes = [vp, ip, ip, ip]
     lib.pnoeom_set_ladder_mode.argtypes = [vp, C.c_int, C.c_int]
+    lib.pnoeom_set_ring_mode.argtypes = [vp, C.c_int]
+    lib.pnoeom_ring_mode_used.argtypes = [vp]
+    lib.pnoeom_set_bf16_passes.argtypes = [vp, C.c_int]
+    lib.pnoeom_davidson_phase.argtypes = [vp, C.c_int, C.c_int, dp, dp, ip, ip, dp]
     lib.pnoeom_build_ladder.argtypes = [vp, vp, vp, C.c_int]
     lib.pnoeom_ladder_apply.argtypes = [vp, C.c_int, vp, vp, C.c_int]
     lib.pnoeom_ladder_apply_noalloc.argtypes = [vp, C.c_int, vp, vp, C.c_int]
@@ -161,6 +171,39 @@ def _dev(t, shape=None, name="tensor"):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
     return C.c_void_p(t.data_ptr())
+
+
+def gemm_bf16(A, B, C_out, alpha=1.0, beta=0.0, variant=0):
+    """C_out = alpha A B^T + beta C_out on the library's bfloat16 MFMA kernels.  A [M, K] and
+    B [N, K] torch.bfloat16 on the device (contiguous, K a multiple of 64), C_out [M, N]
+    torch.float32 (contiguous)."""
+    import torch
+    lib = load_library()
+    for t, dt, nm in ((A, torch.bfloat16, "A"), (B, torch.bfloat16, "B"), (C_out, torch.float32, "C")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise TypeError(f"{nm} must be a contiguous {dt} tensor on a HIP device")
+    M, K = A.shape
+    N = B.shape[0]
+    if B.shape[1] != K or tuple(C_out.shape) != (M, N):
+        raise ValueError("gemm_bf16: shapes do not match")
+    st = lib.pnoeom_gemm_bf16(C.c_void_p(torch.cuda.current_stream().cuda_stream), M, N, K, float(alpha),
+                              C.c_void_p(A.data_ptr()), K, C.c_void_p(B.data_ptr()), K, float(beta),
+                              C.c_void_p(C_out.data_ptr()), N, int(variant))
+    if st != 0:
+        raise PnoEomError(st, "gemm_bf16 failed")
+    return C_out
+
+
+def gemm_bf16_time(M, N, K, variant=0, reps=10):
+    """Mean milliseconds of one bfloat16 GEMM launch of shape M x N x K (scratch operands)."""
+    import torch
+    lib = load_library()
+    ms = C.c_double()
+    st = lib.pnoeom_gemm_bf16_time(C.c_void_p(torch.cuda.current_stream().cuda_stream), M, N, K, int(variant),
+                                   int(reps), C.byref(ms))
+    if st != 0:
+        raise PnoEomError(st, "gemm_bf16_time failed")
+    return ms.value
 
 
 class PnoEom:
@@ -285,7 +328,15 @@ class PnoEom:
                                       C.byref(ns))
         if st not in (0, -6):
             self._check(st)
-        return dict(omega=om, resnorm=rn, iters=it.value, nsigma=ns.value, complex=(st == -6))
+        out = dict(omega=om, resnorm=rn, iters=it.value, nsigma=ns.value, complex=(st == -6))
+        for ph, name in ((0, "main_phase"), (1, "refine_phase")):
+            pom = np.zeros(nroots)
+            prn = np.zeros(nroots)
+            pit, pns, psec = C.c_int(), C.c_int(), C.c_double()
+            if self.lib.pnoeom_davidson_phase(self.h, ph, nroots, _dptr(pom), _dptr(prn), C.byref(pit),
+                                              C.byref(pns), C.byref(psec)) == 0:
+                out[name] = dict(omega=pom, resnorm=prn, iters=pit.value, nsigma=pns.value, seconds=psec.value)
+        return out
 
     def ccsd_residual(self, B, eps, t1, t2):
         """CCSD residual (Omega1 [o][v], Omega2 [o][o][v][v]) and E_CC - E_ref of given amplitudes.
@@ -346,6 +397,21 @@ class PnoEom:
                 self._check(st)
             out["npno"], out["nosv"] = npno, nosv
         return out
+
+    def set_ring_mode(self, mode=0):
+        """R1-driven ring terms for the next build_df: 0 auto, 1 through (ij|ab)', 2 through the
+        T-only intermediates."""
+        self._check(self.lib.pnoeom_set_ring_mode(self.h, int(mode)))
+
+    def set_bf16_passes(self, passes=3):
+        """bfloat16 ring products of BF16 contractions for the next build_df: 1 or 3 passes."""
+        self._check(self.lib.pnoeom_set_bf16_passes(self.h, int(passes)))
+
+    def ring_mode_used(self):
+        st = self.lib.pnoeom_ring_mode_used(self.h)
+        if st < 0:
+            self._check(st)
+        return st
 
     def set_ladder_mode(self, mode=LADDER_AUTO, max_slab=0):
         """Cached or streamed W+/- for the next build_df (LADDER_AUTO / _CACHED / _STREAMED)."""

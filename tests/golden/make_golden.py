@@ -121,11 +121,48 @@ def sec_c2_sigma():
     return out
 
 
+def sec_c4_sigma():
+    """sigma of one seeded trial vector at the config-4 size (o=40, v=400, naux=1200), from the
+    sampled-output oracle: seeded entries of the sigma2 blocks of a few pairs (diagonal,
+    off-diagonal, first and last occupied) and of sigma1 at a few virtual orbitals."""
+    from synthgen import random_r
+    from oracle.sigma_pairs import PairSigmaOracle
+    from oracle.ladder import ladder_entries
+    s = config_system(4)
+    o, v = s.o, s.v
+    out = dict(config="4", o=o, v=v, naux=s.naux, seed=s.seed)
+    seed_r = 2026
+    r1, r2 = random_r(o, v, seed_r, nvec=1)
+    pairs = [(0, 1), (5, 5), (17, 39), (39, 39)]
+    cols = [0, 133, 399]
+    t0 = time.time()
+    po = PairSigmaOracle(s.eps, s.B, o, s.t1)
+    s1, s2 = po.sigma(r1[0], r2[0], pairs, cols)
+    out["sigma_seconds"] = time.time() - t0
+    rng = np.random.default_rng(78)
+    ent = []
+    for (i, j) in pairs:
+        ab = rng.choice(v * v, size=600, replace=False)
+        for e in ab:
+            a, b = divmod(int(e), v)
+            ent.append([i, j, a, b, float(s2[(i, j)][a, b])])
+    out.update(seed_r=seed_r, pairs=pairs, cols=cols, sigma1_cols=s1.tolist(), entries2=ent,
+               block_max=[float(np.max(np.abs(s2[p]))) for p in pairs],
+               block_norm=[float(np.linalg.norm(s2[p])) for p in pairs])
+    # bfloat16 rounding scale of the ladder at the same entries (sum |B~||R||B~|, both c-d orders)
+    t0 = time.time()
+    X = r2[0].reshape(o * o, v, v)
+    samples = [(i * o + j, a, b) for i, j, a, b, _ in ent]
+    out["ladder_abs"] = ladder_entries(s.B, o, s.t1, X, samples, absolute=True).tolist()
+    out["ladder_abs_seconds"] = time.time() - t0
+    return out
+
+
 if __name__ == "__main__":
     for name in sys.argv[1:]:
         t0 = time.time()
         res = globals()["sec_" + name]()
         res["wall_seconds"] = time.time() - t0
-        with open(os.path.join(HERE, name + ".json"), "w") as fh:
+        with open(os.path.join(os.environ.get("GOLDEN_OUT", HERE), name + ".json"), "w") as fh:
             json.dump(res, fh, indent=1)
         print(name, "done in", round(time.time() - t0, 1), "s", flush=True)

@@ -24,10 +24,11 @@ def _torch():
     return torch
 
 
-def _ctx(s, precision=0, t2=None):
+def _ctx(s, precision=0, t2=None, ring_mode=0):
     torch = _torch()
     from paper_1802_06738_amd import PnoEom
     ctx = PnoEom(s.o, s.v, s.naux)
+    ctx.set_ring_mode(ring_mode)
     B = torch.from_numpy(s.B).cuda()
     eps = torch.from_numpy(s.eps).cuda()
     t1 = torch.from_numpy(s.t1).cuda()
@@ -56,6 +57,30 @@ def test_sigma_fp64_matches_oracle(o, v, naux, t1s, seed):
         a1, a2 = so.sigma(r1[k], r2[k])
         assert np.max(np.abs(g1[k] - a1)) <= 1e-12 * np.max(np.abs(a1))
         assert np.max(np.abs(g2[k] - a2)) <= 1e-12 * np.max(np.abs(a2))
+
+
+@pytest.mark.parametrize("ring_mode", [1, 2])
+@pytest.mark.parametrize("o,v,naux,t1s,seed", [CASES[1], CASES[3], CASES_O_GT_V[1]])
+def test_sigma_ring_modes_match_oracle(o, v, naux, t1s, seed, ring_mode):
+    """The R1-driven ring terms through (ij|ab)' (mode 1) or through the T-only intermediates
+    Y, Z (mode 2), FP64 and FP32 contractions."""
+    print(f"[sigma ring mode {ring_mode}] o={o} v={v} naux={naux} seed={seed}", flush=True)
+    torch = _torch()
+    from oracle.sigma import SigmaOracle
+    s = make_system(o, v, naux, seed, t1_sigma=t1s)
+    so = SigmaOracle(s.eps, s.B, o, s.t1)
+    r1, r2 = random_r(o, v, seed + 60, nvec=3)
+    R1, R2 = torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda()
+    for prec, tol in ((0, 1e-12), (1, 2e-5)):
+        ctx = _ctx(s, precision=prec, ring_mode=ring_mode)
+        assert ctx.ring_mode_used() == ring_mode
+        g1, g2 = ctx.sigma(R1, R2, precision=prec)
+        g1, g2 = g1.cpu().numpy(), g2.cpu().numpy()
+        for k in range(3):
+            a1, a2 = so.sigma(r1[k], r2[k])
+            assert np.max(np.abs(g1[k] - a1)) <= tol * np.max(np.abs(a1))
+            assert np.max(np.abs(g2[k] - a2)) <= tol * np.max(np.abs(a2))
+        ctx.close()
 
 
 @pytest.mark.parametrize("o,v,naux,t1s,seed", CASES[:3] + CASES_O_GT_V)
@@ -98,14 +123,15 @@ def _ladder_bf16_bound(so, r2):
 
 @pytest.mark.parametrize("o,v,naux,t1s,seed", CASES[:2])
 def test_sigma_bf16_ladder_within_rounding_bound(o, v, naux, t1s, seed):
-    """BF16 mode: ladder on bfloat16 operands with FP32 accumulation, everything else
-    FP32.  Each sigma2 element must lie within the ladder's rounding bound plus the
-    FP32 tolerance; sigma1 (no ladder) within the FP32 tolerance."""
+    """BF16 mode with the ring products on FP32 MFMA (ring mode 1): ladder on bfloat16
+    operands with FP32 accumulation, everything else FP32.  Each sigma2 element must lie
+    within the ladder's rounding bound plus the FP32 tolerance; sigma1 (no ladder) within
+    the FP32 tolerance."""
     print(f"[sigma bf16] o={o} v={v} naux={naux} seed={seed}", flush=True)
     torch = _torch()
     from oracle.sigma import SigmaOracle
     s = make_system(o, v, naux, seed, t1_sigma=t1s)
-    ctx = _ctx(s, precision=2)
+    ctx = _ctx(s, precision=2, ring_mode=1)
     r1, r2 = random_r(o, v, seed + 50)
     g1, g2 = ctx.sigma(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda(), precision=2)
     so = SigmaOracle(s.eps, s.B, o, s.t1)
@@ -116,6 +142,50 @@ def test_sigma_bf16_ladder_within_rounding_bound(o, v, naux, t1s, seed):
     bound = _ladder_bf16_bound(so, r2[0]) + 2e-5 * np.max(np.abs(a2))
     assert np.all(err2 <= bound)
     assert np.max(err2) > 1e-6 * np.max(np.abs(a2))  # the bfloat16 path was taken
+
+
+@pytest.mark.parametrize("o,v,naux,t1s,seed", CASES[:3])
+def test_sigma_bf16_ring_passes(o, v, naux, t1s, seed):
+    """BF16 mode with the T-only ring intermediates: the ring products R^s [Dr | Xr] and
+    R_ia DX2 on bfloat16 MFMA too.  Three passes (operands split x = hi + lo, products
+    hi hi + hi lo + lo hi) leave a relative error of about 2^-16 per product term against
+    2^-8 for one pass.  Against the oracle, sigma2 must stay within the ladder's rounding
+    bound plus 1e-4 (three passes) or 1e-2 (one pass) of max|sigma2|.  The ring's own part of
+    the error is the difference from the same BF16 build with the ring on FP32 MFMA (ring
+    mode 1, same bfloat16 ladder): nonzero, and smaller with three passes than with one."""
+    torch = _torch()
+    from oracle.sigma import SigmaOracle
+    from paper_1802_06738_amd import PnoEom
+    s = make_system(o, v, naux, seed, t1_sigma=t1s)
+    r1, r2 = random_r(o, v, seed + 50)
+    R1, R2 = torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda()
+    so = SigmaOracle(s.eps, s.B, o, s.t1)
+    a1, a2 = so.sigma(r1[0], r2[0])
+    lb = _ladder_bf16_bound(so, r2[0])
+    B, eps, t1 = (torch.from_numpy(x).cuda() for x in (s.B, s.eps, s.t1))
+
+    def run(ring_mode, passes):
+        ctx = PnoEom(s.o, s.v, s.naux)
+        ctx.set_ring_mode(ring_mode)
+        ctx.set_bf16_passes(passes)
+        ctx.build_df(B, eps, t1, precision=2)
+        g1, g2 = ctx.sigma(R1, R2, precision=2)
+        ctx.close()
+        return g1.cpu().numpy()[0], g2.cpu().numpy()[0]
+
+    _, f2 = run(1, 3)
+    ring = {}
+    for passes, allow in ((3, 1e-4), (1, 1e-2)):
+        print(f"[sigma bf16 ring] passes {passes} o={o} v={v} naux={naux} seed={seed}", flush=True)
+        g1, g2 = run(2, passes)
+        err1 = np.abs(g1 - a1)
+        err2 = np.abs(g2 - a2)
+        ring[passes] = float(np.max(np.abs(g2 - f2))) / np.max(np.abs(a2))
+        print(f"[sigma bf16 ring] passes {passes}: ring part {ring[passes]:.2e}, total sigma2 error "
+              f"{np.max(err2) / np.max(np.abs(a2)):.2e} of max|sigma2|", flush=True)
+        assert np.max(err1) <= 2e-5 * np.max(np.abs(a1))
+        assert np.all(err2 <= lb + allow * np.max(np.abs(a2)))
+    assert 0.0 < ring[3] < ring[1]
 
 
 def test_gemm_variants_keep_sigma_parity():
