@@ -598,8 +598,9 @@ def headline_pno(args):
         "dtype": "bf16", "data": "synthetic",
         "config": {"workload": f"config {cfgid}: SA-PNO-EOM-CCSD sigma blocks of {nroots} trial vectors in the "
                                f"PNO space (T_cut={tcut:g}, {npno.mean():.1f} PNOs/pair), o={o}, v={v}, "
-                               f"naux={naux}; bfloat16 MFMA contractions (ladder and ring; ring split into "
-                               f"{args.bf16_passes} pass(es)) with FP32 accumulation, FP32 / FP64 others",
+                               f"naux={naux}; bfloat16 MFMA contractions with FP32 accumulation (particle and "
+                               f"hole ladders, ring products in {args.bf16_passes} pass(es), X_klij, M1, DF "
+                               f"and R1 ring terms), FP64 small terms",
                    "o": o, "v": v, "naux": naux, "nroots": nroots, "space": "pno", "tcut": tcut,
                    "step": "one sigma block: back-transform, canonical sigma, projection, PNO-space ladder"},
         "roofline": roof,
@@ -687,7 +688,7 @@ def main():
                     help="ground- vs excited-state PNO truncation errors (reduced PNO workload)")
     ap.add_argument("--ccsd", action="store_true",
                     help="CCSD ground state, then EOM-CCSD on its amplitudes (config 1-3)")
-    ap.add_argument("--bf16-passes", type=int, default=3, help="passes of the bfloat16 ring products (1 or 3)")
+    ap.add_argument("--bf16-passes", type=int, default=1, help="passes of the bfloat16 ring products (1 or 3)")
     ap.add_argument("--no-ttc", action="store_true", help="skip the Davidson time-to-convergence runs")
     ap.add_argument("--no-config2", action="store_true", help="skip the o=20, v=150 oracle comparison")
     ap.add_argument("--legacy", action="store_true",

@@ -193,8 +193,19 @@ int pnoeom_ring_mode_used(const pnoeom_ctx* ctx);
  * only with the T-only ring intermediates, else those products run on FP32 MFMA): 1 = one
  * bfloat16 product (inputs rounded to bfloat16, relative error ~2^-8), 3 = each operand
  * split as hi + lo (both bfloat16) and hi hi + hi lo + lo hi summed in FP32 by one GEMM of
- * three times the depth (relative error ~2^-16).  Default 3.  Errors: EINVAL. */
+ * three times the depth (relative error ~2^-16).  Default 1.  Errors: EINVAL. */
 int pnoeom_set_bf16_passes(pnoeom_ctx* ctx, int passes);
+
+/* Which contractions PNOEOM_BF16 puts on bfloat16 MFMA (next pnoeom_build_df); all of them
+ * accumulate in FP32, and the small / R1-one-index products stay FP64 in every scope.
+ *   scope 0: the particle ladder and (with the T-only ring intermediates) the ring products
+ *            R^s [Dr | Xr] and R_ia DX2; the other large contractions run on FP32 MFMA;
+ *   scope 1: also the hole ladder W_klij R_kl^ab, X_klij = sum_cd R_ij^cd (kc|ld) and its
+ *            product with T, M1 = U(R) B~_ov, the DF-factorised ring terms and the R1 ring
+ *            term through Yr (when their bfloat16 staging fits: o <= v, o v naux <= o^2 v^2).
+ * Default 1.  The bfloat16 rounding of both operands of a product term (relative 2^-9 each)
+ * bounds each product's error by 2^-8 sum |a||b|.  Errors: EINVAL. */
+int pnoeom_set_bf16_scope(pnoeom_ctx* ctx, int scope);
 
 /* Prepare the context for pnoeom_ladder_apply alone: the dressed virtual factors
  * B~^Q_ac = B^Q_ac - sum_k t_k^a B^Q_kc (the virtual block of the T1 similarity
@@ -414,7 +425,10 @@ int pnoeom_gemm_set_table(int n, const long long* keys, const int* variants);
  * device bfloat16 bit patterns (K contiguous; K, lda, ldb multiples of 64 with the
  * padding columns zero; 16-byte aligned), C [M][ldc] device FP32, ldc >= N.  variant:
  * 0 = chosen by shape, 1 = 128 x 128 tiles (16x16x32 MFMA), 2 = 256 x 256 tiles
- * (32x32x16 MFMA; needs M, N >= 256).  Stream-ordered on hip_stream (NULL = default).
+ * (32x32x16 MFMA, direct-to-LDS loads; needs M, N >= 256), 3 = as 2 with the k-steps
+ * rotated across the K-tile barrier, 4 / 5 = as 3 with the tiles taken M-fastest / in
+ * groups of 8 tile columns (3 chooses between M-fastest and groups of 4 by shape).
+ * Stream-ordered on hip_stream (NULL = default).
  * pnoeom_gemm_bf16_time times a variant on scratch operands of shape M x N x K that it
  * allocates (reps launches; *ms = mean milliseconds, -1 above 16 GiB of operands).
  * Errors: EINVAL (shape, padding, alignment, variant), EHIP, ENOMEM. */

@@ -253,6 +253,13 @@ int pnoeom_set_bf16_passes(pnoeom_ctx* ctx, int passes) {
   });
 }
 
+int pnoeom_set_bf16_scope(pnoeom_ctx* ctx, int scope) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(scope == 0 || scope == 1, PNOEOM_EINVAL, "set_bf16_scope: 0 or 1");
+    c.bf16_scope = scope;
+  });
+}
+
 int pnoeom_ring_mode_used(const pnoeom_ctx* ctx) {
   if (!ctx) return PNOEOM_EINVAL;
   if (!ctx->c.have_df) return PNOEOM_ESTATE;

@@ -124,12 +124,15 @@ struct GemmBf16Desc {
   float* C = nullptr;
   int64_t ldc = 0;
   int tag = 0;      // 1: the particle-particle ladder, 2: its W slab build, 3: ring products
-  int variant = 0;  // 0: by shape; 1: 128 x 128 tiles; 2: 256 x 256 tiles (M, N >= 256)
+  // 0: by shape; 1: 128 x 128 tiles; 2: 256 x 256 tiles (M, N >= 256); 3: 256 x 256, rotated
+  // k-steps (tile order by shape); 4, 5: variant 3 with the tile order M-fastest / in groups
+  // of 8 tile columns
+  int variant = 0;
 };
 void gemm_bf16(const GemmBf16Desc& d, hipStream_t s);
 // the 256 x 256-tile kernel (gemm_bf16.hip) and the shapes it takes
 bool gemm_bf16_big_fits(int64_t M, int64_t N);
-void gemm_bf16_big(const GemmBf16Desc& d, hipStream_t s);
+void gemm_bf16_big(const GemmBf16Desc& d, hipStream_t s, bool rotated, int group);
 // average ms of one launch of a variant on scratch operands of shape M x N x K (K padded to 64)
 double gemm_bf16_time(hipStream_t s, int64_t M, int64_t N, int64_t K, int variant, int reps);
 

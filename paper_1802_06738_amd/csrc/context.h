@@ -110,7 +110,10 @@ struct Context {
   // so that the products sum to hi hi + hi lo + lo hi
   DBuf<uint16_t> DXb, DX2b;
   int64_t ldr = 0;
-  int ring_passes = 3;
+  int ring_passes = 1;
+  // BF16 scope (next build_df): 0 = the ladder and the ring products on bfloat16 MFMA, the
+  // other contractions FP32; 1 = also the hole ladder, X_klij, M1 and the DF and R1 ring terms
+  int bf16_scope = 1;
   // packed ladder: W+[(a<=b),(c<=d)] = W_abcd + W_abdc, W-[(a<b),(c<d)] = W_abcd - W_abdc
   DBuf<double> Wp, Wm;          // FP64 (always: the FP64 sigma and the refinement of mixed runs)
   DBuf<float> Wpf, Wmf;         // FP32 (precision FP32)
@@ -120,6 +123,14 @@ struct Context {
   // FP32 copies of the T-only right factors of the hole-ladder and three-body products and of
   // B~_ov (precision FP32 / BF16: those products then run on FP32 MFMA)
   DBuf<float> Whf, g2f, T32, BovTf;
+  DBuf<float> BYUf, YUf;  // FP32 copies of the DF ring factors (precision FP32 / BF16)
+  // bfloat16 operands of the other large products in BF16 mode (rows padded to 64 values):
+  // Wh [(ij)][(kl)], g2 [(kl)][(cd)], T^T [(ab)][(kl)] (hole ladder and X_klij), B~_ov as
+  // [Q][(jb)] (M1), BYU^T and YU^T as [(kc)][Q] (DF ring terms, rows of ldq), and Yr with
+  // its last two indices swapped, [(a, n)][c] (R1 term of the ring)
+  DBuf<uint16_t> Whb, g2b, TTb, BovQb, BYUb, YUb, Yrb;
+  int64_t ldoo = 0, ldvv = 0, ldov = 0, ldv = 0;
+  bool bf_rest = false;
   // build-time temporaries of build_df, by slot (each slot's uses follow one another on the
   // stream); kept between builds while keep_build_tmp is set (the repeated builds of the
   // CCSD solver then allocate nothing), else released at the end of each build

@@ -513,6 +513,19 @@ DavidsonResult run_davidson(Context& c, Operator& op, int ntarget, const double*
   const int maxs = std::max(opt.max_sub, nroots + nguess);
   const int cap = maxs + nroots;
   DBuf<double> V, S, X, R, cand, dY, dc, dcb, dth;
+  {
+    // the sigma workspaces of earlier calls may hold most of the device (their chunk is sized
+    // to the free memory): drop them when the subspace would not fit beside them; the first
+    // sigma block re-sizes them against what is left
+    size_t fr = 0, tot = 0;
+    PNO_HIP(hipMemGetInfo(&fr, &tot));
+    const int64_t need = ((int64_t)(2 * cap + 2 * nroots + 1) * N + 3 * (int64_t)cap * nroots) * 8 + (1ll << 30);
+    if ((int64_t)fr < need && !c.keep_build_tmp) {
+      c.drop_graphs();  // captured sigma blocks refer to the workspaces
+      c.sw.release();
+      for (DBuf<double>* b : {&c.pno.r1, &c.pno.r2, &c.pno.s1, &c.pno.s2}) b->release();
+    }
+  }
   V.alloc((int64_t)cap * N);
   S.alloc((int64_t)cap * N);
   X.alloc((int64_t)nroots * N);

@@ -132,6 +132,27 @@ __device__ __forceinline__ uint16_t cvt_out<uint16_t>(double x) {
   return bf16_bits(x);
 }
 
+// dst[q][c][r] = bf16(src[q][r][c]) for r < R, zero for R <= r < ld (rows of ld values), c < C:
+// a transpose through 32 x 32 LDS tiles, reads along c and writes along r
+__global__ __launch_bounds__(256) void bf16_transpose_kernel(int64_t R, int64_t C, const double* __restrict__ src,
+                                                             int64_t sbatch, uint16_t* __restrict__ dst, int64_t ld,
+                                                             int64_t dbatch) {
+  __shared__ double t[32][33];
+  const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+  const double* sq = src + (int64_t)blockIdx.z * sbatch;
+  uint16_t* dq = dst + (int64_t)blockIdx.z * dbatch;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t r = r0 + yy, c = c0 + tx;
+    t[yy][tx] = (r < R && c < C) ? sq[r * C + c] : 0.0;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t c = c0 + yy, r = r0 + tx;
+    if (c < C && r < ld) dq[c * ld + r] = bf16_bits(t[tx][yy]);
+  }
+}
+
 // bfloat16 operand rows of the BF16 ring products: row m of out holds `passes` blocks of ldk
 // values; with x = src[m sm + k sk] (0 for k >= K), hi = bf16(x) and lo = bf16(x - hi), a left
 // operand (right = 0) takes [hi | hi | lo] and a right operand [hi | lo | hi], so that the
@@ -287,8 +308,9 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   c.drop_graphs();
   if (!c.keep_build_tmp) c.sw.release();  // (the CCSD iteration keeps its FP64 sigma workspaces)
   c.pno.reset();
-  if (precision == PNOEOM_FP64)
-    for (DBuf<float>* b : {&c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf}) b->release();
+  for (DBuf<float>* b : {&c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf, &c.BYUf, &c.YUf}) b->release();
+  for (DBuf<uint16_t>* b : {&c.Whb, &c.g2b, &c.TTb, &c.BovQb, &c.BYUb, &c.YUb, &c.Yrb, &c.DXb, &c.DX2b}) b->release();
+  c.bf_rest = false;
   c.ring_y = false;
   c.Yr.release();
   c.Zr.release();
@@ -460,7 +482,8 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   {
     size_t fr = 0, tot = 0;
     PNO_HIP(hipMemGetInfo(&fr, &tot));
-    const double need = 8.0 * 2.0 * (double)ov * ((double)vv + (double)oo);
+    double need = 8.0 * 2.0 * (double)ov * ((double)vv + (double)oo);
+    if (precision == PNOEOM_BF16) need += 2.0 * 2.0 * (double)ov * v * bf16_ld(v);  // + its bfloat16 copy
     c.ring_y = c.ring_mode == 2 || (c.ring_mode == 0 && need <= (double)fr / 3.0);
   }
   if (c.ring_y) {
@@ -579,12 +602,17 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     }
     PNO_HIP(hipStreamSynchronize(s));
   }
-  if (precision == PNOEOM_FP32 || precision == PNOEOM_BF16) {  // FP32 operands of the other contractions
+  // BF16: the hole ladder, X_klij, M1 and the DF ring terms run on bfloat16 MFMA when their
+  // staging in sigma fits (o <= v and o v naux <= o^2 v^2), else on FP32 like in FP32 mode
+  c.bf_rest = precision == PNOEOM_BF16 && c.bf16_scope == 1 && oo * oo <= oovv && ov * naux <= oovv;
+  if (precision == PNOEOM_FP32 || (precision == PNOEOM_BF16 && !c.ring_y)) {  // FP32 ring operands
     c.DX2f.alloc(oovv);
     const int64_t ndx = c.ring_y ? 2 * oovv : 4 * oovv;
     c.DXTTf.alloc(ndx);
     to_float(s, oovv, c.DX2, c.DX2f);
     to_float(s, ndx, c.DXTT, c.DXTTf);
+  }
+  if (precision == PNOEOM_FP32 || (precision == PNOEOM_BF16 && !c.bf_rest)) {  // FP32 operands of the rest
     c.Whf.alloc(oo * oo);
     c.g2f.alloc(oovv);
     c.T32.alloc(oovv);
@@ -593,6 +621,42 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     to_float(s, oovv, c.g2, c.g2f);
     to_float(s, oovv, c.T, c.T32);
     to_float(s, ov * naux, c.BovT, c.BovTf);
+    c.BYUf.alloc((int64_t)naux * ov);
+    c.YUf.alloc((int64_t)naux * ov);
+    to_float(s, (int64_t)naux * ov, c.BYU, c.BYUf);
+    to_float(s, (int64_t)naux * ov, c.YU, c.YUf);
+  }
+  if (c.bf_rest) {
+    c.ldoo = bf16_ld(oo);
+    c.ldvv = bf16_ld(vv);
+    c.ldov = bf16_ld(ov);
+    c.ldq = bf16_ld(naux);
+    c.ldv = bf16_ld(v);
+    c.Whb.alloc(oo * c.ldoo);
+    c.g2b.alloc(oo * c.ldvv);
+    c.TTb.alloc(vv * c.ldoo);
+    c.BovQb.alloc(naux * c.ldov);
+    c.BYUb.alloc(ov * c.ldq);
+    c.YUb.alloc(ov * c.ldq);
+    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(oo * c.ldoo)), dim3(256), 0, s, oo, oo, (const double*)c.Wh, oo,
+                       (int64_t)1, (uint16_t*)c.Whb, c.ldoo, 1, 0);
+    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(oo * c.ldvv)), dim3(256), 0, s, oo, vv, (const double*)c.g2, vv,
+                       (int64_t)1, (uint16_t*)c.g2b, c.ldvv, 1, 0);
+    auto tr = [&](int64_t R, int64_t C, const double* src, int64_t sb, uint16_t* dst, int64_t ld, int64_t db,
+                  int64_t nbat) {
+      hipLaunchKernelGGL(bf16_transpose_kernel, dim3((unsigned)((C + 31) / 32), (unsigned)((ld + 31) / 32), (unsigned)nbat),
+                         dim3(256), 0, s, R, C, src, sb, dst, ld, db);
+    };
+    tr(oo, vv, c.T, 0, c.TTb, c.ldoo, 0, 1);        // T [(kl)][(ab)] -> [(ab)][(kl)]
+    tr(ov, naux, c.BovT, 0, c.BovQb, c.ldov, 0, 1);  // B~_ov [(jb)][Q] -> [Q][(jb)]
+    tr(naux, ov, c.BYU, 0, c.BYUb, c.ldq, 0, 1);    // BYU [Q][(kc)] -> [(kc)][Q]
+    tr(naux, ov, c.YU, 0, c.YUb, c.ldq, 0, 1);
+    if (c.ring_y) {  // Yr[(a,c)][n] -> Yrb[(a,n)][c], one transpose per a
+      const int64_t ov2 = 2 * ov;
+      c.Yrb.alloc((int64_t)v * ov2 * c.ldv);
+      tr(v, ov2, c.Yr, (int64_t)v * ov2, c.Yrb, c.ldv, ov2 * c.ldv, v);
+    }
+    PNO_HIP(hipGetLastError());
   }
   c.DXb.release();
   c.DX2b.release();
@@ -630,6 +694,17 @@ int64_t bf16_ring_floats(const Context& c, int precision, int64_t nb) {
   return nb * c.ov() * c.ring_passes * c.ldr;  // two left operands of nb ov rows
 }
 
+// bfloat16 values of fa staging that the other BF16 products of sigma_rest take for nb vectors
+// (0 when they run in another precision): R2^T rows (hole ladder), then R2 rows (X_klij), then
+// Xh rows; U(R)_ia rows (M1); B'_vo, M1 and R1 rows (DF and R1 ring terms)
+int64_t bf16_rest_values(const Context& c, int precision, int64_t nb) {
+  if (precision != PNOEOM_BF16 || !c.bf_rest) return 0;
+  const int64_t oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, ov = c.ov();
+  const int64_t hole = std::max({vv * c.ldoo, oo * c.ldvv, oo * c.ldoo});
+  const int64_t df = 2 * ov * c.ldq + (c.Yrb.p ? (int64_t)c.o * c.ldv : 0);
+  return nb * std::max({hole, ov * c.ldov, df});
+}
+
 // device memory of the per-vector work arrays of sigma_rest (bytes per vector)
 int64_t rest_bytes_per_vector(const Context& c, bool f32) {
   const int64_t ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, oovv = c.oovv();
@@ -638,8 +713,9 @@ int64_t rest_bytes_per_vector(const Context& c, bool f32) {
   int64_t nd = narr * oovv + (ov + oo + vv) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv + oo + vv + oo +
                (c.ring_y ? ov : 0);
   int64_t bytes = nd * (int64_t)sizeof(double);
-  if (f32)  // fa and fc (two oovv each; fa larger when it stages the BF16 ring operands)
-    bytes += (2 * oovv + std::max<int64_t>(2 * oovv, bf16_ring_floats(c, PNOEOM_BF16, 1) + 1)) *
+  if (f32)  // fa and fc (two oovv each; fa larger when it stages the BF16 operands)
+    bytes += (2 * oovv + std::max({2 * oovv, bf16_ring_floats(c, PNOEOM_BF16, 1) + 1,
+                                   bf16_rest_values(c, PNOEOM_BF16, 1) / 2 + 1})) *
              (int64_t)sizeof(float);
   return bytes;
 }
@@ -685,7 +761,7 @@ int sigma_chunk(Context& c, int nvec, int precision, bool pno) {
   const int64_t per = sigma_bytes_per_vector(c, precision, pno);
   size_t freeb = 0, totalb = 0;
   PNO_HIP(hipMemGetInfo(&freeb, &totalb));
-  const int64_t headroom = std::max<int64_t>(2ll << 30, (int64_t)totalb / 10);
+  const int64_t headroom = std::max<int64_t>(2ll << 30, (int64_t)totalb * 3 / 100);
   const int64_t avail = (int64_t)freeb + sigma_held_bytes(c) - headroom;
   const int64_t nb = avail > 0 ? avail / per : 0;
   c.last_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nb, nvec));
@@ -715,7 +791,8 @@ void alloc_sigma_work(Context& c, int precision, int nb) {
   grow(w.Xh, B * oo * oo); grow(w.O4p, B * oo * oo); grow(w.M1, B * ov * c.naux);
   grow(w.Ftv, B * vv); grow(w.Fto, B * oo);
   if (precision != PNOEOM_FP64) {
-    grow(w.fa, std::max<int64_t>(2 * B * oovv, bf16_ring_floats(c, precision, nb)));
+    grow(w.fa, std::max({2 * B * oovv, bf16_ring_floats(c, precision, nb),
+                         (bf16_rest_values(c, precision, nb) + 1) / 2}));
     grow(w.fc, 2 * B * oovv);
   }
 }
@@ -867,8 +944,32 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   // per-vector left operands staged in FP32 in fa; the staging holds 2 nb o^2 v^2 floats in
   // each of fa and fc: M1 stages nb o v naux floats in fc, R2 and Xh take nb (o^2 v^2 + o^4)
   // in fa and Xh's product nb o^4 in fc, so o <= v is needed besides o v naux <= 2 o^2 v^2)
-  const bool f32x = f32 && ovn <= 2 * oovv && o4 <= oovv;
-  if (f32x) {
+  // (BF16 with the bfloat16 operands built: these products and those of the hole ladder,
+  // X_klij and the DF and R1 ring terms run on bfloat16 MFMA with FP32 accumulation, the
+  // per-vector operands converted into bfloat16 rows staged in fa, the FP32 results in fc)
+  const bool bfr = precision == PNOEOM_BF16 && c.bf_rest;
+  const bool f32x = !bfr && f32 && ovn <= 2 * oovv && o4 <= oovv;
+  uint16_t* hb = reinterpret_cast<uint16_t*>((float*)w.fa);
+  // rows m < M of K values, src[m sm + k], as bfloat16 rows of ld values (zero beyond K)
+  auto rows_bf16 = [&](int64_t Mr, int64_t Kr, const double* src, int64_t sm, uint16_t* out, int64_t ld) {
+    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(Mr * ld)), dim3(256), 0, s, Mr, Kr, src, sm, (int64_t)1, out,
+                       ld, 1, 0);
+    PNO_HIP(hipGetLastError());
+  };
+  // C = alpha A B^T + beta C with A [Mg][ld], B [Ng][ld] bfloat16 rows, C FP32 rows of ldc
+  auto bgemm = [&](int64_t Mg, int64_t Ng, int64_t ld, float alpha, const uint16_t* A, const uint16_t* Bm,
+                   float beta, float* C, int64_t ldc) {
+    GemmBf16Desc d;
+    d.M = Mg; d.N = Ng; d.K = ld; d.alpha = alpha; d.beta = beta; d.A = A; d.lda = ld; d.B = Bm; d.ldb = ld;
+    d.C = C; d.ldc = ldc;
+    gemm_bf16(d, s);
+  };
+  if (bfr) {
+    // M1[(q,i,a)][Q] = sum_(jb) U(R)_ia[(q,i,a)][(jb)] B~_ov[(jb)][Q], all vectors in one product
+    rows_bf16(nb * ov, ov, w.UiaR, ov, hb, c.ldov);
+    bgemm(nb * ov, naux, c.ldov, 1.f, hb, c.BovQb, 0.f, w.fc, naux);
+    to_double(s, nb * ovn, w.fc, w.M1, 0.0);
+  } else if (f32x) {
     to_float(s, nb * oovv, w.UiaR, w.fa);
     gmbf(s, false, false, ov, naux, ov, 1.0, w.fa, ov, oovv, c.BovTf, naux, 0, 0.0, w.M1, nb, w.fc);
   } else {
@@ -881,7 +982,18 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   // ---------------------------------------------------------------- sigma2, direct (not P-symmetrised)
   float* R2f = w.fa;             // FP32 staging of R2, then of Xh after it
   float* Xhf = w.fa + nb * oovv;
-  if (f32x) {
+  if (bfr) {
+    // hole ladder Sd[q] += Wh R2[q] (R2[q]^T as bfloat16 rows [(ab)][(kl)]), FP32 into fc[q]
+    hipLaunchKernelGGL(bf16_transpose_kernel, dim3((unsigned)((vv + 31) / 32), (unsigned)((c.ldoo + 31) / 32), (unsigned)nb),
+                       dim3(256), 0, s, oo, vv, R2, oovv, hb, c.ldoo, vv * c.ldoo);
+    PNO_HIP(hipGetLastError());
+    for (int q = 0; q < nb; ++q)
+      bgemm(oo, vv, c.ldoo, 1.f, c.Whb, hb + q * vv * c.ldoo, 0.f, w.fc + q * oovv, vv);
+    // Xh[(q,i,j)][(kl)] = sum_(ab) R2[(q,i,j)][(ab)] g2[(kl)][(ab)], into fc after the ladder block
+    rows_bf16(nb * oo, vv, R2, vv, hb, c.ldvv);
+    bgemm(nb * oo, oo, c.ldvv, 1.f, hb, c.g2b, 0.f, w.fc + nb * oovv, oo);
+    to_double(s, nb * o4, w.fc + nb * oovv, w.Xh, 0.0);
+  } else if (f32x) {
     to_float(s, nb * oovv, R2, R2f);
     gmbf(s, false, false, oo, vv, oo, 1.0, c.Whf, oo, 0, R2f, vv, oovv, 1.0, Sd, nb, w.fc);
     gmbf(s, false, true, oo, oo, vv, 1.0, R2f, vv, oovv, c.g2f, vv, 0, 0.0, w.Xh, nb, w.fc);
@@ -896,7 +1008,12 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     const int pp[4] = {1, 3, 0, 2};
     permute_c(s, dims, pp, 1.0, w.O4p, 1.0, w.Xh, nb);
   }
-  if (f32x) {
+  if (bfr) {
+    // Sd[q] += Xh[q] T, all vectors in one product onto the ladder block in fc
+    rows_bf16(nb * oo, oo, w.Xh, oo, hb, c.ldoo);
+    bgemm(nb * oo, vv, c.ldoo, 1.f, hb, c.TTb, 1.f, w.fc, vv);
+    to_double(s, nb * oovv, w.fc, Sd, 1.0);
+  } else if (f32x) {
     to_float(s, nb * o4, w.Xh, Xhf);
     gmbf(s, false, false, oo, vv, oo, 1.0, Xhf, oo, o4, c.T32, vv, 0, 1.0, Sd, nb, w.fc);
   } else {
@@ -968,7 +1085,6 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     to_float(s, nt, w.Ria, fa);
     d.N = ov; d.K = ov; d.alpha = 1.f; d.beta = 1.f; d.A = fa; d.lda = ov; d.B = c.DX2f; d.ldb = ov;
     gemm(d, s);
-    to_double(s, 2 * nt, fc, w.ZZ, 0.0);
   } else {
     GemmDesc<double> d;
     d.M = M; d.N = ov2; d.K = K1; d.alpha = -1.0; d.beta = 0.0; d.lda = ldre; d.ldb = ov2; d.C = w.ZZ; d.ldc = ov2;
@@ -981,28 +1097,71 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   c.region_end(ring_ev, 3, s, 2, 2.0 * (double)M * ov2 * K1 + 2.0 * (double)M * ov * ov,
                8.0 * ((double)M * K1 + (double)K1 * ov2 + 5.0 * M * ov + (double)oovv));
   // ==== ring product launches: end
-  if (bf_ring) to_double(s, 2 * (int64_t)nb * oovv, w.fc, w.ZZ, 0.0);
+  // the DF-factorised parts of the ring terms, into the Ziajb half: (B'_vo BYU + 1/2 M1 YU), in
+  // FP32 on top of the FP32 ring result when the contractions are FP32 / BF16 (then one
+  // conversion of the whole ring block to FP64), else in FP64 below
+  const bool df32 = f32 && c.BYUf.p && 2 * ovn <= (int64_t)w.fa.n / std::max(nb, 1);
+  const bool ybf = bfr && c.ring_y && c.Yrb.p;  // R1 ring term through Yr on bfloat16 MFMA
+  if (ybf) {
+    // R1c: the block's R1 compacted as [(q,j)][c]
+    Perm4 p;
+    p.d[0] = nb; p.d[1] = 1; p.d[2] = 1; p.d[3] = ov;
+    p.is[0] = stride1; p.is[1] = 0; p.is[2] = 0; p.is[3] = 1;
+    p.os[0] = ov; p.os[1] = 0; p.os[2] = 0; p.os[3] = 1;
+    permute4(s, p, 1.0, r1, 0.0, w.R1c);
+  }
+  if (bfr) {
+    // B'_vo BYU + 1/2 M1 YU on top of the FP32 ring block (rows (q,i,a) of 2 ov in fc)
+    uint16_t* bv = hb;
+    uint16_t* bm = hb + nb * ov * c.ldq;
+    rows_bf16(nb * ov, naux, w.BvopT, naux, bv, c.ldq);
+    rows_bf16(nb * ov, naux, w.M1, naux, bm, c.ldq);
+    bgemm(nb * ov, ov, c.ldq, 1.f, bv, c.BYUb, 1.f, w.fc, ov2);
+    bgemm(nb * ov, ov, c.ldq, 0.5f, bm, c.YUb, 1.f, w.fc, ov2);
+    if (ybf) {
+      // -sum_c R1[q][j][c] Yr[(a,c)][n] for all (q,j) x (a,n) at once: the rows (q,j,a) of the
+      // ring block are the rows (q,j) of a [nb o][v 2 ov] matrix
+      uint16_t* br = bm + nb * ov * c.ldq;
+      rows_bf16(nb * o, v, w.R1c, v, br, c.ldv);
+      bgemm(nb * o, v * ov2, c.ldv, -1.f, br, c.Yrb, 1.f, w.fc, v * ov2);
+    }
+    to_double(s, 2 * (int64_t)nb * oovv, w.fc, w.ZZ, 0.0);
+  } else if (f32) {
+    if (df32) {
+      float* fa = w.fa;
+      to_float(s, nb * ovn, w.BvopT, fa);
+      to_float(s, nb * ovn, w.M1, fa + nb * ovn);
+      GemmDesc<float> d;
+      d.M = ov; d.N = ov; d.K = naux; d.alpha = 1.f; d.beta = 1.f; d.A = fa; d.lda = naux; d.sA = ovn;
+      d.B = c.BYUf; d.ldb = ov; d.sB = 0; d.C = w.fc; d.ldc = ov2; d.sC = 2 * oovv; d.batch = nb;
+      gemm(d, s);
+      d.alpha = 0.5f; d.A = fa + nb * ovn; d.B = c.YUf;
+      gemm(d, s);
+    }
+    to_double(s, 2 * (int64_t)nb * oovv, w.fc, w.ZZ, 0.0);
+  }
+  if (!df32 && !bfr) {
+    gmb(s, false, false, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.BYU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
+    gmb(s, false, false, ov, ov, naux, 0.5, w.M1, naux, ovn, c.YU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
+  }
   if (c.ring_y) {
     // E_X [T_ia | T^s_ia] = sum_c r_j^c Yr[(a,c)] - sum_l r_l^a Zr[(j,l)], with the sign of the
     // fused product: ZZ[(q,j,a)] -= sum_c R1[q][j][c] Yr[(a,c)], += sum_l R1[q][l][a] Zr[(j,l)]
-    {
+    if (!ybf) {
       Perm4 p;  // R1 of the block compacted to [(q,j)][c]
       p.d[0] = nb; p.d[1] = 1; p.d[2] = 1; p.d[3] = ov;
       p.is[0] = stride1; p.is[1] = 0; p.is[2] = 0; p.is[3] = 1;
       p.os[0] = ov; p.os[1] = 0; p.os[2] = 0; p.os[3] = 1;
       permute4(s, p, 1.0, r1, 0.0, w.R1c);
+      // one product per a over all vectors: [(q,j)] x [c] times Yr[(a,c)] into rows (q,j,a)
+      gmb(s, false, false, (int64_t)nb * o, ov2, v, -1.0, w.R1c, v, 0, c.Yr, ov2, v * ov2, 1.0, w.ZZ, v * ov2,
+          ov2, v);
     }
-    // one product per a over all vectors: [(q,j)] x [c] times Yr[(a,c)] into rows (q,j,a)
-    gmb(s, false, false, (int64_t)nb * o, ov2, v, -1.0, w.R1c, v, 0, c.Yr, ov2, v * ov2, 1.0, w.ZZ, v * ov2,
-        ov2, v);
     // per vector, one product per j: R1[q]^T (v x o) times Zr[(j,l)] (o x 2 ov) into rows (q,j,a)
     for (int q = 0; q < nb; ++q)
       gmb(s, true, false, v, ov2, o, 1.0, w.R1c + q * ov, v, 0, c.Zr, ov2, (int64_t)o * ov2, 1.0,
           w.ZZ + (int64_t)q * ov * ov2, ov2, v * ov2, o);
   }
-  // the DF-factorised parts of the ring terms, into the Ziajb half
-  gmb(s, false, false, ov, ov, naux, 1.0, w.BvopT, naux, ovn, c.BYU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
-  gmb(s, false, false, ov, ov, naux, 0.5, w.M1, naux, ovn, c.YU, ov, 0, 1.0, w.ZZ, ov2, 2 * oovv, nb);
 
   // ---------------------------------------------------------------- Fock-type terms in [i][j][a][b]
   gm(s, false, true, (int64_t)nb * oo * v, v, v, 1.0, R2, v, c.Fvv, v, 0.0, w.Zp, v);

@@ -27,6 +27,7 @@ EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pno
                     "pnoeom_gemm_bf16", "pnoeom_gemm_bf16_time",
                     "pnoeom_set_graph_mode", "pnoeom_graph_stats", "pnoeom_set_ladder_mode",
                     "pnoeom_set_ring_mode", "pnoeom_ring_mode_used", "pnoeom_set_bf16_passes",
+                    "pnoeom_set_bf16_scope",
                     "pnoeom_davidson_phase",
                     "pnoeom_build_ladder", "pnoeom_ladder_apply", "pnoeom_ladder_apply_noalloc",
                     "pnoeom_ladder_noalloc_limit", "pnoeom_set_pno_ladder",
@@ -105,6 +106,7 @@ def load_library():
     lib.pnoeom_set_ring_mode.argtypes = [vp, C.c_int]
     lib.pnoeom_ring_mode_used.argtypes = [vp]
     lib.pnoeom_set_bf16_passes.argtypes = [vp, C.c_int]
+    lib.pnoeom_set_bf16_scope.argtypes = [vp, C.c_int]
     lib.pnoeom_davidson_phase.argtypes = [vp, C.c_int, C.c_int, dp, dp, ip, ip, dp]
     lib.pnoeom_build_ladder.argtypes = [vp, vp, vp, C.c_int]
     lib.pnoeom_ladder_apply.argtypes = [vp, C.c_int, vp, vp, C.c_int]
@@ -403,9 +405,14 @@ class PnoEom:
         T-only intermediates."""
         self._check(self.lib.pnoeom_set_ring_mode(self.h, int(mode)))
 
-    def set_bf16_passes(self, passes=3):
+    def set_bf16_passes(self, passes=1):
         """bfloat16 ring products of BF16 contractions for the next build_df: 1 or 3 passes."""
         self._check(self.lib.pnoeom_set_bf16_passes(self.h, int(passes)))
+
+    def set_bf16_scope(self, scope=1):
+        """Contractions of BF16 mode on bfloat16 MFMA for the next build_df: 0 the ladder and the
+        ring products, 1 also the hole ladder, X_klij, M1, the DF and R1 ring terms."""
+        self._check(self.lib.pnoeom_set_bf16_scope(self.h, int(scope)))
 
     def ring_mode_used(self):
         st = self.lib.pnoeom_ring_mode_used(self.h)

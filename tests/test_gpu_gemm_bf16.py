@@ -10,7 +10,8 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(256, 256, 64), (300, 520, 192), (513, 777, 320), (1030, 260, 640), (40, 700, 128)]
+SHAPES = [(256, 256, 64), (300, 520, 192), (513, 777, 320), (1030, 260, 640), (40, 700, 128),
+          (1300, 3400, 64)]   # 6 x 14 tiles of 256: XCD chunks and a ragged last tile-column group
 
 
 def _torch():
@@ -20,7 +21,7 @@ def _torch():
 
 
 @pytest.mark.parametrize("M,N,K", SHAPES)
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 def test_gemm_bf16_matches_exact_product(M, N, K, variant):
     print(f"[gemm bf16] variant {variant} M={M} N={N} K={K}", flush=True)
     torch = _torch()
@@ -30,9 +31,9 @@ def test_gemm_bf16_matches_exact_product(M, N, K, variant):
     B = torch.randn((N, K), generator=g).to(torch.bfloat16)
     C0 = torch.randn((M, N), generator=g, dtype=torch.float32)
     Ad, Bd = A.cuda(), B.cuda()
-    if variant == 2 and (M < 256 or N < 256):
+    if variant >= 2 and (M < 256 or N < 256):
         with pytest.raises(PnoEomError):
-            gemm_bf16(Ad, Bd, torch.zeros((M, N), dtype=torch.float32, device="cuda"), variant=2)
+            gemm_bf16(Ad, Bd, torch.zeros((M, N), dtype=torch.float32, device="cuda"), variant=variant)
         return
     a = A.double().numpy()
     b = B.double().numpy()

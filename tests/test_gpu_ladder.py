@@ -137,6 +137,7 @@ def test_sigma_with_streamed_ladder_matches_oracle(o, v, naux, t1s, seed):
     s = make_system(o, v, naux, seed, t1_sigma=t1s)
     ctx = PnoEom(o, v, naux)
     ctx.set_ladder_mode(LADDER_STREAMED, 3)
+    ctx.set_bf16_scope(0)   # BF16: the ladder (and ring) on bfloat16, the rest FP32
     ctx.build_df(torch.from_numpy(s.B).cuda(), torch.from_numpy(s.eps).cuda(), torch.from_numpy(s.t1).cuda(),
                  precision=2)
     r1, r2 = random_r(o, v, seed + 50, nvec=2)
