@@ -570,11 +570,13 @@ def headline_pno(args):
                         "frac": tf / PEAK[peak[1]], "algorithmic_flops_per_launch": fl / n})
         return out
 
-    ring_txt = (f"ring products R^s [Dr | Xr] and R_ia DX2 of all vectors of a block on bfloat16 MFMA "
-                f"(gemm_bf16 tag 3, {args.bf16_passes} pass(es): algorithmic flops counted once)")
+    ring_txt = (f"ring products of all vectors of a chunk on bfloat16 MFMA (gemm_bf16 tag 3, "
+                f"{args.bf16_passes} pass(es), algorithmic flops counted once): one pass fuses the left "
+                f"half [-R^s | R_ia | B'_vo | M1/2] [Dr ; DX2 ; BYU ; YU] (K = 2 ov + 2 naux) and the "
+                f"right half -R^s Xr (K = ov)")
     fams = {
         "ring": family(regs, "ring", ("mfma", "bf16"), ring_txt,
-                       "one bfloat16 GEMM launch (M = vectors x ov, N = 2 ov or ov, K = ov)"),
+                       "one bfloat16 GEMM launch (M = vectors x ov, N = ov)"),
         "ladder": family(regs, "ladder_bf16", ("mfma", "bf16"),
                          "particle ladder of the pairs kept canonical, +/- packed (gemm_bf16 tag 1)",
                          "one bfloat16 GEMM launch (+ or - half)"),

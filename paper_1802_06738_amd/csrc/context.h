@@ -9,10 +9,10 @@ namespace pnoeom {
 struct SigmaWork {
   DBuf<double> Bp, hp, Jp, Kp, fp, dp, fp_ov, fp_vv, fp_oo;
   DBuf<double> BvopT, BoopT, BvvpT;
-  DBuf<double> R2c, Ria, UiaR, UR, URp, Ubr;
+  DBuf<double> R2c, Ria, UiaR, UR;  // (R2c: R2 compacted, only for strided input)
   // ZZ[(q,i,a)][Ziajb row | Z3 row]; RE[(q,i,a)][R^s row | E_X row] (the stacked left operand
   // of the fused ring product; R^s rows only when the E_X products go through Yr / Zr)
-  DBuf<double> ZZ, RE, Zp, Cba, Xh, O4p, OOVVp, M1;
+  DBuf<double> ZZ, RE, Zp, Xh, O4p, OOVVp, M1;
   DBuf<double> R1c;  // the block's R1 compacted as [(q,j)][c] (ring terms through Yr / Zr)
   DBuf<double> Ftv, Fto;
   DBuf<double> LadAll, Sp, Am, SigP, SigM;  // batched packed ladder
@@ -22,7 +22,7 @@ struct SigmaWork {
   DBuf<float> fa, fc;
   void release() {
     for (DBuf<double>* b : {&Bp, &hp, &Jp, &Kp, &fp, &dp, &fp_ov, &fp_vv, &fp_oo, &BvopT, &BoopT, &BvvpT, &R2c, &Ria,
-                            &UiaR, &UR, &URp, &Ubr, &ZZ, &RE, &Zp, &Cba, &Xh, &O4p,
+                            &UiaR, &UR, &ZZ, &RE, &Zp, &Xh, &O4p,
                             &OOVVp, &M1, &R1c, &Ftv, &Fto, &LadAll, &Sp, &Am, &SigP, &SigM})
       b->release();
     for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fc}) b->release();
@@ -110,6 +110,10 @@ struct Context {
   // so that the products sum to hi hi + hi lo + lo hi
   DBuf<uint16_t> DXb, DX2b;
   int64_t ldr = 0;
+  // BF16 scope 1, one pass: right operand of the ring product fused with the DF ring terms,
+  // row n = [Dr^T | DX2^T | BYU^T | YU^T] of kfold = 2 ldr + 2 ldq bfloat16 values
+  DBuf<uint16_t> RBb;
+  int64_t kfold = 0;
   int ring_passes = 1;
   // BF16 scope (next build_df): 0 = the ladder and the ring products on bfloat16 MFMA, the
   // other contractions FP32; 1 = also the hole ladder, X_klij, M1 and the DF and R1 ring terms
@@ -124,6 +128,7 @@ struct Context {
   // B~_ov (precision FP32 / BF16: those products then run on FP32 MFMA)
   DBuf<float> Whf, g2f, T32, BovTf;
   DBuf<float> BYUf, YUf;  // FP32 copies of the DF ring factors (precision FP32 / BF16)
+  DBuf<float> Fvvf, Zrf;  // BF16 scope 1: FP32 copies of Fvv and Zr (Fock-type and Zr ring terms)
   // bfloat16 operands of the other large products in BF16 mode (rows padded to 64 values):
   // Wh [(ij)][(kl)], g2 [(kl)][(cd)], T^T [(ab)][(kl)] (hole ladder and X_klij), B~_ov as
   // [Q][(jb)] (M1), BYU^T and YU^T as [(kc)][Q] (DF ring terms, rows of ldq), and Yr with

@@ -371,7 +371,8 @@ void build_ladder(Context& c, const double* B, const double* t1, int precision, 
                           &c.U, &c.Tia, &c.Tsia, &c.UiaT, &c.OVVO, &c.OOVVx, &c.Dr, &c.Xr, &c.DX2, &c.YU, &c.BYU, &c.B,
                           &c.DXTT})
     b->release();
-  for (DBuf<float>* b : {&c.Wpf, &c.Wmf, &c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf, &c.BYUf, &c.YUf})
+  for (DBuf<float>* b : {&c.Wpf, &c.Wmf, &c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf, &c.BYUf, &c.YUf,
+                         &c.Fvvf, &c.Zrf})
     b->release();
   for (DBuf<uint16_t>* b : {&c.Whb, &c.g2b, &c.TTb, &c.BovQb, &c.BYUb, &c.YUb, &c.Yrb, &c.DXb, &c.DX2b}) b->release();
   c.bf_rest = false;

@@ -153,16 +153,18 @@ __global__ __launch_bounds__(256) void bf16_transpose_kernel(int64_t R, int64_t 
   }
 }
 
-// bfloat16 operand rows of the BF16 ring products: row m of out holds `passes` blocks of ldk
-// values; with x = src[m sm + k sk] (0 for k >= K), hi = bf16(x) and lo = bf16(x - hi), a left
-// operand (right = 0) takes [hi | hi | lo] and a right operand [hi | lo | hi], so that the
-// three passes of one product sum to hi hi + hi lo + lo hi; one pass takes hi alone
+// bfloat16 operand rows: row m of out (row stride ldo) holds `passes` blocks of ldk values;
+// with x = scale src[m sm + k sk] (0 for k >= K; scale a power of two), hi = bf16(x) and
+// lo = bf16(x - hi), a left operand (right = 0) takes [hi | hi | lo] and a right operand
+// [hi | lo | hi], so that the three passes of one product sum to hi hi + hi lo + lo hi; one
+// pass takes hi alone
 __global__ void bf16_split_kernel(int64_t M, int64_t K, const double* __restrict__ src, int64_t sm, int64_t sk,
-                                  uint16_t* __restrict__ out, int64_t ldk, int passes, int right) {
-  const int64_t total = M * ldk, row = ldk * passes;
+                                  uint16_t* __restrict__ out, int64_t ldk, int64_t ldo, int passes, int right,
+                                  double scale) {
+  const int64_t total = M * ldk, row = ldo;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t m = e / ldk, k = e % ldk;
-    const double x = k < K ? src[m * sm + k * sk] : 0.0;
+    const double x = k < K ? scale * src[m * sm + k * sk] : 0.0;
     const uint16_t hi = bf16_bits(x);
     uint16_t* o = out + m * row + k;
     o[0] = hi;
@@ -172,6 +174,22 @@ __global__ void bf16_split_kernel(int64_t M, int64_t K, const double* __restrict
       o[2 * ldk] = right ? hi : lo;
     }
   }
+}
+
+unsigned grid1(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+// host side of bf16_split_kernel (ldo: row stride of out, at least passes x ldk)
+void bf16_rows(hipStream_t s, int64_t M, int64_t K, const double* src, int64_t sm, int64_t sk, uint16_t* out,
+               int64_t ldk, int64_t ldo, int passes = 1, int right = 0, double scale = 1.0) {
+  PNO_CHECK(ldo >= passes * ldk && K <= ldk, PNOEOM_EINVAL, "bf16_rows: row layout");
+  hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(M * ldk)), dim3(256), 0, s, M, K, src, sm, sk, out, ldk, ldo,
+                     passes, right, scale);
+  PNO_HIP(hipGetLastError());
 }
 
 // W+[(a<=b),(c<=d)] = W_abcd + W_abdc (c<d), W_abcc (c=d);  W-[(a<b),(c<d)] = W_abcd - W_abdc,
@@ -254,12 +272,6 @@ __global__ void ladder_unpack_kernel(int o, int v, int nvec, const InT* __restri
   }
 }
 
-unsigned grid1(int64_t n) {
-  int64_t b = (n + 255) / 256;
-  if (b > 65536) b = 65536;
-  if (b < 1) b = 1;
-  return (unsigned)b;
-}
 
 // x~ = (1 - t)^T x (1 + t^T) for nb stacked nmo x nmo matrices; work has the same size as x
 void dress(Context& c, const double* x, double* out, double* work, int64_t nb) {
@@ -308,7 +320,8 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   c.drop_graphs();
   if (!c.keep_build_tmp) c.sw.release();  // (the CCSD iteration keeps its FP64 sigma workspaces)
   c.pno.reset();
-  for (DBuf<float>* b : {&c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf, &c.BYUf, &c.YUf}) b->release();
+  for (DBuf<float>* b : {&c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf, &c.BYUf, &c.YUf, &c.Fvvf, &c.Zrf})
+    b->release();
   for (DBuf<uint16_t>* b : {&c.Whb, &c.g2b, &c.TTb, &c.BovQb, &c.BYUb, &c.YUb, &c.Yrb, &c.DXb, &c.DX2b}) b->release();
   c.bf_rest = false;
   c.ring_y = false;
@@ -638,10 +651,8 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     c.BovQb.alloc(naux * c.ldov);
     c.BYUb.alloc(ov * c.ldq);
     c.YUb.alloc(ov * c.ldq);
-    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(oo * c.ldoo)), dim3(256), 0, s, oo, oo, (const double*)c.Wh, oo,
-                       (int64_t)1, (uint16_t*)c.Whb, c.ldoo, 1, 0);
-    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(oo * c.ldvv)), dim3(256), 0, s, oo, vv, (const double*)c.g2, vv,
-                       (int64_t)1, (uint16_t*)c.g2b, c.ldvv, 1, 0);
+    bf16_rows(s, oo, oo, c.Wh, oo, 1, c.Whb, c.ldoo, c.ldoo);
+    bf16_rows(s, oo, vv, c.g2, vv, 1, c.g2b, c.ldvv, c.ldvv);
     auto tr = [&](int64_t R, int64_t C, const double* src, int64_t sb, uint16_t* dst, int64_t ld, int64_t db,
                   int64_t nbat) {
       hipLaunchKernelGGL(bf16_transpose_kernel, dim3((unsigned)((C + 31) / 32), (unsigned)((ld + 31) / 32), (unsigned)nbat),
@@ -655,22 +666,38 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
       const int64_t ov2 = 2 * ov;
       c.Yrb.alloc((int64_t)v * ov2 * c.ldv);
       tr(v, ov2, c.Yr, (int64_t)v * ov2, c.Yrb, c.ldv, ov2 * c.ldv, v);
+      c.Zrf.alloc(oo * ov2);
+      to_float(s, oo * ov2, c.Zr, c.Zrf);
     }
+    // FP32 operands of the Fock-type products R Fvv^T and T Ftv^T
+    c.Fvvf.alloc(vv);
+    c.T32.alloc(oovv);
+    to_float(s, vv, c.Fvv, c.Fvvf);
+    to_float(s, oovv, c.T, c.T32);
     PNO_HIP(hipGetLastError());
   }
   c.DXb.release();
   c.DX2b.release();
+  c.RBb.release();
+  c.kfold = 0;
   if (precision == PNOEOM_BF16 && c.ring_y) {  // bfloat16 right operands of the ring products
     const int64_t ov2 = 2 * ov;
     c.ldr = bf16_ld(ov);
     const int64_t kr = c.ring_passes * c.ldr;
     c.DXb.alloc(ov2 * kr);
     c.DX2b.alloc(ov * kr);
-    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(ov2 * c.ldr)), dim3(256), 0, s, ov2, ov, (const double*)c.DXTT,
-                       (int64_t)1, ov2, (uint16_t*)c.DXb, c.ldr, c.ring_passes, 1);
-    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(ov * c.ldr)), dim3(256), 0, s, ov, ov, (const double*)c.DX2,
-                       (int64_t)1, ov, (uint16_t*)c.DX2b, c.ldr, c.ring_passes, 1);
-    PNO_HIP(hipGetLastError());
+    bf16_rows(s, ov2, ov, c.DXTT, 1, ov2, c.DXb, c.ldr, kr, c.ring_passes, 1);
+    bf16_rows(s, ov, ov, c.DX2, 1, ov, c.DX2b, c.ldr, kr, c.ring_passes, 1);
+    if (c.bf_rest && c.ring_passes == 1) {
+      // right operand of the fused product (see sigma_rest_block): row n = [Dr^T | DX2^T | BYU^T |
+      // YU^T] (column n of Dr, DX2, BYU and YU), rows of kfold = 2 ldr + 2 ldq values
+      c.kfold = 2 * c.ldr + 2 * c.ldq;
+      c.RBb.alloc(ov * c.kfold);
+      bf16_rows(s, ov, ov, c.DXTT, 1, ov2, c.RBb, c.ldr, c.kfold);
+      bf16_rows(s, ov, ov, c.DX2, 1, ov, c.RBb + c.ldr, c.ldr, c.kfold);
+      bf16_rows(s, ov, naux, c.BYU, 1, ov, c.RBb + 2 * c.ldr, c.ldq, c.kfold);
+      bf16_rows(s, ov, naux, c.YU, 1, ov, c.RBb + 2 * c.ldr + c.ldq, c.ldq, c.kfold);
+    }
   }
   PNO_HIP(hipStreamSynchronize(s));
   // kept only stacked (DXTT) from here on
@@ -691,6 +718,7 @@ void grow(DBuf<T>& b, int64_t n) {
 // (nb ov rows of ring_passes x ldr bfloat16 values); 0 when the ring is not run in BF16
 int64_t bf16_ring_floats(const Context& c, int precision, int64_t nb) {
   if (precision != PNOEOM_BF16 || !c.ring_y || !c.DXb.p) return 0;
+  if (c.RBb.p) return (nb * c.ov() * c.kfold + 1) / 2;  // one left operand of nb ov rows of kfold
   return nb * c.ov() * c.ring_passes * c.ldr;  // two left operands of nb ov rows
 }
 
@@ -706,10 +734,11 @@ int64_t bf16_rest_values(const Context& c, int precision, int64_t nb) {
 }
 
 // device memory of the per-vector work arrays of sigma_rest (bytes per vector)
-int64_t rest_bytes_per_vector(const Context& c, bool f32) {
+int64_t rest_bytes_per_vector(const Context& c, bool f32, bool r2c) {
   const int64_t ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, oovv = c.oovv();
-  // 13 o^2 v^2 arrays, 11 when the E_X products go through Yr / Zr (RE holds R^s only, no OOVVp)
-  const int64_t narr = c.ring_y ? 11 : 13;
+  // 9 o^2 v^2 arrays (Ria, UiaR, UR, ZZ x 2, RE x 2, Zp, OOVVp), 7 when the E_X products go
+  // through Yr / Zr (RE holds R^s only, no OOVVp), + R2c for strided input
+  const int64_t narr = (c.ring_y ? 7 : 9) + (r2c ? 1 : 0);
   int64_t nd = narr * oovv + (ov + oo + vv) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv + oo + vv + oo +
                (c.ring_y ? ov : 0);
   int64_t bytes = nd * (int64_t)sizeof(double);
@@ -729,7 +758,8 @@ int64_t sigma_bytes_per_vector(const Context& c, int precision, bool pno) {
   const int64_t npair = (int64_t)c.o * (c.o + 1) / 2, vp = (int64_t)c.v * (c.v + 1) / 2;
   const int64_t vm = std::max<int64_t>((int64_t)c.v * (c.v - 1) / 2, 1);
   const bool f32 = precision != PNOEOM_FP64;
-  int64_t b = rest_bytes_per_vector(c, f32) + c.oovv() * (int64_t)sizeof(double);  // + LadAll
+  // (the PNO path expands its vectors with the singles and doubles apart: no R2c)
+  int64_t b = rest_bytes_per_vector(c, f32, !pno) + c.oovv() * (int64_t)sizeof(double);  // + LadAll
   const int64_t in_elt = precision == PNOEOM_FP64 ? 8 : precision == PNOEOM_FP32 ? 4 : 2;
   const int64_t out_elt = precision == PNOEOM_FP64 ? 8 : 4;
   const int64_t kp = precision == PNOEOM_BF16 ? c.ldpb + c.ldmb : vp + vm;
@@ -743,8 +773,8 @@ int64_t sigma_held_bytes(const Context& c) {
   const SigmaWork& w = c.sw;
   int64_t b = 0;
   for (const DBuf<double>* x : {&w.Bp, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT,
-                                &w.BoopT, &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.ZZ,
-                                &w.RE, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.R1c, &w.Ftv, &w.Fto,
+                                &w.BoopT, &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.UR, &w.ZZ,
+                                &w.RE, &w.Zp, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.R1c, &w.Ftv, &w.Fto,
                                 &w.LadAll, &w.Sp, &w.Am, &w.SigP, &w.SigM, &c.pno.r1, &c.pno.r2, &c.pno.s1,
                                 &c.pno.s2})
     b += (int64_t)x->n * 8;
@@ -769,7 +799,7 @@ int sigma_chunk(Context& c, int nvec, int precision, bool pno) {
 }
 
 namespace {
-void alloc_sigma_work(Context& c, int precision, int nb) {
+void alloc_sigma_work(Context& c, int precision, int nb, bool need_r2c) {
   SigmaWork& w = c.sw;
   const int64_t n2 = (int64_t)c.nmo * c.nmo, ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v;
   const int64_t oovv = c.oovv(), B = nb;
@@ -779,11 +809,10 @@ void alloc_sigma_work(Context& c, int precision, int nb) {
   // per-vector arrays, [nb][...]
   grow(w.fp_ov, B * ov); grow(w.fp_vv, B * vv); grow(w.fp_oo, B * oo);
   grow(w.BvopT, B * ov * c.naux); grow(w.BoopT, B * oo * c.naux); grow(w.BvvpT, B * vv * c.naux);
-  grow(w.R2c, B * oovv);
+  if (need_r2c) grow(w.R2c, B * oovv);
   grow(w.Ria, B * oovv); grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
-  grow(w.URp, B * oovv); grow(w.Ubr, B * oovv);
   grow(w.ZZ, 2 * B * oovv); grow(w.RE, (c.ring_y ? 1 : 2) * B * oovv);
-  grow(w.Zp, B * oovv); grow(w.Cba, B * oovv);
+  grow(w.Zp, B * oovv);
   if (c.ring_y)
     grow(w.R1c, B * ov);
   else
@@ -812,10 +841,10 @@ void gmbf(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, doub
 
 namespace {
 // s2[q] = Sd[q] + Z(i,j,a,b) + Z(j,i,b,a) for nb vectors, with
-// Z(i,j,a,b) = Zp[i][j][a][b] + Ziajb[i][a][j][b] + Z3[j][a][i][b] - Cba[i][j][b][a]
+// Z(i,j,a,b) = Zp[i][j][a][b] + Ziajb[i][a][j][b] + Z3[j][a][i][b]
 // where Ziajb and Z3 of vector q are the two halves of the rows of ZZ[q] ([(i,a)][2 ov]).
-// Four of the eight reads run along a for fixed b (Cba[i][j][b][:], Zp[j][i][b][:] and the
-// (j,b) / (i,b) rows of ZZ), the other four along b: one workgroup takes a 32 x 32 (a, b)
+// Three of the six reads run along a for fixed b (Zp[j][i][b][:] and the (j,b) / (i,b) rows
+// of ZZ), the other three along b: one workgroup takes a 32 x 32 (a, b)
 // tile of one pair (i, j) of one vector, sums the a-contiguous terms into LDS with lanes
 // along a, and adds them transposed to the b-contiguous terms read and written with lanes
 // along b, so that every global access is a contiguous 256-byte row segment.
@@ -823,7 +852,6 @@ constexpr int kAsmTile = 32;
 __global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, const double* __restrict__ Sd,
                                                                 const double* __restrict__ Zp,
                                                                 const double* __restrict__ ZZ,
-                                                                const double* __restrict__ Cba,
                                                                 double* __restrict__ s2, int64_t stride2) {
   __shared__ double tile[kAsmTile][kAsmTile + 1];
   const int64_t V = v, O = o, n = O * O * V * V, ov = O * V, ov2 = 2 * ov;
@@ -833,13 +861,12 @@ __global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, co
   const int tx = threadIdx.x % kAsmTile, ty = threadIdx.x / kAsmTile;  // 32 x 8
   const double* zp = Zp + q * n;
   const double* zz = ZZ + q * 2 * n;
-  const double* cb = Cba + q * n;
   // terms contiguous along a: tile[b][a]
   for (int bb = ty; bb < kAsmTile; bb += 256 / kAsmTile) {
     const int64_t a = a0 + tx, b = b0 + bb;
     if (a < V && b < V)
       tile[bb][tx] = zp[((j * O + i) * V + b) * V + a] + zz[(j * V + b) * ov2 + i * V + a] +
-                     zz[(i * V + b) * ov2 + ov + j * V + a] - cb[((i * O + j) * V + b) * V + a];
+                     zz[(i * V + b) * ov2 + ov + j * V + a];
   }
   __syncthreads();
   // terms contiguous along b, plus the tile transposed
@@ -848,9 +875,51 @@ __global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, co
     if (a < V && b < V) {
       const int64_t e = ((i * O + j) * V + a) * V + b;
       s2[q * stride2 + e] = Sd[q * n + e] + zp[e] + zz[(i * V + a) * ov2 + j * V + b] +
-                            zz[(j * V + a) * ov2 + ov + i * V + b] - cb[((j * O + i) * V + a) * V + b] +
-                            tile[tx][aa];
+                            zz[(j * V + a) * ov2 + ov + i * V + b] + tile[tx][aa];
     }
+  }
+}
+
+// The layouts of R2 that the rest of sigma reads, in one pass over R2 (one workgroup per
+// 32 x 32 (a, b) tile of a pair (i, j) of a vector, the tile and its mirror (b, a) in LDS):
+//   Ria[(q,i,a)][(j,b)] = R_ij^ab,   UiaR[(q,i,a)][(j,b)] = UR[q][i][j][a][b] = 2 R_ij^ab - R_ij^ba,
+//   URp[q][i][j][a][b] = 2 R_ij^ba - R_ij^ab,   R^s[(q,i,b)][(j,a)] = R_ij^ab (rows of ldre in RE)
+// every store runs along a row segment of 32 consecutive values (R^s through the LDS transpose)
+__global__ __launch_bounds__(256) void r2_layouts_kernel(int o, int v, const double* __restrict__ R2,
+                                                         double* __restrict__ Ria, double* __restrict__ UiaR,
+                                                         double* __restrict__ UR, double* __restrict__ URp,
+                                                         double* __restrict__ RE, int64_t ldre) {
+  __shared__ double t[kAsmTile][kAsmTile + 1];  // t[a - a0][b - b0] = R_ij^ab
+  __shared__ double u[kAsmTile][kAsmTile + 1];  // u[b - b0][a - a0] = R_ij^ba
+  const int64_t V = v, O = o, vv = V * V, n = O * O * vv;
+  const int ntb = (v + kAsmTile - 1) / kAsmTile;
+  const int a0 = (int)(blockIdx.x / ntb) * kAsmTile, b0 = (int)(blockIdx.x % ntb) * kAsmTile;
+  const int64_t i = blockIdx.y / o, j = blockIdx.y % o, q = blockIdx.z;
+  const int64_t base = q * n + (i * O + j) * vv;
+  const double* R = R2 + base;
+  const int tx = threadIdx.x % kAsmTile, ty = threadIdx.x / kAsmTile;  // 32 x 8
+  for (int r = ty; r < kAsmTile; r += 256 / kAsmTile) {
+    const int64_t a = a0 + r, b = b0 + tx;
+    t[r][tx] = (a < V && b < V) ? R[a * V + b] : 0.0;
+    const int64_t b2 = b0 + r, a2 = a0 + tx;
+    u[r][tx] = (b2 < V && a2 < V) ? R[b2 * V + a2] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < kAsmTile; r += 256 / kAsmTile) {
+    const int64_t a = a0 + r, b = b0 + tx;
+    if (a < V && b < V) {
+      const double x = t[r][tx], y = u[tx][r];
+      const int64_t e = base + a * V + b;
+      const int64_t f = q * n + ((i * V + a) * O + j) * V + b;
+      Ria[f] = x;
+      UiaR[f] = 2.0 * x - y;
+      UR[e] = 2.0 * x - y;
+      URp[e] = 2.0 * y - x;
+    }
+  }
+  for (int r = ty; r < kAsmTile; r += 256 / kAsmTile) {
+    const int64_t b = b0 + r, a = a0 + tx;
+    if (a < V && b < V) RE[((q * O + i) * V + b) * ldre + j * V + a] = t[tx][r];
   }
 }
 
@@ -865,7 +934,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   const int64_t n2 = (int64_t)nmo * nmo, ov = c.ov(), oo = (int64_t)o * o, vv = (int64_t)v * v;
   const int64_t oovv = c.oovv(), oon = oo * naux, ovn = ov * naux, vvn = vv * naux, o4 = oo * oo;
   const bool f32 = precision != PNOEOM_FP64;  // FP32 or BF16: FP32 contractions here
-  alloc_sigma_work(c, precision, nb);
+  alloc_sigma_work(c, precision, nb, stride2 != oovv);
 
   // ---------------------------------------------------------------- R1: one-index transformed factors, per vector
   for (int q = 0; q < nb; ++q) {
@@ -906,33 +975,17 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     R2 = w.R2c;
   }
   const int64_t nbo = (int64_t)nb * o;
-  perm(s, R2, nbo, o, v, v, 0, 2, 1, 3, w.Ria);
   const int64_t ov2 = 2 * ov;
   const int64_t ldre = c.ring_y ? ov : ov2;  // RE rows: [R^s] or [R^s | E_X]
+  // Ria, R^s (left half of the rows of RE), UiaR = 2 R_ia - R^s, UR and URp (U(R) with a <-> b,
+  // for sigma1; kept in Zp, which is written later) in one pass over R2
+  double* URp = w.Zp;
   {
-    // R^s[(q,i,b)][(j,a)] = R[q][i][j][a][b] into the left half of the rows of RE
-    Perm4 p;
-    p.d[0] = nbo; p.d[1] = v; p.d[2] = o; p.d[3] = v;
-    p.is[0] = (int64_t)o * vv; p.is[1] = 1; p.is[2] = vv; p.is[3] = v;
-    p.os[0] = (int64_t)v * ldre; p.os[1] = ldre; p.os[2] = v; p.os[3] = 1;
-    permute4(s, p, 1.0, R2, 0.0, w.RE);
-  }
-  PNO_HIP(hipMemcpyAsync(w.UiaR, w.Ria, nb * oovv * sizeof(double), hipMemcpyDeviceToDevice, s));
-  {
-    // UiaR = 2 R_ia - R^s (R^s read from RE)
-    Perm4 p;
-    p.d[0] = (int64_t)nb * ov; p.d[1] = ov; p.d[2] = 1; p.d[3] = 1;
-    p.is[0] = ldre; p.is[1] = 1; p.is[2] = 0; p.is[3] = 0;
-    p.os[0] = ov; p.os[1] = 1; p.os[2] = 0; p.os[3] = 0;
-    permute4(s, p, -1.0, w.RE, 2.0, w.UiaR);
-  }
-  perm(s, R2, nbo, o, v, v, 0, 1, 3, 2, w.UR, -1.0, 0.0);
-  axpby(s, nb * oovv, 2.0, R2, 1.0, w.UR);
-  perm(s, w.UR, nbo, o, v, v, 0, 1, 3, 2, w.URp);
-  {
-    const int64_t dims[4] = {o, o, v, v};
-    const int pp[4] = {2, 0, 1, 3};
-    permute_c(s, dims, pp, 1.0, w.UR, 0.0, w.Ubr, nb);
+    const unsigned ntb = (unsigned)((v + kAsmTile - 1) / kAsmTile);
+    PNO_CHECK((int64_t)o * o <= 65535 && nb <= 65535, PNOEOM_EINVAL, "sigma: too many pairs or vectors per block");
+    hipLaunchKernelGGL(r2_layouts_kernel, dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb), dim3(256), 0, s, o, v,
+                       R2, (double*)w.Ria, (double*)w.UiaR, (double*)w.UR, URp, (double*)w.RE, ldre);
+    PNO_HIP(hipGetLastError());
   }
 
   // ---------------------------------------------------------------- sigma1
@@ -952,9 +1005,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   uint16_t* hb = reinterpret_cast<uint16_t*>((float*)w.fa);
   // rows m < M of K values, src[m sm + k], as bfloat16 rows of ld values (zero beyond K)
   auto rows_bf16 = [&](int64_t Mr, int64_t Kr, const double* src, int64_t sm, uint16_t* out, int64_t ld) {
-    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(Mr * ld)), dim3(256), 0, s, Mr, Kr, src, sm, (int64_t)1, out,
-                       ld, 1, 0);
-    PNO_HIP(hipGetLastError());
+    bf16_rows(s, Mr, Kr, src, sm, 1, out, ld, ld);
   };
   // C = alpha A B^T + beta C with A [Mg][ld], B [Ng][ld] bfloat16 rows, C FP32 rows of ldc
   auto bgemm = [&](int64_t Mg, int64_t Ng, int64_t ld, float alpha, const uint16_t* A, const uint16_t* Bm,
@@ -977,7 +1028,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   }
   gmb(s, false, false, o, v, (int64_t)v * naux, 1.0, w.M1, (int64_t)v * naux, ovn, c.Bvv2, v, 0, 1.0, s1, v,
       stride1, nb);
-  gmb(s, false, false, o, v, oo * v, -1.0, c.OOOVp, oo * v, 0, w.URp, v, oovv, 1.0, s1, v, stride1, nb);
+  gmb(s, false, false, o, v, oo * v, -1.0, c.OOOVp, oo * v, 0, URp, v, oovv, 1.0, s1, v, stride1, nb);
 
   // ---------------------------------------------------------------- sigma2, direct (not P-symmetrised)
   float* R2f = w.fa;             // FP32 staging of R2, then of Xh after it
@@ -1050,21 +1101,36 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   const int64_t K1 = c.ring_y ? ov : ov2;
   // ==== ring product launches: begin
   const bool bf_ring = precision == PNOEOM_BF16 && c.ring_y && c.DXb.p;
+  // BF16 scope 1, one pass: the DF-factorised ring terms join the ring products.  The left
+  // half of ZZ's rows is one product with K = 2 ov + 2 naux, [-R^s | R_ia | B'_vo | M1 / 2]
+  // times [Dr ; DX2 ; BYU ; YU], the right half -R^s Xr (the first ldr values of the same rows):
+  // no partial result is written and read back
+  const bool fold = bf_ring && bfr && c.RBb.p && c.ring_passes == 1;
   uint16_t* ab1 = nullptr;
   uint16_t* ab2 = nullptr;
   const int64_t kr = c.ring_passes * c.ldr;
-  if (bf_ring) {
+  if (fold) {
+    ab1 = reinterpret_cast<uint16_t*>((float*)w.fa);
+    bf16_rows(s, M, ov, w.RE, ldre, 1, ab1, c.ldr, c.kfold, 1, 0, -1.0);
+    bf16_rows(s, M, ov, w.Ria, ov, 1, ab1 + c.ldr, c.ldr, c.kfold);
+    bf16_rows(s, M, naux, w.BvopT, naux, 1, ab1 + 2 * c.ldr, c.ldq, c.kfold);
+    bf16_rows(s, M, naux, w.M1, naux, 1, ab1 + 2 * c.ldr + c.ldq, c.ldq, c.kfold, 1, 0, 0.5);
+  } else if (bf_ring) {
     // the left operands R^s and R_ia as bfloat16 rows of ring_passes x ldr values, staged in fa
     ab1 = reinterpret_cast<uint16_t*>((float*)w.fa);
     ab2 = ab1 + M * kr;
-    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(M * c.ldr)), dim3(256), 0, s, M, ov, (const double*)w.RE, ldre,
-                       (int64_t)1, ab1, c.ldr, c.ring_passes, 0);
-    hipLaunchKernelGGL(bf16_split_kernel, dim3(grid1(M * c.ldr)), dim3(256), 0, s, M, ov, (const double*)w.Ria, ov,
-                       (int64_t)1, ab2, c.ldr, c.ring_passes, 0);
-    PNO_HIP(hipGetLastError());
+    bf16_rows(s, M, ov, w.RE, ldre, 1, ab1, c.ldr, kr, c.ring_passes, 0);
+    bf16_rows(s, M, ov, w.Ria, ov, 1, ab2, c.ldr, kr, c.ring_passes, 0);
   }
   hipEvent_t ring_ev = c.region_begin(3, s);
-  if (bf_ring) {
+  if (fold) {
+    GemmBf16Desc d;
+    d.M = M; d.N = ov; d.K = c.kfold; d.alpha = 1.f; d.beta = 0.f; d.A = ab1; d.lda = c.kfold; d.B = c.RBb;
+    d.ldb = c.kfold; d.C = w.fc; d.ldc = ov2; d.tag = 3;
+    gemm_bf16(d, s);
+    d.K = c.ldr; d.B = c.DXb + ov * kr; d.ldb = kr; d.C = w.fc + ov;
+    gemm_bf16(d, s);
+  } else if (bf_ring) {
     // bfloat16 MFMA with FP32 accumulation: -R^s [Dr | Xr], then + R_ia DX2 into the left half
     GemmBf16Desc d;
     d.M = M; d.N = ov2; d.K = kr; d.alpha = -1.f; d.beta = 0.f; d.A = ab1; d.lda = kr; d.B = c.DXb; d.ldb = kr;
@@ -1094,7 +1160,8 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     d.N = ov; d.K = ov; d.alpha = 1.0; d.beta = 1.0; d.A = w.Ria; d.lda = ov; d.B = c.DX2; d.ldb = ov;
     gemm(d, s);
   }
-  c.region_end(ring_ev, 3, s, 2, 2.0 * (double)M * ov2 * K1 + 2.0 * (double)M * ov * ov,
+  c.region_end(ring_ev, 3, s, 2,
+               2.0 * (double)M * ov2 * K1 + 2.0 * (double)M * ov * ov + (fold ? 4.0 * (double)M * ov * naux : 0.0),
                8.0 * ((double)M * K1 + (double)K1 * ov2 + 5.0 * M * ov + (double)oovv));
   // ==== ring product launches: end
   // the DF-factorised parts of the ring terms, into the Ziajb half: (B'_vo BYU + 1/2 M1 YU), in
@@ -1102,6 +1169,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   // conversion of the whole ring block to FP64), else in FP64 below
   const bool df32 = f32 && c.BYUf.p && 2 * ovn <= (int64_t)w.fa.n / std::max(nb, 1);
   const bool ybf = bfr && c.ring_y && c.Yrb.p;  // R1 ring term through Yr on bfloat16 MFMA
+  const bool zf32 = ybf && c.Zrf.p;             // and the one through Zr on FP32 MFMA
   if (ybf) {
     // R1c: the block's R1 compacted as [(q,j)][c]
     Perm4 p;
@@ -1111,19 +1179,34 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     permute4(s, p, 1.0, r1, 0.0, w.R1c);
   }
   if (bfr) {
-    // B'_vo BYU + 1/2 M1 YU on top of the FP32 ring block (rows (q,i,a) of 2 ov in fc)
+    // B'_vo BYU + 1/2 M1 YU on top of the FP32 ring block (rows (q,i,a) of 2 ov in fc), unless
+    // the ring products took them
     uint16_t* bv = hb;
     uint16_t* bm = hb + nb * ov * c.ldq;
-    rows_bf16(nb * ov, naux, w.BvopT, naux, bv, c.ldq);
-    rows_bf16(nb * ov, naux, w.M1, naux, bm, c.ldq);
-    bgemm(nb * ov, ov, c.ldq, 1.f, bv, c.BYUb, 1.f, w.fc, ov2);
-    bgemm(nb * ov, ov, c.ldq, 0.5f, bm, c.YUb, 1.f, w.fc, ov2);
+    if (!fold) {
+      rows_bf16(nb * ov, naux, w.BvopT, naux, bv, c.ldq);
+      rows_bf16(nb * ov, naux, w.M1, naux, bm, c.ldq);
+      bgemm(nb * ov, ov, c.ldq, 1.f, bv, c.BYUb, 1.f, w.fc, ov2);
+      bgemm(nb * ov, ov, c.ldq, 0.5f, bm, c.YUb, 1.f, w.fc, ov2);
+    }
     if (ybf) {
       // -sum_c R1[q][j][c] Yr[(a,c)][n] for all (q,j) x (a,n) at once: the rows (q,j,a) of the
       // ring block are the rows (q,j) of a [nb o][v 2 ov] matrix
       uint16_t* br = bm + nb * ov * c.ldq;
       rows_bf16(nb * o, v, w.R1c, v, br, c.ldv);
       bgemm(nb * o, v * ov2, c.ldv, -1.f, br, c.Yrb, 1.f, w.fc, v * ov2);
+    }
+    if (zf32) {
+      // + sum_l R1[q][l][a] Zr[(j,l)][n] in FP32 on the ring block: per vector one product per j
+      float* r1f = w.fa;
+      to_float(s, nb * ov, w.R1c, r1f);
+      for (int q = 0; q < nb; ++q) {
+        GemmDesc<float> d;
+        d.ta = true; d.M = v; d.N = ov2; d.K = o; d.alpha = 1.f; d.beta = 1.f;
+        d.A = r1f + q * ov; d.lda = v; d.sA = 0; d.B = c.Zrf; d.ldb = ov2; d.sB = (int64_t)o * ov2;
+        d.C = w.fc + (int64_t)q * ov * ov2; d.ldc = ov2; d.sC = v * ov2; d.batch = o;
+        gemm(d, s);
+      }
     }
     to_double(s, 2 * (int64_t)nb * oovv, w.fc, w.ZZ, 0.0);
   } else if (f32) {
@@ -1158,29 +1241,51 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
           ov2, v);
     }
     // per vector, one product per j: R1[q]^T (v x o) times Zr[(j,l)] (o x 2 ov) into rows (q,j,a)
-    for (int q = 0; q < nb; ++q)
-      gmb(s, true, false, v, ov2, o, 1.0, w.R1c + q * ov, v, 0, c.Zr, ov2, (int64_t)o * ov2, 1.0,
-          w.ZZ + (int64_t)q * ov * ov2, ov2, v * ov2, o);
+    if (!zf32)
+      for (int q = 0; q < nb; ++q)
+        gmb(s, true, false, v, ov2, o, 1.0, w.R1c + q * ov, v, 0, c.Zr, ov2, (int64_t)o * ov2, 1.0,
+            w.ZZ + (int64_t)q * ov * ov2, ov2, v * ov2, o);
   }
 
   // ---------------------------------------------------------------- Fock-type terms in [i][j][a][b]
-  gm(s, false, true, (int64_t)nb * oo * v, v, v, 1.0, R2, v, c.Fvv, v, 0.0, w.Zp, v);
-  gmb(s, true, false, o, vv, o, -1.0, c.Foo, o, 0, R2, vv, o * vv, 1.0, w.Zp, vv, o * vv, nbo);
-  gmb(s, false, false, v, v, oo * v, -1.0, w.Ubr, oo * v, oovv, c.Gq, v, 0, 0.0, w.Ftv, v, vv, nb);
+  // Ftv[q][a][b] = -sum_(i,j) sum_c U(R)[q][i][j][a][c] Gq[(i,j,c)][b]: per vector one product
+  // summed over the o^2 pair blocks (v x v times v x v), rows of U(R) read in place
+  for (int q = 0; q < nb; ++q)
+    gmb(s, false, false, v, v, v, -1.0, w.UR + q * oovv, v, vv, c.Gq, v, vv, 0.0, w.Ftv + q * vv, v, 0, oo, true);
   axpby(s, nb * vv, 1.0, w.fp_vv, 1.0, w.Ftv);
+  if (bfr && c.Fvvf.p && c.T32.p) {
+    // BF16 scope 1: R Fvv^T + T Ftv^T on FP32 MFMA (operands staged in fa, result in fc)
+    float* r2f = w.fa;
+    float* ftf = w.fa + nb * oovv;
+    to_float(s, nb * oovv, R2, r2f);
+    to_float(s, nb * vv, w.Ftv, ftf);
+    GemmDesc<float> d;
+    d.tb = true; d.M = (int64_t)nb * oo * v; d.N = v; d.K = v; d.alpha = 1.f; d.beta = 0.f;
+    d.A = r2f; d.lda = v; d.B = c.Fvvf; d.ldb = v; d.C = w.fc; d.ldc = v;
+    gemm(d, s);
+    d.M = oo * v; d.beta = 1.f; d.A = c.T32; d.sA = 0; d.B = ftf; d.sB = vv; d.sC = oovv; d.batch = nb;
+    gemm(d, s);
+    to_double(s, nb * oovv, w.fc, w.Zp, 0.0);
+  } else {
+    gm(s, false, true, (int64_t)nb * oo * v, v, v, 1.0, R2, v, c.Fvv, v, 0.0, w.Zp, v);
+    gmb(s, false, true, oo * v, v, v, 1.0, c.T, v, 0, w.Ftv, v, vv, 1.0, w.Zp, v, oovv, nb);
+  }
+  gmb(s, true, false, o, vv, o, -1.0, c.Foo, o, 0, R2, vv, o * vv, 1.0, w.Zp, vv, o * vv, nbo);
   gmb(s, false, true, o, o, ov * v, 1.0, c.g2, ov * v, 0, w.UR, ov * v, oovv, 0.0, w.Fto, o, oo, nb);
   axpby(s, nb * oo, 1.0, w.fp_oo, 1.0, w.Fto);
-  gmb(s, false, true, oo * v, v, v, 1.0, c.T, v, 0, w.Ftv, v, vv, 1.0, w.Zp, v, oovv, nb);
   for (int q = 0; q < nb; ++q)
     gmb(s, true, false, o, vv, o, -1.0, w.Fto + q * oo, o, 0, c.T, vv, o * vv, 1.0, w.Zp + q * oovv, vv, o * vv, o);
-  // -P[ sum_k r_k^a Wvo_kbij ] collected as Cba[i][j][b][a] = sum_k Wvo2[(ijb)][k] r1[k][a]
-  gmb(s, false, false, oo * v, v, o, 1.0, c.Wvo2, o, 0, r1, v, stride1, 0.0, w.Cba, v, oovv, nb);
+  // -P[ sum_k r_k^a Wvo_kbij ]: Zp[q][(i,j)][a][b] -= sum_k r1[q][k][a] Wvo2[(i,j,b)][k], one
+  // product per pair and vector (the P symmetrisation is the assembly's)
+  for (int q = 0; q < nb; ++q)
+    gmb(s, true, true, v, v, o, -1.0, r1 + q * stride1, v, 0, c.Wvo2, o, (int64_t)v * o, 1.0, w.Zp + q * oovv, v,
+        vv, oo);
 
   {
     const unsigned ntb = (unsigned)((v + kAsmTile - 1) / kAsmTile);
     PNO_CHECK((int64_t)o * o <= 65535 && nb <= 65535, PNOEOM_EINVAL, "sigma: too many pairs or vectors per block");
     hipLaunchKernelGGL(assemble_s2_tiled_kernel, dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb), dim3(256), 0, s,
-                       o, v, (const double*)Sd, (const double*)w.Zp, (const double*)w.ZZ, (const double*)w.Cba, s2,
+                       o, v, (const double*)Sd, (const double*)w.Zp, (const double*)w.ZZ, s2,
                        stride2);
     PNO_HIP(hipGetLastError());
   }
@@ -1486,8 +1591,8 @@ uint64_t sigma_signature(Context& c, hipStream_t s) {
   };
   SigmaWork& w = c.sw;
   for (DBuf<double>* b : {&w.Bp, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT, &w.BoopT,
-                          &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.UR, &w.URp, &w.Ubr, &w.ZZ,
-                          &w.RE, &w.Zp, &w.Cba, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.R1c, &w.Ftv, &w.Fto, &w.LadAll, &w.Sp,
+                          &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.UR, &w.ZZ,
+                          &w.RE, &w.Zp, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.R1c, &w.Ftv, &w.Fto, &w.LadAll, &w.Sp,
                           &w.Am, &w.SigP, &w.SigM, &c.pno.Tw, &c.pno.r1, &c.pno.r2, &c.pno.s1, &c.pno.s2, &c.gin,
                           &c.gout})
     mix(b->p, b->n);
