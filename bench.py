@@ -64,6 +64,35 @@ def gemm_kernel_sha():
     return h.hexdigest()
 
 
+# HBM bytes per launch of the bfloat16 ring products of the headline workload (o=40, v=400
+# SA-PNO sigma blocks), from two rocprofv3 --pmc runs of the headline command (FETCH_SIZE,
+# WRITE_SIZE; profiles/ring_bf16_config4_counters.md), scaled by what the counters read for the
+# 1 GiB + 1 GiB device copy of the same run.  Valid for the code they were taken on: the
+# 256 x 256 kernel file, the bfloat16 GEMM dispatch of gemm.hip and the ring launches of
+# sigma.hip, by hash; reported as null once any of them changes.
+BF16_RING_TRAFFIC = None
+
+
+def bf16_kernel_sha():
+    """sha256 over csrc/gemm_bf16.hip, the bfloat16 GEMM dispatch (marked region of gemm.hip)
+    and the ring product launches (marked region of sigma.hip)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1802_06738_amd", "csrc")
+    h = hashlib.sha256()
+    with open(os.path.join(csrc, "gemm_bf16.hip"), "rb") as fh:
+        h.update(fh.read())
+    h.update(_region(os.path.join(csrc, "gemm.hip"), "bf16 GEMM dispatch").encode())
+    h.update(_region(os.path.join(csrc, "sigma.hip"), "ring product launches").encode())
+    return h.hexdigest()
+
+
+def bf16_ring_traffic():
+    t = BF16_RING_TRAFFIC
+    if t is None or bf16_kernel_sha() != t["sha256"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
 def kernel_traffic(name, config, pno_only):
     t = KERNEL_TRAFFIC.get(name)
     if t is None or config != t["config"] or pno_only:
@@ -588,7 +617,8 @@ def headline_pno(args):
     fams = {k: v_ for k, v_ in fams.items() if v_ is not None}
     dom = max(fams, key=lambda k: fams[k]["ms_per_step"])
     roof = dict(fams[dom])
-    roof["traffic"] = None
+    roof["traffic"] = bf16_ring_traffic() if dom == "ring" and cfgid == 4 else None
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)"
     roof["peak_measured"] = peaks["bf16_tflops"] if roof["unit"] == "TFLOP/s" else peaks["copy_gbs"]
     out = {
         "metric": METRIC,

@@ -425,9 +425,11 @@ int pnoeom_gemm_set_table(int n, const long long* keys, const int* variants);
  * device bfloat16 bit patterns (K contiguous; K, lda, ldb multiples of 64 with the
  * padding columns zero; 16-byte aligned), C [M][ldc] device FP32, ldc >= N.  variant:
  * 0 = chosen by shape, 1 = 128 x 128 tiles (16x16x32 MFMA), 2 = 256 x 256 tiles
- * (32x32x16 MFMA, direct-to-LDS loads; needs M, N >= 256), 3 = as 2 with the k-steps
+ * (32x32x16 MFMA, direct-to-LDS loads; needs M, N >= 160), 3 = as 2 with the k-steps
  * rotated across the K-tile barrier, 4 / 5 = as 3 with the tiles taken M-fastest / in
- * groups of 8 tile columns (3 chooses between M-fastest and groups of 4 by shape).
+ * groups of 8 tile columns (3 chooses between M-fastest and groups of 4 by shape).  Variants
+ * 0 and 3 split K (partials in a library workspace, summed in a fixed order) when the
+ * tiles fill the 256 compute units poorly and K is long.
  * Stream-ordered on hip_stream (NULL = default).
  * pnoeom_gemm_bf16_time times a variant on scratch operands of shape M x N x K that it
  * allocates (reps launches; *ms = mean milliseconds, -1 above 16 GiB of operands).

@@ -128,11 +128,14 @@ struct GemmBf16Desc {
   // k-steps (tile order by shape); 4, 5: variant 3 with the tile order M-fastest / in groups
   // of 8 tile columns
   int variant = 0;
+  bool no_split = false;  // never split K (the split partials live in an allocated workspace)
 };
 void gemm_bf16(const GemmBf16Desc& d, hipStream_t s);
 // the 256 x 256-tile kernel (gemm_bf16.hip) and the shapes it takes
 bool gemm_bf16_big_fits(int64_t M, int64_t N);
-void gemm_bf16_big(const GemmBf16Desc& d, hipStream_t s, bool rotated, int group);
+// nsplit > 1: K split over grid.y, partials alpha A B^T into ws[split][M][N] (the caller sums them)
+void gemm_bf16_big(const GemmBf16Desc& d, hipStream_t s, bool rotated, int group, int nsplit = 1,
+                   float* ws = nullptr);
 // average ms of one launch of a variant on scratch operands of shape M x N x K (K padded to 64)
 double gemm_bf16_time(hipStream_t s, int64_t M, int64_t N, int64_t K, int variant, int reps);
 

@@ -128,13 +128,19 @@ struct Context {
   // B~_ov (precision FP32 / BF16: those products then run on FP32 MFMA)
   DBuf<float> Whf, g2f, T32, BovTf;
   DBuf<float> BYUf, YUf;  // FP32 copies of the DF ring factors (precision FP32 / BF16)
-  DBuf<float> Fvvf, Zrf;  // BF16 scope 1: FP32 copies of Fvv and Zr (Fock-type and Zr ring terms)
+  // BF16 scope 1: FP32 copies of Foo, Wvo2 and Zr (Fock-type, Wvo and Zr ring terms)
+  DBuf<float> Foof, Wvo2f, Zrf;
   // bfloat16 operands of the other large products in BF16 mode (rows padded to 64 values):
   // Wh [(ij)][(kl)], g2 [(kl)][(cd)], T^T [(ab)][(kl)] (hole ladder and X_klij), B~_ov as
   // [Q][(jb)] (M1), BYU^T and YU^T as [(kc)][Q] (DF ring terms, rows of ldq), and Yr with
   // its last two indices swapped, [(a, n)][c] (R1 term of the ring)
   DBuf<uint16_t> Whb, g2b, TTb, BovQb, BYUb, YUb, Yrb;
-  int64_t ldoo = 0, ldvv = 0, ldov = 0, ldv = 0;
+  DBuf<uint16_t> Gqb;  // Gq^T as [b][(k,l,d)] (Ftv), rows of ldg
+  // T as rows [(i,j,a)][c] and Fvv without its diagonal as rows [b][c] (rows of ldv; the
+  // Fock-type products T Ftv^T and R (Fvv - diag)^T), and the diagonal of Fvv
+  DBuf<uint16_t> Tvb, Fvob;
+  DBuf<double> Fvvd;
+  int64_t ldoo = 0, ldvv = 0, ldov = 0, ldv = 0, ldg = 0;
   bool bf_rest = false;
   // build-time temporaries of build_df, by slot (each slot's uses follow one another on the
   // stream); kept between builds while keep_build_tmp is set (the repeated builds of the

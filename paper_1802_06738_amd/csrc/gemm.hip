@@ -64,6 +64,11 @@ struct KArgs {
   int tiles_m, tiles_n;
   int64_t xper;       // tiles per XCD chunk; 0: grid index = tile index
   int64_t it_split;   // K-loop iterations per split (split-K); 0: no split
+  // split launches: one 1-D grid over the units (tile, batch entry, split), tile fastest,
+  // handed to the XCDs in 8 contiguous chunks of uper units (0: 3-D grid)
+  int64_t uper, nbz, nsplit;
+  int nfast;  // tile order N fastest (few tile columns: the A panel of a row of tiles is read
+              // once by neighbouring workgroups, the few B panels stay in L2); else M fastest
   T* ws;              // split-K partials [split][batch_out][M][N]
   int vec_a, vec_b;   // FP32 operands whose interior tiles load as 16-byte vectors (aligned rows)
 };
@@ -92,14 +97,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
   // tile index -> (tm, tn): column-of-tiles major so that consecutive workgroups
   // share the same B panel
   int64_t tile = blockIdx.x;
-  if (g.xper > 0) {
+  int64_t bz = blockIdx.y, kz = blockIdx.z, nbz = gridDim.y;
+  if (g.uper > 0) {
+    // the tiles of one (batch entry, split) run side by side on one XCD and share their
+    // operand panels in its L2
+    const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n;
+    const int64_t u = (int64_t)(blockIdx.x % 8) * g.uper + blockIdx.x / 8;
+    if (u >= tiles * g.nbz * g.nsplit) return;  // padding of the last chunk
+    tile = u % tiles;
+    bz = (u / tiles) % g.nbz;
+    kz = u / (tiles * g.nbz);
+    nbz = g.nbz;
+  } else if (g.xper > 0) {
     tile = (int64_t)(blockIdx.x % 8) * g.xper + blockIdx.x / 8;
     if (tile >= (int64_t)g.tiles_m * g.tiles_n) return;  // padding of the last chunk
   }
-  const int64_t tmi = tile % g.tiles_m;
-  const int64_t tni = tile / g.tiles_m;
+  const int64_t tmi = g.nfast ? tile / g.tiles_n : tile % g.tiles_m;
+  const int64_t tni = g.nfast ? tile % g.tiles_n : tile / g.tiles_m;
   const int64_t m0 = tmi * BM, n0 = tni * BN;
-  const int64_t bz = blockIdx.y;
 
   typedef typename Mfma<T>::v4 v4;
   v4 acc[TM][TN];
@@ -258,7 +273,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
 
   int64_t it_begin = 0, it_end = total;
   if (g.it_split > 0) {
-    it_begin = (int64_t)blockIdx.z * g.it_split;
+    it_begin = kz * g.it_split;
     it_end = it_begin + g.it_split < total ? it_begin + g.it_split : total;
   }
   if (it_begin < it_end) load(it_begin);
@@ -274,7 +289,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
   T* C;
   int64_t ldc;
   if (split) {
-    C = g.ws + ((int64_t)blockIdx.z * gridDim.y + bz) * g.M * g.N;
+    C = g.ws + (kz * nbz + bz) * g.M * g.N;
     ldc = g.N;
   } else {
     C = g.C + (g.reduce ? 0 : bz * g.sC);
@@ -366,6 +381,7 @@ void launch_tile(const GemmDesc<T>& d, hipStream_t s, int split_mode = 0) {
 #endif
   g.tiles_m = (int)((d.M + BM - 1) / BM);
   g.tiles_n = (int)((d.N + BN - 1) / BN);
+  g.nfast = g.tiles_n <= 8 && g.tiles_m > g.tiles_n ? 1 : 0;
   const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n;
   PNO_CHECK(tiles < (1ll << 31), PNOEOM_EINVAL, "gemm: too many tiles");
   const int64_t gy = d.reduce ? 1 : d.batch;
@@ -390,15 +406,27 @@ void launch_tile(const GemmDesc<T>& d, hipStream_t s, int split_mode = 0) {
     nsplit = (loop + g.it_split - 1) / g.it_split;
     g.ws = splitk_ws<T>(s, (size_t)nsplit * gy * d.M * d.N);
   }
-  // XCD-contiguous tile order (the grid is padded to a multiple of 8)
+  // XCD-contiguous tile order (the grid is padded to a multiple of 8); a split launch runs
+  // as one 1-D grid over (tile, batch entry, split) units in XCD-contiguous chunks
   g.xper = 0;
+  g.uper = 0;
+  g.nbz = gy;
+  g.nsplit = nsplit;
   int64_t gx = tiles;
-  if (tiles >= 64) {
-    g.xper = (tiles + 7) / 8;
-    gx = 8 * g.xper;
+  dim3 grid;
+  if (nsplit > 1) {
+    g.uper = (tiles * gy * nsplit + 7) / 8;
+    gx = 8 * g.uper;
+    PNO_CHECK(gx < (1ll << 31), PNOEOM_EINVAL, "gemm: too many tiles");
+    grid = dim3((unsigned)gx, 1, 1);
+  } else {
+    if (tiles >= 64) {
+      g.xper = (tiles + 7) / 8;
+      gx = 8 * g.xper;
+    }
+    PNO_CHECK(gx < (1ll << 31), PNOEOM_EINVAL, "gemm: too many tiles");
+    grid = dim3((unsigned)gx, (unsigned)gy, (unsigned)nsplit);
   }
-  PNO_CHECK(gx < (1ll << 31), PNOEOM_EINVAL, "gemm: too many tiles");
-  dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)nsplit);
   if (d.tag == 1 && !d.ta && d.tb)
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, false, true, 1>), grid, dim3(NT), 0, s, g);
   else if (d.tag == 2 && !d.ta && d.tb)
@@ -747,6 +775,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
 }
 }  // namespace
 
+// ==== bf16 GEMM dispatch: begin
 void gemm_bf16(const GemmBf16Desc& d, hipStream_t s) {
   PNO_CHECK(d.M >= 0 && d.N >= 0 && d.K >= 0, PNOEOM_EINVAL, "gemm_bf16: negative size");
   if (d.M == 0 || d.N == 0) return;
@@ -757,9 +786,30 @@ void gemm_bf16(const GemmBf16Desc& d, hipStream_t s) {
             "gemm_bf16: operands must be 16-byte aligned");
   PNO_CHECK(d.variant >= 0 && d.variant <= 5, PNOEOM_EINVAL, "gemm_bf16: unknown variant");
   PNO_CHECK(d.variant < 2 || gemm_bf16_big_fits(d.M, d.N), PNOEOM_EINVAL,
-            "gemm_bf16: the 256 x 256 tiles need M, N >= 256");
-  if (d.variant >= 2 || (d.variant == 0 && gemm_bf16_big_fits(d.M, d.N) &&
-                         ((d.M + 255) / 256) * ((d.N + 255) / 256) >= 256)) {
+            "gemm_bf16: the 256 x 256 tiles need M, N >= 160");
+  const int64_t tiles256 = ((d.M + 255) / 256) * ((d.N + 255) / 256);
+  const int64_t ktiles = d.K / kBf16K;
+  if (d.variant >= 2 || (d.variant == 0 && gemm_bf16_big_fits(d.M, d.N) && (tiles256 >= 256 || ktiles >= 32))) {
+    // split K when the tiles fill the 256 CUs poorly (fraction of the waves of workgroups that
+    // has work) and the K loop is long: partials in the split-K workspace, summed in split
+    // order by splitk_reduce_kernel.  A split costs about one write and one read of the
+    // output per partial against 2 K flops per output element: sp 1000 / K of the time
+    int nsplit = 1;
+    if (!d.no_split && (d.variant == 0 || d.variant == 3)) {
+      auto fill = [](int64_t t) { return (double)t / (double)(((t + 255) / 256) * 256); };
+      double best = fill(tiles256) + 0.05;
+      for (int sp = 2; sp <= 64 && ktiles / sp >= 16; ++sp) {
+        const double f = fill(tiles256 * sp) - sp * 1000.0 / (double)d.K;
+        if (f > best) {
+          best = f;
+          nsplit = sp;
+        }
+      }
+      if (nsplit > 1) {
+        const int64_t kper = (ktiles + nsplit - 1) / nsplit;
+        nsplit = (int)((ktiles + kper - 1) / kper);
+      }
+    }
     // tile order: with at most 32 rows of tiles and a long K loop, M-fastest order keeps every
     // row of a tile column running at once on each XCD (the B panel shared in the XCD's L2,
     // the A panels shared across XCDs in the memory-side cache; 4920 x 80200 x 80256: 1111
@@ -768,7 +818,18 @@ void gemm_bf16(const GemmBf16Desc& d, hipStream_t s) {
     int group = (d.M + 255) / 256 <= 32 && d.K >= 8192 ? 0 : 4;
     if (d.variant == 4) group = 0;
     if (d.variant == 5) group = 8;
-    gemm_bf16_big(d, s, d.variant != 2, group);
+    if (nsplit > 1) {
+      float* ws = splitk_ws<float>(s, (size_t)nsplit * d.M * d.N);
+      gemm_bf16_big(d, s, d.variant != 2, group, nsplit, ws);
+      const int64_t total = d.M * d.N;
+      int64_t blocks = (total + 255) / 256;
+      if (blocks > 65536) blocks = 65536;
+      hipLaunchKernelGGL((splitk_reduce_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, s, d.M, d.N,
+                         (int64_t)1, (int64_t)nsplit, d.beta, (const float*)ws, d.C, d.ldc, (int64_t)0);
+      PNO_HIP(hipGetLastError());
+    } else {
+      gemm_bf16_big(d, s, d.variant != 2, group);
+    }
     return;
   }
   constexpr int BM = 128, BN = 128;
@@ -795,6 +856,7 @@ void gemm_bf16(const GemmBf16Desc& d, hipStream_t s) {
     hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, 0>), dim3((unsigned)gx), dim3(NT), 0, s, g);
   PNO_HIP(hipGetLastError());
 }
+// ==== bf16 GEMM dispatch: end
 
 namespace {
 __global__ void fill_bf16_kernel(int64_t n, uint16_t* x) {

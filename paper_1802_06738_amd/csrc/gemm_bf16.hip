@@ -49,6 +49,8 @@ struct BigArgs {
   int tiles_m, tiles_n;
   int64_t xper;  // tiles per XCD chunk; 0: grid index = tile index
   int group;     // tile columns per group of the tile order (0: M fastest over all rows)
+  int64_t kper;  // split K: K-tiles per split (grid.y = splits), partials alpha A B^T into
+  float* ws;     // ws[split][M][N]; kper = 0: no split, C = alpha A B^T + beta C
 };
 
 // origin of tile t of the tile order
@@ -73,6 +75,36 @@ constexpr int WM = TM / 2, WN = TN / 2, FM = WM / 32, FN = WN / 32;
 constexpr int NQA = TM / 32, NQB = TN / 32;  // 1 KB direct loads per wave per operand tile
 
 typedef __attribute__((address_space(3))) void lds_void;
+
+// C tile store: accumulator r of lane l holds column l%32 and row 8 (r/4) + 4 (l/32) + r%4 of
+// each 32 x 32 block; with split K the partial alpha A B^T goes to ws[split] (rows of N)
+__device__ __forceinline__ void store_tile(const BigArgs& g, const f32x16 (&acc)[FM][FN], int64_t m0, int64_t n0,
+                                           int wm, int wn, int lr, int lk) {
+  float* C = g.C;
+  int64_t ldc = g.ldc;
+  float beta = g.beta;
+  if (g.kper > 0) {
+    C = g.ws + (int64_t)blockIdx.y * g.M * g.N;
+    ldc = g.N;
+    beta = 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t gn = n0 + wn * WN + j * 32 + lr;
+      if (gn >= g.N) continue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t gm = m0 + wm * WM + i * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
+        if (gm >= g.M) continue;
+        float* c = C + gm * ldc + gn;
+        float val = g.alpha * acc[i][j][r];
+        if (beta != 0.f) val += beta * (*c);
+        *c = val;
+      }
+    }
+}
 
 template <int TAG>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1))) void gemm_bf16_big_kernel(BigArgs g) {
@@ -135,14 +167,18 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1))) void ge
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  const int64_t ktiles = g.K / TK;
-  if (ktiles > 0) issue(0, 0);
+  int64_t kb = 0, ke = g.K / TK;  // this workgroup's K-tiles
+  if (g.kper > 0) {
+    kb = (int64_t)blockIdx.y * g.kper;
+    ke = kb + g.kper < ke ? kb + g.kper : ke;
+  }
+  if (kb < ke) issue(kb, 0);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   bf16x8 fa[2][FM], fb[2][FN];
-  for (int64_t kt = 0; kt < ktiles; ++kt) {
-    const int cur = (int)(kt & 1);
-    if (kt + 1 < ktiles) issue(kt + 1, cur ^ 1);  // its buffer was last read before the barrier
+  for (int64_t kt = kb; kt < ke; ++kt) {
+    const int cur = (int)((kt - kb) & 1);
+    if (kt + 1 < ke) issue(kt + 1, cur ^ 1);  // its buffer was last read before the barrier
     const uint16_t* as = lds + cur * (TM + TN) * TK;
     const uint16_t* bs = as + TM * TK;
 #pragma unroll
@@ -177,22 +213,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1))) void ge
     __syncthreads();
   }
 
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int64_t gn = n0 + wn * WN + j * 32 + lr;
-      if (gn >= g.N) continue;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t gm = m0 + wm * WM + i * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
-        if (gm >= g.M) continue;
-        float* c = g.C + gm * g.ldc + gn;
-        float val = g.alpha * acc[i][j][r];
-        if (g.beta != 0.f) val += g.beta * (*c);
-        *c = val;
-      }
-    }
+  store_tile(g, acc, m0, n0, wm, wn, lr, lk);
 }
 
 // The same tile and staging with the k-steps rotated across the barrier: the last k-step's
@@ -280,16 +301,20 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1))) void ge
   };
   // K-tile kt + 1 is loaded while tile kt is multiplied: its direct loads are issued right
   // after the barrier that ends the reads of the buffer it replaces (tile kt - 1's)
-  const int64_t ktiles = g.K / TK;
-  if (ktiles > 0) {
-    issue(0, 0);
+  int64_t kb = 0, ke = g.K / TK;  // this workgroup's K-tiles
+  if (g.kper > 0) {
+    kb = (int64_t)blockIdx.y * g.kper;
+    ke = kb + g.kper < ke ? kb + g.kper : ke;
+  }
+  if (kb < ke) {
+    issue(kb, 0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (ktiles > 1) issue(1, 1);
+    if (kb + 1 < ke) issue(kb + 1, 1);
     load_frags(0, lds, lds + TM * TK, 0);
   }
-  for (int64_t kt = 0; kt < ktiles; ++kt) {
-    const int cur = (int)(kt & 1);
+  for (int64_t kt = kb; kt < ke; ++kt) {
+    const int cur = (int)((kt - kb) & 1);
     const uint16_t* as = lds + cur * (TM + TN) * TK;
     const uint16_t* bs = as + TM * TK;
     load_frags(1, as, bs, 1);
@@ -303,7 +328,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1))) void ge
     interleave();
     __builtin_amdgcn_s_waitcnt(0);  // tile kt + 1 has landed and tile kt's reads are done
     __syncthreads();
-    if (kt + 2 < ktiles) issue(kt + 2, cur);
+    if (kt + 2 < ke) issue(kt + 2, cur);
     // first fragments of the next K-tile (after the last one: read but unused) under step 3
     const uint16_t* an = lds + (cur ^ 1) * (TM + TN) * TK;
     load_frags(0, an, an + TM * TK, 0);
@@ -311,32 +336,30 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1))) void ge
     interleave();
   }
 
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int64_t gn = n0 + wn * WN + j * 32 + lr;
-      if (gn >= g.N) continue;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t gm = m0 + wm * WM + i * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
-        if (gm >= g.M) continue;
-        float* c = g.C + gm * g.ldc + gn;
-        float val = g.alpha * acc[i][j][r];
-        if (g.beta != 0.f) val += g.beta * (*c);
-        *c = val;
-      }
-    }
+  store_tile(g, acc, m0, n0, wm, wn, lr, lk);
 }
 
 }  // namespace
 
-bool gemm_bf16_big_fits(int64_t M, int64_t N) { return M >= TM && N >= TN; }
+// rows and columns past the end of A / B are clamped on load and never stored, so any shape
+// runs; below 5/8 of a tile in either dimension the 128 x 128 kernel wastes less
+bool gemm_bf16_big_fits(int64_t M, int64_t N) { return M >= 160 && N >= 160; }
 
-void gemm_bf16_big(const GemmBf16Desc& d, hipStream_t s, bool rotated, int group) {
+void gemm_bf16_big(const GemmBf16Desc& d, hipStream_t s, bool rotated, int group, int nsplit, float* ws) {
   static_assert(TM == 256 && TN == 256, "tile_origin assumes 256 x 256 tiles");
   BigArgs g;
   g.group = group;
+  g.kper = 0;
+  g.ws = nullptr;
+  const int64_t ktiles = d.K / TK;
+  if (nsplit > 1) {
+    PNO_CHECK(ws != nullptr && nsplit <= 65535, PNOEOM_EINVAL, "gemm_bf16: split K without a workspace");
+    g.kper = (ktiles + nsplit - 1) / nsplit;
+    PNO_CHECK((ktiles + g.kper - 1) / g.kper == nsplit, PNOEOM_EINVAL, "gemm_bf16: empty K split");
+    g.ws = ws;
+  } else {
+    nsplit = 1;
+  }
   g.M = d.M; g.N = d.N; g.K = d.K; g.alpha = d.alpha; g.beta = d.beta;
   g.A = d.A; g.lda = d.lda; g.B = d.B; g.ldb = d.ldb; g.C = d.C; g.ldc = d.ldc;
   g.tiles_m = (int)((d.M + TM - 1) / TM);
@@ -351,17 +374,17 @@ void gemm_bf16_big(const GemmBf16Desc& d, hipStream_t s, bool rotated, int group
   PNO_CHECK(gx < (1ll << 31), PNOEOM_EINVAL, "gemm_bf16: too many tiles");
   if (rotated) {
     switch (d.tag) {
-      case 1: hipLaunchKernelGGL(gemm_bf16_rot_kernel<1>, dim3((unsigned)gx), dim3(BT), 0, s, g); break;
-      case 2: hipLaunchKernelGGL(gemm_bf16_rot_kernel<2>, dim3((unsigned)gx), dim3(BT), 0, s, g); break;
-      case 3: hipLaunchKernelGGL(gemm_bf16_rot_kernel<3>, dim3((unsigned)gx), dim3(BT), 0, s, g); break;
-      default: hipLaunchKernelGGL(gemm_bf16_rot_kernel<0>, dim3((unsigned)gx), dim3(BT), 0, s, g); break;
+      case 1: hipLaunchKernelGGL(gemm_bf16_rot_kernel<1>, dim3((unsigned)gx, (unsigned)nsplit), dim3(BT), 0, s, g); break;
+      case 2: hipLaunchKernelGGL(gemm_bf16_rot_kernel<2>, dim3((unsigned)gx, (unsigned)nsplit), dim3(BT), 0, s, g); break;
+      case 3: hipLaunchKernelGGL(gemm_bf16_rot_kernel<3>, dim3((unsigned)gx, (unsigned)nsplit), dim3(BT), 0, s, g); break;
+      default: hipLaunchKernelGGL(gemm_bf16_rot_kernel<0>, dim3((unsigned)gx, (unsigned)nsplit), dim3(BT), 0, s, g); break;
     }
   } else {
     switch (d.tag) {
-      case 1: hipLaunchKernelGGL(gemm_bf16_big_kernel<1>, dim3((unsigned)gx), dim3(BT), 0, s, g); break;
-      case 2: hipLaunchKernelGGL(gemm_bf16_big_kernel<2>, dim3((unsigned)gx), dim3(BT), 0, s, g); break;
-      case 3: hipLaunchKernelGGL(gemm_bf16_big_kernel<3>, dim3((unsigned)gx), dim3(BT), 0, s, g); break;
-      default: hipLaunchKernelGGL(gemm_bf16_big_kernel<0>, dim3((unsigned)gx), dim3(BT), 0, s, g); break;
+      case 1: hipLaunchKernelGGL(gemm_bf16_big_kernel<1>, dim3((unsigned)gx, (unsigned)nsplit), dim3(BT), 0, s, g); break;
+      case 2: hipLaunchKernelGGL(gemm_bf16_big_kernel<2>, dim3((unsigned)gx, (unsigned)nsplit), dim3(BT), 0, s, g); break;
+      case 3: hipLaunchKernelGGL(gemm_bf16_big_kernel<3>, dim3((unsigned)gx, (unsigned)nsplit), dim3(BT), 0, s, g); break;
+      default: hipLaunchKernelGGL(gemm_bf16_big_kernel<0>, dim3((unsigned)gx, (unsigned)nsplit), dim3(BT), 0, s, g); break;
     }
   }
   PNO_HIP(hipGetLastError());

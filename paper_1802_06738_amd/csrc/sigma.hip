@@ -153,6 +153,42 @@ __global__ __launch_bounds__(256) void bf16_transpose_kernel(int64_t R, int64_t 
   }
 }
 
+// out[b][c] = bf16(F[b][c]) for c != b (zero on the diagonal and beyond n, rows of ld values),
+// d[b] = F[b][b]: a square matrix split into its exact diagonal and a bfloat16 remainder
+__global__ void offdiag_rows_bf16_kernel(int64_t n, const double* __restrict__ F, uint16_t* __restrict__ out,
+                                         int64_t ld, double* __restrict__ d) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * ld; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / ld, c = e % ld;
+    out[e] = bf16_bits(c < n && c != b ? F[b * n + c] : 0.0);
+    if (c == b) d[b] = F[b * n + b];
+  }
+}
+
+// Zp[e] = acc[e] + R[e] d[e % v]: the FP32 sum of the Fock-type products plus the diagonal part
+// of R Fvv^T, in FP64
+__global__ void zp_finish_kernel(int64_t n, int64_t v, const float* __restrict__ acc, const double* __restrict__ R,
+                                 const double* __restrict__ d, double* __restrict__ Zp) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    Zp[e] = (double)acc[e] + R[e] * d[e % v];
+}
+
+// out[q][a][(p, c)] = bf16(U[q][p][a][c]) for pairs p < npair (U: [nb][npair][v][v]), rows of
+// ld values, zero beyond npair v: the left operand of Ftv = -sum_(p,c) U[p][a][c] Gq[(p,c)][b]
+__global__ void pair_rows_bf16_kernel(int64_t nb, int64_t npair, int64_t v, const double* __restrict__ U,
+                                      uint16_t* __restrict__ out, int64_t ld) {
+  const int64_t total = nb * v * ld;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e % ld, r = e / ld;  // r = (q, a)
+    const int64_t q = r / v, a = r % v;
+    double x = 0.0;
+    if (k < npair * v) {
+      const int64_t p = k / v, c = k % v;
+      x = U[((q * npair + p) * v + a) * v + c];
+    }
+    out[e] = bf16_bits(x);
+  }
+}
+
 // bfloat16 operand rows: row m of out (row stride ldo) holds `passes` blocks of ldk values;
 // with x = scale src[m sm + k sk] (0 for k >= K; scale a power of two), hi = bf16(x) and
 // lo = bf16(x - hi), a left operand (right = 0) takes [hi | hi | lo] and a right operand
@@ -320,9 +356,13 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   c.drop_graphs();
   if (!c.keep_build_tmp) c.sw.release();  // (the CCSD iteration keeps its FP64 sigma workspaces)
   c.pno.reset();
-  for (DBuf<float>* b : {&c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf, &c.BYUf, &c.YUf, &c.Fvvf, &c.Zrf})
+  for (DBuf<float>* b : {&c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf, &c.BYUf, &c.YUf, &c.Foof,
+                         &c.Wvo2f, &c.Zrf})
     b->release();
-  for (DBuf<uint16_t>* b : {&c.Whb, &c.g2b, &c.TTb, &c.BovQb, &c.BYUb, &c.YUb, &c.Yrb, &c.DXb, &c.DX2b}) b->release();
+  for (DBuf<uint16_t>* b : {&c.Whb, &c.g2b, &c.TTb, &c.BovQb, &c.BYUb, &c.YUb, &c.Yrb, &c.DXb, &c.DX2b, &c.Gqb,
+                            &c.Tvb, &c.Fvob})
+    b->release();
+  c.Fvvd.release();
   c.bf_rest = false;
   c.ring_y = false;
   c.Yr.release();
@@ -662,6 +702,16 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     tr(ov, naux, c.BovT, 0, c.BovQb, c.ldov, 0, 1);  // B~_ov [(jb)][Q] -> [Q][(jb)]
     tr(naux, ov, c.BYU, 0, c.BYUb, c.ldq, 0, 1);    // BYU [Q][(kc)] -> [(kc)][Q]
     tr(naux, ov, c.YU, 0, c.YUb, c.ldq, 0, 1);
+    c.ldg = bf16_ld(oo * v);
+    c.Gqb.alloc(v * c.ldg);
+    tr(oo * v, v, c.Gq, 0, c.Gqb, c.ldg, 0, 1);  // Gq [(k,l,d)][b] -> [b][(k,l,d)]
+    c.Tvb.alloc(oo * v * c.ldv);
+    bf16_rows(s, oo * v, v, c.T, v, 1, c.Tvb, c.ldv, c.ldv);
+    c.Fvvd.alloc(v);
+    c.Fvob.alloc(v * c.ldv);
+    hipLaunchKernelGGL(offdiag_rows_bf16_kernel, dim3(grid1(v * c.ldv)), dim3(256), 0, s, (int64_t)v, (const double*)c.Fvv,
+                       (uint16_t*)c.Fvob, c.ldv, (double*)c.Fvvd);
+    PNO_HIP(hipGetLastError());
     if (c.ring_y) {  // Yr[(a,c)][n] -> Yrb[(a,n)][c], one transpose per a
       const int64_t ov2 = 2 * ov;
       c.Yrb.alloc((int64_t)v * ov2 * c.ldv);
@@ -669,10 +719,12 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
       c.Zrf.alloc(oo * ov2);
       to_float(s, oo * ov2, c.Zr, c.Zrf);
     }
-    // FP32 operands of the Fock-type products R Fvv^T and T Ftv^T
-    c.Fvvf.alloc(vv);
+    // FP32 operands of the Fock-type and Wvo products (R Fvv^T, T Ftv^T, Foo R, Fto T, r1 Wvo)
+    c.Foof.alloc(oo);
+    c.Wvo2f.alloc(oo * v * o);
     c.T32.alloc(oovv);
-    to_float(s, vv, c.Fvv, c.Fvvf);
+    to_float(s, oo, c.Foo, c.Foof);
+    to_float(s, oo * v * o, c.Wvo2, c.Wvo2f);
     to_float(s, oovv, c.T, c.T32);
     PNO_HIP(hipGetLastError());
   }
@@ -724,13 +776,16 @@ int64_t bf16_ring_floats(const Context& c, int precision, int64_t nb) {
 
 // bfloat16 values of fa staging that the other BF16 products of sigma_rest take for nb vectors
 // (0 when they run in another precision): R2^T rows (hole ladder), then R2 rows (X_klij), then
-// Xh rows; U(R)_ia rows (M1); B'_vo, M1 and R1 rows (DF and R1 ring terms)
+// Xh rows; U(R)_ia rows (M1); B'_vo, M1 and R1 rows (DF and R1 ring terms); U(R) rows (Ftv);
+// the operands of the Fock-type products
 int64_t bf16_rest_values(const Context& c, int precision, int64_t nb) {
   if (precision != PNOEOM_BF16 || !c.bf_rest) return 0;
   const int64_t oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, ov = c.ov();
   const int64_t hole = std::max({vv * c.ldoo, oo * c.ldvv, oo * c.ldoo});
   const int64_t df = 2 * ov * c.ldq + (c.Yrb.p ? (int64_t)c.o * c.ldv : 0);
-  return nb * std::max({hole, ov * c.ldov, df});
+  // Fock-type block: R2, Fto and R1 in FP32, then R2 and Ftv rows in bfloat16
+  const int64_t fock = 2 * (c.oovv() + oo + ov + 4) + (oo + 1) * c.v * c.ldv;
+  return nb * std::max({hole, ov * c.ldov, df, (int64_t)c.v * c.ldg, fock});
 }
 
 // device memory of the per-vector work arrays of sigma_rest (bytes per vector)
@@ -1250,36 +1305,74 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   // ---------------------------------------------------------------- Fock-type terms in [i][j][a][b]
   // Ftv[q][a][b] = -sum_(i,j) sum_c U(R)[q][i][j][a][c] Gq[(i,j,c)][b]: per vector one product
   // summed over the o^2 pair blocks (v x v times v x v), rows of U(R) read in place
-  for (int q = 0; q < nb; ++q)
-    gmb(s, false, false, v, v, v, -1.0, w.UR + q * oovv, v, vv, c.Gq, v, vv, 0.0, w.Ftv + q * vv, v, 0, oo, true);
+  if (bfr && c.Gqb.p) {
+    // BF16 scope 1: one bfloat16 product per vector, U(R) rows as [a][(k,l,d)] staged in fa
+    uint16_t* ub = reinterpret_cast<uint16_t*>((float*)w.fa);
+    hipLaunchKernelGGL(pair_rows_bf16_kernel, dim3(grid1(nb * v * c.ldg)), dim3(256), 0, s, (int64_t)nb, oo,
+                       (int64_t)v, (const double*)w.UR, ub, c.ldg);
+    PNO_HIP(hipGetLastError());
+    float* ftv32 = w.fc;
+    for (int q = 0; q < nb; ++q)
+      bgemm(v, v, c.ldg, -1.f, ub + q * v * c.ldg, c.Gqb, 0.f, ftv32 + q * vv, v);
+    to_double(s, nb * vv, ftv32, w.Ftv, 0.0);
+  } else {
+    for (int q = 0; q < nb; ++q)
+      gmb(s, false, false, v, v, v, -1.0, w.UR + q * oovv, v, vv, c.Gq, v, vv, 0.0, w.Ftv + q * vv, v, 0, oo,
+          true);
+  }
   axpby(s, nb * vv, 1.0, w.fp_vv, 1.0, w.Ftv);
-  if (bfr && c.Fvvf.p && c.T32.p) {
-    // BF16 scope 1: R Fvv^T + T Ftv^T on FP32 MFMA (operands staged in fa, result in fc)
+  gmb(s, false, true, o, o, ov * v, 1.0, c.g2, ov * v, 0, w.UR, ov * v, oovv, 0.0, w.Fto, o, oo, nb);
+  axpby(s, nb * oo, 1.0, w.fp_oo, 1.0, w.Fto);
+  // Zp[q][i][j][a][b] = sum_c R_ij^ac Fvv[b][c] - sum_k Foo[k][j] R_ik^ab + sum_c T_ij^ac Ftv[b][c]
+  //                   - sum_k Fto[k][j] T_ik^ab - sum_k r_k^a Wvo2[(i,j,b)][k]
+  // (the last one is -P[ sum_k r_k^a Wvo_kbij ] before the P symmetrisation of the assembly)
+  if (bfr && c.Fvob.p && c.Wvo2f.p && c.T32.p) {
+    // BF16 scope 1: R (Fvv - diag)^T and T Ftv^T on bfloat16 MFMA, the three products with
+    // K = o on FP32 MFMA, all into fc (operands staged in fa); the diagonal part of R Fvv^T is
+    // added exactly in the conversion to FP64
     float* r2f = w.fa;
-    float* ftf = w.fa + nb * oovv;
+    float* fof = r2f + nb * oovv;
+    float* r1f = fof + nb * oo;
+    const int64_t boff = (nb * (oovv + oo + ov) + 3) / 4 * 4;  // floats: bfloat16 rows 16-byte aligned
+    uint16_t* r2b = reinterpret_cast<uint16_t*>((float*)w.fa + boff);
+    uint16_t* ftb = r2b + nb * oo * v * c.ldv;
     to_float(s, nb * oovv, R2, r2f);
-    to_float(s, nb * vv, w.Ftv, ftf);
-    GemmDesc<float> d;
-    d.tb = true; d.M = (int64_t)nb * oo * v; d.N = v; d.K = v; d.alpha = 1.f; d.beta = 0.f;
-    d.A = r2f; d.lda = v; d.B = c.Fvvf; d.ldb = v; d.C = w.fc; d.ldc = v;
-    gemm(d, s);
-    d.M = oo * v; d.beta = 1.f; d.A = c.T32; d.sA = 0; d.B = ftf; d.sB = vv; d.sC = oovv; d.batch = nb;
-    gemm(d, s);
-    to_double(s, nb * oovv, w.fc, w.Zp, 0.0);
+    to_float(s, nb * oo, w.Fto, fof);
+    for (int q = 0; q < nb; ++q) to_float(s, ov, r1 + q * stride1, r1f + q * ov);
+    rows_bf16(nb * oo * v, v, R2, v, r2b, c.ldv);
+    rows_bf16(nb * v, v, w.Ftv, v, ftb, c.ldv);
+    bgemm(nb * oo * v, v, c.ldv, 1.f, r2b, c.Fvob, 0.f, w.fc, v);
+    for (int q = 0; q < nb; ++q) bgemm(oo * v, v, c.ldv, 1.f, c.Tvb, ftb + q * v * c.ldv, 1.f, w.fc + q * oovv, v);
+    GemmDesc<float> e;  // - Foo^T R, batched over (q, i)
+    e.ta = true; e.M = o; e.N = vv; e.K = o; e.alpha = -1.f; e.beta = 1.f; e.A = c.Foof; e.lda = o; e.sA = 0;
+    e.B = r2f; e.ldb = vv; e.sB = o * vv; e.C = w.fc; e.ldc = vv; e.sC = o * vv; e.batch = nbo;
+    gemm(e, s);
+    for (int q = 0; q < nb; ++q) {
+      GemmDesc<float> f;  // - Fto[q]^T T, batched over i
+      f.ta = true; f.M = o; f.N = vv; f.K = o; f.alpha = -1.f; f.beta = 1.f; f.A = fof + q * oo; f.lda = o;
+      f.sA = 0; f.B = c.T32; f.ldb = vv; f.sB = o * vv; f.C = w.fc + q * oovv; f.ldc = vv; f.sC = o * vv;
+      f.batch = o;
+      gemm(f, s);
+      GemmDesc<float> g;  // - r1[q]^T Wvo2_ij^T, batched over the pairs
+      g.ta = true; g.tb = true; g.M = v; g.N = v; g.K = o; g.alpha = -1.f; g.beta = 1.f; g.A = r1f + q * ov;
+      g.lda = v; g.sA = 0; g.B = c.Wvo2f; g.ldb = o; g.sB = (int64_t)v * o; g.C = w.fc + q * oovv; g.ldc = v;
+      g.sC = vv; g.batch = oo;
+      gemm(g, s);
+    }
+    hipLaunchKernelGGL(zp_finish_kernel, dim3(grid1(nb * oovv)), dim3(256), 0, s, nb * oovv, (int64_t)v,
+                       (const float*)w.fc, R2, (const double*)c.Fvvd, (double*)w.Zp);
+    PNO_HIP(hipGetLastError());
   } else {
     gm(s, false, true, (int64_t)nb * oo * v, v, v, 1.0, R2, v, c.Fvv, v, 0.0, w.Zp, v);
     gmb(s, false, true, oo * v, v, v, 1.0, c.T, v, 0, w.Ftv, v, vv, 1.0, w.Zp, v, oovv, nb);
+    gmb(s, true, false, o, vv, o, -1.0, c.Foo, o, 0, R2, vv, o * vv, 1.0, w.Zp, vv, o * vv, nbo);
+    for (int q = 0; q < nb; ++q)
+      gmb(s, true, false, o, vv, o, -1.0, w.Fto + q * oo, o, 0, c.T, vv, o * vv, 1.0, w.Zp + q * oovv, vv, o * vv,
+          o);
+    for (int q = 0; q < nb; ++q)
+      gmb(s, true, true, v, v, o, -1.0, r1 + q * stride1, v, 0, c.Wvo2, o, (int64_t)v * o, 1.0, w.Zp + q * oovv, v,
+          vv, oo);
   }
-  gmb(s, true, false, o, vv, o, -1.0, c.Foo, o, 0, R2, vv, o * vv, 1.0, w.Zp, vv, o * vv, nbo);
-  gmb(s, false, true, o, o, ov * v, 1.0, c.g2, ov * v, 0, w.UR, ov * v, oovv, 0.0, w.Fto, o, oo, nb);
-  axpby(s, nb * oo, 1.0, w.fp_oo, 1.0, w.Fto);
-  for (int q = 0; q < nb; ++q)
-    gmb(s, true, false, o, vv, o, -1.0, w.Fto + q * oo, o, 0, c.T, vv, o * vv, 1.0, w.Zp + q * oovv, vv, o * vv, o);
-  // -P[ sum_k r_k^a Wvo_kbij ]: Zp[q][(i,j)][a][b] -= sum_k r1[q][k][a] Wvo2[(i,j,b)][k], one
-  // product per pair and vector (the P symmetrisation is the assembly's)
-  for (int q = 0; q < nb; ++q)
-    gmb(s, true, true, v, v, o, -1.0, r1 + q * stride1, v, 0, c.Wvo2, o, (int64_t)v * o, 1.0, w.Zp + q * oovv, v,
-        vv, oo);
 
   {
     const unsigned ntb = (unsigned)((v + kAsmTile - 1) / kAsmTile);
@@ -1514,7 +1607,7 @@ void ladder_apply_noalloc(Context& c, int nmat, const double* X, double* Y, int 
     hipLaunchKernelGGL((ladder_pack_kernel<uint16_t>), dim3(grid1(tot)), dim3(256), 0, s, 1, (int)v, nmat, X,
                        v * v, (uint16_t*)Sb, lds, (uint16_t*)Ab, lda, (const int*)nullptr, (int64_t)1);
     GemmBf16Desc d;
-    d.M = nmat; d.N = vp; d.K = c.ldpb; d.tag = 1;
+    d.M = nmat; d.N = vp; d.K = c.ldpb; d.tag = 1; d.no_split = true;
     d.A = (const uint16_t*)Sb; d.lda = c.ldpb; d.B = c.Wpb; d.ldb = c.ldpb; d.C = (float*)Pb; d.ldc = vp;
     gemm_bf16(d, s);
     d.N = vm; d.K = c.ldmb; d.A = (const uint16_t*)Ab; d.lda = c.ldmb; d.B = c.Wmb; d.ldb = c.ldmb;

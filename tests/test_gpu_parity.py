@@ -312,6 +312,32 @@ def test_davidson_c1_fp64_matches_dense_eig():
     assert np.max(np.abs(r["omega"] - np.array(gold["dense_eig"][:3]))) <= 1e-8
 
 
+def test_davidson_config2_matches_oracle_golden():
+    """Full config-2 size (o=20, v=150, naux=450), FP64 canonical, 6 roots with 4 extra tracked
+    Ritz pairs: every root within 1e-8 Eh of the oracle's Davidson (tests/golden/c2.json,
+    written by tests/golden/make_golden.py with residual norms below 1e-7), and the BF16-mixed
+    run with FP64 refinement within 1e-6 Eh of it."""
+    path = os.path.join(GOLD, "c2.json")
+    if not os.path.exists(path):
+        pytest.skip("config-2 oracle Davidson not generated")
+    print("[davidson c2] fp64", flush=True)
+    gold = np.array(json.load(open(path))["davidson"])
+    s = config_system(2)
+    c2 = CONFIGS[2]
+    ctx = _ctx(s, precision=2)
+    r = ctx.davidson(c2["nroots"], tol_e=1e-10, tol_r=1e-6, max_sub=c2.get("max_sub", 60), nextra=c2["nextra"])
+    err = np.abs(r["omega"] - gold[:c2["nroots"]])
+    print(f"[davidson c2] fp64 per-root error {err}", flush=True)
+    assert np.max(err) <= 1e-8
+    print("[davidson c2] bf16 mixed + fp64 refinement", flush=True)
+    r = ctx.davidson(c2["nroots"], precision=2, tol_e=1e-8, tol_r=1e-5, max_sub=c2.get("max_sub", 60),
+                     nextra=c2["nextra"], refine_fp64=True)
+    err = np.abs(r["omega"] - gold[:c2["nroots"]])
+    print(f"[davidson c2] bf16 mixed per-root error {err}", flush=True)
+    assert np.max(err) <= 1e-6
+    ctx.close()
+
+
 def test_davidson_c1_fp32_mixed():
     print("[davidson c1 fp32]", flush=True)
     gold = json.load(open(os.path.join(GOLD, "c1.json")))

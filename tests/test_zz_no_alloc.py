@@ -4,7 +4,8 @@ pnoeom_ladder_apply, through the C ABI.
 Both run the same packing and MFMA kernels; the allocation-free one never splits K,
 so FP64 and FP32 agree to the summation-order bounds of the ladder tests (FP64
 1e-12 of max|Y|; FP32 twice the FP32 bound (naux + v+ + 6) 2^-24 L elementwise)
-and BF16 (no split in either) bit for bit.  Each precision makes two calls in a row,
+and BF16 bit for bit (at these sizes, under 160 rows, both take the 128 x 128 bfloat16
+kernel, which never splits K).  Each precision makes two calls in a row,
 the second with fewer matrices, after calls of another precision have left other
 data in the shared scratch array.
 """
