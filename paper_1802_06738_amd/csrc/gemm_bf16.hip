@@ -234,7 +234,8 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1))) void ge
   }
   int64_t m0, n0;
   tile_origin(g, tile, m0, n0);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: LDS bases in scalar registers
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 31, lk = lane >> 5;
   const int drow = lane >> 3, dslot = lane & 7;
@@ -284,6 +285,23 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1))) void ge
 #pragma unroll
     for (int j = 0; j < FN; ++j) fb[set][j] = frag(bs, wn * WN + j * 32 + lr, 2 * st + lk);
   };
+  // direct loads q = 2p, 2p + 1 of the A tile and of the B tile
+  auto issue_part = [&](int64_t kt, int buf, int p) {
+    uint16_t* as = lds + buf * (TM + TN) * TK;
+    uint16_t* bs = as + TM * TK;
+    const int64_t k0 = kt * TK;
+#pragma unroll
+    for (int q = 2 * p; q < 2 * p + 2; ++q) {
+      __builtin_amdgcn_global_load_lds((const void*)(ga[q] + k0), (lds_void*)(as + (wave * NQA + q) * 8 * TK), 16, 0,
+                                       0);
+      __builtin_amdgcn_global_load_lds((const void*)(gb[q] + k0), (lds_void*)(bs + (wave * NQB + q) * 8 * TK), 16, 0,
+                                       0);
+    }
+  };
+  auto mma_row = [&](int set, int i) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[set][i], fb[set][j], acc[i][j], 0, 0, 0);
+  };
   auto mma = [&](int set) {
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -328,13 +346,23 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1))) void ge
     interleave();
     __builtin_amdgcn_s_waitcnt(0);  // tile kt + 1 has landed and tile kt's reads are done
     __syncthreads();
-    if (kt + 2 < ke) issue(kt + 2, cur);
-    // first fragments of the next K-tile (after the last one: read but unused) under step 3
+    // first fragments of the next K-tile (after the last one: read but unused), then step 3's
+    // MFMAs row by row, each row beside a quarter of the direct loads of tile kt + 2 into the
+    // buffer just freed (so that the load issue does not hold the matrix cores); in the last
+    // two K-tiles the loads repeat the last K-tile (unused), which keeps them in the same
+    // block as the MFMAs
     const uint16_t* an = lds + (cur ^ 1) * (TM + TN) * TK;
     load_frags(0, an, an + TM * TK, 0);
-    mma(1);
-    interleave();
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t kn = kt + 2 < ke ? kt + 2 : ke - 1;
+#pragma unroll
+    for (int p = 0; p < FM; ++p) {
+      issue_part(kn, cur, p);
+      mma_row(1, p);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
+  __builtin_amdgcn_s_waitcnt(0);  // no direct load is left in flight
 
   store_tile(g, acc, m0, n0, wm, wn, lr, lk);
 }
