@@ -7,7 +7,7 @@ namespace pnoeom {
 
 // Per-vector workspace of the canonical sigma (all FP64, sized once).
 struct SigmaWork {
-  DBuf<double> Bp, hp, Jp, Kp, fp, dp, fp_ov, fp_vv, fp_oo;
+  DBuf<double> Bp, Bc, hp, Jp, Kp, fp, dp, fp_ov, fp_vv, fp_oo;  // (Bc: occupied columns of B')
   DBuf<double> BvopT, BoopT, BvvpT;
   DBuf<double> R2c, Ria, UiaR, UR;  // (R2c: R2 compacted, only for strided input)
   // ZZ[(q,i,a)][Ziajb row | Z3 row]; RE[(q,i,a)][R^s row | E_X row] (the stacked left operand
@@ -21,7 +21,7 @@ struct SigmaWork {
   // FP32 staging for the mixed-precision contractions
   DBuf<float> fa, fc;
   void release() {
-    for (DBuf<double>* b : {&Bp, &hp, &Jp, &Kp, &fp, &dp, &fp_ov, &fp_vv, &fp_oo, &BvopT, &BoopT, &BvvpT, &R2c, &Ria,
+    for (DBuf<double>* b : {&Bp, &Bc, &hp, &Jp, &Kp, &fp, &dp, &fp_ov, &fp_vv, &fp_oo, &BvopT, &BoopT, &BvvpT, &R2c, &Ria,
                             &UiaR, &UR, &ZZ, &RE, &Zp, &Xh, &O4p,
                             &OOVVp, &M1, &R1c, &Ftv, &Fto, &LadAll, &Sp, &Am, &SigP, &SigM})
       b->release();

@@ -56,6 +56,17 @@ void perm(hipStream_t s, const double* in, int64_t a, int64_t b, int64_t c, int6
   permute_c(s, dims, pp, alpha, in, beta, out);
 }
 
+// d[q] = sum_{k < o} X[q sq + k ld + k]: the occupied-block trace of each fitting function's matrix
+__global__ void trace_rows_kernel(int naux, int64_t ld, int64_t sq, int o, const double* __restrict__ X,
+                                  double* __restrict__ d) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= naux) return;
+  const double* b = X + (int64_t)q * sq;
+  double acc = 0.0;
+  for (int k = 0; k < o; ++k) acc += b[(int64_t)k * ld + k];
+  d[q] = acc;
+}
+
 __global__ void trace_occ_kernel(int naux, int nmo, int o, const double* __restrict__ B, double* __restrict__ d) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= naux) return;
@@ -794,7 +805,8 @@ int64_t rest_bytes_per_vector(const Context& c, bool f32, bool r2c) {
   // 9 o^2 v^2 arrays (Ria, UiaR, UR, ZZ x 2, RE x 2, Zp, OOVVp), 7 when the E_X products go
   // through Yr / Zr (RE holds R^s only, no OOVVp), + R2c for strided input
   const int64_t narr = (c.ring_y ? 7 : 9) + (r2c ? 1 : 0);
-  int64_t nd = narr * oovv + (ov + oo + vv) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv + oo + vv + oo +
+  int64_t nd = narr * oovv + (ov + oo + (c.ring_y ? 0 : vv)) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv +
+               oo + vv + oo +
                (c.ring_y ? ov : 0);
   int64_t bytes = nd * (int64_t)sizeof(double);
   if (f32)  // fa and fc (two oovv each; fa larger when it stages the BF16 operands)
@@ -827,7 +839,7 @@ int64_t sigma_bytes_per_vector(const Context& c, int precision, bool pno) {
 int64_t sigma_held_bytes(const Context& c) {
   const SigmaWork& w = c.sw;
   int64_t b = 0;
-  for (const DBuf<double>* x : {&w.Bp, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT,
+  for (const DBuf<double>* x : {&w.Bp, &w.Bc, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT,
                                 &w.BoopT, &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.UR, &w.ZZ,
                                 &w.RE, &w.Zp, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.R1c, &w.Ftv, &w.Fto,
                                 &w.LadAll, &w.Sp, &w.Am, &w.SigP, &w.SigM, &c.pno.r1, &c.pno.r2, &c.pno.s1,
@@ -859,11 +871,15 @@ void alloc_sigma_work(Context& c, int precision, int nb, bool need_r2c) {
   const int64_t n2 = (int64_t)c.nmo * c.nmo, ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v;
   const int64_t oovv = c.oovv(), B = nb;
   // one-vector scratch of the R1 one-index transformation
-  grow(w.Bp, (int64_t)c.naux * n2);
+  if (c.ring_y)
+    grow(w.Bc, (int64_t)c.naux * c.nmo * c.o);
+  else
+    grow(w.Bp, (int64_t)c.naux * n2);
   grow(w.hp, n2); grow(w.Jp, n2); grow(w.Kp, n2); grow(w.fp, n2); grow(w.dp, c.naux);
   // per-vector arrays, [nb][...]
   grow(w.fp_ov, B * ov); grow(w.fp_vv, B * vv); grow(w.fp_oo, B * oo);
-  grow(w.BvopT, B * ov * c.naux); grow(w.BoopT, B * oo * c.naux); grow(w.BvvpT, B * vv * c.naux);
+  grow(w.BvopT, B * ov * c.naux); grow(w.BoopT, B * oo * c.naux);
+  if (!c.ring_y) grow(w.BvvpT, B * vv * c.naux);
   if (need_r2c) grow(w.R2c, B * oovv);
   grow(w.Ria, B * oovv); grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
   grow(w.ZZ, 2 * B * oovv); grow(w.RE, (c.ring_y ? 1 : 2) * B * oovv);
@@ -992,7 +1008,38 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   alloc_sigma_work(c, precision, nb, stride2 != oovv);
 
   // ---------------------------------------------------------------- R1: one-index transformed factors, per vector
-  for (int q = 0; q < nb; ++q) {
+  // B'^Q = -r^T B~^Q (virtual rows) + B~^Q r^T (occupied columns) has a zero occupied-virtual
+  // block, and with the T-only ring intermediates only its occupied columns are read: the
+  // oo and vo blocks Bc[Q][p][i] = B'^Q_{p,i} (nmo x o), the Coulomb part through the one-index
+  // transformation of D = sum_Q dt_Q B~^Q (c.J) and the exchange part from Bc (without them the
+  // whole B' is formed for its vv block)
+  for (int q = 0; q < nb && c.ring_y; ++q) {
+    const double* r1q = r1 + q * stride1;
+    const int64_t sc = (int64_t)nmo * o;
+    gmb(s, false, true, nmo, o, v, 1.0, c.Bt + o, nmo, n2, r1q, v, 0, 0.0, w.Bc, o, sc, naux);
+    gmb(s, true, false, v, o, o, -1.0, r1q, v, 0, c.Bt, nmo, n2, 1.0, w.Bc + (int64_t)o * o, o, sc, naux);
+    fill(s, n2, 0.0, w.hp);
+    gm(s, true, false, v, nmo, o, -1.0, r1q, v, c.hd, nmo, 1.0, w.hp + (int64_t)o * nmo, nmo);
+    gm(s, false, true, nmo, o, v, 1.0, c.hd + o, nmo, r1q, v, 1.0, w.hp, nmo);
+    hipLaunchKernelGGL(trace_rows_kernel, dim3((naux + 255) / 256), dim3(256), 0, s, naux, (int64_t)o, sc, o,
+                       (const double*)w.Bc, (double*)w.dp);
+    // J' = sum_Q dp_Q B~^Q + (one-index transformed D);  K' = sum_Q Bc^Q B~^Q[occ, :] + B~^Q[:, occ] Bc^Q[occ, :]
+    gm(s, false, false, 1, n2, naux, 1.0, w.dp, naux, c.Bt, n2, 0.0, w.Jp, n2);
+    gm(s, true, false, v, nmo, o, -1.0, r1q, v, c.J, nmo, 1.0, w.Jp + (int64_t)o * nmo, nmo);
+    gm(s, false, true, nmo, o, v, 1.0, c.J + o, nmo, r1q, v, 1.0, w.Jp, nmo);
+    gmb(s, false, false, nmo, nmo, o, 1.0, w.Bc, o, sc, c.Bt, nmo, n2, 0.0, w.Kp, nmo, 0, naux, true);
+    gmb(s, false, false, nmo, o, o, 1.0, c.Bt, nmo, n2, w.Bc, o, sc, 1.0, w.Kp, nmo, 0, naux, true);
+    PNO_HIP(hipMemcpyAsync(w.fp, w.hp, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    axpby(s, n2, 2.0, w.Jp, 1.0, w.fp);
+    axpby(s, n2, -1.0, w.Kp, 1.0, w.fp);
+    ext(s, o, v, 1, 1, nmo, 1, 0, 0, w.fp + o, w.fp_ov + q * ov);
+    ext(s, v, v, 1, 1, nmo, 1, 0, 0, w.fp + (int64_t)o * nmo + o, w.fp_vv + q * vv);
+    ext(s, o, o, 1, 1, nmo, 1, 0, 0, w.fp, w.fp_oo + q * oo);
+    ext(s, o, v, naux, 1, 1, o, sc, 0, w.Bc + (int64_t)o * o, w.BvopT + q * ovn);  // [(i,a)][Q] = B'^Q_{o+a,i}
+    ext(s, o, o, naux, 1, o, 1, sc, 0, w.Bc, w.BoopT + q * oon);                  // [(j,i)][Q] = B'^Q_{j,i}
+    ext(s, o, v, 1, 1, 1, nmo, 0, 0, w.fp + (int64_t)o * nmo, s1 + q * stride1);  // f'_ai
+  }
+  for (int q = 0; q < nb && !c.ring_y; ++q) {
     const double* r1q = r1 + q * stride1;
     fill(s, (int64_t)naux * n2, 0.0, w.Bp);
     gmb(s, true, false, v, nmo, o, -1.0, r1q, v, 0, c.Bt, nmo, n2, 1.0, w.Bp + (int64_t)o * nmo, nmo, n2, naux);
@@ -1683,7 +1730,7 @@ uint64_t sigma_signature(Context& c, hipStream_t s) {
     h ^= (uint64_t)n * 0x100000001b3ull;
   };
   SigmaWork& w = c.sw;
-  for (DBuf<double>* b : {&w.Bp, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT, &w.BoopT,
+  for (DBuf<double>* b : {&w.Bp, &w.Bc, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT, &w.BoopT,
                           &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.UR, &w.ZZ,
                           &w.RE, &w.Zp, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.R1c, &w.Ftv, &w.Fto, &w.LadAll, &w.Sp,
                           &w.Am, &w.SigP, &w.SigM, &c.pno.Tw, &c.pno.r1, &c.pno.r2, &c.pno.s1, &c.pno.s2, &c.gin,
