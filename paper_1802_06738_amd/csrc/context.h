@@ -18,6 +18,8 @@ struct SigmaWork {
   DBuf<double> LadAll, Sp, Am, SigP, SigM;  // batched packed ladder
   DBuf<float> Spf, Amf, SigPf, SigMf;
   DBuf<uint16_t> Spb, Amb;  // bfloat16 bits, rows padded to the W+/- column padding
+  // BF16 fused ring product: left operand rows [-R^s | R_ia | B'_vo | M1/2] (kfold values)
+  DBuf<uint16_t> RAb;
   // FP32 staging for the mixed-precision contractions
   DBuf<float> fa, fc;
   void release() {
@@ -27,6 +29,7 @@ struct SigmaWork {
       b->release();
     for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fc}) b->release();
     Spb.release();
+    RAb.release();
     Amb.release();
   }
 };

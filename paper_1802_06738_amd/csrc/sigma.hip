@@ -781,8 +781,15 @@ void grow(DBuf<T>& b, int64_t n) {
 // (nb ov rows of ring_passes x ldr bfloat16 values); 0 when the ring is not run in BF16
 int64_t bf16_ring_floats(const Context& c, int precision, int64_t nb) {
   if (precision != PNOEOM_BF16 || !c.ring_y || !c.DXb.p) return 0;
-  if (c.RBb.p) return (nb * c.ov() * c.kfold + 1) / 2;  // one left operand of nb ov rows of kfold
+  if (c.RBb.p) return 0;  // the fused product's left operand has its own buffer (RAb)
   return nb * c.ov() * c.ring_passes * c.ldr;  // two left operands of nb ov rows
+}
+
+// BF16 scope 1, one pass: the ring products fused with the DF ring terms, their left operand
+// rows written by r2_layouts_kernel (R^s, R_ia) and the R1 part (B'_vo, M1) into RAb, and
+// neither R_ia nor R^s kept in FP64
+bool ring_fold(const Context& c, int precision) {
+  return precision == PNOEOM_BF16 && c.bf_rest && c.ring_y && c.RBb.p && c.DXb.p && c.ring_passes == 1;
 }
 
 // bfloat16 values of fa staging that the other BF16 products of sigma_rest take for nb vectors
@@ -800,15 +807,19 @@ int64_t bf16_rest_values(const Context& c, int precision, int64_t nb) {
 }
 
 // device memory of the per-vector work arrays of sigma_rest (bytes per vector)
-int64_t rest_bytes_per_vector(const Context& c, bool f32, bool r2c) {
+int64_t rest_bytes_per_vector(const Context& c, int precision, bool r2c) {
+  const bool f32 = precision != PNOEOM_FP64;
+  const bool fold = ring_fold(c, precision);
   const int64_t ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, oovv = c.oovv();
   // 9 o^2 v^2 arrays (Ria, UiaR, UR, ZZ x 2, RE x 2, Zp, OOVVp), 7 when the E_X products go
-  // through Yr / Zr (RE holds R^s only, no OOVVp), + R2c for strided input
-  const int64_t narr = (c.ring_y ? 7 : 9) + (r2c ? 1 : 0);
+  // through Yr / Zr (RE holds R^s only, no OOVVp), 5 with the fused BF16 ring product (no Ria,
+  // no RE: their bfloat16 rows go to RAb), + R2c for strided input
+  const int64_t narr = (c.ring_y ? (fold ? 5 : 7) : 9) + (r2c ? 1 : 0);
   int64_t nd = narr * oovv + (ov + oo + (c.ring_y ? 0 : vv)) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv +
                oo + vv + oo +
                (c.ring_y ? ov : 0);
   int64_t bytes = nd * (int64_t)sizeof(double);
+  if (fold) bytes += ov * c.kfold * (int64_t)sizeof(uint16_t);
   if (f32)  // fa and fc (two oovv each; fa larger when it stages the BF16 operands)
     bytes += (2 * oovv + std::max({2 * oovv, bf16_ring_floats(c, PNOEOM_BF16, 1) + 1,
                                    bf16_rest_values(c, PNOEOM_BF16, 1) / 2 + 1})) *
@@ -824,9 +835,8 @@ int64_t rest_bytes_per_vector(const Context& c, bool f32, bool r2c) {
 int64_t sigma_bytes_per_vector(const Context& c, int precision, bool pno) {
   const int64_t npair = (int64_t)c.o * (c.o + 1) / 2, vp = (int64_t)c.v * (c.v + 1) / 2;
   const int64_t vm = std::max<int64_t>((int64_t)c.v * (c.v - 1) / 2, 1);
-  const bool f32 = precision != PNOEOM_FP64;
   // (the PNO path expands its vectors with the singles and doubles apart: no R2c)
-  int64_t b = rest_bytes_per_vector(c, f32, !pno) + c.oovv() * (int64_t)sizeof(double);  // + LadAll
+  int64_t b = rest_bytes_per_vector(c, precision, !pno) + c.oovv() * (int64_t)sizeof(double);  // + LadAll
   const int64_t in_elt = precision == PNOEOM_FP64 ? 8 : precision == PNOEOM_FP32 ? 4 : 2;
   const int64_t out_elt = precision == PNOEOM_FP64 ? 8 : 4;
   const int64_t kp = precision == PNOEOM_BF16 ? c.ldpb + c.ldmb : vp + vm;
@@ -846,7 +856,7 @@ int64_t sigma_held_bytes(const Context& c) {
                                 &c.pno.s2})
     b += (int64_t)x->n * 8;
   for (const DBuf<float>* x : {&w.Spf, &w.Amf, &w.SigPf, &w.SigMf, &w.fa, &w.fc}) b += (int64_t)x->n * 4;
-  b += (int64_t)(w.Spb.n + w.Amb.n) * 2;
+  b += (int64_t)(w.Spb.n + w.Amb.n + w.RAb.n) * 2;
   return b;
 }
 
@@ -880,9 +890,23 @@ void alloc_sigma_work(Context& c, int precision, int nb, bool need_r2c) {
   grow(w.fp_ov, B * ov); grow(w.fp_vv, B * vv); grow(w.fp_oo, B * oo);
   grow(w.BvopT, B * ov * c.naux); grow(w.BoopT, B * oo * c.naux);
   if (!c.ring_y) grow(w.BvvpT, B * vv * c.naux);
-  if (need_r2c) grow(w.R2c, B * oovv);
-  grow(w.Ria, B * oovv); grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
-  grow(w.ZZ, 2 * B * oovv); grow(w.RE, (c.ring_y ? 1 : 2) * B * oovv);
+  if (need_r2c)
+    grow(w.R2c, B * oovv);
+  else
+    w.R2c.release();
+  grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
+  grow(w.ZZ, 2 * B * oovv);
+  // (the chunk size counts what the workspaces hold as free: an array this call does not use
+  // is released rather than kept)
+  if (ring_fold(c, precision)) {
+    w.Ria.release();
+    w.RE.release();
+    grow(w.RAb, B * c.ov() * c.kfold);
+  } else {
+    w.RAb.release();
+    grow(w.Ria, B * oovv);
+    grow(w.RE, (c.ring_y ? 1 : 2) * B * oovv);
+  }
   grow(w.Zp, B * oovv);
   if (c.ring_y)
     grow(w.R1c, B * ov);
@@ -956,10 +980,13 @@ __global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, co
 //   Ria[(q,i,a)][(j,b)] = R_ij^ab,   UiaR[(q,i,a)][(j,b)] = UR[q][i][j][a][b] = 2 R_ij^ab - R_ij^ba,
 //   URp[q][i][j][a][b] = 2 R_ij^ba - R_ij^ab,   R^s[(q,i,b)][(j,a)] = R_ij^ab (rows of ldre in RE)
 // every store runs along a row segment of 32 consecutive values (R^s through the LDS transpose)
+//   (fused BF16 ring product: -R^s and R_ia instead as bfloat16 into the rows of RAb, the
+//    first two blocks of ldr values of rows of ldra, and no FP64 Ria / RE)
 __global__ __launch_bounds__(256) void r2_layouts_kernel(int o, int v, const double* __restrict__ R2,
                                                          double* __restrict__ Ria, double* __restrict__ UiaR,
                                                          double* __restrict__ UR, double* __restrict__ URp,
-                                                         double* __restrict__ RE, int64_t ldre) {
+                                                         double* __restrict__ RE, int64_t ldre,
+                                                         uint16_t* __restrict__ RAb, int64_t ldra, int64_t ldr) {
   __shared__ double t[kAsmTile][kAsmTile + 1];  // t[a - a0][b - b0] = R_ij^ab
   __shared__ double u[kAsmTile][kAsmTile + 1];  // u[b - b0][a - a0] = R_ij^ba
   const int64_t V = v, O = o, vv = V * V, n = O * O * vv;
@@ -982,7 +1009,10 @@ __global__ __launch_bounds__(256) void r2_layouts_kernel(int o, int v, const dou
       const double x = t[r][tx], y = u[tx][r];
       const int64_t e = base + a * V + b;
       const int64_t f = q * n + ((i * V + a) * O + j) * V + b;
-      Ria[f] = x;
+      if (RAb)
+        RAb[((q * O + i) * V + a) * ldra + ldr + j * V + b] = bf16_bits(x);
+      else
+        Ria[f] = x;
       UiaR[f] = 2.0 * x - y;
       UR[e] = 2.0 * x - y;
       URp[e] = 2.0 * y - x;
@@ -990,8 +1020,20 @@ __global__ __launch_bounds__(256) void r2_layouts_kernel(int o, int v, const dou
   }
   for (int r = ty; r < kAsmTile; r += 256 / kAsmTile) {
     const int64_t b = b0 + r, a = a0 + tx;
-    if (a < V && b < V) RE[((q * O + i) * V + b) * ldre + j * V + a] = t[tx][r];
+    if (a < V && b < V) {
+      if (RAb)
+        RAb[((q * O + i) * V + b) * ldra + j * V + a] = bf16_bits(-t[tx][r]);
+      else
+        RE[((q * O + i) * V + b) * ldre + j * V + a] = t[tx][r];
+    }
   }
+}
+
+// out[r ld + c] = 0 for rows r < rows and columns c0 <= c < c1 (padding of bfloat16 rows)
+__global__ void zero_cols_kernel(int64_t rows, int64_t ld, int64_t c0, int64_t c1, uint16_t* __restrict__ out) {
+  const int64_t w = c1 - c0, total = rows * w;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    out[(e / w) * ld + c0 + e % w] = 0;
 }
 
 // every sigma term except the particle ladder, for nb vectors at once; the caller
@@ -1082,12 +1124,23 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   // Ria, R^s (left half of the rows of RE), UiaR = 2 R_ia - R^s, UR and URp (U(R) with a <-> b,
   // for sigma1; kept in Zp, which is written later) in one pass over R2
   double* URp = w.Zp;
+  const bool fold = ring_fold(c, precision);
   {
     const unsigned ntb = (unsigned)((v + kAsmTile - 1) / kAsmTile);
     PNO_CHECK((int64_t)o * o <= 65535 && nb <= 65535, PNOEOM_EINVAL, "sigma: too many pairs or vectors per block");
+    uint16_t* rab = fold ? (uint16_t*)w.RAb : nullptr;
     hipLaunchKernelGGL(r2_layouts_kernel, dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb), dim3(256), 0, s, o, v,
-                       R2, (double*)w.Ria, (double*)w.UiaR, (double*)w.UR, URp, (double*)w.RE, ldre);
+                       R2, (double*)w.Ria, (double*)w.UiaR, (double*)w.UR, URp, (double*)w.RE, ldre, rab, c.kfold,
+                       c.ldr);
     PNO_HIP(hipGetLastError());
+    if (fold && c.ldr > ov) {  // padding of the -R^s and R_ia blocks of the rows
+      const int64_t rows = (int64_t)nb * ov;
+      hipLaunchKernelGGL(zero_cols_kernel, dim3(grid1(rows * (c.ldr - ov))), dim3(256), 0, s, rows, c.kfold, ov, c.ldr,
+                         rab);
+      hipLaunchKernelGGL(zero_cols_kernel, dim3(grid1(rows * (c.ldr - ov))), dim3(256), 0, s, rows, c.kfold,
+                         c.ldr + ov, 2 * c.ldr, rab);
+      PNO_HIP(hipGetLastError());
+    }
   }
 
   // ---------------------------------------------------------------- sigma1
@@ -1207,14 +1260,12 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   // half of ZZ's rows is one product with K = 2 ov + 2 naux, [-R^s | R_ia | B'_vo | M1 / 2]
   // times [Dr ; DX2 ; BYU ; YU], the right half -R^s Xr (the first ldr values of the same rows):
   // no partial result is written and read back
-  const bool fold = bf_ring && bfr && c.RBb.p && c.ring_passes == 1;
   uint16_t* ab1 = nullptr;
   uint16_t* ab2 = nullptr;
   const int64_t kr = c.ring_passes * c.ldr;
   if (fold) {
-    ab1 = reinterpret_cast<uint16_t*>((float*)w.fa);
-    bf16_rows(s, M, ov, w.RE, ldre, 1, ab1, c.ldr, c.kfold, 1, 0, -1.0);
-    bf16_rows(s, M, ov, w.Ria, ov, 1, ab1 + c.ldr, c.ldr, c.kfold);
+    // -R^s and R_ia are in RAb already (r2_layouts_kernel); the R1 part joins them
+    ab1 = w.RAb;
     bf16_rows(s, M, naux, w.BvopT, naux, 1, ab1 + 2 * c.ldr, c.ldq, c.kfold);
     bf16_rows(s, M, naux, w.M1, naux, 1, ab1 + 2 * c.ldr + c.ldq, c.ldq, c.kfold, 1, 0, 0.5);
   } else if (bf_ring) {
@@ -1292,9 +1343,9 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
       bgemm(nb * ov, ov, c.ldq, 0.5f, bm, c.YUb, 1.f, w.fc, ov2);
     }
     if (ybf) {
+      uint16_t* br = bm + nb * ov * c.ldq;
       // -sum_c R1[q][j][c] Yr[(a,c)][n] for all (q,j) x (a,n) at once: the rows (q,j,a) of the
       // ring block are the rows (q,j) of a [nb o][v 2 ov] matrix
-      uint16_t* br = bm + nb * ov * c.ldq;
       rows_bf16(nb * o, v, w.R1c, v, br, c.ldv);
       bgemm(nb * o, v * ov2, c.ldv, -1.f, br, c.Yrb, 1.f, w.fc, v * ov2);
     }
@@ -1738,6 +1789,7 @@ uint64_t sigma_signature(Context& c, hipStream_t s) {
     mix(b->p, b->n);
   for (DBuf<float>* b : {&w.Spf, &w.Amf, &w.SigPf, &w.SigMf, &w.fa, &w.fc}) mix(b->p, b->n);
   mix(w.Spb.p, w.Spb.n);
+  mix(w.RAb.p, w.RAb.n);
   mix(w.Amb.p, w.Amb.n);
   mix((const void*)(uintptr_t)gemm_workspace_signature(s), 0);
   return h;
