@@ -22,12 +22,13 @@ struct SigmaWork {
   DBuf<uint16_t> RAb;
   // FP32 staging for the mixed-precision contractions
   DBuf<float> fa, fc;
+  DBuf<float> fz;  // FP32 sum of the Zp terms (fused BF16 ring mode)
   void release() {
     for (DBuf<double>* b : {&Bp, &Bc, &hp, &Jp, &Kp, &fp, &dp, &fp_ov, &fp_vv, &fp_oo, &BvopT, &BoopT, &BvvpT, &R2c, &Ria,
                             &UiaR, &UR, &ZZ, &RE, &Zp, &Xh, &O4p,
                             &OOVVp, &M1, &R1c, &Ftv, &Fto, &LadAll, &Sp, &Am, &SigP, &SigM})
       b->release();
-    for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fc}) b->release();
+    for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fc, &fz}) b->release();
     Spb.release();
     RAb.release();
     Amb.release();

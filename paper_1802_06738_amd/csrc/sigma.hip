@@ -175,12 +175,12 @@ __global__ void offdiag_rows_bf16_kernel(int64_t n, const double* __restrict__ F
   }
 }
 
-// Zp[e] = acc[e] + R[e] d[e % v]: the FP32 sum of the Fock-type products plus the diagonal part
-// of R Fvv^T, in FP64
-__global__ void zp_finish_kernel(int64_t n, int64_t v, const float* __restrict__ acc, const double* __restrict__ R,
-                                 const double* __restrict__ d, double* __restrict__ Zp) {
+// acc[e] += R[e] d[e % v]: the diagonal part of R Fvv^T added to the FP32 sum of the Fock-type
+// products (the product itself in FP64, rounded once)
+__global__ void zp_finish_kernel(int64_t n, int64_t v, float* __restrict__ acc, const double* __restrict__ R,
+                                 const double* __restrict__ d) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-    Zp[e] = (double)acc[e] + R[e] * d[e % v];
+    acc[e] = (float)((double)acc[e] + R[e] * d[e % v]);
 }
 
 // out[q][a][(p, c)] = bf16(U[q][p][a][c]) for pairs p < npair (U: [nb][npair][v][v]), rows of
@@ -812,14 +812,14 @@ int64_t rest_bytes_per_vector(const Context& c, int precision, bool r2c) {
   const bool fold = ring_fold(c, precision);
   const int64_t ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, oovv = c.oovv();
   // 9 o^2 v^2 arrays (Ria, UiaR, UR, ZZ x 2, RE x 2, Zp, OOVVp), 7 when the E_X products go
-  // through Yr / Zr (RE holds R^s only, no OOVVp), 5 with the fused BF16 ring product (no Ria,
-  // no RE: their bfloat16 rows go to RAb), + R2c for strided input
-  const int64_t narr = (c.ring_y ? (fold ? 5 : 7) : 9) + (r2c ? 1 : 0);
+  // through Yr / Zr (RE holds R^s only, no OOVVp), 3 with the fused BF16 ring product (no Ria,
+  // no RE: their bfloat16 rows go to RAb; no ZZ: the ring block stays FP32), + R2c for strided input
+  const int64_t narr = (c.ring_y ? (fold ? 3 : 7) : 9) + (r2c ? 1 : 0);
   int64_t nd = narr * oovv + (ov + oo + (c.ring_y ? 0 : vv)) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv +
                oo + vv + oo +
                (c.ring_y ? ov : 0);
   int64_t bytes = nd * (int64_t)sizeof(double);
-  if (fold) bytes += ov * c.kfold * (int64_t)sizeof(uint16_t);
+  if (fold) bytes += ov * c.kfold * (int64_t)sizeof(uint16_t) + oovv * (int64_t)sizeof(float);  // RAb, fz
   if (f32)  // fa and fc (two oovv each; fa larger when it stages the BF16 operands)
     bytes += (2 * oovv + std::max({2 * oovv, bf16_ring_floats(c, PNOEOM_BF16, 1) + 1,
                                    bf16_rest_values(c, PNOEOM_BF16, 1) / 2 + 1})) *
@@ -855,7 +855,7 @@ int64_t sigma_held_bytes(const Context& c) {
                                 &w.LadAll, &w.Sp, &w.Am, &w.SigP, &w.SigM, &c.pno.r1, &c.pno.r2, &c.pno.s1,
                                 &c.pno.s2})
     b += (int64_t)x->n * 8;
-  for (const DBuf<float>* x : {&w.Spf, &w.Amf, &w.SigPf, &w.SigMf, &w.fa, &w.fc}) b += (int64_t)x->n * 4;
+  for (const DBuf<float>* x : {&w.Spf, &w.Amf, &w.SigPf, &w.SigMf, &w.fa, &w.fc, &w.fz}) b += (int64_t)x->n * 4;
   b += (int64_t)(w.Spb.n + w.Amb.n + w.RAb.n) * 2;
   return b;
 }
@@ -895,17 +895,22 @@ void alloc_sigma_work(Context& c, int precision, int nb, bool need_r2c) {
   else
     w.R2c.release();
   grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
-  grow(w.ZZ, 2 * B * oovv);
   // (the chunk size counts what the workspaces hold as free: an array this call does not use
   // is released rather than kept)
+  // (the fused BF16 ring mode keeps the ring block and the Fock-type sum in FP32 (fc, fz) for
+  // the assembly: no FP64 ZZ)
   if (ring_fold(c, precision)) {
     w.Ria.release();
     w.RE.release();
+    w.ZZ.release();
     grow(w.RAb, B * c.ov() * c.kfold);
+    grow(w.fz, B * oovv);
   } else {
     w.RAb.release();
+    w.fz.release();
     grow(w.Ria, B * oovv);
     grow(w.RE, (c.ring_y ? 1 : 2) * B * oovv);
+    grow(w.ZZ, 2 * B * oovv);
   }
   grow(w.Zp, B * oovv);
   if (c.ring_y)
@@ -942,11 +947,13 @@ namespace {
 // of ZZ), the other three along b: one workgroup takes a 32 x 32 (a, b)
 // tile of one pair (i, j) of one vector, sums the a-contiguous terms into LDS with lanes
 // along a, and adds them transposed to the b-contiguous terms read and written with lanes
-// along b, so that every global access is a contiguous 256-byte row segment.
+// along b, so that every global access is a contiguous 256-byte row segment.  Zp and ZZ are
+// FP64, or FP32 (BF16 mode: the FP32 accumulators of the bfloat16 products, read as they are)
 constexpr int kAsmTile = 32;
+template <typename TZ>
 __global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, const double* __restrict__ Sd,
-                                                                const double* __restrict__ Zp,
-                                                                const double* __restrict__ ZZ,
+                                                                const TZ* __restrict__ Zp,
+                                                                const TZ* __restrict__ ZZ,
                                                                 double* __restrict__ s2, int64_t stride2) {
   __shared__ double tile[kAsmTile][kAsmTile + 1];
   const int64_t V = v, O = o, n = O * O * V * V, ov = O * V, ov2 = 2 * ov;
@@ -954,14 +961,14 @@ __global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, co
   const int a0 = (int)(blockIdx.x / ntb) * kAsmTile, b0 = (int)(blockIdx.x % ntb) * kAsmTile;
   const int64_t i = blockIdx.y / o, j = blockIdx.y % o, q = blockIdx.z;
   const int tx = threadIdx.x % kAsmTile, ty = threadIdx.x / kAsmTile;  // 32 x 8
-  const double* zp = Zp + q * n;
-  const double* zz = ZZ + q * 2 * n;
+  const TZ* zp = Zp + q * n;
+  const TZ* zz = ZZ + q * 2 * n;
   // terms contiguous along a: tile[b][a]
   for (int bb = ty; bb < kAsmTile; bb += 256 / kAsmTile) {
     const int64_t a = a0 + tx, b = b0 + bb;
     if (a < V && b < V)
-      tile[bb][tx] = zp[((j * O + i) * V + b) * V + a] + zz[(j * V + b) * ov2 + i * V + a] +
-                     zz[(i * V + b) * ov2 + ov + j * V + a];
+      tile[bb][tx] = (double)zp[((j * O + i) * V + b) * V + a] + (double)zz[(j * V + b) * ov2 + i * V + a] +
+                     (double)zz[(i * V + b) * ov2 + ov + j * V + a];
   }
   __syncthreads();
   // terms contiguous along b, plus the tile transposed
@@ -969,8 +976,8 @@ __global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, co
     const int64_t a = a0 + aa, b = b0 + tx;
     if (a < V && b < V) {
       const int64_t e = ((i * O + j) * V + a) * V + b;
-      s2[q * stride2 + e] = Sd[q * n + e] + zp[e] + zz[(i * V + a) * ov2 + j * V + b] +
-                            zz[(j * V + a) * ov2 + ov + i * V + b] + tile[tx][aa];
+      s2[q * stride2 + e] = Sd[q * n + e] + (double)zp[e] + (double)zz[(i * V + a) * ov2 + j * V + b] +
+                            (double)zz[(j * V + a) * ov2 + ov + i * V + b] + tile[tx][aa];
     }
   }
 }
@@ -1323,6 +1330,9 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   const bool df32 = f32 && c.BYUf.p && 2 * ovn <= (int64_t)w.fa.n / std::max(nb, 1);
   const bool ybf = bfr && c.ring_y && c.Yrb.p;  // R1 ring term through Yr on bfloat16 MFMA
   const bool zf32 = ybf && c.Zrf.p;             // and the one through Zr on FP32 MFMA
+  // the fused mode has no FP64 ZZ: every term of the ring block and of Zp goes through FP32
+  PNO_CHECK(!fold || (zf32 && c.Gqb.p && c.Fvob.p && c.Wvo2f.p && c.T32.p), PNOEOM_ESTATE,
+            "sigma: BF16 operands of the fused mode missing");
   if (ybf) {
     // R1c: the block's R1 compacted as [(q,j)][c]
     Perm4 p;
@@ -1361,7 +1371,8 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
         gemm(d, s);
       }
     }
-    to_double(s, 2 * (int64_t)nb * oovv, w.fc, w.ZZ, 0.0);
+    // (the fused mode keeps the ring block in FP32 for the assembly)
+    if (!fold) to_double(s, 2 * (int64_t)nb * oovv, w.fc, w.ZZ, 0.0);
   } else if (f32) {
     if (df32) {
       float* fa = w.fa;
@@ -1409,7 +1420,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     hipLaunchKernelGGL(pair_rows_bf16_kernel, dim3(grid1(nb * v * c.ldg)), dim3(256), 0, s, (int64_t)nb, oo,
                        (int64_t)v, (const double*)w.UR, ub, c.ldg);
     PNO_HIP(hipGetLastError());
-    float* ftv32 = w.fc;
+    float* ftv32 = fold ? (float*)w.fz : (float*)w.fc;  // (fc holds the FP32 ring block in the fused mode)
     for (int q = 0; q < nb; ++q)
       bgemm(v, v, c.ldg, -1.f, ub + q * v * c.ldg, c.Gqb, 0.f, ftv32 + q * vv, v);
     to_double(s, nb * vv, ftv32, w.Ftv, 0.0);
@@ -1439,27 +1450,30 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     for (int q = 0; q < nb; ++q) to_float(s, ov, r1 + q * stride1, r1f + q * ov);
     rows_bf16(nb * oo * v, v, R2, v, r2b, c.ldv);
     rows_bf16(nb * v, v, w.Ftv, v, ftb, c.ldv);
-    bgemm(nb * oo * v, v, c.ldv, 1.f, r2b, c.Fvob, 0.f, w.fc, v);
-    for (int q = 0; q < nb; ++q) bgemm(oo * v, v, c.ldv, 1.f, c.Tvb, ftb + q * v * c.ldv, 1.f, w.fc + q * oovv, v);
+    // (FP32 sum in fz in the fused mode, where it goes to the assembly as it is; else in fc)
+    float* zf = fold ? (float*)w.fz : (float*)w.fc;
+    bgemm(nb * oo * v, v, c.ldv, 1.f, r2b, c.Fvob, 0.f, zf, v);
+    for (int q = 0; q < nb; ++q) bgemm(oo * v, v, c.ldv, 1.f, c.Tvb, ftb + q * v * c.ldv, 1.f, zf + q * oovv, v);
     GemmDesc<float> e;  // - Foo^T R, batched over (q, i)
     e.ta = true; e.M = o; e.N = vv; e.K = o; e.alpha = -1.f; e.beta = 1.f; e.A = c.Foof; e.lda = o; e.sA = 0;
-    e.B = r2f; e.ldb = vv; e.sB = o * vv; e.C = w.fc; e.ldc = vv; e.sC = o * vv; e.batch = nbo;
+    e.B = r2f; e.ldb = vv; e.sB = o * vv; e.C = zf; e.ldc = vv; e.sC = o * vv; e.batch = nbo;
     gemm(e, s);
     for (int q = 0; q < nb; ++q) {
       GemmDesc<float> f;  // - Fto[q]^T T, batched over i
       f.ta = true; f.M = o; f.N = vv; f.K = o; f.alpha = -1.f; f.beta = 1.f; f.A = fof + q * oo; f.lda = o;
-      f.sA = 0; f.B = c.T32; f.ldb = vv; f.sB = o * vv; f.C = w.fc + q * oovv; f.ldc = vv; f.sC = o * vv;
+      f.sA = 0; f.B = c.T32; f.ldb = vv; f.sB = o * vv; f.C = zf + q * oovv; f.ldc = vv; f.sC = o * vv;
       f.batch = o;
       gemm(f, s);
       GemmDesc<float> g;  // - r1[q]^T Wvo2_ij^T, batched over the pairs
       g.ta = true; g.tb = true; g.M = v; g.N = v; g.K = o; g.alpha = -1.f; g.beta = 1.f; g.A = r1f + q * ov;
-      g.lda = v; g.sA = 0; g.B = c.Wvo2f; g.ldb = o; g.sB = (int64_t)v * o; g.C = w.fc + q * oovv; g.ldc = v;
+      g.lda = v; g.sA = 0; g.B = c.Wvo2f; g.ldb = o; g.sB = (int64_t)v * o; g.C = zf + q * oovv; g.ldc = v;
       g.sC = vv; g.batch = oo;
       gemm(g, s);
     }
-    hipLaunchKernelGGL(zp_finish_kernel, dim3(grid1(nb * oovv)), dim3(256), 0, s, nb * oovv, (int64_t)v,
-                       (const float*)w.fc, R2, (const double*)c.Fvvd, (double*)w.Zp);
+    hipLaunchKernelGGL(zp_finish_kernel, dim3(grid1(nb * oovv)), dim3(256), 0, s, nb * oovv, (int64_t)v, zf, R2,
+                       (const double*)c.Fvvd);
     PNO_HIP(hipGetLastError());
+    if (!fold) to_double(s, nb * oovv, zf, w.Zp, 0.0);
   } else {
     gm(s, false, true, (int64_t)nb * oo * v, v, v, 1.0, R2, v, c.Fvv, v, 0.0, w.Zp, v);
     gmb(s, false, true, oo * v, v, v, 1.0, c.T, v, 0, w.Ftv, v, vv, 1.0, w.Zp, v, oovv, nb);
@@ -1475,9 +1489,12 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   {
     const unsigned ntb = (unsigned)((v + kAsmTile - 1) / kAsmTile);
     PNO_CHECK((int64_t)o * o <= 65535 && nb <= 65535, PNOEOM_EINVAL, "sigma: too many pairs or vectors per block");
-    hipLaunchKernelGGL(assemble_s2_tiled_kernel, dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb), dim3(256), 0, s,
-                       o, v, (const double*)Sd, (const double*)w.Zp, (const double*)w.ZZ, s2,
-                       stride2);
+    if (fold)
+      hipLaunchKernelGGL(assemble_s2_tiled_kernel<float>, dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb), dim3(256),
+                         0, s, o, v, (const double*)Sd, (const float*)w.fz, (const float*)w.fc, s2, stride2);
+    else
+      hipLaunchKernelGGL(assemble_s2_tiled_kernel<double>, dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb), dim3(256),
+                         0, s, o, v, (const double*)Sd, (const double*)w.Zp, (const double*)w.ZZ, s2, stride2);
     PNO_HIP(hipGetLastError());
   }
 }
@@ -1787,7 +1804,7 @@ uint64_t sigma_signature(Context& c, hipStream_t s) {
                           &w.Am, &w.SigP, &w.SigM, &c.pno.Tw, &c.pno.r1, &c.pno.r2, &c.pno.s1, &c.pno.s2, &c.gin,
                           &c.gout})
     mix(b->p, b->n);
-  for (DBuf<float>* b : {&w.Spf, &w.Amf, &w.SigPf, &w.SigMf, &w.fa, &w.fc}) mix(b->p, b->n);
+  for (DBuf<float>* b : {&w.Spf, &w.Amf, &w.SigPf, &w.SigMf, &w.fa, &w.fc, &w.fz}) mix(b->p, b->n);
   mix(w.Spb.p, w.Spb.n);
   mix(w.RAb.p, w.RAb.n);
   mix(w.Amb.p, w.Amb.n);
