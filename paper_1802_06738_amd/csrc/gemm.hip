@@ -295,8 +295,28 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
     C = g.C + (g.reduce ? 0 : bz * g.sC);
     ldc = g.ldc;
   }
+  // (with beta != 0 the values of C of one row block are all read before any is written, so
+  // that the reads are in flight together; rows and columns past the end read the last one)
+  const bool rd = !split && g.beta != T(0);
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TM; ++i) {
+    T cv[TN][4];
+    if (rd) {
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t gn = min(n0 + wn * WN + j * 16 + lr, g.N - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gm = min(m0 + wm * WM + i * 16 + Mfma<T>::row(lk, r), g.M - 1);
+          cv[j][r] = g.beta * C[gm * ldc + gn];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cv[j][r] = T(0);
+    }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int64_t gn = n0 + wn * WN + j * 16 + lr;
@@ -305,12 +325,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
       for (int r = 0; r < 4; ++r) {
         const int64_t gm = m0 + wm * WM + i * 16 + Mfma<T>::row(lk, r);
         if (gm >= g.M) continue;
-        T* c = C + gm * ldc + gn;
-        T val = g.alpha * acc[i][j][r];
-        if (!split && g.beta != T(0)) val += g.beta * (*c);
-        *c = val;
+        C[gm * ldc + gn] = g.alpha * acc[i][j][r] + cv[j][r];
       }
     }
+  }
 }
 
 // C[b][m][n] = beta * C[b][m][n] + sum_z ws[z][b][m][n], summed in split order
@@ -756,8 +774,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
     }
     __syncthreads();
   }
+  // (beta != 0: the values of C of one row block read before any is written, as above)
+  const bool rd = g.beta != 0.f;
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TM; ++i) {
+    float cv[TN][4];
+    if (rd) {
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t gn = min(n0 + wn * WN + j * 16 + lr, g.N - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gm = min(m0 + wm * WM + i * 16 + 4 * lk + r, g.M - 1);
+          cv[j][r] = g.beta * g.C[gm * g.ldc + gn];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cv[j][r] = 0.f;
+    }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int64_t gn = n0 + wn * WN + j * 16 + lr;
@@ -766,12 +803,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ge
       for (int r = 0; r < 4; ++r) {
         const int64_t gm = m0 + wm * WM + i * 16 + 4 * lk + r;
         if (gm >= g.M) continue;
-        float* c = g.C + gm * g.ldc + gn;
-        float val = g.alpha * acc[i][j][r];
-        if (g.beta != 0.f) val += g.beta * (*c);
-        *c = val;
+        g.C[gm * g.ldc + gn] = g.alpha * acc[i][j][r] + cv[j][r];
       }
     }
+  }
 }
 }  // namespace
 

@@ -23,6 +23,9 @@
 // valid as long as A and B agree).  Accumulator r of lane l holds column l%32 and row
 // 8 (r/4) + 4 (l/32) + r%4 of the 32 x 32 tile.
 //
+// Epilogue: the accumulators go through LDS (half a tile at a time) so that C is written in
+// whole rows, 16 bytes per lane, and for beta != 0 read in batches ahead of the writes.
+//
 // Tile order: workgroup b runs on XCD b % 8, so tiles are handed out in eight contiguous
 // chunks, one per XCD.  Within the tile sequence, columns of tiles are taken in groups of
 // `group` (M fastest across a group's rows, N fastest within a row of the group), so the ~32
@@ -76,10 +79,16 @@ constexpr int NQA = TM / 32, NQB = TN / 32;  // 1 KB direct loads per wave per o
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-// C tile store: accumulator r of lane l holds column l%32 and row 8 (r/4) + 4 (l/32) + r%4 of
-// each 32 x 32 block; with split K the partial alpha A B^T goes to ws[split] (rows of N)
+// C tile store, through LDS in two halves of 128 rows (the operand buffers are free by then):
+// the accumulators of a half go to LDS as [128][256] FP32 (accumulator r of lane l holds
+// column l%32 and row 8 (r/4) + 4 (l/32) + r%4 of each 32 x 32 block), then each wave writes
+// whole rows of C, 16 bytes per lane.  For beta != 0 eight rows of C per lane are read before
+// any is written, so that the reads are in flight together (read after the stores before them,
+// each would wait for the previous store).  Edge tiles (or C rows not 16-byte aligned) take
+// the element-wise form.  With split K the partial alpha A B^T goes to ws[split] (rows of N).
 __device__ __forceinline__ void store_tile(const BigArgs& g, const f32x16 (&acc)[FM][FN], int64_t m0, int64_t n0,
-                                           int wm, int wn, int lr, int lk) {
+                                           int wm, int wn, int lr, int lk, uint16_t* lds) {
+  float* sm = reinterpret_cast<float*>(lds);
   float* C = g.C;
   int64_t ldc = g.ldc;
   float beta = g.beta;
@@ -88,22 +97,71 @@ __device__ __forceinline__ void store_tile(const BigArgs& g, const f32x16 (&acc)
     ldc = g.N;
     beta = 0.f;
   }
+  const float alpha = g.alpha;
+  const int tid = threadIdx.x, c4 = tid & 63, r0 = tid >> 6;
+  const bool vec = m0 + TM <= g.M && n0 + TN <= g.N && (ldc & 3) == 0 && ((uintptr_t)C & 15) == 0;
+  float* Ct = C + m0 * ldc + n0;
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();  // LDS free: operand reads (or the previous half) done
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int64_t gn = n0 + wn * WN + j * 32 + lr;
-      if (gn >= g.N) continue;
+    for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t gm = m0 + wm * WM + i * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          sm[(wm * 64 + ii * 32 + 8 * (r >> 2) + 4 * lk + (r & 3)) * TN + wn * WN + j * 32 + lr] =
+              acc[2 * h + ii][j][r];
+    __syncthreads();
+    // local row lr of the half is tile row (lr / 64) 128 + 64 h + lr % 64
+    if (vec) {
+#pragma unroll
+      for (int kb = 0; kb < 32; kb += 8) {
+        float4 cv[8];
+        if (beta != 0.f) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int lrow = r0 + 4 * (kb + k);
+            const int64_t trow = (lrow >> 6) * WM + h * 64 + (lrow & 63);
+            cv[k] = *reinterpret_cast<const float4*>(Ct + trow * ldc + 4 * c4);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int lrow = r0 + 4 * (kb + k);
+          const int64_t trow = (lrow >> 6) * WM + h * 64 + (lrow & 63);
+          const float4 a = *reinterpret_cast<const float4*>(sm + lrow * TN + 4 * c4);
+          float4 o;
+          o.x = alpha * a.x;
+          o.y = alpha * a.y;
+          o.z = alpha * a.z;
+          o.w = alpha * a.w;
+          if (beta != 0.f) {
+            o.x += beta * cv[k].x;
+            o.y += beta * cv[k].y;
+            o.z += beta * cv[k].z;
+            o.w += beta * cv[k].w;
+          }
+          *reinterpret_cast<float4*>(Ct + trow * ldc + 4 * c4) = o;
+        }
+      }
+    } else {
+      for (int k = 0; k < 32; ++k) {
+        const int lrow = r0 + 4 * k;
+        const int64_t gm = m0 + (lrow >> 6) * WM + h * 64 + (lrow & 63);
         if (gm >= g.M) continue;
-        float* c = C + gm * ldc + gn;
-        float val = g.alpha * acc[i][j][r];
-        if (beta != 0.f) val += beta * (*c);
-        *c = val;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t gn = n0 + 4 * c4 + e;
+          if (gn >= g.N) continue;
+          float* c = C + gm * ldc + gn;
+          float val = alpha * sm[lrow * TN + 4 * c4 + e];
+          if (beta != 0.f) val += beta * (*c);
+          *c = val;
+        }
       }
     }
+  }
 }
 
 template <int TAG>
@@ -213,7 +271,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1))) void ge
     __syncthreads();
   }
 
-  store_tile(g, acc, m0, n0, wm, wn, lr, lk);
+  store_tile(g, acc, m0, n0, wm, wn, lr, lk, lds);
 }
 
 // The same tile and staging with the k-steps rotated across the barrier: the last k-step's
@@ -364,7 +422,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1))) void ge
   }
   __builtin_amdgcn_s_waitcnt(0);  // no direct load is left in flight
 
-  store_tile(g, acc, m0, n0, wm, wn, lr, lk);
+  store_tile(g, acc, m0, n0, wm, wn, lr, lk, lds);
 }
 
 }  // namespace
