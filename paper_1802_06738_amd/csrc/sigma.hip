@@ -1065,7 +1065,8 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   for (int q = 0; q < nb && c.ring_y; ++q) {
     const double* r1q = r1 + q * stride1;
     const int64_t sc = (int64_t)nmo * o;
-    gmb(s, false, true, nmo, o, v, 1.0, c.Bt + o, nmo, n2, r1q, v, 0, 0.0, w.Bc, o, sc, naux);
+    // (the rows (Q, p) of B~ and of Bc are uniformly strided: one product over all of them)
+    gm(s, false, true, (int64_t)naux * nmo, o, v, 1.0, c.Bt + o, nmo, r1q, v, 0.0, w.Bc, o);
     gmb(s, true, false, v, o, o, -1.0, r1q, v, 0, c.Bt, nmo, n2, 1.0, w.Bc + (int64_t)o * o, o, sc, naux);
     fill(s, n2, 0.0, w.hp);
     gm(s, true, false, v, nmo, o, -1.0, r1q, v, c.hd, nmo, 1.0, w.hp + (int64_t)o * nmo, nmo);
@@ -1151,7 +1152,8 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   }
 
   // ---------------------------------------------------------------- sigma1
-  gmb(s, false, false, ov, 1, ov, 1.0, c.UiaT, ov, 0, w.fp_ov, 1, ov, 1.0, s1, 1, stride1, nb);
+  // (s1[q] += U_ia fp_ov[q] for all vectors in one product, U_ia read once)
+  gm(s, false, true, nb, ov, ov, 1.0, w.fp_ov, ov, c.UiaT, ov, 1.0, s1, stride1);
   gmb(s, true, false, o, v, o, -1.0, c.Fqoo, o, 0, r1, v, stride1, 1.0, s1, v, stride1, nb);
   gmb(s, false, true, o, v, v, 1.0, r1, v, stride1, c.Fqvv, v, 0, 1.0, s1, v, stride1, nb);
   gmb(s, false, false, ov, 1, ov, 1.0, w.UiaR, ov, oovv, c.fd_ov, 1, 0, 1.0, s1, 1, stride1, nb);
@@ -1188,8 +1190,11 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   } else {
     gmb(s, false, false, ov, naux, ov, 1.0, w.UiaR, ov, oovv, c.BovT, naux, 0, 0.0, w.M1, naux, ovn, nb);
   }
-  gmb(s, false, false, o, v, (int64_t)v * naux, 1.0, w.M1, (int64_t)v * naux, ovn, c.Bvv2, v, 0, 1.0, s1, v,
-      stride1, nb);
+  if (stride1 == ov)  // rows (q, i) of M1 and of s1 uniformly strided: one product, Bvv2 read once
+    gm(s, false, false, (int64_t)nb * o, v, (int64_t)v * naux, 1.0, w.M1, (int64_t)v * naux, c.Bvv2, v, 1.0, s1, v);
+  else
+    gmb(s, false, false, o, v, (int64_t)v * naux, 1.0, w.M1, (int64_t)v * naux, ovn, c.Bvv2, v, 0, 1.0, s1, v,
+        stride1, nb);
   gmb(s, false, false, o, v, oo * v, -1.0, c.OOOVp, oo * v, 0, URp, v, oovv, 1.0, s1, v, stride1, nb);
 
   // ---------------------------------------------------------------- sigma2, direct (not P-symmetrised)
@@ -1430,7 +1435,10 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
           true);
   }
   axpby(s, nb * vv, 1.0, w.fp_vv, 1.0, w.Ftv);
-  gmb(s, false, true, o, o, ov * v, 1.0, c.g2, ov * v, 0, w.UR, ov * v, oovv, 0.0, w.Fto, o, oo, nb);
+  // Fto[q][k][j] = sum_x g2[k][x] U(R)[q][j][x]: one product over the rows (q, j) of U(R) into
+  // [q][j][k] (in O4p, free by now), then transposed per vector
+  gm(s, false, true, nbo, o, ov * v, 1.0, w.UR, ov * v, c.g2, ov * v, 0.0, w.O4p, o);
+  ext(s, nb, o, o, 1, oo, 1, o, 0, w.O4p, w.Fto);
   axpby(s, nb * oo, 1.0, w.fp_oo, 1.0, w.Fto);
   // Zp[q][i][j][a][b] = sum_c R_ij^ac Fvv[b][c] - sum_k Foo[k][j] R_ik^ab + sum_c T_ij^ac Ftv[b][c]
   //                   - sum_k Fto[k][j] T_ik^ab - sum_k r_k^a Wvo2[(i,j,b)][k]
