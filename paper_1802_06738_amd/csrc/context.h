@@ -23,12 +23,13 @@ struct SigmaWork {
   // FP32 staging for the mixed-precision contractions
   DBuf<float> fa, fc;
   DBuf<float> fz;  // FP32 sum of the Zp terms (fused BF16 ring mode)
+  DBuf<float> Sdf;  // FP32 direct block: hole ladder, X_klij T and the ladder (fused BF16 ring mode)
   void release() {
     for (DBuf<double>* b : {&Bp, &Bc, &hp, &Jp, &Kp, &fp, &dp, &fp_ov, &fp_vv, &fp_oo, &BvopT, &BoopT, &BvvpT, &R2c, &Ria,
                             &UiaR, &UR, &ZZ, &RE, &Zp, &Xh, &O4p,
                             &OOVVp, &M1, &R1c, &Ftv, &Fto, &LadAll, &Sp, &Am, &SigP, &SigM})
       b->release();
-    for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fc, &fz}) b->release();
+    for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fc, &fz, &Sdf}) b->release();
     Spb.release();
     RAb.release();
     Amb.release();
@@ -62,6 +63,7 @@ struct PNOData {
   int nat_cut = 0, nat_pairs = 0, canon_pairs = 0;
   std::vector<int> prow;
   DBuf<int> d_prow;
+  DBuf<int> d_slot;             // per slot of the packed ladder: i o + j of its pair (i <= j)
   DBuf<double> Bbar, Y1, Ypart;  // Ypart: split-K partial blocks of the second product
   GroupTable t_na, t_nb;
   DBuf<int> d_nn, d_nch;         // per native pair: n_p, K chunks
@@ -74,7 +76,7 @@ struct PNOData {
     U.release(); denom_base.release(); d_off.release(); d_n.release(); d_xpair.release();
     Tw.release(); r1.release(); r2.release(); s1.release(); s2.release();
     nat_cut = nat_pairs = canon_pairs = 0;
-    prow.clear(); d_prow.release(); Bbar.release(); Y1.release(); Ypart.release(); nat_flops = 0;
+    prow.clear(); d_prow.release(); d_slot.release(); Bbar.release(); Y1.release(); Ypart.release(); nat_flops = 0;
     d_nn.release(); d_nch.release(); d_poff.release(); d_yoff.release();
   }
 };
@@ -160,7 +162,9 @@ struct Context {
   int lad_mode = 0, lad_max_slab = 0;
   // restricted canonical ladder (PNO sigma with native pairs): slot per pair or -1, slots per vector
   const int* lad_prow = nullptr;
+  const int* lad_slot = nullptr;  // and the pair (i o + j) of each slot
   int64_t lad_nsub = -1;
+  DBuf<int> slot_all;             // i o + j of every pair i <= j in ladder-slot order
   bool lad_streamed = false;    // W+/- not stored: rebuilt slab by slab in every sigma
   bool have_lad = false;        // the ladder can be applied (build_df or build_ladder done)
   DBuf<float> BvvTf;            // FP32 copy of BvvT (streamed, precision FP32)

@@ -389,6 +389,13 @@ void build_native_ladder(Context& c, const std::vector<int>& pi, const std::vect
   }
   P.d_prow.alloc(npair);
   PNO_HIP(hipMemcpy(P.d_prow, P.prow.data(), npair * sizeof(int), hipMemcpyHostToDevice));
+  {
+    std::vector<int> slot(std::max(P.canon_pairs, 1), 0);
+    for (int p = 0; p < npair; ++p)
+      if (P.prow[p] >= 0) slot[P.prow[p]] = pi[p] * o + pj[p];
+    P.d_slot.alloc((int64_t)slot.size());
+    PNO_HIP(hipMemcpy(P.d_slot, slot.data(), slot.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
   if (P.nat_pairs == 0) return;
   P.Bbar.alloc(bw);
   P.Y1.alloc(bw);
@@ -452,8 +459,6 @@ void build_native_ladder(Context& c, const std::vector<int>& pi, const std::vect
   PNO_HIP(hipMemcpy(P.d_poff, hpoff.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice));
   PNO_HIP(hipMemcpy(P.d_yoff, hyoff.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice));
   PNO_HIP(hipStreamSynchronize(s));
-  (void)pi;
-  (void)pj;
 }
 }  // namespace
 
@@ -903,12 +908,14 @@ void sigma_pno(Context& c, int nvec, const double* x, double* y, int precision) 
   // canonical sigma with the ladder restricted to the pairs that keep it
   struct Restrict {
     Context& c;
-    Restrict(Context& cc, const int* prow, int64_t nsub) : c(cc) {
+    Restrict(Context& cc, const int* prow, const int* slot, int64_t nsub) : c(cc) {
       c.lad_prow = prow;
+      c.lad_slot = slot;
       c.lad_nsub = nsub;
     }
     ~Restrict() {
       c.lad_prow = nullptr;
+      c.lad_slot = nullptr;
       c.lad_nsub = -1;
     }
   };
@@ -916,7 +923,8 @@ void sigma_pno(Context& c, int nvec, const double* x, double* y, int precision) 
     const int n = std::min(nb, nvec - q0);
     pno_expand(c, n, x + (int64_t)q0 * P.len, P.r1, P.r2);
     {
-      Restrict r(c, P.nat_pairs > 0 ? (const int*)P.d_prow : nullptr, P.nat_pairs > 0 ? P.canon_pairs : -1);
+      Restrict r(c, P.nat_pairs > 0 ? (const int*)P.d_prow : nullptr, P.nat_pairs > 0 ? (const int*)P.d_slot : nullptr,
+                 P.nat_pairs > 0 ? P.canon_pairs : -1);
       sigma_block(c, n, P.r1, P.r2, P.s1, P.s2, c.ov(), c.oovv(), precision);
     }
     pno_compress(c, n, P.s1, P.s2, y + (int64_t)q0 * P.len);

@@ -286,6 +286,30 @@ __global__ void ladder_pack_kernel(int o, int v, int nvec, const double* __restr
   }
 }
 
+// the same packing driven by the list of slots (slot_ij: i o + j of the pair of each of the nrow
+// slots): only the R blocks of the listed pairs are read
+template <typename OutT>
+__global__ void ladder_pack_slots_kernel(int o, int v, int nvec, const double* __restrict__ r2, int64_t stride,
+                                         OutT* __restrict__ S, int64_t ldS, OutT* __restrict__ A, int64_t ldA,
+                                         const int* __restrict__ slot_ij, int64_t nrow) {
+  const int64_t O = o, V = v, VV = V * V;
+  const int64_t total = (int64_t)nvec * nrow * VV;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    const int64_t d = r % V; r /= V;
+    const int64_t c = r % V; r /= V;
+    const int64_t slot = r % nrow;
+    const int64_t q = r / nrow;
+    if (d < c) continue;
+    const int64_t ij = slot_ij[slot], i = ij / O, j = ij % O;
+    const double* R = r2 + q * stride + (i * O + j) * VV;
+    const double x = R[c * V + d], y = R[d * V + c];
+    const int64_t row = q * nrow + slot;
+    S[row * ldS + tri_idx(c, d, V)] = cvt_out<OutT>(c < d ? 0.5 * (x + y) : x);
+    if (c < d) A[row * ldA + stri_idx(c, d, V)] = cvt_out<OutT>(0.5 * (x - y));
+  }
+}
+
 // out[q][i][j][a][b] = sigma_ij^ab of the ladder from sigma+ (a<=b) and sigma- (a<b) of pair min(i,j), max(i,j)
 // (rows as in ladder_pack_kernel; zero for a pair without a slot)
 template <typename InT>
@@ -319,6 +343,33 @@ __global__ void ladder_unpack_kernel(int o, int v, int nvec, const InT* __restri
   }
 }
 
+// out[q][x][y][a][b] += sigma_xy^ab of the ladder for the nrow pairs (i <= j) listed in slot_ij
+// (i o + j per slot; rows of sigma+ / sigma- as in ladder_pack_kernel), both blocks (i, j) and
+// (j, i) (sigma_ji^ab = sigma_ij^ba), each written along b; the other pairs are left alone
+__global__ void ladder_unpack_add_kernel(int o, int v, int nvec, int64_t nrow, const float* __restrict__ SP,
+                                         const float* __restrict__ SM, const int* __restrict__ slot_ij,
+                                         float* __restrict__ out) {
+  const int64_t O = o, V = v, VV = V * V, vp = V * (V + 1) / 2, vm = V * (V - 1) / 2;
+  const int64_t total = (int64_t)nvec * nrow * 2 * VV;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e;
+    const int64_t b = r % V; r /= V;
+    const int64_t a = r % V; r /= V;
+    const int64_t dir = r % 2; r /= 2;
+    const int64_t slot = r % nrow;
+    const int64_t q = r / nrow;
+    const int64_t ij = slot_ij[slot], i = ij / O, j = ij % O;
+    if (dir == 1 && i == j) continue;
+    const int64_t x = dir ? j : i, y = dir ? i : j;
+    const int64_t aa = dir ? b : a, bb = dir ? a : b;  // sigma_xy^ab = sigma_ij^(aa bb)
+    const int64_t row = q * nrow + slot;
+    float val;
+    if (aa == bb) val = SP[row * vp + tri_idx(aa, aa, V)];
+    else if (aa < bb) val = SP[row * vp + tri_idx(aa, bb, V)] + SM[row * vm + stri_idx(aa, bb, V)];
+    else val = SP[row * vp + tri_idx(bb, aa, V)] - SM[row * vm + stri_idx(bb, aa, V)];
+    out[q * O * O * VV + (x * O + y) * VV + a * V + b] += val;
+  }
+}
 
 // x~ = (1 - t)^T x (1 + t^T) for nb stacked nmo x nmo matrices; work has the same size as x
 void dress(Context& c, const double* x, double* out, double* work, int64_t nb) {
@@ -819,7 +870,7 @@ int64_t rest_bytes_per_vector(const Context& c, int precision, bool r2c) {
                oo + vv + oo +
                (c.ring_y ? ov : 0);
   int64_t bytes = nd * (int64_t)sizeof(double);
-  if (fold) bytes += ov * c.kfold * (int64_t)sizeof(uint16_t) + oovv * (int64_t)sizeof(float);  // RAb, fz
+  if (fold) bytes += ov * c.kfold * (int64_t)sizeof(uint16_t) + 2 * oovv * (int64_t)sizeof(float);  // RAb, fz, Sdf
   if (f32)  // fa and fc (two oovv each; fa larger when it stages the BF16 operands)
     bytes += (2 * oovv + std::max({2 * oovv, bf16_ring_floats(c, PNOEOM_BF16, 1) + 1,
                                    bf16_rest_values(c, PNOEOM_BF16, 1) / 2 + 1})) *
@@ -836,7 +887,8 @@ int64_t sigma_bytes_per_vector(const Context& c, int precision, bool pno) {
   const int64_t npair = (int64_t)c.o * (c.o + 1) / 2, vp = (int64_t)c.v * (c.v + 1) / 2;
   const int64_t vm = std::max<int64_t>((int64_t)c.v * (c.v - 1) / 2, 1);
   // (the PNO path expands its vectors with the singles and doubles apart: no R2c)
-  int64_t b = rest_bytes_per_vector(c, precision, !pno) + c.oovv() * (int64_t)sizeof(double);  // + LadAll
+  int64_t b = rest_bytes_per_vector(c, precision, !pno) +
+              (ring_fold(c, precision) ? 0 : c.oovv() * (int64_t)sizeof(double));  // + LadAll
   const int64_t in_elt = precision == PNOEOM_FP64 ? 8 : precision == PNOEOM_FP32 ? 4 : 2;
   const int64_t out_elt = precision == PNOEOM_FP64 ? 8 : 4;
   const int64_t kp = precision == PNOEOM_BF16 ? c.ldpb + c.ldmb : vp + vm;
@@ -855,7 +907,7 @@ int64_t sigma_held_bytes(const Context& c) {
                                 &w.LadAll, &w.Sp, &w.Am, &w.SigP, &w.SigM, &c.pno.r1, &c.pno.r2, &c.pno.s1,
                                 &c.pno.s2})
     b += (int64_t)x->n * 8;
-  for (const DBuf<float>* x : {&w.Spf, &w.Amf, &w.SigPf, &w.SigMf, &w.fa, &w.fc, &w.fz}) b += (int64_t)x->n * 4;
+  for (const DBuf<float>* x : {&w.Spf, &w.Amf, &w.SigPf, &w.SigMf, &w.fa, &w.fc, &w.fz, &w.Sdf}) b += (int64_t)x->n * 4;
   b += (int64_t)(w.Spb.n + w.Amb.n + w.RAb.n) * 2;
   return b;
 }
@@ -905,9 +957,11 @@ void alloc_sigma_work(Context& c, int precision, int nb, bool need_r2c) {
     w.ZZ.release();
     grow(w.RAb, B * c.ov() * c.kfold);
     grow(w.fz, B * oovv);
+    grow(w.Sdf, B * oovv);
   } else {
     w.RAb.release();
     w.fz.release();
+    w.Sdf.release();
     grow(w.Ria, B * oovv);
     grow(w.RE, (c.ring_y ? 1 : 2) * B * oovv);
     grow(w.ZZ, 2 * B * oovv);
@@ -950,8 +1004,8 @@ namespace {
 // along b, so that every global access is a contiguous 256-byte row segment.  Zp and ZZ are
 // FP64, or FP32 (BF16 mode: the FP32 accumulators of the bfloat16 products, read as they are)
 constexpr int kAsmTile = 32;
-template <typename TZ>
-__global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, const double* __restrict__ Sd,
+template <typename TS, typename TZ>
+__global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, const TS* __restrict__ Sd,
                                                                 const TZ* __restrict__ Zp,
                                                                 const TZ* __restrict__ ZZ,
                                                                 double* __restrict__ s2, int64_t stride2) {
@@ -976,7 +1030,7 @@ __global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, co
     const int64_t a = a0 + aa, b = b0 + tx;
     if (a < V && b < V) {
       const int64_t e = ((i * O + j) * V + a) * V + b;
-      s2[q * stride2 + e] = Sd[q * n + e] + (double)zp[e] + (double)zz[(i * V + a) * ov2 + j * V + b] +
+      s2[q * stride2 + e] = (double)Sd[q * n + e] + (double)zp[e] + (double)zz[(i * V + a) * ov2 + j * V + b] +
                             (double)zz[(j * V + a) * ov2 + ov + i * V + b] + tile[tx][aa];
     }
   }
@@ -1044,10 +1098,13 @@ __global__ void zero_cols_kernel(int64_t rows, int64_t ld, int64_t c0, int64_t c
 }
 
 // every sigma term except the particle ladder, for nb vectors at once; the caller
-// has written the ladder of vector q into Sd + q * oovv.  Contractions whose one
+// has written the ladder of vector q into Sd + q * oovv (in the fused BF16 ring mode Sd is
+// null: the packed ladder results of the chunk are added into the FP32 direct block Sdf
+// here).  Contractions whose one
 // operand is a fixed intermediate run as one batched GEMM over the vectors.
 void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, const double* r2, int64_t stride2,
                       double* s1, double* s2, int precision, double* Sd) {
+  PNO_CHECK(Sd || ring_fold(c, precision), PNOEOM_EINVAL, "sigma: no ladder block");
   SigmaWork& w = c.sw;
   hipStream_t s = c.stream;
   const int o = c.o, v = c.v, nmo = c.nmo, naux = c.naux;
@@ -1205,8 +1262,10 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     hipLaunchKernelGGL(bf16_transpose_kernel, dim3((unsigned)((vv + 31) / 32), (unsigned)((c.ldoo + 31) / 32), (unsigned)nb),
                        dim3(256), 0, s, oo, vv, R2, oovv, hb, c.ldoo, vv * c.ldoo);
     PNO_HIP(hipGetLastError());
+    // (the fused mode keeps this direct block in FP32: Sdf, the ladder added into it below)
+    float* dblk = fold ? (float*)w.Sdf : (float*)w.fc;
     for (int q = 0; q < nb; ++q)
-      bgemm(oo, vv, c.ldoo, 1.f, c.Whb, hb + q * vv * c.ldoo, 0.f, w.fc + q * oovv, vv);
+      bgemm(oo, vv, c.ldoo, 1.f, c.Whb, hb + q * vv * c.ldoo, 0.f, dblk + q * oovv, vv);
     // Xh[(q,i,j)][(kl)] = sum_(ab) R2[(q,i,j)][(ab)] g2[(kl)][(ab)], into fc after the ladder block
     rows_bf16(nb * oo, vv, R2, vv, hb, c.ldvv);
     bgemm(nb * oo, oo, c.ldvv, 1.f, hb, c.g2b, 0.f, w.fc + nb * oovv, oo);
@@ -1229,8 +1288,22 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   if (bfr) {
     // Sd[q] += Xh[q] T, all vectors in one product onto the ladder block in fc
     rows_bf16(nb * oo, oo, w.Xh, oo, hb, c.ldoo);
-    bgemm(nb * oo, vv, c.ldoo, 1.f, hb, c.TTb, 1.f, w.fc, vv);
-    to_double(s, nb * oovv, w.fc, Sd, 1.0);
+    float* dblk = fold ? (float*)w.Sdf : (float*)w.fc;
+    bgemm(nb * oo, vv, c.ldoo, 1.f, hb, c.TTb, 1.f, dblk, vv);
+    if (fold) {
+      // + the particle ladder of the pairs that keep the canonical ladder (packed results
+      // of this chunk in SigPf / SigMf)
+      const int64_t nrow = c.lad_nsub >= 0 ? c.lad_nsub : (int64_t)o * (o + 1) / 2;
+      const int* slot = c.lad_nsub >= 0 ? c.lad_slot : (const int*)c.slot_all;
+      PNO_CHECK(slot != nullptr, PNOEOM_ESTATE, "sigma: no pair table of the ladder slots");
+      if (nrow > 0) {
+        hipLaunchKernelGGL(ladder_unpack_add_kernel, dim3(grid1((int64_t)nb * nrow * 2 * vv)), dim3(256), 0, s, o, v,
+                           nb, nrow, (const float*)w.SigPf, (const float*)w.SigMf, slot, dblk);
+        PNO_HIP(hipGetLastError());
+      }
+    } else {
+      to_double(s, nb * oovv, w.fc, Sd, 1.0);
+    }
   } else if (f32x) {
     to_float(s, nb * o4, w.Xh, Xhf);
     gmbf(s, false, false, oo, vv, oo, 1.0, Xhf, oo, o4, c.T32, vv, 0, 1.0, Sd, nb, w.fc);
@@ -1498,11 +1571,13 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     const unsigned ntb = (unsigned)((v + kAsmTile - 1) / kAsmTile);
     PNO_CHECK((int64_t)o * o <= 65535 && nb <= 65535, PNOEOM_EINVAL, "sigma: too many pairs or vectors per block");
     if (fold)
-      hipLaunchKernelGGL(assemble_s2_tiled_kernel<float>, dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb), dim3(256),
-                         0, s, o, v, (const double*)Sd, (const float*)w.fz, (const float*)w.fc, s2, stride2);
+      hipLaunchKernelGGL((assemble_s2_tiled_kernel<float, float>), dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb),
+                         dim3(256), 0, s, o, v, (const float*)w.Sdf, (const float*)w.fz, (const float*)w.fc, s2,
+                         stride2);
     else
-      hipLaunchKernelGGL(assemble_s2_tiled_kernel<double>, dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb), dim3(256),
-                         0, s, o, v, (const double*)Sd, (const double*)w.Zp, (const double*)w.ZZ, s2, stride2);
+      hipLaunchKernelGGL((assemble_s2_tiled_kernel<double, double>), dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb),
+                         dim3(256), 0, s, o, v, (const double*)Sd, (const double*)w.Zp, (const double*)w.ZZ, s2,
+                         stride2);
     PNO_HIP(hipGetLastError());
   }
 }
@@ -1578,7 +1653,7 @@ void ladder_contract(Context& c, int precision, int64_t rows) {
 // packs nvec vectors (pairs of o occupied) into the ladder work arrays of a precision; with
 // prow, only the pairs with a slot (nrow slots per vector), else all o(o+1)/2 pairs
 void ladder_pack(Context& c, int precision, int o, int nvec, const double* r2, int64_t stride2,
-                 const int* prow = nullptr, int64_t nrow = -1) {
+                 const int* prow = nullptr, int64_t nrow = -1, const int* slot = nullptr) {
   SigmaWork& w = c.sw;
   hipStream_t s = c.stream;
   const int64_t v = c.v, vp = v * (v + 1) / 2, vm = v * (v - 1) / 2, vm1 = std::max<int64_t>(vm, 1);
@@ -1606,8 +1681,13 @@ void ladder_pack(Context& c, int precision, int o, int nvec, const double* r2, i
                          (uint16_t*)w.Amb);
       PNO_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL((ladder_pack_kernel<uint16_t>), dim3(grid1(tot)), dim3(256), 0, s, o, (int)v, nvec, r2,
-                       stride2, (uint16_t*)w.Spb, c.ldpb, (uint16_t*)w.Amb, c.ldmb, prow, nrow);
+    if (slot)  // (only the listed pairs' blocks of R are read)
+      hipLaunchKernelGGL((ladder_pack_slots_kernel<uint16_t>), dim3(grid1((int64_t)nvec * nrow * v * v)), dim3(256), 0,
+                         s, o, (int)v, nvec, r2, stride2, (uint16_t*)w.Spb, c.ldpb, (uint16_t*)w.Amb, c.ldmb, slot,
+                         nrow);
+    else
+      hipLaunchKernelGGL((ladder_pack_kernel<uint16_t>), dim3(grid1(tot)), dim3(256), 0, s, o, (int)v, nvec, r2,
+                         stride2, (uint16_t*)w.Spb, c.ldpb, (uint16_t*)w.Amb, c.ldmb, prow, nrow);
   } else {
     grow(w.Sp, rows * vp); grow(w.Am, rows * vm1);
     hipLaunchKernelGGL((ladder_pack_kernel<double>), dim3(grid1(tot)), dim3(256), 0, s, o, (int)v, nvec, r2,
@@ -1772,13 +1852,27 @@ void sigma_block_chunk(Context& c, int nvec, const double* r1, const double* r2,
   const int* prow = c.lad_nsub >= 0 ? c.lad_prow : nullptr;
   const int64_t nrow = c.lad_nsub >= 0 ? c.lad_nsub : (int64_t)o * (o + 1) / 2;
   const int64_t rows = (int64_t)nvec * nrow;
-  grow(w.LadAll, (int64_t)nvec * oovv);
+  // (the fused BF16 ring mode adds the packed ladder results into its FP32 direct block inside
+  // sigma_rest_block: no FP64 unpacked ladder)
+  const bool defer = ring_fold(c, precision);
+  if (c.lad_nsub < 0 && (int64_t)c.slot_all.n < nrow) {
+    std::vector<int> all;
+    for (int i = 0; i < o; ++i)
+      for (int j = i; j < o; ++j) all.push_back(i * o + j);
+    c.slot_all.alloc((int64_t)all.size());
+    PNO_HIP(hipMemcpy(c.slot_all, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
+  const int* slot = c.lad_nsub >= 0 ? c.lad_slot : (const int*)c.slot_all;
+  if (defer)
+    w.LadAll.release();
+  else
+    grow(w.LadAll, (int64_t)nvec * oovv);
   // ---------------------------------------------------------------- particle ladder, all vectors at once
-  ladder_pack(c, precision, o, nvec, r2, stride2, prow, nrow);
+  ladder_pack(c, precision, o, nvec, r2, stride2, prow, nrow, slot);
   ladder_contract(c, precision, rows);
-  ladder_unpack(c, precision, o, nvec, w.LadAll, oovv, prow, nrow);
+  if (!defer) ladder_unpack(c, precision, o, nvec, w.LadAll, oovv, prow, nrow);
   // ---------------------------------------------------------------- everything else
-  sigma_rest_block(c, nvec, r1, stride1, r2, stride2, s1, s2, precision, w.LadAll);
+  sigma_rest_block(c, nvec, r1, stride1, r2, stride2, s1, s2, precision, defer ? nullptr : (double*)w.LadAll);
 }
 }  // namespace
 
@@ -1812,7 +1906,7 @@ uint64_t sigma_signature(Context& c, hipStream_t s) {
                           &w.Am, &w.SigP, &w.SigM, &c.pno.Tw, &c.pno.r1, &c.pno.r2, &c.pno.s1, &c.pno.s2, &c.gin,
                           &c.gout})
     mix(b->p, b->n);
-  for (DBuf<float>* b : {&w.Spf, &w.Amf, &w.SigPf, &w.SigMf, &w.fa, &w.fc, &w.fz}) mix(b->p, b->n);
+  for (DBuf<float>* b : {&w.Spf, &w.Amf, &w.SigPf, &w.SigMf, &w.fa, &w.fc, &w.fz, &w.Sdf}) mix(b->p, b->n);
   mix(w.Spb.p, w.Spb.n);
   mix(w.RAb.p, w.RAb.n);
   mix(w.Amb.p, w.Amb.n);
