@@ -124,7 +124,9 @@ int pnoeom_pno_layout(const pnoeom_ctx* ctx, long long* offsets, long long* len)
 int pnoeom_pno_transform(pnoeom_ctx* ctx, int nvec, int direction, double* r1, double* r2, double* x);
 
 /* sigma = <mu|[H-bar, R]|0> for nvec trial vectors.
- *   space = PNOEOM_CANONICAL: r1 device [nvec][o][v], r2 device [nvec][o][o][v][v];
+ *   space = PNOEOM_CANONICAL: r1 device [nvec][o][v], r2 device [nvec][o][o][v][v]
+ *           with the closed-shell pair symmetry r2[q][i][j][a][b] = r2[q][j][i][b][a]
+ *           (the doubles space of the method; the contractions rely on it);
  *           s1, s2 the same shapes (outputs).
  *   space = PNOEOM_PNO: r1 = device [nvec][len] PNO-space vectors (r2 ignored, may be
  *           NULL); s1 = device [nvec][len] receives P sigma in the same layout.

@@ -146,6 +146,7 @@ struct Context {
   // Fock-type products T Ftv^T and R (Fvv - diag)^T), and the diagonal of Fvv
   DBuf<uint16_t> Tvb, Fvob;
   DBuf<double> Fvvd;
+  DBuf<double> Food;  // diagonal of Foo (BF16 scope 1: its off-diagonal part rides in Whb)
   int64_t ldoo = 0, ldvv = 0, ldov = 0, ldv = 0, ldg = 0;
   bool bf_rest = false;
   // build-time temporaries of build_df, by slot (each slot's uses follow one another on the

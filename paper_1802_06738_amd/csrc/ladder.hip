@@ -378,6 +378,7 @@ void build_ladder(Context& c, const double* B, const double* t1, int precision, 
                             &c.Tvb, &c.Fvob})
     b->release();
   c.Fvvd.release();
+  c.Food.release();
   c.bf_rest = false;
   c.Yr.release();
   c.Zr.release();

@@ -175,12 +175,35 @@ __global__ void offdiag_rows_bf16_kernel(int64_t n, const double* __restrict__ F
   }
 }
 
-// acc[e] += R[e] d[e % v]: the diagonal part of R Fvv^T added to the FP32 sum of the Fock-type
-// products (the product itself in FP64, rounded once)
-__global__ void zp_finish_kernel(int64_t n, int64_t v, float* __restrict__ acc, const double* __restrict__ R,
-                                 const double* __restrict__ d) {
+// acc[e] += R[e] (d[b] - fd[j]) for e = (((q o + i) o + j) v + a) v + b: the diagonal parts of
+// R Fvv^T and of -Foo^T R added to the FP32 sum of the Fock-type products (the products
+// themselves in FP64, rounded once)
+__global__ void zp_finish_kernel(int64_t n, int64_t o, int64_t v, float* __restrict__ acc,
+                                 const double* __restrict__ R, const double* __restrict__ d,
+                                 const double* __restrict__ fd) {
+  const int64_t vv = v * v;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-    acc[e] = (float)((double)acc[e] + R[e] * d[e % v]);
+    acc[e] = (float)((double)acc[e] + R[e] * (d[e % v] - fd[(e / vv) % o]));
+}
+
+// bfloat16 rows (ld columns, zero beyond o^2) of Wh[(ij)][(kl)] - delta_ik Foo[l][j] (l != j)
+// - delta_jl Foo[k][i] (k != i): the off-diagonal part of the -Foo^T R Fock-type term and of its
+// (ij, ab) <-> (ji, ba) partner, carried by the hole ladder (R_kj^ab = R_jk^ba); fd = diag(Foo)
+__global__ void wh_foo_rows_bf16_kernel(int64_t o, const double* __restrict__ Wh, const double* __restrict__ Foo,
+                                        uint16_t* __restrict__ out, int64_t ld, double* __restrict__ fd) {
+  const int64_t oo = o * o;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < oo * ld; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / ld, cl = e % ld;
+    double val = 0.0;
+    if (cl < oo) {
+      const int64_t i = r / o, j = r % o, k = cl / o, l = cl % o;
+      val = Wh[r * oo + cl];
+      if (i == k && l != j) val -= Foo[l * o + j];
+      if (j == l && k != i) val -= Foo[k * o + i];
+    }
+    out[e] = bf16_bits(val);
+    if (e < o) fd[e] = Foo[e * o + e];
+  }
 }
 
 // out[q][a][(p, c)] = bf16(U[q][p][a][c]) for pairs p < npair (U: [nb][npair][v][v]), rows of
@@ -425,6 +448,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
                             &c.Tvb, &c.Fvob})
     b->release();
   c.Fvvd.release();
+  c.Food.release();
   c.bf_rest = false;
   c.ring_y = false;
   c.Yr.release();
@@ -753,7 +777,10 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     c.BovQb.alloc(naux * c.ldov);
     c.BYUb.alloc(ov * c.ldq);
     c.YUb.alloc(ov * c.ldq);
-    bf16_rows(s, oo, oo, c.Wh, oo, 1, c.Whb, c.ldoo, c.ldoo);
+    c.Food.alloc(o);
+    hipLaunchKernelGGL(wh_foo_rows_bf16_kernel, dim3(grid1(oo * c.ldoo)), dim3(256), 0, s, (int64_t)o,
+                       (const double*)c.Wh, (const double*)c.Foo, (uint16_t*)c.Whb, c.ldoo, (double*)c.Food);
+    PNO_HIP(hipGetLastError());
     bf16_rows(s, oo, vv, c.g2, vv, 1, c.g2b, c.ldvv, c.ldvv);
     auto tr = [&](int64_t R, int64_t C, const double* src, int64_t sb, uint16_t* dst, int64_t ld, int64_t db,
                   int64_t nbat) {
@@ -852,8 +879,8 @@ int64_t bf16_rest_values(const Context& c, int precision, int64_t nb) {
   const int64_t oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, ov = c.ov();
   const int64_t hole = std::max({vv * c.ldoo, oo * c.ldvv, oo * c.ldoo});
   const int64_t df = 2 * ov * c.ldq + (c.Yrb.p ? (int64_t)c.o * c.ldv : 0);
-  // Fock-type block: R2, Fto and R1 in FP32, then R2 and Ftv rows in bfloat16
-  const int64_t fock = 2 * (c.oovv() + oo + ov + 4) + (oo + 1) * c.v * c.ldv;
+  // Fock-type block: Fto and R1 in FP32, then R2 and Ftv rows in bfloat16
+  const int64_t fock = 2 * (oo + ov + 4) + (oo + 1) * c.v * c.ldv;
   return nb * std::max({hole, ov * c.ldov, df, (int64_t)c.v * c.ldg, fock});
 }
 
@@ -1517,16 +1544,15 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   //                   - sum_k Fto[k][j] T_ik^ab - sum_k r_k^a Wvo2[(i,j,b)][k]
   // (the last one is -P[ sum_k r_k^a Wvo_kbij ] before the P symmetrisation of the assembly)
   if (bfr && c.Fvob.p && c.Wvo2f.p && c.T32.p) {
-    // BF16 scope 1: R (Fvv - diag)^T and T Ftv^T on bfloat16 MFMA, the three products with
-    // K = o on FP32 MFMA, all into fc (operands staged in fa); the diagonal part of R Fvv^T is
-    // added exactly in the conversion to FP64
-    float* r2f = w.fa;
-    float* fof = r2f + nb * oovv;
+    // BF16 scope 1: R (Fvv - diag)^T and T Ftv^T on bfloat16 MFMA, the products with K = o
+    // (Fto T, r1 Wvo2) on FP32 MFMA, all into one FP32 sum (operands staged in fa); the
+    // diagonal parts of R Fvv^T and of -Foo^T R are added exactly by zp_finish_kernel, the
+    // off-diagonal part of -Foo^T R rides with the hole ladder (Whb)
+    float* fof = w.fa;
     float* r1f = fof + nb * oo;
-    const int64_t boff = (nb * (oovv + oo + ov) + 3) / 4 * 4;  // floats: bfloat16 rows 16-byte aligned
+    const int64_t boff = (nb * (oo + ov) + 3) / 4 * 4;  // floats: bfloat16 rows 16-byte aligned
     uint16_t* r2b = reinterpret_cast<uint16_t*>((float*)w.fa + boff);
     uint16_t* ftb = r2b + nb * oo * v * c.ldv;
-    to_float(s, nb * oovv, R2, r2f);
     to_float(s, nb * oo, w.Fto, fof);
     for (int q = 0; q < nb; ++q) to_float(s, ov, r1 + q * stride1, r1f + q * ov);
     rows_bf16(nb * oo * v, v, R2, v, r2b, c.ldv);
@@ -1535,10 +1561,8 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     float* zf = fold ? (float*)w.fz : (float*)w.fc;
     bgemm(nb * oo * v, v, c.ldv, 1.f, r2b, c.Fvob, 0.f, zf, v);
     for (int q = 0; q < nb; ++q) bgemm(oo * v, v, c.ldv, 1.f, c.Tvb, ftb + q * v * c.ldv, 1.f, zf + q * oovv, v);
-    GemmDesc<float> e;  // - Foo^T R, batched over (q, i)
-    e.ta = true; e.M = o; e.N = vv; e.K = o; e.alpha = -1.f; e.beta = 1.f; e.A = c.Foof; e.lda = o; e.sA = 0;
-    e.B = r2f; e.ldb = vv; e.sB = o * vv; e.C = zf; e.ldc = vv; e.sC = o * vv; e.batch = nbo;
-    gemm(e, s);
+    // (- Foo^T R: its off-diagonal part went with the hole ladder (Whb), its diagonal part is
+    // added exactly below)
     for (int q = 0; q < nb; ++q) {
       GemmDesc<float> f;  // - Fto[q]^T T, batched over i
       f.ta = true; f.M = o; f.N = vv; f.K = o; f.alpha = -1.f; f.beta = 1.f; f.A = fof + q * oo; f.lda = o;
@@ -1551,8 +1575,8 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
       g.sC = vv; g.batch = oo;
       gemm(g, s);
     }
-    hipLaunchKernelGGL(zp_finish_kernel, dim3(grid1(nb * oovv)), dim3(256), 0, s, nb * oovv, (int64_t)v, zf, R2,
-                       (const double*)c.Fvvd);
+    hipLaunchKernelGGL(zp_finish_kernel, dim3(grid1(nb * oovv)), dim3(256), 0, s, nb * oovv, (int64_t)o, (int64_t)v,
+                       zf, R2, (const double*)c.Fvvd, (const double*)c.Food);
     PNO_HIP(hipGetLastError());
     if (!fold) to_double(s, nb * oovv, zf, w.Zp, 0.0);
   } else {
