@@ -68,6 +68,8 @@ struct PNOData {
   GroupTable t_na, t_nb;
   DBuf<int> d_nn, d_nch;         // per native pair: n_p, K chunks
   DBuf<int64_t> d_poff, d_yoff;  // per native pair: first partial block, block in the compressed vector
+  DBuf<int64_t> d_small;        // native pairs with n_p <= 16 (fused kernel): n, Bbar, vector, partial offsets
+  int nsmall = 0;
   double nat_flops = 0;         // flops of the native ladder of one vector
   void reset() {
     built = false;
@@ -77,7 +79,7 @@ struct PNOData {
     Tw.release(); r1.release(); r2.release(); s1.release(); s2.release();
     nat_cut = nat_pairs = canon_pairs = 0;
     prow.clear(); d_prow.release(); d_slot.release(); Bbar.release(); Y1.release(); Ypart.release(); nat_flops = 0;
-    d_nn.release(); d_nch.release(); d_poff.release(); d_yoff.release();
+    d_nn.release(); d_nch.release(); d_poff.release(); d_yoff.release(); d_small.release(); nsmall = 0;
   }
 };
 

@@ -327,6 +327,55 @@ void batched_syev(hipStream_t s, int nmat, const std::vector<int>& nsz, int ld, 
 
 // ----------------------------------------------------------------------------- build
 namespace {
+// Native ladder of the pairs with n_p <= kNatSmall in one kernel: workgroup (ch, g) forms the
+// partial sum over Q in [ch kNatQ, ch kNatQ + kNatQ) of Bbar^Q Rbar Bbar^Q^T for small pair g
+// (tab[4 g ..]: n, Bbar offset, offset of Rbar in x, partial-block offset), FP64, without the
+// Y1 intermediate.  The 256 threads form 256 / n^2 lanes of n^2 threads, one (a, b) each; lane
+// l takes every (256 / n^2)-th Q: T = Bbar^Q Rbar into LDS, then S[a][b] += T[a][:] . Bbar^Q[b][:].
+constexpr int kNatSmall = 16, kNatQ = 64;
+__global__ __launch_bounds__(256) void native_small_kernel(int naux, const int64_t* __restrict__ tab,
+                                                           const double* __restrict__ Bbar,
+                                                           const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double Rs[kNatSmall * kNatSmall];
+  __shared__ double Bq[256];
+  __shared__ double Ts[256];
+  const int64_t* t = tab + 4 * (int64_t)blockIdx.y;
+  const int n = (int)t[0];
+  const int64_t boff = t[1], roff = t[2], poff = t[3];
+  const int n2 = n * n, nl = 256 / n2;
+  const int tid = threadIdx.x, lane = tid / n2, e = tid % n2, a = e / n, b = e % n;
+  const bool act = lane < nl;
+  const int q0 = blockIdx.x * kNatQ, q1 = min(q0 + kNatQ, naux);
+  for (int i = tid; i < n2; i += 256) Rs[i] = x[roff + i];
+  double acc = 0.0;
+  const int steps = (q1 - q0 + nl - 1) / nl;
+  for (int st = 0; st < steps; ++st) {
+    const int Q = q0 + st * nl + lane;
+    __syncthreads();  // Rs written; the previous step's reads of Bq and Ts done
+    if (act) Bq[lane * n2 + e] = Q < q1 ? Bbar[boff + ((int64_t)a * naux + Q) * n + b] : 0.0;
+    __syncthreads();
+    if (act) {
+      double sm = 0.0;
+      for (int c = 0; c < n; ++c) sm += Bq[lane * n2 + a * n + c] * Rs[c * n + b];
+      Ts[lane * n2 + e] = sm;
+    }
+    __syncthreads();
+    if (act) {
+      double sm = 0.0;
+      for (int d = 0; d < n; ++d) sm += Ts[lane * n2 + a * n + d] * Bq[lane * n2 + b * n + d];
+      acc += sm;
+    }
+  }
+  __syncthreads();
+  if (act) Ts[lane * n2 + e] = acc;
+  __syncthreads();
+  if (tid < n2) {
+    double sm = 0.0;
+    for (int l = 0; l < nl; ++l) sm += Ts[l * n2 + tid];
+    part[poff + (int64_t)blockIdx.x * n2 + tid] = sm;
+  }
+}
+
 // y[yoff[g] + e] += sum_ch part[poff[g] + ch n^2 + e] for e < n^2 = nn[g]^2 (one workgroup per pair g)
 __global__ void sum_chunks_kernel(const int* __restrict__ nn, const int* __restrict__ nch,
                                   const int64_t* __restrict__ poff, const int64_t* __restrict__ yoff,
@@ -398,7 +447,11 @@ void build_native_ladder(Context& c, const std::vector<int>& pi, const std::vect
   }
   if (P.nat_pairs == 0) return;
   P.Bbar.alloc(bw);
-  P.Y1.alloc(bw);
+  {
+    bool large = false;  // Y1 (offsets of Bbar) for the pairs the fused small-pair kernel does not take
+    for (int p = 0; p < npair; ++p) large = large || (boff[p] >= 0 && P.npno[p] > kNatSmall);
+    if (large) P.Y1.alloc(bw);
+  }
   // Bbar_p[a][Q][k] = sum_xy U_p[x][a] B~^Q[o+x][o+y] U_p[y][k], two batched GEMMs over Q per pair
   DBuf<double> T1;
   T1.alloc((int64_t)naux * v * nmax);
@@ -424,11 +477,21 @@ void build_native_ladder(Context& c, const std::vector<int>& pi, const std::vect
   // block (so that every pair spreads over several workgroups), summed by a reduction
   std::vector<GroupDesc> ga, gb;
   std::vector<int> hn, hch;
-  std::vector<int64_t> hpoff, hyoff;
+  std::vector<int64_t> hpoff, hyoff, hsmall;
   int64_t pw = 0;
   for (int p = 0; p < npair; ++p) {
     if (boff[p] < 0) continue;
     const int64_t n = P.npno[p];
+    if (n <= kNatSmall) {  // fused small-pair kernel: partial blocks per kNatQ values of Q
+      const int64_t nch = (naux + kNatQ - 1) / kNatQ;
+      hsmall.insert(hsmall.end(), {n, boff[p], P.off[o + p], pw});
+      hn.push_back((int)n);
+      hch.push_back((int)nch);
+      hpoff.push_back(pw);
+      hyoff.push_back(P.off[o + p]);
+      pw += nch * n * n;
+      continue;
+    }
     GroupDesc d{};
     d.M = n * naux; d.N = n; d.K = n; d.offA = boff[p]; d.lda = n; d.offB = P.off[o + p]; d.ldb = n;
     d.offC = boff[p]; d.ldc = n;
@@ -458,6 +521,11 @@ void build_native_ladder(Context& c, const std::vector<int>& pi, const std::vect
   PNO_HIP(hipMemcpy(P.d_nch, hch.data(), nn * sizeof(int), hipMemcpyHostToDevice));
   PNO_HIP(hipMemcpy(P.d_poff, hpoff.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice));
   PNO_HIP(hipMemcpy(P.d_yoff, hyoff.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice));
+  P.nsmall = (int)(hsmall.size() / 4);
+  if (P.nsmall > 0) {
+    P.d_small.alloc((int64_t)hsmall.size());
+    PNO_HIP(hipMemcpy(P.d_small, hsmall.data(), hsmall.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  }
   PNO_HIP(hipStreamSynchronize(s));
 }
 }  // namespace
@@ -929,10 +997,16 @@ void sigma_pno(Context& c, int nvec, const double* x, double* y, int precision) 
     }
     pno_compress(c, n, P.s1, P.s2, y + (int64_t)q0 * P.len);
   }
-  // the native pairs' ladder, added in the PNO space (FP64 grouped MFMA GEMMs)
+  // the native pairs' ladder, added in the PNO space (FP64: the fused small-pair kernel for
+  // n_p <= 16, grouped MFMA GEMMs for the others)
   if (P.nat_pairs > 0) {
     hipEvent_t ev = c.region_begin(4, c.stream);
+    PNO_CHECK(P.nsmall <= 65535, PNOEOM_EINVAL, "native ladder: too many pairs for one launch");
     for (int q = 0; q < nvec; ++q) {
+      if (P.nsmall > 0)
+        hipLaunchKernelGGL(native_small_kernel, dim3((unsigned)((c.naux + kNatQ - 1) / kNatQ), (unsigned)P.nsmall),
+                           dim3(256), 0, c.stream, c.naux, (const int64_t*)P.d_small, (const double*)P.Bbar,
+                           (const double*)(x + (int64_t)q * P.len), (double*)P.Ypart);
       gemm_grouped(P.t_na, 1.0, P.Bbar, x + (int64_t)q * P.len, 0.0, P.Y1, c.stream);
       gemm_grouped(P.t_nb, 1.0, P.Y1, P.Bbar, 0.0, P.Ypart, c.stream);
       hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)P.nat_pairs), dim3(256), 0, c.stream,
