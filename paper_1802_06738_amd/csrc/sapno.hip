@@ -349,22 +349,39 @@ __global__ __launch_bounds__(256) void native_small_kernel(int naux, const int64
   for (int i = tid; i < n2; i += 256) Rs[i] = x[roff + i];
   double acc = 0.0;
   const int steps = (q1 - q0 + nl - 1) / nl;
-  for (int st = 0; st < steps; ++st) {
+  // this thread's element of Bbar^Q at step st; the elements of the next kPre steps are loaded
+  // while the current ones are used
+  constexpr int kPre = 8;
+  auto bval = [&](int st) -> double {
     const int Q = q0 + st * nl + lane;
-    __syncthreads();  // Rs written; the previous step's reads of Bq and Ts done
-    if (act) Bq[lane * n2 + e] = Q < q1 ? Bbar[boff + ((int64_t)a * naux + Q) * n + b] : 0.0;
-    __syncthreads();
-    if (act) {
-      double sm = 0.0;
-      for (int c = 0; c < n; ++c) sm += Bq[lane * n2 + a * n + c] * Rs[c * n + b];
-      Ts[lane * n2 + e] = sm;
+    return act && st < steps && Q < q1 ? Bbar[boff + ((int64_t)a * naux + Q) * n + b] : 0.0;
+  };
+  double cur[kPre], nxt[kPre];
+#pragma unroll
+  for (int k = 0; k < kPre; ++k) cur[k] = bval(k);
+  for (int g0 = 0; g0 < steps; g0 += kPre) {
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) nxt[k] = bval(g0 + kPre + k);
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+      if (g0 + k >= steps) break;  // (uniform)
+      __syncthreads();  // Rs written; the previous step's reads of Bq and Ts done
+      if (act) Bq[lane * n2 + e] = cur[k];
+      __syncthreads();
+      if (act) {
+        double sm = 0.0;
+        for (int c = 0; c < n; ++c) sm += Bq[lane * n2 + a * n + c] * Rs[c * n + b];
+        Ts[lane * n2 + e] = sm;
+      }
+      __syncthreads();
+      if (act) {
+        double sm = 0.0;
+        for (int d = 0; d < n; ++d) sm += Ts[lane * n2 + a * n + d] * Bq[lane * n2 + b * n + d];
+        acc += sm;
+      }
     }
-    __syncthreads();
-    if (act) {
-      double sm = 0.0;
-      for (int d = 0; d < n; ++d) sm += Ts[lane * n2 + a * n + d] * Bq[lane * n2 + b * n + d];
-      acc += sm;
-    }
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) cur[k] = nxt[k];
   }
   __syncthreads();
   if (act) Ts[lane * n2 + e] = acc;
