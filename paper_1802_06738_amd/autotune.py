@@ -13,6 +13,10 @@ wider) are chosen per shape.  This tuner
 
 Run on the GPU:
     python -m paper_1802_06738_amd.autotune --config 2 --out /tmp/gemm_gfx950.json
+
+For a workload too large to solve while recording (config 4), `--sigma-blocks` records the
+shapes of a few SA-PNO sigma blocks (BF16 and FP64) instead, times only the shapes below
+`--max-flops`, and adds the entries to those of the table given by `--merge`.
 """
 from __future__ import annotations
 
@@ -104,6 +108,42 @@ def record_shapes(config, log=print):
     return [tuple(buf[8 * i + j] for j in range(8)) for i in range(n)]
 
 
+def record_sigma_blocks(config, log=print):
+    """Shapes of the SA-PNO sigma blocks of a config (one block per precision, BF16 and FP64)."""
+    import torch
+    sys.path.insert(0, os.path.dirname(HERE))
+    from synthgen import config_system, CONFIGS
+    from .pnoeom import load_library, PnoEom, FP64, BF16
+    lib = load_library()
+    cfg = CONFIGS[config]
+    s = config_system(config)
+    dev = torch.device("cuda:0")
+    B = torch.from_numpy(s.B).to(dev)
+    eps = torch.from_numpy(s.eps).to(dev)
+    t1 = torch.from_numpy(s.t1).to(dev)
+    ctx = PnoEom(s.o, s.v, s.naux)
+    ctx.build_df(B, eps, t1, precision=BF16)
+    ctx.build_sapno(cfg["nroots"], cfg.get("tcut_pno", cfg.get("tcut", 1e-7)))
+    _, plen = ctx.pno_layout()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1808)
+    X = torch.randn((cfg["nroots"], plen), generator=gen, dtype=torch.float64, device=dev)
+    lib.pnoeom_gemm_record(1)
+    for prec in (BF16, FP64):
+        t0 = time.time()
+        ctx.sigma_pno(X, precision=prec)
+        torch.cuda.synchronize()
+        log(f"[autotune] recorded a sigma block in precision {prec} ({time.time() - t0:.1f} s)")
+    lib.pnoeom_gemm_record(0)
+    ctx.close()  # (the timing allocates its own operands)
+    del X, B, eps, t1
+    torch.cuda.empty_cache()
+    n = lib.pnoeom_gemm_recorded(None, 0)
+    buf = (C.c_longlong * (8 * max(n, 1)))()
+    lib.pnoeom_gemm_recorded(buf, n)
+    return [tuple(buf[8 * i + j] for j in range(8)) for i in range(n)]
+
+
 def time_key(lib, key, variant, reps):
     k = (C.c_longlong * 8)(*key)
     ms = C.c_double()
@@ -113,16 +153,18 @@ def time_key(lib, key, variant, reps):
     return ms.value
 
 
-def tune(config=2, margin=0.03, log=print):
+def tune(config=2, margin=0.03, log=print, sigma_blocks=False, max_flops=None):
     from .pnoeom import load_library
     lib = load_library()
     clear_table(lib)
-    keys = record_shapes(config, log)
+    keys = record_sigma_blocks(config, log) if sigma_blocks else record_shapes(config, log)
     log(f"[autotune] {len(keys)} GEMM shapes")
     entries = []
     t0 = time.time()
     for i, key in enumerate(keys):
         flops = 2.0 * key[4] * key[5] * key[6] * key[7]
+        if max_flops is not None and flops > max_flops:
+            continue
         reps = 2 if flops > 5e11 else 5
         dv = default_variant(key)
         t_def = time_key(lib, key, dv, reps)
@@ -142,7 +184,8 @@ def tune(config=2, margin=0.03, log=print):
         if (i + 1) % 20 == 0:
             log(f"[autotune] {i + 1}/{len(keys)} shapes timed ({time.time() - t0:.0f} s), "
                 f"{len(entries)} improved")
-    return dict(device="gfx950", workload=f"config {config}", margin=margin, shapes=len(keys), entries=entries)
+    work = f"config {config}" + (" sigma blocks" if sigma_blocks else "")
+    return dict(device="gfx950", workload=work, margin=margin, shapes=len(keys), entries=entries)
 
 
 def main():
@@ -150,8 +193,19 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--margin", type=float, default=0.03)
     ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--sigma-blocks", action="store_true")
+    ap.add_argument("--max-flops", type=float, default=None)
+    ap.add_argument("--merge", default=None, help="table whose entries (other shapes) are kept")
     args = ap.parse_args()
-    tab = tune(args.config, args.margin, log=lambda m: print(m, file=sys.stderr, flush=True))
+    tab = tune(args.config, args.margin, log=lambda m: print(m, file=sys.stderr, flush=True),
+               sigma_blocks=args.sigma_blocks, max_flops=args.max_flops)
+    if args.merge:
+        with open(args.merge) as fh:
+            old = json.load(fh)
+        mine = {tuple(e["key"]) for e in tab["entries"]}
+        tab["entries"] = [e for e in old["entries"] if tuple(e["key"]) not in mine] + tab["entries"]
+        tab["workload"] = old["workload"] + ", " + tab["workload"]
+        tab["shapes"] = old["shapes"] + tab["shapes"]
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as fh:
         json.dump(tab, fh, indent=1)
