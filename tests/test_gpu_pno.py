@@ -188,6 +188,36 @@ def test_pno_sigma_ladder_split_matches_oracle(max_native, streamed):
     assert (t["pno_native_ladder"]["launches"] > 0) == (st["native_pairs"] > 0)
 
 
+@pytest.mark.parametrize("max_native", [6, 1000])
+def test_pno_sigma_bf16_matches_fp64(max_native):
+    """P sigma in BF16 mode (bfloat16 products, FP32 blocks into the assembly, the restricted
+    canonical ladder added into the FP32 direct block, the off-diagonal Foo in the hole ladder)
+    against the FP64 P sigma of the same context, expanded: within 2^-8 max|sigma|, the bound of
+    a product of two bfloat16-rounded operands (as in the canonical BF16 tests)."""
+    print(f"[pno sigma bf16] max_native={max_native}", flush=True)
+    import torch
+    from paper_1802_06738_amd import PnoEom, BF16, FP64
+    o, v, naux, kappa, nst, tcut, seed = SMALL[1]
+    s = make_system(o, v, naux, seed, kappa=kappa, t1_sigma=1e-3)
+    ctx = PnoEom(o, v, naux)
+    ctx.build_df(torch.from_numpy(s.B).cuda(), torch.from_numpy(s.eps).cuda(), torch.from_numpy(s.t1).cuda(),
+                 precision=BF16)
+    ctx.set_pno_ladder(max_native)
+    ctx.build_sapno(nst, tcut)
+    st = ctx.pno_ladder_stats()
+    if max_native == 6:
+        assert st["native_pairs"] > 0 and st["canonical_pairs"] > 0
+    r1, r2 = random_r(o, v, seed + 7, nvec=3)
+    x = ctx.pno_compress(torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda())
+    g1, g2 = (a.cpu().numpy() for a in ctx.pno_expand(ctx.sigma_pno(x, precision=FP64)))
+    b1, b2 = (a.cpu().numpy() for a in ctx.pno_expand(ctx.sigma_pno(x, precision=BF16)))
+    for k in range(3):
+        e1 = np.max(np.abs(b1[k] - g1[k])) / np.max(np.abs(g1[k]))
+        e2 = np.max(np.abs(b2[k] - g2[k])) / np.max(np.abs(g2[k]))
+        print(f"[pno sigma bf16] vector {k}: sigma1 {e1:.2e}, sigma2 {e2:.2e} of max|sigma|", flush=True)
+        assert e1 <= 2.0 ** -8 and e2 <= 2.0 ** -8
+
+
 @pytest.mark.parametrize("states", [[2], [0, 2], [1]])
 def test_state_specific_and_listed_state_pnos(states):
     """PNOs from the densities of listed CIS states (one state: state-specific PNOs):
