@@ -366,31 +366,28 @@ __global__ void ladder_unpack_kernel(int o, int v, int nvec, const InT* __restri
   }
 }
 
-// out[q][x][y][a][b] += sigma_xy^ab of the ladder for the nrow pairs (i <= j) listed in slot_ij
-// (i o + j per slot; rows of sigma+ / sigma- as in ladder_pack_kernel), both blocks (i, j) and
-// (j, i) (sigma_ji^ab = sigma_ij^ba), each written along b; the other pairs are left alone
+// out[q][i][j][a][b] += sigma_ij^ab of the ladder for the nrow pairs (i <= j) listed in slot_ij
+// (i o + j per slot; rows of sigma+ / sigma- as in ladder_pack_kernel), written along b; the
+// blocks (j, i) of those pairs and the other pairs are left alone (the fused-mode assembly
+// reads the direct block at i <= j only)
 __global__ void ladder_unpack_add_kernel(int o, int v, int nvec, int64_t nrow, const float* __restrict__ SP,
                                          const float* __restrict__ SM, const int* __restrict__ slot_ij,
                                          float* __restrict__ out) {
   const int64_t O = o, V = v, VV = V * V, vp = V * (V + 1) / 2, vm = V * (V - 1) / 2;
-  const int64_t total = (int64_t)nvec * nrow * 2 * VV;
+  const int64_t total = (int64_t)nvec * nrow * VV;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     int64_t r = e;
     const int64_t b = r % V; r /= V;
     const int64_t a = r % V; r /= V;
-    const int64_t dir = r % 2; r /= 2;
     const int64_t slot = r % nrow;
     const int64_t q = r / nrow;
     const int64_t ij = slot_ij[slot], i = ij / O, j = ij % O;
-    if (dir == 1 && i == j) continue;
-    const int64_t x = dir ? j : i, y = dir ? i : j;
-    const int64_t aa = dir ? b : a, bb = dir ? a : b;  // sigma_xy^ab = sigma_ij^(aa bb)
     const int64_t row = q * nrow + slot;
     float val;
-    if (aa == bb) val = SP[row * vp + tri_idx(aa, aa, V)];
-    else if (aa < bb) val = SP[row * vp + tri_idx(aa, bb, V)] + SM[row * vm + stri_idx(aa, bb, V)];
-    else val = SP[row * vp + tri_idx(bb, aa, V)] - SM[row * vm + stri_idx(bb, aa, V)];
-    out[q * O * O * VV + (x * O + y) * VV + a * V + b] += val;
+    if (a == b) val = SP[row * vp + tri_idx(a, a, V)];
+    else if (a < b) val = SP[row * vp + tri_idx(a, b, V)] + SM[row * vm + stri_idx(a, b, V)];
+    else val = SP[row * vp + tri_idx(b, a, V)] - SM[row * vm + stri_idx(b, a, V)];
+    out[q * O * O * VV + (i * O + j) * VV + a * V + b] += val;
   }
 }
 
@@ -1063,6 +1060,69 @@ __global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, co
   }
 }
 
+// Fused BF16 mode: sigma2 has the pair symmetry s_ji^ba = s_ij^ab, and so has each block that
+// enters it, so one workgroup per 32 x 32 (a, b) tile of a pair i <= j of vector q forms
+//   s_ij^ab = Sd_ij^ab + D(i,j,a,b) + D(j,i,b,a) + R_ij^ab (Fvv_aa + Fvv_bb - Foo_ii - Foo_jj),
+//   D(i,j,a,b) = Zp_ij^ab + Z[(i,a)][(j,b)] + Z'[(j,a)][(i,b)]
+// from the FP32 direct, Fock-type and ring blocks (Z | Z' the two halves of the ring rows) and
+// the orbital-energy terms (dv, doo: diagonals of Fvv and Foo) in FP64, and writes it to (i, j)
+// and, transposed through LDS, to (j, i): every element of the blocks is read once (Sd at
+// (i, j) only).  The D(j,i,b,a) terms are read along a into LDS, the rest along b.
+__global__ __launch_bounds__(256) void assemble_s2_sym_kernel(int o, int v, const float* __restrict__ Sd,
+                                                              const float* __restrict__ Zp,
+                                                              const float* __restrict__ ZZ,
+                                                              const double* __restrict__ R2,
+                                                              const double* __restrict__ dv,
+                                                              const double* __restrict__ doo,
+                                                              double* __restrict__ s2, int64_t stride2) {
+  __shared__ double tile[kAsmTile][kAsmTile + 1];
+  const int64_t V = v, O = o, n = O * O * V * V, ov = O * V, ov2 = 2 * ov;
+  const int ntb = (v + kAsmTile - 1) / kAsmTile;
+  const int a0 = (int)(blockIdx.x / ntb) * kAsmTile, b0 = (int)(blockIdx.x % ntb) * kAsmTile;
+  int64_t p = blockIdx.y, i = 0;  // pair p (i <= j, row-major) -> (i, j)
+  while (p >= O - i) {
+    p -= O - i;
+    ++i;
+  }
+  const int64_t j = i + p, q = blockIdx.z;
+  const int tx = threadIdx.x % kAsmTile, ty = threadIdx.x / kAsmTile;  // 32 x 8
+  const float* zp = Zp + q * n;
+  const float* zz = ZZ + q * 2 * n;
+  // D(j,i,b,a), contiguous along a: tile[b][a]
+  for (int bb = ty; bb < kAsmTile; bb += 256 / kAsmTile) {
+    const int64_t a = a0 + tx, b = b0 + bb;
+    if (a < V && b < V)
+      tile[bb][tx] = (double)zp[((j * O + i) * V + b) * V + a] + (double)zz[(j * V + b) * ov2 + i * V + a] +
+                     (double)zz[(i * V + b) * ov2 + ov + j * V + a];
+  }
+  __syncthreads();
+  double val[kAsmTile / 8];
+  const double fij = doo[i] + doo[j];
+#pragma unroll
+  for (int k = 0; k < kAsmTile / 8; ++k) {
+    const int aa = ty + 8 * k;
+    const int64_t a = a0 + aa, b = b0 + tx;
+    val[k] = 0.0;
+    if (a < V && b < V) {
+      const int64_t e = ((i * O + j) * V + a) * V + b;
+      val[k] = (double)Sd[q * n + e] + (double)zp[e] + (double)zz[(i * V + a) * ov2 + j * V + b] +
+               (double)zz[(j * V + a) * ov2 + ov + i * V + b] + tile[tx][aa] +
+               R2[q * n + e] * (dv[a] + dv[b] - fij);
+      s2[q * stride2 + e] = val[k];
+    }
+  }
+  if (i == j) return;  // (uniform) the mirror tile writes the mirror elements of a diagonal pair
+  __syncthreads();     // the reads of the tile are done
+#pragma unroll
+  for (int k = 0; k < kAsmTile / 8; ++k) tile[ty + 8 * k][tx] = val[k];  // tile[a][b]
+  __syncthreads();
+  // s_ji^ba = s_ij^ab, rows b of pair (j, i) along a
+  for (int bb = ty; bb < kAsmTile; bb += 256 / kAsmTile) {
+    const int64_t a = a0 + tx, b = b0 + bb;
+    if (a < V && b < V) s2[q * stride2 + ((j * O + i) * V + b) * V + a] = tile[tx][bb];
+  }
+}
+
 // The layouts of R2 that the rest of sigma reads, in one pass over R2 (one workgroup per
 // 32 x 32 (a, b) tile of a pair (i, j) of a vector, the tile and its mirror (b, a) in LDS):
 //   Ria[(q,i,a)][(j,b)] = R_ij^ab,   UiaR[(q,i,a)][(j,b)] = UR[q][i][j][a][b] = 2 R_ij^ab - R_ij^ba,
@@ -1324,7 +1384,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
       const int* slot = c.lad_nsub >= 0 ? c.lad_slot : (const int*)c.slot_all;
       PNO_CHECK(slot != nullptr, PNOEOM_ESTATE, "sigma: no pair table of the ladder slots");
       if (nrow > 0) {
-        hipLaunchKernelGGL(ladder_unpack_add_kernel, dim3(grid1((int64_t)nb * nrow * 2 * vv)), dim3(256), 0, s, o, v,
+        hipLaunchKernelGGL(ladder_unpack_add_kernel, dim3(grid1((int64_t)nb * nrow * vv)), dim3(256), 0, s, o, v,
                            nb, nrow, (const float*)w.SigPf, (const float*)w.SigMf, slot, dblk);
         PNO_HIP(hipGetLastError());
       }
@@ -1546,8 +1606,9 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   if (bfr && c.Fvob.p && c.Wvo2f.p && c.T32.p) {
     // BF16 scope 1: R (Fvv - diag)^T and T Ftv^T on bfloat16 MFMA, the products with K = o
     // (Fto T, r1 Wvo2) on FP32 MFMA, all into one FP32 sum (operands staged in fa); the
-    // diagonal parts of R Fvv^T and of -Foo^T R are added exactly by zp_finish_kernel, the
-    // off-diagonal part of -Foo^T R rides with the hole ladder (Whb)
+    // diagonal parts of R Fvv^T and of -Foo^T R are added exactly by zp_finish_kernel (by the
+    // assembly in the fused mode), the off-diagonal part of -Foo^T R rides with the hole
+    // ladder (Whb)
     float* fof = w.fa;
     float* r1f = fof + nb * oo;
     const int64_t boff = (nb * (oo + ov) + 3) / 4 * 4;  // floats: bfloat16 rows 16-byte aligned
@@ -1575,10 +1636,13 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
       g.sC = vv; g.batch = oo;
       gemm(g, s);
     }
-    hipLaunchKernelGGL(zp_finish_kernel, dim3(grid1(nb * oovv)), dim3(256), 0, s, nb * oovv, (int64_t)o, (int64_t)v,
-                       zf, R2, (const double*)c.Fvvd, (const double*)c.Food);
-    PNO_HIP(hipGetLastError());
-    if (!fold) to_double(s, nb * oovv, zf, w.Zp, 0.0);
+    // (the fused mode's assembly adds the orbital-energy terms itself)
+    if (!fold) {
+      hipLaunchKernelGGL(zp_finish_kernel, dim3(grid1(nb * oovv)), dim3(256), 0, s, nb * oovv, (int64_t)o,
+                         (int64_t)v, zf, R2, (const double*)c.Fvvd, (const double*)c.Food);
+      PNO_HIP(hipGetLastError());
+      to_double(s, nb * oovv, zf, w.Zp, 0.0);
+    }
   } else {
     gm(s, false, true, (int64_t)nb * oo * v, v, v, 1.0, R2, v, c.Fvv, v, 0.0, w.Zp, v);
     gmb(s, false, true, oo * v, v, v, 1.0, c.T, v, 0, w.Ftv, v, vv, 1.0, w.Zp, v, oovv, nb);
@@ -1595,9 +1659,9 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     const unsigned ntb = (unsigned)((v + kAsmTile - 1) / kAsmTile);
     PNO_CHECK((int64_t)o * o <= 65535 && nb <= 65535, PNOEOM_EINVAL, "sigma: too many pairs or vectors per block");
     if (fold)
-      hipLaunchKernelGGL((assemble_s2_tiled_kernel<float, float>), dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb),
-                         dim3(256), 0, s, o, v, (const float*)w.Sdf, (const float*)w.fz, (const float*)w.fc, s2,
-                         stride2);
+      hipLaunchKernelGGL(assemble_s2_sym_kernel, dim3(ntb * ntb, (unsigned)(o * (o + 1) / 2), (unsigned)nb), dim3(256),
+                         0, s, o, v, (const float*)w.Sdf, (const float*)w.fz, (const float*)w.fc, R2,
+                         (const double*)c.Fvvd, (const double*)c.Food, s2, stride2);
     else
       hipLaunchKernelGGL((assemble_s2_tiled_kernel<double, double>), dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb),
                          dim3(256), 0, s, o, v, (const double*)Sd, (const double*)w.Zp, (const double*)w.ZZ, s2,
