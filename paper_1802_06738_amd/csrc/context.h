@@ -143,6 +143,7 @@ struct Context {
   // [Q][(jb)] (M1), BYU^T and YU^T as [(kc)][Q] (DF ring terms, rows of ldq), and Yr with
   // its last two indices swapped, [(a, n)][c] (R1 term of the ring)
   DBuf<uint16_t> Whb, g2b, TTb, BovQb, BYUb, YUb, Yrb;
+  DBuf<uint16_t> Whbs;  // the rows (i <= j) of Whb, pairs in row-major order (fused BF16 mode)
   DBuf<uint16_t> Gqb;  // Gq^T as [b][(k,l,d)] (Ftv), rows of ldg
   // T as rows [(i,j,a)][c] and Fvv without its diagonal as rows [b][c] (rows of ldv; the
   // Fock-type products T Ftv^T and R (Fvv - diag)^T), and the diagonal of Fvv

@@ -374,7 +374,7 @@ void build_ladder(Context& c, const double* B, const double* t1, int precision, 
   for (DBuf<float>* b : {&c.Wpf, &c.Wmf, &c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf, &c.BYUf, &c.YUf,
                          &c.Foof, &c.Wvo2f, &c.Zrf})
     b->release();
-  for (DBuf<uint16_t>* b : {&c.Whb, &c.g2b, &c.TTb, &c.BovQb, &c.BYUb, &c.YUb, &c.Yrb, &c.DXb, &c.DX2b, &c.Gqb,
+  for (DBuf<uint16_t>* b : {&c.Whb, &c.Whbs, &c.g2b, &c.TTb, &c.BovQb, &c.BYUb, &c.YUb, &c.Yrb, &c.DXb, &c.DX2b, &c.Gqb,
                             &c.Tvb, &c.Fvob})
     b->release();
   c.Fvvd.release();

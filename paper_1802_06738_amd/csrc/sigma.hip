@@ -206,6 +206,32 @@ __global__ void wh_foo_rows_bf16_kernel(int64_t o, const double* __restrict__ Wh
   }
 }
 
+// row p of a pair-compacted array <- row (i o + j) of the full one, for the pairs p = (i <= j)
+// in row-major order (i, then j >= i); one workgroup per destination row (nvec x o(o+1)/2
+// rows: grid.y = vector, grid.x = pair), FP64 source rows of K values converted to bfloat16
+// rows of ld (zero beyond K), or bfloat16 rows copied (src16)
+__device__ __forceinline__ void pair_of(int64_t p, int64_t o, int64_t& i, int64_t& j) {
+  i = 0;
+  while (p >= o - i) {
+    p -= o - i;
+    ++i;
+  }
+  j = i + p;
+}
+__global__ void pair_rows_gather_kernel(int o, int64_t K, const double* __restrict__ src,
+                                        const uint16_t* __restrict__ src16, int64_t ld, uint16_t* __restrict__ dst) {
+  const int64_t O = o, np = O * (O + 1) / 2, p = blockIdx.x, q = blockIdx.y;
+  int64_t i, j;
+  pair_of(p, O, i, j);
+  const int64_t srow = (q * O + i) * O + j, drow = q * np + p;
+  for (int64_t c = threadIdx.x; c < ld; c += blockDim.x) {
+    if (src16)
+      dst[drow * ld + c] = src16[srow * ld + c];
+    else
+      dst[drow * ld + c] = c < K ? bf16_bits(src[srow * K + c]) : (uint16_t)0;
+  }
+}
+
 // out[q][a][(p, c)] = bf16(U[q][p][a][c]) for pairs p < npair (U: [nb][npair][v][v]), rows of
 // ld values, zero beyond npair v: the left operand of Ftv = -sum_(p,c) U[p][a][c] Gq[(p,c)][b]
 __global__ void pair_rows_bf16_kernel(int64_t nb, int64_t npair, int64_t v, const double* __restrict__ U,
@@ -366,10 +392,9 @@ __global__ void ladder_unpack_kernel(int o, int v, int nvec, const InT* __restri
   }
 }
 
-// out[q][i][j][a][b] += sigma_ij^ab of the ladder for the nrow pairs (i <= j) listed in slot_ij
-// (i o + j per slot; rows of sigma+ / sigma- as in ladder_pack_kernel), written along b; the
-// blocks (j, i) of those pairs and the other pairs are left alone (the fused-mode assembly
-// reads the direct block at i <= j only)
+// out[q][p][a][b] += sigma_ij^ab of the ladder for the nrow pairs p = (i <= j) listed in slot_ij
+// (i o + j per slot; rows of sigma+ / sigma- as in ladder_pack_kernel; out holds the pairs
+// i <= j in row-major order, the fused mode's direct block), written along b
 __global__ void ladder_unpack_add_kernel(int o, int v, int nvec, int64_t nrow, const float* __restrict__ SP,
                                          const float* __restrict__ SM, const int* __restrict__ slot_ij,
                                          float* __restrict__ out) {
@@ -387,7 +412,7 @@ __global__ void ladder_unpack_add_kernel(int o, int v, int nvec, int64_t nrow, c
     if (a == b) val = SP[row * vp + tri_idx(a, a, V)];
     else if (a < b) val = SP[row * vp + tri_idx(a, b, V)] + SM[row * vm + stri_idx(a, b, V)];
     else val = SP[row * vp + tri_idx(b, a, V)] - SM[row * vm + stri_idx(b, a, V)];
-    out[q * O * O * VV + (i * O + j) * VV + a * V + b] += val;
+    out[(q * (O * (O + 1) / 2) + pair_idx(i, j, O)) * VV + a * V + b] += val;
   }
 }
 
@@ -441,7 +466,7 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
   for (DBuf<float>* b : {&c.DX2f, &c.DXTTf, &c.Whf, &c.g2f, &c.T32, &c.BovTf, &c.BYUf, &c.YUf, &c.Foof,
                          &c.Wvo2f, &c.Zrf})
     b->release();
-  for (DBuf<uint16_t>* b : {&c.Whb, &c.g2b, &c.TTb, &c.BovQb, &c.BYUb, &c.YUb, &c.Yrb, &c.DXb, &c.DX2b, &c.Gqb,
+  for (DBuf<uint16_t>* b : {&c.Whb, &c.Whbs, &c.g2b, &c.TTb, &c.BovQb, &c.BYUb, &c.YUb, &c.Yrb, &c.DXb, &c.DX2b, &c.Gqb,
                             &c.Tvb, &c.Fvob})
     b->release();
   c.Fvvd.release();
@@ -777,6 +802,9 @@ void build_df(Context& c, const double* Bin, const double* epsin, const double* 
     c.Food.alloc(o);
     hipLaunchKernelGGL(wh_foo_rows_bf16_kernel, dim3(grid1(oo * c.ldoo)), dim3(256), 0, s, (int64_t)o,
                        (const double*)c.Wh, (const double*)c.Foo, (uint16_t*)c.Whb, c.ldoo, (double*)c.Food);
+    c.Whbs.alloc((int64_t)o * (o + 1) / 2 * c.ldoo);
+    hipLaunchKernelGGL(pair_rows_gather_kernel, dim3((unsigned)(o * (o + 1) / 2), 1), dim3(256), 0, s, o, (int64_t)0,
+                       (const double*)nullptr, (const uint16_t*)c.Whb, c.ldoo, (uint16_t*)c.Whbs);
     PNO_HIP(hipGetLastError());
     bf16_rows(s, oo, vv, c.g2, vv, 1, c.g2b, c.ldvv, c.ldvv);
     auto tr = [&](int64_t R, int64_t C, const double* src, int64_t sb, uint16_t* dst, int64_t ld, int64_t db,
@@ -894,7 +922,9 @@ int64_t rest_bytes_per_vector(const Context& c, int precision, bool r2c) {
                oo + vv + oo +
                (c.ring_y ? ov : 0);
   int64_t bytes = nd * (int64_t)sizeof(double);
-  if (fold) bytes += ov * c.kfold * (int64_t)sizeof(uint16_t) + 2 * oovv * (int64_t)sizeof(float);  // RAb, fz, Sdf
+  if (fold)  // RAb, fz, Sdf (pairs i <= j)
+    bytes += ov * c.kfold * (int64_t)sizeof(uint16_t) +
+             (oovv + (int64_t)c.o * (c.o + 1) / 2 * vv) * (int64_t)sizeof(float);
   if (f32)  // fa and fc (two oovv each; fa larger when it stages the BF16 operands)
     bytes += (2 * oovv + std::max({2 * oovv, bf16_ring_floats(c, PNOEOM_BF16, 1) + 1,
                                    bf16_rest_values(c, PNOEOM_BF16, 1) / 2 + 1})) *
@@ -952,10 +982,34 @@ int sigma_chunk(Context& c, int nvec, int precision, bool pno) {
 }
 
 namespace {
+// The chunk size counts what the workspaces hold as free, so an array a call of this
+// precision does not use is released before anything is grown
+void trim_sigma_work(Context& c, int precision, bool need_r2c) {
+  SigmaWork& w = c.sw;
+  if (precision == PNOEOM_FP64) {
+    w.fa.release();
+    w.fc.release();
+  }
+  if (ring_fold(c, precision)) {  // (the fused BF16 ring mode keeps the ring block and the
+                                  // Fock-type sum in FP32 (fc, fz): no FP64 ZZ, Ria or RE)
+    w.Ria.release();
+    w.RE.release();
+    w.ZZ.release();
+    w.LadAll.release();
+  } else {
+    w.RAb.release();
+    w.fz.release();
+    w.Sdf.release();
+  }
+  if (!need_r2c) w.R2c.release();
+}
+
 void alloc_sigma_work(Context& c, int precision, int nb, bool need_r2c) {
   SigmaWork& w = c.sw;
   const int64_t n2 = (int64_t)c.nmo * c.nmo, ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v;
   const int64_t oovv = c.oovv(), B = nb;
+  const bool fold = ring_fold(c, precision);
+  trim_sigma_work(c, precision, need_r2c);
   // one-vector scratch of the R1 one-index transformation
   if (c.ring_y)
     grow(w.Bc, (int64_t)c.naux * c.nmo * c.o);
@@ -966,26 +1020,13 @@ void alloc_sigma_work(Context& c, int precision, int nb, bool need_r2c) {
   grow(w.fp_ov, B * ov); grow(w.fp_vv, B * vv); grow(w.fp_oo, B * oo);
   grow(w.BvopT, B * ov * c.naux); grow(w.BoopT, B * oo * c.naux);
   if (!c.ring_y) grow(w.BvvpT, B * vv * c.naux);
-  if (need_r2c)
-    grow(w.R2c, B * oovv);
-  else
-    w.R2c.release();
+  if (need_r2c) grow(w.R2c, B * oovv);
   grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
-  // (the chunk size counts what the workspaces hold as free: an array this call does not use
-  // is released rather than kept)
-  // (the fused BF16 ring mode keeps the ring block and the Fock-type sum in FP32 (fc, fz) for
-  // the assembly: no FP64 ZZ)
-  if (ring_fold(c, precision)) {
-    w.Ria.release();
-    w.RE.release();
-    w.ZZ.release();
+  if (fold) {
     grow(w.RAb, B * c.ov() * c.kfold);
     grow(w.fz, B * oovv);
-    grow(w.Sdf, B * oovv);
+    grow(w.Sdf, B * (int64_t)c.o * (c.o + 1) / 2 * vv);
   } else {
-    w.RAb.release();
-    w.fz.release();
-    w.Sdf.release();
     grow(w.Ria, B * oovv);
     grow(w.RE, (c.ring_y ? 1 : 2) * B * oovv);
     grow(w.ZZ, 2 * B * oovv);
@@ -1064,7 +1105,8 @@ __global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, co
 // enters it, so one workgroup per 32 x 32 (a, b) tile of a pair i <= j of vector q forms
 //   s_ij^ab = Sd_ij^ab + D(i,j,a,b) + D(j,i,b,a) + R_ij^ab (Fvv_aa + Fvv_bb - Foo_ii - Foo_jj),
 //   D(i,j,a,b) = Zp_ij^ab + Z[(i,a)][(j,b)] + Z'[(j,a)][(i,b)]
-// from the FP32 direct, Fock-type and ring blocks (Z | Z' the two halves of the ring rows) and
+// from the FP32 direct (pairs i <= j in row-major order), Fock-type and ring blocks (Z | Z' the
+// two halves of the ring rows) and
 // the orbital-energy terms (dv, doo: diagonals of Fvv and Foo) in FP64, and writes it to (i, j)
 // and, transposed through LDS, to (j, i): every element of the blocks is read once (Sd at
 // (i, j) only).  The D(j,i,b,a) terms are read along a into LDS, the rest along b.
@@ -1105,7 +1147,7 @@ __global__ __launch_bounds__(256) void assemble_s2_sym_kernel(int o, int v, cons
     val[k] = 0.0;
     if (a < V && b < V) {
       const int64_t e = ((i * O + j) * V + a) * V + b;
-      val[k] = (double)Sd[q * n + e] + (double)zp[e] + (double)zz[(i * V + a) * ov2 + j * V + b] +
+      val[k] = (double)Sd[(q * (O * (O + 1) / 2) + blockIdx.y) * V * V + a * V + b] + (double)zp[e] + (double)zz[(i * V + a) * ov2 + j * V + b] +
                (double)zz[(j * V + a) * ov2 + ov + i * V + b] + tile[tx][aa] +
                R2[q * n + e] * (dv[a] + dv[b] - fij);
       s2[q * stride2 + e] = val[k];
@@ -1197,6 +1239,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   const int o = c.o, v = c.v, nmo = c.nmo, naux = c.naux;
   const int64_t n2 = (int64_t)nmo * nmo, ov = c.ov(), oo = (int64_t)o * o, vv = (int64_t)v * v;
   const int64_t oovv = c.oovv(), oon = oo * naux, ovn = ov * naux, vvn = vv * naux, o4 = oo * oo;
+  const int64_t npair = (int64_t)o * (o + 1) / 2;
   const bool f32 = precision != PNOEOM_FP64;  // FP32 or BF16: FP32 contractions here
   alloc_sigma_work(c, precision, nb, stride2 != oovv);
 
@@ -1349,10 +1392,13 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     hipLaunchKernelGGL(bf16_transpose_kernel, dim3((unsigned)((vv + 31) / 32), (unsigned)((c.ldoo + 31) / 32), (unsigned)nb),
                        dim3(256), 0, s, oo, vv, R2, oovv, hb, c.ldoo, vv * c.ldoo);
     PNO_HIP(hipGetLastError());
-    // (the fused mode keeps this direct block in FP32: Sdf, the ladder added into it below)
+    // (the fused mode keeps this direct block in FP32, Sdf, for the pairs i <= j only (the
+    // assembly reads no other): rows of Whbs, the ladder added into it below)
     float* dblk = fold ? (float*)w.Sdf : (float*)w.fc;
+    const int64_t nrw = fold ? npair : oo;  // rows (pairs) of the direct block per vector
     for (int q = 0; q < nb; ++q)
-      bgemm(oo, vv, c.ldoo, 1.f, c.Whb, hb + q * vv * c.ldoo, 0.f, dblk + q * oovv, vv);
+      bgemm(nrw, vv, c.ldoo, 1.f, fold ? (const uint16_t*)c.Whbs : (const uint16_t*)c.Whb, hb + q * vv * c.ldoo, 0.f,
+            dblk + q * nrw * vv, vv);
     // Xh[(q,i,j)][(kl)] = sum_(ab) R2[(q,i,j)][(ab)] g2[(kl)][(ab)], into fc after the ladder block
     rows_bf16(nb * oo, vv, R2, vv, hb, c.ldvv);
     bgemm(nb * oo, oo, c.ldvv, 1.f, hb, c.g2b, 0.f, w.fc + nb * oovv, oo);
@@ -1373,10 +1419,17 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     permute_c(s, dims, pp, 1.0, w.O4p, 1.0, w.Xh, nb);
   }
   if (bfr) {
-    // Sd[q] += Xh[q] T, all vectors in one product onto the ladder block in fc
-    rows_bf16(nb * oo, oo, w.Xh, oo, hb, c.ldoo);
+    // Sd[q] += Xh[q] T, all vectors in one product onto the ladder block in fc (the fused
+    // mode: the rows (q, i <= j) onto Sdf)
     float* dblk = fold ? (float*)w.Sdf : (float*)w.fc;
-    bgemm(nb * oo, vv, c.ldoo, 1.f, hb, c.TTb, 1.f, dblk, vv);
+    if (fold) {
+      hipLaunchKernelGGL(pair_rows_gather_kernel, dim3((unsigned)npair, (unsigned)nb), dim3(256), 0, s, o, oo,
+                         (const double*)w.Xh, (const uint16_t*)nullptr, c.ldoo, hb);
+      PNO_HIP(hipGetLastError());
+    } else {
+      rows_bf16(nb * oo, oo, w.Xh, oo, hb, c.ldoo);
+    }
+    bgemm(nb * (fold ? npair : oo), vv, c.ldoo, 1.f, hb, c.TTb, 1.f, dblk, vv);
     if (fold) {
       // + the particle ladder of the pairs that keep the canonical ladder (packed results
       // of this chunk in SigPf / SigMf)
@@ -1749,9 +1802,24 @@ void ladder_pack(Context& c, int precision, int o, int nvec, const double* r2, i
   const int64_t rows = std::max<int64_t>((int64_t)nvec * nrow, 1);
   const int64_t tot = (int64_t)nvec * o * o * v * v;
   const bool f32 = precision == PNOEOM_FP32, bf = precision == PNOEOM_BF16;
+  // (the other precisions' operands are released: the chunk size counts them as free)
+  if (!f32) {
+    w.Spf.release();
+    w.Amf.release();
+  }
+  if (!bf) {
+    w.Spb.release();
+    w.Amb.release();
+  }
   if (f32 || bf) {
+    w.Sp.release();
+    w.Am.release();
+    w.SigP.release();
+    w.SigM.release();
     grow(w.SigPf, rows * vp); grow(w.SigMf, rows * vm1);
   } else {
+    w.SigPf.release();
+    w.SigMf.release();
     grow(w.SigP, rows * vp); grow(w.SigM, rows * vm1);
   }
   if (f32) {
@@ -1943,6 +2011,7 @@ void sigma_block_chunk(Context& c, int nvec, const double* r1, const double* r2,
   // (the fused BF16 ring mode adds the packed ladder results into its FP32 direct block inside
   // sigma_rest_block: no FP64 unpacked ladder)
   const bool defer = ring_fold(c, precision);
+  trim_sigma_work(c, precision, stride2 != oovv);
   if (c.lad_nsub < 0 && (int64_t)c.slot_all.n < nrow) {
     std::vector<int> all;
     for (int i = 0; i < o; ++i)
