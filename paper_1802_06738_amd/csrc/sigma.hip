@@ -915,9 +915,10 @@ int64_t rest_bytes_per_vector(const Context& c, int precision, bool r2c) {
   const bool fold = ring_fold(c, precision);
   const int64_t ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, oovv = c.oovv();
   // 9 o^2 v^2 arrays (Ria, UiaR, UR, ZZ x 2, RE x 2, Zp, OOVVp), 7 when the E_X products go
-  // through Yr / Zr (RE holds R^s only, no OOVVp), 3 with the fused BF16 ring product (no Ria,
-  // no RE: their bfloat16 rows go to RAb; no ZZ: the ring block stays FP32), + R2c for strided input
-  const int64_t narr = (c.ring_y ? (fold ? 3 : 7) : 9) + (r2c ? 1 : 0);
+  // through Yr / Zr (RE holds R^s only, no OOVVp), 2 with the fused BF16 ring product (no Ria,
+  // no RE: their bfloat16 rows go to RAb; no ZZ, no Zp: the ring block and the Fock-type sum
+  // stay FP32), + R2c for strided input
+  const int64_t narr = (c.ring_y ? (fold ? 2 : 7) : 9) + (r2c ? 1 : 0);
   int64_t nd = narr * oovv + (ov + oo + (c.ring_y ? 0 : vv)) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv +
                oo + vv + oo +
                (c.ring_y ? ov : 0);
@@ -996,6 +997,7 @@ void trim_sigma_work(Context& c, int precision, bool need_r2c) {
     w.RE.release();
     w.ZZ.release();
     w.LadAll.release();
+    w.Zp.release();
   } else {
     w.RAb.release();
     w.fz.release();
@@ -1031,7 +1033,7 @@ void alloc_sigma_work(Context& c, int precision, int nb, bool need_r2c) {
     grow(w.RE, (c.ring_y ? 1 : 2) * B * oovv);
     grow(w.ZZ, 2 * B * oovv);
   }
-  grow(w.Zp, B * oovv);
+  if (!fold) grow(w.Zp, B * oovv);  // (the FP64 sum of the Fock-type products)
   if (c.ring_y)
     grow(w.R1c, B * ov);
   else
@@ -1168,13 +1170,13 @@ __global__ __launch_bounds__(256) void assemble_s2_sym_kernel(int o, int v, cons
 // The layouts of R2 that the rest of sigma reads, in one pass over R2 (one workgroup per
 // 32 x 32 (a, b) tile of a pair (i, j) of a vector, the tile and its mirror (b, a) in LDS):
 //   Ria[(q,i,a)][(j,b)] = R_ij^ab,   UiaR[(q,i,a)][(j,b)] = UR[q][i][j][a][b] = 2 R_ij^ab - R_ij^ba,
-//   URp[q][i][j][a][b] = 2 R_ij^ba - R_ij^ab,   R^s[(q,i,b)][(j,a)] = R_ij^ab (rows of ldre in RE)
+//   R^s[(q,i,b)][(j,a)] = R_ij^ab (rows of ldre in RE)
 // every store runs along a row segment of 32 consecutive values (R^s through the LDS transpose)
 //   (fused BF16 ring product: -R^s and R_ia instead as bfloat16 into the rows of RAb, the
 //    first two blocks of ldr values of rows of ldra, and no FP64 Ria / RE)
 __global__ __launch_bounds__(256) void r2_layouts_kernel(int o, int v, const double* __restrict__ R2,
                                                          double* __restrict__ Ria, double* __restrict__ UiaR,
-                                                         double* __restrict__ UR, double* __restrict__ URp,
+                                                         double* __restrict__ UR,
                                                          double* __restrict__ RE, int64_t ldre,
                                                          uint16_t* __restrict__ RAb, int64_t ldra, int64_t ldr) {
   __shared__ double t[kAsmTile][kAsmTile + 1];  // t[a - a0][b - b0] = R_ij^ab
@@ -1205,7 +1207,6 @@ __global__ __launch_bounds__(256) void r2_layouts_kernel(int o, int v, const dou
         Ria[f] = x;
       UiaR[f] = 2.0 * x - y;
       UR[e] = 2.0 * x - y;
-      URp[e] = 2.0 * y - x;
     }
   }
   for (int r = ty; r < kAsmTile; r += 256 / kAsmTile) {
@@ -1316,16 +1317,14 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   const int64_t nbo = (int64_t)nb * o;
   const int64_t ov2 = 2 * ov;
   const int64_t ldre = c.ring_y ? ov : ov2;  // RE rows: [R^s] or [R^s | E_X]
-  // Ria, R^s (left half of the rows of RE), UiaR = 2 R_ia - R^s, UR and URp (U(R) with a <-> b,
-  // for sigma1; kept in Zp, which is written later) in one pass over R2
-  double* URp = w.Zp;
+  // Ria, R^s (left half of the rows of RE), UiaR = 2 R_ia - R^s and UR in one pass over R2
   const bool fold = ring_fold(c, precision);
   {
     const unsigned ntb = (unsigned)((v + kAsmTile - 1) / kAsmTile);
     PNO_CHECK((int64_t)o * o <= 65535 && nb <= 65535, PNOEOM_EINVAL, "sigma: too many pairs or vectors per block");
     uint16_t* rab = fold ? (uint16_t*)w.RAb : nullptr;
     hipLaunchKernelGGL(r2_layouts_kernel, dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb), dim3(256), 0, s, o, v,
-                       R2, (double*)w.Ria, (double*)w.UiaR, (double*)w.UR, URp, (double*)w.RE, ldre, rab, c.kfold,
+                       R2, (double*)w.Ria, (double*)w.UiaR, (double*)w.UR, (double*)w.RE, ldre, rab, c.kfold,
                        c.ldr);
     PNO_HIP(hipGetLastError());
     if (fold && c.ldr > ov) {  // padding of the -R^s and R_ia blocks of the rows
@@ -1382,7 +1381,11 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   else
     gmb(s, false, false, o, v, (int64_t)v * naux, 1.0, w.M1, (int64_t)v * naux, ovn, c.Bvv2, v, 0, 1.0, s1, v,
         stride1, nb);
-  gmb(s, false, false, o, v, oo * v, -1.0, c.OOOVp, oo * v, 0, URp, v, oovv, 1.0, s1, v, stride1, nb);
+  // s1[q][i][a] -= sum_(k,l,c) OOOV'[i][(k,l,c)] U(R)[q][k][l][a][c]: per vector one product per
+  // pair (k, l) (K = c), summed over the pairs into s1 (U(R) read in place, no a <-> b copy)
+  for (int q = 0; q < nb; ++q)
+    gmb(s, false, true, o, v, v, -1.0, c.OOOVp, oo * v, v, w.UR + q * oovv, v, vv, 1.0, s1 + q * stride1, v, 0, oo,
+        true);
 
   // ---------------------------------------------------------------- sigma2, direct (not P-symmetrised)
   float* R2f = w.fa;             // FP32 staging of R2, then of Xh after it
