@@ -10,6 +10,7 @@ struct SigmaWork {
   DBuf<double> Bp, Bc, hp, Jp, Kp, fp, dp, fp_ov, fp_vv, fp_oo;  // (Bc: occupied columns of B')
   DBuf<double> BvopT, BoopT, BvvpT;
   DBuf<double> R2c, Ria, UiaR, UR;  // (R2c: R2 compacted, only for strided input)
+  DBuf<double> S1p;                  // partial sums of sigma1's U(R)_ia f' term (fused BF16 mode)
   // ZZ[(q,i,a)][Ziajb row | Z3 row]; RE[(q,i,a)][R^s row | E_X row] (the stacked left operand
   // of the fused ring product; R^s rows only when the E_X products go through Yr / Zr)
   DBuf<double> ZZ, RE, Zp, Xh, O4p, OOVVp, M1;
@@ -27,7 +28,7 @@ struct SigmaWork {
   void release() {
     for (DBuf<double>* b : {&Bp, &Bc, &hp, &Jp, &Kp, &fp, &dp, &fp_ov, &fp_vv, &fp_oo, &BvopT, &BoopT, &BvvpT, &R2c, &Ria,
                             &UiaR, &UR, &ZZ, &RE, &Zp, &Xh, &O4p,
-                            &OOVVp, &M1, &R1c, &Ftv, &Fto, &LadAll, &Sp, &Am, &SigP, &SigM})
+                            &OOVVp, &M1, &R1c, &Ftv, &Fto, &LadAll, &Sp, &Am, &SigP, &SigM, &S1p})
       b->release();
     for (DBuf<float>* b : {&Spf, &Amf, &SigPf, &SigMf, &fa, &fc, &fz, &Sdf}) b->release();
     Spb.release();

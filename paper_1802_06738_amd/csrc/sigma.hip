@@ -111,6 +111,8 @@ __global__ void symmetrize_kernel(int o, int v, double* __restrict__ r2) {
   }
 }
 
+constexpr int kAsmTile = 32;  // (a, b) tile edge of the R2 layout and sigma2 assembly kernels
+
 __host__ __device__ __forceinline__ int64_t tri_idx(int64_t c, int64_t d, int64_t v) {  // c <= d
   return c * v - c * (c - 1) / 2 + (d - c);
 }
@@ -915,17 +917,18 @@ int64_t rest_bytes_per_vector(const Context& c, int precision, bool r2c) {
   const bool fold = ring_fold(c, precision);
   const int64_t ov = c.ov(), oo = (int64_t)c.o * c.o, vv = (int64_t)c.v * c.v, oovv = c.oovv();
   // 9 o^2 v^2 arrays (Ria, UiaR, UR, ZZ x 2, RE x 2, Zp, OOVVp), 7 when the E_X products go
-  // through Yr / Zr (RE holds R^s only, no OOVVp), 2 with the fused BF16 ring product (no Ria,
-  // no RE: their bfloat16 rows go to RAb; no ZZ, no Zp: the ring block and the Fock-type sum
-  // stay FP32), + R2c for strided input
-  const int64_t narr = (c.ring_y ? (fold ? 2 : 7) : 9) + (r2c ? 1 : 0);
+  // through Yr / Zr (RE holds R^s only, no OOVVp), 1 (UR) with the fused BF16 ring product (no
+  // Ria, no RE: their bfloat16 rows go to RAb; no UiaR: its bfloat16 rows go to fa; no ZZ, no
+  // Zp: the ring block and the Fock-type sum stay FP32), + R2c for strided input
+  const int64_t narr = (c.ring_y ? (fold ? 1 : 7) : 9) + (r2c ? 1 : 0);
   int64_t nd = narr * oovv + (ov + oo + (c.ring_y ? 0 : vv)) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv +
                oo + vv + oo +
                (c.ring_y ? ov : 0);
   int64_t bytes = nd * (int64_t)sizeof(double);
-  if (fold)  // RAb, fz, Sdf (pairs i <= j)
+  if (fold)  // RAb, fz, Sdf (pairs i <= j), S1p
     bytes += ov * c.kfold * (int64_t)sizeof(uint16_t) +
-             (oovv + (int64_t)c.o * (c.o + 1) / 2 * vv) * (int64_t)sizeof(float);
+             (oovv + (int64_t)c.o * (c.o + 1) / 2 * vv) * (int64_t)sizeof(float) +
+             ov * c.o * ((c.v + kAsmTile - 1) / kAsmTile) * (int64_t)sizeof(double);
   if (f32)  // fa and fc (two oovv each; fa larger when it stages the BF16 operands)
     bytes += (2 * oovv + std::max({2 * oovv, bf16_ring_floats(c, PNOEOM_BF16, 1) + 1,
                                    bf16_rest_values(c, PNOEOM_BF16, 1) / 2 + 1})) *
@@ -957,7 +960,7 @@ int64_t sigma_held_bytes(const Context& c) {
   const SigmaWork& w = c.sw;
   int64_t b = 0;
   for (const DBuf<double>* x : {&w.Bp, &w.Bc, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT,
-                                &w.BoopT, &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.UR, &w.ZZ,
+                                &w.BoopT, &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.S1p, &w.UR, &w.ZZ,
                                 &w.RE, &w.Zp, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.R1c, &w.Ftv, &w.Fto,
                                 &w.LadAll, &w.Sp, &w.Am, &w.SigP, &w.SigM, &c.pno.r1, &c.pno.r2, &c.pno.s1,
                                 &c.pno.s2})
@@ -998,10 +1001,12 @@ void trim_sigma_work(Context& c, int precision, bool need_r2c) {
     w.ZZ.release();
     w.LadAll.release();
     w.Zp.release();
+    w.UiaR.release();
   } else {
     w.RAb.release();
     w.fz.release();
     w.Sdf.release();
+    w.S1p.release();
   }
   if (!need_r2c) w.R2c.release();
 }
@@ -1023,7 +1028,11 @@ void alloc_sigma_work(Context& c, int precision, int nb, bool need_r2c) {
   grow(w.BvopT, B * ov * c.naux); grow(w.BoopT, B * oo * c.naux);
   if (!c.ring_y) grow(w.BvvpT, B * vv * c.naux);
   if (need_r2c) grow(w.R2c, B * oovv);
-  grow(w.UiaR, B * oovv); grow(w.UR, B * oovv);
+  grow(w.UR, B * oovv);
+  if (fold)  // (U(R)_ia only as bfloat16 rows in fa, sigma1's term as partial sums)
+    grow(w.S1p, B * ov * c.o * ((c.v + kAsmTile - 1) / kAsmTile));
+  else
+    grow(w.UiaR, B * oovv);
   if (fold) {
     grow(w.RAb, B * c.ov() * c.kfold);
     grow(w.fz, B * oovv);
@@ -1070,7 +1079,6 @@ namespace {
 // along a, and adds them transposed to the b-contiguous terms read and written with lanes
 // along b, so that every global access is a contiguous 256-byte row segment.  Zp and ZZ are
 // FP64, or FP32 (BF16 mode: the FP32 accumulators of the bfloat16 products, read as they are)
-constexpr int kAsmTile = 32;
 template <typename TS, typename TZ>
 __global__ __launch_bounds__(256) void assemble_s2_tiled_kernel(int o, int v, const TS* __restrict__ Sd,
                                                                 const TZ* __restrict__ Zp,
@@ -1173,12 +1181,16 @@ __global__ __launch_bounds__(256) void assemble_s2_sym_kernel(int o, int v, cons
 //   R^s[(q,i,b)][(j,a)] = R_ij^ab (rows of ldre in RE)
 // every store runs along a row segment of 32 consecutive values (R^s through the LDS transpose)
 //   (fused BF16 ring product: -R^s and R_ia instead as bfloat16 into the rows of RAb, the
-//    first two blocks of ldr values of rows of ldra, and no FP64 Ria / RE)
+//    first two blocks of ldr values of rows of ldra, and no FP64 Ria / RE; U(R)_ia as bfloat16
+//    rows of ldu (UiaRb, the M1 operand) instead of FP64, and sigma1's U(R)_ia f'_ov term as
+//    partial sums over the b of a tile, s1p[(q,i,a)][(j, b tile)] = sum_b U(R)_ia,jb f'_jb)
 __global__ __launch_bounds__(256) void r2_layouts_kernel(int o, int v, const double* __restrict__ R2,
                                                          double* __restrict__ Ria, double* __restrict__ UiaR,
                                                          double* __restrict__ UR,
                                                          double* __restrict__ RE, int64_t ldre,
-                                                         uint16_t* __restrict__ RAb, int64_t ldra, int64_t ldr) {
+                                                         uint16_t* __restrict__ RAb, int64_t ldra, int64_t ldr,
+                                                         uint16_t* __restrict__ UiaRb, int64_t ldu,
+                                                         const double* __restrict__ fdov, double* __restrict__ s1p) {
   __shared__ double t[kAsmTile][kAsmTile + 1];  // t[a - a0][b - b0] = R_ij^ab
   __shared__ double u[kAsmTile][kAsmTile + 1];  // u[b - b0][a - a0] = R_ij^ba
   const int64_t V = v, O = o, vv = V * V, n = O * O * vv;
@@ -1197,6 +1209,7 @@ __global__ __launch_bounds__(256) void r2_layouts_kernel(int o, int v, const dou
   __syncthreads();
   for (int r = ty; r < kAsmTile; r += 256 / kAsmTile) {
     const int64_t a = a0 + r, b = b0 + tx;
+    double part = 0.0;
     if (a < V && b < V) {
       const double x = t[r][tx], y = u[tx][r];
       const int64_t e = base + a * V + b;
@@ -1205,8 +1218,17 @@ __global__ __launch_bounds__(256) void r2_layouts_kernel(int o, int v, const dou
         RAb[((q * O + i) * V + a) * ldra + ldr + j * V + b] = bf16_bits(x);
       else
         Ria[f] = x;
-      UiaR[f] = 2.0 * x - y;
-      UR[e] = 2.0 * x - y;
+      const double uia = 2.0 * x - y;
+      if (UiaRb)
+        UiaRb[((q * O + i) * V + a) * ldu + j * V + b] = bf16_bits(uia);
+      else
+        UiaR[f] = uia;
+      UR[e] = uia;
+      if (s1p) part = uia * fdov[j * V + b];
+    }
+    if (s1p) {  // (uniform) sum over the 32 lanes of this row (one half of a wave)
+      for (int m = 16; m >= 1; m >>= 1) part += __shfl_xor(part, m, 32);
+      if (tx == 0 && a < V) s1p[((q * O + i) * V + a) * (O * ntb) + j * ntb + b0 / kAsmTile] = part;
     }
   }
   for (int r = ty; r < kAsmTile; r += 256 / kAsmTile) {
@@ -1217,6 +1239,17 @@ __global__ __launch_bounds__(256) void r2_layouts_kernel(int o, int v, const dou
       else
         RE[((q * O + i) * V + b) * ldre + j * V + a] = t[tx][r];
     }
+  }
+}
+
+// s1[q][r] += sum_m part[(q ov + r) nm + m] for r < ov (the partial sums of r2_layouts_kernel,
+// in order)
+__global__ void s1_partials_kernel(int64_t nb, int64_t ov, int64_t nm, const double* __restrict__ part,
+                                   double* __restrict__ s1, int64_t stride1) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nb * ov; e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int64_t m = 0; m < nm; ++m) acc += part[e * nm + m];
+    s1[(e / ov) * stride1 + e % ov] += acc;
   }
 }
 
@@ -1323,9 +1356,19 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     const unsigned ntb = (unsigned)((v + kAsmTile - 1) / kAsmTile);
     PNO_CHECK((int64_t)o * o <= 65535 && nb <= 65535, PNOEOM_EINVAL, "sigma: too many pairs or vectors per block");
     uint16_t* rab = fold ? (uint16_t*)w.RAb : nullptr;
+    // (fused mode: U(R)_ia as the bfloat16 rows of the M1 product in fa, and sigma1's
+    // U(R)_ia f'_ov term as partial sums, no FP64 U(R)_ia)
+    uint16_t* ub = fold ? reinterpret_cast<uint16_t*>((float*)w.fa) : nullptr;
     hipLaunchKernelGGL(r2_layouts_kernel, dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb), dim3(256), 0, s, o, v,
                        R2, (double*)w.Ria, (double*)w.UiaR, (double*)w.UR, (double*)w.RE, ldre, rab, c.kfold,
-                       c.ldr);
+                       c.ldr, ub, c.ldov, (const double*)c.fd_ov, fold ? (double*)w.S1p : (double*)nullptr);
+    PNO_HIP(hipGetLastError());
+    if (fold && c.ldov > ov)
+      hipLaunchKernelGGL(zero_cols_kernel, dim3(grid1((int64_t)nb * ov * (c.ldov - ov))), dim3(256), 0, s,
+                         (int64_t)nb * ov, c.ldov, ov, c.ldov, ub);
+    if (fold)
+      hipLaunchKernelGGL(s1_partials_kernel, dim3(grid1((int64_t)nb * ov)), dim3(256), 0, s, (int64_t)nb, ov,
+                         (int64_t)o * ntb, (const double*)w.S1p, s1, stride1);
     PNO_HIP(hipGetLastError());
     if (fold && c.ldr > ov) {  // padding of the -R^s and R_ia blocks of the rows
       const int64_t rows = (int64_t)nb * ov;
@@ -1342,7 +1385,8 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   gm(s, false, true, nb, ov, ov, 1.0, w.fp_ov, ov, c.UiaT, ov, 1.0, s1, stride1);
   gmb(s, true, false, o, v, o, -1.0, c.Fqoo, o, 0, r1, v, stride1, 1.0, s1, v, stride1, nb);
   gmb(s, false, true, o, v, v, 1.0, r1, v, stride1, c.Fqvv, v, 0, 1.0, s1, v, stride1, nb);
-  gmb(s, false, false, ov, 1, ov, 1.0, w.UiaR, ov, oovv, c.fd_ov, 1, 0, 1.0, s1, 1, stride1, nb);
+  if (!fold)  // (the fused mode summed it in the layout pass)
+    gmb(s, false, false, ov, 1, ov, 1.0, w.UiaR, ov, oovv, c.fd_ov, 1, 0, 1.0, s1, 1, stride1, nb);
   // (FP32 / BF16: the products with a T-only right factor below run on FP32 MFMA, their
   // per-vector left operands staged in FP32 in fa; the staging holds 2 nb o^2 v^2 floats in
   // each of fa and fc: M1 stages nb o v naux floats in fc, R2 and Xh take nb (o^2 v^2 + o^4)
@@ -1367,7 +1411,7 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   };
   if (bfr) {
     // M1[(q,i,a)][Q] = sum_(jb) U(R)_ia[(q,i,a)][(jb)] B~_ov[(jb)][Q], all vectors in one product
-    rows_bf16(nb * ov, ov, w.UiaR, ov, hb, c.ldov);
+    if (!fold) rows_bf16(nb * ov, ov, w.UiaR, ov, hb, c.ldov);  // (the fused mode's layout pass wrote them)
     bgemm(nb * ov, naux, c.ldov, 1.f, hb, c.BovQb, 0.f, w.fc, naux);
     to_double(s, nb * ovn, w.fc, w.M1, 0.0);
   } else if (f32x) {
@@ -2061,7 +2105,7 @@ uint64_t sigma_signature(Context& c, hipStream_t s) {
   };
   SigmaWork& w = c.sw;
   for (DBuf<double>* b : {&w.Bp, &w.Bc, &w.hp, &w.Jp, &w.Kp, &w.fp, &w.dp, &w.fp_ov, &w.fp_vv, &w.fp_oo, &w.BvopT, &w.BoopT,
-                          &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.UR, &w.ZZ,
+                          &w.BvvpT, &w.R2c, &w.Ria, &w.UiaR, &w.S1p, &w.UR, &w.ZZ,
                           &w.RE, &w.Zp, &w.Xh, &w.O4p, &w.OOVVp, &w.M1, &w.R1c, &w.Ftv, &w.Fto, &w.LadAll, &w.Sp,
                           &w.Am, &w.SigP, &w.SigM, &c.pno.Tw, &c.pno.r1, &c.pno.r2, &c.pno.s1, &c.pno.s2, &c.gin,
                           &c.gout})
