@@ -923,7 +923,7 @@ int64_t rest_bytes_per_vector(const Context& c, int precision, bool r2c) {
   const int64_t narr = (c.ring_y ? (fold ? 1 : 7) : 9) + (r2c ? 1 : 0);
   int64_t nd = narr * oovv + (ov + oo + (c.ring_y ? 0 : vv)) * (int64_t)c.naux + ov * c.naux + 2 * oo * oo + ov + vv +
                oo + vv + oo +
-               (c.ring_y ? ov : 0);
+               (c.ring_y ? ov + (int64_t)c.nmo * c.o * c.naux : 0);  // (+ the vector's columns of Bc)
   int64_t bytes = nd * (int64_t)sizeof(double);
   if (fold)  // RAb, fz, Sdf (pairs i <= j), S1p
     bytes += ov * c.kfold * (int64_t)sizeof(uint16_t) +
@@ -1017,9 +1017,9 @@ void alloc_sigma_work(Context& c, int precision, int nb, bool need_r2c) {
   const int64_t oovv = c.oovv(), B = nb;
   const bool fold = ring_fold(c, precision);
   trim_sigma_work(c, precision, need_r2c);
-  // one-vector scratch of the R1 one-index transformation
+  // scratch of the R1 one-index transformation (Bc: all vectors of the chunk)
   if (c.ring_y)
-    grow(w.Bc, (int64_t)c.naux * c.nmo * c.o);
+    grow(w.Bc, B * c.naux * c.nmo * c.o);
   else
     grow(w.Bp, (int64_t)c.naux * n2);
   grow(w.hp, n2); grow(w.Jp, n2); grow(w.Kp, n2); grow(w.fp, n2); grow(w.dp, c.naux);
@@ -1283,31 +1283,40 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   // oo and vo blocks Bc[Q][p][i] = B'^Q_{p,i} (nmo x o), the Coulomb part through the one-index
   // transformation of D = sum_Q dt_Q B~^Q (c.J) and the exchange part from Bc (without them the
   // whole B' is formed for its vv block)
+  // Bc holds all vectors of the block, [Q][p][(q, i)] (row stride nbo): the product over the
+  // virtual columns is one GEMM over all rows (Q, p) of B~ and, with uniformly strided r1 rows,
+  // over all vectors at once (B~'s vo block read once)
+  const int64_t ldc1 = (int64_t)nb * o, sc = (int64_t)nmo * ldc1;
+  if (c.ring_y) {
+    if (stride1 == ov)
+      gm(s, false, true, (int64_t)naux * nmo, ldc1, v, 1.0, c.Bt + o, nmo, r1, v, 0.0, w.Bc, ldc1);
+    else
+      for (int q = 0; q < nb; ++q)
+        gm(s, false, true, (int64_t)naux * nmo, o, v, 1.0, c.Bt + o, nmo, r1 + q * stride1, v, 0.0, w.Bc + q * o, ldc1);
+  }
   for (int q = 0; q < nb && c.ring_y; ++q) {
     const double* r1q = r1 + q * stride1;
-    const int64_t sc = (int64_t)nmo * o;
-    // (the rows (Q, p) of B~ and of Bc are uniformly strided: one product over all of them)
-    gm(s, false, true, (int64_t)naux * nmo, o, v, 1.0, c.Bt + o, nmo, r1q, v, 0.0, w.Bc, o);
-    gmb(s, true, false, v, o, o, -1.0, r1q, v, 0, c.Bt, nmo, n2, 1.0, w.Bc + (int64_t)o * o, o, sc, naux);
+    double* bcq = w.Bc + q * o;  // this vector's columns of Bc
+    gmb(s, true, false, v, o, o, -1.0, r1q, v, 0, c.Bt, nmo, n2, 1.0, bcq + (int64_t)o * ldc1, ldc1, sc, naux);
     fill(s, n2, 0.0, w.hp);
     gm(s, true, false, v, nmo, o, -1.0, r1q, v, c.hd, nmo, 1.0, w.hp + (int64_t)o * nmo, nmo);
     gm(s, false, true, nmo, o, v, 1.0, c.hd + o, nmo, r1q, v, 1.0, w.hp, nmo);
-    hipLaunchKernelGGL(trace_rows_kernel, dim3((naux + 255) / 256), dim3(256), 0, s, naux, (int64_t)o, sc, o,
-                       (const double*)w.Bc, (double*)w.dp);
+    hipLaunchKernelGGL(trace_rows_kernel, dim3((naux + 255) / 256), dim3(256), 0, s, naux, ldc1, sc, o,
+                       (const double*)bcq, (double*)w.dp);
     // J' = sum_Q dp_Q B~^Q + (one-index transformed D);  K' = sum_Q Bc^Q B~^Q[occ, :] + B~^Q[:, occ] Bc^Q[occ, :]
     gm(s, false, false, 1, n2, naux, 1.0, w.dp, naux, c.Bt, n2, 0.0, w.Jp, n2);
     gm(s, true, false, v, nmo, o, -1.0, r1q, v, c.J, nmo, 1.0, w.Jp + (int64_t)o * nmo, nmo);
     gm(s, false, true, nmo, o, v, 1.0, c.J + o, nmo, r1q, v, 1.0, w.Jp, nmo);
-    gmb(s, false, false, nmo, nmo, o, 1.0, w.Bc, o, sc, c.Bt, nmo, n2, 0.0, w.Kp, nmo, 0, naux, true);
-    gmb(s, false, false, nmo, o, o, 1.0, c.Bt, nmo, n2, w.Bc, o, sc, 1.0, w.Kp, nmo, 0, naux, true);
+    gmb(s, false, false, nmo, nmo, o, 1.0, bcq, ldc1, sc, c.Bt, nmo, n2, 0.0, w.Kp, nmo, 0, naux, true);
+    gmb(s, false, false, nmo, o, o, 1.0, c.Bt, nmo, n2, bcq, ldc1, sc, 1.0, w.Kp, nmo, 0, naux, true);
     PNO_HIP(hipMemcpyAsync(w.fp, w.hp, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
     axpby(s, n2, 2.0, w.Jp, 1.0, w.fp);
     axpby(s, n2, -1.0, w.Kp, 1.0, w.fp);
     ext(s, o, v, 1, 1, nmo, 1, 0, 0, w.fp + o, w.fp_ov + q * ov);
     ext(s, v, v, 1, 1, nmo, 1, 0, 0, w.fp + (int64_t)o * nmo + o, w.fp_vv + q * vv);
     ext(s, o, o, 1, 1, nmo, 1, 0, 0, w.fp, w.fp_oo + q * oo);
-    ext(s, o, v, naux, 1, 1, o, sc, 0, w.Bc + (int64_t)o * o, w.BvopT + q * ovn);  // [(i,a)][Q] = B'^Q_{o+a,i}
-    ext(s, o, o, naux, 1, o, 1, sc, 0, w.Bc, w.BoopT + q * oon);                  // [(j,i)][Q] = B'^Q_{j,i}
+    ext(s, o, v, naux, 1, 1, ldc1, sc, 0, bcq + (int64_t)o * ldc1, w.BvopT + q * ovn);  // [(i,a)][Q] = B'^Q_{o+a,i}
+    ext(s, o, o, naux, 1, ldc1, 1, sc, 0, bcq, w.BoopT + q * oon);                      // [(j,i)][Q] = B'^Q_{j,i}
     ext(s, o, v, 1, 1, 1, nmo, 0, 0, w.fp + (int64_t)o * nmo, s1 + q * stride1);  // f'_ai
   }
   for (int q = 0; q < nb && !c.ring_y; ++q) {
