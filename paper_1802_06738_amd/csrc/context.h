@@ -251,6 +251,7 @@ struct Context {
   DBuf<double> pack_in, pack_out;     // packed canonical vectors of apply_sigma in graph mode
   int fixed_chunk = 0;                // > 0: vectors per sigma chunk (set while capturing)
   int last_chunk = 0;
+  int sw_precision = -1;              // precision the sigma workspaces were last sized for
   int graph_launches = 0, graph_captures = 0;
   void drop_graphs() {
     for (SigmaGraph& g : graphs)

@@ -975,6 +975,15 @@ int64_t sigma_held_bytes(const Context& c) {
 // caller.  While a graph is captured the decision of the eager run is reused.
 int sigma_chunk(Context& c, int nvec, int precision, bool pno) {
   if (c.fixed_chunk > 0) return std::max(1, std::min(c.fixed_chunk, nvec));
+  if (c.sw_precision >= 0 && c.sw_precision != precision) {
+    // another precision's workspaces keep the sizes of its chunk (arrays only grow), which the
+    // count below would take as free for this precision's arrays: release them (and the graphs
+    // that refer to them), so that the chunk is sized against what is really free
+    c.drop_graphs();
+    c.sw.release();
+    for (DBuf<double>* b : {&c.pno.r1, &c.pno.r2, &c.pno.s1, &c.pno.s2}) b->release();
+  }
+  c.sw_precision = precision;
   const int64_t per = sigma_bytes_per_vector(c, precision, pno);
   size_t freeb = 0, totalb = 0;
   PNO_HIP(hipMemGetInfo(&freeb, &totalb));
