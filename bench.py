@@ -67,12 +67,13 @@ def gemm_kernel_sha():
 # HBM bytes per launch of the bfloat16 ring products of the headline workload (o=40, v=400
 # SA-PNO sigma blocks), from two rocprofv3 --pmc runs of the headline command (FETCH_SIZE,
 # WRITE_SIZE; profiles/ring_bf16_config4_counters.md), scaled by what the counters read for the
-# 1 GiB + 1 GiB device copy of the same run.  Valid for the code they were taken on: the
+# 1 GiB + 1 GiB device copy of the same run (6-vector blocks in chunks of 5 + 1 vectors, the
+# chunk sizes that run's free memory gave).  Valid for the code they were taken on: the
 # 256 x 256 kernel file, the bfloat16 GEMM dispatch of gemm.hip and the ring launches of
 # sigma.hip, by hash; reported as null once any of them changes.
 BF16_RING_TRAFFIC = {"sha256": "73acf1277b6f6d0e79cf8876648061f1fa49eb3ebb8752e49a1774050c92b47c",
-                     "fetch_kib": 32191694.90, "fetch_scale": 1048576.0 / 524302.4,
-                     "write_kib": 3000000.2, "write_scale": 1048576.0 / 1048576.1}
+                     "fetch_kib": 32902282.39, "fetch_scale": 1048576.0 / 524302.1,
+                     "write_kib": 3000000.1, "write_scale": 1048576.0 / 1048576.2}
 
 
 def bf16_kernel_sha():
