@@ -574,7 +574,9 @@ __global__ __launch_bounds__(NT) void gemm_grouped_kernel(const GroupDesc* __res
   #pragma unroll
       for (int j = 0; j < TN; ++j) acc[i][j] = v4{0, 0, 0, 0};
     const int64_t kt = (g.K + GBK - 1) / GBK;
-    for (int64_t it = 0; it < kt; ++it) {
+    // the next K-tile's operands are loaded into registers while the current one is used
+    T ra[LA], rb[LB];
+    auto gload = [&](int64_t it) {
       const int64_t k0 = it * GBK;
   #pragma unroll
       for (int q = 0; q < LA; ++q) {
@@ -584,7 +586,7 @@ __global__ __launch_bounds__(NT) void gemm_grouped_kernel(const GroupDesc* __res
         const int64_t gm = m0 + mm, gk = k0 + kk;
         T val = 0;
         if (gm < g.M && gk < g.K) val = TA ? A[gk * g.lda + gm] : A[gm * g.lda + gk];
-        As[kk][mm] = val;
+        ra[q] = val;
       }
   #pragma unroll
       for (int q = 0; q < LB; ++q) {
@@ -594,9 +596,23 @@ __global__ __launch_bounds__(NT) void gemm_grouped_kernel(const GroupDesc* __res
         const int64_t gn = n0 + nn, gk = k0 + kk;
         T val = 0;
         if (gn < g.N && gk < g.K) val = TB ? B[gn * g.ldb + gk] : B[gk * g.ldb + gn];
-        Bs[kk][nn] = val;
+        rb[q] = val;
+      }
+    };
+    if (kt > 0) gload(0);
+    for (int64_t it = 0; it < kt; ++it) {
+  #pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        const int e = tid + q * NT;
+        if (TA) As[e / GBM][e % GBM] = ra[q]; else As[e % GBK][e / GBK] = ra[q];
+      }
+  #pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        const int e = tid + q * NT;
+        if (TB) Bs[e % GBK][e / GBK] = rb[q]; else Bs[e / GBN][e % GBN] = rb[q];
       }
       __syncthreads();
+      if (it + 1 < kt) gload(it + 1);
   #pragma unroll
       for (int kk = 0; kk < GBK; kk += 4) {
         T av[TM], bv[TN];
