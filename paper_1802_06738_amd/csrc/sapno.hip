@@ -225,13 +225,27 @@ __global__ __launch_bounds__(256) void expand_pairs_kernel(int o, int v, const i
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = v4{0.0, 0.0, 0.0, 0.0};
+  // the next K-step's operands are loaded into registers while the current one is used
+  constexpr int kL = kXT * kXK / 256;
+  double ra[kL], rb[kL];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < kL; ++q) {
+      const int e = tid + 256 * q, r = e / kXK, k = e % kXK;
+      ra[q] = (a0 + r < v && k0 + k < n) ? T[(int64_t)(a0 + r) * n + k0 + k] : 0.0;
+      rb[q] = (b0 + r < v && k0 + k < n) ? Up[(int64_t)(b0 + r) * n + k0 + k] : 0.0;
+    }
+  };
+  if (n > 0) gload(0);
   for (int k0 = 0; k0 < n; k0 += kXK) {
-    for (int e = tid; e < kXT * kXK; e += 256) {
-      const int r = e / kXK, k = e % kXK;
-      As[k][r] = (a0 + r < v && k0 + k < n) ? T[(int64_t)(a0 + r) * n + k0 + k] : 0.0;
-      Bs[k][r] = (b0 + r < v && k0 + k < n) ? Up[(int64_t)(b0 + r) * n + k0 + k] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kL; ++q) {
+      const int e = tid + 256 * q, r = e / kXK, k = e % kXK;
+      As[k][r] = ra[q];
+      Bs[k][r] = rb[q];
     }
     __syncthreads();
+    if (k0 + kXK < n) gload(k0 + kXK);
 #pragma unroll
     for (int kk = 0; kk < kXK; kk += 4) {
       double av[2], bv[2];
