@@ -292,11 +292,12 @@ __global__ void precond_pno_kernel(int64_t n, double theta, const double* __rest
 // symmetrise the diagonal pair blocks of a compressed vector
 __global__ void sym_diag_blocks_kernel(int ndiag, const int64_t* __restrict__ off, const int* __restrict__ nd,
                                        double* __restrict__ x) {
-  const int b = blockIdx.x;
+  const int b = blockIdx.x;  // (diagonal block b, slice blockIdx.y of its elements)
   if (b >= ndiag) return;
   const int n = nd[b];
   double* X = x + off[b];
-  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) {
+  for (int64_t e = blockIdx.y * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * n;
+       e += (int64_t)gridDim.y * blockDim.x) {
     const int i = (int)(e / n), j = (int)(e % n);
     if (i < j) {
       const double m = 0.5 * (X[(int64_t)i * n + j] + X[(int64_t)j * n + i]);
@@ -977,7 +978,7 @@ void project_pno(Context& c, double* x) { project_pno(c, c.pno, x); }
 void project_pno(Context& c, PNOData& P, double* x) {
   const int nd = (int)P.d_n.n;
   if (nd == 0) return;
-  hipLaunchKernelGGL(sym_diag_blocks_kernel, dim3(nd), dim3(256), 0, c.stream, nd, (const int64_t*)P.d_off,
+  hipLaunchKernelGGL(sym_diag_blocks_kernel, dim3(nd, 32), dim3(256), 0, c.stream, nd, (const int64_t*)P.d_off,
                      (const int*)P.d_n, x);
   PNO_HIP(hipGetLastError());
 }

@@ -931,7 +931,7 @@ int64_t rest_bytes_per_vector(const Context& c, int precision, bool r2c) {
              ov * c.o * ((c.v + kAsmTile - 1) / kAsmTile) * (int64_t)sizeof(double);
   if (f32)  // fa and fc (two oovv each; fa larger when it stages the BF16 operands)
     bytes += (2 * oovv + std::max({2 * oovv, bf16_ring_floats(c, PNOEOM_BF16, 1) + 1,
-                                   bf16_rest_values(c, PNOEOM_BF16, 1) / 2 + 1})) *
+                                   (bf16_rest_values(c, PNOEOM_BF16, 1) + (fold ? c.v * c.ldg + 8 : 0)) / 2 + 1})) *
              (int64_t)sizeof(float);
   return bytes;
 }
@@ -1060,7 +1060,7 @@ void alloc_sigma_work(Context& c, int precision, int nb, bool need_r2c) {
   grow(w.Ftv, B * vv); grow(w.Fto, B * oo);
   if (precision != PNOEOM_FP64) {
     grow(w.fa, std::max({2 * B * oovv, bf16_ring_floats(c, precision, nb),
-                         (bf16_rest_values(c, precision, nb) + 1) / 2}));
+                         (bf16_rest_values(c, precision, nb) + (fold ? B * c.v * c.ldg + 8 : 0) + 1) / 2}));
     grow(w.fc, 2 * B * oovv);
   }
 }
@@ -1192,14 +1192,16 @@ __global__ __launch_bounds__(256) void assemble_s2_sym_kernel(int o, int v, cons
 //   (fused BF16 ring product: -R^s and R_ia instead as bfloat16 into the rows of RAb, the
 //    first two blocks of ldr values of rows of ldra, and no FP64 Ria / RE; U(R)_ia as bfloat16
 //    rows of ldu (UiaRb, the M1 operand) instead of FP64, and sigma1's U(R)_ia f'_ov term as
-//    partial sums over the b of a tile, s1p[(q,i,a)][(j, b tile)] = sum_b U(R)_ia,jb f'_jb)
+//    partial sums over the b of a tile, s1p[(q,i,a)][(j, b tile)] = sum_b U(R)_ia,jb f'_jb; and
+//    U(R) also as the bfloat16 rows [(q,a)][(i,j,b)] of ldg values of the Ftv product, URb)
 __global__ __launch_bounds__(256) void r2_layouts_kernel(int o, int v, const double* __restrict__ R2,
                                                          double* __restrict__ Ria, double* __restrict__ UiaR,
                                                          double* __restrict__ UR,
                                                          double* __restrict__ RE, int64_t ldre,
                                                          uint16_t* __restrict__ RAb, int64_t ldra, int64_t ldr,
                                                          uint16_t* __restrict__ UiaRb, int64_t ldu,
-                                                         const double* __restrict__ fdov, double* __restrict__ s1p) {
+                                                         const double* __restrict__ fdov, double* __restrict__ s1p,
+                                                         uint16_t* __restrict__ URb, int64_t ldg) {
   __shared__ double t[kAsmTile][kAsmTile + 1];  // t[a - a0][b - b0] = R_ij^ab
   __shared__ double u[kAsmTile][kAsmTile + 1];  // u[b - b0][a - a0] = R_ij^ba
   const int64_t V = v, O = o, vv = V * V, n = O * O * vv;
@@ -1233,6 +1235,7 @@ __global__ __launch_bounds__(256) void r2_layouts_kernel(int o, int v, const dou
       else
         UiaR[f] = uia;
       UR[e] = uia;
+      if (URb) URb[(q * V + a) * ldg + (i * O + j) * V + b] = bf16_bits(uia);
       if (s1p) part = uia * fdov[j * V + b];
     }
     if (s1p) {  // (uniform) sum over the 32 lanes of this row (one half of a wave)
@@ -1370,6 +1373,14 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   const int64_t ldre = c.ring_y ? ov : ov2;  // RE rows: [R^s] or [R^s | E_X]
   // Ria, R^s (left half of the rows of RE), UiaR = 2 R_ia - R^s and UR in one pass over R2
   const bool fold = ring_fold(c, precision);
+  // (fused mode: the bfloat16 rows of U(R) for the Ftv product, written by the layout pass at
+  // the end of fa, beyond every staging used before the Ftv product)
+  uint16_t* urb = nullptr;
+  if (fold && c.Gqb.p) {
+    const int64_t need = (int64_t)nb * v * c.ldg, cap = 2 * (int64_t)w.fa.n;
+    PNO_CHECK(cap >= need + bf16_rest_values(c, precision, nb), PNOEOM_EINVAL, "sigma: BF16 staging too small");
+    urb = reinterpret_cast<uint16_t*>((float*)w.fa) + ((cap - need) & ~(int64_t)7);
+  }
   {
     const unsigned ntb = (unsigned)((v + kAsmTile - 1) / kAsmTile);
     PNO_CHECK((int64_t)o * o <= 65535 && nb <= 65535, PNOEOM_EINVAL, "sigma: too many pairs or vectors per block");
@@ -1379,11 +1390,15 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
     uint16_t* ub = fold ? reinterpret_cast<uint16_t*>((float*)w.fa) : nullptr;
     hipLaunchKernelGGL(r2_layouts_kernel, dim3(ntb * ntb, (unsigned)(o * o), (unsigned)nb), dim3(256), 0, s, o, v,
                        R2, (double*)w.Ria, (double*)w.UiaR, (double*)w.UR, (double*)w.RE, ldre, rab, c.kfold,
-                       c.ldr, ub, c.ldov, (const double*)c.fd_ov, fold ? (double*)w.S1p : (double*)nullptr);
+                       c.ldr, ub, c.ldov, (const double*)c.fd_ov, fold ? (double*)w.S1p : (double*)nullptr, urb,
+                       c.ldg);
     PNO_HIP(hipGetLastError());
     if (fold && c.ldov > ov)
       hipLaunchKernelGGL(zero_cols_kernel, dim3(grid1((int64_t)nb * ov * (c.ldov - ov))), dim3(256), 0, s,
                          (int64_t)nb * ov, c.ldov, ov, c.ldov, ub);
+    if (urb && c.ldg > oo * v)  // (padding of the Ftv operand rows: zeros, as the product reads them)
+      hipLaunchKernelGGL(zero_cols_kernel, dim3(grid1((int64_t)nb * v * (c.ldg - oo * v))), dim3(256), 0, s,
+                         (int64_t)nb * v, c.ldg, oo * v, c.ldg, urb);
     if (fold)
       hipLaunchKernelGGL(s1_partials_kernel, dim3(grid1((int64_t)nb * ov)), dim3(256), 0, s, (int64_t)nb, ov,
                          (int64_t)o * ntb, (const double*)w.S1p, s1, stride1);
@@ -1699,10 +1714,13 @@ void sigma_rest_block(Context& c, int nb, const double* r1, int64_t stride1, con
   // summed over the o^2 pair blocks (v x v times v x v), rows of U(R) read in place
   if (bfr && c.Gqb.p) {
     // BF16 scope 1: one bfloat16 product per vector, U(R) rows as [a][(k,l,d)] staged in fa
-    uint16_t* ub = reinterpret_cast<uint16_t*>((float*)w.fa);
-    hipLaunchKernelGGL(pair_rows_bf16_kernel, dim3(grid1(nb * v * c.ldg)), dim3(256), 0, s, (int64_t)nb, oo,
-                       (int64_t)v, (const double*)w.UR, ub, c.ldg);
-    PNO_HIP(hipGetLastError());
+    // (written by the layout pass in the fused mode)
+    uint16_t* ub = urb ? urb : reinterpret_cast<uint16_t*>((float*)w.fa);
+    if (!urb) {
+      hipLaunchKernelGGL(pair_rows_bf16_kernel, dim3(grid1(nb * v * c.ldg)), dim3(256), 0, s, (int64_t)nb, oo,
+                         (int64_t)v, (const double*)w.UR, ub, c.ldg);
+      PNO_HIP(hipGetLastError());
+    }
     float* ftv32 = fold ? (float*)w.fz : (float*)w.fc;  // (fc holds the FP32 ring block in the fused mode)
     for (int q = 0; q < nb; ++q)
       bgemm(v, v, c.ldg, -1.f, ub + q * v * c.ldg, c.Gqb, 0.f, ftv32 + q * vv, v);
