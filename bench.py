@@ -72,8 +72,8 @@ def gemm_kernel_sha():
 # 256 x 256 kernel file, the bfloat16 GEMM dispatch of gemm.hip and the ring launches of
 # sigma.hip, by hash; reported as null once any of them changes.
 BF16_RING_TRAFFIC = {"sha256": "73acf1277b6f6d0e79cf8876648061f1fa49eb3ebb8752e49a1774050c92b47c",
-                     "fetch_kib": 32902282.39, "fetch_scale": 1048576.0 / 524302.1,
-                     "write_kib": 3000000.1, "write_scale": 1048576.0 / 1048576.2}
+                     "fetch_kib": 33735852.37, "fetch_scale": 1048576.0 / 524302.3,
+                     "write_kib": 3000000.2, "write_scale": 1048576.0 / 1048576.0}
 
 
 def bf16_kernel_sha():
