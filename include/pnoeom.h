@@ -451,6 +451,29 @@ int pnoeom_gemm_bf16_time(void* hip_stream, long long M, long long N, long long 
  * Errors: EINVAL (n < 1 or null), ENOTCONV. */
 int pnoeom_host_syev(int n, const double* a, double* w, double* v);
 
+/* Where pnoeom_build_sapno (and pnoeom_syev_batched) solve symmetric eigenproblems larger
+ * than 128 (Methods: the per-pair diagonalisation of the state-averaged densities, whose
+ * kept eigenvectors are the PNOs, and the semicanonical rotation of each kept space):
+ *   backend 0 (default): on the GPU up to n = 1024 -- Householder reduction to tridiagonal
+ *             form, all eigenvalues by Sturm bisection, and only the eigenvectors that the
+ *             truncation keeps by inverse iteration (reorthogonalised inside clusters of
+ *             close eigenvalues), back-transformed by the reflectors; larger n on the host;
+ *   backend 1: on host threads (pnoeom_host_syev's algorithm), all eigenvectors.
+ * Matrices up to 128 always use the GPU Jacobi kernel.  Errors: EINVAL (null ctx, bad mode). */
+int pnoeom_set_eig_backend(pnoeom_ctx* ctx, int backend);
+
+/* The batched symmetric eigensolver of pnoeom_build_sapno on caller data, on the context's
+ * stream (synchronised on return).
+ *   a   : device [nmat][n][n] row-major symmetric matrices, overwritten (workspace)
+ *   cut : eigenvectors are required only for eigenvalues with |lambda| >= cut (0: all)
+ *   ev  : device [nmat][n] eigenvalues (ascending for n > 128 on the GPU backend, unordered
+ *         otherwise)
+ *   vt  : device [nmat][n][n]; row k of matrix m is the unit eigenvector of ev[m][k] for
+ *         every k with |ev[m][k]| >= cut (rows of the other eigenvalues may be zero)
+ * n above 1024 goes to the host solver.  Caller owns all buffers.  Errors: EINVAL (null ctx
+ * or pointers, nmat < 0, n < 1), ENOTCONV (host solver). */
+int pnoeom_syev_batched(pnoeom_ctx* ctx, int nmat, int n, double* a, double cut, double* ev, double* vt);
+
 /* Time spent in the last pnoeom_davidson / pnoeom_apply_sigma call, measured with
  * HIP events on the context's stream: total milliseconds; milliseconds inside the
  * particle-ladder contractions and the number of ladder GEMM launches (two per

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpnoeom.so")
-SOURCES = ["gemm.hip", "gemm_bf16.hip", "tensor.hip", "sigma.hip", "ladder.hip", "davidson.hip", "sapno.hip", "ccsd.hip", "probe.hip", "eig.cpp",
+SOURCES = ["gemm.hip", "gemm_bf16.hip", "tensor.hip", "sigma.hip", "ladder.hip", "davidson.hip", "sapno.hip", "syev.hip", "ccsd.hip", "probe.hip", "eig.cpp",
            "capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

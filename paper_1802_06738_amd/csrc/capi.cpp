@@ -577,6 +577,25 @@ int pnoeom_gemm_set_table(int n, const long long* keys, const int* variants) {
   return PNOEOM_OK;
 }
 
+int pnoeom_set_eig_backend(pnoeom_ctx* ctx, int backend) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(backend == 0 || backend == 1, PNOEOM_EINVAL, "set_eig_backend: backend must be 0 or 1");
+    c.eig_backend = backend;
+  });
+}
+
+int pnoeom_syev_batched(pnoeom_ctx* ctx, int nmat, int n, double* a, double cut, double* ev, double* vt) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(nmat >= 0 && n >= 1, PNOEOM_EINVAL, "syev_batched: nmat < 0 or n < 1");
+    if (nmat == 0) return;
+    PNO_CHECK(a && ev && vt, PNOEOM_EINVAL, "syev_batched: null pointer");
+    std::vector<int> nsz(nmat, n);
+    pnoeom::DBuf<int> dn;
+    dn.alloc(nmat);
+    pnoeom::batched_syev(c.stream, c.eig_backend, nmat, nsz, n, a, vt, ev, dn, cut);
+  });
+}
+
 int pnoeom_host_syev(int n, const double* a, double* w, double* v) {
   try {
     return pnoeom::host_syev(n, a, w, v);

@@ -113,6 +113,8 @@ struct Context {
   DBuf<double> Yr, Zr;
   bool ring_y = false;
   int ring_mode = 0;
+  // symmetric eigenproblems above 128: 0 on the GPU (tridiagonal solver), 1 on host threads
+  int eig_backend = 0;
   // BF16 ring products (precision BF16 with ring_y): right operands [Dr | Xr]^T and DX2^T as
   // bfloat16 rows of ring_passes blocks of ldr (= ov padded to 64) values: one pass takes
   // bf16(x), three passes the split x = hi + lo as [hi | lo | hi] (left operands [hi | hi | lo]),
@@ -339,5 +341,17 @@ int host_eig(int n, const double* a, double* wr, double* wi, double* vr, int nve
 int host_syev(int n, const double* a, double* w, double* v);
 void probe_peaks(hipStream_t s, double* fp64_tflops, double* fp32_tflops, double* bf16_tflops, double* copy_gbs);
 int host_syev_batched(int nmat, const int* nsz, int ld, double* A, double* ev, double* Vt, int nthreads);
+
+// GPU batched symmetric eigensolver through tridiagonal form (syev.hip) for matrices of up to
+// kSyevMaxN: A[m] (nsz[m] x nsz[m], device sizes dn, leading dimension and row stride ld, matrix
+// stride ld*ld) is overwritten; ev[m*ld + k] gets every eigenvalue in ascending order and row k of
+// Vt[m] the unit eigenvector of eigenvalue k when |ev| >= cut (zero rows otherwise).
+constexpr int kSyevMaxN = 1024;
+void syev_tridiag(hipStream_t s, int nmat, const int* dn, int nmax, int ld, double* A, double* Vt, double* ev,
+                  double cut);
+// batched_syev (sapno.hip): Jacobi up to 128, else syev_tridiag (eig_backend 0, n <= kSyevMaxN)
+// or the host solver; eigenvector rows of eigenvalues below cut may be left zero
+void batched_syev(hipStream_t s, int backend, int nmat, const std::vector<int>& nsz, int ld, double* A, double* Vt,
+                  double* ev, int* dn, double cut);
 
 }  // namespace pnoeom

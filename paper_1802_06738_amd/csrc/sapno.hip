@@ -309,22 +309,26 @@ __global__ void sym_diag_blocks_kernel(int ndiag, const int64_t* __restrict__ of
 
 }  // namespace
 
-// Batched symmetric eigenproblems of matrices up to nmax: the one-workgroup Jacobi
-// kernel while its O(n^3) HBM traffic per sweep is small (n <= kJacobiMaxN); above
-// that, the matrices go to the host and are solved there in parallel (Householder
-// tridiagonalisation + implicit QR, csrc/eig.cpp), which is far faster than a
-// memory-bound per-matrix sweep.  Same output layout either way.
+// Batched symmetric eigenproblems of matrices up to nmax: the one-workgroup Jacobi kernel
+// while its O(n^3) HBM traffic per sweep is small (n <= kJacobiMaxN); above that the GPU
+// tridiagonal solver (syev.hip; eigenvectors only of eigenvalues with |lambda| >= cut), or,
+// with backend 1 or beyond kSyevMaxN, the host solver in parallel threads (Householder
+// tridiagonalisation + implicit QR, csrc/eig.cpp).  Same output layout in every case.
 constexpr int kJacobiMaxN = 128;
 
-void batched_syev(hipStream_t s, int nmat, const std::vector<int>& nsz, int ld, double* A, double* Vt, double* ev,
-                  int* dn) {
+void batched_syev(hipStream_t s, int backend, int nmat, const std::vector<int>& nsz, int ld, double* A, double* Vt,
+                  double* ev, int* dn, double cut) {
   int nmax = 0;
   for (int m = 0; m < nmat; ++m) nmax = std::max(nmax, nsz[m]);
-  if (nmax <= kJacobiMaxN) {
+  if (nmax <= kJacobiMaxN || (backend == 0 && nmax <= kSyevMaxN)) {
     PNO_HIP(hipMemcpyAsync(dn, nsz.data(), nmat * sizeof(int), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(jacobi_kernel, dim3(nmat), dim3(256), 0, s, ld, (const int*)dn, A, Vt, ev, 60);
-    PNO_HIP(hipGetLastError());
-    PNO_HIP(hipStreamSynchronize(s));
+    if (nmax <= kJacobiMaxN) {
+      hipLaunchKernelGGL(jacobi_kernel, dim3(nmat), dim3(256), 0, s, ld, (const int*)dn, A, Vt, ev, 60);
+      PNO_HIP(hipGetLastError());
+      PNO_HIP(hipStreamSynchronize(s));
+    } else {
+      syev_tridiag(s, nmat, dn, nmax, ld, A, Vt, ev, cut);
+    }
     return;
   }
   const size_t tot = (size_t)nmat * ld * ld;
@@ -608,7 +612,7 @@ void pnos_from_density(Context& c, PNOData& P, const double* D, double inv_n, do
   PNO_HIP(hipGetLastError());
   {
     std::vector<int> nv(npair, v);
-    batched_syev(s, npair, nv, v, Dp, Vt, ev, dn);
+    batched_syev(s, c.eig_backend, npair, nv, v, Dp, Vt, ev, dn, std::min(tcut_pno, tcut_osv));
   }
   std::vector<double> evh((size_t)npair * v);
   PNO_HIP(hipMemcpyAsync(evh.data(), ev, evh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -699,7 +703,7 @@ void pnos_from_density(Context& c, PNOData& P, const double* D, double inv_n, do
     gemm_grouped(t2, 1.0, U0, Tb, 0.0, Fb, s);
     DBuf<int> dnb;
     dnb.alloc(nblk);
-    batched_syev(s, nblk, bn, nmax, Fb, Wt, fev, dnb);
+    batched_syev(s, c.eig_backend, nblk, bn, nmax, Fb, Wt, fev, dnb, 0.0);
     P.U.alloc(std::max<int64_t>(utot, 1));
     gemm_grouped(t3, 1.0, U0, Wt, 0.0, P.U, s);
     PNO_HIP(hipStreamSynchronize(s));

@@ -32,7 +32,8 @@ EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pno
                     "pnoeom_build_ladder", "pnoeom_ladder_apply", "pnoeom_ladder_apply_noalloc",
                     "pnoeom_ladder_noalloc_limit", "pnoeom_set_pno_ladder",
                     "pnoeom_pno_ladder_stats", "pnoeom_set_pno_states", "pnoeom_ccsd_defaults",
-                    "pnoeom_ccsd_residual", "pnoeom_ccsd", "pnoeom_ccsd_history", "pnoeom_ccsd_gs_counts"]
+                    "pnoeom_ccsd_residual", "pnoeom_ccsd", "pnoeom_ccsd_history", "pnoeom_ccsd_gs_counts",
+                    "pnoeom_set_eig_backend", "pnoeom_syev_batched"]
 
 
 class PnoEomError(RuntimeError):
@@ -114,6 +115,8 @@ def load_library():
     lib.pnoeom_ladder_noalloc_limit.argtypes = [vp, C.c_int]
     lib.pnoeom_ladder_noalloc_limit.restype = C.c_longlong
     lib.pnoeom_set_pno_ladder.argtypes = [vp, C.c_int]
+    lib.pnoeom_set_eig_backend.argtypes = [vp, C.c_int]
+    lib.pnoeom_syev_batched.argtypes = [vp, C.c_int, C.c_int, vp, C.c_double, vp, vp]
     lib.pnoeom_set_pno_states.argtypes = [vp, C.c_int, ip]
     lib.pnoeom_pno_ladder_stats.argtypes = [vp, ip, ip, ip, dp]
     lib.pnoeom_ccsd_defaults.argtypes = [C.POINTER(CcsdOpts)]
@@ -461,6 +464,22 @@ class PnoEom:
     def set_pno_ladder(self, max_native=-1):
         """PNO-space ladder for pairs with n_p <= max_native at the next build_sapno (-1 auto, 0 none)."""
         self._check(self.lib.pnoeom_set_pno_ladder(self.h, int(max_native)))
+
+    def set_eig_backend(self, backend=0):
+        """Symmetric eigenproblems above 128 in build_sapno / syev_batched: 0 GPU, 1 host threads."""
+        self._check(self.lib.pnoeom_set_eig_backend(self.h, int(backend)))
+
+    def syev_batched(self, a, cut=0.0):
+        """Eigenpairs of the symmetric matrices a [nmat, n, n] (float64 on the device, overwritten):
+        (ev [nmat, n], vt [nmat, n, n]) with row k of vt[m] the eigenvector of ev[m, k] wherever
+        |ev[m, k]| >= cut (other rows may be zero)."""
+        import torch
+        nmat, n = int(a.shape[0]), int(a.shape[1])
+        pa = _dev(a, (nmat, n, n), "a")
+        ev = torch.empty((nmat, n), dtype=torch.float64, device=a.device)
+        vt = torch.empty((nmat, n, n), dtype=torch.float64, device=a.device)
+        self._check(self.lib.pnoeom_syev_batched(self.h, nmat, n, pa, float(cut), _dev(ev), _dev(vt)))
+        return ev, vt
 
     def pno_ladder_stats(self):
         v = [C.c_int() for _ in range(3)]

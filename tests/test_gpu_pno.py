@@ -75,9 +75,9 @@ def test_sapno_counts_and_projector(o, v, naux, kappa, nst, tcut, seed):
     assert np.max(np.abs(f2[0] - q2)) <= 1e-9 * np.max(np.abs(q2))
 
 
-def test_sapno_large_blocks_use_host_eigensolver():
+def test_sapno_large_blocks_tridiagonal_solver():
     """v = 136 > 128: the pair densities (and large semicanonical blocks) are
-    diagonalised by the library's host solver; counts exact, projector 1e-9."""
+    diagonalised by the GPU tridiagonal solver; counts exact, projector 1e-9."""
     print("[sapno large v]", flush=True)
     import torch
     o, v, naux, nst, tcut = 3, 136, 60, 2, 1e-6
