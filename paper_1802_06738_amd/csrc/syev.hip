@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void inviter_kernel(int ld, const int* __restr
   __shared__ double d[kMaxN], e[kMaxN];
   __shared__ double fd[kMaxN], fu[kMaxN], fu2[kMaxN], fl[kMaxN];
   __shared__ unsigned char pv[kMaxN];
-  __shared__ double x[kMaxN], coef[kMaxN];
+  __shared__ double x[kMaxN];
   __shared__ int mem[kMaxN];
   __shared__ double red[4];
   if (n <= 0) return;
@@ -241,6 +241,7 @@ __global__ __launch_bounds__(256) void inviter_kernel(int ld, const int* __restr
       // LU with partial pivoting of T - lu I; the running pivot row is carried in registers
       // (dc: its diagonal, uc: its superdiagonal), the reciprocal pivots go to fd
       double dc = d[0] - lu, uc = n > 1 ? e[0] : 0.0;
+#pragma unroll 4
       for (int i = 0; i + 1 < n; ++i) {
         const double l = e[i], dn = d[i + 1] - lu, un = i + 2 < n ? e[i + 1] : 0.0;
         double piv;
@@ -276,6 +277,7 @@ __global__ __launch_bounds__(256) void inviter_kernel(int ld, const int* __restr
       if (tid == 0) {
         // forward: the row interchanges and multipliers, the running entry in a register
         double cur = x[0];
+#pragma unroll 4
         for (int i = 0; i + 1 < n; ++i) {
           const double nx = x[i + 1];
           if (!pv[i]) {
@@ -293,6 +295,7 @@ __global__ __launch_bounds__(256) void inviter_kernel(int ld, const int* __restr
           x1 = (x[n - 2] - fu[n - 2] * x2) * fd[n - 2];
           x[n - 2] = x1;
         }
+#pragma unroll 4
         for (int i = n - 3; i >= 0; --i) {
           const double xi = (x[i] - fu[i] * x1 - fu2[i] * x2) * fd[i];
           x[i] = xi;
@@ -308,21 +311,53 @@ __global__ __launch_bounds__(256) void inviter_kernel(int ld, const int* __restr
       const double inv = mx > 0.0 ? 1.0 / mx : 0.0;
       for (int i = tid; i < n; i += 256) x[i] *= inv;
       __syncthreads();
+      // x -= Z Z^T x over the cluster's earlier vectors Z (rows mem[] of Vt), twice.  Wave w
+      // takes members w, w + 4, ...: one coalesced read of each member row gives both its
+      // coefficient (against the x of this pass, held in registers) and its share of the
+      // update; the four waves' shares are subtracted in turn.
       for (int pass = 0; pass < 2 && nclus > 0; ++pass) {
-        for (int p = wv; p < nclus; p += 4) {
-          const double* z = Vt + (int64_t)mem[p] * ld;
-          double acc = 0.0;
-          for (int i = lane; i < n; i += 64) acc += z[i] * x[i];
-          acc = wave_sum(acc);
-          if (lane == 0) coef[p] = acc;
+        double xr[kSlots], up[kSlots];
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) {
+          const int i = lane + 64 * q;
+          xr[q] = i < n ? x[i] : 0.0;
+          up[q] = 0.0;
         }
-        __syncthreads();
-        for (int i = tid; i < n; i += 256) {
-          double acc = x[i];
-          for (int p = 0; p < nclus; ++p) acc -= coef[p] * Vt[(int64_t)mem[p] * ld + i];
-          x[i] = acc;
+        for (int p = wv; p < nclus; p += 8) {
+          const bool two = p + 4 < nclus;
+          const double* z0 = Vt + (int64_t)mem[p] * ld;
+          const double* z1 = Vt + (int64_t)mem[two ? p + 4 : p] * ld;
+          double za[kSlots], zb[kSlots];
+          double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+          for (int q = 0; q < kSlots; ++q) {
+            za[q] = 0.0;
+            zb[q] = 0.0;
+            if (64 * q < n) {
+              const int i = lane + 64 * q;
+              if (i < n) {
+                za[q] = z0[i];
+                zb[q] = z1[i];
+              }
+              a0 += za[q] * xr[q];
+              a1 += zb[q] * xr[q];
+            }
+          }
+          a0 = wave_sum(a0);
+          a1 = two ? wave_sum(a1) : 0.0;
+#pragma unroll
+          for (int q = 0; q < kSlots; ++q) up[q] += a0 * za[q] + a1 * zb[q];
         }
-        __syncthreads();
+        for (int w = 0; w < 4; ++w) {
+          if (wv == w) {
+#pragma unroll
+            for (int q = 0; q < kSlots; ++q) {
+              const int i = lane + 64 * q;
+              if (i < n) x[i] -= up[q];
+            }
+          }
+          __syncthreads();
+        }
       }
       double s = 0.0;
       for (int i = tid; i < n; i += 256) s += x[i] * x[i];
