@@ -537,12 +537,22 @@ def headline_pno(args):
     ctx.build_df(B, eps, t1, precision=BF16)
     torch.cuda.synchronize()
     t_df = time.perf_counter() - t0
+    # the SA-PNO build once with the pair-density eigenproblems on host threads (for the
+    # record), then with the GPU tridiagonal solver, whose PNOs the run uses
+    ctx.set_eig_backend(1)
+    t0 = time.perf_counter()
+    npno_h, nosv_h = ctx.build_sapno(nroots, tcut)
+    torch.cuda.synchronize()
+    t_pno_host = time.perf_counter() - t0
+    ctx.set_eig_backend(0)
     t0 = time.perf_counter()
     npno, nosv = ctx.build_sapno(nroots, tcut)
     torch.cuda.synchronize()
     t_pno = time.perf_counter() - t0
     split = ctx.pno_ladder_stats()
-    log(f"setup: build_df {t_df:.1f} s, build_sapno {t_pno:.1f} s, {npno.mean():.1f} PNOs/pair")
+    log(f"setup: build_df {t_df:.1f} s, build_sapno {t_pno:.2f} s (host eigensolver {t_pno_host:.2f} s, "
+        f"counts {'equal' if np.array_equal(npno, npno_h) and np.array_equal(nosv, nosv_h) else 'DIFFER'}), "
+        f"{npno.mean():.1f} PNOs/pair")
     _, plen = ctx.pno_layout()
     # one sigma block = the trial vectors one Davidson iteration adds (one per root)
     gen = torch.Generator(device=dev)
@@ -644,7 +654,8 @@ def headline_pno(args):
                              "speedup_bf16_vs_fp64": (dt64 / nb64) / (dt / args.steps),
                              "ring": family(regs64, "ring", ("mfma", "fp64"), "ring products (gemm_kernel tag 3)",
                                             "one FP64 GEMM launch")},
-        "setup": {"generate_s": t_gen, "build_df_s": t_df, "build_sapno_s": t_pno, "npno_mean": float(npno.mean()),
+        "setup": {"generate_s": t_gen, "build_df_s": t_df, "build_sapno_s": t_pno, "build_sapno_host_eig_s": t_pno_host,
+                  "pno_counts_match_host_eig": bool(np.array_equal(npno, npno_h) and np.array_equal(nosv, nosv_h)), "npno_mean": float(npno.mean()),
                   "npno_min": int(npno.min()), "npno_max": int(npno.max()), "nosv_mean": float(nosv.mean()),
                   "pno_len": plen, "ladder_split": split},
         "measured_peaks": dict(peaks, note="register-only MFMA loops on every CU; HBM = 1 GiB device copy"),
