@@ -550,6 +550,9 @@ def headline_pno(args):
     torch.cuda.synchronize()
     t_pno = time.perf_counter() - t0
     split = ctx.pno_ladder_stats()
+    mem_per, mem_avail, mem_chunk = ctx.sigma_memory(PNO, BF16)
+    log(f"sigma memory (PNO, BF16): {mem_per / 2**30:.2f} GiB per vector, {mem_avail / 2**30:.1f} GiB available, "
+        f"chunks of {mem_chunk}")
     log(f"setup: build_df {t_df:.1f} s, build_sapno {t_pno:.2f} s (host eigensolver {t_pno_host:.2f} s, "
         f"counts {'equal' if np.array_equal(npno, npno_h) and np.array_equal(nosv, nosv_h) else 'DIFFER'}), "
         f"{npno.mean():.1f} PNOs/pair")
@@ -657,7 +660,9 @@ def headline_pno(args):
         "setup": {"generate_s": t_gen, "build_df_s": t_df, "build_sapno_s": t_pno, "build_sapno_host_eig_s": t_pno_host,
                   "pno_counts_match_host_eig": bool(np.array_equal(npno, npno_h) and np.array_equal(nosv, nosv_h)), "npno_mean": float(npno.mean()),
                   "npno_min": int(npno.min()), "npno_max": int(npno.max()), "nosv_mean": float(nosv.mean()),
-                  "pno_len": plen, "ladder_split": split},
+                  "pno_len": plen, "ladder_split": split,
+                  "sigma_bf16_bytes_per_vector": mem_per, "sigma_bf16_avail_bytes": mem_avail,
+                  "sigma_bf16_chunk": mem_chunk},
         "measured_peaks": dict(peaks, note="register-only MFMA loops on every CU; HBM = 1 GiB device copy"),
     }
     if not args.no_ttc:

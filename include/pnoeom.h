@@ -451,6 +451,17 @@ int pnoeom_gemm_bf16_time(void* hip_stream, long long M, long long N, long long 
  * Errors: EINVAL (n < 1 or null), ENOTCONV. */
 int pnoeom_host_syev(int n, const double* a, double* w, double* v);
 
+/* Device memory of sigma evaluations (pnoeom_apply_sigma, the Davidson): the bytes one trial
+ * vector of a chunk needs for (space, precision) -- the work arrays of the non-ladder terms,
+ * the ladder's packed operands and results, and in the PNO space the canonical expansion of
+ * the vector and of its sigma --, the bytes available to a chunk now (free device memory plus
+ * what the sigma workspaces hold, less a headroom of max(2 GiB, 3% of the device) left to
+ * the caller), and the vectors per chunk that gives (at least 1; a call on more vectors runs
+ * in chunks of that many).  Any output may be NULL.  Errors: EINVAL (null ctx, bad space or
+ * precision), ESTATE (before pnoeom_build_df; PNO space before pnoeom_build_sapno). */
+int pnoeom_sigma_memory(pnoeom_ctx* ctx, int space, int precision, long long* per_vector, long long* avail,
+                        int* chunk);
+
 /* Where pnoeom_build_sapno (and pnoeom_syev_batched) solve symmetric eigenproblems larger
  * than 128 (Methods: the per-pair diagonalisation of the state-averaged densities, whose
  * kept eigenvectors are the PNOs, and the semicanonical rotation of each kept space):

@@ -577,6 +577,24 @@ int pnoeom_gemm_set_table(int n, const long long* keys, const int* variants) {
   return PNOEOM_OK;
 }
 
+int pnoeom_sigma_memory(pnoeom_ctx* ctx, int space, int precision, long long* per_vector, long long* avail,
+                        int* chunk) {
+  return guarded(ctx, [&](pnoeom::Context& c) {
+    PNO_CHECK(c.have_df, PNOEOM_ESTATE, "sigma_memory before build_df");
+    PNO_CHECK(precision == PNOEOM_FP64 || precision == PNOEOM_FP32 || precision == PNOEOM_BF16, PNOEOM_EINVAL,
+              "sigma_memory: bad precision");
+    PNO_CHECK(space == PNOEOM_CANONICAL || space == PNOEOM_PNO, PNOEOM_EINVAL, "sigma_memory: bad space");
+    PNO_CHECK(space == PNOEOM_CANONICAL || c.pno.built, PNOEOM_ESTATE, "sigma_memory: PNO space before build_sapno");
+    const int64_t per = pnoeom::sigma_bytes_per_vector(c, precision, space == PNOEOM_PNO);
+    size_t freeb = 0, totalb = 0;
+    PNO_HIP(hipMemGetInfo(&freeb, &totalb));
+    const int64_t av = (int64_t)freeb + pnoeom::sigma_held_bytes(c) - pnoeom::sigma_headroom((int64_t)totalb);
+    if (per_vector) *per_vector = per;
+    if (avail) *avail = av;
+    if (chunk) *chunk = (int)std::max<int64_t>(1, av > 0 ? av / per : 0);
+  });
+}
+
 int pnoeom_set_eig_backend(pnoeom_ctx* ctx, int backend) {
   return guarded(ctx, [&](pnoeom::Context& c) {
     PNO_CHECK(backend == 0 || backend == 1, PNOEOM_EINVAL, "set_eig_backend: backend must be 0 or 1");

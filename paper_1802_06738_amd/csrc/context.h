@@ -309,6 +309,9 @@ void sigma_pno(Context& c, int nvec, const double* x, double* y, int precision);
 // vectors per sigma chunk that fit the free device memory (pno: with the canonical
 // expansions of the PNO-space sigma)
 int sigma_chunk(Context& c, int nvec, int precision, bool pno);
+int64_t sigma_bytes_per_vector(const Context& c, int precision, bool pno);
+int64_t sigma_held_bytes(const Context& c);
+int64_t sigma_headroom(int64_t total);
 // sigma of nv packed vectors X[q] = x + q*N (canonical: [r1 | r2], PNO: compressed)
 // into S; through captured graphs when c.graph_mode
 void sigma_apply(Context& c, int space, int nv, const double* X, double* S, int64_t N, int precision);

@@ -970,9 +970,13 @@ int64_t sigma_held_bytes(const Context& c) {
   return b;
 }
 
+// device bytes sigma chunks leave to the caller: 3% of the device, at least 2 GiB (split-K
+// partials, graphs and the caller's own tensors)
+int64_t sigma_headroom(int64_t total) { return std::max<int64_t>(2ll << 30, total * 3 / 100); }
+
 // vectors per sigma chunk: as many as fit in the free device memory plus what the
-// workspaces already hold, leaving a tenth of the device (at least 2 GiB) to the
-// caller.  While a graph is captured the decision of the eager run is reused.
+// workspaces already hold, less the headroom.  While a graph is captured the decision of
+// the eager run is reused.
 int sigma_chunk(Context& c, int nvec, int precision, bool pno) {
   if (c.fixed_chunk > 0) return std::max(1, std::min(c.fixed_chunk, nvec));
   if (c.sw_precision >= 0 && c.sw_precision != precision) {
@@ -987,8 +991,7 @@ int sigma_chunk(Context& c, int nvec, int precision, bool pno) {
   const int64_t per = sigma_bytes_per_vector(c, precision, pno);
   size_t freeb = 0, totalb = 0;
   PNO_HIP(hipMemGetInfo(&freeb, &totalb));
-  const int64_t headroom = std::max<int64_t>(2ll << 30, (int64_t)totalb * 3 / 100);
-  const int64_t avail = (int64_t)freeb + sigma_held_bytes(c) - headroom;
+  const int64_t avail = (int64_t)freeb + sigma_held_bytes(c) - sigma_headroom((int64_t)totalb);
   const int64_t nb = avail > 0 ? avail / per : 0;
   c.last_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nb, nvec));
   return c.last_chunk;

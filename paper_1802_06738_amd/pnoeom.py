@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = ["pnoeom_create", "pnoeom_destroy", "pnoeom_last_error", "pno
                     "pnoeom_ladder_noalloc_limit", "pnoeom_set_pno_ladder",
                     "pnoeom_pno_ladder_stats", "pnoeom_set_pno_states", "pnoeom_ccsd_defaults",
                     "pnoeom_ccsd_residual", "pnoeom_ccsd", "pnoeom_ccsd_history", "pnoeom_ccsd_gs_counts",
-                    "pnoeom_set_eig_backend", "pnoeom_syev_batched"]
+                    "pnoeom_set_eig_backend", "pnoeom_syev_batched", "pnoeom_sigma_memory"]
 
 
 class PnoEomError(RuntimeError):
@@ -116,6 +116,7 @@ def load_library():
     lib.pnoeom_ladder_noalloc_limit.restype = C.c_longlong
     lib.pnoeom_set_pno_ladder.argtypes = [vp, C.c_int]
     lib.pnoeom_set_eig_backend.argtypes = [vp, C.c_int]
+    lib.pnoeom_sigma_memory.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong), ip]
     lib.pnoeom_syev_batched.argtypes = [vp, C.c_int, C.c_int, vp, C.c_double, vp, vp]
     lib.pnoeom_set_pno_states.argtypes = [vp, C.c_int, ip]
     lib.pnoeom_pno_ladder_stats.argtypes = [vp, ip, ip, ip, dp]
@@ -464,6 +465,13 @@ class PnoEom:
     def set_pno_ladder(self, max_native=-1):
         """PNO-space ladder for pairs with n_p <= max_native at the next build_sapno (-1 auto, 0 none)."""
         self._check(self.lib.pnoeom_set_pno_ladder(self.h, int(max_native)))
+
+    def sigma_memory(self, space, precision):
+        """(bytes per trial vector of a sigma chunk, bytes available to chunks, vectors per chunk)."""
+        per, av, ch = C.c_longlong(), C.c_longlong(), C.c_int()
+        self._check(self.lib.pnoeom_sigma_memory(self.h, int(space), int(precision), C.byref(per), C.byref(av),
+                                                 C.byref(ch)))
+        return per.value, av.value, ch.value
 
     def set_eig_backend(self, backend=0):
         """Symmetric eigenproblems above 128 in build_sapno / syev_batched: 0 GPU, 1 host threads."""
