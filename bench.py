@@ -556,6 +556,15 @@ def headline_pno(args):
     log(f"setup: build_df {t_df:.1f} s, build_sapno {t_pno:.2f} s (host eigensolver {t_pno_host:.2f} s, "
         f"counts {'equal' if np.array_equal(npno, npno_h) and np.array_equal(nosv, nosv_h) else 'DIFFER'}), "
         f"{npno.mean():.1f} PNOs/pair")
+    if args.setup_only:
+        print(json.dumps({"workload": f"config {cfgid} setup", "o": o, "v": v, "naux": naux, "nroots": nroots,
+                          "tcut": tcut, "generate_s": t_gen, "build_df_s": t_df, "build_sapno_s": t_pno,
+                          "build_sapno_host_eig_s": t_pno_host,
+                          "pno_counts_match_host_eig": bool(np.array_equal(npno, npno_h)
+                                                            and np.array_equal(nosv, nosv_h)),
+                          "npno_mean": float(npno.mean()), "npno_max": int(npno.max()),
+                          "sigma_bf16_bytes_per_vector": mem_per, "sigma_bf16_chunk": mem_chunk}), flush=True)
+        return
     _, plen = ctx.pno_layout()
     # one sigma block = the trial vectors one Davidson iteration adds (one per root)
     gen = torch.Generator(device=dev)
@@ -742,6 +751,8 @@ def main():
     ap.add_argument("--bf16-passes", type=int, default=1, help="passes of the bfloat16 ring products (1 or 3)")
     ap.add_argument("--no-ttc", action="store_true", help="skip the Davidson time-to-convergence runs")
     ap.add_argument("--no-config2", action="store_true", help="skip the o=20, v=150 oracle comparison")
+    ap.add_argument("--setup-only", action="store_true",
+                    help="time the DF and SA-PNO setup only (the PNO build with both eigensolver backends)")
     ap.add_argument("--legacy", action="store_true",
                     help="config 3/4: the whole-Davidson steps of the canonical-workload flow instead")
     ap.add_argument("--pno-ladder", type=int, default=-1,
