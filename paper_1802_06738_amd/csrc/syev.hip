@@ -6,8 +6,8 @@
 //   2. every eigenvalue by bisection on Sturm-sequence counts, one thread per eigenvalue;
 //   3. the eigenvectors of the kept eigenvalues (|lambda| >= cut) of the tridiagonal matrix by
 //      inverse iteration (partial-pivoting LU of T - lambda I, four solves from a fixed
-//      pseudo-random start), each iterate orthogonalised (classical Gram-Schmidt, twice)
-//      against the earlier vectors of its cluster of close eigenvalues;
+//      pseudo-random start), each iterate orthogonalised (classical Gram-Schmidt; twice after
+//      the last solve) against the earlier vectors of its cluster of close eigenvalues;
 //   4. back-transform of those vectors by the stored reflectors, one wave per vector.
 // The reduction reads and writes the trailing matrix once per column (HBM/L2 bound, 4/3 n^3
 // flops); bisection and inverse iteration are O(n^2) and O(n * kept) per matrix.
@@ -197,6 +197,7 @@ __device__ __forceinline__ double start_value(int i, int k) {
 // vectors (a zero matrix is one cluster).  Pivots below eps ||T|| are replaced by
 // +-eps ||T||; each solve is rescaled to max |x| = 1 before the projections and normalised
 // after them.
+template <int NS>
 __global__ __launch_bounds__(256) void inviter_kernel(int ld, const int* __restrict__ nsz, const double* __restrict__ dall,
                                                       const double* __restrict__ eall, const double* __restrict__ evall,
                                                       double cut, double* __restrict__ Vtall) {
@@ -311,47 +312,43 @@ __global__ __launch_bounds__(256) void inviter_kernel(int ld, const int* __restr
       const double inv = mx > 0.0 ? 1.0 / mx : 0.0;
       for (int i = tid; i < n; i += 256) x[i] *= inv;
       __syncthreads();
-      // x -= Z Z^T x over the cluster's earlier vectors Z (rows mem[] of Vt), twice.  Wave w
-      // takes members w, w + 4, ...: one coalesced read of each member row gives both its
-      // coefficient (against the x of this pass, held in registers) and its share of the
-      // update; the four waves' shares are subtracted in turn.
-      for (int pass = 0; pass < 2 && nclus > 0; ++pass) {
-        double xr[kSlots], up[kSlots];
+      // x -= Z Z^T x over the cluster's earlier vectors Z (rows mem[] of Vt): once per
+      // iteration, twice in the last.  Wave w takes members w, w + 4, ..., four at a time: one
+      // coalesced read of each member row gives both its coefficient (against the x of this
+      // pass, held in registers) and its share of the update; the four waves' shares are
+      // subtracted in turn.
+      const int passes = it + 1 < kInvIters ? 1 : 2;
+      for (int pass = 0; pass < passes && nclus > 0; ++pass) {
+        double xr[NS], up[NS];
 #pragma unroll
-        for (int q = 0; q < kSlots; ++q) {
+        for (int q = 0; q < NS; ++q) {
           const int i = lane + 64 * q;
           xr[q] = i < n ? x[i] : 0.0;
           up[q] = 0.0;
         }
-        for (int p = wv; p < nclus; p += 8) {
-          const bool two = p + 4 < nclus;
-          const double* z0 = Vt + (int64_t)mem[p] * ld;
-          const double* z1 = Vt + (int64_t)mem[two ? p + 4 : p] * ld;
-          double za[kSlots], zb[kSlots];
-          double a0 = 0.0, a1 = 0.0;
+        for (int p = wv; p < nclus; p += 16) {
+          double z[4][NS], a[4];
 #pragma unroll
-          for (int q = 0; q < kSlots; ++q) {
-            za[q] = 0.0;
-            zb[q] = 0.0;
-            if (64 * q < n) {
+          for (int m = 0; m < 4; ++m) {
+            const int pm = p + 4 * m;
+            const double* zr = Vt + (int64_t)mem[pm < nclus ? pm : p] * ld;
+            a[m] = 0.0;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
               const int i = lane + 64 * q;
-              if (i < n) {
-                za[q] = z0[i];
-                zb[q] = z1[i];
-              }
-              a0 += za[q] * xr[q];
-              a1 += zb[q] * xr[q];
+              z[m][q] = (pm < nclus && i < n) ? zr[i] : 0.0;
+              a[m] += z[m][q] * xr[q];
             }
           }
-          a0 = wave_sum(a0);
-          a1 = two ? wave_sum(a1) : 0.0;
 #pragma unroll
-          for (int q = 0; q < kSlots; ++q) up[q] += a0 * za[q] + a1 * zb[q];
+          for (int m = 0; m < 4; ++m) a[m] = wave_sum(a[m]);
+#pragma unroll
+          for (int q = 0; q < NS; ++q) up[q] += a[0] * z[0][q] + a[1] * z[1][q] + a[2] * z[2][q] + a[3] * z[3][q];
         }
         for (int w = 0; w < 4; ++w) {
           if (wv == w) {
 #pragma unroll
-            for (int q = 0; q < kSlots; ++q) {
+            for (int q = 0; q < NS; ++q) {
               const int i = lane + 64 * q;
               if (i < n) x[i] -= up[q];
             }
@@ -434,8 +431,12 @@ void syev_tridiag(hipStream_t s, int nmat, const int* dn, int nmax, int ld, doub
   hipLaunchKernelGGL(bisect_kernel, dim3((nmax + 255) / 256, nmat), dim3(256), 0, s, ld, dn, (const double*)d,
                      (const double*)e, ev);
   PNO_HIP(hipGetLastError());
-  hipLaunchKernelGGL(inviter_kernel, dim3(nmat), dim3(256), 0, s, ld, dn, (const double*)d, (const double*)e,
-                     (const double*)ev, cut, Vt);
+  if (nmax <= 512)
+    hipLaunchKernelGGL(inviter_kernel<8>, dim3(nmat), dim3(256), 0, s, ld, dn, (const double*)d, (const double*)e,
+                       (const double*)ev, cut, Vt);
+  else
+    hipLaunchKernelGGL(inviter_kernel<kSlots>, dim3(nmat), dim3(256), 0, s, ld, dn, (const double*)d,
+                       (const double*)e, (const double*)ev, cut, Vt);
   PNO_HIP(hipGetLastError());
   hipLaunchKernelGGL(backxf_kernel, dim3(nmat, (nmax + 3) / 4), dim3(256), 0, s, ld, dn, (const double*)A,
                      (const double*)t, (const double*)ev, cut, Vt);
