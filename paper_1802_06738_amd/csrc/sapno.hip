@@ -7,9 +7,11 @@
 // - e_a - e_b) come from the DF factors (K is the sigma-doubles of R1 = b_k at T = 0,
 // i.e. the (ai|bj) response to the one-index transformation by b_k); the pair
 // densities D^{ij} += 2/(1+d_ij)/N (B Bt^T + B^T Bt), Bt = 2B - B^T, are batched MFMA
-// GEMMs over all pairs.  Per-pair eigenproblems use a batched cyclic parallel Jacobi
-// method (one workgroup per matrix, Brent-Luk round-robin ordering), which keeps
-// small occupation numbers to high relative accuracy.  Compressed vectors hold the
+// GEMMs over all pairs.  Per-pair eigenproblems up to n = 128 use a batched cyclic parallel
+// Jacobi method (one workgroup per matrix, Brent-Luk round-robin ordering), which keeps
+// small occupation numbers to high relative accuracy; larger ones the batched tridiagonal
+// solver of syev.hip, which forms only the eigenvectors the truncation keeps (occupations
+// to eps times the largest).  Compressed vectors hold the
 // singles blocks U^i^T r^i, then the pair blocks w_p U^p^T R^{ij} U^p for i <= j
 // (w_p = sqrt 2 for i < j, 1 for i = j), so plain dot products are the full-array
 // Frobenius inner product.
