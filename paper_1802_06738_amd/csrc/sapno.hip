@@ -619,6 +619,8 @@ void pnos_from_density(Context& c, PNOData& P, const double* D, double inv_n, do
   std::vector<double> evh((size_t)npair * v);
   PNO_HIP(hipMemcpyAsync(evh.data(), ev, evh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   PNO_HIP(hipStreamSynchronize(s));
+  PNO_CHECK(std::all_of(evh.begin(), evh.end(), [](double x) { return std::isfinite(x); }), PNOEOM_ENOTCONV,
+            "build_sapno: non-finite pair-density occupation");
   Dp.release();
 
   // 4. kept vectors: pairs with |n| >= tcut_pno, OSVs (diagonal pairs) with |n| >= tcut_osv.
@@ -712,6 +714,10 @@ void pnos_from_density(Context& c, PNOData& P, const double* D, double inv_n, do
   }
   std::vector<double> fevh((size_t)nblk * nmax);
   PNO_HIP(hipMemcpy(fevh.data(), fev, fevh.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int b = 0; b < nblk; ++b)  // (entries past bn[b] of a block are not written)
+    for (int k = 0; k < bn[b]; ++k)
+      PNO_CHECK(std::isfinite(fevh[(size_t)b * nmax + k]), PNOEOM_ENOTCONV,
+                "build_sapno: non-finite semicanonical orbital energy");
 
   // 6. layout of compressed vectors: singles of i = 0..o-1, then pairs p
   P.npno.assign(bn.begin(), bn.begin() + npair);
