@@ -5,7 +5,7 @@
 //   1. Householder reduction to tridiagonal form, one workgroup per matrix;
 //   2. every eigenvalue by bisection on Sturm-sequence counts, one thread per eigenvalue;
 //   3. the eigenvectors of the kept eigenvalues (|lambda| >= cut) of the tridiagonal matrix by
-//      inverse iteration (partial-pivoting LU of T - lambda I, four solves from a fixed
+//      inverse iteration (partial-pivoting LU of T - lambda I, three solves from a fixed
 //      pseudo-random start), each iterate orthogonalised (classical Gram-Schmidt; twice after
 //      the last solve) against the earlier vectors of its cluster of close eigenvalues;
 //   4. back-transform of those vectors by the stored reflectors, one wave per vector.
@@ -22,7 +22,7 @@ namespace {
 constexpr int kTriThreads = 512;
 constexpr int kMaxN = kSyevMaxN;
 constexpr int kSlots = kMaxN / 64;   // vector elements per lane in the back-transform
-constexpr int kInvIters = 4;
+constexpr int kInvIters = 3;
 
 __device__ __forceinline__ double wave_sum(double x) {
   for (int m = 32; m > 0; m >>= 1) x += __shfl_xor(x, m, 64);
