@@ -490,25 +490,50 @@ void build_native_ladder(Context& c, const std::vector<int>& pi, const std::vect
     for (int p = 0; p < npair; ++p) large = large || (boff[p] >= 0 && P.npno[p] > kNatSmall);
     if (large) P.Y1.alloc(bw);
   }
-  // Bbar_p[a][Q][k] = sum_xy U_p[x][a] B~^Q[o+x][o+y] U_p[y][k], two batched GEMMs over Q per pair
-  DBuf<double> T1;
-  T1.alloc((int64_t)naux * v * nmax);
-  for (int p = 0; p < npair; ++p) {
-    if (boff[p] < 0) continue;
-    const int n = P.npno[p];
-    const double* Up = P.U + P.uoff[p];
+  // Bbar_p[a][Q][k] = sum_xy U_p[x][a] B~^Q[o+x][o+y] U_p[y][k]: T1 = B~^Q U for a group of
+  // consecutive native pairs at once (their U columns side by side, at most 512 of them, so
+  // that B~_vv is read once per group and the product is wide), then U_p^T T1 per pair
+  // (the group's T1 kept within 4 GiB, but at least one pair wide)
+  const int64_t kGroupN = std::max<int64_t>(nmax, std::min<int64_t>(512, (4ll << 30) / (8 * (int64_t)naux * v)));
+  DBuf<double> T1, Ug;
+  T1.alloc((int64_t)naux * v * kGroupN);
+  Ug.alloc((int64_t)v * kGroupN);
+  for (int p0 = 0; p0 < npair;) {
+    std::vector<int> grp;
+    int64_t ncol = 0;
+    int p = p0;
+    for (; p < npair; ++p) {
+      if (boff[p] < 0) continue;
+      if (!grp.empty() && ncol + P.npno[p] > kGroupN) break;
+      grp.push_back(p);
+      ncol += P.npno[p];
+    }
+    p0 = p;
+    if (grp.empty()) continue;
+    int64_t col = 0;
+    for (int q : grp) {
+      const int64_t n = P.npno[q];
+      PNO_HIP(hipMemcpy2DAsync((double*)Ug + col, ncol * sizeof(double), P.U + P.uoff[q], n * sizeof(double),
+                               n * sizeof(double), v, hipMemcpyDeviceToDevice, s));
+      col += n;
+    }
     GemmDesc<double> d;
-    d.M = v; d.N = n; d.K = v; d.batch = naux;
+    d.M = v; d.N = ncol; d.K = v; d.batch = naux;
     d.A = c.Bt + (int64_t)o * nmo + o; d.lda = nmo; d.sA = n2;
-    d.B = Up; d.ldb = n; d.sB = 0;
-    d.C = T1; d.ldc = n; d.sC = (int64_t)v * n;
+    d.B = Ug; d.ldb = ncol; d.sB = 0;
+    d.C = T1; d.ldc = ncol; d.sC = (int64_t)v * ncol;
     gemm(d, s);
-    GemmDesc<double> e;
-    e.ta = true; e.M = n; e.N = n; e.K = v; e.batch = naux;
-    e.A = Up; e.lda = n; e.sA = 0;
-    e.B = T1; e.ldb = n; e.sB = (int64_t)v * n;
-    e.C = P.Bbar + boff[p]; e.ldc = (int64_t)naux * n; e.sC = n;
-    gemm(e, s);
+    col = 0;
+    for (int q : grp) {
+      const int n = P.npno[q];
+      GemmDesc<double> e;
+      e.ta = true; e.M = n; e.N = n; e.K = v; e.batch = naux;
+      e.A = P.U + P.uoff[q]; e.lda = n; e.sA = 0;
+      e.B = T1 + col; e.ldb = ncol; e.sB = (int64_t)v * ncol;
+      e.C = P.Bbar + boff[q]; e.ldc = (int64_t)naux * n; e.sC = n;
+      gemm(e, s);
+      col += n;
+    }
   }
   // one vector's tables (bases shifted per vector): Y1 = Bbar_p Rbar_p, then the n x n result
   // over K = naux n in chunks of about 2048 (whole Q blocks), each chunk its own partial
