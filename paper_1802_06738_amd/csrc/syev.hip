@@ -9,8 +9,9 @@
 //      pseudo-random start), each iterate orthogonalised (classical Gram-Schmidt; twice after
 //      the last solve) against the earlier vectors of its cluster of close eigenvalues;
 //   4. back-transform of those vectors by the stored reflectors, one wave per vector.
-// The reduction reads and writes the trailing matrix once per column (HBM/L2 bound, 4/3 n^3
-// flops); bisection and inverse iteration are O(n^2) and O(n * kept) per matrix.
+// The reduction reads the trailing block twice and writes it once per column (HBM/L2 bound,
+// 4/3 n^3 flops); bisection is O(n^2) per matrix, inverse iteration O(n) per kept vector plus
+// O(n c) for the c earlier vectors of its cluster.
 #include <cfloat>
 #include <cmath>
 
